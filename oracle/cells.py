@@ -1,0 +1,53 @@
+"""Cell list rebuilt every iteration ("updating data structures", Algorithm 1).
+
+The paper keys its sparse background grid by Morton code and a compact hash
+(section 3.1.3, Eq. 9-10). For the particle cell list of the relaxation loop
+the key here is the plain x-fastest linear index of a uniform grid, offset per
+geometry of a batch; particles are ordered by (key, id), and cell_start[c] is
+the first sorted index of cell c (cell_start[ncell] = N).
+
+The cell coordinate is defined in binary32, one rounding per operation:
+    t = fl32(fl32(x - origin) * inv_cell),  c = clamp(floor(t), 0, dim - 1)
+with NaN mapped to cell 0.
+"""
+import numpy as np
+
+
+def cell_coords(pos32: np.ndarray, origin, inv_cell, dims) -> np.ndarray:
+    """Integer cell coordinates [N, 3] of binary32 positions [N, 3]."""
+    p = np.asarray(pos32, np.float32)
+    t = (p - np.asarray(origin, np.float32)).astype(np.float32)
+    t = (t * np.float32(inv_cell)).astype(np.float32)
+    hi = (np.asarray(dims, np.int64) - 1).astype(np.float32)
+    t = np.fmin(np.fmax(t, np.float32(0.0)), hi)   # fmax/fmin drop NaN -> 0
+    return np.floor(t).astype(np.int64)
+
+
+def cell_keys(wl, pos32=None, gid=None) -> np.ndarray:
+    """Batch-global cell key of every particle of a workload."""
+    pos32 = wl.pos if pos32 is None else pos32
+    gid = wl.gid if gid is None else gid
+    keys = np.empty(len(pos32), np.int64)
+    for g, geo in enumerate(wl.geoms):
+        m = gid == g
+        c = cell_coords(pos32[m], geo.origin, geo.inv_cell, geo.dims)
+        nx, ny = int(geo.dims[0]), int(geo.dims[1])
+        keys[m] = geo.cell_begin + (c[:, 2] * ny + c[:, 1]) * nx + c[:, 0]
+    return keys
+
+
+def total_cells(wl) -> int:
+    return int(sum(g.ncell for g in wl.geoms))
+
+
+def sort_order(keys: np.ndarray, ids: np.ndarray) -> np.ndarray:
+    """Permutation putting particles in (key, id) order."""
+    return np.lexsort((ids, keys))
+
+
+def cell_start(sorted_keys: np.ndarray, ncell: int) -> np.ndarray:
+    """Exclusive prefix sum of the per-cell particle counts, length ncell + 1."""
+    counts = np.bincount(sorted_keys, minlength=ncell)
+    out = np.zeros(ncell + 1, np.int64)
+    np.cumsum(counts, out=out[1:])
+    return out

@@ -1,0 +1,422 @@
+"""Seeded synthetic workloads: meshes plus an initial (unrelaxed) particle cloud.
+
+The paper seeds particles at the centres of internal and surface grid cells,
+maps surface seeds onto facets and places feature-line particles at a spacing
+that divides each line evenly (section 3.2). Its models are not available, so
+this module builds stand-ins with the same structure: a jittered lattice of
+volume particles clipped to the inside, surface particles lying exactly on
+facets (with the owning facet recorded), feature particles on the sharp-edge
+polylines (with their segment and arc-length coordinate), and fixed singular
+particles at corners. All randomness comes from numpy's PCG64 with a stated
+seed.
+
+Particle tags (the particle classes of section 2.2 / 3.3):
+  0 singular point (never moves)   1 feature-line particle
+  2 surface particle                3 volume particle
+  4 fixed volume particle (innermost layer of the narrow band, never moves)
+
+Owner: facet index (global over the batch) for surface particles, feature slot
+for feature particles, -1 otherwise.
+
+This module is an input generator shared by the oracle and the GPU path; it
+performs none of the relaxation method's arithmetic.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import meshes as M
+
+SINGULAR, FEATURE, SURFACE, VOLUME, FIXED = 0, 1, 2, 3, 4
+ALL_MOVING = (1 << FEATURE) | (1 << SURFACE) | (1 << VOLUME)
+
+
+def f32(x) -> float:
+    """Round a Python float to the nearest binary32 value (returned as float)."""
+    return float(np.float32(x))
+
+
+@dataclass
+class Geometry:
+    """One geometry of a batch: its mesh and the particle-grid description.
+
+    The particle grid is a uniform Cartesian grid of cell edge (2h/k)(1+2^-8)
+    starting at `origin`; a cell key is the x-fastest linear index of the cell
+    plus `cell_begin`, the offset of this geometry in the batch key space.
+    """
+    mesh: M.Mesh
+    dx: float
+    h: float              # binary32 value
+    k: int
+    proj_radius: float    # binary32 value
+    origin: np.ndarray    # float32 [3]
+    inv_cell: float       # binary32 value
+    dims: np.ndarray      # int64 [3]
+    part_begin: int = 0
+    part_end: int = 0
+    cell_begin: int = 0
+    tri_begin: int = 0
+    seg_begin: int = 0
+    line_begin: int = 0
+    feat_begin: int = 0
+
+    @property
+    def ncell(self) -> int:
+        return int(np.prod(self.dims))
+
+
+def particle_grid(lo, hi, h, k=1, pad=None):
+    """Grid parameters covering [lo, hi] plus a margin of one support radius."""
+    rc = f32(2.0 * h)
+    pad = rc if pad is None else pad
+    cell = f32((rc / k) * (1.0 + 2.0 ** -8))
+    inv = f32(1.0 / cell)
+    origin = (np.asarray(lo, np.float64) - pad).astype(np.float32)
+    ext = np.asarray(hi, np.float64) + pad - origin.astype(np.float64)
+    dims = np.ceil(ext * inv).astype(np.int64) + 1
+    return origin, inv, dims
+
+
+@dataclass
+class Workload:
+    name: str
+    geoms: list
+    pos: np.ndarray        # float32 [N, 3]
+    tag: np.ndarray        # int32 [N]
+    owner: np.ndarray      # int32 [N]
+    gid: np.ndarray        # int32 [N] geometry index
+    feat_seg: np.ndarray   # int32 [n_feat] global segment index
+    feat_u: np.ndarray     # float64 [n_feat] arc length inside the segment
+    move_mask: int = ALL_MOVING
+    seed: int = 0
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.pos.shape[0])
+
+    @property
+    def ids(self) -> np.ndarray:
+        return np.arange(self.n, dtype=np.int32)
+
+    def n_moving(self) -> int:
+        return int(np.sum((self.move_mask >> self.tag) & 1))
+
+    def counts(self) -> dict:
+        names = ["singular", "feature", "surface", "volume", "fixed"]
+        return {nm: int(np.sum(self.tag == t)) for t, nm in enumerate(names)}
+
+
+class _Builder:
+    """Accumulates particles of one geometry."""
+
+    def __init__(self):
+        self.pos, self.tag, self.owner = [], [], []
+        self.feat_seg, self.feat_u = [], []
+
+    def add(self, pos, tag, owner=None):
+        pos = np.asarray(pos, np.float64).reshape(-1, 3)
+        self.pos.append(pos)
+        self.tag.append(np.full(len(pos), tag, np.int32))
+        self.owner.append(np.full(len(pos), -1, np.int32) if owner is None
+                          else np.asarray(owner, np.int32))
+
+    def add_feature(self, pos, seg, u):
+        base = sum(len(s) for s in self.feat_seg)
+        self.feat_seg.append(np.asarray(seg, np.int32))
+        self.feat_u.append(np.asarray(u, np.float64))
+        self.add(pos, FEATURE, base + np.arange(len(seg)))
+
+
+def _seg_table(lines: M.FeatureLines):
+    p0, p1 = lines.seg_p[:, 0], lines.seg_p[:, 1]
+    ln = np.linalg.norm(p1 - p0, axis=1)
+    return p0, p1, ln
+
+
+def _feature_particles(b: _Builder, mesh: M.Mesh, dx: float, rng, jitter: float):
+    """Particles along every feature line at spacing L/ceil(L/dx) (section 3.2.2).
+
+    Open lines exclude their end points (those are singular points); loops
+    place ceil(L/dx) particles. Each gets a uniform jitter along the line.
+    """
+    lines = mesh.lines
+    p0, p1, ln = _seg_table(lines)
+    for l in range(lines.n_line):
+        s0, s1 = lines.line_seg_begin[l], lines.line_seg_begin[l + 1]
+        seg_len = ln[s0:s1]
+        cum = np.concatenate([[0.0], np.cumsum(seg_len)])
+        L = cum[-1]
+        m = max(int(np.ceil(L / dx)), 1)
+        sp = L / m
+        if lines.line_closed[l]:
+            s = (np.arange(m) + 0.5) * sp
+        else:
+            s = np.arange(1, m) * sp
+        if len(s) == 0:
+            continue
+        s = s + rng.uniform(-jitter, jitter, len(s)) * sp
+        if lines.line_closed[l]:
+            s = np.mod(s, L)
+        k = np.clip(np.searchsorted(cum, s, side="right") - 1, 0, len(seg_len) - 1)
+        u = s - cum[k]
+        u = np.clip(u, 0.0, seg_len[k])
+        seg = s0 + k
+        t = (p1[seg] - p0[seg]) / ln[seg][:, None]
+        pos = p0[seg] + u[:, None] * t
+        b.add_feature(pos, seg, u)
+
+
+def _finish(name, parts, move_mask, seed, meta=None) -> Workload:
+    """Concatenate per-geometry builders into one workload with global offsets."""
+    geoms, pos, tag, owner, gid, fseg, fu = [], [], [], [], [], [], []
+    n = tri_off = seg_off = line_off = feat_off = cell_off = 0
+    for g, (geom, b) in enumerate(parts):
+        p = np.concatenate(b.pos, 0) if b.pos else np.zeros((0, 3))
+        t = np.concatenate(b.tag) if b.tag else np.zeros(0, np.int32)
+        o = np.concatenate(b.owner) if b.owner else np.zeros(0, np.int32)
+        o = o.copy()
+        o[t == SURFACE] += tri_off
+        o[t == FEATURE] += feat_off
+        geom.part_begin, geom.part_end = n, n + len(p)
+        geom.tri_begin, geom.seg_begin, geom.line_begin = tri_off, seg_off, line_off
+        geom.feat_begin, geom.cell_begin = feat_off, cell_off
+        geoms.append(geom)
+        pos.append(p.astype(np.float32))
+        tag.append(t)
+        owner.append(o)
+        gid.append(np.full(len(p), g, np.int32))
+        if b.feat_seg:
+            fseg.append(np.concatenate(b.feat_seg) + seg_off)
+            fu.append(np.concatenate(b.feat_u))
+            feat_off += len(fseg[-1])
+        n += len(p)
+        tri_off += geom.mesh.n_tri
+        seg_off += geom.mesh.lines.n_seg
+        line_off += geom.mesh.lines.n_line
+        cell_off += geom.ncell
+    return Workload(
+        name=name, geoms=geoms, pos=np.concatenate(pos, 0), tag=np.concatenate(tag),
+        owner=np.concatenate(owner), gid=np.concatenate(gid),
+        feat_seg=(np.concatenate(fseg) if fseg else np.zeros(0, np.int32)).astype(np.int32),
+        feat_u=np.concatenate(fu) if fu else np.zeros(0, np.float64),
+        move_mask=move_mask, seed=seed, meta=meta or {})
+
+
+def _make_geom(mesh, dx, k=1, proj_radius=None):
+    h = f32(1.3 * dx)
+    lo, hi = mesh.bbox()
+    origin, inv, dims = particle_grid(lo, hi, h, k)
+    R = f32(2.0 * h) if proj_radius is None else f32(proj_radius)
+    return Geometry(mesh=mesh, dx=dx, h=h, k=k, proj_radius=R, origin=origin,
+                    inv_cell=inv, dims=dims)
+
+
+# ---------------------------------------------------------------------------
+# Unit cube
+# ---------------------------------------------------------------------------
+
+def _tri_owner_on_plane(mesh: M.Mesh, cand: np.ndarray, pts: np.ndarray) -> np.ndarray:
+    """Index (into cand) of the candidate facet containing each point (points on the facet planes)."""
+    A = mesh.vert[mesh.tri[cand, 0]]
+    B = mesh.vert[mesh.tri[cand, 1]]
+    C = mesh.vert[mesh.tri[cand, 2]]
+    out = np.full(len(pts), -1, np.int64)
+    for c in range(len(cand)):
+        n = np.cross(B[c] - A[c], C[c] - A[c])
+        s0 = np.cross(B[c] - A[c], pts - A[c]) @ n
+        s1 = np.cross(C[c] - B[c], pts - B[c]) @ n
+        s2 = np.cross(A[c] - C[c], pts - C[c]) @ n
+        inside = (s0 >= 0) & (s1 >= 0) & (s2 >= 0) & (out < 0)
+        out[inside] = c
+    return out
+
+
+def cube_workload(n=24, jitter=0.3, seed=1, k=1, with_volume=True, with_surface=True,
+                  with_features=True, move_mask=ALL_MOVING, name=None) -> Workload:
+    """Unit cube [0,1]^3, dx = 1/n: a jittered (i+1/2)dx lattice of volume
+    particles, (a+1/2)dx x (b+1/2)dx surface particles per face with tangential
+    jitter, features at m*dx along the 12 edges, fixed particles at the 8 corners."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mesh = M.cube()
+    dx = 1.0 / n
+    geom = _make_geom(mesh, dx, k)
+    b = _Builder()
+    c = (np.arange(n) + 0.5) * dx
+    if with_volume:
+        g = np.stack(np.meshgrid(c, c, c, indexing="ij"), -1).reshape(-1, 3)
+        g = g + rng.uniform(-jitter, jitter, g.shape) * dx
+        b.add(g, VOLUME)
+    if with_surface:
+        nrm = np.cross(mesh.vert[mesh.tri[:, 1]] - mesh.vert[mesh.tri[:, 0]],
+                       mesh.vert[mesh.tri[:, 2]] - mesh.vert[mesh.tri[:, 0]])
+        for axis in range(3):
+            u, v = [a for a in range(3) if a != axis]
+            for side in (0.0, 1.0):
+                uu, vv = np.meshgrid(c, c, indexing="ij")
+                pts = np.zeros((n * n, 3))
+                pts[:, u] = uu.ravel() + rng.uniform(-jitter, jitter, n * n) * dx
+                pts[:, v] = vv.ravel() + rng.uniform(-jitter, jitter, n * n) * dx
+                pts[:, axis] = side
+                want = np.zeros(3)
+                want[axis] = 1.0 if side == 1.0 else -1.0
+                cand = np.nonzero(np.isclose(nrm @ want, np.linalg.norm(nrm, axis=1)))[0]
+                own = _tri_owner_on_plane(mesh, cand, pts)
+                assert (own >= 0).all()
+                b.add(pts, SURFACE, cand[own])
+    if with_features:
+        _feature_particles(b, mesh, dx, rng, jitter)
+        b.add(mesh.singular, SINGULAR)
+    return _finish(name or f"cube_n{n}", [(geom, b)], move_mask, seed,
+                   {"dx": dx, "jitter": jitter})
+
+
+def dyadic_lattice_workload(m=16, dx=2.0 ** -5, k=1) -> Workload:
+    """Exact lattice of m^3 volume particles at (i+1/2)dx, no jitter, no mesh
+    constraints exercised: every coordinate is a binary32 value."""
+    mesh = M.cube((0.0, 0.0, 0.0), (m * dx, m * dx, m * dx))
+    geom = _make_geom(mesh, dx, k)
+    b = _Builder()
+    c = (np.arange(m) + 0.5) * dx
+    g = np.stack(np.meshgrid(c, c, c, indexing="ij"), -1).reshape(-1, 3)
+    b.add(g, VOLUME)
+    return _finish(f"dyadic_m{m}", [(geom, b)], 1 << VOLUME, 0, {"dx": dx})
+
+
+# ---------------------------------------------------------------------------
+# Sphere
+# ---------------------------------------------------------------------------
+
+def _facet_planes(mesh):
+    A = mesh.vert[mesh.tri[:, 0]]
+    B = mesh.vert[mesh.tri[:, 1]]
+    C = mesh.vert[mesh.tri[:, 2]]
+    n = np.cross(B - A, C - A)
+    n /= np.linalg.norm(n, axis=1)[:, None]
+    return A, B, C, n
+
+
+def _radial_map_sphere(mesh: M.Mesh, dirs: np.ndarray):
+    """Map unit directions from the origin onto the facet the ray hits."""
+    from scipy.spatial import cKDTree
+    A, B, C, n = _facet_planes(mesh)
+    cen = (A + B + C) / 3
+    cen /= np.linalg.norm(cen, axis=1)[:, None]
+    tree = cKDTree(cen)
+    _, cand = tree.query(dirs, k=8)
+    owner = np.full(len(dirs), -1, np.int64)
+    for c in range(cand.shape[1]):
+        t = cand[:, c]
+        s0 = np.einsum("ij,ij->i", np.cross(A[t], B[t]), dirs)
+        s1 = np.einsum("ij,ij->i", np.cross(B[t], C[t]), dirs)
+        s2 = np.einsum("ij,ij->i", np.cross(C[t], A[t]), dirs)
+        ok = (s0 >= 0) & (s1 >= 0) & (s2 >= 0) & (owner < 0)
+        owner[ok] = t[ok]
+    assert (owner >= 0).all(), "radial map: direction outside all candidate facets"
+    s = np.einsum("ij,ij->i", n[owner], A[owner]) / np.einsum("ij,ij->i", n[owner], dirs)
+    return dirs * s[:, None], owner
+
+
+def fibonacci_sphere(m: int) -> np.ndarray:
+    i = np.arange(m) + 0.5
+    z = 1.0 - 2.0 * i / m
+    r = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    phi = i * np.pi * (3.0 - np.sqrt(5.0))
+    return np.stack([r * np.cos(phi), r * np.sin(phi), z], 1)
+
+
+def sphere_workload(level=5, dx=0.01, jitter=0.3, seed=2, k=1, with_volume=True,
+                    with_surface=True, move_mask=ALL_MOVING, name=None) -> Workload:
+    """Icosphere of radius 1. Volume: jittered (i+1/2)dx lattice on [-1,1]^3 kept
+    where the distance to the mesh is at least dx/2 inside (tested against the
+    inscribed radius of the mesh). Surface: round(4 pi / dx^2) Fibonacci
+    directions with tangential jitter, mapped radially onto the facet they hit."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mesh = M.icosphere(level)
+    geom = _make_geom(mesh, dx, k)
+    A, B, C, n = _facet_planes(mesh)
+    r_in = float(np.min(np.einsum("ij,ij->i", n, A)))
+    b = _Builder()
+    if with_volume:
+        m = int(round(2.0 / dx))
+        c = -1.0 + (np.arange(m) + 0.5) * dx
+        keep = []
+        for ix in range(m):  # slab by slab to bound memory
+            yy, zz = np.meshgrid(c, c, indexing="ij")
+            g = np.stack([np.full(yy.size, c[ix]), yy.ravel(), zz.ravel()], 1)
+            g = g + rng.uniform(-jitter, jitter, g.shape) * dx
+            keep.append(g[np.linalg.norm(g, axis=1) <= r_in - 0.5 * dx])
+        b.add(np.concatenate(keep, 0), VOLUME)
+    if with_surface:
+        ms = int(round(4.0 * np.pi / dx ** 2))
+        d = fibonacci_sphere(ms)
+        d = d + rng.uniform(-jitter, jitter, d.shape) * dx
+        d /= np.linalg.norm(d, axis=1)[:, None]
+        p, own = _radial_map_sphere(mesh, d)
+        b.add(p, SURFACE, own)
+    return _finish(name or f"sphere_l{level}_dx{dx:g}", [(geom, b)], move_mask, seed,
+                   {"dx": dx, "jitter": jitter, "r_in": r_in})
+
+
+# ---------------------------------------------------------------------------
+# Regular tetrahedron
+# ---------------------------------------------------------------------------
+
+def _convex_inside(mesh, pts, margin):
+    """Points whose distance to every facet plane is at least `margin` inside (convex mesh)."""
+    A, B, C, n = _facet_planes(mesh)
+    sd = (pts @ n.T) - np.einsum("ij,ij->i", n, A)[None, :]
+    return np.all(sd <= -margin, axis=1)
+
+
+def tetra_workload(dx=0.045, jitter=0.3, seed=5, k=1, move_mask=ALL_MOVING, name=None) -> Workload:
+    """Regular tetrahedron of edge 1. Volume: jittered lattice at least dx/2
+    inside. Surface: per face a jittered square lattice in the face plane, kept
+    at least dx/2 from the face edges. Features on the 6 edges, 4 singular corners."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mesh = M.tetrahedron()
+    geom = _make_geom(mesh, dx, k)
+    b = _Builder()
+    lo, hi = mesh.bbox()
+    axes = [np.arange(lo[a] + 0.5 * dx, hi[a], dx) for a in range(3)]
+    g = np.stack(np.meshgrid(*axes, indexing="ij"), -1).reshape(-1, 3)
+    g = g + rng.uniform(-jitter, jitter, g.shape) * dx
+    b.add(g[_convex_inside(mesh, g, 0.5 * dx)], VOLUME)
+    A, B, C, n = _facet_planes(mesh)
+    for f in range(mesh.n_tri):
+        e0 = (B[f] - A[f]) / np.linalg.norm(B[f] - A[f])
+        e1 = np.cross(n[f], e0)
+        span = np.arange(-0.5, 1.5, dx)
+        uu, vv = np.meshgrid(span, span, indexing="ij")
+        uv = np.stack([uu.ravel(), vv.ravel()], 1)
+        uv = uv + rng.uniform(-jitter, jitter, uv.shape) * dx
+        pts = A[f] + uv[:, :1] * e0 + uv[:, 1:] * e1
+        # keep points inside the facet at least dx/2 from its edges
+        ok = np.ones(len(pts), bool)
+        for (P, Q) in ((A[f], B[f]), (B[f], C[f]), (C[f], A[f])):
+            ein = np.cross(n[f], Q - P)
+            ein /= np.linalg.norm(ein)
+            ok &= (pts - P) @ ein >= 0.5 * dx
+        b.add(pts[ok], SURFACE, np.full(int(ok.sum()), f))
+    _feature_particles(b, mesh, dx, rng, jitter)
+    b.add(mesh.singular, SINGULAR)
+    return _finish(name or f"tetra_dx{dx:g}", [(geom, b)], move_mask, seed, {"dx": dx})
+
+
+def custom_workload(mesh, dx, pos, tag, owner=None, feat_seg=None, feat_u=None,
+                    move_mask=ALL_MOVING, k=1, name="custom") -> Workload:
+    """A single-geometry workload from explicit particle arrays (for small cases)."""
+    geom = _make_geom(mesh, dx, k)
+    b = _Builder()
+    pos = np.asarray(pos, np.float64).reshape(-1, 3)
+    tag = np.asarray(tag, np.int32).reshape(-1)
+    owner = np.full(len(pos), -1, np.int32) if owner is None else np.asarray(owner, np.int32)
+    b.pos.append(pos)
+    b.tag.append(tag)
+    b.owner.append(owner)
+    if feat_seg is not None and len(feat_seg):
+        b.feat_seg.append(np.asarray(feat_seg, np.int32))
+        b.feat_u.append(np.asarray(feat_u, np.float64))
+    return _finish(name, [(geom, b)], move_mask, 0, {"dx": dx})
