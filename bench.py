@@ -1,0 +1,186 @@
+"""Benchmark: particle-relaxation iterations per second on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sphere|cube|gear]
+
+A step is one iteration of the relaxation loop (Algorithm 1 of arXiv
+2501.03056): cell rebuild, forces + time step + displacement, projection.
+Default workload: icosphere of radius 1 (subdivision level 5, 20,480 facets),
+dx = 0.01, h = 1.3 dx: ~4.13 M volume + 125,664 surface particles, all moving,
+synthetic and seeded (the paper's models are not available).
+
+Prints ONE JSON line with the whole-job throughput (particle-updates/s), the
+pair-evaluation rate, the force kernel's roofline figures (timed with HIP
+events on its launch stream, inside the timed region) and the CPU oracle timed
+on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3          # MI355X vector FP32 (published)
+PEAK_HBM_GBS = 8000.0
+FLOPS_PER_PAIR = 19               # see roofline_note()
+KERNEL_SOURCES = ["paper_2501_03056_amd/csrc/force.hip", "paper_2501_03056_amd/csrc/internal.h"]
+
+
+def roofline_note():
+    return ("algorithmic work of the force kernel = true (receiver, source) pairs x 19 flops: "
+            "3 sub + 3 mul + 2 add (squared distance), 1 sqrt, 1 fma (1 - r/2h), 2 mul (cube), "
+            "3 fma (accumulate); candidates rejected by the predicate are not counted")
+
+
+def make_workload(name):
+    import synth
+    if name == "sphere":
+        return synth.sphere_workload(level=5, dx=0.01, seed=2), "icosphere_l5_r1_dx0.01_h1.3dx"
+    if name == "cube":
+        return synth.cube_workload(n=24, seed=1), "unit_cube_dx1/24_h1.3dx"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def source_hash(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(kernel_hash):
+    """HBM bytes per force launch measured by rocprofv3 counters (committed
+    summary), or None if absent or taken on a different kernel source."""
+    p = os.path.join(ROOT, "profiles", "force_sphere_l5_counters.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_source_hash") != kernel_hash:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(wl, sample=160, seed=0):
+    """The oracle (brute force, FP64) on a bounded sample of the same step:
+    forces of `sample` moving receivers against all particles, then their
+    projection / inside test. Reported rate = sampled particle-updates / s."""
+    from oracle import force as oforce
+    from oracle import geometry as ogeo
+    from oracle import step as ostep
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mov = np.nonzero(oforce.moving_mask(wl.tag, wl.move_mask))[0]
+    rec = np.sort(rng.choice(mov, size=min(sample, len(mov)), replace=False))
+    t0 = time.perf_counter()
+    a, S, cnt = oforce.accel(wl, rec)
+    # the step needs amax over all particles; the sample uses its own max (same cost per particle)
+    tau = (float(wl.geoms[0].h) / 16.0) / max(np.linalg.norm(a, axis=1).max(), 1e-300)
+    y = wl.pos[rec].astype(np.float64) + tau * a
+    s = wl.tag[rec] == 2
+    if s.any():
+        ostep.project_surface(wl, y[s], 0)
+    v = wl.tag[rec] == 3
+    if v.any():
+        ogeo.winding_number(y[v], wl.geoms[0].mesh.vert, wl.geoms[0].mesh.tri)
+    dt = time.perf_counter() - t0
+    return {"value": len(rec) / dt, "unit": "particle-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(rec)} random moving particles of the same workload: brute-force forces against "
+                      f"all {wl.n} particles, FP64 projection over all facets or winding-number inside test "
+                      f"({dt:.1f} s, numpy single thread)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="sphere")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=160)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design "
+              "is described in DESIGN.md and is not built", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2501_03056_amd import Relaxer
+
+    t0 = time.perf_counter()
+    wl, wname = make_workload(args.workload)
+    print(f"[bench] workload {wname}: {wl.n} particles {wl.counts()} built in {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    r = Relaxer(wl, device=0)
+    n_moving = wl.n_moving()
+    for _ in range(args.warmup):
+        r.step(keep_accel=False)
+    # true pair count (separate counting pass, not timed)
+    r.build_cells()
+    r.relax_step(count_pairs=True)
+    r.project()
+    pairs0 = float(r.accel[:, 3].double().sum().item())
+    torch.cuda.synchronize()
+    print(f"[bench] warmup done, {pairs0:.4g} pairs/step", file=sys.stderr, flush=True)
+
+    r.profile(True)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    start.record()
+    for _ in range(args.steps):
+        r.step(keep_accel=False)
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = start.elapsed_time(stop)
+    prof = r.profile_read()
+    r.profile(False)
+    r.build_cells()
+    r.relax_step(count_pairs=True)
+    pairs1 = float(r.accel[:, 3].double().sum().item())
+    status = r.read_status()
+    pairs = 0.5 * (pairs0 + pairs1)
+
+    ms_step = ms / args.steps
+    value = n_moving * args.steps / (ms / 1e3)
+    f_ms, f_n = prof["force"]
+    force_ms = f_ms / max(f_n, 1)
+    achieved = pairs * FLOPS_PER_PAIR / (force_ms / 1e3) / 1e12
+    khash = source_hash(KERNEL_SOURCES)
+    traffic = traffic_from_profile(khash)
+    out = {
+        "metric": "particle-updates/s per relaxation step",
+        "value": value,
+        "unit": "particle-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wname, "particles": wl.n, "moving": n_moving, "facets": int(r.geom.n_tri),
+                   "stencil_k": int(wl.geoms[0].k), "h_over_dx": 1.3, "pairs_per_step": pairs},
+        "pair_evals_per_s": pairs * args.steps / (ms / 1e3),
+        "kernels_ms_per_step": {k: (v[0] / max(v[1], 1)) for k, v in prof.items() if v[1]},
+        "roofline": {"bound": "alu", "kernel": "k_force", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
+                     "work_per_launch": pairs * FLOPS_PER_PAIR, "avg_launch_ms": force_ms,
+                     "kernel_source_hash": khash},
+        "device_status": status,
+        "wall_s": wall,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,285 @@
+/*
+ * fppg.h - C ABI of the MI355X (gfx950) particle-relaxation library.
+ *
+ * The library implements the per-iteration hot path of the physics-based
+ * particle relaxation of the feature-preserving particle generation method
+ * (FPPG, arXiv 2501.03056, section 3.3, Algorithm 1):
+ *
+ *   fppg_build_cells  rebuild the cell-linked list of the particles by a
+ *                     counting sort on the cell key ("updating data
+ *                     structures", Algorithm 1; the paper's sorted compact
+ *                     list of section 3.1.3 is the analogue)
+ *   fppg_relax_step   Wendland C2 kernel-gradient repulsion (Eq. 15-17), the
+ *                     bounded time step, velocity reset and displacement
+ *                     (Eq. 22-23) restricted to the geometry (Eq. 24-25)
+ *   fppg_project      surface reprojection onto the nearest facet with revert
+ *                     (section 3.3.3), feature-line motion, volume particles
+ *                     kept inside the closed mesh
+ *   fppg_relax_hvp    Jacobian-vector product of the force field (Hessian-
+ *                     vector product of the pair energy), for Newton-Krylov
+ *                     relaxation and for differentiation
+ *
+ * Conventions
+ *  - Every function returns an fppg_status (0 = OK, < 0 = error) and never
+ *    throws. On error, fppg_last_error(ctx) describes it.
+ *  - Array arguments of the per-iteration calls (build_cells, relax_step,
+ *    project, relax_hvp, debug_neighbors) are DEVICE pointers owned by the
+ *    caller; the library never frees them and allocates nothing in these
+ *    calls: scratch memory is the caller's workspace `ws` of at least
+ *    fppg_workspace_size bytes (256-byte aligned).
+ *  - These calls only enqueue work on `stream` (a hipStream_t passed as
+ *    void*; NULL = the default stream) and do not synchronise. Conditions
+ *    found on the device (non-finite values) set bits of a device status word
+ *    read by fppg_read_status, which synchronises the stream.
+ *  - Positions are float4 arrays passed as float*, 16-byte aligned: x, y, z
+ *    in binary32 and w holding int32 bits  tag | (geometry << 8)  where tag is
+ *    the particle class 0 singular point, 1 feature-line particle, 2 surface
+ *    particle, 3 volume particle, 4 fixed volume particle (innermost layer),
+ *    and geometry is the index of the particle's geometry in the batch.
+ *  - Facets and feature segments are numbered globally over a batch: the
+ *    facets of geometry g follow those of geometries 0..g-1 (same for
+ *    segments). `owner` holds the global facet of a surface particle, the
+ *    feature slot (index into feat_seg / feat_u) of a feature particle, and
+ *    -1 otherwise.
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef FPPG_H
+#define FPPG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fppg_status;
+#define FPPG_OK             0
+#define FPPG_E_ARG         -1  /* invalid argument: null/misaligned pointer, bad size or descriptor */
+#define FPPG_E_HIP         -2  /* a HIP runtime call failed */
+#define FPPG_E_WORKSPACE   -3  /* workspace too small */
+#define FPPG_E_CAPACITY    -4  /* a fixed-size limit of the library was exceeded */
+#define FPPG_E_UNSUPPORTED -5  /* configuration not supported (e.g. stencil half-width) */
+#define FPPG_E_NODEVICE    -6  /* no usable gfx950 device */
+
+/* particle classes (low 3 bits of pos.w) */
+#define FPPG_TAG_SINGULAR 0
+#define FPPG_TAG_FEATURE  1
+#define FPPG_TAG_SURFACE  2
+#define FPPG_TAG_VOLUME   3
+#define FPPG_TAG_FIXED    4
+
+/* flags of fppg_relax_step */
+#define FPPG_F_COUNT_PAIRS 1u  /* accel.w = number of sources of the receiver (as float) */
+
+/* device status bits (fppg_read_status) */
+#define FPPG_S_NONFINITE_ACCEL 1u  /* a receiver's acceleration was not finite (it did not move) */
+#define FPPG_S_NONFINITE_POS   2u  /* a moved position was not finite (the move was reverted) */
+#define FPPG_S_BAD_INDEX       4u  /* a geometry, owner or feature index was out of range (particle held) */
+
+/* counters accumulated by fppg_project (int64 each) */
+#define FPPG_C_REVERT_SURFACE 0
+#define FPPG_C_REVERT_FEATURE 1
+#define FPPG_C_REVERT_VOLUME  2
+#define FPPG_C_SURFACE_MOVED  3
+#define FPPG_C_VOLUME_TESTED  4  /* volume moves that needed the surface-crossing test */
+#define FPPG_NCOUNTERS        8
+
+typedef struct fppg_ctx fppg_ctx;
+typedef struct fppg_geom fppg_geom;
+
+/*
+ * One geometry of a batch (host memory; fppg_geom_create copies it).
+ *
+ * Particle grid (cell list of section 3.1.1's uniform background grid,
+ * rebuilt every iteration): cell (cx, cy, cz) of a position p is
+ *   c = clamp(floor(fl32(fl32(p - origin) * inv_cell)), 0, dims - 1)
+ * (binary32, one rounding per operation) and its key is
+ *   cell_begin(g) + (cz * dims[1] + cy) * dims[0] + cx
+ * with cell_begin(g) the total cell count of geometries 0..g-1. The cell edge
+ * 1/inv_cell must be at least (2h/k)(1 + 2^-9) so that the (2k+1)^3 cell
+ * stencil holds every pair with q < 2; k is 1 or 2 and equal across a batch.
+ *
+ * Particles of geometry g occupy the index range [part_begin, part_end) of
+ * the particle arrays, which the cell sort preserves.
+ *
+ * Mesh: closed triangle surface, facets counter-clockwise seen from outside
+ * (outward normal (B-A)x(C-A)), FP64 vertices. Feature lines: line l has the
+ * segments line_seg_begin[l] .. line_seg_begin[l+1]-1 (local numbering), each
+ * segment s runs from seg_p[6s..6s+2] to seg_p[6s+3..6s+5], consecutive
+ * segments of a line are joined, line_closed[l] != 0 for a loop.
+ *
+ * proj_radius R: a surface projection is accepted only if the particle is
+ * within R of the facet plane (section 3.3.3). The facet search grid uses
+ * cells of edge R(1 + 2^-6), so R should be of the order of the support radius.
+ */
+typedef struct {
+  float   origin[3];
+  float   inv_cell;
+  int32_t dims[3];
+  int32_t k;
+  float   h;                 /* smoothing length; support radius 2h */
+  float   proj_radius;       /* R */
+  int64_t part_begin, part_end;
+  const double*  vert;  int32_t n_vert;   /* [n_vert * 3] */
+  const int32_t* tri;   int32_t n_tri;    /* [n_tri * 3] */
+  const int32_t* line_seg_begin; int32_t n_line;  /* [n_line + 1], may be NULL if n_line = 0 */
+  const double*  seg_p;                   /* [n_seg * 6], n_seg = line_seg_begin[n_line] */
+  const uint8_t* line_closed;             /* [n_line] */
+} fppg_geom_desc;
+
+/* ---- context ---------------------------------------------------------------------------- */
+
+/* Select HIP device `device` (must be gfx950), allocate the device status word. */
+fppg_status fppg_create(int32_t device, fppg_ctx** out);
+void        fppg_destroy(fppg_ctx* ctx);
+const char* fppg_status_str(fppg_status s);
+const char* fppg_last_error(const fppg_ctx* ctx);   /* never NULL */
+
+/* Synchronise `stream`, return the device status bits (FPPG_S_*) and clear them. */
+fppg_status fppg_read_status(fppg_ctx* ctx, void* stream, uint32_t* flags);
+
+/*
+ * Kernel timing with HIP events recorded on the launch stream. enable != 0
+ * creates the events (allocation happens here, not in the hot calls) and
+ * resets the accumulators; while enabled, every per-iteration call records an
+ * event pair around each of its phases. fppg_profile_read synchronises on the
+ * recorded events and returns, per phase, the summed milliseconds and the
+ * number of launches:
+ *   0 build_cells (all its kernels)  1 force + amax kernel
+ *   2 displacement kernel            3 project (all its kernels)
+ *   4 relax_hvp kernel
+ * Phase times are accumulated when read; at most 4096 launches per phase are
+ * kept between reads (further launches are not timed: count stops growing).
+ */
+#define FPPG_NPHASES 5
+fppg_status fppg_profile(fppg_ctx* ctx, int32_t enable);
+fppg_status fppg_profile_read(fppg_ctx* ctx, double* ms /*[FPPG_NPHASES]*/, int64_t* launches /*[FPPG_NPHASES]*/);
+
+/* ---- geometry ----------------------------------------------------------------------------- */
+
+/*
+ * Build the device-resident geometry of a batch of n_geom geometries: facet
+ * frames (FP64), the facet search grid (facets registered conservatively in
+ * every cell they touch, section 3.1.1-3.1.2; built on the host), feature
+ * segments, and the per-geometry particle-grid descriptors. Synchronous;
+ * allocates device memory owned by the returned object.
+ * Errors: FPPG_E_ARG for inconsistent descriptors (particle ranges must tile
+ * [0, n) in order, indices in range), FPPG_E_UNSUPPORTED for k not in {1, 2}
+ * or differing across the batch, FPPG_E_CAPACITY beyond 2^31 cells/entries.
+ */
+fppg_status fppg_geom_create(fppg_ctx* ctx, const fppg_geom_desc* descs, int32_t n_geom,
+                             fppg_geom** out);
+void        fppg_geom_destroy(fppg_geom* geom);
+
+/* Sizes of a built geometry: total particle cells (cell_start has ncell + 2
+ * entries), facets, segments, facet-search cells and their facet entries. */
+fppg_status fppg_geom_info(const fppg_geom* geom, int64_t* ncell, int64_t* n_tri, int64_t* n_seg,
+                           int64_t* search_cells, int64_t* search_entries);
+
+/* Workspace bytes needed by the per-iteration calls for n particles. */
+fppg_status fppg_workspace_size(const fppg_geom* geom, int64_t n, size_t* bytes);
+
+/* ---- per-iteration calls (device pointers, stream-ordered, no allocation) ---------------- */
+
+/*
+ * Counting sort of the particles by cell key, then by id inside a cell.
+ * in:  pos_in [n*4], id_in [n], owner_in [n] (ids unique per particle)
+ * out: pos_out, id_out, owner_out (must not alias the inputs), the same
+ *      particles in (key, id) order; cell_start [ncell + 2]: first sorted
+ *      index of every cell, then cell_start[ncell] = first index of the
+ *      quarantine range and cell_start[ncell + 1] = n. Particles with a
+ *      non-finite coordinate get the key ncell (after every geometry, where no
+ *      stencil reaches: they are nobody's neighbour) and FPPG_S_NONFINITE_POS.
+ * The order is deterministic (independent of atomic ordering).
+ */
+fppg_status fppg_build_cells(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
+                             const float* pos_in, const int32_t* id_in, const int32_t* owner_in,
+                             float* pos_out, int32_t* id_out, int32_t* owner_out,
+                             int32_t* cell_start, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Forces, time step and displacement of one iteration (Eq. 15-17, 22-25).
+ * pos [n*4] and cell_start come from fppg_build_cells. A particle moves iff
+ * its tag is 1, 2 or 3 and bit `tag` of move_mask is set. For every moving
+ * receiver i:
+ *   a_i = K sum_{j in src(i)} (1 - |r_ij|/2h)^3 r_ij,  r_ij = x_i - x_j,
+ *   K = 5 alpha / h^2, alpha = 21/(16 pi h^3) (Eq. 17's 3-D factor written
+ *   with the coefficient that normalises the kernel), prefactor of Eq. 15 = 1,
+ * where src(i) are the particles j != i of the geometry with
+ *   fl32(fl32(fl32(dx^2) + fl32(dy^2)) + fl32(dz^2)) < fl32(2h)^2 (binary32)
+ * and rank(tag_j) <= rank(tag_i), ranks 0,1,2,3,3 for tags 0..4
+ * (section 2.2: each class is bounded by the classes of lower rank).
+ * amax[g] = max |a_i| over moving i of geometry g; dt^2 = (h/16)/amax[g]
+ * (time-step reading: dt = 0.25 sqrt(h/amax)); v reset to 0 (Eq. 22), so the
+ * displacement is dr_i = dt^2 a_i, then restricted (Eq. 24-25):
+ *   surface: dr - (dr . n) n, n the normal of facet owner[i]
+ *   feature: du = dr . t in FP64, t the unit tangent of segment
+ *            feat_seg[owner[i]]; the double du is stored in the bytes of
+ *            disp[4i..4i+1] and disp[4i+2..4i+3] = 0.
+ *   volume:  dr;  non-moving: 0.
+ * Outputs: accel [n*4] (may be NULL: the workspace holds it; w = 0, or the
+ * source count with FPPG_F_COUNT_PAIRS), amax [n_geom] (float), disp [n*4].
+ * Non-finite accelerations are excluded from amax and give a zero
+ * displacement (FPPG_S_NONFINITE_ACCEL); an out-of-range owner or feature
+ * segment gives a zero displacement (FPPG_S_BAD_INDEX).
+ */
+fppg_status fppg_relax_step(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
+                            const float* pos, const int32_t* owner, const int32_t* cell_start,
+                            const int32_t* feat_seg, int32_t n_feat, uint32_t move_mask, uint32_t flags,
+                            float* accel, float* amax, float* disp,
+                            void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Apply the displacement and project back onto the geometry (section 3.3.3).
+ *  surface: y = x + dr (FP64); among the facets registered in the 27 search
+ *           cells around y, the plane foot p = y - d n with all barycentric
+ *           coordinates >= 0 and |d| <= R and the smallest |d| (ties: lowest
+ *           facet) wins: pos = fl32(p), owner = that facet; none: pos stays x
+ *           (revert).
+ *  feature: u' = u + du walked along the polyline of segment feat_seg[slot],
+ *           carrying into neighbouring segments; leaving an open line
+ *           reverts, a loop wraps; pos = fl32(p0 + u' t), feat_seg/feat_u
+ *           updated in place (slot = owner[i]).
+ *  volume:  y = fl32(x + dr); the move is reverted iff the segment [x, y]
+ *           meets a facet (x is inside, the step is shorter than a search
+ *           cell, so this equals "the signed distance of y is >= 0" for
+ *           meshes thicker than the step).
+ * pos [n*4] in: positions x, out: new positions; owner [n] in/out;
+ * disp [n*4] from fppg_relax_step; feat_seg/feat_u [n_feat] in/out (may be
+ * NULL if n_feat = 0); counters [FPPG_NCOUNTERS] int64 on the device,
+ * incremented (may be NULL).
+ */
+fppg_status fppg_project(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
+                         float* pos, int32_t* owner, const float* disp,
+                         int32_t* feat_seg, double* feat_u, int32_t n_feat, uint32_t move_mask,
+                         int64_t* counters, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Jacobian-vector product of the force field of fppg_relax_step with respect
+ * to the positions, at fixed neighbour sets (same traversal as the forces):
+ *   transpose = 0:  Jv_i = sum_{j in src(i)} M(r_ij) (v_i - v_j)  for moving i, else 0
+ *   transpose = 1:  Jv_k = [sum_{j in src(k)} M(r_kj)] v_k - sum_{i moving, k in src(i)} M(r_ik) v_i
+ *                   (first term only for moving k)
+ * with M(r) = K [ t^3 I - (3/2h) t^2 r r^T / |r| ], t = 1 - |r|/2h.
+ * For one moving class with fixed other sources J = -Hess(E) of the pair
+ * energy E and both products agree. v, Jv: [n*4] float (w ignored / 0).
+ */
+fppg_status fppg_relax_hvp(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
+                           const float* pos, const int32_t* cell_start, uint32_t move_mask,
+                           int32_t transpose, const float* v, float* Jv, void* stream);
+
+/*
+ * Test/diagnostic export of the neighbour sets seen by the force traversal:
+ * for every particle i (moving or not), count[i] = |{j != i : predicate}| over
+ * all tags of its geometry, and list[i*cap .. i*cap+min(count,cap)-1] the
+ * sorted indices j in traversal order. count [n] int32, list [n*cap] int32.
+ */
+fppg_status fppg_debug_neighbors(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
+                                 const float* pos, const int32_t* cell_start,
+                                 int32_t* count, int32_t* list, int32_t cap, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FPPG_H */

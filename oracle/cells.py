@@ -4,7 +4,9 @@ The paper keys its sparse background grid by Morton code and a compact hash
 (section 3.1.3, Eq. 9-10). For the particle cell list of the relaxation loop
 the key here is the plain x-fastest linear index of a uniform grid, offset per
 geometry of a batch; particles are ordered by (key, id), and cell_start[c] is
-the first sorted index of cell c (cell_start[ncell] = N).
+the first sorted index of cell c. A particle with a non-finite coordinate gets
+the key ncell (one past every geometry's cells; reading: such a particle is
+nobody's neighbour), so cell_start has ncell + 2 entries, the last being N.
 
 The cell coordinate is defined in binary32, one rounding per operation:
     t = fl32(fl32(x - origin) * inv_cell),  c = clamp(floor(t), 0, dim - 1)
@@ -33,6 +35,7 @@ def cell_keys(wl, pos32=None, gid=None) -> np.ndarray:
         c = cell_coords(pos32[m], geo.origin, geo.inv_cell, geo.dims)
         nx, ny = int(geo.dims[0]), int(geo.dims[1])
         keys[m] = geo.cell_begin + (c[:, 2] * ny + c[:, 1]) * nx + c[:, 0]
+    keys[~np.all(np.isfinite(pos32), axis=1)] = total_cells(wl)
     return keys
 
 
@@ -46,8 +49,9 @@ def sort_order(keys: np.ndarray, ids: np.ndarray) -> np.ndarray:
 
 
 def cell_start(sorted_keys: np.ndarray, ncell: int) -> np.ndarray:
-    """Exclusive prefix sum of the per-cell particle counts, length ncell + 1."""
-    counts = np.bincount(sorted_keys, minlength=ncell)
-    out = np.zeros(ncell + 1, np.int64)
+    """Exclusive prefix sum of the per-cell particle counts (the ncell cells
+    and the non-finite key ncell), length ncell + 2."""
+    counts = np.bincount(sorted_keys, minlength=ncell + 1)
+    out = np.zeros(ncell + 2, np.int64)
     np.cumsum(counts, out=out[1:])
     return out

@@ -1,0 +1,96 @@
+"""ctypes binding of libfppg.so: the entry points of include/fppg.h with the same names.
+
+Argument marshalling only. The library is built in-tree by build.py; loading
+fails loudly when it is missing or does not export the declared entry points.
+"""
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_float, c_int32, c_int64, c_size_t, c_uint8, c_uint32, c_void_p
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfppg.so")
+
+OK, E_ARG, E_HIP, E_WORKSPACE, E_CAPACITY, E_UNSUPPORTED, E_NODEVICE = 0, -1, -2, -3, -4, -5, -6
+F_COUNT_PAIRS = 1
+S_NONFINITE_ACCEL, S_NONFINITE_POS, S_BAD_INDEX = 1, 2, 4
+C_REVERT_SURFACE, C_REVERT_FEATURE, C_REVERT_VOLUME, C_SURFACE_MOVED, C_VOLUME_TESTED = 0, 1, 2, 3, 4
+NCOUNTERS = 8
+NPHASES = 5
+PHASES = ("build_cells", "force", "update", "project", "hvp")
+
+
+class GeomDesc(ctypes.Structure):
+    _fields_ = [
+        ("origin", c_float * 3), ("inv_cell", c_float), ("dims", c_int32 * 3), ("k", c_int32),
+        ("h", c_float), ("proj_radius", c_float), ("part_begin", c_int64), ("part_end", c_int64),
+        ("vert", POINTER(c_double)), ("n_vert", c_int32),
+        ("tri", POINTER(c_int32)), ("n_tri", c_int32),
+        ("line_seg_begin", POINTER(c_int32)), ("n_line", c_int32),
+        ("seg_p", POINTER(c_double)), ("line_closed", POINTER(c_uint8)),
+    ]
+
+
+_P = c_void_p
+_SIGS = {
+    "fppg_create": (c_int32, [c_int32, POINTER(c_void_p)]),
+    "fppg_destroy": (None, [_P]),
+    "fppg_status_str": (c_char_p, [c_int32]),
+    "fppg_last_error": (c_char_p, [_P]),
+    "fppg_read_status": (c_int32, [_P, _P, POINTER(c_uint32)]),
+    "fppg_profile": (c_int32, [_P, c_int32]),
+    "fppg_profile_read": (c_int32, [_P, POINTER(c_double), POINTER(c_int64)]),
+    "fppg_geom_create": (c_int32, [_P, POINTER(GeomDesc), c_int32, POINTER(c_void_p)]),
+    "fppg_geom_destroy": (None, [_P]),
+    "fppg_geom_info": (c_int32, [_P, POINTER(c_int64), POINTER(c_int64), POINTER(c_int64),
+                                 POINTER(c_int64), POINTER(c_int64)]),
+    "fppg_workspace_size": (c_int32, [_P, c_int64, POINTER(c_size_t)]),
+    "fppg_build_cells": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, _P, _P, _P, _P, c_size_t, _P]),
+    "fppg_relax_step": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, c_int32, c_uint32, c_uint32,
+                                  _P, _P, _P, _P, c_size_t, _P]),
+    "fppg_project": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, _P, c_int32, c_uint32, _P, _P,
+                               c_size_t, _P]),
+    "fppg_relax_hvp": (c_int32, [_P, _P, c_int64, _P, _P, c_uint32, c_int32, _P, _P, _P]),
+    "fppg_debug_neighbors": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, c_int32, _P]),
+}
+
+_lib = None
+
+
+class FppgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"fppg status {status}: {msg}")
+        self.status = status
+
+
+def lib():
+    """Load libfppg.so (building it first if it is not there)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        from .build import build
+        build()
+    L = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(L, name)        # AttributeError = library does not export it: fail loudly
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def check(status, ctx=None):
+    if status != OK:
+        L = lib()
+        msg = L.fppg_last_error(ctx).decode() if ctx else L.fppg_status_str(status).decode()
+        raise FppgError(status, msg or L.fppg_status_str(status).decode())
+    return status
+
+
+def ptr(t):
+    """Device (or host) address of a torch tensor / numpy array, or None."""
+    if t is None:
+        return None
+    if hasattr(t, "data_ptr"):
+        return c_void_p(t.data_ptr())
+    return c_void_p(t.ctypes.data)

@@ -1,0 +1,234 @@
+// Cell-list rebuild by counting sort (the "updating data structures" step of
+// Algorithm 1). The final order is (cell key, particle id): deterministic,
+// whatever order the atomics of the counting pass complete in.
+//
+//   fill      count[c] = 0
+//   key       key_i of every particle (non-finite positions: the quarantine
+//             key ncell, after every geometry), rank_i = arrival index in its cell
+//             (one atomic per run of equal keys in a wavefront: the input is
+//             the previous iteration's sorted order, so runs are long)
+//   scan      cell_start = exclusive prefix sum of count (reduce / top / down)
+//   scatter   slot = cell_start[key] + rank: id, source index and key to slot
+//   final     inside each cell, the rank of the particle's id among the cell's
+//             ids gives its final slot; gather pos/id/owner there
+#include "internal.h"
+
+namespace fppg {
+
+__device__ __forceinline__ int cell_key(const float4 p, const GeomDev& G) {
+  // binary32, one rounding per operation (file compiled without FP contraction)
+  float tx = (p.x - G.origin[0]) * G.inv_cell;
+  float ty = (p.y - G.origin[1]) * G.inv_cell;
+  float tz = (p.z - G.origin[2]) * G.inv_cell;
+  tx = fminf(fmaxf(tx, 0.0f), float(G.dims[0] - 1));   // fmaxf(NaN, 0) = 0
+  ty = fminf(fmaxf(ty, 0.0f), float(G.dims[1] - 1));
+  tz = fminf(fmaxf(tz, 0.0f), float(G.dims[2] - 1));
+  const int cx = int(floorf(tx)), cy = int(floorf(ty)), cz = int(floorf(tz));
+  return int(G.cell_begin) + (cz * G.dims[1] + cy) * G.dims[0] + cx;
+}
+
+__global__ void k_fill_i32(int* __restrict__ a, int64_t n, int v) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    a[i] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_key_count(const float4* __restrict__ pos, int n,
+                                                      const GeomDev* __restrict__ geoms, int n_geom,
+                                                      int quarantine, int* __restrict__ key,
+                                                      int* __restrict__ rank, int* __restrict__ count,
+                                                      uint32_t* status) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  int k = -1;
+  if (i < n) {
+    const float4 p = pos[i];
+    int g = geom_of(p.w);
+    if (g >= n_geom) {
+      atomicOr(status, FPPG_S_BAD_INDEX);
+      g = n_geom - 1;
+    }
+    if (isfinite(p.x) && isfinite(p.y) && isfinite(p.z)) {
+      k = cell_key(p, geoms[g]);
+    } else {
+      atomicOr(status, FPPG_S_NONFINITE_POS);
+      k = quarantine;   // after every geometry's cells: no stencil reaches it
+    }
+  }
+  // runs of equal keys among consecutive lanes share one atomic
+  const int kprev = __shfl_up(k, 1);
+  const bool head = (lane == 0) || (kprev != k);
+  const uint64_t heads = __ballot(head);
+  const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1);
+  const int start = 63 - __clzll(heads & upto);
+  const uint64_t above = heads & ~upto;
+  const int end = above ? (__ffsll((long long)above) - 1) : 64;
+  int base = 0;
+  if (head && k >= 0) base = atomicAdd(&count[k], end - lane);
+  base = __shfl(base, start);
+  if (i < n) {
+    key[i] = k;
+    rank[i] = base + (lane - start);
+  }
+}
+
+// Block-wide exclusive scan of 4 items per thread (1024 threads).
+constexpr int kScanThreads = 1024;
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(v, o);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// returns the exclusive prefix of `v` over the block and the block total
+__device__ __forceinline__ int block_excl_scan(int v, int* total) {
+  __shared__ int wsum[kScanThreads / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int inc = wave_incl_scan(v, lane);
+  if (lane == 63) wsum[wid] = inc;
+  __syncthreads();
+  if (wid == 0) {
+    int s = lane < kScanThreads / 64 ? wsum[lane] : 0;
+    s = wave_incl_scan(s, lane);
+    if (lane < kScanThreads / 64) wsum[lane] = s;
+  }
+  __syncthreads();
+  const int before = wid > 0 ? wsum[wid - 1] : 0;
+  *total = wsum[kScanThreads / 64 - 1];
+  __syncthreads();
+  return before + inc - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int* __restrict__ count, int64_t ncell,
+                                                              int* __restrict__ blocksum) {
+  const int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
+  int s = 0;
+#pragma unroll
+  for (int q = 0; q < kScanItems; ++q)
+    if (base + q < ncell) s += count[base + q];
+  int total;
+  block_excl_scan(s, &total);
+  if (threadIdx.x == 0) blocksum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_top(int* __restrict__ blocksum, int nb) {
+  int carry = 0;
+  for (int b0 = 0; b0 < nb; b0 += kScanThreads) {
+    const int b = b0 + threadIdx.x;
+    const int v = b < nb ? blocksum[b] : 0;
+    int total;
+    const int ex = block_excl_scan(v, &total);
+    if (b < nb) blocksum[b] = carry + ex;
+    carry += total;
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(const int* __restrict__ count, int64_t ncell,
+                                                            const int* __restrict__ blocksum,
+                                                            int* __restrict__ cell_start, int n) {
+  const int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
+  int v[kScanItems];
+  int s = 0;
+#pragma unroll
+  for (int q = 0; q < kScanItems; ++q) {
+    v[q] = (base + q < ncell) ? count[base + q] : 0;
+    s += v[q];
+  }
+  int total;
+  int ex = block_excl_scan(s, &total) + blocksum[blockIdx.x];
+#pragma unroll
+  for (int q = 0; q < kScanItems; ++q) {
+    if (base + q < ncell) cell_start[base + q] = ex;
+    ex += v[q];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) cell_start[ncell] = n;   // ncell here counts the quarantine cell
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter(const int* __restrict__ key, const int* __restrict__ rank,
+                                                    const int* __restrict__ id, const int* __restrict__ cell_start,
+                                                    int n, int* __restrict__ tmp_id, int* __restrict__ tmp_src,
+                                                    int* __restrict__ tmp_key) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int k = key[i];
+  const int slot = cell_start[k] + rank[i];
+  tmp_id[slot] = id[i];
+  tmp_src[slot] = i;
+  tmp_key[slot] = k;
+}
+
+__global__ __launch_bounds__(kBlock) void k_final(const int* __restrict__ tmp_id, const int* __restrict__ tmp_src,
+                                                  const int* __restrict__ tmp_key, const int* __restrict__ cell_start,
+                                                  int n, const float4* __restrict__ pos_in,
+                                                  const int* __restrict__ owner_in, float4* __restrict__ pos_out,
+                                                  int* __restrict__ id_out, int* __restrict__ owner_out) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int k = tmp_key[s];
+  const int b = cell_start[k], e = cell_start[k + 1];
+  const int my = tmp_id[s];
+  int r = 0;
+  for (int t = b; t < e; ++t) r += tmp_id[t] < my;
+  const int dst = b + r;
+  const int src = tmp_src[s];
+  pos_out[dst] = pos_in[src];
+  id_out[dst] = my;
+  owner_out[dst] = owner_in[src];
+}
+
+static inline int grid_for(int64_t n, int block) { return int((n + block - 1) / block); }
+
+}  // namespace fppg
+
+using namespace fppg;
+
+extern "C" fppg_status fppg_build_cells(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, const float* pos_in,
+                                        const int32_t* id_in, const int32_t* owner_in, float* pos_out,
+                                        int32_t* id_out, int32_t* owner_out, int32_t* cell_start, void* ws,
+                                        size_t ws_bytes, void* stream) {
+  if (!ctx || !geom) return fail(ctx, FPPG_E_ARG, "null ctx/geom");
+  if (n != geom->n_part) return fail(ctx, FPPG_E_ARG, "n differs from the particle count of the geometry descriptors");
+  if (n > 0 && (!pos_in || !id_in || !owner_in || !pos_out || !id_out || !owner_out))
+    return fail(ctx, FPPG_E_ARG, "null particle array");
+  if (!cell_start || !ws) return fail(ctx, FPPG_E_ARG, "null cell_start/ws");
+  if (!aligned(pos_in, 16) || !aligned(pos_out, 16) || !aligned(ws, 256))
+    return fail(ctx, FPPG_E_ARG, "pos must be 16-byte and ws 256-byte aligned");
+  if (pos_in == pos_out || id_in == id_out || owner_in == owner_out)
+    return fail(ctx, FPPG_E_ARG, "build_cells output must not alias its input");
+  const WsLayout L = ws_layout(geom, n);
+  if (ws_bytes < L.build_end) return fail(ctx, FPPG_E_WORKSPACE, "workspace too small for build_cells");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  int* key = reinterpret_cast<int*>(w + L.key);
+  int* rank = reinterpret_cast<int*>(w + L.rank);
+  int* tmp_id = reinterpret_cast<int*>(w + L.tmp_id);
+  int* tmp_src = reinterpret_cast<int*>(w + L.tmp_src);
+  int* tmp_key = reinterpret_cast<int*>(w + L.tmp_key);
+  int* count = reinterpret_cast<int*>(w + L.count);
+  int* blocksum = reinterpret_cast<int*>(w + L.blocksum);
+  const int64_t nc = geom->ncell + 1;   // the geometries' cells and the quarantine cell
+  const int nb = int((nc + kScanTile - 1) / kScanTile);
+  const int ni = int(n);
+  PhaseTimer timer(ctx, 0, s);
+  k_fill_i32<<<std::min(grid_for(nc, kBlock), 4096), kBlock, 0, s>>>(count, nc, 0);
+  if (ni > 0)
+    k_key_count<<<grid_for(ni, kBlock), kBlock, 0, s>>>(reinterpret_cast<const float4*>(pos_in), ni, geom->d_geom,
+                                                        geom->n_geom, int(geom->ncell), key, rank, count,
+                                                        ctx->d_status);
+  k_scan_reduce<<<nb, kScanThreads, 0, s>>>(count, nc, blocksum);
+  k_scan_top<<<1, kScanThreads, 0, s>>>(blocksum, nb);
+  k_scan_down<<<nb, kScanThreads, 0, s>>>(count, nc, blocksum, cell_start, ni);
+  if (ni > 0) {
+    k_scatter<<<grid_for(ni, kBlock), kBlock, 0, s>>>(key, rank, id_in, cell_start, ni, tmp_id, tmp_src, tmp_key);
+    k_final<<<grid_for(ni, kBlock), kBlock, 0, s>>>(tmp_id, tmp_src, tmp_key, cell_start, ni,
+                                                    reinterpret_cast<const float4*>(pos_in), owner_in,
+                                                    reinterpret_cast<float4*>(pos_out), id_out, owner_out);
+  }
+  FPPG_HIP(ctx, hipGetLastError());
+  return FPPG_OK;
+}

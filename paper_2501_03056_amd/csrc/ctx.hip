@@ -1,0 +1,482 @@
+// Context, errors, workspace layout and device-resident geometry of libfppg.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+namespace fppg {
+
+fppg_status fail(fppg_ctx* ctx, fppg_status s, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return s;
+}
+
+fppg_status hip_fail(fppg_ctx* ctx, hipError_t e, const char* what) {
+  if (ctx) ctx->err = std::string(what) + ": " + hipGetErrorString(e);
+  return FPPG_E_HIP;
+}
+
+static size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
+
+WsLayout ws_layout(const Geom* g, int64_t n) {
+  WsLayout L{};
+  const size_t N = size_t(n > 0 ? n : 1);
+  const size_t nc = size_t(g->ncell > 0 ? g->ncell : 1);
+  size_t o = 0;
+  L.key = o;      o += up256(4 * N);
+  L.rank = o;     o += up256(4 * N);
+  L.tmp_id = o;   o += up256(4 * N);
+  L.tmp_src = o;  o += up256(4 * N);
+  L.tmp_key = o;  o += up256(4 * N);
+  L.count = o;    o += up256(4 * (nc + 2));
+  L.blocksum = o; o += up256(4 * ((nc + 1 + 4095) / 4096 + 2));
+  L.build_end = o;
+  o = 0;
+  L.accel = o;    o += up256(16 * N);
+  L.step_end = o;
+  o = 0;
+  L.list_surf = o;  o += up256(4 * N);
+  L.list_feat = o;  o += up256(4 * N);
+  L.list_vol = o;   o += up256(4 * N);
+  L.list_count = o; o += up256(64);
+  L.project_end = o;
+  L.total = std::max(L.build_end, std::max(L.step_end, L.project_end));
+  return L;
+}
+
+// ---- facet search grid (host) ------------------------------------------------------------
+
+// Separating-axis test of a triangle against an axis-aligned box given by its
+// centre and half extents (the triangle-box overlap test of Akenine-Moeller,
+// written as the generic 13-axis separating-axis theorem: the 3 box normals,
+// the triangle normal and the 9 products of box axes with triangle edges).
+static bool tri_box_overlap(const double c[3], const double hw[3], const double* A,
+                            const double* B, const double* C) {
+  double v[3][3];
+  for (int q = 0; q < 3; ++q) {
+    v[0][q] = A[q] - c[q];
+    v[1][q] = B[q] - c[q];
+    v[2][q] = C[q] - c[q];
+  }
+  double e[3][3];
+  for (int q = 0; q < 3; ++q) {
+    e[0][q] = v[1][q] - v[0][q];
+    e[1][q] = v[2][q] - v[1][q];
+    e[2][q] = v[0][q] - v[2][q];
+  }
+  auto separated = [&](const double L[3]) {
+    if (L[0] == 0.0 && L[1] == 0.0 && L[2] == 0.0) return false;
+    double p0 = L[0] * v[0][0] + L[1] * v[0][1] + L[2] * v[0][2];
+    double p1 = L[0] * v[1][0] + L[1] * v[1][1] + L[2] * v[1][2];
+    double p2 = L[0] * v[2][0] + L[1] * v[2][1] + L[2] * v[2][2];
+    double lo = std::min(p0, std::min(p1, p2)), hi = std::max(p0, std::max(p1, p2));
+    double r = hw[0] * std::fabs(L[0]) + hw[1] * std::fabs(L[1]) + hw[2] * std::fabs(L[2]);
+    return lo > r || hi < -r;
+  };
+  for (int a = 0; a < 3; ++a) {
+    double L[3] = {0, 0, 0};
+    L[a] = 1.0;
+    if (separated(L)) return false;
+  }
+  double nrm[3] = {e[0][1] * e[1][2] - e[0][2] * e[1][1], e[0][2] * e[1][0] - e[0][0] * e[1][2],
+                   e[0][0] * e[1][1] - e[0][1] * e[1][0]};
+  if (separated(nrm)) return false;
+  for (int a = 0; a < 3; ++a) {
+    for (int k = 0; k < 3; ++k) {
+      double u[3] = {0, 0, 0};
+      u[a] = 1.0;
+      double L[3] = {u[1] * e[k][2] - u[2] * e[k][1], u[2] * e[k][0] - u[0] * e[k][2],
+                     u[0] * e[k][1] - u[1] * e[k][0]};
+      if (separated(L)) return false;
+    }
+  }
+  return true;
+}
+
+struct SearchGrid {
+  double origin[3], cell, inv;
+  int32_t dims[3];
+  std::vector<int64_t> start;  // [ncell + 1]
+  std::vector<int32_t> tri;    // global facet ids, ascending within a cell
+  std::vector<uint8_t> flag;
+};
+
+// Register every facet in every search cell it touches. Cells are padded by a
+// relative margin so that a point on a facet whose cell index is computed with
+// rounding still finds the facet in the computed cell.
+static fppg_status build_search_grid(fppg_ctx* ctx, const fppg_geom_desc& d, int32_t tri_begin,
+                                     SearchGrid& sg) {
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int32_t v = 0; v < d.n_vert; ++v)
+    for (int q = 0; q < 3; ++q) {
+      lo[q] = std::min(lo[q], d.vert[3 * v + q]);
+      hi[q] = std::max(hi[q], d.vert[3 * v + q]);
+    }
+  sg.cell = double(d.proj_radius) * (1.0 + 1.0 / 64.0);
+  sg.inv = 1.0 / sg.cell;
+  int64_t ncell = 1;
+  for (int q = 0; q < 3; ++q) {
+    sg.origin[q] = lo[q] - 2.0 * sg.cell;
+    double ext = (hi[q] - lo[q]) * sg.inv;
+    if (!(ext < 1e6)) return fail(ctx, FPPG_E_CAPACITY, "facet search grid too large (proj_radius too small)");
+    sg.dims[q] = int32_t(std::ceil(ext)) + 5;
+    ncell *= sg.dims[q];
+  }
+  if (ncell > (int64_t(1) << 30)) return fail(ctx, FPPG_E_CAPACITY, "facet search grid exceeds 2^30 cells");
+  const double pad = 1e-6 * sg.cell;
+  std::vector<std::pair<int64_t, int32_t>> reg;
+  for (int32_t t = 0; t < d.n_tri; ++t) {
+    const double* P[3] = {d.vert + 3 * d.tri[3 * t], d.vert + 3 * d.tri[3 * t + 1], d.vert + 3 * d.tri[3 * t + 2]};
+    int32_t c0[3], c1[3];
+    for (int q = 0; q < 3; ++q) {
+      double mn = std::min(P[0][q], std::min(P[1][q], P[2][q])) - pad;
+      double mx = std::max(P[0][q], std::max(P[1][q], P[2][q])) + pad;
+      c0[q] = std::max(0, int32_t(std::floor((mn - sg.origin[q]) * sg.inv)));
+      c1[q] = std::min(sg.dims[q] - 1, int32_t(std::floor((mx - sg.origin[q]) * sg.inv)));
+    }
+    for (int32_t z = c0[2]; z <= c1[2]; ++z)
+      for (int32_t y = c0[1]; y <= c1[1]; ++y)
+        for (int32_t x = c0[0]; x <= c1[0]; ++x) {
+          double cen[3] = {sg.origin[0] + (x + 0.5) * sg.cell, sg.origin[1] + (y + 0.5) * sg.cell,
+                           sg.origin[2] + (z + 0.5) * sg.cell};
+          double hw[3] = {0.5 * sg.cell + pad, 0.5 * sg.cell + pad, 0.5 * sg.cell + pad};
+          if (tri_box_overlap(cen, hw, P[0], P[1], P[2]))
+            reg.emplace_back((int64_t(z) * sg.dims[1] + y) * sg.dims[0] + x, tri_begin + t);
+        }
+  }
+  if (reg.size() >= (size_t(1) << 31)) return fail(ctx, FPPG_E_CAPACITY, "facet search grid exceeds 2^31 entries");
+  sg.start.assign(ncell + 1, 0);
+  for (auto& r : reg) sg.start[r.first + 1]++;
+  for (int64_t c = 0; c < ncell; ++c) sg.start[c + 1] += sg.start[c];
+  sg.tri.resize(reg.size());
+  std::vector<int64_t> cur(sg.start.begin(), sg.start.end() - 1);
+  for (auto& r : reg) sg.tri[cur[r.first]++] = r.second;  // facets visited in ascending order
+  sg.flag.assign(ncell, 0);
+  const int32_t nx = sg.dims[0], ny = sg.dims[1], nz = sg.dims[2];
+  for (int32_t z = 0; z < nz; ++z)
+    for (int32_t y = 0; y < ny; ++y)
+      for (int32_t x = 0; x < nx; ++x) {
+        int64_t c = (int64_t(z) * ny + y) * nx + x;
+        if (sg.start[c + 1] == sg.start[c]) continue;
+        sg.flag[c] |= kCellHasFacet;
+        for (int dz = -1; dz <= 1; ++dz)
+          for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+              int32_t xx = x + dx, yy = y + dy, zz = z + dz;
+              if (xx < 0 || yy < 0 || zz < 0 || xx >= nx || yy >= ny || zz >= nz) continue;
+              sg.flag[(int64_t(zz) * ny + yy) * nx + xx] |= kCellNearSurface;
+            }
+      }
+  return FPPG_OK;
+}
+
+template <class T>
+static fppg_status upload(fppg_ctx* ctx, T** dst, const std::vector<T>& src) {
+  size_t bytes = std::max<size_t>(1, src.size()) * sizeof(T);
+  FPPG_HIP(ctx, hipMalloc(reinterpret_cast<void**>(dst), bytes));
+  if (!src.empty()) FPPG_HIP(ctx, hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+  return FPPG_OK;
+}
+
+static void free_geom(Geom* g) {
+  if (!g) return;
+  hipFree(g->d_geom);
+  hipFree(g->d_facet);
+  hipFree(g->d_n32);
+  hipFree(g->d_seg);
+  hipFree(g->d_tg_start);
+  hipFree(g->d_tg_tri);
+  hipFree(g->d_tg_flag);
+}
+
+static fppg_status geom_create(fppg_ctx* ctx, const fppg_geom_desc* descs, int32_t n_geom,
+                               fppg_geom** out) {
+  if (!ctx || !out) return fail(ctx, FPPG_E_ARG, "null ctx/out");
+  *out = nullptr;
+  if (!descs || n_geom < 1 || n_geom > kMaxGeom) return fail(ctx, FPPG_E_ARG, "n_geom out of range");
+  const int32_t k = descs[0].k;
+  if (k != 1 && k != 2) return fail(ctx, FPPG_E_UNSUPPORTED, "stencil half-width k must be 1 or 2");
+  std::vector<GeomDev> gd(n_geom);
+  std::vector<FacetDev> facets;
+  std::vector<float4> n32;
+  std::vector<SegDev> segs;
+  std::vector<int32_t> tg_start;   // global
+  std::vector<int32_t> tg_tri;
+  std::vector<uint8_t> tg_flag;
+  int64_t ncell = 0, part = 0, tg_cells = 0;
+  int32_t tri_off = 0, seg_off = 0;
+  for (int32_t g = 0; g < n_geom; ++g) {
+    const fppg_geom_desc& d = descs[g];
+    GeomDev& G = gd[g];
+    if (d.k != k) return fail(ctx, FPPG_E_UNSUPPORTED, "stencil half-width differs across the batch");
+    if (!(d.h > 0.f) || !(d.proj_radius > 0.f) || !(d.inv_cell > 0.f) || !std::isfinite(d.inv_cell))
+      return fail(ctx, FPPG_E_ARG, "geometry " + std::to_string(g) + ": h, proj_radius, inv_cell must be > 0");
+    if (d.part_begin != part || d.part_end < d.part_begin)
+      return fail(ctx, FPPG_E_ARG, "geometry " + std::to_string(g) + ": particle ranges must tile [0, n) in order");
+    const float rc = 2.0f * d.h;
+    if (double(1.0f / d.inv_cell) * k < double(rc) * (1.0 + 1.0 / 512.0) ||
+        1.0 / double(d.inv_cell) * k < double(rc) * (1.0 + 1.0 / 512.0))
+      return fail(ctx, FPPG_E_ARG, "geometry " + std::to_string(g) + ": cell edge smaller than (2h/k)(1+2^-9)");
+    int64_t nc = 1;
+    for (int q = 0; q < 3; ++q) {
+      if (d.dims[q] < 1) return fail(ctx, FPPG_E_ARG, "dims must be >= 1");
+      nc *= d.dims[q];
+      G.origin[q] = d.origin[q];
+      G.dims[q] = d.dims[q];
+    }
+    G.inv_cell = d.inv_cell;
+    G.k = k;
+    G.h = d.h;
+    G.rc2 = rc * rc;
+    G.R = d.proj_radius;
+    const double hd = d.h;
+    G.kcoef = float(105.0 / (16.0 * M_PI * hd * hd * hd * hd * hd));
+    G.cell_begin = ncell;
+    G.part_begin = d.part_begin;
+    G.part_end = d.part_end;
+    ncell += nc;
+    if (ncell >= (int64_t(1) << 31) - 1) return fail(ctx, FPPG_E_CAPACITY, "more than 2^31 particle cells");
+    part = d.part_end;
+    // mesh
+    if (d.n_tri < 0 || d.n_vert < 0 || (d.n_tri > 0 && (!d.tri || !d.vert)))
+      return fail(ctx, FPPG_E_ARG, "geometry " + std::to_string(g) + ": bad mesh arrays");
+    for (int64_t i = 0; i < int64_t(d.n_tri) * 3; ++i)
+      if (d.tri[i] < 0 || d.tri[i] >= d.n_vert) return fail(ctx, FPPG_E_ARG, "facet vertex index out of range");
+    G.tri_begin = tri_off;
+    G.tri_end = tri_off + d.n_tri;
+    for (int32_t t = 0; t < d.n_tri; ++t) {
+      const double* A = d.vert + 3 * d.tri[3 * t];
+      const double* B = d.vert + 3 * d.tri[3 * t + 1];
+      const double* C = d.vert + 3 * d.tri[3 * t + 2];
+      FacetDev f;
+      for (int q = 0; q < 3; ++q) {
+        f.a[q] = A[q];
+        f.e0[q] = B[q] - A[q];
+        f.e1[q] = C[q] - A[q];
+      }
+      double nn[3] = {f.e0[1] * f.e1[2] - f.e0[2] * f.e1[1], f.e0[2] * f.e1[0] - f.e0[0] * f.e1[2],
+                      f.e0[0] * f.e1[1] - f.e0[1] * f.e1[0]};
+      double ln = std::sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
+      if (!(ln > 0)) return fail(ctx, FPPG_E_ARG, "degenerate facet " + std::to_string(t));
+      for (int q = 0; q < 3; ++q) f.n[q] = nn[q] / ln;
+      f.d00 = f.e0[0] * f.e0[0] + f.e0[1] * f.e0[1] + f.e0[2] * f.e0[2];
+      f.d01 = f.e0[0] * f.e1[0] + f.e0[1] * f.e1[1] + f.e0[2] * f.e1[2];
+      f.d11 = f.e1[0] * f.e1[0] + f.e1[1] * f.e1[1] + f.e1[2] * f.e1[2];
+      f.inv_den = 1.0 / (f.d00 * f.d11 - f.d01 * f.d01);
+      facets.push_back(f);
+      n32.push_back(make_float4(float(f.n[0]), float(f.n[1]), float(f.n[2]), 0.f));
+    }
+    // feature segments
+    G.seg_begin = seg_off;
+    if (d.n_line < 0 || (d.n_line > 0 && (!d.line_seg_begin || !d.seg_p || !d.line_closed)))
+      return fail(ctx, FPPG_E_ARG, "bad feature-line arrays");
+    int32_t nseg = d.n_line > 0 ? d.line_seg_begin[d.n_line] : 0;
+    for (int32_t l = 0; l < d.n_line; ++l) {
+      int32_t b = d.line_seg_begin[l], e = d.line_seg_begin[l + 1];
+      if (b < 0 || e < b || e > nseg) return fail(ctx, FPPG_E_ARG, "line_seg_begin not monotone");
+      for (int32_t s = b; s < e; ++s) {
+        SegDev sd;
+        const double* p = d.seg_p + 6 * s;
+        double v[3] = {p[3] - p[0], p[4] - p[1], p[5] - p[2]};
+        sd.len = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        if (!(sd.len > 0)) return fail(ctx, FPPG_E_ARG, "zero-length feature segment");
+        for (int q = 0; q < 3; ++q) {
+          sd.p0[q] = p[q];
+          sd.t[q] = v[q] / sd.len;
+        }
+        sd.lo = seg_off + b;
+        sd.hi = seg_off + e;
+        sd.closed = d.line_closed[l] ? 1 : 0;
+        sd.pad = 0;
+        segs.push_back(sd);
+      }
+    }
+    seg_off += nseg;
+    G.seg_end = seg_off;
+    // facet search grid
+    SearchGrid sg;
+    fppg_status st = build_search_grid(ctx, d, tri_off, sg);
+    if (st != FPPG_OK) return st;
+    tri_off += d.n_tri;
+    for (int q = 0; q < 3; ++q) {
+      G.tg_origin[q] = sg.origin[q];
+      G.tg_dims[q] = sg.dims[q];
+    }
+    G.tg_inv = sg.inv;
+    G.pad0 = 0;
+    G.tg_begin = tg_cells;
+    const int64_t base = int64_t(tg_tri.size());
+    if (base + int64_t(sg.tri.size()) >= (int64_t(1) << 31))
+      return fail(ctx, FPPG_E_CAPACITY, "facet search grid exceeds 2^31 entries");
+    for (size_t c = 0; c + 1 < sg.start.size(); ++c) tg_start.push_back(int32_t(base + sg.start[c]));
+    tg_tri.insert(tg_tri.end(), sg.tri.begin(), sg.tri.end());
+    tg_flag.insert(tg_flag.end(), sg.flag.begin(), sg.flag.end());
+    tg_cells += int64_t(sg.flag.size());
+  }
+  tg_start.push_back(int32_t(tg_tri.size()));
+  Geom* geo = new (std::nothrow) fppg_geom();
+  if (!geo) return fail(ctx, FPPG_E_CAPACITY, "out of host memory");
+  geo->n_geom = n_geom;
+  geo->k = k;
+  geo->ncell = ncell;
+  geo->n_tri = tri_off;
+  geo->n_seg = seg_off;
+  geo->tg_cells = tg_cells;
+  geo->tg_entries = int64_t(tg_tri.size());
+  geo->n_part = part;
+  geo->host = gd;
+  geo->device = ctx->device;
+  fppg_status st = FPPG_OK;
+  if ((st = upload(ctx, &geo->d_geom, gd)) != FPPG_OK || (st = upload(ctx, &geo->d_facet, facets)) != FPPG_OK ||
+      (st = upload(ctx, &geo->d_n32, n32)) != FPPG_OK || (st = upload(ctx, &geo->d_seg, segs)) != FPPG_OK ||
+      (st = upload(ctx, &geo->d_tg_start, tg_start)) != FPPG_OK ||
+      (st = upload(ctx, &geo->d_tg_tri, tg_tri)) != FPPG_OK || (st = upload(ctx, &geo->d_tg_flag, tg_flag)) != FPPG_OK) {
+    free_geom(geo);
+    delete static_cast<fppg_geom*>(geo);
+    return st;
+  }
+  *out = static_cast<fppg_geom*>(geo);
+  return FPPG_OK;
+}
+
+}  // namespace fppg
+
+using namespace fppg;
+
+extern "C" {
+
+const char* fppg_status_str(fppg_status s) {
+  switch (s) {
+    case FPPG_OK: return "ok";
+    case FPPG_E_ARG: return "invalid argument";
+    case FPPG_E_HIP: return "HIP runtime error";
+    case FPPG_E_WORKSPACE: return "workspace too small";
+    case FPPG_E_CAPACITY: return "capacity exceeded";
+    case FPPG_E_UNSUPPORTED: return "unsupported configuration";
+    case FPPG_E_NODEVICE: return "no usable gfx950 device";
+    default: return "unknown status";
+  }
+}
+
+const char* fppg_last_error(const fppg_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+fppg_status fppg_create(int32_t device, fppg_ctx** out) {
+  if (!out) return FPPG_E_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return FPPG_E_NODEVICE;
+  if (device < 0 || device >= count) return FPPG_E_ARG;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return FPPG_E_NODEVICE;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return FPPG_E_NODEVICE;
+  if (hipSetDevice(device) != hipSuccess) return FPPG_E_NODEVICE;
+  fppg_ctx* ctx = new (std::nothrow) fppg_ctx();
+  if (!ctx) return FPPG_E_CAPACITY;
+  ctx->device = device;
+  if (hipMalloc(reinterpret_cast<void**>(&ctx->d_status), 64) != hipSuccess ||
+      hipMemset(ctx->d_status, 0, 64) != hipSuccess) {
+    delete ctx;
+    return FPPG_E_HIP;
+  }
+  *out = ctx;
+  return FPPG_OK;
+}
+
+static void destroy_events(fppg_ctx* ctx) {
+  for (auto& p : ctx->prof) {
+    for (auto e : p.start) hipEventDestroy(e);
+    for (auto e : p.stop) hipEventDestroy(e);
+    p.start.clear();
+    p.stop.clear();
+    p.used = 0;
+    p.ms = 0.0;
+    p.launches = 0;
+  }
+  ctx->profiling = false;
+}
+
+void fppg_destroy(fppg_ctx* ctx) {
+  if (!ctx) return;
+  destroy_events(ctx);
+  hipFree(ctx->d_status);
+  delete ctx;
+}
+
+fppg_status fppg_profile(fppg_ctx* ctx, int32_t enable) {
+  if (!ctx) return FPPG_E_ARG;
+  FPPG_HIP(ctx, hipSetDevice(ctx->device));
+  destroy_events(ctx);
+  if (!enable) return FPPG_OK;
+  for (auto& p : ctx->prof) {
+    p.start.resize(kProfSlots);
+    p.stop.resize(kProfSlots);
+    for (int i = 0; i < kProfSlots; ++i) {
+      FPPG_HIP(ctx, hipEventCreate(&p.start[i]));
+      FPPG_HIP(ctx, hipEventCreate(&p.stop[i]));
+    }
+  }
+  ctx->profiling = true;
+  return FPPG_OK;
+}
+
+fppg_status fppg_profile_read(fppg_ctx* ctx, double* ms, int64_t* launches) {
+  if (!ctx || !ms || !launches) return fail(ctx, FPPG_E_ARG, "null argument");
+  for (int ph = 0; ph < FPPG_NPHASES; ++ph) {
+    PhaseProf& p = ctx->prof[ph];
+    for (int i = 0; i < p.used; ++i) {
+      FPPG_HIP(ctx, hipEventSynchronize(p.stop[i]));
+      float t = 0.f;
+      FPPG_HIP(ctx, hipEventElapsedTime(&t, p.start[i], p.stop[i]));
+      p.ms += t;
+      p.launches++;
+    }
+    p.used = 0;
+    ms[ph] = p.ms;
+    launches[ph] = p.launches;
+  }
+  return FPPG_OK;
+}
+
+fppg_status fppg_read_status(fppg_ctx* ctx, void* stream, uint32_t* flags) {
+  if (!ctx || !flags) return fail(ctx, FPPG_E_ARG, "null ctx/flags");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  uint32_t v = 0;
+  FPPG_HIP(ctx, hipMemcpyAsync(&v, ctx->d_status, 4, hipMemcpyDeviceToHost, s));
+  FPPG_HIP(ctx, hipStreamSynchronize(s));
+  FPPG_HIP(ctx, hipMemsetAsync(ctx->d_status, 0, 4, s));
+  FPPG_HIP(ctx, hipStreamSynchronize(s));
+  *flags = v;
+  return FPPG_OK;
+}
+
+fppg_status fppg_geom_create(fppg_ctx* ctx, const fppg_geom_desc* descs, int32_t n_geom, fppg_geom** out) {
+  if (ctx) FPPG_HIP(ctx, hipSetDevice(ctx->device));
+  return geom_create(ctx, descs, n_geom, out);
+}
+
+void fppg_geom_destroy(fppg_geom* geom) {
+  if (!geom) return;
+  free_geom(geom);
+  delete geom;
+}
+
+fppg_status fppg_geom_info(const fppg_geom* g, int64_t* ncell, int64_t* n_tri, int64_t* n_seg,
+                           int64_t* search_cells, int64_t* search_entries) {
+  if (!g) return FPPG_E_ARG;
+  if (ncell) *ncell = g->ncell;
+  if (n_tri) *n_tri = g->n_tri;
+  if (n_seg) *n_seg = g->n_seg;
+  if (search_cells) *search_cells = g->tg_cells;
+  if (search_entries) *search_entries = g->tg_entries;
+  return FPPG_OK;
+}
+
+fppg_status fppg_workspace_size(const fppg_geom* g, int64_t n, size_t* bytes) {
+  if (!g || !bytes || n < 0) return FPPG_E_ARG;
+  *bytes = ws_layout(g, n).total;
+  return FPPG_OK;
+}
+
+}  // extern "C"

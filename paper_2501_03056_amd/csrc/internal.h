@@ -1,0 +1,154 @@
+// Internal definitions shared by the HIP translation units of libfppg.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fppg.h"
+
+namespace fppg {
+
+constexpr int kBlock = 256;          // threads per block of the streaming kernels
+constexpr int kMaxGeom = 1 << 16;    // geometry index lives in bits 8..23 of pos.w
+
+// Per-geometry descriptor as the kernels read it (device array, one per geometry).
+struct GeomDev {
+  float origin[3];
+  float inv_cell;
+  int32_t dims[3];
+  int32_t k;
+  float h;
+  float rc2;        // fl32(fl32(2h)^2)
+  float R;          // projection radius
+  float kcoef;      // K = 5 alpha / h^2 (binary32)
+  int64_t cell_begin;
+  int64_t part_begin, part_end;
+  // facet search grid
+  double tg_origin[3];
+  double tg_inv;    // 1 / search-cell edge
+  int32_t tg_dims[3];
+  int32_t pad0;
+  int64_t tg_begin; // offset of this geometry's cells in the global search-cell arrays
+  int32_t tri_begin, tri_end, seg_begin, seg_end;
+};
+
+// FP64 facet frame for the projection and crossing tests.
+struct FacetDev {
+  double a[3];      // vertex A
+  double n[3];      // unit outward normal
+  double e0[3];     // B - A
+  double e1[3];     // C - A
+  double d00, d01, d11, inv_den;  // Gram matrix of (e0, e1) and 1/det
+};
+
+// FP64 feature segment: start point, unit tangent, length, its line's segment range.
+struct SegDev {
+  double p0[3];
+  double t[3];
+  double len;
+  int32_t lo, hi;   // global segment range [lo, hi) of the segment's line
+  int32_t closed;
+  int32_t pad;
+};
+
+// Search-cell flag bits.
+constexpr uint8_t kCellHasFacet = 1;
+constexpr uint8_t kCellNearSurface = 2;   // the cell or one of its 26 neighbours holds a facet
+
+struct Geom {
+  int32_t n_geom = 0;
+  int32_t k = 1;
+  int64_t ncell = 0;
+  int64_t n_tri = 0, n_seg = 0;
+  int64_t tg_cells = 0, tg_entries = 0;
+  int64_t n_part = 0;
+  std::vector<GeomDev> host;
+  GeomDev* d_geom = nullptr;
+  FacetDev* d_facet = nullptr;
+  float4* d_n32 = nullptr;          // binary32 unit normals (tangential projection)
+  SegDev* d_seg = nullptr;
+  int32_t* d_tg_start = nullptr;    // [tg_cells + 1]
+  int32_t* d_tg_tri = nullptr;      // [tg_entries] global facet ids
+  uint8_t* d_tg_flag = nullptr;     // [tg_cells]
+  int device = 0;
+};
+
+}  // namespace fppg
+
+namespace fppg {
+constexpr int kProfSlots = 4096;
+struct PhaseProf {
+  std::vector<hipEvent_t> start, stop;
+  int used = 0;          // event pairs recorded since the last read
+  double ms = 0.0;       // accumulated at read time
+  int64_t launches = 0;
+};
+}  // namespace fppg
+
+struct fppg_ctx {
+  int device = 0;
+  std::string err;
+  uint32_t* d_status = nullptr;     // device status word
+  bool profiling = false;
+  fppg::PhaseProf prof[FPPG_NPHASES];
+};
+
+struct fppg_geom : fppg::Geom {};
+
+namespace fppg {
+
+// Record an error message in the context and return the status.
+fppg_status fail(fppg_ctx* ctx, fppg_status s, const std::string& msg);
+fppg_status hip_fail(fppg_ctx* ctx, hipError_t e, const char* what);
+
+#define FPPG_HIP(ctx, call)                                   \
+  do {                                                        \
+    hipError_t e_ = (call);                                   \
+    if (e_ != hipSuccess) return fppg::hip_fail(ctx, e_, #call); \
+  } while (0)
+
+inline bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+// Event pair around one phase of a per-iteration call (no-op unless profiling).
+struct PhaseTimer {
+  PhaseProf* p = nullptr;
+  hipStream_t s;
+  PhaseTimer(fppg_ctx* ctx, int phase, hipStream_t stream) : s(stream) {
+    if (ctx && ctx->profiling && ctx->prof[phase].used < kProfSlots) {
+      p = &ctx->prof[phase];
+      hipEventRecord(p->start[p->used], s);
+    }
+  }
+  ~PhaseTimer() {
+    if (p) {
+      hipEventRecord(p->stop[p->used], s);
+      p->used++;
+    }
+  }
+};
+
+// Workspace layout (byte offsets from the workspace base, 256-aligned).
+struct WsLayout {
+  // build_cells
+  size_t key, rank, tmp_id, tmp_src, tmp_key, count, blocksum, build_end;
+  // relax_step
+  size_t accel, step_end;
+  // project
+  size_t list_surf, list_feat, list_vol, list_count, project_end;
+  size_t total;
+};
+WsLayout ws_layout(const Geom* g, int64_t n);
+
+// Device helpers ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int tag_of(float w) { return __float_as_int(w) & 7; }
+__device__ __forceinline__ int geom_of(float w) { return (__float_as_int(w) >> 8) & 0xFFFF; }
+__device__ __forceinline__ int rank_of(int tag) { return tag < 3 ? tag : 3; }
+__device__ __forceinline__ bool is_moving(int tag, uint32_t move_mask) {
+  return tag >= 1 && tag <= 3 && ((move_mask >> tag) & 1u);
+}
+
+}  // namespace fppg

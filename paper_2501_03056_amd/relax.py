@@ -1,0 +1,247 @@
+"""Python driver of the relaxation loop (Algorithm 1) on one GPU.
+
+`Relaxer` owns the device state of a batch of geometries as torch tensors
+(torch provides the device memory and the stream) and calls the four C-ABI
+entry points in order every iteration:
+
+    build_cells -> relax_step -> project
+
+Particle state (structure of arrays, sorted by (cell, id) after build_cells):
+    pos    float32 [N, 4]  x, y, z and the int32 bits tag | geometry << 8
+    id     int32   [N]     original particle index
+    owner  int32   [N]     facet (surface), feature slot (feature), else -1
+    feat_seg int32 [F], feat_u float64 [F]  feature table (by slot, not permuted)
+All arithmetic runs in the library's kernels; this module only marshals.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from ._lib import check, ptr
+
+
+def _pack_w(tag: np.ndarray, gid: np.ndarray) -> np.ndarray:
+    bits = (np.asarray(tag, np.int32) & 7) | (np.asarray(gid, np.int32) << 8)
+    return bits.astype(np.int32).view(np.float32)
+
+
+def geom_descs(geoms):
+    """ctypes descriptors of a batch; returns (array, keep-alive list)."""
+    arr = (L.GeomDesc * len(geoms))()
+    keep = []
+    for g, geo in enumerate(geoms):
+        d = arr[g]
+        for q in range(3):
+            d.origin[q] = float(geo.origin[q])
+            d.dims[q] = int(geo.dims[q])
+        d.inv_cell = float(geo.inv_cell)
+        d.k = int(geo.k)
+        d.h = float(geo.h)
+        d.proj_radius = float(geo.proj_radius)
+        d.part_begin = int(geo.part_begin)
+        d.part_end = int(geo.part_end)
+        vert = np.ascontiguousarray(geo.mesh.vert, np.float64)
+        tri = np.ascontiguousarray(geo.mesh.tri, np.int32)
+        lines = geo.mesh.lines
+        lsb = np.ascontiguousarray(lines.line_seg_begin, np.int32)
+        segp = np.ascontiguousarray(lines.seg_p, np.float64).reshape(-1)
+        closed = np.ascontiguousarray(lines.line_closed, np.uint8)
+        keep += [vert, tri, lsb, segp, closed]
+        d.vert = vert.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.n_vert = len(vert)
+        d.tri = tri.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        d.n_tri = len(tri)
+        d.line_seg_begin = lsb.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        d.n_line = int(lines.n_line)
+        d.seg_p = segp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if len(segp) else None
+        d.line_closed = closed.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)) if len(closed) else None
+    return arr, keep
+
+
+class Context:
+    """fppg_create / fppg_destroy."""
+
+    def __init__(self, device: int = 0):
+        self.lib = L.lib()
+        h = ctypes.c_void_p()
+        check(self.lib.fppg_create(int(device), ctypes.byref(h)))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            self.lib.fppg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Geometry:
+    """fppg_geom_create / fppg_geom_destroy for a batch of geometries."""
+
+    def __init__(self, ctx: Context, geoms):
+        arr, keep = geom_descs(geoms)
+        h = ctypes.c_void_p()
+        check(ctx.lib.fppg_geom_create(ctx.handle, arr, len(geoms), ctypes.byref(h)), ctx.handle)
+        self.ctx = ctx
+        self.handle = h
+        vals = [ctypes.c_int64() for _ in range(5)]
+        check(ctx.lib.fppg_geom_info(h, *[ctypes.byref(v) for v in vals]))
+        self.ncell, self.n_tri, self.n_seg, self.search_cells, self.search_entries = (v.value for v in vals)
+        self.n_geom = len(geoms)
+
+    def workspace_size(self, n: int) -> int:
+        b = ctypes.c_size_t()
+        check(self.ctx.lib.fppg_workspace_size(self.handle, int(n), ctypes.byref(b)))
+        return int(b.value)
+
+    def close(self):
+        if self.handle:
+            self.ctx.lib.fppg_geom_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Relaxer:
+    """Device state and the per-iteration calls for one batch (see module doc)."""
+
+    def __init__(self, wl, device: int = 0, ctx: Context | None = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("Relaxer needs a GPU (HIP device); none is available")
+        self.dev = torch.device("cuda", device)
+        self.ctx = ctx or Context(device)
+        self.geom = Geometry(self.ctx, wl.geoms)
+        self.n = int(wl.n)
+        self.n_feat = int(len(wl.feat_seg))
+        self.move_mask = int(wl.move_mask)
+        pos = np.zeros((self.n, 4), np.float32)
+        pos[:, :3] = wl.pos
+        pos[:, 3] = _pack_w(wl.tag, wl.gid)
+        t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(self.dev, dt)
+        self.pos = t(pos, torch.float32)
+        self.id = t(np.arange(self.n, dtype=np.int32), torch.int32)
+        self.owner = t(wl.owner.astype(np.int32), torch.int32)
+        self.pos_b = torch.empty_like(self.pos)
+        self.id_b = torch.empty_like(self.id)
+        self.owner_b = torch.empty_like(self.owner)
+        self.feat_seg = t(wl.feat_seg.astype(np.int32), torch.int32) if self.n_feat else \
+            torch.zeros(1, dtype=torch.int32, device=self.dev)
+        self.feat_u = t(wl.feat_u.astype(np.float64), torch.float64) if self.n_feat else \
+            torch.zeros(1, dtype=torch.float64, device=self.dev)
+        self.cell_start = torch.zeros(self.geom.ncell + 2, dtype=torch.int32, device=self.dev)
+        self.accel = torch.zeros((self.n, 4), dtype=torch.float32, device=self.dev)
+        self.disp = torch.zeros((self.n, 4), dtype=torch.float32, device=self.dev)
+        self.amax = torch.zeros(self.geom.n_geom, dtype=torch.float32, device=self.dev)
+        self.counters = torch.zeros(L.NCOUNTERS, dtype=torch.int64, device=self.dev)
+        self.ws_bytes = self.geom.workspace_size(self.n)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.dev)
+        off = (-self.ws.data_ptr()) % 256
+        self.ws_ptr = ctypes.c_void_p(self.ws.data_ptr() + off)
+
+    # ---- the four entry points -------------------------------------------------------------
+    @property
+    def stream(self):
+        return ctypes.c_void_p(torch.cuda.current_stream(self.dev).cuda_stream)
+
+    def build_cells(self):
+        lib, c = self.ctx.lib, self.ctx.handle
+        check(lib.fppg_build_cells(c, self.geom.handle, self.n, ptr(self.pos), ptr(self.id), ptr(self.owner),
+                                   ptr(self.pos_b), ptr(self.id_b), ptr(self.owner_b), ptr(self.cell_start),
+                                   self.ws_ptr, self.ws_bytes, self.stream), c)
+        self.pos, self.pos_b = self.pos_b, self.pos
+        self.id, self.id_b = self.id_b, self.id
+        self.owner, self.owner_b = self.owner_b, self.owner
+
+    def relax_step(self, count_pairs: bool = False, keep_accel: bool = True):
+        lib, c = self.ctx.lib, self.ctx.handle
+        flags = L.F_COUNT_PAIRS if count_pairs else 0
+        check(lib.fppg_relax_step(c, self.geom.handle, self.n, ptr(self.pos), ptr(self.owner), ptr(self.cell_start),
+                                  ptr(self.feat_seg), self.n_feat, self.move_mask, flags,
+                                  ptr(self.accel) if keep_accel else None, ptr(self.amax), ptr(self.disp),
+                                  self.ws_ptr, self.ws_bytes, self.stream), c)
+
+    def project(self):
+        lib, c = self.ctx.lib, self.ctx.handle
+        check(lib.fppg_project(c, self.geom.handle, self.n, ptr(self.pos), ptr(self.owner), ptr(self.disp),
+                               ptr(self.feat_seg), ptr(self.feat_u), self.n_feat, self.move_mask,
+                               ptr(self.counters), self.ws_ptr, self.ws_bytes, self.stream), c)
+
+    def hvp(self, v: torch.Tensor, transpose: bool = False, out: torch.Tensor | None = None) -> torch.Tensor:
+        """J v (or J^T v) for v [N, 4] float32 in the current (sorted) order."""
+        lib, c = self.ctx.lib, self.ctx.handle
+        out = torch.empty_like(v) if out is None else out
+        check(lib.fppg_relax_hvp(c, self.geom.handle, self.n, ptr(self.pos), ptr(self.cell_start),
+                                 self.move_mask, int(bool(transpose)), ptr(v), ptr(out), self.stream), c)
+        return out
+
+    def neighbors(self, cap: int = 160):
+        lib, c = self.ctx.lib, self.ctx.handle
+        count = torch.zeros(self.n, dtype=torch.int32, device=self.dev)
+        lst = torch.full((self.n, cap), -1, dtype=torch.int32, device=self.dev)
+        check(lib.fppg_debug_neighbors(c, self.geom.handle, self.n, ptr(self.pos), ptr(self.cell_start),
+                                       ptr(count), ptr(lst), cap, self.stream), c)
+        return count, lst
+
+    def profile(self, enable: bool = True):
+        """Time every phase of the per-iteration calls with HIP events on the launch stream."""
+        check(self.ctx.lib.fppg_profile(self.ctx.handle, int(bool(enable))), self.ctx.handle)
+
+    def profile_read(self) -> dict:
+        """{phase: (total ms, launches)} since profiling was enabled."""
+        ms = (ctypes.c_double * L.NPHASES)()
+        cnt = (ctypes.c_int64 * L.NPHASES)()
+        check(self.ctx.lib.fppg_profile_read(self.ctx.handle, ms, cnt), self.ctx.handle)
+        return {name: (ms[i], cnt[i]) for i, name in enumerate(L.PHASES)}
+
+    def read_status(self) -> int:
+        f = ctypes.c_uint32()
+        check(self.ctx.lib.fppg_read_status(self.ctx.handle, self.stream, ctypes.byref(f)), self.ctx.handle)
+        return int(f.value)
+
+    # ---- loop -------------------------------------------------------------------------------
+    def step(self, count_pairs: bool = False, keep_accel: bool = True):
+        """One iteration of Algorithm 1."""
+        self.build_cells()
+        self.relax_step(count_pairs=count_pairs, keep_accel=keep_accel)
+        self.project()
+
+    def run(self, iters: int):
+        for _ in range(iters):
+            self.step(keep_accel=False)
+
+    # ---- host views (by particle id) ---------------------------------------------------------
+    def host_state(self):
+        """(pos32 [N,3], owner [N], feat_seg, feat_u) ordered by particle id."""
+        torch.cuda.synchronize(self.dev)
+        ids = self.id.cpu().numpy()
+        pos = self.pos.cpu().numpy()
+        own = self.owner.cpu().numpy()
+        p = np.empty((self.n, 3), np.float32)
+        o = np.empty(self.n, np.int32)
+        p[ids] = pos[:, :3]
+        o[ids] = own
+        fs = self.feat_seg.cpu().numpy()[: self.n_feat].copy()
+        fu = self.feat_u.cpu().numpy()[: self.n_feat].copy()
+        return p, o, fs, fu
+
+    def by_id(self, t: torch.Tensor) -> np.ndarray:
+        """Rows of a per-particle tensor in the current order, re-ordered by id."""
+        torch.cuda.synchronize(self.dev)
+        ids = self.id.cpu().numpy()
+        a = t.detach().cpu().numpy()
+        out = np.empty_like(a)
+        out[ids] = a
+        return out

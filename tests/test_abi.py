@@ -1,0 +1,78 @@
+"""The C-ABI library loads, exports every entry point of include/fppg.h and
+validates its arguments on the host (no GPU needed); the product path and the
+oracle stay independent."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "fppg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fppg_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_entry_point():
+    from paper_2501_03056_amd import _lib
+    L = _lib.lib()
+    names = _declared()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(_lib._SIGS), set(names) ^ set(_lib._SIGS)
+
+
+def test_host_side_validation_without_gpu():
+    from paper_2501_03056_amd import _lib
+    L = _lib.lib()
+    assert L.fppg_status_str(-3) == b"workspace too small"
+    assert L.fppg_status_str(0) == b"ok"
+    assert L.fppg_last_error(None) == b"null context"
+    nul = None
+    assert L.fppg_build_cells(nul, nul, 0, nul, nul, nul, nul, nul, nul, nul, nul, 0, nul) == _lib.E_ARG
+    assert L.fppg_relax_step(nul, nul, 0, nul, nul, nul, nul, 0, 0, 0, nul, nul, nul, nul, 0, nul) == _lib.E_ARG
+    assert L.fppg_project(nul, nul, 0, nul, nul, nul, nul, nul, 0, 0, nul, nul, 0, nul) == _lib.E_ARG
+    assert L.fppg_relax_hvp(nul, nul, 0, nul, nul, 0, 0, nul, nul, nul) == _lib.E_ARG
+    assert L.fppg_debug_neighbors(nul, nul, 0, nul, nul, nul, nul, 0, nul) == _lib.E_ARG
+    b = ctypes.c_size_t()
+    assert L.fppg_workspace_size(nul, 10, ctypes.byref(b)) == _lib.E_ARG
+    assert L.fppg_geom_info(nul, None, None, None, None, None) == _lib.E_ARG
+    assert L.fppg_geom_create(nul, None, 0, None) == _lib.E_ARG
+    import torch
+    if not torch.cuda.is_available():
+        h = ctypes.c_void_p()
+        assert L.fppg_create(0, ctypes.byref(h)) == _lib.E_NODEVICE
+
+
+def _py_sources(d):
+    for base, _, files in os.walk(os.path.join(ROOT, d)):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                yield os.path.join(base, f)
+
+
+def test_product_path_does_not_use_the_oracle():
+    for f in _py_sources("paper_2501_03056_amd"):
+        src = open(f).read()
+        assert not re.search(r"^\s*(from|import)\s+oracle\b", src, re.M), f
+        assert "oracle." not in src, f
+
+
+def test_oracle_does_not_use_the_product_path():
+    for f in _py_sources("oracle"):
+        src = open(f).read()
+        assert "paper_2501_03056_amd" not in src, f
+
+
+def test_relaxer_refuses_to_run_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    import synth
+    from paper_2501_03056_amd import Relaxer
+    with pytest.raises(RuntimeError):
+        Relaxer(synth.cube_workload(n=4))

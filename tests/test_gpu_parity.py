@@ -1,0 +1,234 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, element by element.
+
+Bars (the tolerances the method's hot path is held to):
+  * cell order, cell_start and neighbour sets: bit-exact
+  * forces: |a_gpu - a_64| <= 1e-5 * S_i  with S_i = sum_j K (1-q/2)^3 |r_ij|
+  * positions after one step: |x_gpu - x_64|_inf <= 1e-5 * max(|x_64|_inf, dx)
+    for particles whose projection/revert decision is not within rounding of
+    flipping (the oracle flags those as margin; they must still satisfy the
+    geometric invariants)
+Every comparison starts from the same binary32 state.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import cells as ocells
+from oracle import force as oforce
+from oracle import geometry as ogeo
+from oracle import hvp as ohvp
+from oracle import neighbors as onb
+from oracle import step as ostep
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _relaxer(wl):
+    from paper_2501_03056_amd import Relaxer
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return Relaxer(wl, device=0)
+
+
+CASES = {
+    "cube_n8": lambda: synth.cube_workload(n=8, seed=1),
+    "cube_n24": lambda: synth.cube_workload(n=24, seed=1),
+    "cube_n10_k2": lambda: synth.cube_workload(n=10, seed=7, k=2),
+    "sphere_l3": lambda: synth.sphere_workload(level=3, dx=0.08, seed=2),
+    "tetra": lambda: synth.tetra_workload(dx=0.06, seed=5),
+}
+
+
+@pytest.mark.parametrize("case", ["cube_n8", "sphere_l3", "cube_n10_k2"])
+def test_cells_bit_exact(case):
+    wl = CASES[case]()
+    r = _relaxer(wl)
+    r.build_cells()
+    torch.cuda.synchronize()
+    keys = ocells.cell_keys(wl)
+    order = ocells.sort_order(keys, wl.ids)
+    cs = ocells.cell_start(keys[order], ocells.total_cells(wl))
+    assert np.array_equal(r.id.cpu().numpy(), order)
+    assert np.array_equal(r.cell_start.cpu().numpy(), cs)
+    pos = r.pos.cpu().numpy()
+    assert np.array_equal(pos[:, :3], wl.pos[order])
+    assert np.array_equal(r.owner.cpu().numpy(), wl.owner[order])
+    # a second rebuild of an already sorted state is the identity
+    before = r.pos.clone()
+    r.build_cells()
+    assert torch.equal(before, r.pos)
+
+
+@pytest.mark.parametrize("case", ["cube_n8", "sphere_l3", "cube_n10_k2"])
+def test_neighbor_sets_bit_exact(case):
+    wl = CASES[case]()
+    r = _relaxer(wl)
+    r.build_cells()
+    count, lst = r.neighbors(cap=200)
+    count = count.cpu().numpy()
+    lst = lst.cpu().numpy()
+    ids = r.id.cpu().numpy()
+    ref = onb.neighbor_lists(wl)
+    for s in range(wl.n):
+        i = ids[s]
+        got = np.sort(ids[lst[s, : count[s]]])
+        assert count[s] == len(ref[i]) and np.array_equal(got, ref[i]), (s, i)
+
+
+def test_neighbor_sets_adversarial_pairs_at_cell_faces():
+    """Pairs within an ulp of r_c, straddling particle-cell faces."""
+    dx = 0.05
+    h = synth.f32(1.3 * dx)
+    rc = np.float32(2) * np.float32(h)
+    from synth import meshes as M
+    geo_wl = synth.workload.custom_workload(M.cube(), dx, np.zeros((1, 3)), [3])
+    g = geo_wl.geoms[0]
+    cell = np.float32(1) / np.float32(g.inv_cell)
+    rng = np.random.Generator(np.random.PCG64(31))
+    pts = []
+    for _ in range(300):
+        c = rng.integers(3, 10, 3)
+        a = (g.origin + c.astype(np.float32) * cell).astype(np.float32)    # on a cell corner
+        a = np.nextafter(a, a + np.float32(rng.choice([-1, 1])))
+        for off in (np.nextafter(rc, np.float32(0)), rc):
+            b = a.copy()
+            ax = rng.integers(3)
+            b[ax] = np.float32(a[ax] + off)
+            pts += [a, b]
+    p = np.array(pts, np.float32)
+    wl = synth.workload.custom_workload(M.cube(), dx, p, np.full(len(p), 3))
+    r = _relaxer(wl)
+    r.build_cells()
+    count, lst = r.neighbors(cap=64)
+    count, lst, ids = count.cpu().numpy(), lst.cpu().numpy(), r.id.cpu().numpy()
+    ref = onb.neighbor_lists(wl)
+    for s in range(wl.n):
+        assert np.array_equal(np.sort(ids[lst[s, : count[s]]]), ref[ids[s]])
+
+
+@pytest.mark.parametrize("case", ["cube_n24", "sphere_l3", "tetra", "cube_n10_k2"])
+def test_forces_within_1e5_of_fp64(case):
+    wl = CASES[case]()
+    r = _relaxer(wl)
+    r.build_cells()
+    r.relax_step(count_pairs=True)
+    acc = r.by_id(r.accel)
+    a64, S, cnt = oforce.accel(wl)
+    mov = oforce.moving_mask(wl.tag, wl.move_mask)
+    err = np.linalg.norm(acc[:, :3].astype(np.float64) - a64, axis=1)
+    assert np.all(err[mov] <= 1e-5 * S[mov]), float(np.max(err[mov] / np.maximum(S[mov], 1e-300)))
+    assert np.array_equal(acc[:, 3].astype(np.int64), np.where(mov, cnt, 0))
+    assert not acc[~mov, :3].any()
+    amax = oforce.amax_per_geometry(wl, a64)
+    assert np.allclose(r.amax.cpu().numpy(), amax, rtol=1e-5)
+    assert r.read_status() == 0
+
+
+def _compare_step(wl, r, ref, check_owner=True):
+    pos, owner, fs, fu = r.host_state()
+    ok = ~ref.margin
+    x = ref.pos32.astype(np.float64)
+    dx = wl.geoms[0].dx
+    tol = 1e-5 * np.maximum(np.abs(x).max(1), dx)
+    err = np.abs(pos.astype(np.float64) - x).max(1)
+    bad = ok & (err > tol)
+    assert not bad.any(), (int(bad.sum()), np.nonzero(bad)[0][:10], float(err[ok].max()))
+    if check_owner:
+        s = ok & (wl.tag == synth.SURFACE)
+        assert np.array_equal(owner[s], ref.owner[s])
+    f = np.nonzero(ok & (wl.tag == synth.FEATURE))[0]
+    if len(f):
+        slots = wl.owner[f]
+        assert np.array_equal(fs[slots], ref.feat_seg[slots])
+        assert np.allclose(fu[slots], ref.feat_u[slots], rtol=0, atol=1e-5 * dx)
+    return pos, owner
+
+
+@pytest.mark.parametrize("case", ["cube_n24", "sphere_l3", "tetra", "cube_n10_k2"])
+def test_one_step_positions_within_1e5_of_fp64(case):
+    wl = CASES[case]()
+    r = _relaxer(wl)
+    r.step()
+    ref = ostep.relax_step(wl)
+    _compare_step(wl, r, ref)
+    c = r.counters.cpu().numpy()
+    s = wl.tag == synth.SURFACE
+    assert abs(int(c[0]) - int(np.sum(ref.reverted & s))) <= int(np.sum(ref.margin & s))
+    assert r.read_status() == 0
+
+
+def test_steps_keep_invariants_and_match_oracle_each_step():
+    """Five iterations on the cube: every step from the GPU's own state is
+    checked against the oracle applied to that same state, and the invariants
+    hold (surface particles on their facet plane, features on their edge,
+    volume particles inside)."""
+    wl = synth.cube_workload(n=12, seed=9)
+    r = _relaxer(wl)
+    dx = wl.geoms[0].dx
+    for it in range(5):
+        pos, owner, fs, fu = r.host_state()
+        ref = ostep.relax_step(wl, pos32=pos, owner=owner, feat_seg=fs, feat_u=fu)
+        r.step()
+        p2, o2 = _compare_step(wl, r, ref)
+        x = p2.astype(np.float64)
+        s = wl.tag == synth.SURFACE
+        A, B, C, n = ogeo.facet_frames(wl.geoms[0].mesh.vert, wl.geoms[0].mesh.tri)
+        d = np.einsum("ij,ij->i", x[s] - A[o2[s]], n[o2[s]])
+        assert np.abs(d).max() <= 1e-6 * dx
+        v = wl.tag == synth.VOLUME
+        sd = ogeo.signed_distance_many(x[v], wl.geoms[0].mesh.vert, wl.geoms[0].mesh.tri)
+        assert (sd < 0).all()
+
+
+def test_determinism_bitwise():
+    wl = synth.sphere_workload(level=3, dx=0.08, seed=2)
+    outs = []
+    for _ in range(2):
+        r = _relaxer(wl)
+        for _ in range(3):
+            r.step()
+        outs.append(r.host_state())
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
+
+
+def test_hvp_matches_oracle_jacobian():
+    wl = synth.cube_workload(n=10, seed=12)
+    r = _relaxer(wl)
+    r.build_cells()
+    rng = np.random.Generator(np.random.PCG64(13))
+    v = rng.normal(size=(wl.n, 3))
+    ids = r.id.cpu().numpy()
+    v4 = np.zeros((wl.n, 4), np.float32)
+    v4[:, :3] = v[ids]
+    vt = torch.from_numpy(v4).cuda()
+    for transpose in (False, True):
+        out = r.by_id(r.hvp(vt, transpose=transpose))[:, :3].astype(np.float64)
+        ref = ohvp.vjp(wl, v.astype(np.float32).astype(np.float64)) if transpose else \
+            ohvp.jvp(wl, v.astype(np.float32).astype(np.float64))
+        err = np.linalg.norm(out - ref, axis=1)
+        scale = np.linalg.norm(ref, axis=1).max()
+        assert err.max() <= 1e-4 * scale, (transpose, float(err.max() / scale))
+
+
+def test_nonfinite_input_is_flagged_and_held():
+    """A NaN position is never anyone's neighbour, is reported through the
+    status word when it is moved, and leaves the other particles' forces equal
+    to the oracle's."""
+    wl = synth.cube_workload(n=8, seed=3)
+    wl.pos[5] = np.nan
+    r = _relaxer(wl)
+    r.build_cells()
+    r.relax_step()
+    acc = r.by_id(r.accel)
+    assert np.isfinite(acc).all()
+    a64, S, _ = oforce.accel(wl)
+    mov = oforce.moving_mask(wl.tag, wl.move_mask)
+    mov[5] = False
+    err = np.linalg.norm(acc[:, :3].astype(np.float64) - a64, axis=1)
+    assert np.all(err[mov] <= 1e-5 * S[mov])
+    r.project()
+    assert r.read_status() & 2          # FPPG_S_NONFINITE_POS
+    pos, _, _, _ = r.host_state()
+    assert np.isnan(pos[5]).all() and np.isfinite(np.delete(pos, 5, 0)).all()

@@ -143,15 +143,17 @@ def test_cell_keys_contain_particles_and_order_is_key_then_id():
     keys = cells.cell_keys(wl, pos32=pos)
     cell = 1.0 / np.float64(geo.inv_cell)
     nx, ny, nz = (int(v) for v in geo.dims)
+    fin = np.all(np.isfinite(pos), 1)
     c = np.stack([keys % nx, (keys // nx) % ny, keys // (nx * ny)], 1)
-    assert (c >= 0).all() and (c < [nx, ny, nz]).all()
+    assert (c[fin] >= 0).all() and (c[fin] < [nx, ny, nz]).all()
     inside = np.all(np.isfinite(pos), 1) & np.all(pos > -1, 1) & np.all(pos < 1.5, 1)
     lo = geo.origin.astype(np.float64) + c * cell
     x = pos.astype(np.float64)
     tol = 1e-5 * cell
     assert np.all(x[inside] >= lo[inside] - tol) and np.all(x[inside] < lo[inside] + cell + tol)
     assert keys[0] == (int(c[0, 2]) * ny + int(c[0, 1])) * nx + 0            # clamped low in x
-    assert c[1, 1] == ny - 1 and c[3, 2] == 0 and c[2, 0] == 0                # clamped / NaN
+    assert c[1, 1] == ny - 1 and c[3, 2] == 0                                 # clamped
+    assert keys[2] == cells.total_cells(wl)                                   # NaN: quarantine key
     order = cells.sort_order(keys, wl.ids)
     want = [i for _, i in sorted(zip(keys.tolist(), wl.ids.tolist()))]
     assert order.tolist() == want
@@ -159,9 +161,9 @@ def test_cell_keys_contain_particles_and_order_is_key_then_id():
     counts = {}
     for k in keys.tolist():
         counts[k] = counts.get(k, 0) + 1
-    for k in range(cells.total_cells(wl)):
+    for k in range(cells.total_cells(wl) + 1):
         assert cs[k + 1] - cs[k] == counts.get(k, 0)
-    assert cs[-1] == wl.n
+    assert cs[-1] == wl.n and len(cs) == cells.total_cells(wl) + 2
 
 
 # --------------------------------------------------------------------------- forces
