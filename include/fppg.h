@@ -81,9 +81,7 @@ typedef int32_t fppg_status;
 #define FPPG_C_REVERT_SURFACE 0
 #define FPPG_C_REVERT_FEATURE 1
 #define FPPG_C_REVERT_VOLUME  2
-#define FPPG_C_SURFACE_MOVED  3
-#define FPPG_C_VOLUME_TESTED  4  /* volume moves that needed the surface-crossing test */
-#define FPPG_NCOUNTERS        8
+#define FPPG_NCOUNTERS        8  /* slots 3..7 reserved */
 
 typedef struct fppg_ctx fppg_ctx;
 typedef struct fppg_geom fppg_geom;
@@ -232,28 +230,30 @@ fppg_status fppg_relax_step(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
 
 /*
  * Apply the displacement and project back onto the geometry (section 3.3.3).
+ * No workspace: one kernel, one lane per particle.
  *  surface: y = x + dr (FP64); among the facets registered in the 27 search
  *           cells around y, the plane foot p = y - d n with all barycentric
  *           coordinates >= 0 and |d| <= R and the smallest |d| (ties: lowest
  *           facet) wins: pos = fl32(p), owner = that facet; none: pos stays x
- *           (revert).
+ *           (revert). The own cell is searched first and a neighbouring cell
+ *           only if it comes within the best |d| found (same result).
  *  feature: u' = u + du walked along the polyline of segment feat_seg[slot],
  *           carrying into neighbouring segments; leaving an open line
  *           reverts, a loop wraps; pos = fl32(p0 + u' t), feat_seg/feat_u
  *           updated in place (slot = owner[i]).
  *  volume:  y = fl32(x + dr); the move is reverted iff the segment [x, y]
- *           meets a facet (x is inside, the step is shorter than a search
- *           cell, so this equals "the signed distance of y is >= 0" for
- *           meshes thicker than the step).
+ *           meets a facet (tested against the facets of the search cells the
+ *           segment's bounding box touches). With x inside, this equals "the
+ *           signed distance of y is >= 0" for meshes thicker than the step.
  * pos [n*4] in: positions x, out: new positions; owner [n] in/out;
  * disp [n*4] from fppg_relax_step; feat_seg/feat_u [n_feat] in/out (may be
  * NULL if n_feat = 0); counters [FPPG_NCOUNTERS] int64 on the device,
- * incremented (may be NULL).
+ * incremented by the number of reverts per class (FPPG_C_*).
  */
 fppg_status fppg_project(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
                          float* pos, int32_t* owner, const float* disp,
                          int32_t* feat_seg, double* feat_u, int32_t n_feat, uint32_t move_mask,
-                         int64_t* counters, void* ws, size_t ws_bytes, void* stream);
+                         int64_t* counters, void* stream);
 
 /*
  * Jacobian-vector product of the force field of fppg_relax_step with respect

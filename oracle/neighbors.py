@@ -26,13 +26,13 @@ def pair_d2(pi: np.ndarray, pj: np.ndarray) -> np.ndarray:
     pj = np.asarray(pj, np.float32)
     acc = None
     for k in range(3):                      # ((ddx^2 + ddy^2) + ddz^2), each op rounded
-        d = np.subtract(pi[..., k], pj[..., k], dtype=np.float32)
+        d = np.atleast_1d(np.subtract(pi[..., k], pj[..., k], dtype=np.float32))
         np.multiply(d, d, out=d)
         if acc is None:
             acc = d
         else:
             np.add(acc, d, out=acc)
-    return acc
+    return acc if acc.shape == np.broadcast_shapes(pi.shape, pj.shape)[:-1] else acc.reshape(())
 
 
 def neighbor_lists(wl, receivers=None, pos32=None, chunk=256):

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libfppg.so")
 OK, E_ARG, E_HIP, E_WORKSPACE, E_CAPACITY, E_UNSUPPORTED, E_NODEVICE = 0, -1, -2, -3, -4, -5, -6
 F_COUNT_PAIRS = 1
 S_NONFINITE_ACCEL, S_NONFINITE_POS, S_BAD_INDEX = 1, 2, 4
-C_REVERT_SURFACE, C_REVERT_FEATURE, C_REVERT_VOLUME, C_SURFACE_MOVED, C_VOLUME_TESTED = 0, 1, 2, 3, 4
+C_REVERT_SURFACE, C_REVERT_FEATURE, C_REVERT_VOLUME = 0, 1, 2
 NCOUNTERS = 8
 NPHASES = 5
 PHASES = ("build_cells", "force", "update", "project", "hvp")
@@ -47,8 +47,7 @@ _SIGS = {
     "fppg_build_cells": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, _P, _P, _P, _P, c_size_t, _P]),
     "fppg_relax_step": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, c_int32, c_uint32, c_uint32,
                                   _P, _P, _P, _P, c_size_t, _P]),
-    "fppg_project": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, _P, c_int32, c_uint32, _P, _P,
-                               c_size_t, _P]),
+    "fppg_project": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, _P, c_int32, c_uint32, _P, _P]),
     "fppg_relax_hvp": (c_int32, [_P, _P, c_int64, _P, _P, c_uint32, c_int32, _P, _P, _P]),
     "fppg_debug_neighbors": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, c_int32, _P]),
 }

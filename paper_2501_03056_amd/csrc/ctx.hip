@@ -36,13 +36,7 @@ WsLayout ws_layout(const Geom* g, int64_t n) {
   o = 0;
   L.accel = o;    o += up256(16 * N);
   L.step_end = o;
-  o = 0;
-  L.list_surf = o;  o += up256(4 * N);
-  L.list_feat = o;  o += up256(4 * N);
-  L.list_vol = o;   o += up256(4 * N);
-  L.list_count = o; o += up256(64);
-  L.project_end = o;
-  L.total = std::max(L.build_end, std::max(L.step_end, L.project_end));
+  L.total = std::max(L.build_end, L.step_end);
   return L;
 }
 
@@ -154,21 +148,8 @@ static fppg_status build_search_grid(fppg_ctx* ctx, const fppg_geom_desc& d, int
   std::vector<int64_t> cur(sg.start.begin(), sg.start.end() - 1);
   for (auto& r : reg) sg.tri[cur[r.first]++] = r.second;  // facets visited in ascending order
   sg.flag.assign(ncell, 0);
-  const int32_t nx = sg.dims[0], ny = sg.dims[1], nz = sg.dims[2];
-  for (int32_t z = 0; z < nz; ++z)
-    for (int32_t y = 0; y < ny; ++y)
-      for (int32_t x = 0; x < nx; ++x) {
-        int64_t c = (int64_t(z) * ny + y) * nx + x;
-        if (sg.start[c + 1] == sg.start[c]) continue;
-        sg.flag[c] |= kCellHasFacet;
-        for (int dz = -1; dz <= 1; ++dz)
-          for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-              int32_t xx = x + dx, yy = y + dy, zz = z + dz;
-              if (xx < 0 || yy < 0 || zz < 0 || xx >= nx || yy >= ny || zz >= nz) continue;
-              sg.flag[(int64_t(zz) * ny + yy) * nx + xx] |= kCellNearSurface;
-            }
-      }
+  for (int64_t c = 0; c < ncell; ++c)
+    if (sg.start[c + 1] > sg.start[c]) sg.flag[c] = kCellHasFacet;
   return FPPG_OK;
 }
 

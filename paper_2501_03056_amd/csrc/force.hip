@@ -2,48 +2,89 @@
 // displacement update (Eq. 22-25), the Jacobian-vector products of the force
 // field, and the neighbour-set export used by the tests.
 //
-// One lane per sorted receiver. With x-fastest cell keys the (2k+1) cells of
-// a stencil row along x are contiguous in the sorted order, so a receiver
-// visits (2k+1)^2 contiguous index ranges. Sources are summed in that order
-// (rows by dz then dy ascending, then sorted index), which makes the sums
-// bitwise deterministic. The neighbour predicate is the binary32 expression
+// One lane per sorted receiver. With x-fastest cell keys the cells of a
+// stencil row along x are contiguous in the sorted order, so a receiver
+// visits at most (2k+1)^2 contiguous index ranges. Rows and the x-extent of a
+// row are culled in cell units against the support radius: a skipped cell is
+// at least k cell edges (> 2h, the edge being (2h/k)(1+2^-9) or more) from the
+// receiver, so it holds no source and the culled sums are bitwise identical to
+// the full-stencil sums. Sources are summed in a fixed order (rows by dz then
+// dy ascending, then sorted index): the sums are deterministic.
+//
+// The neighbour predicate is the binary32 expression
 // fl32(fl32(fl32(dx*dx) + fl32(dy*dy)) + fl32(dz*dz)) < rc2; this file is
-// compiled without floating-point contraction so that the compiler cannot
-// fuse it, and the accumulations use explicit fmaf.
+// compiled without floating-point contraction so that the compiler cannot fuse
+// it, and the accumulations use explicit fmaf.
 #include "internal.h"
 
 namespace fppg {
 
-struct Cell3 {
+// Receiver cell and its fractional position inside the cell (cell units).
+struct Stencil {
   int x, y, z;
+  float fx, fy, fz;
 };
 
-__device__ __forceinline__ Cell3 cell_of(const float4 p, const GeomDev& G) {
+__device__ __forceinline__ Stencil stencil_of(const float4 p, const GeomDev& G) {
   float tx = (p.x - G.origin[0]) * G.inv_cell;
   float ty = (p.y - G.origin[1]) * G.inv_cell;
   float tz = (p.z - G.origin[2]) * G.inv_cell;
+  // clamping moves an outside receiver onto the grid box: gaps only shrink
   tx = fminf(fmaxf(tx, 0.0f), float(G.dims[0] - 1));
   ty = fminf(fmaxf(ty, 0.0f), float(G.dims[1] - 1));
   tz = fminf(fmaxf(tz, 0.0f), float(G.dims[2] - 1));
-  return Cell3{int(floorf(tx)), int(floorf(ty)), int(floorf(tz))};
+  const float cx = floorf(tx), cy = floorf(ty), cz = floorf(tz);
+  return Stencil{int(cx), int(cy), int(cz), tx - cx, ty - cy, tz - cz};
 }
 
-// Visit the contiguous source ranges of the (2K+1)^2 stencil rows of cell c.
+// Distance in cell units from a receiver at fraction f of its cell to the
+// cell d cells away along one axis.
+__device__ __forceinline__ float cell_gap(int d, float f) {
+  return d > 0 ? float(d) - f : (d < 0 ? f + float(-d - 1) : 0.0f);
+}
+
+// Visit the source index ranges of the stencil of a receiver, culled to the
+// cells within k cell edges.
 template <int K, class F>
-__device__ __forceinline__ void for_each_row(const Cell3 c, const GeomDev& G, const int* __restrict__ cs, F&& f) {
-  const int x0 = max(c.x - K, 0), x1 = min(c.x + K, G.dims[0] - 1);
+__device__ __forceinline__ void for_each_row(const Stencil s, const GeomDev& G, const int* __restrict__ cs, F&& f) {
+  const float kk = float(K * K);
 #pragma unroll
   for (int dz = -K; dz <= K; ++dz) {
-    const int z = c.z + dz;
+    const int z = s.z + dz;
     if (z < 0 || z >= G.dims[2]) continue;
+    const float gz = cell_gap(dz, s.fz);
 #pragma unroll
     for (int dy = -K; dy <= K; ++dy) {
-      const int y = c.y + dy;
+      const int y = s.y + dy;
       if (y < 0 || y >= G.dims[1]) continue;
+      const float gy = cell_gap(dy, s.fy);
+      const float r2 = kk - (gy * gy + gz * gz);
+      if (!(r2 > 0.0f)) continue;
+      const float rho = __builtin_amdgcn_sqrtf(r2);
+      const int below = min(K, int(ceilf(rho - s.fx + 1.0f)) - 1);   // |dx| with f + |dx| - 1 < rho
+      const int above = min(K, int(ceilf(rho + s.fx)) - 1);          // dx with dx - f < rho
+      const int x0 = max(s.x - below, 0), x1 = min(s.x + above, G.dims[0] - 1);
       const int row = int(G.cell_begin) + (z * G.dims[1] + y) * G.dims[0];
       f(cs[row + x0], cs[row + x1 + 1]);
     }
   }
+}
+
+// Visit every source index of the stencil, four loads in flight at a time.
+template <int K, class F>
+__device__ __forceinline__ void for_each_source(const Stencil s, const GeomDev& G, const int* __restrict__ cs,
+                                                const float4* __restrict__ pos, F&& f) {
+  for_each_row<K>(s, G, cs, [&](int j0, int j1) {
+    int j = j0;
+    for (; j + 4 <= j1; j += 4) {
+      const float4 q0 = pos[j], q1 = pos[j + 1], q2 = pos[j + 2], q3 = pos[j + 3];
+      f(j, q0);
+      f(j + 1, q1);
+      f(j + 2, q2);
+      f(j + 3, q3);
+    }
+    for (; j < j1; ++j) f(j, pos[j]);
+  });
 }
 
 __device__ __forceinline__ float pair_d2(float dx, float dy, float dz) {
@@ -57,6 +98,25 @@ __global__ void k_zero_f32(float* __restrict__ a, int n) {
 
 // ---- forces + amax ---------------------------------------------------------------------
 
+// One source: K-less pair term (1 - r/2h)^3 r_ij if j is a source of i.
+// RANKED: check rank(tag_j) <= rank(tag_i) as tag_j <= T (T = rank, or 7 for
+// volume receivers which take every class). The receiver itself contributes
+// r = 0, so it needs no test (the count subtracts it).
+template <bool RANKED, bool COUNT>
+__device__ __forceinline__ void add_pair(const float4 p, const float4 q, float rc2, float inv2h, uint32_t T,
+                                         float& ax, float& ay, float& az, float& cnt) {
+  const float dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
+  const float d2 = pair_d2(dx, dy, dz);
+  bool src = d2 < rc2;
+  if (RANKED) src = src & ((__float_as_uint(q.w) & 7u) <= T);
+  const float t = fmaxf(fmaf(-__builtin_amdgcn_sqrtf(d2), inv2h, 1.0f), 0.0f);
+  const float w = src ? t * t * t : 0.0f;
+  ax = fmaf(w, dx, ax);
+  ay = fmaf(w, dy, ay);
+  az = fmaf(w, dz, az);
+  if (COUNT) cnt += src ? 1.0f : 0.0f;
+}
+
 template <int K, bool COUNT>
 __global__ __launch_bounds__(kBlock) void k_force(const float4* __restrict__ pos, int n,
                                                   const int* __restrict__ cs, const GeomDev* __restrict__ geoms,
@@ -65,54 +125,69 @@ __global__ __launch_bounds__(kBlock) void k_force(const float4* __restrict__ pos
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   float anorm = 0.0f;
   int g = 0;
+  bool mov = false;
+  float4 p = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  int tag = 0;
   if (i < n) {
-    const float4 p = pos[i];
-    const int tag = tag_of(p.w);
+    p = pos[i];
+    tag = tag_of(p.w);
     g = min(geom_of(p.w), n_geom - 1);
-    float ax = 0.0f, ay = 0.0f, az = 0.0f, cnt = 0.0f;
-    const bool finite = isfinite(p.x) && isfinite(p.y) && isfinite(p.z);
-    if (!finite && is_moving(tag, move_mask)) atomicOr(status, FPPG_S_NONFINITE_ACCEL);
-    if (finite && is_moving(tag, move_mask)) {
-      const GeomDev& G = geoms[g];
-      const int rk = rank_of(tag);
-      const float rc2 = G.rc2;
-      const float inv2h = 0.5f / G.h;
-      for_each_row<K>(cell_of(p, G), G, cs, [&](int j0, int j1) {
-        for (int j = j0; j < j1; ++j) {
-          const float4 q = pos[j];
-          const float dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
-          const float d2 = pair_d2(dx, dy, dz);
-          const bool src = (d2 < rc2) & (j != i) & (rank_of(tag_of(q.w)) <= rk);
-          const float t = fmaxf(1.0f - __builtin_sqrtf(d2) * inv2h, 0.0f);
-          const float w = src ? t * t * t : 0.0f;
-          ax = fmaf(w, dx, ax);
-          ay = fmaf(w, dy, ay);
-          az = fmaf(w, dz, az);
-          if (COUNT) cnt += src ? 1.0f : 0.0f;
-        }
-      });
-      ax *= G.kcoef;
-      ay *= G.kcoef;
-      az *= G.kcoef;
-      anorm = sqrtf(ax * ax + ay * ay + az * az);
-      if (!isfinite(anorm)) {
-        atomicOr(status, FPPG_S_NONFINITE_ACCEL);
-        ax = ay = az = 0.0f;
-        anorm = 0.0f;
-      }
+    mov = is_moving(tag, move_mask);
+    if (mov && !(isfinite(p.x) && isfinite(p.y) && isfinite(p.z))) {
+      atomicOr(status, FPPG_S_NONFINITE_ACCEL);   // quarantined particle: no force, no move
+      mov = false;
     }
-    accel[i] = make_float4(ax, ay, az, cnt);
   }
-  // per-geometry max of |a|: one atomic per wavefront when the wave is in one geometry
+  // wavefronts of volume receivers only skip the class test
+  const bool ranked = __ballot(mov && tag < FPPG_TAG_VOLUME) != 0;
+  float ax = 0.0f, ay = 0.0f, az = 0.0f, cnt = 0.0f;
+  if (mov) {
+    const GeomDev& G = geoms[g];
+    const float rc2 = G.rc2;
+    const float inv2h = 0.5f / G.h;
+    const uint32_t T = tag < FPPG_TAG_VOLUME ? uint32_t(tag) : 7u;
+    const Stencil st = stencil_of(p, G);
+    if (ranked)
+      for_each_source<K>(st, G, cs, pos, [&](int, const float4 q) { add_pair<true, COUNT>(p, q, rc2, inv2h, T, ax, ay, az, cnt); });
+    else
+      for_each_source<K>(st, G, cs, pos, [&](int, const float4 q) { add_pair<false, COUNT>(p, q, rc2, inv2h, T, ax, ay, az, cnt); });
+    ax *= G.kcoef;
+    ay *= G.kcoef;
+    az *= G.kcoef;
+    if (COUNT) cnt -= 1.0f;   // the receiver itself
+    anorm = sqrtf(ax * ax + ay * ay + az * az);
+    if (!isfinite(anorm)) {
+      atomicOr(status, FPPG_S_NONFINITE_ACCEL);
+      ax = ay = az = 0.0f;
+      anorm = 0.0f;
+    }
+  }
+  if (i < n) accel[i] = make_float4(ax, ay, az, cnt);
+  // per-geometry max of |a|: wave max, block max, one atomic per block and geometry
+  __shared__ float s_max[kBlock / 64];
+  __shared__ int s_geo[kBlock / 64];
   const int g0 = __shfl(g, 0);
-  const uint64_t mixed = __ballot(anorm > 0.0f && g != g0);
-  if (mixed == 0) {
-    float m = anorm;
+  const bool mixed = __ballot(anorm > 0.0f && g != g0) != 0;
+  if (mixed && anorm > 0.0f) atomicMax(&amax_bits[g], __float_as_uint(anorm));   // wave spans geometries
+  float m = mixed ? 0.0f : anorm;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-    if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(&amax_bits[g0], __float_as_uint(m));
-  } else if (anorm > 0.0f) {
-    atomicMax(&amax_bits[g], __float_as_uint(anorm));
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) {
+    s_max[threadIdx.x >> 6] = m;
+    s_geo[threadIdx.x >> 6] = g0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < kBlock / 64; ++w) {
+      float mm = s_max[w];
+      if (!(mm > 0.0f)) continue;
+      for (int w2 = w + 1; w2 < kBlock / 64; ++w2)
+        if (s_geo[w2] == s_geo[w]) {
+          mm = fmaxf(mm, s_max[w2]);
+          s_max[w2] = 0.0f;
+        }
+      atomicMax(&amax_bits[s_geo[w]], __float_as_uint(mm));
+    }
   }
 }
 
@@ -172,8 +247,8 @@ __global__ __launch_bounds__(kBlock) void k_update(const float4* __restrict__ po
 // M(r) w = K [ t^3 w - (3/2h) t^2 (r.w) r / |r| ],  t = 1 - |r|/2h  (0 outside the support)
 __device__ __forceinline__ void pair_jac_apply(float dx, float dy, float dz, float d2, float inv2h, float w0, float w1,
                                                float w2, float& o0, float& o1, float& o2, float scale) {
-  const float r = __builtin_sqrtf(d2);
-  const float t = fmaxf(1.0f - r * inv2h, 0.0f);
+  const float r = __builtin_amdgcn_sqrtf(d2);
+  const float t = fmaxf(fmaf(-r, inv2h, 1.0f), 0.0f);
   const float c1 = t * t * t;
   const float rw = dx * w0 + dy * w1 + dz * w2;
   const float c2 = r > 0.0f ? (3.0f * inv2h) * t * t * rw / r : 0.0f;
@@ -199,22 +274,19 @@ __global__ __launch_bounds__(kBlock) void k_jvp(const float4* __restrict__ pos, 
     const float rc2 = G.rc2;
     const float inv2h = 0.5f / G.h;
     const float4 vi = v[i];
-    for_each_row<K>(cell_of(p, G), G, cs, [&](int j0, int j1) {
-      for (int j = j0; j < j1; ++j) {
-        const float4 q = pos[j];
-        const float dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
-        const float d2 = pair_d2(dx, dy, dz);
-        if (!(d2 < rc2) || j == i) continue;
-        const int tj = tag_of(q.w);
-        const int rj = rank_of(tj);
-        const float4 vj = v[j];
-        if (!TRANSPOSE) {
-          if (rj <= rk) pair_jac_apply(dx, dy, dz, d2, inv2h, vi.x - vj.x, vi.y - vj.y, vi.z - vj.z, o0, o1, o2, 1.0f);
-        } else {
-          if (mov_i && rj <= rk) pair_jac_apply(dx, dy, dz, d2, inv2h, vi.x, vi.y, vi.z, o0, o1, o2, 1.0f);
-          if (is_moving(tj, move_mask) && rk <= rj)
-            pair_jac_apply(dx, dy, dz, d2, inv2h, vj.x, vj.y, vj.z, o0, o1, o2, -1.0f);
-        }
+    for_each_source<K>(stencil_of(p, G), G, cs, pos, [&](int j, const float4 q) {
+      const float dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
+      const float d2 = pair_d2(dx, dy, dz);
+      if (!(d2 < rc2) || j == i) return;
+      const int tj = tag_of(q.w);
+      const int rj = rank_of(tj);
+      const float4 vj = v[j];
+      if (!TRANSPOSE) {
+        if (rj <= rk) pair_jac_apply(dx, dy, dz, d2, inv2h, vi.x - vj.x, vi.y - vj.y, vi.z - vj.z, o0, o1, o2, 1.0f);
+      } else {
+        if (mov_i && rj <= rk) pair_jac_apply(dx, dy, dz, d2, inv2h, vi.x, vi.y, vi.z, o0, o1, o2, 1.0f);
+        if (is_moving(tj, move_mask) && rk <= rj)
+          pair_jac_apply(dx, dy, dz, d2, inv2h, vj.x, vj.y, vj.z, o0, o1, o2, -1.0f);
       }
     });
     o0 *= G.kcoef;
@@ -236,14 +308,11 @@ __global__ __launch_bounds__(kBlock) void k_neighbors(const float4* __restrict__
   const GeomDev& G = geoms[min(geom_of(p.w), n_geom - 1)];
   int c = 0;
   const float rc2 = G.rc2;
-  for_each_row<K>(cell_of(p, G), G, cs, [&](int j0, int j1) {
-    for (int j = j0; j < j1; ++j) {
-      const float4 q = pos[j];
-      const float d2 = pair_d2(p.x - q.x, p.y - q.y, p.z - q.z);
-      if (d2 < rc2 && j != i) {
-        if (c < cap) list[int64_t(i) * cap + c] = j;
-        ++c;
-      }
+  for_each_source<K>(stencil_of(p, G), G, cs, pos, [&](int j, const float4 q) {
+    const float d2 = pair_d2(p.x - q.x, p.y - q.y, p.z - q.z);
+    if (d2 < rc2 && j != i) {
+      if (c < cap) list[int64_t(i) * cap + c] = j;
+      ++c;
     }
   });
   count[i] = c;

@@ -54,9 +54,8 @@ struct SegDev {
   int32_t pad;
 };
 
-// Search-cell flag bits.
+// Search-cell flag: the cell holds at least one facet.
 constexpr uint8_t kCellHasFacet = 1;
-constexpr uint8_t kCellNearSurface = 2;   // the cell or one of its 26 neighbours holds a facet
 
 struct Geom {
   int32_t n_geom = 0;
@@ -136,8 +135,6 @@ struct WsLayout {
   size_t key, rank, tmp_id, tmp_src, tmp_key, count, blocksum, build_end;
   // relax_step
   size_t accel, step_end;
-  // project
-  size_t list_surf, list_feat, list_vol, list_count, project_end;
   size_t total;
 };
 WsLayout ws_layout(const Geom* g, int64_t n);

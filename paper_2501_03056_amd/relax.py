@@ -177,7 +177,7 @@ class Relaxer:
         lib, c = self.ctx.lib, self.ctx.handle
         check(lib.fppg_project(c, self.geom.handle, self.n, ptr(self.pos), ptr(self.owner), ptr(self.disp),
                                ptr(self.feat_seg), ptr(self.feat_u), self.n_feat, self.move_mask,
-                               ptr(self.counters), self.ws_ptr, self.ws_bytes, self.stream), c)
+                               ptr(self.counters), self.stream), c)
 
     def hvp(self, v: torch.Tensor, transpose: bool = False, out: torch.Tensor | None = None) -> torch.Tensor:
         """J v (or J^T v) for v [N, 4] float32 in the current (sorted) order."""

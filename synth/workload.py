@@ -67,7 +67,7 @@ class Geometry:
         return int(np.prod(self.dims))
 
 
-def particle_grid(lo, hi, h, k=1, pad=None):
+def particle_grid(lo, hi, h, k=2, pad=None):
     """Grid parameters covering [lo, hi] plus a margin of one support radius."""
     rc = f32(2.0 * h)
     pad = rc if pad is None else pad
@@ -205,7 +205,7 @@ def _finish(name, parts, move_mask, seed, meta=None) -> Workload:
         move_mask=move_mask, seed=seed, meta=meta or {})
 
 
-def _make_geom(mesh, dx, k=1, proj_radius=None):
+def _make_geom(mesh, dx, k=2, proj_radius=None):
     h = f32(1.3 * dx)
     lo, hi = mesh.bbox()
     origin, inv, dims = particle_grid(lo, hi, h, k)
@@ -234,7 +234,7 @@ def _tri_owner_on_plane(mesh: M.Mesh, cand: np.ndarray, pts: np.ndarray) -> np.n
     return out
 
 
-def cube_workload(n=24, jitter=0.3, seed=1, k=1, with_volume=True, with_surface=True,
+def cube_workload(n=24, jitter=0.3, seed=1, k=2, with_volume=True, with_surface=True,
                   with_features=True, move_mask=ALL_MOVING, name=None) -> Workload:
     """Unit cube [0,1]^3, dx = 1/n: a jittered (i+1/2)dx lattice of volume
     particles, (a+1/2)dx x (b+1/2)dx surface particles per face with tangential
@@ -273,7 +273,7 @@ def cube_workload(n=24, jitter=0.3, seed=1, k=1, with_volume=True, with_surface=
                    {"dx": dx, "jitter": jitter})
 
 
-def dyadic_lattice_workload(m=16, dx=2.0 ** -5, k=1) -> Workload:
+def dyadic_lattice_workload(m=16, dx=2.0 ** -5, k=2) -> Workload:
     """Exact lattice of m^3 volume particles at (i+1/2)dx, no jitter, no mesh
     constraints exercised: every coordinate is a binary32 value."""
     mesh = M.cube((0.0, 0.0, 0.0), (m * dx, m * dx, m * dx))
@@ -327,7 +327,7 @@ def fibonacci_sphere(m: int) -> np.ndarray:
     return np.stack([r * np.cos(phi), r * np.sin(phi), z], 1)
 
 
-def sphere_workload(level=5, dx=0.01, jitter=0.3, seed=2, k=1, with_volume=True,
+def sphere_workload(level=5, dx=0.01, jitter=0.3, seed=2, k=2, with_volume=True,
                     with_surface=True, move_mask=ALL_MOVING, name=None) -> Workload:
     """Icosphere of radius 1. Volume: jittered (i+1/2)dx lattice on [-1,1]^3 kept
     where the distance to the mesh is at least dx/2 inside (tested against the
@@ -371,7 +371,7 @@ def _convex_inside(mesh, pts, margin):
     return np.all(sd <= -margin, axis=1)
 
 
-def tetra_workload(dx=0.045, jitter=0.3, seed=5, k=1, move_mask=ALL_MOVING, name=None) -> Workload:
+def tetra_workload(dx=0.045, jitter=0.3, seed=5, k=2, move_mask=ALL_MOVING, name=None) -> Workload:
     """Regular tetrahedron of edge 1. Volume: jittered lattice at least dx/2
     inside. Surface: per face a jittered square lattice in the face plane, kept
     at least dx/2 from the face edges. Features on the 6 edges, 4 singular corners."""
@@ -406,7 +406,7 @@ def tetra_workload(dx=0.045, jitter=0.3, seed=5, k=1, move_mask=ALL_MOVING, name
 
 
 def custom_workload(mesh, dx, pos, tag, owner=None, feat_seg=None, feat_u=None,
-                    move_mask=ALL_MOVING, k=1, name="custom") -> Workload:
+                    move_mask=ALL_MOVING, k=2, name="custom") -> Workload:
     """A single-geometry workload from explicit particle arrays (for small cases)."""
     geom = _make_geom(mesh, dx, k)
     b = _Builder()
