@@ -37,12 +37,12 @@ def roofline_note():
             "3 fma (accumulate); candidates rejected by the predicate are not counted")
 
 
-def make_workload(name):
+def make_workload(name, k=2):
     import synth
     if name == "sphere":
-        return synth.sphere_workload(level=5, dx=0.01, seed=2), "icosphere_l5_r1_dx0.01_h1.3dx"
+        return synth.sphere_workload(level=5, dx=0.01, seed=2, k=k), "icosphere_l5_r1_dx0.01_h1.3dx"
     if name == "cube":
-        return synth.cube_workload(n=24, seed=1), "unit_cube_dx1/24_h1.3dx"
+        return synth.cube_workload(n=24, seed=1, k=k), "unit_cube_dx1/24_h1.3dx"
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -101,6 +101,9 @@ def main():
     ap.add_argument("--workload", default="sphere")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=160)
+    ap.add_argument("--k", type=int, default=2, help="stencil half-width of the particle cells (1 or 2)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="copy 1 GiB device to device first (reference kernel for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design "
@@ -109,8 +112,14 @@ def main():
     import torch
     from paper_2501_03056_amd import Relaxer
 
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     t0 = time.perf_counter()
-    wl, wname = make_workload(args.workload)
+    wl, wname = make_workload(args.workload, args.k)
     print(f"[bench] workload {wname}: {wl.n} particles {wl.counts()} built in {time.perf_counter() - t0:.1f}s",
           file=sys.stderr, flush=True)
     r = Relaxer(wl, device=0)

@@ -270,6 +270,55 @@ fppg_status fppg_relax_hvp(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
                            int32_t transpose, const float* v, float* Jv, void* stream);
 
 /*
+ * Pair energy whose negative gradient is the force field of fppg_relax_step
+ * for one moving class with fixed other sources (the line-search objective
+ * of Newton-Krylov relaxation; not in the paper):
+ *   E = sum_{i moving} sum_{j in src(i)} c_ij W(r_ij),  c_ij = 1/2 if j moves, else 1
+ * with W the Wendland C2 kernel of Eq. 16 (alpha = 21/(16 pi h^3)), evaluated
+ * in FP64 from the binary32 positions over the same neighbour sets. out: one
+ * double on the device. Deterministic summation order. ws: at least
+ * fppg_workspace_size bytes.
+ */
+fppg_status fppg_relax_energy(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, const float* pos,
+                              const int32_t* cell_start, uint32_t move_mask, double* out,
+                              void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Vector operations on particle fields (float4 rows, x/y/z used, w ignored),
+ * for Krylov solvers:
+ *   fppg_vec_dot    out[0] = sum_i a_i . b_i in FP64, fixed summation order
+ *                   (device double; ws >= 2048 doubles, 256-byte aligned)
+ *   fppg_vec_axpby  y <- alpha x + beta y
+ * Neither touches w.
+ */
+fppg_status fppg_vec_dot(fppg_ctx* ctx, int64_t n, const float* a, const float* b, double* out,
+                         void* ws, size_t ws_bytes, void* stream);
+fppg_status fppg_vec_axpby(fppg_ctx* ctx, int64_t n, float alpha, const float* x, float beta, float* y,
+                           void* stream);
+/* out[0] (device float) = max_i |a_i| (Euclidean norm of the xyz of row i);
+ * a NaN row counts as +inf. */
+fppg_status fppg_vec_maxnorm(fppg_ctx* ctx, int64_t n, const float* a, float* out, void* stream);
+
+/*
+ * v <- P v row by row: P = I - n n^T for a moving surface particle (n the
+ * unit normal of facet owner[i]), t t^T for a moving feature particle (t the
+ * tangent of segment feat_seg[owner[i]]), I for a moving volume particle, 0
+ * for a particle that does not move. The tangent space of Eq. 24-25.
+ */
+fppg_status fppg_tangent_project(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, const float* pos,
+                                 const int32_t* owner, const int32_t* feat_seg, int32_t n_feat,
+                                 uint32_t move_mask, float* v, void* stream);
+
+/*
+ * disp <- alpha P v in the displacement format of fppg_project (as written by
+ * fppg_relax_step, with alpha v in place of dt^2 a): the step of a
+ * Newton-Krylov update, applied and projected by fppg_project.
+ */
+fppg_status fppg_displace(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, const float* pos,
+                          const int32_t* owner, const int32_t* feat_seg, int32_t n_feat,
+                          uint32_t move_mask, const float* v, float alpha, float* disp, void* stream);
+
+/*
  * Test/diagnostic export of the neighbour sets seen by the force traversal:
  * for every particle i (moving or not), count[i] = |{j != i : predicate}| over
  * all tags of its geometry, and list[i*cap .. i*cap+min(count,cap)-1] the

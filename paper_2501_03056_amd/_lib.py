@@ -50,6 +50,12 @@ _SIGS = {
     "fppg_project": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, _P, c_int32, c_uint32, _P, _P]),
     "fppg_relax_hvp": (c_int32, [_P, _P, c_int64, _P, _P, c_uint32, c_int32, _P, _P, _P]),
     "fppg_debug_neighbors": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, c_int32, _P]),
+    "fppg_relax_energy": (c_int32, [_P, _P, c_int64, _P, _P, c_uint32, _P, _P, c_size_t, _P]),
+    "fppg_vec_dot": (c_int32, [_P, c_int64, _P, _P, _P, _P, c_size_t, _P]),
+    "fppg_vec_axpby": (c_int32, [_P, c_int64, c_float, _P, c_float, _P, _P]),
+    "fppg_vec_maxnorm": (c_int32, [_P, c_int64, _P, _P, _P]),
+    "fppg_tangent_project": (c_int32, [_P, _P, c_int64, _P, _P, _P, c_int32, c_uint32, _P, _P]),
+    "fppg_displace": (c_int32, [_P, _P, c_int64, _P, _P, _P, c_int32, c_uint32, _P, c_float, _P, _P]),
 }
 
 _lib = None

@@ -36,7 +36,9 @@ WsLayout ws_layout(const Geom* g, int64_t n) {
   o = 0;
   L.accel = o;    o += up256(16 * N);
   L.step_end = o;
-  L.total = std::max(L.build_end, L.step_end);
+  // relax_energy: one FP64 partial per block of 256; vec_dot: kDotPartials
+  L.reduce_end = up256(8 * std::max<size_t>((N + 255) / 256 + 1, kDotPartials));
+  L.total = std::max(L.build_end, std::max(L.step_end, L.reduce_end));
   return L;
 }
 

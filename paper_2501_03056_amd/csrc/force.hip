@@ -122,7 +122,7 @@ __global__ __launch_bounds__(kBlock) void k_force(const float4* __restrict__ pos
                                                   const int* __restrict__ cs, const GeomDev* __restrict__ geoms,
                                                   int n_geom, uint32_t move_mask, float4* __restrict__ accel,
                                                   unsigned* __restrict__ amax_bits, uint32_t* status) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = xcd_chunk(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   float anorm = 0.0f;
   int g = 0;
   bool mov = false;
@@ -189,6 +189,43 @@ __global__ __launch_bounds__(kBlock) void k_force(const float4* __restrict__ pos
       atomicMax(&amax_bits[s_geo[w]], __float_as_uint(mm));
     }
   }
+}
+
+// ---- pair energy (line search of Newton-Krylov relaxation) --------------------------------
+
+// E = sum over moving receivers i and their sources j of c_ij W(r_ij), with
+// c_ij = 1/2 when j moves too (the pair is then counted from both ends) and 1
+// otherwise; W (Eq. 16) evaluated in FP64 from the binary32 positions. For a
+// single moving class with fixed other sources, a = -grad E.
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_energy(const float4* __restrict__ pos, int n, const int* __restrict__ cs,
+                                                   const GeomDev* __restrict__ geoms, int n_geom, uint32_t move_mask,
+                                                   double* __restrict__ partial) {
+  const int i = xcd_chunk(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  double e = 0.0;
+  if (i < n) {
+    const float4 p = pos[i];
+    const int tag = tag_of(p.w);
+    if (is_moving(tag, move_mask) && isfinite(p.x) && isfinite(p.y) && isfinite(p.z)) {
+      const GeomDev& G = geoms[min(geom_of(p.w), n_geom - 1)];
+      const int rk = rank_of(tag);
+      const double h = G.h;
+      const double alpha = 21.0 / (16.0 * M_PI * h * h * h);
+      const float rc2 = G.rc2;
+      for_each_source<K>(stencil_of(p, G), G, cs, pos, [&](int j, const float4 q) {
+        if (!(pair_d2(p.x - q.x, p.y - q.y, p.z - q.z) < rc2) || j == i) return;
+        const int tj = tag_of(q.w);
+        if (rank_of(tj) > rk) return;
+        const double dx = double(p.x) - double(q.x), dy = double(p.y) - double(q.y), dz = double(p.z) - double(q.z);
+        const double qq = sqrt(dx * dx + dy * dy + dz * dz) / h;
+        const double t = fmax(1.0 - 0.5 * qq, 0.0);
+        const double w = alpha * (t * t) * (t * t) * (2.0 * qq + 1.0);
+        e += is_moving(tj, move_mask) ? 0.5 * w : w;
+      });
+    }
+  }
+  const double t = block_sum256(e);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
 // ---- displacement (Eq. 22-25) ------------------------------------------------------------
@@ -261,7 +298,7 @@ template <int K, bool TRANSPOSE>
 __global__ __launch_bounds__(kBlock) void k_jvp(const float4* __restrict__ pos, int n, const int* __restrict__ cs,
                                                 const GeomDev* __restrict__ geoms, int n_geom, uint32_t move_mask,
                                                 const float4* __restrict__ v, float4* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = xcd_chunk(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float4 p = pos[i];
   const int tag = tag_of(p.w);
@@ -302,7 +339,7 @@ template <int K>
 __global__ __launch_bounds__(kBlock) void k_neighbors(const float4* __restrict__ pos, int n, const int* __restrict__ cs,
                                                       const GeomDev* __restrict__ geoms, int n_geom,
                                                       int* __restrict__ count, int* __restrict__ list, int cap) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = xcd_chunk(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float4 p = pos[i];
   const GeomDev& G = geoms[min(geom_of(p.w), n_geom - 1)];
@@ -399,6 +436,23 @@ extern "C" fppg_status fppg_relax_hvp(fppg_ctx* ctx, const fppg_geom* geom, int6
   }
   FPPG_HIP(ctx, hipGetLastError());
   return FPPG_OK;
+}
+
+extern "C" fppg_status fppg_relax_energy(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, const float* pos,
+                                         const int32_t* cell_start, uint32_t move_mask, double* out, void* ws,
+                                         size_t ws_bytes, void* stream) {
+  fppg_status st = check_common(ctx, geom, n, pos, cell_start);
+  if (st != FPPG_OK) return st;
+  if (!out || !ws || !aligned(ws, 256)) return fail(ctx, FPPG_E_ARG, "null out or null/misaligned ws");
+  const int nb = std::max(1, grid_for(n));
+  if (ws_bytes < size_t(nb) * sizeof(double)) return fail(ctx, FPPG_E_WORKSPACE, "workspace too small for relax_energy");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double* partial = static_cast<double*>(ws);
+  const float4* p4 = reinterpret_cast<const float4*>(pos);
+  if (geom->k == 1) k_energy<1><<<nb, kBlock, 0, s>>>(p4, int(n), cell_start, geom->d_geom, geom->n_geom, move_mask, partial);
+  else k_energy<2><<<nb, kBlock, 0, s>>>(p4, int(n), cell_start, geom->d_geom, geom->n_geom, move_mask, partial);
+  FPPG_HIP(ctx, hipGetLastError());
+  return sum_partials(ctx, partial, nb, out, s);
 }
 
 extern "C" fppg_status fppg_debug_neighbors(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, const float* pos,

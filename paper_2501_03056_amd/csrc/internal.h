@@ -135,11 +135,42 @@ struct WsLayout {
   size_t key, rank, tmp_id, tmp_src, tmp_key, count, blocksum, build_end;
   // relax_step
   size_t accel, step_end;
+  // relax_energy / vec_dot partial sums
+  size_t reduce_end;
   size_t total;
 };
 WsLayout ws_layout(const Geom* g, int64_t n);
 
+// Deterministic FP64 reductions (linalg.hip): per-block partial sums in a
+// fixed order, then one block sums the partials in index order.
+constexpr int kDotPartials = 2048;   // partial sums of fppg_vec_dot (doubles of workspace)
+fppg_status sum_partials(fppg_ctx* ctx, const double* partial, int nb, double* out, hipStream_t s);
+
 // Device helpers ---------------------------------------------------------------------------
+
+// FP64 sum over a block of 256 threads in a fixed tree order (thread 0 gets it).
+__device__ __forceinline__ double block_sum256(double v) {
+  __shared__ double s_part[4];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) t = (s_part[0] + s_part[1]) + (s_part[2] + s_part[3]);
+  __syncthreads();
+  return t;
+}
+
+// Workgroups are dealt to the 8 XCDs round-robin (workgroup b to XCD b % 8),
+// each XCD with its own L2. Map workgroup b to chunk c so that every XCD gets
+// one contiguous range of chunks: neighbouring receivers then share the halo
+// rows they read in the same L2. A bijection on [0, nb) for any nb.
+constexpr int kNumXcd = 8;
+__device__ __forceinline__ int xcd_chunk(int b, int nb) {
+  const int q = nb / kNumXcd, r = nb % kNumXcd;
+  const int x = b % kNumXcd, k = b / kNumXcd;
+  return x * q + min(x, r) + k;
+}
 
 __device__ __forceinline__ int tag_of(float w) { return __float_as_int(w) & 7; }
 __device__ __forceinline__ int geom_of(float w) { return (__float_as_int(w) >> 8) & 0xFFFF; }

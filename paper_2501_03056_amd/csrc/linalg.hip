@@ -1,0 +1,246 @@
+// Vector kernels for Newton-Krylov relaxation on particle fields (float4
+// arrays, x/y/z used, w ignored): FP64 dot products with a fixed summation
+// order (deterministic), y = alpha x + beta y, projection onto the tangent
+// spaces of the constrained particles, and the conversion of a direction into
+// the displacement format of fppg_project.
+#include "internal.h"
+
+namespace fppg {
+
+constexpr int kRedBlock = 256;   // block_sum256 assumes 256 threads
+
+__global__ __launch_bounds__(kRedBlock) void k_dot_partial(const float4* __restrict__ a, const float4* __restrict__ b,
+                                                           int n, int per_block, double* __restrict__ partial) {
+  const int base = blockIdx.x * per_block;
+  const int end = min(n, base + per_block);
+  double s = 0.0;
+  for (int i = base + threadIdx.x; i < end; i += kRedBlock) {
+    const float4 x = a[i], y = b[i];
+    s += double(x.x) * double(y.x) + double(x.y) * double(y.y) + double(x.z) * double(y.z);
+  }
+  const double t = block_sum256(s);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kRedBlock) void k_sum_partials(const double* __restrict__ partial, int nb,
+                                                            double* __restrict__ out) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += kRedBlock) s += partial[i];
+  const double t = block_sum256(s);
+  if (threadIdx.x == 0) *out = t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_axpby(int n, float alpha, const float4* __restrict__ x, float beta,
+                                                  float4* __restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float4 a = x[i];
+  float4 b = y[i];
+  b.x = fmaf(alpha, a.x, beta * b.x);
+  b.y = fmaf(alpha, a.y, beta * b.y);
+  b.z = fmaf(alpha, a.z, beta * b.z);
+  y[i] = b;
+}
+
+// v <- P v: surface I - n n^T (owner facet), feature t t^T (owner segment),
+// volume I, non-moving 0.
+__global__ __launch_bounds__(kBlock) void k_tangent(const float4* __restrict__ pos, const int* __restrict__ owner,
+                                                    const int* __restrict__ feat_seg, int n, int n_feat, int n_tri,
+                                                    int n_seg, const float4* __restrict__ n32,
+                                                    const SegDev* __restrict__ segs, uint32_t move_mask,
+                                                    float4* __restrict__ v, uint32_t* status) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int tag = tag_of(pos[i].w);
+  float4 x = v[i];
+  if (!is_moving(tag, move_mask)) {
+    x = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  } else if (tag == FPPG_TAG_SURFACE) {
+    const int o = owner[i];
+    if (o < 0 || o >= n_tri) {
+      atomicOr(status, FPPG_S_BAD_INDEX);
+      x = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    } else {
+      const float4 nn = n32[o];
+      const float s = x.x * nn.x + x.y * nn.y + x.z * nn.z;
+      x.x -= s * nn.x;
+      x.y -= s * nn.y;
+      x.z -= s * nn.z;
+    }
+  } else if (tag == FPPG_TAG_FEATURE) {
+    const int o = owner[i];
+    const int sg = (o >= 0 && o < n_feat) ? feat_seg[o] : -1;
+    if (sg < 0 || sg >= n_seg) {
+      atomicOr(status, FPPG_S_BAD_INDEX);
+      x = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    } else {
+      const SegDev S = segs[sg];
+      const double s = double(x.x) * S.t[0] + double(x.y) * S.t[1] + double(x.z) * S.t[2];
+      x.x = float(s * S.t[0]);
+      x.y = float(s * S.t[1]);
+      x.z = float(s * S.t[2]);
+    }
+  }
+  v[i] = x;
+}
+
+// disp = alpha P v in the format of fppg_project (feature: FP64 du = alpha v.t).
+__global__ __launch_bounds__(kBlock) void k_displace(const float4* __restrict__ pos, const int* __restrict__ owner,
+                                                     const int* __restrict__ feat_seg, int n, int n_feat, int n_tri,
+                                                     int n_seg, const float4* __restrict__ n32,
+                                                     const SegDev* __restrict__ segs, uint32_t move_mask,
+                                                     const float4* __restrict__ v, float alpha,
+                                                     float4* __restrict__ disp, uint32_t* status) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int tag = tag_of(pos[i].w);
+  float4 d = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  if (is_moving(tag, move_mask)) {
+    const float4 x = v[i];
+    float rx = alpha * x.x, ry = alpha * x.y, rz = alpha * x.z;
+    if (tag == FPPG_TAG_SURFACE) {
+      const int o = owner[i];
+      if (o < 0 || o >= n_tri) {
+        atomicOr(status, FPPG_S_BAD_INDEX);
+        rx = ry = rz = 0.0f;
+      } else {
+        const float4 nn = n32[o];
+        const float s = rx * nn.x + ry * nn.y + rz * nn.z;
+        rx -= s * nn.x;
+        ry -= s * nn.y;
+        rz -= s * nn.z;
+      }
+      d = make_float4(rx, ry, rz, 0.0f);
+    } else if (tag == FPPG_TAG_FEATURE) {
+      const int o = owner[i];
+      const int sg = (o >= 0 && o < n_feat) ? feat_seg[o] : -1;
+      if (sg < 0 || sg >= n_seg) {
+        atomicOr(status, FPPG_S_BAD_INDEX);
+      } else {
+        const SegDev S = segs[sg];
+        const double du = double(rx) * S.t[0] + double(ry) * S.t[1] + double(rz) * S.t[2];
+        const long long bits = __double_as_longlong(du);
+        d = make_float4(__int_as_float(int(bits & 0xffffffffll)), __int_as_float(int(bits >> 32)), 0.0f, 0.0f);
+      }
+    } else {
+      d = make_float4(rx, ry, rz, 0.0f);
+    }
+  }
+  disp[i] = d;
+}
+
+static inline int grid_for(int64_t n) { return int((n + kBlock - 1) / kBlock); }
+
+__global__ void k_zero_u32(unsigned* __restrict__ a, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0u;
+}
+
+fppg_status sum_partials(fppg_ctx* ctx, const double* partial, int nb, double* out, hipStream_t s) {
+  k_sum_partials<<<1, kRedBlock, 0, s>>>(partial, nb, out);
+  FPPG_HIP(ctx, hipGetLastError());
+  return FPPG_OK;
+}
+
+// Deterministic FP64 dot over n float4 rows into out[0] (device).
+fppg_status dot_into(fppg_ctx* ctx, int n, const float4* a, const float4* b, double* out, double* partial,
+                     int max_blocks, hipStream_t s) {
+  int nb = std::max(1, std::min(max_blocks, (n + kRedBlock * 8 - 1) / (kRedBlock * 8)));
+  const int per_block = (n + nb - 1) / nb;
+  if (n > 0) nb = (n + per_block - 1) / per_block;
+  k_dot_partial<<<nb, kRedBlock, 0, s>>>(a, b, n, per_block, partial);
+  k_sum_partials<<<1, kRedBlock, 0, s>>>(partial, n > 0 ? nb : 1, out);
+  FPPG_HIP(ctx, hipGetLastError());
+  return FPPG_OK;
+}
+
+}  // namespace fppg
+
+using namespace fppg;
+
+extern "C" fppg_status fppg_vec_dot(fppg_ctx* ctx, int64_t n, const float* a, const float* b, double* out, void* ws,
+                                    size_t ws_bytes, void* stream) {
+  if (!ctx) return FPPG_E_ARG;
+  if (n < 0 || n >= (int64_t(1) << 31)) return fail(ctx, FPPG_E_ARG, "n out of range");
+  if (!out || !ws || (n > 0 && (!a || !b))) return fail(ctx, FPPG_E_ARG, "null argument");
+  if (!aligned(a, 16) || !aligned(b, 16) || !aligned(ws, 256)) return fail(ctx, FPPG_E_ARG, "misaligned argument");
+  if (ws_bytes < kDotPartials * sizeof(double)) return fail(ctx, FPPG_E_WORKSPACE, "workspace too small for vec_dot");
+  if (n == 0) {
+    double* p = static_cast<double*>(ws);
+    k_sum_partials<<<1, kRedBlock, 0, static_cast<hipStream_t>(stream)>>>(p, 0, out);
+    FPPG_HIP(ctx, hipGetLastError());
+    return FPPG_OK;
+  }
+  return dot_into(ctx, int(n), reinterpret_cast<const float4*>(a), reinterpret_cast<const float4*>(b), out,
+                  static_cast<double*>(ws), kDotPartials, static_cast<hipStream_t>(stream));
+}
+
+extern "C" fppg_status fppg_vec_axpby(fppg_ctx* ctx, int64_t n, float alpha, const float* x, float beta, float* y,
+                                      void* stream) {
+  if (!ctx) return FPPG_E_ARG;
+  if (n < 0 || n >= (int64_t(1) << 31)) return fail(ctx, FPPG_E_ARG, "n out of range");
+  if (n > 0 && (!x || !y)) return fail(ctx, FPPG_E_ARG, "null argument");
+  if (!aligned(x, 16) || !aligned(y, 16)) return fail(ctx, FPPG_E_ARG, "misaligned argument");
+  if (n == 0) return FPPG_OK;
+  k_axpby<<<grid_for(n), kBlock, 0, static_cast<hipStream_t>(stream)>>>(int(n), alpha, reinterpret_cast<const float4*>(x),
+                                                                         beta, reinterpret_cast<float4*>(y));
+  FPPG_HIP(ctx, hipGetLastError());
+  return FPPG_OK;
+}
+
+__global__ __launch_bounds__(kBlock) void k_maxnorm(const float4* __restrict__ a, int n, unsigned* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  float m = 0.0f;
+  if (i < n) {
+    const float4 x = a[i];
+    m = sqrtf(x.x * x.x + x.y * x.y + x.z * x.z);
+    if (!(m >= 0.0f)) m = INFINITY;   // NaN counts as unbounded
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(out, __float_as_uint(m));
+}
+
+extern "C" fppg_status fppg_vec_maxnorm(fppg_ctx* ctx, int64_t n, const float* a, float* out, void* stream) {
+  if (!ctx) return FPPG_E_ARG;
+  if (n < 0 || n >= (int64_t(1) << 31)) return fail(ctx, FPPG_E_ARG, "n out of range");
+  if (!out || (n > 0 && !a) || !aligned(a, 16)) return fail(ctx, FPPG_E_ARG, "null or misaligned argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  k_zero_u32<<<1, 64, 0, s>>>(reinterpret_cast<unsigned*>(out), 1);
+  if (n > 0) k_maxnorm<<<grid_for(n), kBlock, 0, s>>>(reinterpret_cast<const float4*>(a), int(n), reinterpret_cast<unsigned*>(out));
+  FPPG_HIP(ctx, hipGetLastError());
+  return FPPG_OK;
+}
+
+extern "C" fppg_status fppg_tangent_project(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, const float* pos,
+                                            const int32_t* owner, const int32_t* feat_seg, int32_t n_feat,
+                                            uint32_t move_mask, float* v, void* stream) {
+  if (!ctx || !geom) return fail(ctx, FPPG_E_ARG, "null ctx/geom");
+  if (n != geom->n_part) return fail(ctx, FPPG_E_ARG, "n differs from the particle count of the geometry descriptors");
+  if (n > 0 && (!pos || !owner || !v)) return fail(ctx, FPPG_E_ARG, "null argument");
+  if (n_feat < 0 || (n_feat > 0 && !feat_seg)) return fail(ctx, FPPG_E_ARG, "bad feature table");
+  if (!aligned(pos, 16) || !aligned(v, 16)) return fail(ctx, FPPG_E_ARG, "misaligned argument");
+  if (n == 0) return FPPG_OK;
+  k_tangent<<<grid_for(n), kBlock, 0, static_cast<hipStream_t>(stream)>>>(
+      reinterpret_cast<const float4*>(pos), owner, feat_seg, int(n), n_feat, int(geom->n_tri), int(geom->n_seg),
+      geom->d_n32, geom->d_seg, move_mask, reinterpret_cast<float4*>(v), ctx->d_status);
+  FPPG_HIP(ctx, hipGetLastError());
+  return FPPG_OK;
+}
+
+extern "C" fppg_status fppg_displace(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, const float* pos,
+                                     const int32_t* owner, const int32_t* feat_seg, int32_t n_feat, uint32_t move_mask,
+                                     const float* v, float alpha, float* disp, void* stream) {
+  if (!ctx || !geom) return fail(ctx, FPPG_E_ARG, "null ctx/geom");
+  if (n != geom->n_part) return fail(ctx, FPPG_E_ARG, "n differs from the particle count of the geometry descriptors");
+  if (n > 0 && (!pos || !owner || !v || !disp)) return fail(ctx, FPPG_E_ARG, "null argument");
+  if (n_feat < 0 || (n_feat > 0 && !feat_seg)) return fail(ctx, FPPG_E_ARG, "bad feature table");
+  if (!aligned(pos, 16) || !aligned(v, 16) || !aligned(disp, 16)) return fail(ctx, FPPG_E_ARG, "misaligned argument");
+  if (n == 0) return FPPG_OK;
+  k_displace<<<grid_for(n), kBlock, 0, static_cast<hipStream_t>(stream)>>>(
+      reinterpret_cast<const float4*>(pos), owner, feat_seg, int(n), n_feat, int(geom->n_tri), int(geom->n_seg),
+      geom->d_n32, geom->d_seg, move_mask, reinterpret_cast<const float4*>(v), alpha, reinterpret_cast<float4*>(disp),
+      ctx->d_status);
+  FPPG_HIP(ctx, hipGetLastError());
+  return FPPG_OK;
+}

@@ -127,6 +127,7 @@ class Relaxer:
         self.n = int(wl.n)
         self.n_feat = int(len(wl.feat_seg))
         self.move_mask = int(wl.move_mask)
+        self.h_min = min(float(g.h) for g in wl.geoms)
         pos = np.zeros((self.n, 4), np.float32)
         pos[:, :3] = wl.pos
         pos[:, 3] = _pack_w(wl.tag, wl.gid)
@@ -186,6 +187,58 @@ class Relaxer:
         check(lib.fppg_relax_hvp(c, self.geom.handle, self.n, ptr(self.pos), ptr(self.cell_start),
                                  self.move_mask, int(bool(transpose)), ptr(v), ptr(out), self.stream), c)
         return out
+
+    # ---- Newton-Krylov building blocks ---------------------------------------------------------
+    def _scalar(self):
+        if not hasattr(self, "_d_scalar"):
+            self._d_scalar = torch.zeros(2, dtype=torch.float64, device=self.dev)
+        return self._d_scalar
+
+    def energy(self) -> float:
+        """Pair energy E of the moving particles at the current state (cells must be current)."""
+        lib, c = self.ctx.lib, self.ctx.handle
+        out = self._scalar()
+        check(lib.fppg_relax_energy(c, self.geom.handle, self.n, ptr(self.pos), ptr(self.cell_start),
+                                    self.move_mask, ptr(out), self.ws_ptr, self.ws_bytes, self.stream), c)
+        return float(out[0].item())
+
+    def dot(self, a: torch.Tensor, b: torch.Tensor) -> float:
+        lib, c = self.ctx.lib, self.ctx.handle
+        out = self._scalar()
+        check(lib.fppg_vec_dot(c, self.n, ptr(a), ptr(b), ptr(out), self.ws_ptr, self.ws_bytes, self.stream), c)
+        return float(out[0].item())
+
+    def axpby(self, alpha: float, x: torch.Tensor, beta: float, y: torch.Tensor):
+        """y <- alpha x + beta y (in place)."""
+        lib, c = self.ctx.lib, self.ctx.handle
+        check(lib.fppg_vec_axpby(c, self.n, float(alpha), ptr(x), float(beta), ptr(y), self.stream), c)
+
+    def maxnorm(self, a: torch.Tensor) -> float:
+        lib, c = self.ctx.lib, self.ctx.handle
+        out = self._scalar()
+        check(lib.fppg_vec_maxnorm(c, self.n, ptr(a), ptr(out), self.stream), c)
+        return float(out.view(torch.float32)[0].item())
+
+    def tangent(self, v: torch.Tensor):
+        """v <- P v (tangent spaces of the constrained particles; 0 where nothing moves)."""
+        lib, c = self.ctx.lib, self.ctx.handle
+        check(lib.fppg_tangent_project(c, self.geom.handle, self.n, ptr(self.pos), ptr(self.owner),
+                                       ptr(self.feat_seg), self.n_feat, self.move_mask, ptr(v), self.stream), c)
+
+    def displace(self, v: torch.Tensor, alpha: float):
+        """self.disp <- alpha P v in the displacement format that project() applies."""
+        lib, c = self.ctx.lib, self.ctx.handle
+        check(lib.fppg_displace(c, self.geom.handle, self.n, ptr(self.pos), ptr(self.owner), ptr(self.feat_seg),
+                                self.n_feat, self.move_mask, ptr(v), float(alpha), ptr(self.disp), self.stream), c)
+
+    def snapshot(self):
+        """Device copies of the mutable state (positions, ids, owners, feature table, cells)."""
+        return (self.pos.clone(), self.id.clone(), self.owner.clone(), self.feat_seg.clone(),
+                self.feat_u.clone(), self.cell_start.clone())
+
+    def restore(self, snap):
+        for dst, src in zip((self.pos, self.id, self.owner, self.feat_seg, self.feat_u, self.cell_start), snap):
+            dst.copy_(src)
 
     def neighbors(self, cap: int = 160):
         lib, c = self.ctx.lib, self.ctx.handle

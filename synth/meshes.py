@@ -234,3 +234,35 @@ def gear(teeth=24, r_tip=1.0, r_root=0.85, r_bore=0.2, half_thick=0.15,
         closed.append(0)
     lines = FeatureLines.from_polylines(polys, closed)
     return Mesh(vert, tri, lines, np.array(singular))
+
+
+def cylinder(radius=0.5, height=1.0, segments=64) -> Mesh:
+    """Closed cylinder along z centred at the origin: fan caps and a side wall of
+    `segments` quads (4*segments facets); features are the two rim loops."""
+    th = np.arange(segments) * (2 * np.pi / segments)
+    ring = np.stack([radius * np.cos(th), radius * np.sin(th)], 1)
+    zb, zt = -height / 2, height / 2
+    vert = np.concatenate([np.concatenate([ring, np.full((segments, 1), zb)], 1),
+                           np.concatenate([ring, np.full((segments, 1), zt)], 1),
+                           [[0.0, 0.0, zb], [0.0, 0.0, zt]]], 0)
+    cb, ct = 2 * segments, 2 * segments + 1
+    tri = []
+    for k in range(segments):
+        a, b = k, (k + 1) % segments
+        tri.append([cb, b, a])                         # bottom cap
+        tri.append([ct, segments + a, segments + b])   # top cap
+        tri.append([a, b, segments + b])               # side
+        tri.append([a, segments + b, segments + a])
+    tri = _orient_outward(vert, np.array(tri, np.int32), np.zeros(3))
+    loops = [np.concatenate([vert[:segments], vert[:1]], 0),
+             np.concatenate([vert[segments:2 * segments], vert[segments:segments + 1]], 0)]
+    lines = FeatureLines.from_polylines(loops, [1, 1])
+    return Mesh(vert, tri.astype(np.int32), lines, np.zeros((0, 3)))
+
+
+def transformed(mesh: Mesh, R: np.ndarray, t: np.ndarray) -> Mesh:
+    """Rigid motion x -> R x + t of a mesh, its feature lines and singular points."""
+    seg = mesh.lines.seg_p @ R.T + t
+    lines = FeatureLines(mesh.lines.line_seg_begin.copy(), seg, mesh.lines.line_closed.copy())
+    sing = mesh.singular @ R.T + t if len(mesh.singular) else mesh.singular.copy()
+    return Mesh(mesh.vert @ R.T + t, mesh.tri.copy(), lines, sing)

@@ -420,3 +420,130 @@ def custom_workload(mesh, dx, pos, tag, owner=None, feat_seg=None, feat_u=None,
         b.feat_seg.append(np.asarray(feat_seg, np.int32))
         b.feat_u.append(np.asarray(feat_u, np.float64))
     return _finish(name, [(geom, b)], move_mask, 0, {"dx": dx})
+
+
+# ---------------------------------------------------------------------------
+# Convex solids and the batch of independent geometries
+# ---------------------------------------------------------------------------
+
+def _surface_particles_planar(b: _Builder, mesh: M.Mesh, dx: float, rng, jitter: float):
+    """Jittered square lattice of spacing dx on every plane of a mesh whose
+    faces are planar polygons split into coplanar facets; points kept at least
+    dx/2 from the polygon boundary, owner = the facet containing the point."""
+    A, B, C, n = _facet_planes(mesh)
+    d = np.einsum("ij,ij->i", n, A)
+    key = np.round(np.concatenate([n, d[:, None]], 1), 9)
+    _, group = np.unique(key, axis=0, return_inverse=True)
+    group = group.ravel()
+    for gidx in range(group.max() + 1):
+        fs = np.nonzero(group == gidx)[0]
+        nn = n[fs[0]]
+        u = B[fs[0]] - A[fs[0]]
+        u /= np.linalg.norm(u)
+        v = np.cross(nn, u)
+        o = A[fs[0]]
+        # boundary edges of the polygon: edges used by one facet of the group
+        cnt = {}
+        for f in fs:
+            t = mesh.tri[f]
+            for a, c in ((t[0], t[1]), (t[1], t[2]), (t[2], t[0])):
+                e = (min(a, c), max(a, c))
+                cnt[e] = cnt.get(e, 0) + 1
+        bnd = np.array([e for e, k in cnt.items() if k == 1])
+        P = mesh.vert[bnd[:, 0]] - o
+        Q = mesh.vert[bnd[:, 1]] - o
+        p2 = np.stack([P @ u, P @ v], 1)
+        q2 = np.stack([Q @ u, Q @ v], 1)
+        vs = mesh.vert[np.unique(mesh.tri[fs])] - o
+        uv = np.stack([vs @ u, vs @ v], 1)
+        lo, hi = uv.min(0), uv.max(0)
+        ga = np.arange(lo[0] + 0.5 * dx, hi[0], dx)
+        gb = np.arange(lo[1] + 0.5 * dx, hi[1], dx)
+        if len(ga) == 0 or len(gb) == 0:
+            continue
+        g2 = np.stack(np.meshgrid(ga, gb, indexing="ij"), -1).reshape(-1, 2)
+        g2 = g2 + rng.uniform(-jitter, jitter, g2.shape) * dx
+        # distance to every boundary segment (2-D)
+        e = q2 - p2
+        w = g2[:, None, :] - p2[None]
+        tt = np.clip(np.einsum("pek,ek->pe", w, e) / np.einsum("ek,ek->e", e, e), 0.0, 1.0)
+        dist = np.linalg.norm(w - tt[..., None] * e[None], axis=2).min(1)
+        g2 = g2[dist >= 0.5 * dx]
+        pts = o + g2[:, :1] * u + g2[:, 1:] * v
+        own = np.full(len(pts), -1)
+        for f in fs:
+            la, lb, lc = _bary(pts, A[f], B[f], C[f])
+            inside = (np.minimum(np.minimum(la, lb), lc) >= 0) & (own < 0)
+            own[inside] = f
+        keep = own >= 0
+        b.add(pts[keep], SURFACE, own[keep])
+
+
+def _bary(p, A, B, C):
+    e0, e1, w = B - A, C - A, p - A
+    d00, d01, d11 = e0 @ e0, e0 @ e1, e1 @ e1
+    d20, d21 = w @ e0, w @ e1
+    den = d00 * d11 - d01 * d01
+    lb = (d11 * d20 - d01 * d21) / den
+    lc = (d00 * d21 - d01 * d20) / den
+    return 1 - lb - lc, lb, lc
+
+
+def _convex_volume_particles(b: _Builder, mesh: M.Mesh, dx: float, rng, jitter: float):
+    lo, hi = mesh.bbox()
+    axes = [np.arange(lo[a] + 0.5 * dx, hi[a], dx) for a in range(3)]
+    g = np.stack(np.meshgrid(*axes, indexing="ij"), -1).reshape(-1, 3)
+    g = g + rng.uniform(-jitter, jitter, g.shape) * dx
+    b.add(g[_convex_inside(mesh, g, 0.5 * dx)], VOLUME)
+
+
+def _random_rotation(rng) -> np.ndarray:
+    q = rng.normal(size=4)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+                     [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+                     [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)]])
+
+
+def solid_geometry(rng, n_target: float, jitter=0.3, k=2):
+    """One random convex solid (box with edges U(0.1,1), or a 64-segment
+    cylinder with diameter and height U(0.1,1)), randomly rotated, with dx set
+    so that it holds about n_target particles. Returns (Geometry, _Builder, kind)."""
+    if rng.uniform() < 0.5:
+        e = rng.uniform(0.1, 1.0, 3)
+        mesh = M.cube(-e / 2, e / 2)
+        vol = float(np.prod(e))
+        kind = "box"
+    else:
+        dia, hgt = rng.uniform(0.1, 1.0, 2)
+        mesh = M.cylinder(dia / 2, hgt, 64)
+        vol = float(np.pi * (dia / 2) ** 2 * hgt)
+        kind = "cylinder"
+    mesh = M.transformed(mesh, _random_rotation(rng), np.zeros(3))
+    dx = (vol / n_target) ** (1.0 / 3.0)
+    geom = _make_geom(mesh, dx, k)
+    b = _Builder()
+    _convex_volume_particles(b, mesh, dx, rng, jitter)
+    _surface_particles_planar(b, mesh, dx, rng, jitter)
+    _feature_particles(b, mesh, dx, rng, jitter)
+    if len(mesh.singular):
+        b.add(mesh.singular, SINGULAR)
+    return geom, b, kind
+
+
+def batch_workload(n_geom=64, n_min=5e3, n_max=5e5, seed=4000, jitter=0.3, k=2,
+                   move_mask=ALL_MOVING, name=None) -> Workload:
+    """A batch of independent solids relaxed together: geometry b uses PCG64
+    seed `seed + b`, a log-uniform target count in [n_min, n_max]. The
+    geometries do not interact (each has its own cell grid and facets)."""
+    parts, kinds, targets = [], [], []
+    for g in range(n_geom):
+        rng = np.random.Generator(np.random.PCG64(seed + g))
+        n_t = float(np.exp(rng.uniform(np.log(n_min), np.log(n_max))))
+        geom, b, kind = solid_geometry(rng, n_t, jitter, k)
+        parts.append((geom, b))
+        kinds.append(kind)
+        targets.append(n_t)
+    return _finish(name or f"batch{n_geom}_seed{seed}", parts, move_mask, seed,
+                   {"kinds": kinds, "targets": targets})
