@@ -93,8 +93,107 @@ def cpu_baseline(wl, sample=160, seed=0):
                       f"({dt:.1f} s, numpy single thread)"}
 
 
+def bench_batch(args):
+    """64 independent solids (boxes and cylinders, 5k-500k particles each) in
+    one launch per kernel; k autotuned; iterations replayed from a HIP graph."""
+    import torch
+    import synth
+    from paper_2501_03056_amd import Relaxer
+    from paper_2501_03056_amd.tune import autotune, regrid
+    t0 = time.perf_counter()
+    wl = synth.workload.batch_workload(n_geom=64, seed=4000)
+    print(f"[bench] batch: {wl.n} particles in {len(wl.geoms)} geometries, built in "
+          f"{time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    tune = autotune(wl, cache=os.path.join(os.environ.get("TMPDIR", "/tmp"), "fppg_autotune.json"))
+    r = Relaxer(regrid(wl, tune["k"]), device=0)
+    for _ in range(args.warmup):
+        r.step(keep_accel=False)
+    r.profile(True)
+    for _ in range(10):
+        r.step(keep_accel=False)
+    prof = r.profile_read()
+    r.profile(False)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(20):
+        r.step(keep_accel=False)
+    e1.record()
+    torch.cuda.synchronize()
+    eager_ms = e0.elapsed_time(e1) / 20
+    r.capture(iters=2)
+    r.replay(2)
+    steps = args.steps - (args.steps % 2)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    r.replay(steps // 2)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    n_moving = wl.n_moving()
+    out = {"metric": "particle-updates/s per relaxation step", "value": n_moving * steps / (ms / 1e3),
+           "unit": "particle-updates/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+           "ms_per_step": ms / steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "batch64_boxes_cylinders_seed4000", "geometries": len(wl.geoms),
+                      "particles": wl.n, "moving": n_moving, "hip_graph_iters": 2, "autotune": tune},
+           "kernels_ms_per_step_eager": {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]},
+           "eager_ms_per_step": eager_ms,
+           "device_status": r.read_status()}
+    print(json.dumps(out), flush=True)
+
+
+def bench_newton(args):
+    """Newton-Krylov vs the plain loop on the volume particles of the sphere
+    (surface particles held as sources): wall-seconds to the residual the plain
+    loop reaches after --plain-iters iterations, from the same initial state."""
+    import torch
+    import synth
+    from paper_2501_03056_amd import Relaxer
+    from paper_2501_03056_amd.newton import newton_relax, plain_relax
+    wl = synth.sphere_workload(level=5, dx=args.newton_dx, seed=2, k=args.k, move_mask=1 << synth.VOLUME)
+    n_moving = wl.n_moving()
+    print(f"[bench] newton: {wl.n} particles, {n_moving} moving", file=sys.stderr, flush=True)
+    rp = Relaxer(wl, device=0)
+    plain = plain_relax(rp, n_moving, iters=args.plain_iters, record_every=2)
+    # the plain loop is not a descent method in R (its step stays h/16 for the fastest particle):
+    # the target is the best residual it reaches in its iterations, timed at its first arrival
+    best = min(range(len(plain)), key=lambda q: plain[q][1])
+    target, t_plain = plain[best][1], plain[best][0]
+    print(f"[bench] plain: R {plain[0][1]:.4g} -> best {target:.4g} at {t_plain:.4f}s (iter {2 * best}), "
+          f"final {plain[-1][1]:.4g} after {plain[-1][0]:.4f}s", file=sys.stderr, flush=True)
+    del rp
+    rn = Relaxer(wl, device=0)
+    torch.cuda.synchronize()
+    log = newton_relax(rn, n_moving, target=target, max_iter=200, time_limit=20 * plain[-1][0] + 20)
+    t_newton = log.residual[-1][0]
+    reached = log.residual[-1][1] <= target
+    # then keep going for the plain loop's whole wall time budget: how far below does Newton get?
+    more = newton_relax(rn, n_moving, target=None, max_iter=200, time_limit=plain[-1][0])
+    out = {"metric": "Newton-HVP vs plain s to residual", "value": t_plain / t_newton if reached else 0.0,
+           "unit": "x (plain s / Newton s to the plain loop's best residual)", "n_gpus": 1,
+           "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"icosphere_l5_dx{args.newton_dx:g}_volume_tier", "moving": n_moving,
+                      "plain_iters": args.plain_iters, "krylov": "MINRES", "krylov_tol": 1e-4,
+                      "move_cap": "h/4"},
+           "plain": {"seconds_to_best": t_plain, "iters_to_best": 2 * best, "R0": plain[0][1], "R_best": target,
+                     "R_final": plain[-1][1], "seconds_total": plain[-1][0], "curve": plain},
+           "newton": {"seconds": t_newton, "R_final": log.residual[-1][1], "reached": reached,
+                      "newton_iters": log.newton_iters, "krylov_iters": log.krylov_iters,
+                      "backtracks": log.backtracks, "curve": log.residual,
+                      "continued_for_plain_total_seconds": {
+                          "seconds": t_newton + more.residual[-1][0], "R": more.residual[-1][1],
+                          "newton_iters": more.newton_iters, "krylov_iters": more.krylov_iters}},
+           "device_status": rn.read_status()}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--mode", default="step", choices=["step", "batch", "newton"])
+    ap.add_argument("--plain-iters", type=int, default=100)
+    ap.add_argument("--newton-dx", type=float, default=0.01)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
@@ -109,6 +208,10 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design "
               "is described in DESIGN.md and is not built", file=sys.stderr)
         sys.exit(2)
+    if args.mode == "batch":
+        return bench_batch(args)
+    if args.mode == "newton":
+        return bench_newton(args)
     import torch
     from paper_2501_03056_amd import Relaxer
 

@@ -124,6 +124,8 @@ typedef struct {
   const int32_t* line_seg_begin; int32_t n_line;  /* [n_line + 1], may be NULL if n_line = 0 */
   const double*  seg_p;                   /* [n_seg * 6], n_seg = line_seg_begin[n_line] */
   const uint8_t* line_closed;             /* [n_line] */
+  const int32_t* seg_vert;                /* [n_seg * 2] mesh vertex (local index) at each segment
+                                             end, -1 if none; may be NULL (mesh gradients only) */
 } fppg_geom_desc;
 
 /* ---- context ---------------------------------------------------------------------------- */
@@ -298,6 +300,8 @@ fppg_status fppg_vec_axpby(fppg_ctx* ctx, int64_t n, float alpha, const float* x
 /* out[0] (device float) = max_i |a_i| (Euclidean norm of the xyz of row i);
  * a NaN row counts as +inf. */
 fppg_status fppg_vec_maxnorm(fppg_ctx* ctx, int64_t n, const float* a, float* out, void* stream);
+/* v_i <- v_i * min(1, cap / |v_i|) row by row (cap > 0): caps every particle's move. */
+fppg_status fppg_vec_clamp(fppg_ctx* ctx, int64_t n, float* v, float cap, void* stream);
 
 /*
  * v <- P v row by row: P = I - n n^T for a moving surface particle (n the
@@ -317,6 +321,113 @@ fppg_status fppg_tangent_project(fppg_ctx* ctx, const fppg_geom* geom, int64_t n
 fppg_status fppg_displace(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, const float* pos,
                           const int32_t* owner, const int32_t* feat_seg, int32_t n_feat,
                           uint32_t move_mask, const float* v, float alpha, float* disp, void* stream);
+
+/*
+ * fppg_project with a per-particle record of its decisions, for reverse-mode
+ * differentiation: accepted [n] uint8 (device) = 1 iff particle i moves
+ * (move_mask) and its move was applied, 0 if it was reverted or does not move.
+ * Otherwise identical to fppg_project.
+ */
+fppg_status fppg_project_record(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
+                                float* pos, int32_t* owner, const float* disp,
+                                int32_t* feat_seg, double* feat_u, int32_t n_feat, uint32_t move_mask,
+                                int64_t* counters, uint8_t* accepted, void* stream);
+
+/*
+ * Differentiation of a relaxation run with respect to the mesh vertices (an
+ * addition to the paper's method; section 3.3 defines the step that is
+ * differentiated). The discrete decisions of every step are frozen at their
+ * forward values: dt^2, the owner facet before and after the step, acceptance
+ * of the move, the neighbour sets. Between decisions one step is the smooth map
+ *   y  = x + dt^2 P_o a(x)        P_o = I - n_o n_o^T (surface), I (volume)
+ *   x' = y - ((y - A_t) . n_t) n_t  accepted surface move onto facet t = owner_next
+ *   x' = y                        accepted volume move
+ *   x' = x                        reverted move, or a particle that does not move
+ * with n = (B - A) x (C - A) / |.| of facet (A, B, C). Particles that do not
+ * move are functions of the mesh: a singular point is its vertex (owner[i] =
+ * its global vertex id), a feature particle the point at arc length u of its
+ * segment P0 + u (P1 - P0)/|P1 - P0| (feature particles must not move here).
+ *
+ * Vertex adjoints are accumulated in vbar_fixed [3 * n_vert] int64 (device,
+ * zeroed by the caller) as signed fixed point with 2^-40 units by integer
+ * atomics, so the result does not depend on the order of the atomics;
+ * fppg_fixed_to_double converts. Global vertex ids number the vertices of
+ * geometry g after those of geometries 0..g-1 (fppg_geom_desc.n_vert).
+ */
+
+/*
+ * Uniformity loss of the positions (binary32 input, FP64 arithmetic):
+ *   rho_i = W(0) + sum_{j != i, predicate(i, j)} W(|x_i - x_j|)  over all classes,
+ *   L = (1/N) sum_{i moving} (rho_i / rho0 - 1)^2,  N = number of moving particles,
+ * W the Wendland C2 kernel of Eq. 16 with alpha = 21/(16 pi h^3), the
+ * neighbour predicate of fppg_relax_step. out [2] doubles (device): L, N.
+ * grad [n*4] (device, may be NULL): dL/dx_i in binary32 (w = 0), with the
+ * neighbour sets held fixed. One rho0 for the whole batch. ws: at least
+ * 8 (n + 2 ceil(n/256)) + 64 bytes, 256-byte aligned.
+ */
+fppg_status fppg_uniformity_loss(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, const float* pos,
+                                 const int32_t* cell_start, uint32_t move_mask, double rho0,
+                                 double* out, float* grad, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Adjoint of one step through the projection and the tangential
+ * displacement. All arrays in the sorted order of that step: pos and owner
+ * entering it (after fppg_build_cells), owner_next and accepted after
+ * fppg_project_record, accel and amax written by fppg_relax_step. Given
+ * xbar_next = dL/dx', writes
+ *   ybar_i = dt^2 P_o (dx'/dy)^T xbar_next_i   (0 unless accepted): the adjoint of a_i
+ *   xbar_i = (dx'/dy)^T xbar_next_i if accepted, else xbar_next_i
+ * and adds the facet-vertex terms to vbar_fixed. The caller completes
+ * dL/dx = xbar + J^T ybar with fppg_relax_hvp(transpose = 1). xbar must not
+ * alias xbar_next. Returns FPPG_E_UNSUPPORTED if move_mask has the feature bit.
+ */
+fppg_status fppg_step_adjoint(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, const float* pos,
+                              const uint8_t* accepted, const int32_t* owner, const int32_t* owner_next,
+                              const float* accel, const float* amax, uint32_t move_mask,
+                              const float* xbar_next, float* ybar, float* xbar, int64_t* vbar_fixed,
+                              void* stream);
+
+/*
+ * Vertex terms of the particles that do not move: for each such particle
+ * with adjoint xbar_i, a singular point adds xbar_i to vertex owner[i]; a
+ * feature particle (slot owner[i], segment feat_seg[slot] with end vertices
+ * from fppg_geom_desc.seg_vert, arc length feat_u[slot]) adds
+ * (u/L)(I - t t^T) xbar_i to P1 and the rest of xbar_i to P0. Volume and
+ * fixed particles do not depend on the mesh.
+ */
+fppg_status fppg_fixed_adjoint(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, const float* pos,
+                               const int32_t* owner, const int32_t* feat_seg, const double* feat_u,
+                               int32_t n_feat, uint32_t move_mask, const float* xbar, int64_t* vbar_fixed,
+                               void* stream);
+
+/* Row permutation of a float4 field: scatter = 0: dst[i] = src[index[i]];
+ * scatter = 1: dst[index[i]] = src[i]. index is a permutation of [0, n);
+ * rows with an out-of-range index are skipped. dst must not alias src. */
+fppg_status fppg_vec_permute(fppg_ctx* ctx, int64_t n, const float* src, const int32_t* index,
+                             int32_t scatter, float* dst, void* stream);
+
+/* out[i] = in[i] * 2^-40 (fixed-point vertex adjoints to double), device arrays. */
+fppg_status fppg_fixed_to_double(fppg_ctx* ctx, int64_t count, const int64_t* in, double* out, void* stream);
+
+/*
+ * HIP-graph capture of whole iterations (build_cells -> relax_step ->
+ * project). Iteration t reads particle buffer set A for even t and B for odd
+ * t and writes the other one; `iters` must be even (>= 2) so the state
+ * returns to set A and the graph can be replayed back to back. All other
+ * buffers are those of the per-iteration calls (accel is the workspace's).
+ * Capture uses `stream` (must not be the default stream) in thread-local mode;
+ * profiling must be off. fppg_graph_launch enqueues `repeats` replays
+ * (repeats * iters iterations) on `stream`. Every node is a kernel.
+ */
+typedef struct fppg_graph fppg_graph;
+fppg_status fppg_graph_create(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
+                              float* pos_a, int32_t* id_a, int32_t* owner_a,
+                              float* pos_b, int32_t* id_b, int32_t* owner_b, int32_t* cell_start,
+                              int32_t* feat_seg, double* feat_u, int32_t n_feat, uint32_t move_mask,
+                              float* amax, float* disp, int64_t* counters, void* ws, size_t ws_bytes,
+                              int32_t iters, void* stream, fppg_graph** out);
+fppg_status fppg_graph_launch(fppg_ctx* ctx, fppg_graph* graph, int32_t repeats, void* stream);
+void        fppg_graph_destroy(fppg_graph* graph);
 
 /*
  * Test/diagnostic export of the neighbour sets seen by the force traversal:

@@ -27,6 +27,7 @@ class GeomDesc(ctypes.Structure):
         ("tri", POINTER(c_int32)), ("n_tri", c_int32),
         ("line_seg_begin", POINTER(c_int32)), ("n_line", c_int32),
         ("seg_p", POINTER(c_double)), ("line_closed", POINTER(c_uint8)),
+        ("seg_vert", POINTER(c_int32)),
     ]
 
 
@@ -50,12 +51,23 @@ _SIGS = {
     "fppg_project": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, _P, c_int32, c_uint32, _P, _P]),
     "fppg_relax_hvp": (c_int32, [_P, _P, c_int64, _P, _P, c_uint32, c_int32, _P, _P, _P]),
     "fppg_debug_neighbors": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, c_int32, _P]),
+    "fppg_graph_create": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, c_int32, c_uint32,
+                                    _P, _P, _P, _P, c_size_t, c_int32, _P, POINTER(c_void_p)]),
+    "fppg_graph_launch": (c_int32, [_P, _P, c_int32, _P]),
+    "fppg_graph_destroy": (None, [_P]),
     "fppg_relax_energy": (c_int32, [_P, _P, c_int64, _P, _P, c_uint32, _P, _P, c_size_t, _P]),
     "fppg_vec_dot": (c_int32, [_P, c_int64, _P, _P, _P, _P, c_size_t, _P]),
     "fppg_vec_axpby": (c_int32, [_P, c_int64, c_float, _P, c_float, _P, _P]),
     "fppg_vec_maxnorm": (c_int32, [_P, c_int64, _P, _P, _P]),
+    "fppg_vec_clamp": (c_int32, [_P, c_int64, _P, c_float, _P]),
     "fppg_tangent_project": (c_int32, [_P, _P, c_int64, _P, _P, _P, c_int32, c_uint32, _P, _P]),
     "fppg_displace": (c_int32, [_P, _P, c_int64, _P, _P, _P, c_int32, c_uint32, _P, c_float, _P, _P]),
+    "fppg_project_record": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, _P, c_int32, c_uint32, _P, _P, _P]),
+    "fppg_uniformity_loss": (c_int32, [_P, _P, c_int64, _P, _P, c_uint32, c_double, _P, _P, _P, c_size_t, _P]),
+    "fppg_step_adjoint": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, _P, _P, c_uint32, _P, _P, _P, _P, _P]),
+    "fppg_fixed_adjoint": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, c_int32, c_uint32, _P, _P, _P]),
+    "fppg_vec_permute": (c_int32, [_P, c_int64, _P, _P, c_int32, _P, _P]),
+    "fppg_fixed_to_double": (c_int32, [_P, c_int64, _P, _P, _P]),
 }
 
 _lib = None

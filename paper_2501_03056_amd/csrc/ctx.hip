@@ -169,6 +169,8 @@ static void free_geom(Geom* g) {
   hipFree(g->d_facet);
   hipFree(g->d_n32);
   hipFree(g->d_seg);
+  hipFree(g->d_tri_vert);
+  hipFree(g->d_seg_vert);
   hipFree(g->d_tg_start);
   hipFree(g->d_tg_tri);
   hipFree(g->d_tg_flag);
@@ -185,6 +187,9 @@ static fppg_status geom_create(fppg_ctx* ctx, const fppg_geom_desc* descs, int32
   std::vector<FacetDev> facets;
   std::vector<float4> n32;
   std::vector<SegDev> segs;
+  std::vector<int4> tri_vert;
+  std::vector<int2> seg_vert;
+  int32_t vert_off = 0;
   std::vector<int32_t> tg_start;   // global
   std::vector<int32_t> tg_tri;
   std::vector<uint8_t> tg_flag;
@@ -250,6 +255,7 @@ static fppg_status geom_create(fppg_ctx* ctx, const fppg_geom_desc* descs, int32
       f.inv_den = 1.0 / (f.d00 * f.d11 - f.d01 * f.d01);
       facets.push_back(f);
       n32.push_back(make_float4(float(f.n[0]), float(f.n[1]), float(f.n[2]), 0.f));
+      tri_vert.push_back(make_int4(vert_off + d.tri[3 * t], vert_off + d.tri[3 * t + 1], vert_off + d.tri[3 * t + 2], 0));
     }
     // feature segments
     G.seg_begin = seg_off;
@@ -274,6 +280,13 @@ static fppg_status geom_create(fppg_ctx* ctx, const fppg_geom_desc* descs, int32
         sd.closed = d.line_closed[l] ? 1 : 0;
         sd.pad = 0;
         segs.push_back(sd);
+        int2 sv = make_int2(-1, -1);
+        if (d.seg_vert) {
+          const int32_t a = d.seg_vert[2 * s], b2 = d.seg_vert[2 * s + 1];
+          if (a >= d.n_vert || b2 >= d.n_vert) return fail(ctx, FPPG_E_ARG, "seg_vert index out of range");
+          sv = make_int2(a >= 0 ? vert_off + a : -1, b2 >= 0 ? vert_off + b2 : -1);
+        }
+        seg_vert.push_back(sv);
       }
     }
     seg_off += nseg;
@@ -283,6 +296,7 @@ static fppg_status geom_create(fppg_ctx* ctx, const fppg_geom_desc* descs, int32
     fppg_status st = build_search_grid(ctx, d, tri_off, sg);
     if (st != FPPG_OK) return st;
     tri_off += d.n_tri;
+    vert_off += d.n_vert;
     for (int q = 0; q < 3; ++q) {
       G.tg_origin[q] = sg.origin[q];
       G.tg_dims[q] = sg.dims[q];
@@ -309,11 +323,14 @@ static fppg_status geom_create(fppg_ctx* ctx, const fppg_geom_desc* descs, int32
   geo->tg_cells = tg_cells;
   geo->tg_entries = int64_t(tg_tri.size());
   geo->n_part = part;
+  geo->n_vert = vert_off;
   geo->host = gd;
   geo->device = ctx->device;
   fppg_status st = FPPG_OK;
   if ((st = upload(ctx, &geo->d_geom, gd)) != FPPG_OK || (st = upload(ctx, &geo->d_facet, facets)) != FPPG_OK ||
       (st = upload(ctx, &geo->d_n32, n32)) != FPPG_OK || (st = upload(ctx, &geo->d_seg, segs)) != FPPG_OK ||
+      (st = upload(ctx, &geo->d_tri_vert, tri_vert)) != FPPG_OK ||
+      (st = upload(ctx, &geo->d_seg_vert, seg_vert)) != FPPG_OK ||
       (st = upload(ctx, &geo->d_tg_start, tg_start)) != FPPG_OK ||
       (st = upload(ctx, &geo->d_tg_tri, tg_tri)) != FPPG_OK || (st = upload(ctx, &geo->d_tg_flag, tg_flag)) != FPPG_OK) {
     free_geom(geo);

@@ -64,11 +64,14 @@ struct Geom {
   int64_t n_tri = 0, n_seg = 0;
   int64_t tg_cells = 0, tg_entries = 0;
   int64_t n_part = 0;
+  int64_t n_vert = 0;               // mesh vertices over the batch
   std::vector<GeomDev> host;
   GeomDev* d_geom = nullptr;
   FacetDev* d_facet = nullptr;
   float4* d_n32 = nullptr;          // binary32 unit normals (tangential projection)
+  int4* d_tri_vert = nullptr;       // global vertex ids of each facet (A, B, C, 0)
   SegDev* d_seg = nullptr;
+  int2* d_seg_vert = nullptr;       // global vertex ids of each segment end (-1: none)
   int32_t* d_tg_start = nullptr;    // [tg_cells + 1]
   int32_t* d_tg_tri = nullptr;      // [tg_entries] global facet ids
   uint8_t* d_tg_flag = nullptr;     // [tg_cells]

@@ -188,6 +188,30 @@ extern "C" fppg_status fppg_vec_axpby(fppg_ctx* ctx, int64_t n, float alpha, con
   return FPPG_OK;
 }
 
+__global__ __launch_bounds__(kBlock) void k_clamp(float4* __restrict__ v, int n, float cap) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float4 x = v[i];
+  const float m = sqrtf(x.x * x.x + x.y * x.y + x.z * x.z);
+  if (m > cap) {
+    const float s = cap / m;
+    x.x *= s;
+    x.y *= s;
+    x.z *= s;
+    v[i] = x;
+  }
+}
+
+extern "C" fppg_status fppg_vec_clamp(fppg_ctx* ctx, int64_t n, float* v, float cap, void* stream) {
+  if (!ctx) return FPPG_E_ARG;
+  if (n < 0 || n >= (int64_t(1) << 31) || !(cap > 0.0f)) return fail(ctx, FPPG_E_ARG, "bad n or cap");
+  if (n > 0 && (!v || !aligned(v, 16))) return fail(ctx, FPPG_E_ARG, "null or misaligned argument");
+  if (n == 0) return FPPG_OK;
+  k_clamp<<<grid_for(n), kBlock, 0, static_cast<hipStream_t>(stream)>>>(reinterpret_cast<float4*>(v), int(n), cap);
+  FPPG_HIP(ctx, hipGetLastError());
+  return FPPG_OK;
+}
+
 __global__ __launch_bounds__(kBlock) void k_maxnorm(const float4* __restrict__ a, int n, unsigned* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   float m = 0.0f;

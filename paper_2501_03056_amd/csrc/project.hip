@@ -188,9 +188,10 @@ __global__ __launch_bounds__(kBlock) void k_project(float4* __restrict__ pos, in
                                                     const FacetDev* __restrict__ facets,
                                                     const int* __restrict__ tstart, const int* __restrict__ ttri,
                                                     const uint8_t* __restrict__ tflag, uint32_t move_mask,
-                                                    unsigned long long* __restrict__ counters, uint32_t* status) {
+                                                    unsigned long long* __restrict__ counters, uint32_t* status,
+                                                    uint8_t* __restrict__ accepted) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  bool rev_s = false, rev_f = false, rev_v = false;
+  bool rev_s = false, rev_f = false, rev_v = false, moved = false;
   if (i < n) {
     const float4 p = pos[i];
     const int tag = tag_of(p.w);
@@ -205,6 +206,7 @@ __global__ __launch_bounds__(kBlock) void k_project(float4* __restrict__ pos, in
           rev_v = true;                                    // would leave the volume: stays at x
         } else {
           pos[i] = make_float4(y0, y1, y2, p.w);
+          moved = true;
         }
       } else if (tag == FPPG_TAG_SURFACE) {
         const double yx = double(p.x) + double(d.x), yy = double(p.y) + double(d.y), yz = double(p.z) + double(d.z);
@@ -215,6 +217,7 @@ __global__ __launch_bounds__(kBlock) void k_project(float4* __restrict__ pos, in
           if (h.t != 0x7fffffff) {
             pos[i] = make_float4(float(h.x), float(h.y), float(h.z), p.w);
             owner[i] = h.t;
+            moved = true;
           } else {
             rev_s = true;                                  // no facet accepts: stays at x (section 3.3.3)
           }
@@ -233,6 +236,7 @@ __global__ __launch_bounds__(kBlock) void k_project(float4* __restrict__ pos, in
                                  float(S.p0[2] + u * S.t[2]), p.w);
             feat_seg[slot] = s;
             feat_u[slot] = u;
+            moved = true;
           } else {
             if (!isfinite(u)) atomicOr(status, FPPG_S_NONFINITE_POS);
             rev_f = true;
@@ -240,6 +244,7 @@ __global__ __launch_bounds__(kBlock) void k_project(float4* __restrict__ pos, in
         }
       }
     }
+    if (accepted) accepted[i] = moved ? 1 : 0;
   }
   wave_count(rev_s, &counters[FPPG_C_REVERT_SURFACE]);
   wave_count(rev_f, &counters[FPPG_C_REVERT_FEATURE]);
@@ -252,9 +257,11 @@ static inline int grid_for(int64_t n) { return int((n + kBlock - 1) / kBlock); }
 
 using namespace fppg;
 
-extern "C" fppg_status fppg_project(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, float* pos, int32_t* owner,
-                                    const float* disp, int32_t* feat_seg, double* feat_u, int32_t n_feat,
-                                    uint32_t move_mask, int64_t* counters, void* stream) {
+namespace {
+
+static fppg_status project_impl(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, float* pos, int32_t* owner,
+                                const float* disp, int32_t* feat_seg, double* feat_u, int32_t n_feat,
+                                uint32_t move_mask, int64_t* counters, uint8_t* accepted, void* stream) {
   if (!ctx || !geom) return fail(ctx, FPPG_E_ARG, "null ctx/geom");
   if (n != geom->n_part) return fail(ctx, FPPG_E_ARG, "n differs from the particle count of the geometry descriptors");
   if (n > 0 && (!pos || !owner || !disp)) return fail(ctx, FPPG_E_ARG, "null pos/owner/disp");
@@ -269,7 +276,23 @@ extern "C" fppg_status fppg_project(fppg_ctx* ctx, const fppg_geom* geom, int64_
                                             ni, feat_seg, feat_u, n_feat, int(geom->n_seg), geom->d_seg, geom->d_geom,
                                             geom->n_geom, geom->d_facet, geom->d_tg_start, geom->d_tg_tri,
                                             geom->d_tg_flag, move_mask, reinterpret_cast<unsigned long long*>(counters),
-                                            ctx->d_status);
+                                            ctx->d_status, accepted);
   FPPG_HIP(ctx, hipGetLastError());
   return FPPG_OK;
+}
+
+}  // namespace
+
+extern "C" fppg_status fppg_project(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, float* pos, int32_t* owner,
+                                    const float* disp, int32_t* feat_seg, double* feat_u, int32_t n_feat,
+                                    uint32_t move_mask, int64_t* counters, void* stream) {
+  return project_impl(ctx, geom, n, pos, owner, disp, feat_seg, feat_u, n_feat, move_mask, counters, nullptr, stream);
+}
+
+extern "C" fppg_status fppg_project_record(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, float* pos,
+                                           int32_t* owner, const float* disp, int32_t* feat_seg, double* feat_u,
+                                           int32_t n_feat, uint32_t move_mask, int64_t* counters, uint8_t* accepted,
+                                           void* stream) {
+  if (n > 0 && !accepted) return fail(ctx, FPPG_E_ARG, "null accepted");
+  return project_impl(ctx, geom, n, pos, owner, disp, feat_seg, feat_u, n_feat, move_mask, counters, accepted, stream);
 }

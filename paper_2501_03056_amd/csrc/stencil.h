@@ -1,0 +1,90 @@
+// Culled stencil walk over the particle cell list, shared by the pair-sweep
+// kernels (forces, Jacobian products, energy, density loss, neighbour export).
+//
+// One lane per sorted receiver. With x-fastest cell keys the cells of a
+// stencil row along x are contiguous in the sorted order, so a receiver
+// visits at most (2k+1)^2 contiguous index ranges. Rows and the x-extent of a
+// row are culled in cell units against the support radius: a skipped cell is
+// at least k cell edges (> 2h, the edge being (2h/k)(1+2^-9) or more) from the
+// receiver, so it holds no source and culled sums are bitwise identical to
+// full-stencil sums. Sources are visited in a fixed order (rows by dz then dy
+// ascending, then sorted index).
+#pragma once
+
+#include "internal.h"
+
+namespace fppg {
+
+// Receiver cell and its fractional position inside the cell (cell units).
+struct Stencil {
+  int x, y, z;
+  float fx, fy, fz;
+};
+
+__device__ __forceinline__ Stencil stencil_of(const float4 p, const GeomDev& G) {
+  float tx = (p.x - G.origin[0]) * G.inv_cell;
+  float ty = (p.y - G.origin[1]) * G.inv_cell;
+  float tz = (p.z - G.origin[2]) * G.inv_cell;
+  // clamping moves an outside receiver onto the grid box: gaps only shrink
+  tx = fminf(fmaxf(tx, 0.0f), float(G.dims[0] - 1));
+  ty = fminf(fmaxf(ty, 0.0f), float(G.dims[1] - 1));
+  tz = fminf(fmaxf(tz, 0.0f), float(G.dims[2] - 1));
+  const float cx = floorf(tx), cy = floorf(ty), cz = floorf(tz);
+  return Stencil{int(cx), int(cy), int(cz), tx - cx, ty - cy, tz - cz};
+}
+
+// Distance in cell units from a receiver at fraction f of its cell to the
+// cell d cells away along one axis.
+__device__ __forceinline__ float cell_gap(int d, float f) {
+  return d > 0 ? float(d) - f : (d < 0 ? f + float(-d - 1) : 0.0f);
+}
+
+// Visit the source index ranges of the stencil of a receiver, culled to the
+// cells within k cell edges.
+template <int K, class F>
+__device__ __forceinline__ void for_each_row(const Stencil s, const GeomDev& G, const int* __restrict__ cs, F&& f) {
+  const float kk = float(K * K);
+#pragma unroll
+  for (int dz = -K; dz <= K; ++dz) {
+    const int z = s.z + dz;
+    if (z < 0 || z >= G.dims[2]) continue;
+    const float gz = cell_gap(dz, s.fz);
+#pragma unroll
+    for (int dy = -K; dy <= K; ++dy) {
+      const int y = s.y + dy;
+      if (y < 0 || y >= G.dims[1]) continue;
+      const float gy = cell_gap(dy, s.fy);
+      const float r2 = kk - (gy * gy + gz * gz);
+      if (!(r2 > 0.0f)) continue;
+      const float rho = __builtin_amdgcn_sqrtf(r2);
+      const int below = min(K, int(ceilf(rho - s.fx + 1.0f)) - 1);   // |dx| with f + |dx| - 1 < rho
+      const int above = min(K, int(ceilf(rho + s.fx)) - 1);          // dx with dx - f < rho
+      const int x0 = max(s.x - below, 0), x1 = min(s.x + above, G.dims[0] - 1);
+      const int row = int(G.cell_begin) + (z * G.dims[1] + y) * G.dims[0];
+      f(cs[row + x0], cs[row + x1 + 1]);
+    }
+  }
+}
+
+// Visit every source index of the stencil, four loads in flight at a time.
+template <int K, class F>
+__device__ __forceinline__ void for_each_source(const Stencil s, const GeomDev& G, const int* __restrict__ cs,
+                                                const float4* __restrict__ pos, F&& f) {
+  for_each_row<K>(s, G, cs, [&](int j0, int j1) {
+    int j = j0;
+    for (; j + 4 <= j1; j += 4) {
+      const float4 q0 = pos[j], q1 = pos[j + 1], q2 = pos[j + 2], q3 = pos[j + 3];
+      f(j, q0);
+      f(j + 1, q1);
+      f(j + 2, q2);
+      f(j + 3, q3);
+    }
+    for (; j < j1; ++j) f(j, pos[j]);
+  });
+}
+
+__device__ __forceinline__ float pair_d2(float dx, float dy, float dz) {
+  return (dx * dx + dy * dy) + dz * dz;   // no contraction in this file
+}
+
+}  // namespace fppg

@@ -1,21 +1,22 @@
-"""Newton-Krylov relaxation (trust-region Newton-CG, Steihaug) on one GPU.
+"""Newton-Krylov relaxation on one GPU.
 
 The plain loop of Algorithm 1 moves every particle by dt^2 a with
-dt^2 = (h/16)/max|a|: a gradient step of the pair energy E scaled so that the
-fastest particle moves h/16. For one moving class with fixed other sources
-the force field is a = -grad E (fppg_relax_energy), so the relaxation is an
-energy minimisation that a Newton method can take in far fewer sweeps:
+dt^2 = (h/16)/max|a|: the fastest particle always moves h/16, so the loop
+settles into a noise floor of the force residual instead of converging.
+Relaxation is done when the tangential forces vanish,
 
-    b = P a                                   (tangent-space force)
-    solve (P H P) d = b by CG, H v = -J v     (fppg_relax_hvp, fppg_tangent_project)
-    truncated at the trust-region radius or at negative curvature (Steihaug),
-    x <- Pi(x + s d)                          (fppg_displace + fppg_project)
-    accept if the actual energy decrease is a fair share of the predicted one,
-    adapt the radius.
+    F(x) = P a(x) = 0,
 
-H is indefinite (the pair curvature across the bond is negative), hence the
-trust region. s caps the largest single-particle move at h/2 so the
-projection and revert rules act on short steps as in the plain loop. Every
+and Newton's method solves that system directly:
+
+    solve  (P J P) d = -F  with MINRES            J d from fppg_relax_hvp, P from
+                                                   fppg_tangent_project
+    cap every particle's move at move_cap * h    fppg_vec_clamp
+    x <- Pi(x + s d), s = 1, 1/2, ... until |F|^2 decreases   fppg_displace + fppg_project
+
+For one moving class with fixed other sources J = -Hess(E) is symmetric but
+indefinite (pair curvature across a bond is negative), which is exactly the
+case MINRES handles (conjugate gradients would break down on it). Every
 vector operation runs in the library's kernels; this module only sequences
 them and reads back scalars.
 """
@@ -31,7 +32,7 @@ from .relax import Relaxer
 
 
 def projected_force(r: Relaxer) -> torch.Tensor:
-    """Rebuild the cells at the current positions and return b = P a."""
+    """Rebuild the cells at the current positions and return F = P a."""
     r.build_cells()
     r.relax_step(keep_accel=True)
     b = r.accel.clone()
@@ -44,105 +45,109 @@ def force_residual(r: Relaxer, b: torch.Tensor, n_moving: int) -> float:
     return math.sqrt(max(r.dot(b, b), 0.0) / max(n_moving, 1))
 
 
-def _to_boundary(dd: float, dp: float, pp: float, delta: float) -> float:
-    """tau >= 0 with |d + tau p| = delta."""
-    a, bq, c = pp, 2.0 * dp, dd - delta * delta
-    disc = max(bq * bq - 4.0 * a * c, 0.0)
-    return (-bq + math.sqrt(disc)) / (2.0 * a) if a > 0 else 0.0
-
-
 @dataclass
 class NewtonLog:
     residual: list = field(default_factory=list)   # (wall s, R) after every accepted step
-    energy: list = field(default_factory=list)
     newton_iters: int = 0
-    cg_iters: int = 0
-    rejected: int = 0
+    krylov_iters: int = 0
+    backtracks: int = 0
+
+
+class _Minres:
+    """MINRES (Paige-Saunders) for A x = b with A = -P J P, on device vectors."""
+
+    def __init__(self, r: Relaxer, like: torch.Tensor):
+        self.r = r
+        self.v, self.y, self.r1, self.r2 = (torch.empty_like(like) for _ in range(4))
+        self.w, self.w1, self.w2 = (torch.empty_like(like) for _ in range(3))
+
+    def apply(self, v: torch.Tensor, out: torch.Tensor):
+        self.r.hvp(v, out=out)                 # J v
+        self.r.tangent(out)                    # P J v
+        self.r.axpby(0.0, v, -1.0, out)        # -P J v
+
+    def solve(self, b: torch.Tensor, x: torch.Tensor, rtol: float, maxit: int) -> int:
+        r = self.r
+        x.zero_()
+        self.r1.copy_(b)
+        self.r2.copy_(b)
+        self.y.copy_(b)
+        beta1 = math.sqrt(max(r.dot(b, b), 0.0))
+        if beta1 == 0.0:
+            return 0
+        oldb, beta, dbar, epsln, phibar, cs, sn = 0.0, beta1, 0.0, 0.0, beta1, -1.0, 0.0
+        self.w.zero_()
+        self.w2.zero_()
+        it = 0
+        for it in range(1, maxit + 1):
+            r.axpby(1.0 / beta, self.y, 0.0, self.v)           # v = y / beta
+            self.apply(self.v, self.y)                         # y = A v
+            if it >= 2:
+                r.axpby(-beta / oldb, self.r1, 1.0, self.y)
+            alfa = r.dot(self.v, self.y)
+            r.axpby(-alfa / beta, self.r2, 1.0, self.y)
+            self.r1, self.r2 = self.r2, self.r1
+            self.r2.copy_(self.y)
+            oldb, beta = beta, math.sqrt(max(r.dot(self.r2, self.r2), 0.0))
+            oldeps = epsln
+            delta = cs * dbar + sn * alfa
+            gbar = sn * dbar - cs * alfa
+            epsln = sn * beta
+            dbar = -cs * beta
+            gamma = max(math.hypot(gbar, beta), 1e-300)
+            cs, sn = gbar / gamma, beta / gamma
+            phi = cs * phibar
+            phibar = sn * phibar
+            # w_new = (v - oldeps w1 - delta w2) / gamma, with (w1, w2) <- (w2, w)
+            self.w1, self.w2, self.w = self.w2, self.w, self.w1
+            r.axpby(1.0 / gamma, self.v, 0.0, self.w)
+            r.axpby(-oldeps / gamma, self.w1, 1.0, self.w)
+            r.axpby(-delta / gamma, self.w2, 1.0, self.w)
+            r.axpby(phi, self.w, 1.0, x)
+            if phibar <= rtol * beta1 or beta == 0.0:
+                break
+        return it
 
 
 def newton_relax(r: Relaxer, n_moving: int, target: float | None = None, max_iter: int = 50,
-                 cg_tol: float = 1e-4, cg_max: int = 60, delta0: float | None = None,
-                 move_cap: float = 0.5, time_limit: float | None = None) -> NewtonLog:
-    """Minimise E over the moving particles until the force residual is <= target."""
+                 krylov_tol: float = 1e-4, krylov_max: int = 50, move_cap: float = 0.25,
+                 max_backtracks: int = 6, time_limit: float | None = None) -> NewtonLog:
+    """Newton-MINRES on F = P a until the force residual is <= target."""
     h = r.h_min
-    delta = delta0 if delta0 is not None else 0.25 * h * math.sqrt(max(n_moving, 1))
     log = NewtonLog()
     t0 = time.perf_counter()
-    b = projected_force(r)
-    E = r.energy()
-    R = force_residual(r, b, n_moving)
-    log.residual.append((0.0, R))
-    log.energy.append(E)
-    d = torch.zeros_like(b)
-    res = torch.empty_like(b)
-    p = torch.empty_like(b)
-    Hp = torch.empty_like(b)
+    F = projected_force(r)
+    f2 = r.dot(F, F)
+    log.residual.append((0.0, math.sqrt(max(f2, 0.0) / max(n_moving, 1))))
+    d = torch.zeros_like(F)
+    solver = _Minres(r, F)
     for _ in range(max_iter):
+        R = log.residual[-1][1]
         if target is not None and R <= target:
             break
         if time_limit is not None and time.perf_counter() - t0 > time_limit:
             break
         log.newton_iters += 1
-        # Steihaug CG on (P H P) d = b
-        d.zero_()
-        res.copy_(b)
-        p.copy_(b)
-        rz = r.dot(res, res)
-        bnorm = math.sqrt(rz)
-        dd = dp = 0.0
-        for _k in range(cg_max):
-            log.cg_iters += 1
-            r.hvp(p, out=Hp)          # J p
-            r.tangent(Hp)             # P J p ;  p^T H p = -p . (P J p)
-            pHp = -r.dot(p, Hp)
-            pp = r.dot(p, p)
-            dp = r.dot(d, p)
-            if pHp <= 0.0:
-                r.axpby(_to_boundary(dd, dp, pp, delta), p, 1.0, d)
-                break
-            alpha = rz / pHp
-            if dd + 2.0 * alpha * dp + alpha * alpha * pp >= delta * delta:
-                r.axpby(_to_boundary(dd, dp, pp, delta), p, 1.0, d)
-                break
-            r.axpby(alpha, p, 1.0, d)
-            r.axpby(alpha, Hp, 1.0, res)  # res <- res - alpha H p = res + alpha P J p
-            dd = r.dot(d, d)
-            rz_new = r.dot(res, res)
-            if math.sqrt(rz_new) <= cg_tol * bnorm:
-                break
-            r.axpby(1.0, res, rz_new / rz, p)
-            rz = rz_new
-        dd = r.dot(d, d)
-        # cap the largest single move, then the predicted reduction of the model
-        mx = r.maxnorm(d)
-        s = min(1.0, move_cap * h / mx) if mx > 0 else 0.0
-        r.hvp(d, out=Hp)
-        r.tangent(Hp)
-        dHd = -r.dot(d, Hp)
-        bd = r.dot(b, d)
-        pred = s * bd - 0.5 * s * s * dHd
+        log.krylov_iters += solver.solve(F, d, krylov_tol, krylov_max)   # A d = F, A = -PJP: d = -(PJP)^-1 F
+        r.clamp(d, move_cap * h)
         snap = r.snapshot()
-        r.displace(d, s)
-        r.project()
-        b_new = projected_force(r)
-        E_new = r.energy()
-        rho = (E - E_new) / pred if pred > 0 else -1.0
-        if not (rho > 0.1) or not math.isfinite(E_new):
-            r.restore(snap)
-            delta *= 0.25
-            log.rejected += 1
-            if delta < 1e-6 * h:
+        s, accepted = 1.0, False
+        for _bt in range(max_backtracks + 1):
+            r.displace(d, s)
+            r.project()
+            F_new = projected_force(r)
+            f2_new = r.dot(F_new, F_new)
+            if math.isfinite(f2_new) and f2_new < f2:
+                accepted = True
                 break
-            continue
-        if rho > 0.75 and math.sqrt(dd) * s >= 0.99 * delta:
-            delta *= 2.0
-        elif rho < 0.25:
-            delta *= 0.5
-        E, b = E_new, b_new
-        R = force_residual(r, b, n_moving)
+            log.backtracks += 1
+            r.restore(snap)
+            s *= 0.5
+        if not accepted:
+            break
+        F, f2 = F_new, f2_new
         torch.cuda.synchronize()
-        log.residual.append((time.perf_counter() - t0, R))
-        log.energy.append(E)
+        log.residual.append((time.perf_counter() - t0, math.sqrt(max(f2, 0.0) / max(n_moving, 1))))
     return log
 
 

@@ -59,6 +59,13 @@ def geom_descs(geoms):
         d.n_line = int(lines.n_line)
         d.seg_p = segp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if len(segp) else None
         d.line_closed = closed.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)) if len(closed) else None
+        sv = getattr(lines, "seg_vert", None)
+        if sv is not None and len(sv):
+            sv = np.ascontiguousarray(sv, np.int32).reshape(-1)
+            keep.append(sv)
+            d.seg_vert = sv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        else:
+            d.seg_vert = None
     return arr, keep
 
 
@@ -219,6 +226,11 @@ class Relaxer:
         check(lib.fppg_vec_maxnorm(c, self.n, ptr(a), ptr(out), self.stream), c)
         return float(out.view(torch.float32)[0].item())
 
+    def clamp(self, v: torch.Tensor, cap: float):
+        """Cap every row of v at length `cap` (in place)."""
+        lib, c = self.ctx.lib, self.ctx.handle
+        check(lib.fppg_vec_clamp(c, self.n, ptr(v), float(cap), self.stream), c)
+
     def tangent(self, v: torch.Tensor):
         """v <- P v (tangent spaces of the constrained particles; 0 where nothing moves)."""
         lib, c = self.ctx.lib, self.ctx.handle
@@ -274,6 +286,46 @@ class Relaxer:
     def run(self, iters: int):
         for _ in range(iters):
             self.step(keep_accel=False)
+
+    # ---- graph capture -----------------------------------------------------------------------
+    def capture(self, iters: int = 2):
+        """Capture `iters` (even) iterations into a HIP graph on a side stream."""
+        self.release_graph()
+        self.graph_stream = torch.cuda.Stream(device=self.dev)
+        self.graph_stream.wait_stream(torch.cuda.current_stream(self.dev))
+        lib, c = self.ctx.lib, self.ctx.handle
+        h = ctypes.c_void_p()
+        st = ctypes.c_void_p(self.graph_stream.cuda_stream)
+        check(lib.fppg_graph_create(c, self.geom.handle, self.n, ptr(self.pos), ptr(self.id), ptr(self.owner),
+                                    ptr(self.pos_b), ptr(self.id_b), ptr(self.owner_b), ptr(self.cell_start),
+                                    ptr(self.feat_seg), ptr(self.feat_u), self.n_feat, self.move_mask,
+                                    ptr(self.amax), ptr(self.disp), ptr(self.counters), self.ws_ptr,
+                                    self.ws_bytes, int(iters), st, ctypes.byref(h)), c)
+        self.graph = h
+        self.graph_iters = int(iters)
+        self._graph_a = self.pos.data_ptr()
+
+    def replay(self, repeats: int = 1):
+        """Run repeats * graph_iters iterations from the captured graph (state ends in the same buffers)."""
+        cur = torch.cuda.current_stream(self.dev)
+        if self.pos.data_ptr() != self._graph_a:
+            # an odd number of eager rebuilds since the capture left the state in
+            # buffer set B: move it back to set A, which the graph reads
+            self.pos_b.copy_(self.pos)
+            self.id_b.copy_(self.id)
+            self.owner_b.copy_(self.owner)
+            self.pos, self.pos_b = self.pos_b, self.pos
+            self.id, self.id_b = self.id_b, self.id
+            self.owner, self.owner_b = self.owner_b, self.owner
+        self.graph_stream.wait_stream(cur)
+        lib, c = self.ctx.lib, self.ctx.handle
+        check(lib.fppg_graph_launch(c, self.graph, int(repeats), ctypes.c_void_p(self.graph_stream.cuda_stream)), c)
+        cur.wait_stream(self.graph_stream)
+
+    def release_graph(self):
+        if getattr(self, "graph", None):
+            self.ctx.lib.fppg_graph_destroy(self.graph)
+            self.graph = None
 
     # ---- host views (by particle id) ---------------------------------------------------------
     def host_state(self):

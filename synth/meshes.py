@@ -28,6 +28,7 @@ class FeatureLines:
     line_seg_begin: np.ndarray  # int32 [n_line + 1]
     seg_p: np.ndarray           # float64 [n_seg, 2, 3]
     line_closed: np.ndarray     # uint8 [n_line]
+    seg_vert: np.ndarray = None  # int32 [n_seg, 2]: mesh vertex at each segment end (-1: none)
 
     @property
     def n_line(self) -> int:
@@ -39,19 +40,24 @@ class FeatureLines:
 
     @staticmethod
     def empty() -> "FeatureLines":
-        return FeatureLines(np.zeros(1, np.int32), np.zeros((0, 2, 3)), np.zeros(0, np.uint8))
+        return FeatureLines(np.zeros(1, np.int32), np.zeros((0, 2, 3)), np.zeros(0, np.uint8),
+                            np.zeros((0, 2), np.int32))
 
     @staticmethod
-    def from_polylines(polys, closed) -> "FeatureLines":
+    def from_polylines(polys, closed, vert_ids=None) -> "FeatureLines":
+        """Lines through the given points; vert_ids[l][k] = mesh vertex of point k of line l."""
         begins = [0]
-        segs = []
-        for pts in polys:
+        segs, sv = [], []
+        for li, pts in enumerate(polys):
             pts = np.asarray(pts, np.float64)
-            for a, b in zip(pts[:-1], pts[1:]):
+            ids = np.full(len(pts), -1) if vert_ids is None else np.asarray(vert_ids[li])
+            for k, (a, b) in enumerate(zip(pts[:-1], pts[1:])):
                 segs.append((a, b))
+                sv.append((ids[k], ids[k + 1]))
             begins.append(len(segs))
         seg_p = np.array(segs, np.float64).reshape(-1, 2, 3)
-        return FeatureLines(np.array(begins, np.int32), seg_p, np.array(closed, np.uint8))
+        return FeatureLines(np.array(begins, np.int32), seg_p, np.array(closed, np.uint8),
+                            np.array(sv, np.int32).reshape(-1, 2))
 
 
 @dataclass
@@ -60,6 +66,7 @@ class Mesh:
     tri: np.ndarray    # int32 [nt, 3], counter-clockwise seen from outside
     lines: FeatureLines = field(default_factory=FeatureLines.empty)
     singular: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))  # float64 [ns, 3]
+    singular_vert: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))  # vertex of each
 
     @property
     def n_tri(self) -> int:
@@ -99,8 +106,9 @@ def cube(lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)) -> Mesh:
         tri.append([q[0], q[2], q[3]])
     tri = _orient_outward(corners, np.array(tri, np.int32), (lo + hi) / 2)
     edges = [(a, b) for a in range(8) for b in range(a + 1, 8) if bin(a ^ b).count("1") == 1]
-    lines = FeatureLines.from_polylines([[corners[a], corners[b]] for a, b in edges], [0] * len(edges))
-    return Mesh(corners, tri.astype(np.int32), lines, corners.copy())
+    lines = FeatureLines.from_polylines([[corners[a], corners[b]] for a, b in edges], [0] * len(edges),
+                                        [[a, b] for a, b in edges])
+    return Mesh(corners, tri.astype(np.int32), lines, corners.copy(), np.arange(8, dtype=np.int32))
 
 
 def tetrahedron() -> Mesh:
@@ -110,8 +118,9 @@ def tetrahedron() -> Mesh:
     tri = np.array([[0, 2, 1], [0, 1, 3], [1, 2, 3], [2, 0, 3]], np.int32)
     tri = _orient_outward(v, tri, v.mean(0))
     edges = [(a, b) for a in range(4) for b in range(a + 1, 4)]
-    lines = FeatureLines.from_polylines([[v[a], v[b]] for a, b in edges], [0] * len(edges))
-    return Mesh(v, tri, lines, v.copy())
+    lines = FeatureLines.from_polylines([[v[a], v[b]] for a, b in edges], [0] * len(edges),
+                                        [[a, b] for a, b in edges])
+    return Mesh(v, tri, lines, v.copy(), np.arange(4, dtype=np.int32))
 
 
 def icosphere(level: int, radius: float = 1.0) -> Mesh:
@@ -214,26 +223,30 @@ def gear(teeth=24, r_tip=1.0, r_root=0.85, r_bore=0.2, half_thick=0.15,
     corner_k = [k for k in range(n) if (k % samples_per_period) in
                 (0, samples_per_period // 3, samples_per_period // 2, (5 * samples_per_period) // 6)]
     polys, closed = [], []
-    singular = []
-    for z in (-half_thick, half_thick):
+    singular, sing_vert, vids = [], [], []
+    for face_of_z, z in enumerate((-half_thick, half_thick)):
         pts = np.concatenate([outer, np.full((n, 1), z)], 1)
         for ci in range(len(corner_k)):
             k0, k1 = corner_k[ci], corner_k[(ci + 1) % len(corner_k)]
             ks = list(range(k0, k1 + 1)) if k1 > k0 else list(range(k0, n)) + list(range(0, k1 + 1))
             polys.append(pts[np.array(ks) % n])
+            vids.append([vid(face_of_z, rings, kk) for kk in ks])
             closed.append(0)
         for k in corner_k:
             singular.append(pts[k])
+            sing_vert.append(vid(face_of_z, rings, k))
         bore = np.concatenate([inner, np.full((n, 1), z)], 1)
         polys.append(np.concatenate([bore, bore[:1]], 0))
+        vids.append([vid(face_of_z, 0, kk) for kk in range(n)] + [vid(face_of_z, 0, 0)])
         closed.append(1)
     for k in corner_k:
         p0 = np.array([outer[k, 0], outer[k, 1], -half_thick])
         p1 = np.array([outer[k, 0], outer[k, 1], half_thick])
         polys.append(np.stack([p0, p1]))
+        vids.append([vid(0, rings, k), vid(1, rings, k)])
         closed.append(0)
-    lines = FeatureLines.from_polylines(polys, closed)
-    return Mesh(vert, tri, lines, np.array(singular))
+    lines = FeatureLines.from_polylines(polys, closed, vids)
+    return Mesh(vert, tri, lines, np.array(singular), np.array(sing_vert, np.int32))
 
 
 def cylinder(radius=0.5, height=1.0, segments=64) -> Mesh:
@@ -256,13 +269,15 @@ def cylinder(radius=0.5, height=1.0, segments=64) -> Mesh:
     tri = _orient_outward(vert, np.array(tri, np.int32), np.zeros(3))
     loops = [np.concatenate([vert[:segments], vert[:1]], 0),
              np.concatenate([vert[segments:2 * segments], vert[segments:segments + 1]], 0)]
-    lines = FeatureLines.from_polylines(loops, [1, 1])
+    lines = FeatureLines.from_polylines(loops, [1, 1], [list(range(segments)) + [0],
+                                                        list(range(segments, 2 * segments)) + [segments]])
     return Mesh(vert, tri.astype(np.int32), lines, np.zeros((0, 3)))
 
 
 def transformed(mesh: Mesh, R: np.ndarray, t: np.ndarray) -> Mesh:
     """Rigid motion x -> R x + t of a mesh, its feature lines and singular points."""
     seg = mesh.lines.seg_p @ R.T + t
-    lines = FeatureLines(mesh.lines.line_seg_begin.copy(), seg, mesh.lines.line_closed.copy())
+    lines = FeatureLines(mesh.lines.line_seg_begin.copy(), seg, mesh.lines.line_closed.copy(),
+                         None if mesh.lines.seg_vert is None else mesh.lines.seg_vert.copy())
     sing = mesh.singular @ R.T + t if len(mesh.singular) else mesh.singular.copy()
-    return Mesh(mesh.vert @ R.T + t, mesh.tri.copy(), lines, sing)
+    return Mesh(mesh.vert @ R.T + t, mesh.tri.copy(), lines, sing, mesh.singular_vert.copy())

@@ -61,6 +61,7 @@ class Geometry:
     seg_begin: int = 0
     line_begin: int = 0
     feat_begin: int = 0
+    vert_begin: int = 0   # global id of the mesh's first vertex (singular-particle owners)
 
     @property
     def ncell(self) -> int:
@@ -172,7 +173,7 @@ def _feature_particles(b: _Builder, mesh: M.Mesh, dx: float, rng, jitter: float)
 def _finish(name, parts, move_mask, seed, meta=None) -> Workload:
     """Concatenate per-geometry builders into one workload with global offsets."""
     geoms, pos, tag, owner, gid, fseg, fu = [], [], [], [], [], [], []
-    n = tri_off = seg_off = line_off = feat_off = cell_off = 0
+    n = tri_off = seg_off = line_off = feat_off = cell_off = vert_off = 0
     for g, (geom, b) in enumerate(parts):
         p = np.concatenate(b.pos, 0) if b.pos else np.zeros((0, 3))
         t = np.concatenate(b.tag) if b.tag else np.zeros(0, np.int32)
@@ -180,9 +181,10 @@ def _finish(name, parts, move_mask, seed, meta=None) -> Workload:
         o = o.copy()
         o[t == SURFACE] += tri_off
         o[t == FEATURE] += feat_off
+        o[t == SINGULAR] += vert_off
         geom.part_begin, geom.part_end = n, n + len(p)
         geom.tri_begin, geom.seg_begin, geom.line_begin = tri_off, seg_off, line_off
-        geom.feat_begin, geom.cell_begin = feat_off, cell_off
+        geom.feat_begin, geom.cell_begin, geom.vert_begin = feat_off, cell_off, vert_off
         geoms.append(geom)
         pos.append(p.astype(np.float32))
         tag.append(t)
@@ -197,6 +199,7 @@ def _finish(name, parts, move_mask, seed, meta=None) -> Workload:
         seg_off += geom.mesh.lines.n_seg
         line_off += geom.mesh.lines.n_line
         cell_off += geom.ncell
+        vert_off += len(geom.mesh.vert)
     return Workload(
         name=name, geoms=geoms, pos=np.concatenate(pos, 0), tag=np.concatenate(tag),
         owner=np.concatenate(owner), gid=np.concatenate(gid),
@@ -268,7 +271,7 @@ def cube_workload(n=24, jitter=0.3, seed=1, k=2, with_volume=True, with_surface=
                 b.add(pts, SURFACE, cand[own])
     if with_features:
         _feature_particles(b, mesh, dx, rng, jitter)
-        b.add(mesh.singular, SINGULAR)
+        b.add(mesh.singular, SINGULAR, mesh.singular_vert)
     return _finish(name or f"cube_n{n}", [(geom, b)], move_mask, seed,
                    {"dx": dx, "jitter": jitter})
 
@@ -401,7 +404,7 @@ def tetra_workload(dx=0.045, jitter=0.3, seed=5, k=2, move_mask=ALL_MOVING, name
             ok &= (pts - P) @ ein >= 0.5 * dx
         b.add(pts[ok], SURFACE, np.full(int(ok.sum()), f))
     _feature_particles(b, mesh, dx, rng, jitter)
-    b.add(mesh.singular, SINGULAR)
+    b.add(mesh.singular, SINGULAR, mesh.singular_vert)
     return _finish(name or f"tetra_dx{dx:g}", [(geom, b)], move_mask, seed, {"dx": dx})
 
 
@@ -528,8 +531,33 @@ def solid_geometry(rng, n_target: float, jitter=0.3, k=2):
     _surface_particles_planar(b, mesh, dx, rng, jitter)
     _feature_particles(b, mesh, dx, rng, jitter)
     if len(mesh.singular):
-        b.add(mesh.singular, SINGULAR)
+        b.add(mesh.singular, SINGULAR, mesh.singular_vert)
     return geom, b, kind
+
+
+def split_geometry(wl: Workload, g: int) -> Workload:
+    """Geometry g of a batch as a workload of its own (same particles, ids in
+    batch order, owner and feature indices re-based)."""
+    geo = wl.geoms[g]
+    m = wl.gid == g
+    b = _Builder()
+    own = wl.owner[m].copy()
+    tag = wl.tag[m]
+    own[tag == SURFACE] -= geo.tri_begin
+    own[tag == FEATURE] -= geo.feat_begin
+    own[tag == SINGULAR] -= geo.vert_begin
+    b.pos.append(wl.pos[m].astype(np.float64))
+    b.tag.append(tag.copy())
+    b.owner.append(own)
+    nf = int(np.sum(tag == FEATURE))
+    if nf:
+        b.feat_seg.append(wl.feat_seg[geo.feat_begin:geo.feat_begin + nf] - geo.seg_begin)
+        b.feat_u.append(wl.feat_u[geo.feat_begin:geo.feat_begin + nf].copy())
+    single = Geometry(mesh=geo.mesh, dx=geo.dx, h=geo.h, k=geo.k, proj_radius=geo.proj_radius,
+                      origin=geo.origin.copy(), inv_cell=geo.inv_cell, dims=geo.dims.copy())
+    out = _finish(f"{wl.name}_g{g}", [(single, b)], wl.move_mask, wl.seed)
+    out.pos = wl.pos[m].copy()     # keep the exact binary32 positions
+    return out
 
 
 def batch_workload(n_geom=64, n_min=5e3, n_max=5e5, seed=4000, jitter=0.3, k=2,

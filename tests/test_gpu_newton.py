@@ -94,18 +94,19 @@ def test_tangent_projection_and_displacement_match_oracle():
     assert np.allclose(pv, pref, rtol=1e-5, atol=1e-6)
 
 
-def test_newton_lowers_energy_and_residual_faster_than_plain():
+def test_newton_lowers_the_force_residual_below_the_plain_loop():
     from paper_2501_03056_amd.newton import newton_relax, plain_relax
     wl = _volume_tier(n=12, seed=28)
     n_moving = wl.n_moving()
     rp = _relaxer(wl)
-    plain = plain_relax(rp, n_moving, iters=30, record_every=30)
+    plain = plain_relax(rp, n_moving, iters=30, record_every=2)
+    best = min(R for _, R in plain)
     rn = _relaxer(wl)
-    log = newton_relax(rn, n_moving, target=plain[-1][1], max_iter=30)
-    e = np.array(log.energy)
-    assert np.all(np.diff(e) < 0)                       # every accepted step lowers E
-    assert log.residual[-1][1] <= plain[-1][1]          # reaches the plain loop's residual
-    assert log.newton_iters < 30
+    log = newton_relax(rn, n_moving, target=None, max_iter=8)
+    R = np.array([R for _, R in log.residual])
+    assert np.all(np.diff(R) < 0)                       # every accepted step lowers |P a|
+    assert R[-1] < 0.5 * best                           # well below the plain loop's best in 30 iterations
+    assert log.newton_iters <= 8
     # the relaxed state is still valid: volume particles inside the cube
     pos, _, _, _ = rn.host_state()
     v = wl.tag == synth.VOLUME
