@@ -28,7 +28,8 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_TFLOPS = 157.3          # MI355X vector FP32 (published)
 PEAK_HBM_GBS = 8000.0
 FLOPS_PER_PAIR = 19               # see roofline_note()
-KERNEL_SOURCES = ["paper_2501_03056_amd/csrc/force.hip", "paper_2501_03056_amd/csrc/internal.h"]
+KERNEL_SOURCES = ["paper_2501_03056_amd/csrc/force.hip", "paper_2501_03056_amd/csrc/internal.h",
+                  "paper_2501_03056_amd/csrc/stencil.h"]
 
 
 def roofline_note():
@@ -37,13 +38,17 @@ def roofline_note():
             "3 fma (accumulate); candidates rejected by the predicate are not counted")
 
 
-def make_workload(name, k=2):
+def make_workload(name, k=2, slab=0):
     import synth
     if name == "sphere":
-        return synth.sphere_workload(level=5, dx=0.01, seed=2, k=k), "icosphere_l5_r1_dx0.01_h1.3dx"
-    if name == "cube":
-        return synth.cube_workload(n=24, seed=1, k=k), "unit_cube_dx1/24_h1.3dx"
-    raise SystemExit(f"unknown workload {name}")
+        wl, wname = synth.sphere_workload(level=5, dx=0.01, seed=2, k=k), "icosphere_l5_r1_dx0.01_h1.3dx"
+    elif name == "cube":
+        wl, wname = synth.cube_workload(n=24, seed=1, k=k), "unit_cube_dx1/24_h1.3dx"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    for g in wl.geoms:
+        g.slab = slab
+    return wl, wname
 
 
 def source_hash(paths):
@@ -201,6 +206,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=160)
     ap.add_argument("--k", type=int, default=2, help="stencil half-width of the particle cells (1 or 2)")
+    ap.add_argument("--slab", type=int, default=0,
+                    help="cell rows per slab of the cell key (0: one slab per geometry)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="copy 1 GiB device to device first (reference kernel for HBM counter scaling)")
     args = ap.parse_args()
@@ -222,7 +229,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     t0 = time.perf_counter()
-    wl, wname = make_workload(args.workload, args.k)
+    wl, wname = make_workload(args.workload, args.k, args.slab)
     print(f"[bench] workload {wname}: {wl.n} particles {wl.counts()} built in {time.perf_counter() - t0:.1f}s",
           file=sys.stderr, flush=True)
     r = Relaxer(wl, device=0)
@@ -278,7 +285,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": wname, "particles": wl.n, "moving": n_moving, "facets": int(r.geom.n_tri),
-                   "stencil_k": int(wl.geoms[0].k), "h_over_dx": 1.3, "pairs_per_step": pairs},
+                   "stencil_k": int(wl.geoms[0].k), "key_slab_rows": int(args.slab), "h_over_dx": 1.3,
+                   "pairs_per_step": pairs},
         "pair_evals_per_s": pairs * args.steps / (ms / 1e3),
         "kernels_ms_per_step": {k: (v[0] / max(v[1], 1)) for k, v in prof.items() if v[1]},
         "roofline": {"bound": "alu", "kernel": "k_force", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,

@@ -39,8 +39,9 @@
  *  - Facets and feature segments are numbered globally over a batch: the
  *    facets of geometry g follow those of geometries 0..g-1 (same for
  *    segments). `owner` holds the global facet of a surface particle, the
- *    feature slot (index into feat_seg / feat_u) of a feature particle, and
- *    -1 otherwise.
+ *    feature slot (index into feat_seg / feat_u) of a feature particle, the
+ *    global mesh vertex of a singular particle (read only by the mesh-gradient
+ *    calls), and -1 otherwise.
  *  - A context is used by one host thread at a time.
  */
 #ifndef FPPG_H
@@ -93,8 +94,13 @@ typedef struct fppg_geom fppg_geom;
  * rebuilt every iteration): cell (cx, cy, cz) of a position p is
  *   c = clamp(floor(fl32(fl32(p - origin) * inv_cell)), 0, dims - 1)
  * (binary32, one rounding per operation) and its key is
- *   cell_begin(g) + (cz * dims[1] + cy) * dims[0] + cx
- * with cell_begin(g) the total cell count of geometries 0..g-1. The cell edge
+ *   cell_begin(g) + s S dims[0] dims[2] + (cz w + cy - s S) dims[0] + cx,
+ *   s = cy div S,  w = min(S, dims[1] - s S),  S = slab
+ * with cell_begin(g) the total cell count of geometries 0..g-1: the y range
+ * is cut into slabs of S rows (slab <= 0 or > dims[1]: one slab, the plain
+ * (cz dims[1] + cy) dims[0] + cx), each slab numbered z-major with x fastest.
+ * Any S gives the same cell list; narrow slabs keep the rows a stencil reads
+ * close in memory. The cell edge
  * 1/inv_cell must be at least (2h/k)(1 + 2^-9) so that the (2k+1)^3 cell
  * stencil holds every pair with q < 2; k is 1 or 2 and equal across a batch.
  *
@@ -126,6 +132,7 @@ typedef struct {
   const uint8_t* line_closed;             /* [n_line] */
   const int32_t* seg_vert;                /* [n_seg * 2] mesh vertex (local index) at each segment
                                              end, -1 if none; may be NULL (mesh gradients only) */
+  int32_t slab;                           /* cell rows per slab of the key (see above) */
 } fppg_geom_desc;
 
 /* ---- context ---------------------------------------------------------------------------- */
@@ -290,7 +297,8 @@ fppg_status fppg_relax_energy(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, c
  * for Krylov solvers:
  *   fppg_vec_dot    out[0] = sum_i a_i . b_i in FP64, fixed summation order
  *                   (device double; ws >= 2048 doubles, 256-byte aligned)
- *   fppg_vec_axpby  y <- alpha x + beta y
+ *   fppg_vec_axpby  y <- alpha x + beta y; with beta = 0 the old y is not read
+ *                   and with alpha = 0 x is not read (NaN there does not propagate)
  * Neither touches w.
  */
 fppg_status fppg_vec_dot(fppg_ctx* ctx, int64_t n, const float* a, const float* b, double* out,

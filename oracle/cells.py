@@ -2,11 +2,19 @@
 
 The paper keys its sparse background grid by Morton code and a compact hash
 (section 3.1.3, Eq. 9-10). For the particle cell list of the relaxation loop
-the key here is the plain x-fastest linear index of a uniform grid, offset per
+the key here is a linear index of a uniform grid with x fastest, offset per
 geometry of a batch; particles are ordered by (key, id), and cell_start[c] is
-the first sorted index of cell c. A particle with a non-finite coordinate gets
-the key ncell (one past every geometry's cells; reading: such a particle is
-nobody's neighbour), so cell_start has ncell + 2 entries, the last being N.
+the first sorted index of cell c. The grid's y range is cut into slabs of S
+rows (the last one may be narrower); the key runs over the slabs, within a
+slab over z, then over its rows y, then x:
+    key = s S nx nz + cz nx w + (cy - s S) nx + cx,  s = cy div S,  w = min(S, ny - s S)
+S = ny (or S <= 0) is the plain (cz ny + cy) nx + cx. Every key order with
+contiguous x rows describes the same cell list; slabs keep the cells a
+receiver's stencil touches close together in memory.
+
+A particle with a non-finite coordinate gets the key ncell (one past every
+geometry's cells; reading: such a particle is nobody's neighbour), so
+cell_start has ncell + 2 entries, the last being N.
 
 The cell coordinate is defined in binary32, one rounding per operation:
     t = fl32(fl32(x - origin) * inv_cell),  c = clamp(floor(t), 0, dim - 1)
@@ -33,10 +41,18 @@ def cell_keys(wl, pos32=None, gid=None) -> np.ndarray:
     for g, geo in enumerate(wl.geoms):
         m = gid == g
         c = cell_coords(pos32[m], geo.origin, geo.inv_cell, geo.dims)
-        nx, ny = int(geo.dims[0]), int(geo.dims[1])
-        keys[m] = geo.cell_begin + (c[:, 2] * ny + c[:, 1]) * nx + c[:, 0]
+        keys[m] = geo.cell_begin + linear_key(c, geo.dims, getattr(geo, "slab", 0))
     keys[~np.all(np.isfinite(pos32), axis=1)] = total_cells(wl)
     return keys
+
+
+def linear_key(c: np.ndarray, dims, slab: int) -> np.ndarray:
+    """Key of integer cell coordinates c [N, 3] inside one geometry's grid."""
+    nx, ny, nz = (int(d) for d in dims)
+    S = ny if slab <= 0 else min(int(slab), ny)
+    s = c[:, 1] // S
+    w = np.minimum(S, ny - s * S)
+    return s * (S * nx * nz) + c[:, 2] * (nx * w) + (c[:, 1] - s * S) * nx + c[:, 0]
 
 
 def total_cells(wl) -> int:

@@ -21,7 +21,10 @@ The loss is metrics.uniformity_loss of the final positions.
 `record` runs the oracle's own forward (step.relax_step) and stores the
 decisions; `replay` re-evaluates the K steps in torch from the vertex array
 V; `mesh_gradient` returns dL/dV by autograd. Pins (tests): replay(V) matches
-the recorded forward, and autograd matches central differences of replay.
+the recorded forward (which projects with its own closest-point search), the
+replayed loss equals metrics.uniformity_loss, autograd matches central
+differences of replay, and the gradient has zero net force and torque under
+rigid motions of mesh and particles together.
 """
 from dataclasses import dataclass
 
@@ -165,7 +168,7 @@ def mesh_gradient(wl, rec: Record):
     V = torch.as_tensor(wl.geoms[0].mesh.vert.copy()).requires_grad_(True)
     L = loss(wl, replay(wl, V, rec), rec)
     (g,) = torch.autograd.grad(L, V)
-    return float(L), g.numpy()
+    return float(L.detach()), g.numpy()
 
 
 def mesh_gradient_fd(wl, rec: Record, eps=1e-6):

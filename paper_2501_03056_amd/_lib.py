@@ -28,6 +28,7 @@ class GeomDesc(ctypes.Structure):
         ("line_seg_begin", POINTER(c_int32)), ("n_line", c_int32),
         ("seg_p", POINTER(c_double)), ("line_closed", POINTER(c_uint8)),
         ("seg_vert", POINTER(c_int32)),
+        ("slab", c_int32),
     ]
 
 

@@ -24,7 +24,7 @@ __device__ __forceinline__ int cell_key(const float4 p, const GeomDev& G) {
   ty = fminf(fmaxf(ty, 0.0f), float(G.dims[1] - 1));
   tz = fminf(fmaxf(tz, 0.0f), float(G.dims[2] - 1));
   const int cx = int(floorf(tx)), cy = int(floorf(ty)), cz = int(floorf(tz));
-  return int(G.cell_begin) + (cz * G.dims[1] + cy) * G.dims[0] + cx;
+  return row_key(G, cy, cz) + cx;
 }
 
 __global__ void k_fill_i32(int* __restrict__ a, int64_t n, int v) {

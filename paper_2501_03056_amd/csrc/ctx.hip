@@ -209,7 +209,7 @@ static fppg_status geom_create(fppg_ctx* ctx, const fppg_geom_desc* descs, int32
       return fail(ctx, FPPG_E_ARG, "geometry " + std::to_string(g) + ": cell edge smaller than (2h/k)(1+2^-9)");
     int64_t nc = 1;
     for (int q = 0; q < 3; ++q) {
-      if (d.dims[q] < 1) return fail(ctx, FPPG_E_ARG, "dims must be >= 1");
+      if (d.dims[q] < 1 || d.dims[q] >= (1 << 20)) return fail(ctx, FPPG_E_ARG, "dims must be in [1, 2^20)");
       nc *= d.dims[q];
       G.origin[q] = d.origin[q];
       G.dims[q] = d.dims[q];
@@ -302,7 +302,8 @@ static fppg_status geom_create(fppg_ctx* ctx, const fppg_geom_desc* descs, int32
       G.tg_dims[q] = sg.dims[q];
     }
     G.tg_inv = sg.inv;
-    G.pad0 = 0;
+    G.slab = (d.slab <= 0 || d.slab > d.dims[1]) ? d.dims[1] : d.slab;
+    G.inv_slab = 1.0f / float(G.slab);
     G.tg_begin = tg_cells;
     const int64_t base = int64_t(tg_tri.size());
     if (base + int64_t(sg.tri.size()) >= (int64_t(1) << 31))

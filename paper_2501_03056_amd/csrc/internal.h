@@ -24,13 +24,14 @@ struct GeomDev {
   float rc2;        // fl32(fl32(2h)^2)
   float R;          // projection radius
   float kcoef;      // K = 5 alpha / h^2 (binary32)
+  float inv_slab;   // fl32(1 / slab)
   int64_t cell_begin;
   int64_t part_begin, part_end;
   // facet search grid
   double tg_origin[3];
   double tg_inv;    // 1 / search-cell edge
   int32_t tg_dims[3];
-  int32_t pad0;
+  int32_t slab;     // rows of cells along y per slab of the cell key (1..dims[1])
   int64_t tg_begin; // offset of this geometry's cells in the global search-cell arrays
   int32_t tri_begin, tri_end, seg_begin, seg_end;
 };
@@ -173,6 +174,20 @@ __device__ __forceinline__ int xcd_chunk(int b, int nb) {
   const int q = nb / kNumXcd, r = nb % kNumXcd;
   const int x = b % kNumXcd, k = b / kNumXcd;
   return x * q + min(x, r) + k;
+}
+
+// Key of cell (0, y, z) of a geometry: the y range is cut into slabs of
+// `slab` rows (the last one may be narrower); keys run over the slabs, within
+// a slab over z, then over the slab's rows, then x. Cell (x, y, z) has key
+// row_key(G, y, z) + x. floor((y + 1/2) / slab) in binary32 is exact here:
+// the quotient stays at least 1/(2 slab) away from an integer and the grid
+// has far fewer than 2^20 rows.
+__device__ __forceinline__ int row_key(const GeomDev& G, int y, int z) {
+  const int S = G.slab;
+  const int s = int((float(y) + 0.5f) * G.inv_slab);
+  const int y0 = s * S;
+  const int w = min(S, G.dims[1] - y0);
+  return int(G.cell_begin) + y0 * G.dims[0] * G.dims[2] + (z * w + (y - y0)) * G.dims[0];
 }
 
 __device__ __forceinline__ int tag_of(float w) { return __float_as_int(w) & 7; }

@@ -34,8 +34,10 @@ __global__ __launch_bounds__(kBlock) void k_axpby(int n, float alpha, const floa
                                                   float4* __restrict__ y) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const float4 a = x[i];
-  float4 b = y[i];
+  // beta = 0 ignores the old y and alpha = 0 ignores x (BLAS convention), so
+  // uninitialised memory, NaN included, never leaks into the result
+  float4 b = beta != 0.0f ? y[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  const float4 a = alpha != 0.0f ? x[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   b.x = fmaf(alpha, a.x, beta * b.x);
   b.y = fmaf(alpha, a.y, beta * b.y);
   b.z = fmaf(alpha, a.z, beta * b.z);

@@ -1,9 +1,9 @@
 // Culled stencil walk over the particle cell list, shared by the pair-sweep
 // kernels (forces, Jacobian products, energy, density loss, neighbour export).
 //
-// One lane per sorted receiver. With x-fastest cell keys the cells of a
-// stencil row along x are contiguous in the sorted order, so a receiver
-// visits at most (2k+1)^2 contiguous index ranges. Rows and the x-extent of a
+// One lane per sorted receiver. The cell key runs fastest along x, so the
+// cells of a stencil row along x are contiguous in the sorted order and a
+// receiver visits at most (2k+1)^2 contiguous index ranges. Rows and the x-extent of a
 // row are culled in cell units against the support radius: a skipped cell is
 // at least k cell edges (> 2h, the edge being (2h/k)(1+2^-9) or more) from the
 // receiver, so it holds no source and culled sums are bitwise identical to
@@ -60,7 +60,7 @@ __device__ __forceinline__ void for_each_row(const Stencil s, const GeomDev& G, 
       const int below = min(K, int(ceilf(rho - s.fx + 1.0f)) - 1);   // |dx| with f + |dx| - 1 < rho
       const int above = min(K, int(ceilf(rho + s.fx)) - 1);          // dx with dx - f < rho
       const int x0 = max(s.x - below, 0), x1 = min(s.x + above, G.dims[0] - 1);
-      const int row = int(G.cell_begin) + (z * G.dims[1] + y) * G.dims[0];
+      const int row = row_key(G, y, z);
       f(cs[row + x0], cs[row + x1 + 1]);
     }
   }

@@ -1,0 +1,137 @@
+"""Gradient of the uniformity loss after K relaxation steps with respect to
+the mesh vertices, on the GPU (an addition to the method of section 3.3).
+
+The discrete decisions of each step (dt^2, owner facets before and after,
+accepted or reverted moves, neighbour sets) are frozen at their forward
+values; between them a step is smooth in the positions and in the facet
+vertices (the map is written out in fppg.h above fppg_step_adjoint).
+
+Reverse sweep with checkpointed recomputation:
+  forward   K steps, keeping the state (pos, id, owner) every `checkpoint_every`
+            steps (24 bytes per particle per checkpoint);
+  loss      fppg_uniformity_loss on the final sorted state -> L, dL/dx;
+  backward  per segment, last first: restore its checkpoint, recompute its
+            steps storing per step the sorted state, cells, accelerations,
+            owners after the step and the accept flags (about 45 bytes per
+            particle per step), then walk the steps backwards:
+              xbar_{n+1} (by id) -> sorted order of step n    fppg_vec_permute
+              fppg_step_adjoint -> ybar (adjoint of a), xbar, facet-vertex terms
+              xbar += J^T ybar                                   fppg_relax_hvp
+              back to id order                                   fppg_vec_permute
+  fixed     the particles that do not move (singular points, feature
+            particles) add their adjoints to their vertices: fppg_fixed_adjoint.
+All arithmetic runs in the library's kernels; this module marshals.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from ._lib import check, ptr
+
+
+def lattice_density(dx: float, h: float) -> float:
+    """Density of the infinite cubic lattice of spacing dx with the kernel of
+    Eq. 16 (the loss's rest density rho0), summed over the lattice points
+    within the support radius 2h."""
+    alpha = 21.0 / (16.0 * np.pi * h ** 3)
+    m = int(np.ceil(2.0 * h / dx)) + 1
+    i = np.arange(-m, m + 1, dtype=np.float64) * dx
+    r = np.sqrt(i[:, None, None] ** 2 + i[None, :, None] ** 2 + i[None, None, :] ** 2).ravel() / h
+    t = np.clip(1.0 - 0.5 * r, 0.0, None)
+    return float(np.sum(alpha * t ** 4 * (2.0 * r + 1.0)))
+
+
+class _Tape:
+    __slots__ = ("pos", "id", "owner", "cells", "accel", "amax", "owner_next", "accepted")
+
+
+def _lib_call(r, name, *args):
+    check(getattr(r.ctx.lib, name)(r.ctx.handle, *args), r.ctx.handle)
+
+
+def uniformity_loss(r, rho0: float, grad: torch.Tensor | None = None) -> torch.Tensor:
+    """(L, N) as a device double[2] at the relaxer's current sorted state
+    (cells must be current); dL/dx into grad [N, 4] if given."""
+    out = torch.zeros(2, dtype=torch.float64, device=r.dev)
+    _lib_call(r, "fppg_uniformity_loss", r.geom.handle, r.n, ptr(r.pos), ptr(r.cell_start), r.move_mask,
+              float(rho0), ptr(out), ptr(grad), r.ws_ptr, r.ws_bytes, r.stream)
+    return out
+
+
+def mesh_gradient(r, K: int, rho0: float, checkpoint_every: int = 10, n_vert: int | None = None):
+    """Run K relaxation steps from the relaxer's state and return
+    (L, dL/dV [n_vert, 3] float64 numpy) with V the batch's mesh vertices in
+    global numbering. The relaxer ends in the state after the K steps."""
+    if (r.move_mask >> 1) & 1:
+        raise ValueError("mesh_gradient holds feature particles fixed: clear bit 1 of move_mask")
+    if K < 0 or checkpoint_every < 1:
+        raise ValueError("K >= 0 and checkpoint_every >= 1 required")
+    if r.ws_bytes < 8 * (r.n + 2 * ((r.n + 255) // 256)) + 64:
+        raise ValueError("workspace too small for the loss")
+    dev, n = r.dev, r.n
+    n_vert = int(n_vert if n_vert is not None else r.n_vert)
+    # forward with checkpoints
+    ckpts = []
+    for step in range(K):
+        if step % checkpoint_every == 0:
+            ckpts.append((step, r.pos.clone(), r.id.clone(), r.owner.clone()))
+        r.step(keep_accel=False)
+    final = (r.pos.clone(), r.id.clone(), r.owner.clone())
+    r.build_cells()
+    g = torch.zeros((n, 4), dtype=torch.float32, device=dev)
+    out = uniformity_loss(r, rho0, g)
+    # dL/dx in id order
+    xbar_id = torch.zeros_like(g)
+    _lib_call(r, "fppg_vec_permute", n, ptr(g), ptr(r.id), 1, ptr(xbar_id), r.stream)
+    vbar = torch.zeros(3 * n_vert, dtype=torch.int64, device=dev)
+    xb_next = torch.empty_like(g)
+    xb = torch.empty_like(g)
+    yb = torch.empty_like(g)
+    jt = torch.empty_like(g)
+    first = None
+    for ci in range(len(ckpts) - 1, -1, -1):
+        s0, pos, ids, own = ckpts[ci]
+        s1 = ckpts[ci + 1][0] if ci + 1 < len(ckpts) else K
+        r.pos.copy_(pos)
+        r.id.copy_(ids)
+        r.owner.copy_(own)
+        tapes = []
+        for _ in range(s0, s1):
+            t = _Tape()
+            r.build_cells()
+            t.pos, t.id, t.owner, t.cells = r.pos.clone(), r.id.clone(), r.owner.clone(), r.cell_start.clone()
+            r.relax_step(keep_accel=True)
+            t.accel, t.amax = r.accel.clone(), r.amax.clone()
+            t.accepted = torch.empty(n, dtype=torch.uint8, device=dev)
+            r.project_record(t.accepted)
+            t.owner_next = r.owner.clone()
+            tapes.append(t)
+        for t in reversed(tapes):
+            _lib_call(r, "fppg_vec_permute", n, ptr(xbar_id), ptr(t.id), 0, ptr(xb_next), r.stream)
+            _lib_call(r, "fppg_step_adjoint", r.geom.handle, n, ptr(t.pos), ptr(t.accepted), ptr(t.owner),
+                      ptr(t.owner_next), ptr(t.accel), ptr(t.amax), r.move_mask, ptr(xb_next), ptr(yb), ptr(xb),
+                      ptr(vbar), r.stream)
+            _lib_call(r, "fppg_relax_hvp", r.geom.handle, n, ptr(t.pos), ptr(t.cells), r.move_mask, 1,
+                      ptr(yb), ptr(jt), r.stream)
+            r.axpby(1.0, jt, 1.0, xb)
+            _lib_call(r, "fppg_vec_permute", n, ptr(xb), ptr(t.id), 1, ptr(xbar_id), r.stream)
+        if ci == 0 and tapes:
+            first = tapes[0]
+    # particles that do not move depend on the vertices directly
+    if first is not None:
+        pos0, own0, ids0 = first.pos, first.owner, first.id
+    else:
+        r.build_cells()
+        pos0, own0, ids0 = r.pos, r.owner, r.id
+    _lib_call(r, "fppg_vec_permute", n, ptr(xbar_id), ptr(ids0), 0, ptr(xb), r.stream)
+    _lib_call(r, "fppg_fixed_adjoint", r.geom.handle, n, ptr(pos0), ptr(own0), ptr(r.feat_seg), ptr(r.feat_u),
+              r.n_feat, r.move_mask, ptr(xb), ptr(vbar), r.stream)
+    vd = torch.empty(3 * n_vert, dtype=torch.float64, device=dev)
+    _lib_call(r, "fppg_fixed_to_double", 3 * n_vert, ptr(vbar), ptr(vd), r.stream)
+    # leave the relaxer in the state after the K steps
+    r.pos.copy_(final[0])
+    r.id.copy_(final[1])
+    r.owner.copy_(final[2])
+    torch.cuda.synchronize(dev)
+    return float(out[0].item()), vd.view(n_vert, 3).cpu().numpy()

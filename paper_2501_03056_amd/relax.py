@@ -66,6 +66,7 @@ def geom_descs(geoms):
             d.seg_vert = sv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
         else:
             d.seg_vert = None
+        d.slab = int(getattr(geo, "slab", 0))
     return arr, keep
 
 
@@ -135,6 +136,7 @@ class Relaxer:
         self.n_feat = int(len(wl.feat_seg))
         self.move_mask = int(wl.move_mask)
         self.h_min = min(float(g.h) for g in wl.geoms)
+        self.n_vert = sum(len(g.mesh.vert) for g in wl.geoms)
         pos = np.zeros((self.n, 4), np.float32)
         pos[:, :3] = wl.pos
         pos[:, 3] = _pack_w(wl.tag, wl.gid)
@@ -186,6 +188,13 @@ class Relaxer:
         check(lib.fppg_project(c, self.geom.handle, self.n, ptr(self.pos), ptr(self.owner), ptr(self.disp),
                                ptr(self.feat_seg), ptr(self.feat_u), self.n_feat, self.move_mask,
                                ptr(self.counters), self.stream), c)
+
+    def project_record(self, accepted: torch.Tensor):
+        """project() that also writes accepted [N] uint8 (1 = the particle's move was applied)."""
+        lib, c = self.ctx.lib, self.ctx.handle
+        check(lib.fppg_project_record(c, self.geom.handle, self.n, ptr(self.pos), ptr(self.owner), ptr(self.disp),
+                                      ptr(self.feat_seg), ptr(self.feat_u), self.n_feat, self.move_mask,
+                                      ptr(self.counters), ptr(accepted), self.stream), c)
 
     def hvp(self, v: torch.Tensor, transpose: bool = False, out: torch.Tensor | None = None) -> torch.Tensor:
         """J v (or J^T v) for v [N, 4] float32 in the current (sorted) order."""

@@ -62,6 +62,7 @@ class Geometry:
     line_begin: int = 0
     feat_begin: int = 0
     vert_begin: int = 0   # global id of the mesh's first vertex (singular-particle owners)
+    slab: int = 0         # rows of cells along y per slab of the cell key (0: one slab)
 
     @property
     def ncell(self) -> int:

@@ -48,6 +48,7 @@ def test_batch_equals_separate_runs_bitwise():
         o = own_b[m].copy()
         o[tag == synth.SURFACE] -= geo.tri_begin
         o[tag == synth.FEATURE] -= geo.feat_begin
+        o[tag == synth.SINGULAR] -= geo.vert_begin
         assert np.array_equal(o, own_s)
         nf = len(fs_s)
         assert np.array_equal(fs_b[geo.feat_begin:geo.feat_begin + nf] - geo.seg_begin, fs_s)

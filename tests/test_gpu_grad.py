@@ -1,0 +1,106 @@
+"""GPU parity of the mesh-vertex gradient (uniformity loss through K
+relaxation steps) and of its building blocks against the FP64 oracle
+(oracle/grad.py, autograd through the frozen-decision replay)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import grad as ograd
+from oracle import metrics
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SURF_VOL = (1 << synth.SURFACE) | (1 << synth.VOLUME)
+
+
+def _relaxer(wl):
+    from paper_2501_03056_amd import Relaxer
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return Relaxer(wl, device=0)
+
+
+def _rho0(wl):
+    return metrics.lattice_density(wl.geoms[0].dx, float(wl.geoms[0].h))
+
+
+def test_rest_density_matches_oracle():
+    from paper_2501_03056_amd.grad import lattice_density
+    for dx in (0.01, 0.045, 0.12):
+        h = float(np.float32(1.3 * dx))
+        assert lattice_density(dx, h) == pytest.approx(metrics.lattice_density(dx, h), rel=1e-13)
+
+
+def test_uniformity_loss_and_gradient_match_oracle():
+    from paper_2501_03056_amd.grad import uniformity_loss
+    wl = synth.tetra_workload(dx=0.06, move_mask=SURF_VOL)
+    r = _relaxer(wl)
+    r.build_cells()
+    g = torch.zeros((wl.n, 4), dtype=torch.float32, device=r.dev)
+    out = uniformity_loss(r, _rho0(wl), g).cpu().numpy()
+    L_ref = metrics.uniformity_loss(wl)
+    assert out[1] == np.sum(((wl.tag == synth.SURFACE) | (wl.tag == synth.VOLUME)))
+    assert out[0] == pytest.approx(L_ref, rel=1e-12)
+    # dL/dx by autograd through the oracle's loss over the same pairs
+    rec = ograd.Record([wl.pos], [wl.owner], [], [], [], ograd._pairs(wl, wl.pos, (wl.tag == 2) | (wl.tag == 3),
+                                                                      with_rank=False))
+    x = torch.as_tensor(wl.pos.astype(np.float64)).requires_grad_(True)
+    (gx,) = torch.autograd.grad(ograd.loss(wl, x, rec), x)
+    g_gpu = r.by_id(g)[:, :3]
+    scale = float(gx.abs().max())
+    np.testing.assert_allclose(g_gpu, gx.numpy(), rtol=0, atol=1e-5 * scale)
+
+
+def _gpu_gradient(wl, K, every):
+    from paper_2501_03056_amd.grad import mesh_gradient
+    r = _relaxer(wl)
+    L, g = mesh_gradient(r, K, _rho0(wl), checkpoint_every=every)
+    return L, g, r
+
+
+@pytest.mark.parametrize("dx,K,every", [(0.12, 3, 2), (0.05, 6, 4), (0.045, 20, 10)])
+def test_mesh_gradient_matches_oracle(dx, K, every):
+    wl = synth.tetra_workload(dx=dx, move_mask=SURF_VOL)
+    print(f"[grad] tetra dx={dx} n={wl.n} K={K} every={every}", flush=True)
+    rec = ograd.record(wl, K)
+    L_ref, g_ref = ograd.mesh_gradient(wl, rec)
+    L, g, r = _gpu_gradient(wl, K, every)
+    assert L == pytest.approx(L_ref, rel=1e-5)
+    scale = np.abs(g_ref).max()
+    assert scale > 1e-3
+    np.testing.assert_allclose(g, g_ref, rtol=0, atol=1e-3 * scale)
+    # the relaxer is left in the state after the K steps
+    pos, _, _, _ = r.host_state()
+    np.testing.assert_allclose(pos, rec.pos32[-1], rtol=0, atol=1e-5)
+
+
+def test_mesh_gradient_does_not_depend_on_checkpointing():
+    """Recomputation is deterministic and the vertex sums are fixed point, so
+    every checkpoint spacing gives the same bits."""
+    wl = synth.tetra_workload(dx=0.09, move_mask=SURF_VOL)
+    L1, g1, _ = _gpu_gradient(wl, 5, 1)
+    L2, g2, _ = _gpu_gradient(wl, 5, 5)
+    L3, g3, _ = _gpu_gradient(wl, 5, 3)
+    assert L1 == L2 == L3
+    np.testing.assert_array_equal(g1, g2)
+    np.testing.assert_array_equal(g1, g3)
+
+
+def test_mesh_gradient_with_no_steps_is_the_loss_through_the_fixed_particles():
+    wl = synth.tetra_workload(dx=0.12, move_mask=SURF_VOL)
+    rec = ograd.record(wl, 0)
+    L_ref, g_ref = ograd.mesh_gradient(wl, rec)
+    L, g, _ = _gpu_gradient(wl, 0, 1)
+    # the replay places singular and feature particles at their FP64 positions,
+    # the GPU at their binary32 roundings
+    assert L == pytest.approx(L_ref, rel=1e-6)
+    np.testing.assert_allclose(g, g_ref, rtol=0, atol=1e-4 * np.abs(g_ref).max())
+
+
+def test_mesh_gradient_refuses_moving_feature_particles():
+    from paper_2501_03056_amd.grad import mesh_gradient
+    wl = synth.tetra_workload(dx=0.12)
+    r = _relaxer(wl)
+    with pytest.raises(ValueError):
+        mesh_gradient(r, 1, _rho0(wl))

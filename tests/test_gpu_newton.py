@@ -1,6 +1,6 @@
 """GPU parity of the Newton-Krylov building blocks (pair energy, vector
 operations, tangent projection, displacement) against the CPU oracle, and the
-behaviour of the trust-region Newton-CG driver."""
+behaviour of the Newton-MINRES driver."""
 import numpy as np
 import pytest
 
@@ -68,6 +68,12 @@ def test_vector_ops_match_numpy():
     out = tb.cpu().numpy()
     assert np.allclose(out[:, :3], 0.5 * a[:, :3] - 2.0 * b[:, :3], rtol=1e-6, atol=1e-6)
     assert np.array_equal(out[:, 3], b[:, 3])          # w untouched
+    # beta = 0 does not read y: NaN left in it (uninitialised memory) must not propagate
+    tn = torch.full_like(ta, float("nan"))
+    r.axpby(2.0, ta, 0.0, tn)
+    np.testing.assert_array_equal(tn.cpu().numpy()[:, :3], 2.0 * a[:, :3])
+    r.axpby(0.0, tn.fill_(float("nan")), 1.0, ta)
+    np.testing.assert_array_equal(ta.cpu().numpy()[:, :3], a[:, :3])
     assert abs(r.maxnorm(ta) - np.linalg.norm(a[:, :3], axis=1).max()) <= 1e-6 * np.linalg.norm(a[:, :3], axis=1).max()
 
 

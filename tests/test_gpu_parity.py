@@ -31,8 +31,18 @@ def _relaxer(wl):
     return Relaxer(wl, device=0)
 
 
+def _slab(wl, S):
+    """The same workload with its cell keys cut into slabs of S cell rows."""
+    for g in wl.geoms:
+        g.slab = S
+    return wl
+
+
 CASES = {
     "cube_n8": lambda: synth.cube_workload(n=8, seed=1),
+    "sphere_l3_slab3": lambda: _slab(synth.sphere_workload(level=3, dx=0.08, seed=2), 3),
+    "cube_n10_k1_slab4": lambda: _slab(synth.cube_workload(n=10, seed=7, k=1), 4),
+    "tetra_slab5": lambda: _slab(synth.tetra_workload(dx=0.06, seed=5), 5),
     "cube_n24": lambda: synth.cube_workload(n=24, seed=1),
     "cube_n10_k1": lambda: synth.cube_workload(n=10, seed=7, k=1),
     "sphere_l3": lambda: synth.sphere_workload(level=3, dx=0.08, seed=2),
@@ -40,7 +50,7 @@ CASES = {
 }
 
 
-@pytest.mark.parametrize("case", ["cube_n8", "sphere_l3", "cube_n10_k1"])
+@pytest.mark.parametrize("case", ["cube_n8", "sphere_l3", "cube_n10_k1", "sphere_l3_slab3", "cube_n10_k1_slab4"])
 def test_cells_bit_exact(case):
     wl = CASES[case]()
     r = _relaxer(wl)
@@ -60,7 +70,7 @@ def test_cells_bit_exact(case):
     assert torch.equal(before, r.pos)
 
 
-@pytest.mark.parametrize("case", ["cube_n8", "sphere_l3", "cube_n10_k1"])
+@pytest.mark.parametrize("case", ["cube_n8", "sphere_l3", "cube_n10_k1", "sphere_l3_slab3", "cube_n10_k1_slab4"])
 def test_neighbor_sets_bit_exact(case):
     wl = CASES[case]()
     r = _relaxer(wl)
@@ -115,7 +125,8 @@ def test_neighbor_sets_adversarial_pairs_at_cell_faces():
         assert np.array_equal(np.sort(ids[lst[s, : count[s]]]), ref[ids[s]])
 
 
-@pytest.mark.parametrize("case", ["cube_n24", "sphere_l3", "tetra", "cube_n10_k1"])
+@pytest.mark.parametrize("case", ["cube_n24", "sphere_l3", "tetra", "cube_n10_k1", "sphere_l3_slab3",
+                                  "tetra_slab5"])
 def test_forces_within_1e5_of_fp64(case):
     wl = CASES[case]()
     r = _relaxer(wl)
@@ -153,7 +164,8 @@ def _compare_step(wl, r, ref, check_owner=True):
     return pos, owner
 
 
-@pytest.mark.parametrize("case", ["cube_n24", "sphere_l3", "tetra", "cube_n10_k1"])
+@pytest.mark.parametrize("case", ["cube_n24", "sphere_l3", "tetra", "cube_n10_k1", "sphere_l3_slab3",
+                                  "tetra_slab5"])
 def test_one_step_positions_within_1e5_of_fp64(case):
     wl = CASES[case]()
     r = _relaxer(wl)

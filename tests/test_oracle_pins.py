@@ -166,6 +166,31 @@ def test_cell_keys_contain_particles_and_order_is_key_then_id():
     assert cs[-1] == wl.n and len(cs) == cells.total_cells(wl) + 2
 
 
+@pytest.mark.parametrize("dims,slab", [((7, 10, 5), 3), ((7, 10, 5), 4), ((4, 9, 3), 1), ((5, 6, 2), 6)])
+def test_slab_keys_enumerate_the_cells_with_contiguous_x_rows(dims, slab):
+    """The slab key is a bijection of the cells onto [0, ncell), x rows are
+    runs of consecutive keys, the rows of one slab and plane are consecutive,
+    and a single slab is the plain x-fastest index."""
+    nx, ny, nz = dims
+    g = np.stack(np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij"), -1).reshape(-1, 3)
+    k = cells.linear_key(g, dims, slab)
+    assert sorted(k.tolist()) == list(range(nx * ny * nz))
+    right = g[:, 0] + 1 < nx
+    kr = cells.linear_key(g[right] + [1, 0, 0], dims, slab)
+    assert np.array_equal(kr, k[right] + 1)
+    # walking the keys in order: slab index never decreases, z within a slab never decreases
+    inv = np.empty_like(k)
+    inv[k] = np.arange(len(k))
+    c = g[inv]
+    s = c[:, 1] // slab
+    assert np.all(np.diff(s) >= 0)
+    same = np.diff(s) == 0
+    assert np.all(np.diff(c[:, 2])[same] >= 0)
+    plain = (g[:, 2] * ny + g[:, 1]) * nx + g[:, 0]
+    assert np.array_equal(cells.linear_key(g, dims, 0), plain)
+    assert np.array_equal(cells.linear_key(g, dims, ny), plain)
+
+
 # --------------------------------------------------------------------------- forces
 
 def test_dyadic_lattice_interior_force_vanishes():
