@@ -209,17 +209,22 @@ __global__ __launch_bounds__(kBlock) void k_update(const float4* __restrict__ po
 
 // ---- Jacobian-vector products -----------------------------------------------------------
 
-// M(r) w = K [ t^3 w - (3/2h) t^2 (r.w) r / |r| ],  t = 1 - |r|/2h  (0 outside the support)
-__device__ __forceinline__ void pair_jac_apply(float dx, float dy, float dz, float d2, float inv2h, float w0, float w1,
-                                               float w2, float& o0, float& o1, float& o2, float scale) {
-  const float r = __builtin_amdgcn_sqrtf(d2);
+// M(r) w = K [ t^3 w - (3/2h) t^2 (r.w) r / |r| ],  t = 1 - |r|/2h  (0 outside the support).
+// 1/|r| from the hardware reciprocal square root (about 1 ulp) and |r| = d2/|r|:
+// one transcendental and no division per pair. r = 0 (coincident particles)
+// gives rsq = inf; the r r^T/|r| term is then 0 by the guard.
+__device__ __forceinline__ void pair_jac_apply(float dx, float dy, float dz, float d2, float inv2h, float k3, float w0,
+                                               float w1, float w2, float& o0, float& o1, float& o2, float scale) {
+  const float inv_r = d2 > 0.0f ? __builtin_amdgcn_rsqf(d2) : 0.0f;
+  const float r = d2 * inv_r;
   const float t = fmaxf(fmaf(-r, inv2h, 1.0f), 0.0f);
-  const float c1 = t * t * t;
-  const float rw = dx * w0 + dy * w1 + dz * w2;
-  const float c2 = r > 0.0f ? (3.0f * inv2h) * t * t * rw / r : 0.0f;
-  o0 = fmaf(scale, c1 * w0 - c2 * dx, o0);
-  o1 = fmaf(scale, c1 * w1 - c2 * dy, o1);
-  o2 = fmaf(scale, c1 * w2 - c2 * dz, o2);
+  const float t2 = t * t;
+  const float c1 = scale * (t2 * t);
+  const float rw = fmaf(dz, w2, fmaf(dy, w1, dx * w0));
+  const float c2 = scale * (k3 * t2) * (rw * inv_r);
+  o0 = fmaf(-c2, dx, fmaf(c1, w0, o0));
+  o1 = fmaf(-c2, dy, fmaf(c1, w1, o1));
+  o2 = fmaf(-c2, dz, fmaf(c1, w2, o2));
 }
 
 template <int K, bool TRANSPOSE>
@@ -238,20 +243,20 @@ __global__ __launch_bounds__(kBlock) void k_jvp(const float4* __restrict__ pos, 
     const int rk = rank_of(tag);
     const float rc2 = G.rc2;
     const float inv2h = 0.5f / G.h;
+    const float k3 = 3.0f * inv2h;
     const float4 vi = v[i];
-    for_each_source<K>(stencil_of(p, G), G, cs, pos, [&](int j, const float4 q) {
+    for_each_source_with<K>(stencil_of(p, G), G, cs, pos, v, [&](int j, const float4 q, const float4 vj) {
       const float dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
       const float d2 = pair_d2(dx, dy, dz);
       if (!(d2 < rc2) || j == i) return;
       const int tj = tag_of(q.w);
       const int rj = rank_of(tj);
-      const float4 vj = v[j];
       if (!TRANSPOSE) {
-        if (rj <= rk) pair_jac_apply(dx, dy, dz, d2, inv2h, vi.x - vj.x, vi.y - vj.y, vi.z - vj.z, o0, o1, o2, 1.0f);
+        if (rj <= rk) pair_jac_apply(dx, dy, dz, d2, inv2h, k3, vi.x - vj.x, vi.y - vj.y, vi.z - vj.z, o0, o1, o2, 1.0f);
       } else {
-        if (mov_i && rj <= rk) pair_jac_apply(dx, dy, dz, d2, inv2h, vi.x, vi.y, vi.z, o0, o1, o2, 1.0f);
+        if (mov_i && rj <= rk) pair_jac_apply(dx, dy, dz, d2, inv2h, k3, vi.x, vi.y, vi.z, o0, o1, o2, 1.0f);
         if (is_moving(tj, move_mask) && rk <= rj)
-          pair_jac_apply(dx, dy, dz, d2, inv2h, vj.x, vj.y, vj.z, o0, o1, o2, -1.0f);
+          pair_jac_apply(dx, dy, dz, d2, inv2h, k3, vj.x, vj.y, vj.z, o0, o1, o2, -1.0f);
       }
     });
     o0 *= G.kcoef;

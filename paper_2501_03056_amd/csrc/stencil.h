@@ -83,6 +83,24 @@ __device__ __forceinline__ void for_each_source(const Stencil s, const GeomDev& 
   });
 }
 
+// As for_each_source, also loading row j of a second float4 field with the
+// position, so that its latency overlaps the pair test (Jacobian products).
+template <int K, class F>
+__device__ __forceinline__ void for_each_source_with(const Stencil s, const GeomDev& G, const int* __restrict__ cs,
+                                                     const float4* __restrict__ pos,
+                                                     const float4* __restrict__ aux, F&& f) {
+  for_each_row<K>(s, G, cs, [&](int j0, int j1) {
+    int j = j0;
+    for (; j + 2 <= j1; j += 2) {
+      const float4 q0 = pos[j], q1 = pos[j + 1];
+      const float4 a0 = aux[j], a1 = aux[j + 1];
+      f(j, q0, a0);
+      f(j + 1, q1, a1);
+    }
+    if (j < j1) f(j, pos[j], aux[j]);
+  });
+}
+
 __device__ __forceinline__ float pair_d2(float dx, float dy, float dz) {
   return (dx * dx + dy * dy) + dz * dz;   // no contraction in this file
 }

@@ -59,19 +59,25 @@ def uniformity_loss(r, rho0: float, grad: torch.Tensor | None = None) -> torch.T
     return out
 
 
-def mesh_gradient(r, K: int, rho0: float, checkpoint_every: int = 10, n_vert: int | None = None):
-    """Run K relaxation steps from the relaxer's state and return
-    (L, dL/dV [n_vert, 3] float64 numpy) with V the batch's mesh vertices in
-    global numbering. The relaxer ends in the state after the K steps."""
+class Tape:
+    """What the reverse sweep needs from a forward run: the checkpoints, the
+    final state, the loss and its gradient with respect to the final positions
+    (by particle id)."""
+
+    def __init__(self, K, every, ckpts, final, loss, xbar_id):
+        self.K, self.every, self.ckpts, self.final = K, every, ckpts, final
+        self.loss, self.xbar_id = loss, xbar_id
+
+
+def forward(r, K: int, rho0: float, checkpoint_every: int = 10) -> Tape:
+    """K relaxation steps from the relaxer's state keeping checkpoints, then
+    the uniformity loss of the final state and dL/dx (device, by id)."""
     if (r.move_mask >> 1) & 1:
-        raise ValueError("mesh_gradient holds feature particles fixed: clear bit 1 of move_mask")
+        raise ValueError("mesh gradients hold feature particles fixed: clear bit 1 of move_mask")
     if K < 0 or checkpoint_every < 1:
         raise ValueError("K >= 0 and checkpoint_every >= 1 required")
     if r.ws_bytes < 8 * (r.n + 2 * ((r.n + 255) // 256)) + 64:
         raise ValueError("workspace too small for the loss")
-    dev, n = r.dev, r.n
-    n_vert = int(n_vert if n_vert is not None else r.n_vert)
-    # forward with checkpoints
     ckpts = []
     for step in range(K):
         if step % checkpoint_every == 0:
@@ -79,20 +85,29 @@ def mesh_gradient(r, K: int, rho0: float, checkpoint_every: int = 10, n_vert: in
         r.step(keep_accel=False)
     final = (r.pos.clone(), r.id.clone(), r.owner.clone())
     r.build_cells()
-    g = torch.zeros((n, 4), dtype=torch.float32, device=dev)
+    g = torch.zeros((r.n, 4), dtype=torch.float32, device=r.dev)
     out = uniformity_loss(r, rho0, g)
-    # dL/dx in id order
     xbar_id = torch.zeros_like(g)
-    _lib_call(r, "fppg_vec_permute", n, ptr(g), ptr(r.id), 1, ptr(xbar_id), r.stream)
+    _lib_call(r, "fppg_vec_permute", r.n, ptr(g), ptr(r.id), 1, ptr(xbar_id), r.stream)
+    return Tape(K, checkpoint_every, ckpts, final, out, xbar_id)
+
+
+def backward(r, tape: Tape, n_vert: int | None = None) -> torch.Tensor:
+    """Reverse sweep of a forward run: dL/dV [n_vert, 3] (device, float64).
+    The relaxer is left in the state after the K steps."""
+    dev, n = r.dev, r.n
+    n_vert = int(n_vert if n_vert is not None else r.n_vert)
+    xbar_id = tape.xbar_id.clone()
     vbar = torch.zeros(3 * n_vert, dtype=torch.int64, device=dev)
-    xb_next = torch.empty_like(g)
-    xb = torch.empty_like(g)
-    yb = torch.empty_like(g)
-    jt = torch.empty_like(g)
+    xb_next = torch.empty_like(xbar_id)
+    xb = torch.empty_like(xbar_id)
+    yb = torch.empty_like(xbar_id)
+    jt = torch.empty_like(xbar_id)
     first = None
+    ckpts = tape.ckpts
     for ci in range(len(ckpts) - 1, -1, -1):
         s0, pos, ids, own = ckpts[ci]
-        s1 = ckpts[ci + 1][0] if ci + 1 < len(ckpts) else K
+        s1 = ckpts[ci + 1][0] if ci + 1 < len(ckpts) else tape.K
         r.pos.copy_(pos)
         r.id.copy_(ids)
         r.owner.copy_(own)
@@ -122,6 +137,9 @@ def mesh_gradient(r, K: int, rho0: float, checkpoint_every: int = 10, n_vert: in
     if first is not None:
         pos0, own0, ids0 = first.pos, first.owner, first.id
     else:
+        r.pos.copy_(tape.final[0])
+        r.id.copy_(tape.final[1])
+        r.owner.copy_(tape.final[2])
         r.build_cells()
         pos0, own0, ids0 = r.pos, r.owner, r.id
     _lib_call(r, "fppg_vec_permute", n, ptr(xbar_id), ptr(ids0), 0, ptr(xb), r.stream)
@@ -129,9 +147,44 @@ def mesh_gradient(r, K: int, rho0: float, checkpoint_every: int = 10, n_vert: in
               r.n_feat, r.move_mask, ptr(xb), ptr(vbar), r.stream)
     vd = torch.empty(3 * n_vert, dtype=torch.float64, device=dev)
     _lib_call(r, "fppg_fixed_to_double", 3 * n_vert, ptr(vbar), ptr(vd), r.stream)
-    # leave the relaxer in the state after the K steps
-    r.pos.copy_(final[0])
-    r.id.copy_(final[1])
-    r.owner.copy_(final[2])
-    torch.cuda.synchronize(dev)
-    return float(out[0].item()), vd.view(n_vert, 3).cpu().numpy()
+    r.pos.copy_(tape.final[0])
+    r.id.copy_(tape.final[1])
+    r.owner.copy_(tape.final[2])
+    return vd.view(n_vert, 3)
+
+
+def mesh_gradient(r, K: int, rho0: float, checkpoint_every: int = 10, n_vert: int | None = None):
+    """Run K relaxation steps from the relaxer's state and return
+    (L, dL/dV [n_vert, 3] float64 numpy) with V the batch's mesh vertices in
+    global numbering. The relaxer ends in the state after the K steps."""
+    tape = forward(r, K, rho0, checkpoint_every)
+    g = backward(r, tape, n_vert)
+    torch.cuda.synchronize(r.dev)
+    return float(tape.loss[0].item()), g.cpu().numpy()
+
+
+class RelaxedUniformity(torch.autograd.Function):
+    """L(V): the uniformity loss after K relaxation steps of the relaxer's
+    particles on the mesh with vertices V, as a differentiable torch function.
+    The geometry is the one the relaxer was built with, so V must hold those
+    vertices (checked); forward runs the steps keeping checkpoints, backward
+    runs the reverse sweep in the library's kernels.
+
+        L = RelaxedUniformity.apply(V, relaxer, K, rho0, checkpoint_every)
+        L.backward()      # V.grad = dL/dV
+    """
+
+    @staticmethod
+    def forward(ctx, V, r, K, rho0, checkpoint_every=10):
+        want = torch.as_tensor(r.vert, dtype=torch.float64)
+        if V.shape != want.shape or not torch.equal(V.detach().to("cpu", torch.float64), want):
+            raise ValueError("V must be the vertices the relaxer's geometry was built from")
+        tape = forward(r, int(K), float(rho0), int(checkpoint_every))
+        ctx.r, ctx.tape = r, tape
+        return tape.loss[0].to(V.device, V.dtype)
+
+    @staticmethod
+    def backward(ctx, gL):
+        g = backward(ctx.r, ctx.tape)
+        ctx.r = ctx.tape = None
+        return (gL * g.to(gL.device, gL.dtype)).to(gL.dtype), None, None, None, None

@@ -51,6 +51,7 @@ class NewtonLog:
     newton_iters: int = 0
     krylov_iters: int = 0
     backtracks: int = 0
+    checkpoint: tuple | None = None                  # device snapshot (Relaxer.snapshot)
 
 
 class _Minres:
@@ -110,9 +111,18 @@ class _Minres:
 
 
 def newton_relax(r: Relaxer, n_moving: int, target: float | None = None, max_iter: int = 50,
-                 krylov_tol: float = 1e-4, krylov_max: int = 50, move_cap: float = 0.25,
-                 max_backtracks: int = 6, time_limit: float | None = None) -> NewtonLog:
-    """Newton-MINRES on F = P a until the force residual is <= target."""
+                 krylov_tol: float = 1e-4, krylov_max: int = 10, move_cap: float = 0.25,
+                 max_backtracks: int = 6, time_limit: float | None = None,
+                 forcing: str | None = "ew", checkpoint_every: int = 0) -> NewtonLog:
+    """Newton-MINRES on F = P a until the force residual is <= target.
+
+    forcing = None solves every Newton system to the relative residual
+    krylov_tol; forcing = "ew" picks the tolerance per step by Eisenstat and
+    Walker's second rule (eta_k = 0.9 (|F_k|/|F_k-1|)^2, safeguarded, between
+    krylov_tol and 0.5): loose solves far from the solution, tight ones near it.
+    At most krylov_max MINRES iterations either way. checkpoint_every > 0
+    keeps a device snapshot of the state every that many accepted Newton
+    steps in log.checkpoint (a restart point; Relaxer.restore puts it back)."""
     h = r.h_min
     log = NewtonLog()
     t0 = time.perf_counter()
@@ -121,6 +131,7 @@ def newton_relax(r: Relaxer, n_moving: int, target: float | None = None, max_ite
     log.residual.append((0.0, math.sqrt(max(f2, 0.0) / max(n_moving, 1))))
     d = torch.zeros_like(F)
     solver = _Minres(r, F)
+    eta, f2_prev = 0.5, None
     for _ in range(max_iter):
         R = log.residual[-1][1]
         if target is not None and R <= target:
@@ -128,7 +139,17 @@ def newton_relax(r: Relaxer, n_moving: int, target: float | None = None, max_ite
         if time_limit is not None and time.perf_counter() - t0 > time_limit:
             break
         log.newton_iters += 1
-        log.krylov_iters += solver.solve(F, d, krylov_tol, krylov_max)   # A d = F, A = -PJP: d = -(PJP)^-1 F
+        if forcing == "ew":
+            if f2_prev is not None:
+                e = 0.9 * (f2 / f2_prev)
+                safe = 0.9 * eta * eta
+                eta = max(e, safe) if safe > 0.1 else e
+            eta = min(0.5, max(krylov_tol, eta))
+            tol = eta
+        else:
+            tol = krylov_tol
+        f2_prev = f2
+        log.krylov_iters += solver.solve(F, d, tol, krylov_max)   # A d = F, A = -PJP: d = -(PJP)^-1 F
         r.clamp(d, move_cap * h)
         snap = r.snapshot()
         s, accepted = 1.0, False
@@ -146,6 +167,8 @@ def newton_relax(r: Relaxer, n_moving: int, target: float | None = None, max_ite
         if not accepted:
             break
         F, f2 = F_new, f2_new
+        if checkpoint_every > 0 and log.newton_iters % checkpoint_every == 0:
+            log.checkpoint = r.snapshot()
         torch.cuda.synchronize()
         log.residual.append((time.perf_counter() - t0, math.sqrt(max(f2, 0.0) / max(n_moving, 1))))
     return log

@@ -137,6 +137,7 @@ class Relaxer:
         self.move_mask = int(wl.move_mask)
         self.h_min = min(float(g.h) for g in wl.geoms)
         self.n_vert = sum(len(g.mesh.vert) for g in wl.geoms)
+        self.vert = np.concatenate([np.asarray(g.mesh.vert, np.float64) for g in wl.geoms], 0)
         pos = np.zeros((self.n, 4), np.float32)
         pos[:, :3] = wl.pos
         pos[:, 3] = _pack_w(wl.tag, wl.gid)

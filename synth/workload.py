@@ -576,3 +576,171 @@ def batch_workload(n_geom=64, n_min=5e3, n_max=5e5, seed=4000, jitter=0.3, k=2,
         targets.append(n_t)
     return _finish(name or f"batch{n_geom}_seed{seed}", parts, move_mask, seed,
                    {"kinds": kinds, "targets": targets})
+
+
+# ---------------------------------------------------------------------------
+# Extruded gear (24 teeth, central bore)
+# ---------------------------------------------------------------------------
+
+def _seg_dist2(p, a, b):
+    """Squared distance of 2-D points p [..., 2] to segments a-b [..., 2]."""
+    e = b - a
+    w = p - a
+    t = np.clip(np.sum(w * e, -1) / np.maximum(np.sum(e * e, -1), 1e-300), 0.0, 1.0)
+    d = w - t[..., None] * e
+    return np.sum(d * d, -1)
+
+
+class _GearProfile:
+    """The gear's 2-D outline and bore as polygons sampled at the same n
+    angles (counter-clockwise), with a windowed distance query: the polygons
+    are star-shaped about the axis, so the ray at angle theta crosses edge
+    k = floor(theta n / 2 pi) and the closest edges are a few samples away."""
+
+    def __init__(self, mesh: M.Mesh, n: int, rings: int):
+        self.n, self.rings = n, rings
+        top = (rings + 1) * n            # vertices of face 0 (z < 0) come first
+        self.inner = mesh.vert[:n, :2].copy()
+        self.outer = mesh.vert[rings * n: rings * n + n, :2].copy()
+        assert top == len(mesh.vert) // 2
+        r_out = np.linalg.norm(self.outer, axis=1)
+        self.r_min_out = float(r_out.min())
+        self.r_max_in = float(np.linalg.norm(self.inner, axis=1).max())
+
+    def sector(self, p):
+        th = np.mod(np.arctan2(p[:, 1], p[:, 0]), 2 * np.pi)
+        return np.minimum((th * (self.n / (2 * np.pi))).astype(np.int64), self.n - 1)
+
+    def _side(self, P, k, p):
+        a, b = P[k], P[(k + 1) % self.n]
+        return (b[:, 0] - a[:, 0]) * (p[:, 1] - a[:, 1]) - (b[:, 1] - a[:, 1]) * (p[:, 0] - a[:, 0])
+
+    def _dist(self, P, k, p, W=4):
+        best = np.full(len(p), np.inf)
+        for o in range(-W, W + 1):
+            kk = (k + o) % self.n
+            best = np.minimum(best, _seg_dist2(p, P[kk], P[(kk + 1) % self.n]))
+        return np.sqrt(best)
+
+    def inside(self, p, margin):
+        """2-D points strictly inside the annulus at least `margin` from both polygons."""
+        rho = np.linalg.norm(p, axis=1)
+        ok = (rho > self.r_max_in * 0.99) & (rho < 1.01 * float(np.linalg.norm(self.outer, axis=1).max()))
+        deep = (rho > self.r_max_in + margin + 1e-5) & (rho < self.r_min_out * np.cos(np.pi / self.n) - margin - 1e-5)
+        test = ok & ~deep
+        idx = np.nonzero(test)[0]
+        if len(idx):
+            q = p[idx]
+            k = self.sector(q)
+            good = (self._side(self.outer, k, q) > 0) & (self._side(self.inner, k, q) < 0)
+            good &= (self._dist(self.outer, k, q) >= margin) & (self._dist(self.inner, k, q) >= margin)
+            test[idx] = good
+        return deep | test
+
+
+def _owner_by_candidates(mesh: M.Mesh, cand: np.ndarray, pts: np.ndarray) -> np.ndarray:
+    """First candidate facet (cand [P, C]) whose triangle contains each point
+    (points on the facet's plane; barycentric coordinates >= -1e-12)."""
+    out = np.full(len(pts), -1, np.int64)
+    for c in range(cand.shape[1]):
+        f = cand[:, c]
+        A, B, C = (mesh.vert[mesh.tri[f, q]] for q in range(3))
+        e0, e1, w = B - A, C - A, pts - A
+        d00, d01, d11 = (np.einsum("ij,ij->i", x, y) for x, y in ((e0, e0), (e0, e1), (e1, e1)))
+        d20, d21 = np.einsum("ij,ij->i", w, e0), np.einsum("ij,ij->i", w, e1)
+        den = d00 * d11 - d01 * d01
+        lb = (d11 * d20 - d01 * d21) / den
+        lc = (d00 * d21 - d01 * d20) / den
+        hit = (lb >= -1e-12) & (lc >= -1e-12) & (1 - lb - lc >= -1e-12) & (out < 0)
+        out[hit] = f[hit]
+    return out
+
+
+def gear_workload(dx=0.004, jitter=0.3, seed=3, k=2, move_mask=ALL_MOVING, samples_per_period=60,
+                  rings=35, name=None) -> Workload:
+    """24-tooth extruded gear (meshes.gear: outer radius 1, root 0.85, bore
+    0.2, thickness 0.3, ~207k facets) filled as in section 3.2:
+      volume   (i+1/2)dx lattice jittered by U(+-jitter dx)^3, kept at least
+               dx/2 inside every face;
+      surface  top and bottom: jittered (i+1/2)dx lattice in the face plane at
+               least dx/2 from the rims; walls: points at spacing ~dx in arc
+               length around the rim times (b+1/2)dx in z, jittered in the
+               wall, at least dx/2 from the rims and from the vertical sharp
+               edges; owner = the facet containing the point;
+      feature  spacing L/ceil(L/dx) along every sharp line, jittered along it;
+      singular the 192 tooth corners on the rims."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mesh = M.gear(samples_per_period=samples_per_period, rings=rings)
+    n = 24 * samples_per_period
+    prof = _GearProfile(mesh, n, rings)
+    geom = _make_geom(mesh, dx, k)
+    b = _Builder()
+    half = 0.15
+    m = 0.5 * dx
+    lo, hi = mesh.bbox()
+    gx = np.arange(lo[0] + 0.5 * dx, hi[0], dx)
+    gy = np.arange(lo[1] + 0.5 * dx, hi[1], dx)
+    gz = np.arange(-half + 0.5 * dx, half, dx)
+    # volume, one x column at a time to bound memory
+    vol = []
+    for x in gx:
+        g = np.stack(np.meshgrid([x], gy, gz, indexing="ij"), -1).reshape(-1, 3)
+        g = g + rng.uniform(-jitter, jitter, g.shape) * dx
+        keep = (np.abs(g[:, 2]) <= half - m) & prof.inside(g[:, :2], m)
+        vol.append(g[keep])
+    b.add(np.concatenate(vol, 0), VOLUME)
+    # top and bottom faces
+    nf_face = rings * n * 2
+    g2 = np.stack(np.meshgrid(gx, gy, indexing="ij"), -1).reshape(-1, 2)
+    for face, z in enumerate((-half, half)):
+        q = g2 + rng.uniform(-jitter, jitter, g2.shape) * dx
+        q = q[prof.inside(q, m)]
+        kq = prof.sector(q)
+        r_in = np.linalg.norm(prof.inner[kq], axis=1)
+        r_out = np.linalg.norm(prof.outer[kq], axis=1)
+        s = (np.linalg.norm(q, axis=1) - r_in) / np.maximum(r_out - r_in, 1e-12)
+        j0 = np.clip((s * rings).astype(np.int64), 0, rings - 1)
+        cand = []
+        for dj in (0, -1, 1):
+            for dk in (0, -1, 1):
+                jj = np.clip(j0 + dj, 0, rings - 1)
+                kk = (kq + dk) % n
+                base = face * nf_face + jj * (2 * n) + 2 * kk
+                cand += [base, base + 1]
+        cand = np.stack(cand, 1)
+        pts = np.concatenate([q, np.full((len(q), 1), z)], 1)
+        own = _owner_by_candidates(mesh, cand, pts)
+        ok = own >= 0
+        b.add(pts[ok], SURFACE, own[ok])
+    # walls: bore (ring 0) and outline (ring `rings`)
+    nf = 2 * nf_face
+    corner = np.zeros(n, bool)
+    corner[[kk for kk in range(n) if (kk % samples_per_period) in
+            (0, samples_per_period // 3, samples_per_period // 2, (5 * samples_per_period) // 6)]] = True
+    for wall, P in enumerate((prof.inner, prof.outer)):
+        # points at spacing ~dx in arc length along the closed rim polygon
+        a2, b2 = P, np.roll(P, -1, axis=0)
+        L = np.linalg.norm(b2 - a2, axis=1)
+        cum = np.concatenate([[0.0], np.cumsum(L)])
+        m_arc = int(np.ceil(cum[-1] / dx))
+        sp = cum[-1] / m_arc
+        arc = np.repeat((np.arange(m_arc) + 0.5) * sp, len(gz))
+        Z = np.tile(gz, m_arc)
+        arc = np.mod(arc + rng.uniform(-jitter, jitter, len(arc)) * sp, cum[-1])
+        Z = Z + rng.uniform(-jitter, jitter, len(Z)) * dx
+        K = np.clip(np.searchsorted(cum, arc, side="right") - 1, 0, n - 1)
+        U = (arc - cum[K]) / L[K]
+        xy = a2[K] + U[:, None] * (b2[K] - a2[K])
+        ok = np.abs(Z) <= half - m
+        if wall == 1:   # stay clear of the vertical sharp edges at tooth corners
+            for kc in (K, (K + 1) % n, (K - 1) % n, (K + 2) % n):
+                ok &= ~(corner[kc] & (np.linalg.norm(xy - P[kc], axis=1) < m))
+        K, xy, Z = K[ok], xy[ok], Z[ok]
+        pts = np.concatenate([xy, Z[:, None]], 1)
+        base = nf + wall * 2 * n + 2 * K
+        own = _owner_by_candidates(mesh, np.stack([base, base + 1], 1), pts)
+        good = own >= 0
+        b.add(pts[good], SURFACE, own[good])
+    _feature_particles(b, mesh, dx, rng, jitter)
+    b.add(mesh.singular, SINGULAR, mesh.singular_vert)
+    return _finish(name or f"gear24_dx{dx:g}", [(geom, b)], move_mask, seed, {"dx": dx})

@@ -104,3 +104,18 @@ def test_mesh_gradient_refuses_moving_feature_particles():
     r = _relaxer(wl)
     with pytest.raises(ValueError):
         mesh_gradient(r, 1, _rho0(wl))
+
+
+def test_autograd_function_matches_the_driver():
+    """RelaxedUniformity.apply(V, ...) and .backward() give the driver's L and dL/dV."""
+    from paper_2501_03056_amd.grad import RelaxedUniformity
+    wl = synth.tetra_workload(dx=0.09, move_mask=SURF_VOL)
+    L0, g0, _ = _gpu_gradient(wl, 4, 2)
+    r = _relaxer(wl)
+    V = torch.tensor(wl.geoms[0].mesh.vert, dtype=torch.float64, requires_grad=True)
+    L = RelaxedUniformity.apply(V, r, 4, _rho0(wl), 2)
+    (2.0 * L).backward()
+    assert float(L) == L0
+    np.testing.assert_array_equal(V.grad.numpy(), 2.0 * g0)
+    with pytest.raises(ValueError):
+        RelaxedUniformity.apply(V.detach() + 1e-3, _relaxer(wl), 1, _rho0(wl), 1)

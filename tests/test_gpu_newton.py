@@ -108,8 +108,9 @@ def test_newton_lowers_the_force_residual_below_the_plain_loop():
     plain = plain_relax(rp, n_moving, iters=30, record_every=2)
     best = min(R for _, R in plain)
     rn = _relaxer(wl)
-    log = newton_relax(rn, n_moving, target=None, max_iter=8)
+    log = newton_relax(rn, n_moving, target=None, max_iter=8, checkpoint_every=4)
     R = np.array([R for _, R in log.residual])
+    assert log.checkpoint is not None
     assert np.all(np.diff(R) < 0)                       # every accepted step lowers |P a|
     assert R[-1] < 0.5 * best                           # well below the plain loop's best in 30 iterations
     assert log.newton_iters <= 8
@@ -118,3 +119,8 @@ def test_newton_lowers_the_force_residual_below_the_plain_loop():
     v = wl.tag == synth.VOLUME
     assert np.all((pos[v] > 0) & (pos[v] < 1))
     assert rn.read_status() == 0
+    # the same with every Newton system solved to 1e-4 (fixed forcing)
+    rf = _relaxer(wl)
+    logf = newton_relax(rf, n_moving, target=None, max_iter=4, forcing=None, krylov_tol=1e-4, krylov_max=50)
+    Rf = np.array([R for _, R in logf.residual])
+    assert np.all(np.diff(Rf) < 0) and Rf[-1] < best
