@@ -17,6 +17,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -59,15 +60,18 @@ def source_hash(paths):
 
 
 def traffic_from_profile(kernel_hash):
-    """HBM bytes per force launch measured by rocprofv3 counters (committed
-    summary), or None if absent or taken on a different kernel source."""
-    p = os.path.join(ROOT, "profiles", "force_sphere_l5_counters.json")
+    """HBM bytes per force launch measured by rocprofv3 counters (the committed
+    summary's `kernel_source_hash:` and `hbm_bytes_per_launch:` lines), or
+    None if absent or taken on a different kernel source."""
+    p = os.path.join(ROOT, "profiles", "force_sphere_l5_counters.md")
     if not os.path.exists(p):
         return None
-    d = json.load(open(p))
-    if d.get("kernel_source_hash") != kernel_hash:
+    text = open(p).read()
+    h = re.search(r"^kernel_source_hash:\s*(\S+)", text, re.M)
+    b = re.search(r"^hbm_bytes_per_launch:\s*(\d+)", text, re.M)
+    if not h or not b or h.group(1) != kernel_hash:
         return None
-    return d.get("hbm_bytes_per_launch")
+    return int(b.group(1))
 
 
 def cpu_baseline(wl, sample=160, seed=0):
@@ -151,6 +155,64 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_gear(args):
+    """The gear relaxed in three tiers (feature lines, then surface, then
+    volume particles; the other classes are fixed sources of the moving one),
+    --tier-iters iterations each on the same state. value = sum over tiers of
+    moving particles x iterations / total seconds."""
+    import torch
+    import synth
+    from paper_2501_03056_amd import Relaxer
+    dx = args.gear_dx
+    t0 = time.perf_counter()
+    wl = synth.gear_workload(dx=dx, seed=3, k=args.k)
+    for g in wl.geoms:
+        g.slab = args.slab
+    print(f"[bench] gear dx={dx:g}: {wl.n} particles {wl.counts()} built in {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    r = Relaxer(wl, device=0)
+    print(f"[bench] geometry on the device in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    tiers = [("feature", 1 << synth.FEATURE), ("surface", 1 << synth.SURFACE), ("volume", 1 << synth.VOLUME)]
+    out_tiers, total_s, total_upd = {}, 0.0, 0.0
+    for name, mm in tiers:
+        r.move_mask = mm
+        n_moving = int(np.sum((mm >> wl.tag) & 1))
+        for _ in range(args.warmup):
+            r.step(keep_accel=False)
+        r.build_cells()
+        r.relax_step(count_pairs=True)
+        pairs = float(r.accel[:, 3].double().sum().item())
+        r.profile(True)
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record()
+        for _ in range(args.tier_iters):
+            r.step(keep_accel=False)
+        stop.record()
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(stop)
+        prof = r.profile_read()
+        r.profile(False)
+        total_s += ms / 1e3
+        total_upd += n_moving * args.tier_iters
+        out_tiers[name] = {"moving": n_moving, "iters": args.tier_iters, "ms_per_step": ms / args.tier_iters,
+                           "particle_updates_per_s": n_moving * args.tier_iters / (ms / 1e3),
+                           "pairs_per_step": pairs, "pair_evals_per_s": pairs * args.tier_iters / (ms / 1e3),
+                           "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]}}
+        print(f"[bench] tier {name}: {n_moving} moving, {ms / args.tier_iters:.3f} ms/step", file=sys.stderr,
+              flush=True)
+    out = {"metric": "particle-updates/s", "value": total_upd / total_s, "unit": "particle-updates/s",
+           "n_gpus": 1, "steps": 3 * args.tier_iters, "warmup": 3 * args.warmup,
+           "ms_per_step": 1e3 * total_s / (3 * args.tier_iters), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"gear24_dx{dx:g}_tiers_feature_surface_volume", "particles": wl.n,
+                      "counts": wl.counts(), "facets": int(r.geom.n_tri), "stencil_k": int(wl.geoms[0].k),
+                      "key_slab_rows": int(args.slab)},
+           "tiers": out_tiers, "device_status": r.read_status()}
+    print(json.dumps(out), flush=True)
+
+
 def _first_at_or_below(curve, target):
     for t, R in curve:
         if R <= target:
@@ -227,7 +289,9 @@ def bench_newton(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--mode", default="step", choices=["step", "batch", "newton"])
+    ap.add_argument("--mode", default="step", choices=["step", "batch", "newton", "gear"])
+    ap.add_argument("--gear-dx", type=float, default=0.004)
+    ap.add_argument("--tier-iters", type=int, default=100)
     ap.add_argument("--plain-iters", type=int, default=100)
     ap.add_argument("--newton-dx", type=float, default=None, help="default 0.004 (gear), 0.01 (sphere)")
     ap.add_argument("--newton-workload", default="gear", choices=["gear", "sphere"])
@@ -237,7 +301,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="sphere")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=160)
+    ap.add_argument("--cpu-sample", type=int, default=960)
     ap.add_argument("--k", type=int, default=2, help="stencil half-width of the particle cells (1 or 2)")
     ap.add_argument("--slab", type=int, default=0,
                     help="cell rows per slab of the cell key (0: one slab per geometry)")
@@ -252,6 +316,8 @@ def main():
         return bench_batch(args)
     if args.mode == "newton":
         return bench_newton(args)
+    if args.mode == "gear":
+        return bench_gear(args)
     import torch
     from paper_2501_03056_amd import Relaxer
 

@@ -4,18 +4,25 @@ differentiates the relaxation of section 3.3.
 
 Reading (parity unpinned as a definition; its pins are below): the discrete
 decisions of every step are frozen at their forward values: the time step
-dt_n^2 (Eq. 22-23 reading), each particle's owner facet before and after the
-step, whether its move was accepted or reverted, and the neighbour pairs.
-Between decisions the step is a smooth map of the positions and of the mesh:
+dt_n^2 (Eq. 22-23 reading), each particle's owner facet (feature segment)
+before and after the step, whether its move was accepted or reverted, the
+direction of a feature particle's walk, and the neighbour pairs. Between
+decisions the step is a smooth map of the positions and of the mesh:
 
     y = x + dt^2 P_o a(x)                 P_o = I - n_o n_o^T for surface, I for volume
     x' = y - ((y - A_t) . n_t) n_t        accepted surface move onto facet t
     x' = y                                accepted volume move
+    u' = u + dt^2 a(x).t_s + c            accepted feature move from segment s to s':
+    x' = P0_s' + u' t_s'                  c = -(lengths of the segments walked off
+                                          forwards) + (lengths of those walked onto
+                                          backwards), t = (P1 - P0)/|P1 - P0|
     x' = x                                reverted move, or a particle that does not move
 
-with n = (B - A) x (C - A) / |.| of the facet's vertices. Particles that do
-not move are functions of the mesh: a singular particle sits on its vertex, a
-feature particle at arc length u of its segment P0 + u (P1 - P0)/|P1 - P0|.
+with n = (B - A) x (C - A) / |.| of the facet's vertices and (s, u) a feature
+particle's segment and arc length. Particles that do not move are functions of
+the mesh: a singular particle sits on its vertex, a feature particle at arc
+length u of its segment. Feature particles start on the mesh (at their
+initial (s, u)); surface and volume particles start at their given positions.
 The loss is metrics.uniformity_loss of the final positions.
 
 `record` runs the oracle's own forward (step.relax_step) and stores the
@@ -69,23 +76,29 @@ class Record:
     accepted: list       # bool [N] per step: the move was applied
     pairs: list          # force pairs (I, J) per step
     loss_pairs: tuple    # density pairs of the final state
+    feat_seg: list = None   # feature segment per slot before each step, [K+1]
+    feat_u: list = None     # feature arc length per slot before each step, [K+1]
+    du: list = None         # feature arc-length increment per particle per step
 
 
 def record(wl, K: int) -> Record:
-    """K oracle steps from the workload's state (single geometry, features fixed)."""
+    """K oracle steps from the workload's state (single geometry)."""
     assert len(wl.geoms) == 1, "single geometry"
     mov = F.moving_mask(wl.tag, wl.move_mask)
-    assert not np.any(mov & (wl.tag == FEATURE)), "feature particles are held fixed here"
     pos, owner = wl.pos.copy(), wl.owner.copy()
-    rec = Record([pos], [owner], [], [], [], None)
+    fs, fu = wl.feat_seg.copy(), wl.feat_u.copy()
+    rec = Record([pos], [owner], [], [], [], None, [fs], [fu], [])
     for _ in range(K):
-        out = S.relax_step(wl, pos32=pos, owner=owner)
+        out = S.relax_step(wl, pos32=pos, owner=owner, feat_seg=fs, feat_u=fu)
         rec.tau.append(float(out.tau[0]))
         rec.accepted.append(mov & ~out.reverted)
         rec.pairs.append(_pairs(wl, pos, mov))
-        pos, owner = out.pos32, out.owner
+        rec.du.append(out.du.copy())
+        pos, owner, fs, fu = out.pos32, out.owner, out.feat_seg, out.feat_u
         rec.pos32.append(pos)
         rec.owner.append(owner)
+        rec.feat_seg.append(fs)
+        rec.feat_u.append(fu)
     rec.loss_pairs = _pairs(wl, pos, mov, with_rank=False)
     return rec
 
@@ -96,8 +109,35 @@ def _frames(V, tri):
     return A, n / torch.linalg.norm(n, dim=1, keepdim=True)
 
 
+def _segments(wl, V):
+    """P0, unit tangent and length of every feature segment, from V."""
+    sv = torch.as_tensor(wl.geoms[0].mesh.lines.seg_vert.astype(np.int64))
+    P0, P1 = V[sv[:, 0]], V[sv[:, 1]]
+    L = torch.linalg.norm(P1 - P0, dim=1)
+    return P0, (P1 - P0) / L[:, None], L
+
+
+def _walk(lines, s, s2, forward):
+    """Segments a feature particle walks off (forwards) or onto (backwards)
+    going from segment s to s2 along its line."""
+    lsb = lines.line_seg_begin
+    line = int(np.searchsorted(lsb, s, side="right") - 1)
+    lo, hi, closed = int(lsb[line]), int(lsb[line + 1]), bool(lines.line_closed[line])
+    out, k = [], int(s)
+    while k != s2:
+        if forward:
+            out.append(k)
+            k = k + 1 if k + 1 < hi else (lo if closed else None)
+        else:
+            k = k - 1 if k > lo else (hi - 1 if closed else None)
+            out.append(k)
+        assert k is not None and len(out) <= hi - lo, "feature walk left its line"
+    return out
+
+
 def fixed_positions(wl, V):
-    """Positions of the particles that do not move, as functions of V."""
+    """Positions of the particles that do not move, as functions of V (all
+    feature particles: their initial positions)."""
     geo = wl.geoms[0]
     x = torch.as_tensor(wl.pos.astype(np.float64)).clone()
     sing = np.nonzero(wl.tag == SINGULAR)[0]
@@ -127,7 +167,12 @@ def replay(wl, V, rec: Record, x0=None):
     surf = torch.as_tensor(wl.tag == SURFACE)
     x = fixed_positions(wl, V)
     if x0 is not None:
-        x = torch.where(mov[:, None], x0, x)
+        x = torch.where(mov[:, None] & (torch.as_tensor(wl.tag) != FEATURE)[:, None], x0, x)
+    fmov = np.nonzero(F.moving_mask(wl.tag, wl.move_mask) & (wl.tag == FEATURE))[0]
+    if len(fmov):
+        P0, T, L = _segments(wl, V)
+        lines = geo.mesh.lines
+        u = torch.as_tensor(wl.feat_u.copy())               # arc length per slot (state)
     for n in range(len(rec.tau)):
         I = torch.as_tensor(rec.pairs[n][0].astype(np.int64))
         J = torch.as_tensor(rec.pairs[n][1].astype(np.int64))
@@ -142,6 +187,25 @@ def replay(wl, V, rec: Record, x0=None):
         nt, At = nrm[own_t], A[own_t]
         proj = y - ((y - At) * nt).sum(1, keepdim=True) * nt
         moved = torch.where(surf[:, None], proj, y)
+        if len(fmov):
+            rows, vals, slots, us = [], [], [], []
+            for i in fmov:
+                if not rec.accepted[n][i]:
+                    continue
+                slot = int(wl.owner[i])
+                s0, s2 = int(rec.feat_seg[n][slot]), int(rec.feat_seg[n + 1][slot])
+                du = rec.tau[n] * (a[i] * T[s0]).sum()
+                c = 0.0
+                for k in _walk(lines, s0, s2, rec.du[n][i] > 0):
+                    c = c + (-L[k] if rec.du[n][i] > 0 else L[k])
+                un = u[slot] + du + c
+                rows.append(int(i))
+                vals.append(P0[s2] + un * T[s2])
+                slots.append(slot)
+                us.append(un)
+            if rows:
+                u = u.index_put((torch.as_tensor(slots),), torch.stack(us))
+                moved = moved.index_copy(0, torch.as_tensor(rows), torch.stack(vals))
         acc = torch.as_tensor(rec.accepted[n])
         x = torch.where(acc[:, None], moved, x)
     return x
@@ -171,12 +235,13 @@ def mesh_gradient(wl, rec: Record):
     return float(L.detach()), g.numpy()
 
 
-def mesh_gradient_fd(wl, rec: Record, eps=1e-6):
-    """Central differences of replay + loss in every vertex coordinate."""
+def mesh_gradient_fd(wl, rec: Record, eps=1e-6, verts=None):
+    """Central differences of replay + loss in the coordinates of the given
+    vertices (default: all); other rows are left 0."""
     V0 = wl.geoms[0].mesh.vert.copy()
     g = np.zeros_like(V0)
     with torch.no_grad():
-        for v in range(V0.shape[0]):
+        for v in (range(V0.shape[0]) if verts is None else verts):
             for c in range(3):
                 Vp, Vm = V0.copy(), V0.copy()
                 Vp[v, c] += eps

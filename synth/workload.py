@@ -536,6 +536,21 @@ def solid_geometry(rng, n_target: float, jitter=0.3, k=2):
     return geom, b, kind
 
 
+def cylinder_workload(radius=0.5, height=1.0, segments=24, dx=0.08, jitter=0.3, seed=6, k=2,
+                      move_mask=ALL_MOVING, name=None) -> Workload:
+    """Upright cylinder (two closed rim loops of `segments` feature segments)
+    filled like the batch's solids: volume lattice, per-facet-plane surface
+    lattices, feature particles along the rims. No singular points."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mesh = M.cylinder(radius, height, segments)
+    geom = _make_geom(mesh, dx, k)
+    b = _Builder()
+    _convex_volume_particles(b, mesh, dx, rng, jitter)
+    _surface_particles_planar(b, mesh, dx, rng, jitter)
+    _feature_particles(b, mesh, dx, rng, jitter)
+    return _finish(name or f"cylinder{segments}_dx{dx:g}", [(geom, b)], move_mask, seed, {"dx": dx})
+
+
 def split_geometry(wl: Workload, g: int) -> Workload:
     """Geometry g of a batch as a workload of its own (same particles, ids in
     batch order, owner and feature indices re-based)."""

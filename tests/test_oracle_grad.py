@@ -105,3 +105,36 @@ def test_mesh_gradient_is_consistent_with_rigid_motions():
     torque = torch.cross(V.detach(), gV, dim=1).sum(0) + torch.cross(x0.detach()[mov], gx[mov], dim=1).sum(0)
     assert float(torch.linalg.norm(force)) <= 1e-9 * scale
     assert float(torch.linalg.norm(torque)) <= 1e-9 * scale
+
+
+@pytest.fixture(scope="module")
+def cylinder():
+    """Cylinder with every class moving: feature particles walk along the two
+    24-segment rim loops and some cross segment ends."""
+    wl = W.cylinder_workload(dx=0.08)
+    rec = G.record(wl, 6)
+    return wl, rec
+
+
+def test_feature_walks_cross_segments(cylinder):
+    wl, rec = cylinder
+    fs = np.array(rec.feat_seg)
+    assert (fs[1:] != fs[:-1]).any()
+    f = wl.tag == W.FEATURE
+    assert all(a[f].any() for a in rec.accepted)
+
+
+def test_replay_with_moving_features_reproduces_the_forward(cylinder):
+    wl, rec = cylinder
+    V = torch.as_tensor(wl.geoms[0].mesh.vert)
+    x = G.replay(wl, V, rec).numpy()
+    np.testing.assert_allclose(x, rec.pos32[-1].astype(np.float64), rtol=0, atol=1e-6)
+
+
+def test_mesh_gradient_with_moving_features_matches_central_differences(cylinder):
+    wl, rec = cylinder
+    _, g = G.mesh_gradient(wl, rec)
+    rows = list(range(0, len(wl.geoms[0].mesh.vert), 5))
+    fd = G.mesh_gradient_fd(wl, rec, eps=1e-6, verts=rows)
+    assert np.abs(g[rows]).max() > 1e-3
+    np.testing.assert_allclose(g[rows], fd[rows], rtol=0, atol=1e-6 * np.abs(g).max())
