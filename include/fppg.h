@@ -345,16 +345,20 @@ fppg_status fppg_project_record(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
  * Differentiation of a relaxation run with respect to the mesh vertices (an
  * addition to the paper's method; section 3.3 defines the step that is
  * differentiated). The discrete decisions of every step are frozen at their
- * forward values: dt^2, the owner facet before and after the step, acceptance
- * of the move, the neighbour sets. Between decisions one step is the smooth map
+ * forward values: dt^2, the owner facet (feature segment) before and after the
+ * step, acceptance of the move, the direction of a feature walk, the neighbour
+ * sets. Between decisions one step is the smooth map
  *   y  = x + dt^2 P_o a(x)        P_o = I - n_o n_o^T (surface), I (volume)
  *   x' = y - ((y - A_t) . n_t) n_t  accepted surface move onto facet t = owner_next
  *   x' = y                        accepted volume move
+ *   x' = P0_s' + u' t_s',  u' = t_s.(x - P0_s) + dt^2 a(x).t_s + c
+ *                                 accepted feature move from segment s to s', with
+ *                                 c = -(lengths walked off forwards) + (lengths
+ *                                 walked onto backwards), t = (P1 - P0)/|P1 - P0|
  *   x' = x                        reverted move, or a particle that does not move
- * with n = (B - A) x (C - A) / |.| of facet (A, B, C). Particles that do not
- * move are functions of the mesh: a singular point is its vertex (owner[i] =
- * its global vertex id), a feature particle the point at arc length u of its
- * segment P0 + u (P1 - P0)/|P1 - P0| (feature particles must not move here).
+ * with n = (B - A) x (C - A) / |.| of facet (A, B, C). Singular points are their
+ * vertex (owner[i] = its global vertex id); every feature particle starts at
+ * arc length u of its segment, P0 + u t.
  *
  * Vertex adjoints are accumulated in vbar_fixed [3 * n_vert] int64 (device,
  * zeroed by the caller) as signed fixed point with 2^-40 units by integer
@@ -378,30 +382,33 @@ fppg_status fppg_uniformity_loss(fppg_ctx* ctx, const fppg_geom* geom, int64_t n
                                  double* out, float* grad, void* ws, size_t ws_bytes, void* stream);
 
 /*
- * Adjoint of one step through the projection and the tangential
- * displacement. All arrays in the sorted order of that step: pos and owner
- * entering it (after fppg_build_cells), owner_next and accepted after
- * fppg_project_record, accel and amax written by fppg_relax_step. Given
- * xbar_next = dL/dx', writes
- *   ybar_i = dt^2 P_o (dx'/dy)^T xbar_next_i   (0 unless accepted): the adjoint of a_i
- *   xbar_i = (dx'/dy)^T xbar_next_i if accepted, else xbar_next_i
- * and adds the facet-vertex terms to vbar_fixed. The caller completes
- * dL/dx = xbar + J^T ybar with fppg_relax_hvp(transpose = 1). xbar must not
- * alias xbar_next. Returns FPPG_E_UNSUPPORTED if move_mask has the feature bit.
+ * Adjoint of one step through the projection, the tangential displacement
+ * and the feature walk. Particle arrays in the sorted order of that step: pos
+ * and owner entering it (after fppg_build_cells), owner_next and accepted after
+ * fppg_project_record, accel and amax written by fppg_relax_step; feature
+ * tables by slot: fseg_before (segments entering the step), fseg_after and
+ * fu_after (after it), n_feat slots (may be NULL if 0). Given xbar_next =
+ * dL/dx', writes
+ *   ybar_i = dL/da_i through this step (0 unless accepted)
+ *   xbar_i = the direct part of dL/dx_i (xbar_next_i if not accepted)
+ * and adds the facet- and segment-vertex terms to vbar_fixed. The caller
+ * completes dL/dx = xbar + J^T ybar with fppg_relax_hvp(transpose = 1). xbar
+ * must not alias xbar_next.
  */
 fppg_status fppg_step_adjoint(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, const float* pos,
                               const uint8_t* accepted, const int32_t* owner, const int32_t* owner_next,
-                              const float* accel, const float* amax, uint32_t move_mask,
-                              const float* xbar_next, float* ybar, float* xbar, int64_t* vbar_fixed,
-                              void* stream);
+                              const float* accel, const float* amax, const int32_t* fseg_before,
+                              const int32_t* fseg_after, const double* fu_after, int32_t n_feat,
+                              uint32_t move_mask, const float* xbar_next, float* ybar, float* xbar,
+                              int64_t* vbar_fixed, void* stream);
 
 /*
- * Vertex terms of the particles that do not move: for each such particle
- * with adjoint xbar_i, a singular point adds xbar_i to vertex owner[i]; a
- * feature particle (slot owner[i], segment feat_seg[slot] with end vertices
- * from fppg_geom_desc.seg_vert, arc length feat_u[slot]) adds
- * (u/L)(I - t t^T) xbar_i to P1 and the rest of xbar_i to P0. Volume and
- * fixed particles do not depend on the mesh.
+ * Vertex terms of the initial positions that are functions of the mesh: for
+ * each particle with adjoint xbar_i, a singular point adds xbar_i to vertex
+ * owner[i]; a feature particle (slot owner[i], segment feat_seg[slot] of the
+ * initial state with end vertices from fppg_geom_desc.seg_vert, arc length
+ * feat_u[slot]) adds (u/L)(I - t t^T) xbar_i to P1 and the rest of xbar_i to
+ * P0. Surface, volume and fixed particles start at given positions.
  */
 fppg_status fppg_fixed_adjoint(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, const float* pos,
                                const int32_t* owner, const int32_t* feat_seg, const double* feat_u,

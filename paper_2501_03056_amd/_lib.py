@@ -65,7 +65,8 @@ _SIGS = {
     "fppg_displace": (c_int32, [_P, _P, c_int64, _P, _P, _P, c_int32, c_uint32, _P, c_float, _P, _P]),
     "fppg_project_record": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, _P, c_int32, c_uint32, _P, _P, _P]),
     "fppg_uniformity_loss": (c_int32, [_P, _P, c_int64, _P, _P, c_uint32, c_double, _P, _P, _P, c_size_t, _P]),
-    "fppg_step_adjoint": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, _P, _P, c_uint32, _P, _P, _P, _P, _P]),
+    "fppg_step_adjoint": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, c_int32, c_uint32,
+                                    _P, _P, _P, _P, _P]),
     "fppg_fixed_adjoint": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, c_int32, c_uint32, _P, _P, _P]),
     "fppg_vec_permute": (c_int32, [_P, c_int64, _P, _P, c_int32, _P, _P]),
     "fppg_fixed_to_double": (c_int32, [_P, c_int64, _P, _P, _P]),

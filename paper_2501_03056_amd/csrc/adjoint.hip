@@ -134,7 +134,9 @@ __global__ __launch_bounds__(kBlock) void k_step_adjoint(
     const float4* __restrict__ pos, const uint8_t* __restrict__ accepted, const int* __restrict__ owner,
     const int* __restrict__ owner_next, const float4* __restrict__ accel, const float* __restrict__ amax, int n,
     int n_tri, const GeomDev* __restrict__ geoms, int n_geom, const FacetDev* __restrict__ facets,
-    const int4* __restrict__ tri_vert, uint32_t move_mask, const float4* __restrict__ xbar_next,
+    const int4* __restrict__ tri_vert, const int* __restrict__ fseg_before, const int* __restrict__ fseg_after,
+    const double* __restrict__ fu_after, int n_feat, int n_seg, const SegDev* __restrict__ segs,
+    const int2* __restrict__ seg_vert, uint32_t move_mask, const float4* __restrict__ xbar_next,
     float4* __restrict__ ybar, float4* __restrict__ xbar, unsigned long long* __restrict__ vbar) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -144,10 +146,63 @@ __global__ __launch_bounds__(kBlock) void k_step_adjoint(
   const bool reverted = accepted[i] == 0;
   float4 yb_out = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   float4 xb_out = xb;
-  if (is_moving(tag, move_mask) && !reverted && (tag == FPPG_TAG_VOLUME || tag == FPPG_TAG_SURFACE)) {
+  if (is_moving(tag, move_mask) && !reverted) {
     const int g = min(geom_of(p.w), n_geom - 1);
     const double tau = amax[g] > 0.0f ? (double(geoms[g].h) * 0.0625) / double(amax[g]) : 0.0;
-    if (tag == FPPG_TAG_VOLUME) {
+    if (tag == FPPG_TAG_FEATURE) {
+      const int slot = owner[i];
+      const int s0 = (slot >= 0 && slot < n_feat) ? fseg_before[slot] : -1;
+      const int s2 = (slot >= 0 && slot < n_feat) ? fseg_after[slot] : -1;
+      if (s0 >= 0 && s0 < n_seg && s2 >= 0 && s2 < n_seg) {
+        const SegDev A = segs[s0], B = segs[s2];
+        const float4 a4 = accel[i];
+        const double a[3] = {a4.x, a4.y, a4.z};
+        // x' = P0_s2 + u' t_s2 with u' = u + dt^2 a.t_s0 + c and u = t_s0.(x - P0_s0)
+        const double gu = B.t[0] * xb.x + B.t[1] * xb.y + B.t[2] * xb.z;   // adjoint of u'
+        const double u2 = fu_after[slot];
+        {
+          const double w[3] = {u2 * xb.x, u2 * xb.y, u2 * xb.z};             // adjoint of t_s2
+          const double wt = w[0] * B.t[0] + w[1] * B.t[1] + w[2] * B.t[2];
+          double d[3];
+          for (int q = 0; q < 3; ++q) d[q] = (w[q] - wt * B.t[q]) / B.len;
+          const int2 sv = seg_vert[s2];
+          fix_add3(vbar, sv.y, d[0], d[1], d[2]);
+          fix_add3(vbar, sv.x, xb.x - d[0], xb.y - d[1], xb.z - d[2]);
+        }
+        {
+          // t_s0 through du = dt^2 a.t_s0, and P0_s0 through u = t_s0.(x - P0_s0)
+          const double w[3] = {tau * gu * a[0], tau * gu * a[1], tau * gu * a[2]};
+          const double wt = w[0] * A.t[0] + w[1] * A.t[1] + w[2] * A.t[2];
+          double d[3];
+          for (int q = 0; q < 3; ++q) d[q] = (w[q] - wt * A.t[q]) / A.len;
+          const int2 sv = seg_vert[s0];
+          fix_add3(vbar, sv.y, d[0], d[1], d[2]);
+          fix_add3(vbar, sv.x, -d[0] - gu * A.t[0], -d[1] - gu * A.t[1], -d[2] - gu * A.t[2]);
+        }
+        if (s2 != s0) {
+          // the walk's direction, recomputed as the forward computed du
+          const float am = amax[g];
+          const float tauf = am > 0.0f ? (geoms[g].h * 0.0625f) / am : 0.0f;
+          const double du = double(tauf * a4.x) * A.t[0] + double(tauf * a4.y) * A.t[1] + double(tauf * a4.z) * A.t[2];
+          const bool fwd = du > 0.0;
+          int k = s0;
+          for (int guard = 0; k != s2 && guard <= A.hi - A.lo; ++guard) {
+            if (!fwd) k = k > A.lo ? k - 1 : (A.closed ? A.hi - 1 : -1);
+            if (k < 0) break;
+            // u' -= L_k (walked off forwards) or += L_k (walked onto backwards); dL_k = t_k.(dP1 - dP0)
+            const double sg = fwd ? -gu : gu;
+            const SegDev C = segs[k];
+            const int2 sv = seg_vert[k];
+            fix_add3(vbar, sv.y, sg * C.t[0], sg * C.t[1], sg * C.t[2]);
+            fix_add3(vbar, sv.x, -sg * C.t[0], -sg * C.t[1], -sg * C.t[2]);
+            if (fwd) k = k + 1 < A.hi ? k + 1 : (A.closed ? A.lo : -1);
+            if (k < 0) break;
+          }
+        }
+        yb_out = make_float4(float(tau * gu * A.t[0]), float(tau * gu * A.t[1]), float(tau * gu * A.t[2]), 0.0f);
+        xb_out = make_float4(float(gu * A.t[0]), float(gu * A.t[1]), float(gu * A.t[2]), 0.0f);
+      }
+    } else if (tag == FPPG_TAG_VOLUME) {
       yb_out = make_float4(float(tau * xb.x), float(tau * xb.y), float(tau * xb.z), 0.0f);
     } else {
       const int o = owner[i], t = owner_next[i];
@@ -199,7 +254,8 @@ __global__ __launch_bounds__(kBlock) void k_fixed_adjoint(const float4* __restri
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int tag = tag_of(pos[i].w);
-  if (is_moving(tag, move_mask)) return;
+  // singular points never move; every feature particle starts on its segment
+  if (tag != FPPG_TAG_SINGULAR && tag != FPPG_TAG_FEATURE) return;
   const float4 xb = xbar[i];
   if (tag == FPPG_TAG_SINGULAR) {
     const int v = owner[i];
@@ -280,13 +336,14 @@ extern "C" fppg_status fppg_uniformity_loss(fppg_ctx* ctx, const fppg_geom* geom
 
 extern "C" fppg_status fppg_step_adjoint(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, const float* pos,
                                          const uint8_t* accepted, const int32_t* owner, const int32_t* owner_next,
-                                         const float* accel, const float* amax, uint32_t move_mask,
-                                         const float* xbar_next, float* ybar, float* xbar, int64_t* vbar_fixed,
-                                         void* stream) {
+                                         const float* accel, const float* amax, const int32_t* fseg_before,
+                                         const int32_t* fseg_after, const double* fu_after, int32_t n_feat,
+                                         uint32_t move_mask, const float* xbar_next, float* ybar, float* xbar,
+                                         int64_t* vbar_fixed, void* stream) {
   if (!ctx || !geom) return fail(ctx, FPPG_E_ARG, "null ctx/geom");
   if (n != geom->n_part) return fail(ctx, FPPG_E_ARG, "n differs from the geometry's particle count");
-  if ((move_mask >> FPPG_TAG_FEATURE) & 1u)
-    return fail(ctx, FPPG_E_UNSUPPORTED, "step_adjoint holds feature particles fixed (clear bit 1 of move_mask)");
+  if (n_feat < 0 || (n_feat > 0 && (!fseg_before || !fseg_after || !fu_after)))
+    return fail(ctx, FPPG_E_ARG, "bad feature tables");
   if (n > 0 && (!pos || !accepted || !owner || !owner_next || !accel || !amax || !xbar_next || !ybar || !xbar ||
                 !vbar_fixed))
     return fail(ctx, FPPG_E_ARG, "null argument");
@@ -298,7 +355,8 @@ extern "C" fppg_status fppg_step_adjoint(fppg_ctx* ctx, const fppg_geom* geom, i
   k_step_adjoint<<<grid_for(n), kBlock, 0, static_cast<hipStream_t>(stream)>>>(
       reinterpret_cast<const float4*>(pos), accepted, owner, owner_next,
       reinterpret_cast<const float4*>(accel), amax, int(n), int(geom->n_tri), geom->d_geom, geom->n_geom,
-      geom->d_facet, geom->d_tri_vert, move_mask, reinterpret_cast<const float4*>(xbar_next),
+      geom->d_facet, geom->d_tri_vert, fseg_before, fseg_after, fu_after, n_feat, int(geom->n_seg), geom->d_seg,
+      geom->d_seg_vert, move_mask, reinterpret_cast<const float4*>(xbar_next),
       reinterpret_cast<float4*>(ybar), reinterpret_cast<float4*>(xbar),
       reinterpret_cast<unsigned long long*>(vbar_fixed));
   FPPG_HIP(ctx, hipGetLastError());

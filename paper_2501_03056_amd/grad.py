@@ -18,8 +18,10 @@ Reverse sweep with checkpointed recomputation:
               fppg_step_adjoint -> ybar (adjoint of a), xbar, facet-vertex terms
               xbar += J^T ybar                                   fppg_relax_hvp
               back to id order                                   fppg_vec_permute
-  fixed     the particles that do not move (singular points, feature
-            particles) add their adjoints to their vertices: fppg_fixed_adjoint.
+  initial   singular points and the initial feature positions add their
+            adjoints to their vertices: fppg_fixed_adjoint.
+Checkpoints and per-step tapes include the feature table (segment and arc
+length per slot), which the steps update in place.
 All arithmetic runs in the library's kernels; this module marshals.
 """
 from __future__ import annotations
@@ -43,7 +45,13 @@ def lattice_density(dx: float, h: float) -> float:
 
 
 class _Tape:
-    __slots__ = ("pos", "id", "owner", "cells", "accel", "amax", "owner_next", "accepted")
+    __slots__ = ("pos", "id", "owner", "cells", "accel", "amax", "owner_next", "accepted", "fseg", "fseg_next",
+                 "fu_next")
+
+
+def _restore(r, state):
+    for dst, src in zip((r.pos, r.id, r.owner, r.feat_seg, r.feat_u), state):
+        dst.copy_(src)
 
 
 def _lib_call(r, name, *args):
@@ -64,32 +72,31 @@ class Tape:
     final state, the loss and its gradient with respect to the final positions
     (by particle id)."""
 
-    def __init__(self, K, every, ckpts, final, loss, xbar_id):
+    def __init__(self, K, every, ckpts, final, loss, xbar_id, feat0):
         self.K, self.every, self.ckpts, self.final = K, every, ckpts, final
-        self.loss, self.xbar_id = loss, xbar_id
+        self.loss, self.xbar_id, self.feat0 = loss, xbar_id, feat0
 
 
 def forward(r, K: int, rho0: float, checkpoint_every: int = 10) -> Tape:
     """K relaxation steps from the relaxer's state keeping checkpoints, then
     the uniformity loss of the final state and dL/dx (device, by id)."""
-    if (r.move_mask >> 1) & 1:
-        raise ValueError("mesh gradients hold feature particles fixed: clear bit 1 of move_mask")
     if K < 0 or checkpoint_every < 1:
         raise ValueError("K >= 0 and checkpoint_every >= 1 required")
     if r.ws_bytes < 8 * (r.n + 2 * ((r.n + 255) // 256)) + 64:
         raise ValueError("workspace too small for the loss")
     ckpts = []
+    feat0 = (r.feat_seg.clone(), r.feat_u.clone())
     for step in range(K):
         if step % checkpoint_every == 0:
-            ckpts.append((step, r.pos.clone(), r.id.clone(), r.owner.clone()))
+            ckpts.append((step, r.pos.clone(), r.id.clone(), r.owner.clone(), r.feat_seg.clone(), r.feat_u.clone()))
         r.step(keep_accel=False)
-    final = (r.pos.clone(), r.id.clone(), r.owner.clone())
+    final = (r.pos.clone(), r.id.clone(), r.owner.clone(), r.feat_seg.clone(), r.feat_u.clone())
     r.build_cells()
     g = torch.zeros((r.n, 4), dtype=torch.float32, device=r.dev)
     out = uniformity_loss(r, rho0, g)
     xbar_id = torch.zeros_like(g)
     _lib_call(r, "fppg_vec_permute", r.n, ptr(g), ptr(r.id), 1, ptr(xbar_id), r.stream)
-    return Tape(K, checkpoint_every, ckpts, final, out, xbar_id)
+    return Tape(K, checkpoint_every, ckpts, final, out, xbar_id, feat0)
 
 
 def backward(r, tape: Tape, n_vert: int | None = None) -> torch.Tensor:
@@ -106,27 +113,27 @@ def backward(r, tape: Tape, n_vert: int | None = None) -> torch.Tensor:
     first = None
     ckpts = tape.ckpts
     for ci in range(len(ckpts) - 1, -1, -1):
-        s0, pos, ids, own = ckpts[ci]
+        s0, pos, ids, own, fseg, fu = ckpts[ci]
         s1 = ckpts[ci + 1][0] if ci + 1 < len(ckpts) else tape.K
-        r.pos.copy_(pos)
-        r.id.copy_(ids)
-        r.owner.copy_(own)
+        _restore(r, (pos, ids, own, fseg, fu))
         tapes = []
         for _ in range(s0, s1):
             t = _Tape()
             r.build_cells()
             t.pos, t.id, t.owner, t.cells = r.pos.clone(), r.id.clone(), r.owner.clone(), r.cell_start.clone()
+            t.fseg = r.feat_seg.clone()
             r.relax_step(keep_accel=True)
             t.accel, t.amax = r.accel.clone(), r.amax.clone()
             t.accepted = torch.empty(n, dtype=torch.uint8, device=dev)
             r.project_record(t.accepted)
             t.owner_next = r.owner.clone()
+            t.fseg_next, t.fu_next = r.feat_seg.clone(), r.feat_u.clone()
             tapes.append(t)
         for t in reversed(tapes):
             _lib_call(r, "fppg_vec_permute", n, ptr(xbar_id), ptr(t.id), 0, ptr(xb_next), r.stream)
             _lib_call(r, "fppg_step_adjoint", r.geom.handle, n, ptr(t.pos), ptr(t.accepted), ptr(t.owner),
-                      ptr(t.owner_next), ptr(t.accel), ptr(t.amax), r.move_mask, ptr(xb_next), ptr(yb), ptr(xb),
-                      ptr(vbar), r.stream)
+                      ptr(t.owner_next), ptr(t.accel), ptr(t.amax), ptr(t.fseg), ptr(t.fseg_next), ptr(t.fu_next),
+                      r.n_feat, r.move_mask, ptr(xb_next), ptr(yb), ptr(xb), ptr(vbar), r.stream)
             _lib_call(r, "fppg_relax_hvp", r.geom.handle, n, ptr(t.pos), ptr(t.cells), r.move_mask, 1,
                       ptr(yb), ptr(jt), r.stream)
             r.axpby(1.0, jt, 1.0, xb)
@@ -137,19 +144,15 @@ def backward(r, tape: Tape, n_vert: int | None = None) -> torch.Tensor:
     if first is not None:
         pos0, own0, ids0 = first.pos, first.owner, first.id
     else:
-        r.pos.copy_(tape.final[0])
-        r.id.copy_(tape.final[1])
-        r.owner.copy_(tape.final[2])
+        _restore(r, tape.final)
         r.build_cells()
         pos0, own0, ids0 = r.pos, r.owner, r.id
     _lib_call(r, "fppg_vec_permute", n, ptr(xbar_id), ptr(ids0), 0, ptr(xb), r.stream)
-    _lib_call(r, "fppg_fixed_adjoint", r.geom.handle, n, ptr(pos0), ptr(own0), ptr(r.feat_seg), ptr(r.feat_u),
-              r.n_feat, r.move_mask, ptr(xb), ptr(vbar), r.stream)
+    _lib_call(r, "fppg_fixed_adjoint", r.geom.handle, n, ptr(pos0), ptr(own0), ptr(tape.feat0[0]),
+              ptr(tape.feat0[1]), r.n_feat, r.move_mask, ptr(xb), ptr(vbar), r.stream)
     vd = torch.empty(3 * n_vert, dtype=torch.float64, device=dev)
     _lib_call(r, "fppg_fixed_to_double", 3 * n_vert, ptr(vbar), ptr(vd), r.stream)
-    r.pos.copy_(tape.final[0])
-    r.id.copy_(tape.final[1])
-    r.owner.copy_(tape.final[2])
+    _restore(r, tape.final)
     return vd.view(n_vert, 3)
 
 

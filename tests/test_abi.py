@@ -40,7 +40,8 @@ def test_host_side_validation_without_gpu():
     assert L.fppg_debug_neighbors(nul, nul, 0, nul, nul, nul, nul, 0, nul) == _lib.E_ARG
     assert L.fppg_project_record(nul, nul, 0, nul, nul, nul, nul, nul, 0, 0, nul, nul, nul) == _lib.E_ARG
     assert L.fppg_uniformity_loss(nul, nul, 0, nul, nul, 0, 1.0, nul, nul, nul, 0, nul) == _lib.E_ARG
-    assert L.fppg_step_adjoint(nul, nul, 0, nul, nul, nul, nul, nul, nul, 0, nul, nul, nul, nul, nul) == _lib.E_ARG
+    assert L.fppg_step_adjoint(nul, nul, 0, nul, nul, nul, nul, nul, nul, nul, nul, nul, 0, 0, nul, nul, nul, nul,
+                               nul) == _lib.E_ARG
     assert L.fppg_fixed_adjoint(nul, nul, 0, nul, nul, nul, nul, 0, 0, nul, nul, nul) == _lib.E_ARG
     assert L.fppg_vec_permute(nul, 0, nul, nul, 0, nul, nul) == _lib.E_ARG
     assert L.fppg_fixed_to_double(nul, 0, nul, nul, nul) == _lib.E_ARG

@@ -279,3 +279,60 @@ def test_nonfinite_input_is_flagged_and_held():
     assert r.read_status() & 2          # FPPG_S_NONFINITE_POS
     pos, _, _, _ = r.host_state()
     assert np.isnan(pos[5]).all() and np.isfinite(np.delete(pos, 5, 0)).all()
+
+
+# --------------------------------------------------------------------------- degenerate inputs
+
+def test_empty_workload_steps_cleanly():
+    from synth import meshes as M
+    wl = synth.workload.custom_workload(M.cube(), 0.05, np.zeros((0, 3)), np.zeros(0, np.int32))
+    r = _relaxer(wl)
+    for _ in range(2):
+        r.step()
+    assert r.read_status() == 0
+    assert not r.counters.cpu().numpy().any()
+    assert r.cell_start.cpu().numpy().max() == 0
+
+
+def test_nothing_moves_when_the_move_mask_is_empty():
+    wl = synth.cube_workload(n=8, seed=4, move_mask=0)
+    r = _relaxer(wl)
+    r.build_cells()
+    before = r.pos.clone()
+    r.relax_step()
+    assert float(r.amax.cpu()[0]) == 0.0
+    r.project()
+    assert torch.equal(before, r.pos)
+    assert r.read_status() == 0
+
+
+def test_isolated_and_coincident_particles():
+    """A lone particle feels nothing and does not move; two particles at the
+    same point exert no force on each other (r = 0) but both feel a third."""
+    from synth import meshes as M
+    dx = 0.05
+    p = np.array([[0.2, 0.2, 0.2], [0.6, 0.6, 0.6], [0.6, 0.6, 0.6], [0.62, 0.6, 0.6]])
+    wl = synth.workload.custom_workload(M.cube(), dx, p, np.full(4, synth.VOLUME))
+    r = _relaxer(wl)
+    r.build_cells()
+    r.relax_step(count_pairs=True)
+    acc = r.by_id(r.accel)
+    a64, S, cnt = oforce.accel(wl)
+    assert np.array_equal(acc[:, 3].astype(np.int64), cnt) and cnt.tolist() == [0, 2, 2, 2]
+    assert not acc[0, :3].any()
+    err = np.linalg.norm(acc[:, :3].astype(np.float64) - a64, axis=1)
+    assert np.all(err <= 1e-5 * np.maximum(S, 1e-30))
+    v = np.zeros((4, 4), np.float32)
+    v[:, :3] = np.random.Generator(np.random.PCG64(3)).normal(size=(4, 3))
+    ids = r.id.cpu().numpy()
+    vt = torch.from_numpy(v[ids]).cuda()
+    for transpose in (False, True):
+        out = r.by_id(r.hvp(vt, transpose=transpose))[:, :3].astype(np.float64)
+        vd = v[:, :3].astype(np.float64)
+        ref = ohvp.vjp(wl, vd) if transpose else ohvp.jvp(wl, vd)
+        assert np.all(np.isfinite(out))
+        assert np.abs(out - ref).max() <= 1e-4 * np.abs(ref).max()
+    r.project()
+    pos, _, _, _ = r.host_state()
+    assert np.array_equal(pos[0], wl.pos[0])          # lone particle: a = 0
+    assert r.read_status() == 0
