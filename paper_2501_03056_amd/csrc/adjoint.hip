@@ -350,7 +350,7 @@ extern "C" fppg_status fppg_step_adjoint(fppg_ctx* ctx, const fppg_geom* geom, i
   if (!aligned(pos, 16) || !aligned(accel, 16) || !aligned(xbar_next, 16) ||
       !aligned(ybar, 16) || !aligned(xbar, 16))
     return fail(ctx, FPPG_E_ARG, "misaligned argument");
-  if (xbar == xbar_next) return fail(ctx, FPPG_E_ARG, "xbar must not alias xbar_next");
+  if (n > 0 && xbar == xbar_next) return fail(ctx, FPPG_E_ARG, "xbar must not alias xbar_next");
   if (n == 0) return FPPG_OK;
   k_step_adjoint<<<grid_for(n), kBlock, 0, static_cast<hipStream_t>(stream)>>>(
       reinterpret_cast<const float4*>(pos), accepted, owner, owner_next,
@@ -386,7 +386,7 @@ extern "C" fppg_status fppg_vec_permute(fppg_ctx* ctx, int64_t n, const float* s
   if (!ctx) return FPPG_E_ARG;
   if (n < 0 || n >= (int64_t(1) << 31)) return fail(ctx, FPPG_E_ARG, "n out of range");
   if (n > 0 && (!src || !index || !dst)) return fail(ctx, FPPG_E_ARG, "null argument");
-  if (!aligned(src, 16) || !aligned(dst, 16) || src == dst) return fail(ctx, FPPG_E_ARG, "misaligned or aliased");
+  if (!aligned(src, 16) || !aligned(dst, 16) || (n > 0 && src == dst)) return fail(ctx, FPPG_E_ARG, "misaligned or aliased");
   if (n == 0) return FPPG_OK;
   k_permute<<<grid_for(n), kBlock, 0, static_cast<hipStream_t>(stream)>>>(
       reinterpret_cast<const float4*>(src), index, int(n), scatter ? 1 : 0, reinterpret_cast<float4*>(dst));

@@ -198,7 +198,7 @@ extern "C" fppg_status fppg_build_cells(fppg_ctx* ctx, const fppg_geom* geom, in
   if (!cell_start || !ws) return fail(ctx, FPPG_E_ARG, "null cell_start/ws");
   if (!aligned(pos_in, 16) || !aligned(pos_out, 16) || !aligned(ws, 256))
     return fail(ctx, FPPG_E_ARG, "pos must be 16-byte and ws 256-byte aligned");
-  if (pos_in == pos_out || id_in == id_out || owner_in == owner_out)
+  if (n > 0 && (pos_in == pos_out || id_in == id_out || owner_in == owner_out))
     return fail(ctx, FPPG_E_ARG, "build_cells output must not alias its input");
   const WsLayout L = ws_layout(geom, n);
   if (ws_bytes < L.build_end) return fail(ctx, FPPG_E_WORKSPACE, "workspace too small for build_cells");

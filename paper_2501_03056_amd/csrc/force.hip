@@ -22,7 +22,9 @@ __global__ void k_zero_f32(float* __restrict__ a, int n) {
 // One source: K-less pair term (1 - r/2h)^3 r_ij if j is a source of i.
 // RANKED: check rank(tag_j) <= rank(tag_i) as tag_j <= T (T = rank, or 7 for
 // volume receivers which take every class). The receiver itself contributes
-// r = 0, so it needs no test (the count subtracts it).
+// r = 0, so it needs no test (the count subtracts it). No clamp of 1 - r/2h at
+// 0: a pair that passes the predicate has r < 2h up to the rounding of the
+// square root, so the term is at worst -(2^-23)^3 instead of 0.
 template <bool RANKED, bool COUNT>
 __device__ __forceinline__ void add_pair(const float4 p, const float4 q, float rc2, float inv2h, uint32_t T,
                                          float& ax, float& ay, float& az, float& cnt) {
@@ -30,7 +32,7 @@ __device__ __forceinline__ void add_pair(const float4 p, const float4 q, float r
   const float d2 = pair_d2(dx, dy, dz);
   bool src = d2 < rc2;
   if (RANKED) src = src & ((__float_as_uint(q.w) & 7u) <= T);
-  const float t = fmaxf(fmaf(-__builtin_amdgcn_sqrtf(d2), inv2h, 1.0f), 0.0f);
+  const float t = fmaf(-__builtin_amdgcn_sqrtf(d2), inv2h, 1.0f);
   const float w = src ? t * t * t : 0.0f;
   ax = fmaf(w, dx, ax);
   ay = fmaf(w, dy, ay);
@@ -184,7 +186,7 @@ extern "C" fppg_status fppg_relax_step(fppg_ctx* ctx, const fppg_geom* geom, int
                                        float* amax, float* disp, void* ws, size_t ws_bytes, void* stream) {
   fppg_status st = check_common(ctx, geom, n, pos, cell_start);
   if (st != FPPG_OK) return st;
-  if (!amax || !disp || !owner) return fail(ctx, FPPG_E_ARG, "null amax/disp/owner");
+  if (!amax || (n > 0 && (!disp || !owner))) return fail(ctx, FPPG_E_ARG, "null amax/disp/owner");
   if (n_feat < 0 || (n_feat > 0 && !feat_seg)) return fail(ctx, FPPG_E_ARG, "bad feature table");
   if (!aligned(disp, 16) || (accel && !aligned(accel, 16))) return fail(ctx, FPPG_E_ARG, "accel/disp must be 16-byte aligned");
   const WsLayout L = ws_layout(geom, n);

@@ -72,7 +72,8 @@ __device__ __forceinline__ void for_each_source(const Stencil s, const GeomDev& 
                                                 const float4* __restrict__ pos, F&& f) {
   for_each_row<K>(s, G, cs, [&](int j0, int j1) {
     int j = j0;
-    for (; j + 4 <= j1; j += 4) {
+    const int j1m = j1 - 3;
+    for (; j < j1m; j += 4) {
       const float4 q0 = pos[j], q1 = pos[j + 1], q2 = pos[j + 2], q3 = pos[j + 3];
       f(j, q0);
       f(j + 1, q1);

@@ -1,15 +1,21 @@
-"""Autotuning of the particle-cell layout.
+"""Autotuning of the particle-cell layout and of the launch mode.
 
-The only layout choice with a large effect is the stencil half-width k of the
-particle cells (cell edge (2h/k)(1 + 2^-8)): k = 1 visits fewer, longer
-source rows, k = 2 visits fewer candidates per receiver (about 190 instead of
-370 after culling) in more rows; which is faster depends on the particle
-count per cell and on how uniform the wavefronts are. `autotune` times a few
-real iterations for each candidate and caches the winner in a JSON file keyed
-by device, particle-count bucket and geometry count. The neighbour sets do not
-depend on k (bit-exact either way); the particle order and hence the
-summation order do, so forces for different k agree to rounding (well inside
-the 1e-5 bar), and for a fixed k every run is bitwise reproducible.
+Two choices have a large effect. The stencil half-width k of the particle
+cells (cell edge (2h/k)(1 + 2^-8)): k = 1 visits fewer, longer source rows,
+k = 2 fewer candidates per receiver (about 190 instead of 370 after culling)
+in more rows; which is faster depends on the particle count per cell and on
+how uniform the wavefronts are. And the launch mode: eager launches from the
+host, or iterations replayed from a HIP graph, which removes the host's
+launch latency (decisive for small workloads whose kernels last
+microseconds) but, measured on this runtime, adds time per node for large
+ones (and on the runtime measured here, for small ones too: graph replay of
+the 17.6k-particle cube costs 0.107 ms per iteration against 0.095 ms eager).
+`autotune` times real iterations for each (k, mode) and caches the
+winner in a JSON file keyed by device, particle-count bucket and geometry
+count. The neighbour sets do not depend on k (bit-exact either way); the
+particle order and hence the summation order do, so forces for different k
+agree to rounding (well inside the 1e-5 bar), and for a fixed k every run is
+bitwise reproducible; graph replays are bitwise equal to eager iterations.
 """
 from __future__ import annotations
 
@@ -58,9 +64,30 @@ def _key(wl) -> str:
     return f"{name}|n2^{int(math.log2(max(wl.n, 1)))}|geoms{len(wl.geoms)}"
 
 
-def autotune(wl, candidates=(1, 2), steps: int = 6, warmup: int = 2, cache: str | None = DEFAULT_CACHE,
-             device: int = 0) -> dict:
-    """Time `steps` iterations per candidate k; return {"k": best, "ms": {...}}."""
+def _time_eager(r, steps):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r.step(keep_accel=False)
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t0) / steps
+
+
+def _time_graph(r, steps):
+    r.capture(iters=2)
+    r.replay(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r.replay(max(1, steps // 2))
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / (2 * max(1, steps // 2))
+    r.release_graph()
+    return ms
+
+
+def autotune(wl, candidates=(1, 2), modes=("eager", "graph"), steps: int = 20, warmup: int = 4,
+             cache: str | None = DEFAULT_CACHE, device: int = 0) -> dict:
+    """Time `steps` iterations per (k, mode); return {"k", "mode", "ms_per_step"}."""
     from .relax import Relaxer
     key = _key(wl)
     table = {}
@@ -69,22 +96,19 @@ def autotune(wl, candidates=(1, 2), steps: int = 6, warmup: int = 2, cache: str 
             table = json.load(open(cache))
         except (OSError, ValueError):
             table = {}
-    if key in table:
+    if key in table and "mode" in table[key]:
         return table[key]
     times = {}
     for k in candidates:
         r = Relaxer(regrid(wl, k), device=device)
         for _ in range(warmup):
             r.step(keep_accel=False)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            r.step(keep_accel=False)
-        torch.cuda.synchronize()
-        times[str(k)] = 1e3 * (time.perf_counter() - t0) / steps
+        for mode in modes:
+            times[f"k{k}_{mode}"] = _time_eager(r, steps) if mode == "eager" else _time_graph(r, steps)
         del r
     best = min(times, key=times.get)
-    res = {"k": int(best), "ms_per_step": times}
+    k, mode = best.split("_")
+    res = {"k": int(k[1:]), "mode": mode, "ms_per_step": times}
     if cache:
         table[key] = res
         try:
