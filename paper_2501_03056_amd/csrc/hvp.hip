@@ -55,7 +55,7 @@ __device__ __forceinline__ void pair_jac_apply(float dx, float dy, float dz, flo
                                                float w1, float w2, float& o0, float& o1, float& o2, float scale) {
   const float inv_r = d2 > 0.0f ? __builtin_amdgcn_rsqf(d2) : 0.0f;
   const float r = d2 * inv_r;
-  const float t = fmaxf(fmaf(-r, inv2h, 1.0f), 0.0f);
+  const float t = fmaf(-r, inv2h, 1.0f);   // a pair has r < 2h; non-pairs carry weight 0
   const float t2 = t * t;
   const float c1 = scale * (t2 * t);
   const float rw = fmaf(dz, w2, fmaf(dy, w1, dx * w0));
@@ -75,34 +75,34 @@ __global__ __launch_bounds__(kBlock) void k_jvp(const float4* __restrict__ pos, 
   const int tag = tag_of(p.w);
   const bool mov_i = is_moving(tag, move_mask);
   float o0 = 0.0f, o1 = 0.0f, o2 = 0.0f;
-  if (mov_i || TRANSPOSE) {
+  // a quarantined (non-finite) particle is nobody's neighbour: its row is 0
+  if ((mov_i || TRANSPOSE) && isfinite(p.x) && isfinite(p.y) && isfinite(p.z)) {
     const int g = min(geom_of(p.w), n_geom - 1);
     const GeomDev& G = geoms[g];
     const int rk = rank_of(tag);
+    const uint32_t T = tag < FPPG_TAG_VOLUME ? uint32_t(tag) : 7u;   // tag_j <= T <=> rank_j <= rank_i
     const float rc2 = G.rc2;
     const float inv2h = 0.5f / G.h;
     const float k3 = 3.0f * inv2h;
     const float4 vi = v[i];
-    // Branch-free body: a candidate that is not a pair enters with r = 0 and a
-    // zero weight, so the loads of both rows are issued up front and no exec
-    // mask is juggled per candidate. M(r) is linear in w, so the two terms of
-    // the transposed product share one application.
+    // Branch-free body: a candidate that is not a pair gets weight 0 (all
+    // inputs are finite, so the unused terms stay finite), so the loads of
+    // both rows are issued up front and no exec mask is juggled per
+    // candidate. M(r) is linear in w, so the two terms of the transposed
+    // product share one application.
     for_each_source_with<K>(stencil_of(p, G), G, cs, pos, v, [&](int j, const float4 q, const float4 vj) {
       const float dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
       const float d2 = pair_d2(dx, dy, dz);
-      const int tj = tag_of(q.w);
-      const int rj = rank_of(tj);
+      const uint32_t tj = __float_as_uint(q.w) & 7u;
       // bitwise, not short-circuit, so that nothing here branches
       const bool pair = (d2 < rc2) & (j != i);
-      const float ex = pair ? dx : 0.0f, ey = pair ? dy : 0.0f, ez = pair ? dz : 0.0f;
-      const float e2 = pair ? d2 : 0.0f;
       if (!TRANSPOSE) {
-        const float sc = (pair & (rj <= rk)) ? 1.0f : 0.0f;
-        pair_jac_apply(ex, ey, ez, e2, inv2h, k3, vi.x - vj.x, vi.y - vj.y, vi.z - vj.z, o0, o1, o2, sc);
+        const float sc = (pair & (tj <= T)) ? 1.0f : 0.0f;
+        pair_jac_apply(dx, dy, dz, d2, inv2h, k3, vi.x - vj.x, vi.y - vj.y, vi.z - vj.z, o0, o1, o2, sc);
       } else {
-        const float s1 = (pair & mov_i & (rj <= rk)) ? 1.0f : 0.0f;
-        const float s2 = (pair & is_moving(tj, move_mask) & (rk <= rj)) ? -1.0f : 0.0f;
-        pair_jac_apply(ex, ey, ez, e2, inv2h, k3, fmaf(s1, vi.x, s2 * vj.x), fmaf(s1, vi.y, s2 * vj.y),
+        const float s1 = (pair & mov_i & (tj <= T)) ? 1.0f : 0.0f;
+        const float s2 = (pair & is_moving(int(tj), move_mask) & (rk <= rank_of(int(tj)))) ? -1.0f : 0.0f;
+        pair_jac_apply(dx, dy, dz, d2, inv2h, k3, fmaf(s1, vi.x, s2 * vj.x), fmaf(s1, vi.y, s2 * vj.y),
                        fmaf(s1, vi.z, s2 * vj.z), o0, o1, o2, 1.0f);
       }
     });

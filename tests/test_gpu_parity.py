@@ -336,3 +336,44 @@ def test_isolated_and_coincident_particles():
     pos, _, _, _ = r.host_state()
     assert np.array_equal(pos[0], wl.pos[0])          # lone particle: a = 0
     assert r.read_status() == 0
+
+
+def test_volume_moves_that_end_at_or_across_a_facet_plane_revert():
+    """Prescribed displacements of volume particles a few ulps inside the
+    cube's faces: a move is reverted exactly when its end point lies on or
+    beyond the face (the binary32 plane prefilter defers every close call to
+    the FP64 test)."""
+    from synth import meshes as M
+    one = np.float32(1.0)
+    pts, moves = [], []
+    for axis in range(3):
+        for a in range(1, 7):
+            for b in range(0, 9):
+                p = np.full(3, np.float32(0.3) + np.float32(0.005 * (a + 7 * b)), np.float32)
+                p[axis] = one
+                for _ in range(a):
+                    p[axis] = np.nextafter(p[axis], np.float32(0))
+                y = p[axis]
+                for _ in range(b):
+                    y = np.nextafter(y, np.float32(2))
+                d = np.zeros(3, np.float32)
+                d[axis] = np.float32(y - p[axis])          # exact: both near 1
+                pts.append(p)
+                moves.append(d)
+    p = np.array(pts, np.float32)
+    dvec = np.array(moves, np.float32)
+    wl = synth.workload.custom_workload(M.cube(), 0.05, p, np.full(len(p), synth.VOLUME))
+    r = _relaxer(wl)
+    r.build_cells()
+    ids = r.id.cpu().numpy()
+    disp = np.zeros((wl.n, 4), np.float32)
+    disp[:, :3] = dvec[ids]
+    r.disp.copy_(torch.from_numpy(disp))
+    r.project()
+    pos, _, _, _ = r.host_state()
+    y = (p + dvec).astype(np.float32)
+    outside = np.any(y >= one, axis=1)
+    assert outside.any() and (~outside).any()
+    assert np.array_equal(pos[outside], p[outside])
+    assert np.array_equal(pos[~outside], y[~outside])
+    assert int(r.counters.cpu()[2]) == int(outside.sum())
