@@ -298,7 +298,7 @@ def main():
     ap.add_argument("--plain-iters", type=int, default=100)
     ap.add_argument("--newton-dx", type=float, default=None, help="default 0.004 (gear), 0.01 (sphere)")
     ap.add_argument("--newton-workload", default="gear", choices=["gear", "sphere"])
-    ap.add_argument("--krylov-max", type=int, default=10)
+    ap.add_argument("--krylov-max", type=int, default=3)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)

@@ -279,6 +279,18 @@ fppg_status fppg_relax_hvp(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
                            int32_t transpose, const float* v, float* Jv, void* stream);
 
 /*
+ * The Newton-Krylov operator in one sweep: out = scale P (J v), with J v as
+ * fppg_relax_hvp(transpose = 0) computes it and P the tangent projection of
+ * fppg_tangent_project applied to each receiver's row (owner, feat_seg as
+ * there). For v in the tangent space (P v = v) and scale = -1 this is
+ * -P J P v, the symmetric operator MINRES iterates with. out must not alias v.
+ */
+fppg_status fppg_relax_hvp_projected(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
+                                     const float* pos, const int32_t* cell_start, const int32_t* owner,
+                                     const int32_t* feat_seg, int32_t n_feat, uint32_t move_mask,
+                                     const float* v, float scale, float* out, void* stream);
+
+/*
  * Pair energy whose negative gradient is the force field of fppg_relax_step
  * for one moving class with fixed other sources (the line-search objective
  * of Newton-Krylov relaxation; not in the paper):
@@ -310,6 +322,15 @@ fppg_status fppg_vec_axpby(fppg_ctx* ctx, int64_t n, float alpha, const float* x
 fppg_status fppg_vec_maxnorm(fppg_ctx* ctx, int64_t n, const float* a, float* out, void* stream);
 /* v_i <- v_i * min(1, cap / |v_i|) row by row (cap > 0): caps every particle's move. */
 fppg_status fppg_vec_clamp(fppg_ctx* ctx, int64_t n, float* v, float cap, void* stream);
+
+/*
+ * out <- a x + b y + c z row by row, then acc <- acc + phi out if acc is not
+ * NULL (a term with a zero coefficient is not read and may be NULL). out and
+ * acc must not alias the inputs or each other. The direction and iterate
+ * update of a MINRES iteration in one pass.
+ */
+fppg_status fppg_vec_combine3(fppg_ctx* ctx, int64_t n, float a, const float* x, float b, const float* y,
+                              float c, const float* z, float* out, float phi, float* acc, void* stream);
 
 /*
  * v <- P v row by row: P = I - n n^T for a moving surface particle (n the

@@ -69,6 +69,9 @@ _SIGS = {
                                     _P, _P, _P, _P, _P]),
     "fppg_fixed_adjoint": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, c_int32, c_uint32, _P, _P, _P]),
     "fppg_vec_permute": (c_int32, [_P, c_int64, _P, _P, c_int32, _P, _P]),
+    "fppg_vec_combine3": (c_int32, [_P, c_int64, c_float, _P, c_float, _P, c_float, _P, _P, c_float, _P, _P]),
+    "fppg_relax_hvp_projected": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, c_int32, c_uint32, _P, c_float, _P,
+                                           _P]),
     "fppg_fixed_to_double": (c_int32, [_P, c_int64, _P, _P, _P]),
 }
 

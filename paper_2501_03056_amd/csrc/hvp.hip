@@ -65,10 +65,22 @@ __device__ __forceinline__ void pair_jac_apply(float dx, float dy, float dz, flo
   o2 = fmaf(-c2, dz, fmaf(c1, w2, o2));
 }
 
-template <int K, bool TRANSPOSE>
+// Tangent projection and scale of the product's row (fppg_relax_hvp_projected).
+struct ProjectOut {
+  const int* owner;
+  const int* feat_seg;
+  int n_feat, n_tri, n_seg;
+  const float4* n32;
+  const SegDev* segs;
+  float scale;
+  uint32_t* status;
+};
+
+template <int K, bool TRANSPOSE, bool PROJECT = false>
 __global__ __launch_bounds__(kBlock) void k_jvp(const float4* __restrict__ pos, int n, const int* __restrict__ cs,
                                                 const GeomDev* __restrict__ geoms, int n_geom, uint32_t move_mask,
-                                                const float4* __restrict__ v, float4* __restrict__ out) {
+                                                const float4* __restrict__ v, float4* __restrict__ out,
+                                                ProjectOut po = ProjectOut{}) {
   const int i = xcd_chunk(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float4 p = pos[i];
@@ -110,7 +122,15 @@ __global__ __launch_bounds__(kBlock) void k_jvp(const float4* __restrict__ pos, 
     o1 *= G.kcoef;
     o2 *= G.kcoef;
   }
-  out[i] = make_float4(o0, o1, o2, 0.0f);
+  float4 r = make_float4(o0, o1, o2, 0.0f);
+  if (PROJECT) {
+    r = tangent_apply(r, tag, i, move_mask, po.owner, po.feat_seg, po.n_feat, po.n_tri, po.n_seg, po.n32, po.segs,
+                      po.status);
+    r.x *= po.scale;
+    r.y *= po.scale;
+    r.z *= po.scale;
+  }
+  out[i] = r;
 }
 
 // ---- neighbour export (tests) -------------------------------------------------------------
@@ -172,6 +192,33 @@ extern "C" fppg_status fppg_relax_hvp(fppg_ctx* ctx, const fppg_geom* geom, int6
     if (transpose) k_jvp<2, true><<<grid_for(ni), kBlock, 0, s>>>(p4, ni, cell_start, geom->d_geom, geom->n_geom, move_mask, v4, o4);
     else k_jvp<2, false><<<grid_for(ni), kBlock, 0, s>>>(p4, ni, cell_start, geom->d_geom, geom->n_geom, move_mask, v4, o4);
   }
+  FPPG_HIP(ctx, hipGetLastError());
+  return FPPG_OK;
+}
+
+extern "C" fppg_status fppg_relax_hvp_projected(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, const float* pos,
+                                                const int32_t* cell_start, const int32_t* owner,
+                                                const int32_t* feat_seg, int32_t n_feat, uint32_t move_mask,
+                                                const float* v, float scale, float* out, void* stream) {
+  fppg_status st = check_common(ctx, geom, n, pos, cell_start);
+  if (st != FPPG_OK) return st;
+  if (n > 0 && (!v || !out || !owner)) return fail(ctx, FPPG_E_ARG, "null v/out/owner");
+  if (n_feat < 0 || (n_feat > 0 && !feat_seg)) return fail(ctx, FPPG_E_ARG, "bad feature table");
+  if (!aligned(v, 16) || !aligned(out, 16)) return fail(ctx, FPPG_E_ARG, "v/out must be 16-byte aligned");
+  if (v == out && n > 0) return fail(ctx, FPPG_E_ARG, "out must not alias v");
+  if (n == 0) return FPPG_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int ni = int(n);
+  const ProjectOut po{owner, feat_seg, n_feat, int(geom->n_tri), int(geom->n_seg), geom->d_n32, geom->d_seg, scale,
+                      ctx->d_status};
+  const float4* p4 = reinterpret_cast<const float4*>(pos);
+  const float4* v4 = reinterpret_cast<const float4*>(v);
+  float4* o4 = reinterpret_cast<float4*>(out);
+  PhaseTimer timer(ctx, 4, s);
+  if (geom->k == 1)
+    k_jvp<1, false, true><<<grid_for(ni), kBlock, 0, s>>>(p4, ni, cell_start, geom->d_geom, geom->n_geom, move_mask, v4, o4, po);
+  else
+    k_jvp<2, false, true><<<grid_for(ni), kBlock, 0, s>>>(p4, ni, cell_start, geom->d_geom, geom->n_geom, move_mask, v4, o4, po);
   FPPG_HIP(ctx, hipGetLastError());
   return FPPG_OK;
 }

@@ -197,4 +197,42 @@ __device__ __forceinline__ bool is_moving(int tag, uint32_t move_mask) {
   return tag >= 1 && tag <= 3 && ((move_mask >> tag) & 1u);
 }
 
+// x <- P x for particle i (the tangent spaces of Eq. 24-25): surface
+// I - n n^T with n the binary32 normal of facet owner[i], feature t t^T with
+// t the FP64 tangent of segment feat_seg[owner[i]], volume I, a particle
+// that does not move 0. An out-of-range owner or segment gives 0 and sets
+// FPPG_S_BAD_INDEX.
+__device__ __forceinline__ float4 tangent_apply(float4 x, int tag, int i, uint32_t move_mask,
+                                                const int* __restrict__ owner, const int* __restrict__ feat_seg,
+                                                int n_feat, int n_tri, int n_seg, const float4* __restrict__ n32,
+                                                const SegDev* __restrict__ segs, uint32_t* status) {
+  const float4 zero = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  if (!is_moving(tag, move_mask)) return zero;
+  if (tag == FPPG_TAG_SURFACE) {
+    const int o = owner[i];
+    if (o < 0 || o >= n_tri) {
+      atomicOr(status, FPPG_S_BAD_INDEX);
+      return zero;
+    }
+    const float4 nn = n32[o];
+    const float s = x.x * nn.x + x.y * nn.y + x.z * nn.z;
+    x.x -= s * nn.x;
+    x.y -= s * nn.y;
+    x.z -= s * nn.z;
+  } else if (tag == FPPG_TAG_FEATURE) {
+    const int o = owner[i];
+    const int sg = (o >= 0 && o < n_feat) ? feat_seg[o] : -1;
+    if (sg < 0 || sg >= n_seg) {
+      atomicOr(status, FPPG_S_BAD_INDEX);
+      return zero;
+    }
+    const SegDev S = segs[sg];
+    const double s = double(x.x) * S.t[0] + double(x.y) * S.t[1] + double(x.z) * S.t[2];
+    x.x = float(s * S.t[0]);
+    x.y = float(s * S.t[1]);
+    x.z = float(s * S.t[2]);
+  }
+  return x;
+}
+
 }  // namespace fppg

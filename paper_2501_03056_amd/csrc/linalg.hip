@@ -44,8 +44,7 @@ __global__ __launch_bounds__(kBlock) void k_axpby(int n, float alpha, const floa
   y[i] = b;
 }
 
-// v <- P v: surface I - n n^T (owner facet), feature t t^T (owner segment),
-// volume I, non-moving 0.
+// v <- P v (tangent_apply, internal.h).
 __global__ __launch_bounds__(kBlock) void k_tangent(const float4* __restrict__ pos, const int* __restrict__ owner,
                                                     const int* __restrict__ feat_seg, int n, int n_feat, int n_tri,
                                                     int n_seg, const float4* __restrict__ n32,
@@ -53,37 +52,33 @@ __global__ __launch_bounds__(kBlock) void k_tangent(const float4* __restrict__ p
                                                     float4* __restrict__ v, uint32_t* status) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int tag = tag_of(pos[i].w);
-  float4 x = v[i];
-  if (!is_moving(tag, move_mask)) {
-    x = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-  } else if (tag == FPPG_TAG_SURFACE) {
-    const int o = owner[i];
-    if (o < 0 || o >= n_tri) {
-      atomicOr(status, FPPG_S_BAD_INDEX);
-      x = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    } else {
-      const float4 nn = n32[o];
-      const float s = x.x * nn.x + x.y * nn.y + x.z * nn.z;
-      x.x -= s * nn.x;
-      x.y -= s * nn.y;
-      x.z -= s * nn.z;
-    }
-  } else if (tag == FPPG_TAG_FEATURE) {
-    const int o = owner[i];
-    const int sg = (o >= 0 && o < n_feat) ? feat_seg[o] : -1;
-    if (sg < 0 || sg >= n_seg) {
-      atomicOr(status, FPPG_S_BAD_INDEX);
-      x = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    } else {
-      const SegDev S = segs[sg];
-      const double s = double(x.x) * S.t[0] + double(x.y) * S.t[1] + double(x.z) * S.t[2];
-      x.x = float(s * S.t[0]);
-      x.y = float(s * S.t[1]);
-      x.z = float(s * S.t[2]);
-    }
+  v[i] = tangent_apply(v[i], tag_of(pos[i].w), i, move_mask, owner, feat_seg, n_feat, n_tri, n_seg, n32, segs,
+                       status);
+}
+
+// out = a x + b y + c z (a term with a zero coefficient is not read), then
+// acc += phi out when acc is given: the direction and iterate updates of MINRES.
+__global__ __launch_bounds__(kBlock) void k_combine3(int n, float a, const float4* __restrict__ x, float b,
+                                                     const float4* __restrict__ y, float c,
+                                                     const float4* __restrict__ z, float4* __restrict__ out,
+                                                     float phi, float4* __restrict__ acc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float4 zero = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  const float4 X = a != 0.0f ? x[i] : zero, Y = b != 0.0f ? y[i] : zero, Z = c != 0.0f ? z[i] : zero;
+  float4 o;
+  o.x = fmaf(c, Z.x, fmaf(b, Y.x, a * X.x));
+  o.y = fmaf(c, Z.y, fmaf(b, Y.y, a * X.y));
+  o.z = fmaf(c, Z.z, fmaf(b, Y.z, a * X.z));
+  o.w = 0.0f;
+  out[i] = o;
+  if (acc) {
+    float4 s = acc[i];
+    s.x = fmaf(phi, o.x, s.x);
+    s.y = fmaf(phi, o.y, s.y);
+    s.z = fmaf(phi, o.z, s.z);
+    acc[i] = s;
   }
-  v[i] = x;
 }
 
 // disp = alpha P v in the format of fppg_project (feature: FP64 du = alpha v.t).
@@ -250,6 +245,25 @@ extern "C" fppg_status fppg_tangent_project(fppg_ctx* ctx, const fppg_geom* geom
   k_tangent<<<grid_for(n), kBlock, 0, static_cast<hipStream_t>(stream)>>>(
       reinterpret_cast<const float4*>(pos), owner, feat_seg, int(n), n_feat, int(geom->n_tri), int(geom->n_seg),
       geom->d_n32, geom->d_seg, move_mask, reinterpret_cast<float4*>(v), ctx->d_status);
+  FPPG_HIP(ctx, hipGetLastError());
+  return FPPG_OK;
+}
+
+extern "C" fppg_status fppg_vec_combine3(fppg_ctx* ctx, int64_t n, float a, const float* x, float b,
+                                         const float* y, float c, const float* z, float* out, float phi,
+                                         float* acc, void* stream) {
+  if (!ctx) return FPPG_E_ARG;
+  if (n < 0 || n >= (int64_t(1) << 31)) return fail(ctx, FPPG_E_ARG, "n out of range");
+  if (n > 0 && (!out || (a != 0.0f && !x) || (b != 0.0f && !y) || (c != 0.0f && !z)))
+    return fail(ctx, FPPG_E_ARG, "null argument");
+  if (!aligned(x, 16) || !aligned(y, 16) || !aligned(z, 16) || !aligned(out, 16) || !aligned(acc, 16))
+    return fail(ctx, FPPG_E_ARG, "misaligned argument");
+  if (n > 0 && (out == x || out == y || out == z || (acc && (acc == out || acc == x || acc == y || acc == z))))
+    return fail(ctx, FPPG_E_ARG, "out and acc must not alias the inputs or each other");
+  if (n == 0) return FPPG_OK;
+  k_combine3<<<grid_for(n), kBlock, 0, static_cast<hipStream_t>(stream)>>>(
+      int(n), a, reinterpret_cast<const float4*>(x), b, reinterpret_cast<const float4*>(y), c,
+      reinterpret_cast<const float4*>(z), reinterpret_cast<float4*>(out), phi, reinterpret_cast<float4*>(acc));
   FPPG_HIP(ctx, hipGetLastError());
   return FPPG_OK;
 }

@@ -9,8 +9,8 @@ Relaxation is done when the tangential forces vanish,
 
 and Newton's method solves that system directly:
 
-    solve  (P J P) d = -F  with MINRES            J d from fppg_relax_hvp, P from
-                                                   fppg_tangent_project
+    solve  (P J P) d = -F  with MINRES            -P J v in one sweep from
+                                                   fppg_relax_hvp_projected
     cap every particle's move at move_cap * h    fppg_vec_clamp
     x <- Pi(x + s d), s = 1, 1/2, ... until |F|^2 decreases   fppg_displace + fppg_project
 
@@ -55,40 +55,37 @@ class NewtonLog:
 
 
 class _Minres:
-    """MINRES (Paige-Saunders) for A x = b with A = -P J P, on device vectors."""
+    """MINRES (Paige-Saunders) for A x = b with A = -P J P, on device vectors.
+    One iteration: the operator in one sweep (fppg_relax_hvp_projected), two
+    axpbys, two dot products, one fused direction + iterate update
+    (fppg_vec_combine3); the Lanczos vectors rotate through three buffers."""
 
     def __init__(self, r: Relaxer, like: torch.Tensor):
         self.r = r
         self.v, self.y, self.r1, self.r2 = (torch.empty_like(like) for _ in range(4))
         self.w, self.w1, self.w2 = (torch.empty_like(like) for _ in range(3))
 
-    def apply(self, v: torch.Tensor, out: torch.Tensor):
-        self.r.hvp(v, out=out)                 # J v
-        self.r.tangent(out)                    # P J v
-        self.r.axpby(0.0, v, -1.0, out)        # -P J v
-
     def solve(self, b: torch.Tensor, x: torch.Tensor, rtol: float, maxit: int) -> int:
         r = self.r
         x.zero_()
-        self.r1.copy_(b)
-        self.r2.copy_(b)
-        self.y.copy_(b)
         beta1 = math.sqrt(max(r.dot(b, b), 0.0))
         if beta1 == 0.0:
             return 0
+        self.r1.copy_(b)
+        self.r2.copy_(b)
         oldb, beta, dbar, epsln, phibar, cs, sn = 0.0, beta1, 0.0, 0.0, beta1, -1.0, 0.0
         self.w.zero_()
         self.w2.zero_()
         it = 0
         for it in range(1, maxit + 1):
-            r.axpby(1.0 / beta, self.y, 0.0, self.v)           # v = y / beta
-            self.apply(self.v, self.y)                         # y = A v
+            r.axpby(1.0 / beta, self.r2, 0.0, self.v)           # v = y / beta (r2 holds y)
+            r.hvp_projected(self.v, -1.0, self.y)               # y = A v
             if it >= 2:
                 r.axpby(-beta / oldb, self.r1, 1.0, self.y)
             alfa = r.dot(self.v, self.y)
             r.axpby(-alfa / beta, self.r2, 1.0, self.y)
-            self.r1, self.r2 = self.r2, self.r1
-            self.r2.copy_(self.y)
+            # (r1, r2) <- (r2, y); the old r1 buffer becomes the next y
+            self.r1, self.r2, self.y = self.r2, self.y, self.r1
             oldb, beta = beta, math.sqrt(max(r.dot(self.r2, self.r2), 0.0))
             oldeps = epsln
             delta = cs * dbar + sn * alfa
@@ -99,19 +96,16 @@ class _Minres:
             cs, sn = gbar / gamma, beta / gamma
             phi = cs * phibar
             phibar = sn * phibar
-            # w_new = (v - oldeps w1 - delta w2) / gamma, with (w1, w2) <- (w2, w)
+            # w_new = (v - oldeps w1 - delta w2) / gamma with (w1, w2) <- (w2, w); x += phi w_new
             self.w1, self.w2, self.w = self.w2, self.w, self.w1
-            r.axpby(1.0 / gamma, self.v, 0.0, self.w)
-            r.axpby(-oldeps / gamma, self.w1, 1.0, self.w)
-            r.axpby(-delta / gamma, self.w2, 1.0, self.w)
-            r.axpby(phi, self.w, 1.0, x)
+            r.combine3(1.0 / gamma, self.v, -oldeps / gamma, self.w1, -delta / gamma, self.w2, self.w, phi, x)
             if phibar <= rtol * beta1 or beta == 0.0:
                 break
         return it
 
 
 def newton_relax(r: Relaxer, n_moving: int, target: float | None = None, max_iter: int = 50,
-                 krylov_tol: float = 1e-4, krylov_max: int = 10, move_cap: float = 0.25,
+                 krylov_tol: float = 1e-4, krylov_max: int = 3, move_cap: float = 0.25,
                  max_backtracks: int = 6, time_limit: float | None = None,
                  forcing: str | None = "ew", checkpoint_every: int = 0) -> NewtonLog:
     """Newton-MINRES on F = P a until the force residual is <= target.

@@ -241,6 +241,20 @@ class Relaxer:
         lib, c = self.ctx.lib, self.ctx.handle
         check(lib.fppg_vec_clamp(c, self.n, ptr(v), float(cap), self.stream), c)
 
+    def hvp_projected(self, v: torch.Tensor, scale: float, out: torch.Tensor) -> torch.Tensor:
+        """out = scale P (J v) in one sweep (cells must be current)."""
+        lib, c = self.ctx.lib, self.ctx.handle
+        check(lib.fppg_relax_hvp_projected(c, self.geom.handle, self.n, ptr(self.pos), ptr(self.cell_start),
+                                           ptr(self.owner), ptr(self.feat_seg), self.n_feat, self.move_mask,
+                                           ptr(v), float(scale), ptr(out), self.stream), c)
+        return out
+
+    def combine3(self, a, x, b, y, c3, z, out, phi=0.0, acc=None):
+        """out = a x + b y + c3 z; acc += phi out if acc is given."""
+        lib, c = self.ctx.lib, self.ctx.handle
+        check(lib.fppg_vec_combine3(c, self.n, float(a), ptr(x), float(b), ptr(y), float(c3), ptr(z), ptr(out),
+                                    float(phi), ptr(acc), self.stream), c)
+
     def tangent(self, v: torch.Tensor):
         """v <- P v (tangent spaces of the constrained particles; 0 where nothing moves)."""
         lib, c = self.ctx.lib, self.ctx.handle

@@ -77,6 +77,33 @@ def test_vector_ops_match_numpy():
     assert abs(r.maxnorm(ta) - np.linalg.norm(a[:, :3], axis=1).max()) <= 1e-6 * np.linalg.norm(a[:, :3], axis=1).max()
 
 
+def test_projected_product_and_combine3_match_their_parts():
+    """fppg_relax_hvp_projected = scale * tangent(hvp) bit for bit; fppg_vec_combine3 = numpy."""
+    wl = synth.cube_workload(n=9, seed=29)          # every class moves
+    r = _relaxer(wl)
+    r.build_cells()
+    rng = np.random.Generator(np.random.PCG64(30))
+    v = torch.from_numpy(rng.normal(size=(wl.n, 4)).astype(np.float32)).cuda()
+    v[:, 3] = 0
+    r.tangent(v)
+    ref = r.hvp(v)
+    r.tangent(ref)
+    ref *= -1.0
+    got = r.hvp_projected(v, -1.0, torch.empty_like(v))
+    assert torch.equal(got[:, :3], ref[:, :3])
+    a, b, c = (torch.from_numpy(rng.normal(size=(wl.n, 4)).astype(np.float32)).cuda() for _ in range(3))
+    out, acc = torch.full_like(a, float("nan")), b.clone() * 0.5
+    acc0 = acc.cpu().numpy().astype(np.float64)
+    r.combine3(0.5, a, -2.0, b, 0.25, c, out, 3.0, acc)
+    A, B, C = (t.cpu().numpy().astype(np.float64) for t in (a, b, c))
+    want = 0.5 * A - 2.0 * B + 0.25 * C
+    np.testing.assert_allclose(out.cpu().numpy()[:, :3], want[:, :3], rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose(acc.cpu().numpy()[:, :3], acc0[:, :3] + 3.0 * want[:, :3], rtol=1e-5, atol=1e-5)
+    r.combine3(1.0, a, 0.0, None, 0.0, None, out)    # zero coefficients: operands not read
+    assert torch.equal(out[:, :3], a[:, :3])
+    assert r.read_status() == 0
+
+
 def test_tangent_projection_and_displacement_match_oracle():
     wl = synth.cube_workload(n=8, seed=26)      # all classes move
     r = _relaxer(wl)

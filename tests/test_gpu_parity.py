@@ -377,3 +377,47 @@ def test_volume_moves_that_end_at_or_across_a_facet_plane_revert():
     assert np.array_equal(pos[outside], p[outside])
     assert np.array_equal(pos[~outside], y[~outside])
     assert int(r.counters.cpu()[2]) == int(outside.sum())
+
+
+# --------------------------------------------------------------------------- error paths
+
+def test_host_side_errors_with_a_live_context():
+    """Argument errors are returned (and described) without launching anything."""
+    import ctypes
+    from paper_2501_03056_amd import _lib
+    from paper_2501_03056_amd._lib import ptr
+    from paper_2501_03056_amd.relax import geom_descs
+    wl = synth.cube_workload(n=4, seed=2)
+    r = _relaxer(wl)
+    L, c, g = r.ctx.lib, r.ctx.handle, r.geom.handle
+    st = r.stream
+    # workspace too small
+    assert L.fppg_build_cells(c, g, r.n, ptr(r.pos), ptr(r.id), ptr(r.owner), ptr(r.pos_b), ptr(r.id_b),
+                              ptr(r.owner_b), ptr(r.cell_start), r.ws_ptr, 16, st) == _lib.E_WORKSPACE
+    assert b"workspace" in L.fppg_last_error(c)
+    # particle count differs from the geometry's
+    assert L.fppg_relax_step(c, g, r.n + 1, ptr(r.pos), ptr(r.owner), ptr(r.cell_start), ptr(r.feat_seg),
+                             r.n_feat, r.move_mask, 0, None, ptr(r.amax), ptr(r.disp), r.ws_ptr, r.ws_bytes,
+                             st) == _lib.E_ARG
+    # misaligned position array
+    mis = ctypes.c_void_p(r.pos.data_ptr() + 4)
+    assert L.fppg_project(c, g, r.n, mis, ptr(r.owner), ptr(r.disp), ptr(r.feat_seg), ptr(r.feat_u), r.n_feat,
+                          r.move_mask, ptr(r.counters), st) == _lib.E_ARG
+    # aliasing input and output
+    assert L.fppg_relax_hvp(c, g, r.n, ptr(r.pos), ptr(r.cell_start), r.move_mask, 0, ptr(r.disp), ptr(r.disp),
+                            st) == _lib.E_ARG
+    # an odd iteration count cannot be replayed back to back
+    h = ctypes.c_void_p()
+    side = torch.cuda.Stream()
+    assert L.fppg_graph_create(c, g, r.n, ptr(r.pos), ptr(r.id), ptr(r.owner), ptr(r.pos_b), ptr(r.id_b),
+                               ptr(r.owner_b), ptr(r.cell_start), ptr(r.feat_seg), ptr(r.feat_u), r.n_feat,
+                               r.move_mask, ptr(r.amax), ptr(r.disp), ptr(r.counters), r.ws_ptr, r.ws_bytes, 3,
+                               ctypes.c_void_p(side.cuda_stream), ctypes.byref(h)) == _lib.E_ARG
+    # unsupported stencil half-width
+    bad = synth.cube_workload(n=4, seed=2)
+    bad.geoms[0].k = 3
+    arr, keep = geom_descs(bad.geoms)
+    assert L.fppg_geom_create(c, arr, 1, ctypes.byref(h)) == _lib.E_UNSUPPORTED
+    # nothing above reached the device
+    r.step()
+    assert r.read_status() == 0
