@@ -181,9 +181,12 @@ def bench_gear(args):
     for name, mm in tiers:
         r.move_mask = mm
         n_moving = int(np.sum((mm >> wl.tag) & 1))
+        # a sparse tier launches only its moving particles' lanes
+        r.use_list = not args.no_list and n_moving < wl.n // 2
         for _ in range(args.warmup):
             r.step(keep_accel=False)
         r.build_cells()
+        r.accel.zero_()   # a receiver list leaves the other rows unwritten
         r.relax_step(count_pairs=True)
         pairs = float(r.accel[:, 3].double().sum().item())
         r.profile(True)
@@ -202,6 +205,7 @@ def bench_gear(args):
         out_tiers[name] = {"moving": n_moving, "iters": args.tier_iters, "ms_per_step": ms / args.tier_iters,
                            "particle_updates_per_s": n_moving * args.tier_iters / (ms / 1e3),
                            "pairs_per_step": pairs, "pair_evals_per_s": pairs * args.tier_iters / (ms / 1e3),
+                           "receiver_list": bool(r.use_list),
                            "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]}}
         print(f"[bench] tier {name}: {n_moving} moving, {ms / args.tier_iters:.3f} ms/step", file=sys.stderr,
               flush=True)
@@ -295,6 +299,8 @@ def main():
     ap.add_argument("--mode", default="step", choices=["step", "batch", "newton", "gear"])
     ap.add_argument("--gear-dx", type=float, default=0.004)
     ap.add_argument("--tier-iters", type=int, default=100)
+    ap.add_argument("--no-list", action="store_true",
+                    help="gear tiers: launch every particle's lane instead of the moving-particle list")
     ap.add_argument("--plain-iters", type=int, default=100)
     ap.add_argument("--newton-dx", type=float, default=None, help="default 0.004 (gear), 0.01 (sphere)")
     ap.add_argument("--newton-workload", default="gear", choices=["gear", "sphere"])

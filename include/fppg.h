@@ -230,11 +230,16 @@ fppg_status fppg_build_cells(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
  * Non-finite accelerations are excluded from amax and give a zero
  * displacement (FPPG_S_NONFINITE_ACCEL); an out-of-range owner or feature
  * segment gives a zero displacement (FPPG_S_BAD_INDEX).
+ * Receivers: all n particles (list = NULL), or only the n_list particles
+ * whose sorted indices list [n_list] (device, distinct, in [0, n)) holds, e.g.
+ * the moving particles from fppg_moving_list: a tier in which few particles
+ * move then launches only their lanes. Rows of accel and disp outside the
+ * list are not written.
  */
 fppg_status fppg_relax_step(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
                             const float* pos, const int32_t* owner, const int32_t* cell_start,
                             const int32_t* feat_seg, int32_t n_feat, uint32_t move_mask, uint32_t flags,
-                            float* accel, float* amax, float* disp,
+                            float* accel, float* amax, float* disp, const int32_t* list, int32_t n_list,
                             void* ws, size_t ws_bytes, void* stream);
 
 /*
@@ -257,12 +262,13 @@ fppg_status fppg_relax_step(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
  * pos [n*4] in: positions x, out: new positions; owner [n] in/out;
  * disp [n*4] from fppg_relax_step; feat_seg/feat_u [n_feat] in/out (may be
  * NULL if n_feat = 0); counters [FPPG_NCOUNTERS] int64 on the device,
- * incremented by the number of reverts per class (FPPG_C_*).
+ * incremented by the number of reverts per class (FPPG_C_*). list / n_list
+ * as in fppg_relax_step (NULL: all particles).
  */
 fppg_status fppg_project(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
                          float* pos, int32_t* owner, const float* disp,
                          int32_t* feat_seg, double* feat_u, int32_t n_feat, uint32_t move_mask,
-                         int64_t* counters, void* stream);
+                         int64_t* counters, const int32_t* list, int32_t n_list, void* stream);
 
 /*
  * Jacobian-vector product of the force field of fppg_relax_step with respect
@@ -350,6 +356,17 @@ fppg_status fppg_tangent_project(fppg_ctx* ctx, const fppg_geom* geom, int64_t n
 fppg_status fppg_displace(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, const float* pos,
                           const int32_t* owner, const int32_t* feat_seg, int32_t n_feat,
                           uint32_t move_mask, const float* v, float alpha, float* disp, void* stream);
+
+/*
+ * Sorted indices of the particles that move (tag 1..3 with its bit set in
+ * move_mask), ascending, into list [n] (device); their number into count[0]
+ * (device int32). Deterministic (block counts, prefix sum, write). ws: at
+ * least fppg_workspace_size bytes. The receiver list of fppg_relax_step and
+ * fppg_project for a tier in which one class moves.
+ */
+fppg_status fppg_moving_list(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, const float* pos,
+                             uint32_t move_mask, int32_t* list, int32_t* count, void* ws, size_t ws_bytes,
+                             void* stream);
 
 /*
  * fppg_project with a per-particle record of its decisions, for reverse-mode

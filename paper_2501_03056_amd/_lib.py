@@ -48,8 +48,9 @@ _SIGS = {
     "fppg_workspace_size": (c_int32, [_P, c_int64, POINTER(c_size_t)]),
     "fppg_build_cells": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, _P, _P, _P, _P, c_size_t, _P]),
     "fppg_relax_step": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, c_int32, c_uint32, c_uint32,
-                                  _P, _P, _P, _P, c_size_t, _P]),
-    "fppg_project": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, _P, c_int32, c_uint32, _P, _P]),
+                                  _P, _P, _P, _P, c_int32, _P, c_size_t, _P]),
+    "fppg_project": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, _P, c_int32, c_uint32, _P, _P, c_int32, _P]),
+    "fppg_moving_list": (c_int32, [_P, _P, c_int64, _P, c_uint32, _P, _P, _P, c_size_t, _P]),
     "fppg_relax_hvp": (c_int32, [_P, _P, c_int64, _P, _P, c_uint32, c_int32, _P, _P, _P]),
     "fppg_debug_neighbors": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, c_int32, _P]),
     "fppg_graph_create": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, c_int32, c_uint32,

@@ -181,6 +181,48 @@ __global__ __launch_bounds__(kBlock) void k_final(const int* __restrict__ tmp_id
   owner_out[dst] = owner_in[src];
 }
 
+// ---- list of the moving particles (sorted indices, ascending) -----------------------------
+
+__device__ __forceinline__ bool moving_at(const float4* __restrict__ pos, int i, int n, uint32_t move_mask) {
+  return i < n && is_moving(tag_of(pos[i].w), move_mask);
+}
+
+// moving lanes below this one in the block, and the block's total
+__device__ __forceinline__ int block_rank(bool m, int* total) {
+  __shared__ int wcnt[kBlock / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const uint64_t b = __ballot(m);
+  if (lane == 0) wcnt[wid] = __popcll(b);
+  __syncthreads();
+  int before = 0, t = 0;
+  for (int w = 0; w < kBlock / 64; ++w) {
+    if (w < wid) before += wcnt[w];
+    t += wcnt[w];
+  }
+  *total = t;
+  __syncthreads();
+  return before + __popcll(b & ((1ull << lane) - 1ull));
+}
+
+__global__ __launch_bounds__(kBlock) void k_list_count(const float4* __restrict__ pos, int n, uint32_t move_mask,
+                                                       int* __restrict__ cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int total;
+  block_rank(moving_at(pos, i, n, move_mask), &total);
+  if (threadIdx.x == 0) cnt[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kBlock) void k_list_write(const float4* __restrict__ pos, int n, uint32_t move_mask,
+                                                       const int* __restrict__ offs, int nb,
+                                                       int* __restrict__ list, int* __restrict__ count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool m = moving_at(pos, i, n, move_mask);
+  int total;
+  const int r = block_rank(m, &total);
+  if (m) list[offs[blockIdx.x] + r] = i;
+  if (blockIdx.x == nb - 1 && threadIdx.x == 0) count[0] = offs[blockIdx.x] + total;
+}
+
 static inline int grid_for(int64_t n, int block) { return int((n + block - 1) / block); }
 
 }  // namespace fppg
@@ -229,6 +271,38 @@ extern "C" fppg_status fppg_build_cells(fppg_ctx* ctx, const fppg_geom* geom, in
                                                     reinterpret_cast<const float4*>(pos_in), owner_in,
                                                     reinterpret_cast<float4*>(pos_out), id_out, owner_out);
   }
+  FPPG_HIP(ctx, hipGetLastError());
+  return FPPG_OK;
+}
+
+extern "C" fppg_status fppg_moving_list(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, const float* pos,
+                                        uint32_t move_mask, int32_t* list, int32_t* count, void* ws,
+                                        size_t ws_bytes, void* stream) {
+  if (!ctx || !geom) return fail(ctx, FPPG_E_ARG, "null ctx/geom");
+  if (n != geom->n_part) return fail(ctx, FPPG_E_ARG, "n differs from the particle count of the geometry descriptors");
+  if (!count || !ws || (n > 0 && (!pos || !list))) return fail(ctx, FPPG_E_ARG, "null argument");
+  if (!aligned(pos, 16) || !aligned(ws, 256)) return fail(ctx, FPPG_E_ARG, "pos must be 16-byte and ws 256-byte aligned");
+  const WsLayout L = ws_layout(geom, n);
+  if (ws_bytes < L.list_end) return fail(ctx, FPPG_E_WORKSPACE, "workspace too small for moving_list");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (n == 0) {
+    k_fill_i32<<<1, kBlock, 0, s>>>(count, 1, 0);
+    FPPG_HIP(ctx, hipGetLastError());
+    return FPPG_OK;
+  }
+  char* w = static_cast<char*>(ws);
+  int* cnt = reinterpret_cast<int*>(w + L.list_cnt);
+  int* offs = reinterpret_cast<int*>(w + L.list_offs);
+  int* bsum = reinterpret_cast<int*>(w + L.list_bsum);
+  const int ni = int(n);
+  const int nb = grid_for(ni, kBlock);
+  const int nt = int((int64_t(nb) + kScanTile - 1) / kScanTile);
+  const float4* p4 = reinterpret_cast<const float4*>(pos);
+  k_list_count<<<nb, kBlock, 0, s>>>(p4, ni, move_mask, cnt);
+  k_scan_reduce<<<nt, kScanThreads, 0, s>>>(cnt, nb, bsum);
+  k_scan_top<<<1, kScanThreads, 0, s>>>(bsum, nt);
+  k_scan_down<<<nt, kScanThreads, 0, s>>>(cnt, nb, bsum, offs, 0);
+  k_list_write<<<nb, kBlock, 0, s>>>(p4, ni, move_mask, offs, nb, list, count);
   FPPG_HIP(ctx, hipGetLastError());
   return FPPG_OK;
 }

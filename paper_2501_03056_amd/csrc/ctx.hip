@@ -36,9 +36,15 @@ WsLayout ws_layout(const Geom* g, int64_t n) {
   o = 0;
   L.accel = o;    o += up256(16 * N);
   L.step_end = o;
+  o = 0;
+  const size_t nbl = (N + 255) / 256;
+  L.list_cnt = o;  o += up256(4 * (nbl + 1));
+  L.list_offs = o; o += up256(4 * (nbl + 2));
+  L.list_bsum = o; o += up256(4 * ((nbl + 1 + 4095) / 4096 + 2));
+  L.list_end = o;
   // relax_energy: one FP64 partial per block of 256; vec_dot: kDotPartials
   L.reduce_end = up256(8 * std::max<size_t>((N + 255) / 256 + 1, kDotPartials));
-  L.total = std::max(L.build_end, std::max(L.step_end, L.reduce_end));
+  L.total = std::max(std::max(L.build_end, L.list_end), std::max(L.step_end, L.reduce_end));
   return L;
 }
 

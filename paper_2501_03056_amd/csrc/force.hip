@@ -44,8 +44,9 @@ template <int K, bool COUNT>
 __global__ __launch_bounds__(kBlock) void k_force(const float4* __restrict__ pos, int n,
                                                   const int* __restrict__ cs, const GeomDev* __restrict__ geoms,
                                                   int n_geom, uint32_t move_mask, float4* __restrict__ accel,
-                                                  unsigned* __restrict__ amax_bits, uint32_t* status) {
-  const int i = xcd_chunk(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+                                                  unsigned* __restrict__ amax_bits, uint32_t* status,
+                                                  const int* __restrict__ list, int n_list) {
+  const int i = listed(xcd_chunk(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x, n, list, n_list);
   float anorm = 0.0f;
   int g = 0;
   bool mov = false;
@@ -122,8 +123,9 @@ __global__ __launch_bounds__(kBlock) void k_update(const float4* __restrict__ po
                                                    const GeomDev* __restrict__ geoms, int n_geom,
                                                    const float* __restrict__ amax, const float4* __restrict__ n32,
                                                    const SegDev* __restrict__ segs, uint32_t move_mask,
-                                                   float4* __restrict__ disp, uint32_t* status) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+                                                   float4* __restrict__ disp, uint32_t* status,
+                                                   const int* __restrict__ list, int n_list) {
+  const int i = listed(blockIdx.x * blockDim.x + threadIdx.x, n, list, n_list);
   if (i >= n) return;
   const float4 p = pos[i];
   const int tag = tag_of(p.w);
@@ -183,9 +185,11 @@ using namespace fppg;
 extern "C" fppg_status fppg_relax_step(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, const float* pos,
                                        const int32_t* owner, const int32_t* cell_start, const int32_t* feat_seg,
                                        int32_t n_feat, uint32_t move_mask, uint32_t flags, float* accel,
-                                       float* amax, float* disp, void* ws, size_t ws_bytes, void* stream) {
+                                       float* amax, float* disp, const int32_t* list, int32_t n_list, void* ws,
+                                       size_t ws_bytes, void* stream) {
   fppg_status st = check_common(ctx, geom, n, pos, cell_start);
   if (st != FPPG_OK) return st;
+  if (list && (n_list < 0 || n_list > n)) return fail(ctx, FPPG_E_ARG, "n_list must be in [0, n]");
   if (!amax || (n > 0 && (!disp || !owner))) return fail(ctx, FPPG_E_ARG, "null amax/disp/owner");
   if (n_feat < 0 || (n_feat > 0 && !feat_seg)) return fail(ctx, FPPG_E_ARG, "bad feature table");
   if (!aligned(disp, 16) || (accel && !aligned(accel, 16))) return fail(ctx, FPPG_E_ARG, "accel/disp must be 16-byte aligned");
@@ -198,25 +202,26 @@ extern "C" fppg_status fppg_relax_step(fppg_ctx* ctx, const fppg_geom* geom, int
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int ni = int(n);
+  const int nr = list ? int(n_list) : ni;   // launch slots
   const bool count = (flags & FPPG_F_COUNT_PAIRS) != 0;
   k_zero_f32<<<grid_for(geom->n_geom), kBlock, 0, s>>>(amax, geom->n_geom);
-  if (ni > 0) {
+  if (nr > 0) {
     const float4* p4 = reinterpret_cast<const float4*>(pos);
     unsigned* ab = reinterpret_cast<unsigned*>(amax);
     {
     PhaseTimer timer(ctx, 1, s);
     if (geom->k == 1) {
-      if (count) k_force<1, true><<<grid_for(ni), kBlock, 0, s>>>(p4, ni, cell_start, geom->d_geom, geom->n_geom, move_mask, acc, ab, ctx->d_status);
-      else k_force<1, false><<<grid_for(ni), kBlock, 0, s>>>(p4, ni, cell_start, geom->d_geom, geom->n_geom, move_mask, acc, ab, ctx->d_status);
+      if (count) k_force<1, true><<<grid_for(nr), kBlock, 0, s>>>(p4, ni, cell_start, geom->d_geom, geom->n_geom, move_mask, acc, ab, ctx->d_status, list, nr);
+      else k_force<1, false><<<grid_for(nr), kBlock, 0, s>>>(p4, ni, cell_start, geom->d_geom, geom->n_geom, move_mask, acc, ab, ctx->d_status, list, nr);
     } else {
-      if (count) k_force<2, true><<<grid_for(ni), kBlock, 0, s>>>(p4, ni, cell_start, geom->d_geom, geom->n_geom, move_mask, acc, ab, ctx->d_status);
-      else k_force<2, false><<<grid_for(ni), kBlock, 0, s>>>(p4, ni, cell_start, geom->d_geom, geom->n_geom, move_mask, acc, ab, ctx->d_status);
+      if (count) k_force<2, true><<<grid_for(nr), kBlock, 0, s>>>(p4, ni, cell_start, geom->d_geom, geom->n_geom, move_mask, acc, ab, ctx->d_status, list, nr);
+      else k_force<2, false><<<grid_for(nr), kBlock, 0, s>>>(p4, ni, cell_start, geom->d_geom, geom->n_geom, move_mask, acc, ab, ctx->d_status, list, nr);
     }
     }
     PhaseTimer timer(ctx, 2, s);
-    k_update<<<grid_for(ni), kBlock, 0, s>>>(p4, acc, owner, feat_seg, ni, n_feat, int(geom->n_tri), int(geom->n_seg),
+    k_update<<<grid_for(nr), kBlock, 0, s>>>(p4, acc, owner, feat_seg, ni, n_feat, int(geom->n_tri), int(geom->n_seg),
                                              geom->d_geom, geom->n_geom, amax, geom->d_n32, geom->d_seg, move_mask,
-                                             reinterpret_cast<float4*>(disp), ctx->d_status);
+                                             reinterpret_cast<float4*>(disp), ctx->d_status, list, nr);
   }
   FPPG_HIP(ctx, hipGetLastError());
   return FPPG_OK;

@@ -139,6 +139,8 @@ struct WsLayout {
   size_t key, rank, tmp_id, tmp_src, tmp_key, count, blocksum, build_end;
   // relax_step
   size_t accel, step_end;
+  // moving_list (block counts, their offsets, scan partials)
+  size_t list_cnt, list_offs, list_bsum, list_end;
   // relax_energy / vec_dot partial sums
   size_t reduce_end;
   size_t total;
@@ -233,6 +235,13 @@ __device__ __forceinline__ float4 tangent_apply(float4 x, int tag, int i, uint32
     x.z = float(s * S.t[2]);
   }
   return x;
+}
+
+// Particle handled by launch slot r: r itself, or list[r] when a receiver
+// list is given (slots past n_list get n: idle).
+__device__ __forceinline__ int listed(int r, int n, const int* __restrict__ list, int n_list) {
+  if (!list) return r;
+  return r < n_list ? list[r] : n;
 }
 
 }  // namespace fppg

@@ -189,8 +189,9 @@ __global__ __launch_bounds__(kBlock) void k_project(float4* __restrict__ pos, in
                                                     const int* __restrict__ tstart, const int* __restrict__ ttri,
                                                     const uint8_t* __restrict__ tflag, uint32_t move_mask,
                                                     unsigned long long* __restrict__ counters, uint32_t* status,
-                                                    uint8_t* __restrict__ accepted) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+                                                    uint8_t* __restrict__ accepted, const int* __restrict__ list,
+                                                    int n_list) {
+  const int i = listed(blockIdx.x * blockDim.x + threadIdx.x, n, list, n_list);
   bool rev_s = false, rev_f = false, rev_v = false, moved = false;
   if (i < n) {
     const float4 p = pos[i];
@@ -261,22 +262,26 @@ namespace {
 
 static fppg_status project_impl(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, float* pos, int32_t* owner,
                                 const float* disp, int32_t* feat_seg, double* feat_u, int32_t n_feat,
-                                uint32_t move_mask, int64_t* counters, uint8_t* accepted, void* stream) {
+                                uint32_t move_mask, int64_t* counters, const int32_t* list, int32_t n_list,
+                                uint8_t* accepted, void* stream) {
   if (!ctx || !geom) return fail(ctx, FPPG_E_ARG, "null ctx/geom");
   if (n != geom->n_part) return fail(ctx, FPPG_E_ARG, "n differs from the particle count of the geometry descriptors");
   if (n > 0 && (!pos || !owner || !disp)) return fail(ctx, FPPG_E_ARG, "null pos/owner/disp");
   if (n_feat < 0 || (n_feat > 0 && (!feat_seg || !feat_u))) return fail(ctx, FPPG_E_ARG, "bad feature table");
   if (!aligned(pos, 16) || !aligned(disp, 16)) return fail(ctx, FPPG_E_ARG, "pos/disp must be 16-byte aligned");
   if (!counters) return fail(ctx, FPPG_E_ARG, "null counters");
+  if (list && (n_list < 0 || n_list > n)) return fail(ctx, FPPG_E_ARG, "n_list must be in [0, n]");
   if (n == 0) return FPPG_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int ni = int(n);
+  const int nr = list ? int(n_list) : ni;
+  if (nr == 0) return FPPG_OK;
   PhaseTimer timer(ctx, 3, s);
-  k_project<<<grid_for(ni), kBlock, 0, s>>>(reinterpret_cast<float4*>(pos), owner, reinterpret_cast<const float4*>(disp),
+  k_project<<<grid_for(nr), kBlock, 0, s>>>(reinterpret_cast<float4*>(pos), owner, reinterpret_cast<const float4*>(disp),
                                             ni, feat_seg, feat_u, n_feat, int(geom->n_seg), geom->d_seg, geom->d_geom,
                                             geom->n_geom, geom->d_facet, geom->d_tg_start, geom->d_tg_tri,
                                             geom->d_tg_flag, move_mask, reinterpret_cast<unsigned long long*>(counters),
-                                            ctx->d_status, accepted);
+                                            ctx->d_status, accepted, list, nr);
   FPPG_HIP(ctx, hipGetLastError());
   return FPPG_OK;
 }
@@ -285,8 +290,10 @@ static fppg_status project_impl(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
 
 extern "C" fppg_status fppg_project(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, float* pos, int32_t* owner,
                                     const float* disp, int32_t* feat_seg, double* feat_u, int32_t n_feat,
-                                    uint32_t move_mask, int64_t* counters, void* stream) {
-  return project_impl(ctx, geom, n, pos, owner, disp, feat_seg, feat_u, n_feat, move_mask, counters, nullptr, stream);
+                                    uint32_t move_mask, int64_t* counters, const int32_t* list, int32_t n_list,
+                                    void* stream) {
+  return project_impl(ctx, geom, n, pos, owner, disp, feat_seg, feat_u, n_feat, move_mask, counters, list, n_list,
+                      nullptr, stream);
 }
 
 extern "C" fppg_status fppg_project_record(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, float* pos,
@@ -294,5 +301,6 @@ extern "C" fppg_status fppg_project_record(fppg_ctx* ctx, const fppg_geom* geom,
                                            int32_t n_feat, uint32_t move_mask, int64_t* counters, uint8_t* accepted,
                                            void* stream) {
   if (n > 0 && !accepted) return fail(ctx, FPPG_E_ARG, "null accepted");
-  return project_impl(ctx, geom, n, pos, owner, disp, feat_seg, feat_u, n_feat, move_mask, counters, accepted, stream);
+  return project_impl(ctx, geom, n, pos, owner, disp, feat_seg, feat_u, n_feat, move_mask, counters, nullptr, 0,
+                      accepted, stream);
 }

@@ -161,6 +161,15 @@ class Relaxer:
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.dev)
         off = (-self.ws.data_ptr()) % 256
         self.ws_ptr = ctypes.c_void_p(self.ws.data_ptr() + off)
+        # receiver list (opt-in): only the moving particles' lanes are launched
+        self.use_list = False
+        self._tag_counts = np.bincount(np.asarray(wl.tag, np.int64), minlength=8)
+        self.mlist = torch.zeros(max(self.n, 1), dtype=torch.int32, device=self.dev)
+        self.mcount = torch.zeros(1, dtype=torch.int32, device=self.dev)
+
+    def n_moving(self) -> int:
+        """Particles that move under the current move_mask (classes 1..3)."""
+        return int(sum(self._tag_counts[t] for t in (1, 2, 3) if (self.move_mask >> t) & 1))
 
     # ---- the four entry points -------------------------------------------------------------
     @property
@@ -175,6 +184,17 @@ class Relaxer:
         self.pos, self.pos_b = self.pos_b, self.pos
         self.id, self.id_b = self.id_b, self.id
         self.owner, self.owner_b = self.owner_b, self.owner
+        if self.use_list:
+            self.moving_list()
+
+    def moving_list(self):
+        """Sorted indices of the moving particles into self.mlist (count in self.mcount)."""
+        lib, c = self.ctx.lib, self.ctx.handle
+        check(lib.fppg_moving_list(c, self.geom.handle, self.n, ptr(self.pos), self.move_mask, ptr(self.mlist),
+                                   ptr(self.mcount), self.ws_ptr, self.ws_bytes, self.stream), c)
+
+    def _list_args(self):
+        return (ptr(self.mlist), self.n_moving()) if self.use_list else (None, 0)
 
     def relax_step(self, count_pairs: bool = False, keep_accel: bool = True):
         lib, c = self.ctx.lib, self.ctx.handle
@@ -182,13 +202,13 @@ class Relaxer:
         check(lib.fppg_relax_step(c, self.geom.handle, self.n, ptr(self.pos), ptr(self.owner), ptr(self.cell_start),
                                   ptr(self.feat_seg), self.n_feat, self.move_mask, flags,
                                   ptr(self.accel) if keep_accel else None, ptr(self.amax), ptr(self.disp),
-                                  self.ws_ptr, self.ws_bytes, self.stream), c)
+                                  *self._list_args(), self.ws_ptr, self.ws_bytes, self.stream), c)
 
     def project(self):
         lib, c = self.ctx.lib, self.ctx.handle
         check(lib.fppg_project(c, self.geom.handle, self.n, ptr(self.pos), ptr(self.owner), ptr(self.disp),
                                ptr(self.feat_seg), ptr(self.feat_u), self.n_feat, self.move_mask,
-                               ptr(self.counters), self.stream), c)
+                               ptr(self.counters), *self._list_args(), self.stream), c)
 
     def project_record(self, accepted: torch.Tensor):
         """project() that also writes accepted [N] uint8 (1 = the particle's move was applied)."""

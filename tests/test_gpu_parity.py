@@ -397,12 +397,16 @@ def test_host_side_errors_with_a_live_context():
     assert b"workspace" in L.fppg_last_error(c)
     # particle count differs from the geometry's
     assert L.fppg_relax_step(c, g, r.n + 1, ptr(r.pos), ptr(r.owner), ptr(r.cell_start), ptr(r.feat_seg),
-                             r.n_feat, r.move_mask, 0, None, ptr(r.amax), ptr(r.disp), r.ws_ptr, r.ws_bytes,
-                             st) == _lib.E_ARG
+                             r.n_feat, r.move_mask, 0, None, ptr(r.amax), ptr(r.disp), None, 0, r.ws_ptr,
+                             r.ws_bytes, st) == _lib.E_ARG
+    # a receiver list longer than the particle arrays
+    assert L.fppg_relax_step(c, g, r.n, ptr(r.pos), ptr(r.owner), ptr(r.cell_start), ptr(r.feat_seg),
+                             r.n_feat, r.move_mask, 0, None, ptr(r.amax), ptr(r.disp), ptr(r.mlist), r.n + 1,
+                             r.ws_ptr, r.ws_bytes, st) == _lib.E_ARG
     # misaligned position array
     mis = ctypes.c_void_p(r.pos.data_ptr() + 4)
     assert L.fppg_project(c, g, r.n, mis, ptr(r.owner), ptr(r.disp), ptr(r.feat_seg), ptr(r.feat_u), r.n_feat,
-                          r.move_mask, ptr(r.counters), st) == _lib.E_ARG
+                          r.move_mask, ptr(r.counters), None, 0, st) == _lib.E_ARG
     # aliasing input and output
     assert L.fppg_relax_hvp(c, g, r.n, ptr(r.pos), ptr(r.cell_start), r.move_mask, 0, ptr(r.disp), ptr(r.disp),
                             st) == _lib.E_ARG
@@ -421,3 +425,24 @@ def test_host_side_errors_with_a_live_context():
     # nothing above reached the device
     r.step()
     assert r.read_status() == 0
+
+
+@pytest.mark.parametrize("tier", ["feature", "surface"])
+def test_receiver_list_gives_the_same_iterations(tier):
+    """Relaxing one class with the moving-particle list (only its lanes
+    launched) gives bit for bit the state of the full launch."""
+    mm = {"feature": 1 << synth.FEATURE, "surface": 1 << synth.SURFACE}[tier]
+    wl = synth.gear_workload(dx=0.04, seed=3, samples_per_period=12, rings=4, move_mask=mm)
+    ra, rb = _relaxer(wl), _relaxer(wl)
+    rb.use_list = True
+    for _ in range(3):
+        ra.step()
+        rb.step()
+    assert int(rb.mcount.cpu()[0]) == rb.n_moving() == wl.n_moving()
+    ids = rb.mlist[: rb.n_moving()].cpu().numpy()
+    assert np.all(np.diff(ids) > 0)
+    sa, sb = ra.host_state(), rb.host_state()
+    for x, y in zip(sa, sb):
+        assert np.array_equal(x, y)
+    assert torch.equal(ra.counters, rb.counters)
+    assert ra.read_status() == 0 and rb.read_status() == 0
