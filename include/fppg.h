@@ -147,12 +147,13 @@ const char* fppg_last_error(const fppg_ctx* ctx);   /* never NULL */
 fppg_status fppg_read_status(fppg_ctx* ctx, void* stream, uint32_t* flags);
 
 /*
- * Kernel timing with HIP events recorded on the launch stream. enable != 0
+ * Kernel timing with HIP events recorded on the launch stream. phases: bit p
+ * set times phase p (FPPG_PROFILE_ALL: every phase; 0: off). A nonzero mask
  * creates the events (allocation happens here, not in the hot calls) and
  * resets the accumulators; while enabled, every per-iteration call records an
- * event pair around each of its phases. fppg_profile_read synchronises on the
- * recorded events and returns, per phase, the summed milliseconds and the
- * number of launches:
+ * event pair around each selected phase (each pair adds a little time to the
+ * stream). fppg_profile_read synchronises on the recorded events and returns,
+ * per phase, the summed milliseconds and the number of launches:
  *   0 build_cells (all its kernels)  1 force + amax kernel
  *   2 displacement kernel            3 project (all its kernels)
  *   4 relax_hvp kernel
@@ -160,7 +161,8 @@ fppg_status fppg_read_status(fppg_ctx* ctx, void* stream, uint32_t* flags);
  * kept between reads (further launches are not timed: count stops growing).
  */
 #define FPPG_NPHASES 5
-fppg_status fppg_profile(fppg_ctx* ctx, int32_t enable);
+#define FPPG_PROFILE_ALL 0x1fu
+fppg_status fppg_profile(fppg_ctx* ctx, uint32_t phases);
 fppg_status fppg_profile_read(fppg_ctx* ctx, double* ms /*[FPPG_NPHASES]*/, int64_t* launches /*[FPPG_NPHASES]*/);
 
 /* ---- geometry ----------------------------------------------------------------------------- */
@@ -263,12 +265,15 @@ fppg_status fppg_relax_step(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
  * disp [n*4] from fppg_relax_step; feat_seg/feat_u [n_feat] in/out (may be
  * NULL if n_feat = 0); counters [FPPG_NCOUNTERS] int64 on the device,
  * incremented by the number of reverts per class (FPPG_C_*). list / n_list
- * as in fppg_relax_step (NULL: all particles).
+ * as in fppg_relax_step (NULL: all particles). ws: device workspace, 256-byte
+ * aligned, at least fppg_workspace_size bytes (it queues the surface and
+ * feature particles for a second kernel); its contents are scratch.
  */
 fppg_status fppg_project(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
                          float* pos, int32_t* owner, const float* disp,
                          int32_t* feat_seg, double* feat_u, int32_t n_feat, uint32_t move_mask,
-                         int64_t* counters, const int32_t* list, int32_t n_list, void* stream);
+                         int64_t* counters, const int32_t* list, int32_t n_list, void* ws, size_t ws_bytes,
+                         void* stream);
 
 /*
  * Jacobian-vector product of the force field of fppg_relax_step with respect
@@ -372,12 +377,13 @@ fppg_status fppg_moving_list(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, co
  * fppg_project with a per-particle record of its decisions, for reverse-mode
  * differentiation: accepted [n] uint8 (device) = 1 iff particle i moves
  * (move_mask) and its move was applied, 0 if it was reverted or does not move.
- * Otherwise identical to fppg_project.
+ * Otherwise identical to fppg_project (all particles, no list).
  */
 fppg_status fppg_project_record(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
                                 float* pos, int32_t* owner, const float* disp,
                                 int32_t* feat_seg, double* feat_u, int32_t n_feat, uint32_t move_mask,
-                                int64_t* counters, uint8_t* accepted, void* stream);
+                                int64_t* counters, uint8_t* accepted, void* ws, size_t ws_bytes,
+                                void* stream);
 
 /*
  * Differentiation of a relaxation run with respect to the mesh vertices (an

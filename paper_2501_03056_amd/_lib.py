@@ -39,7 +39,7 @@ _SIGS = {
     "fppg_status_str": (c_char_p, [c_int32]),
     "fppg_last_error": (c_char_p, [_P]),
     "fppg_read_status": (c_int32, [_P, _P, POINTER(c_uint32)]),
-    "fppg_profile": (c_int32, [_P, c_int32]),
+    "fppg_profile": (c_int32, [_P, c_uint32]),
     "fppg_profile_read": (c_int32, [_P, POINTER(c_double), POINTER(c_int64)]),
     "fppg_geom_create": (c_int32, [_P, POINTER(GeomDesc), c_int32, POINTER(c_void_p)]),
     "fppg_geom_destroy": (None, [_P]),
@@ -49,7 +49,8 @@ _SIGS = {
     "fppg_build_cells": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, _P, _P, _P, _P, c_size_t, _P]),
     "fppg_relax_step": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, c_int32, c_uint32, c_uint32,
                                   _P, _P, _P, _P, c_int32, _P, c_size_t, _P]),
-    "fppg_project": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, _P, c_int32, c_uint32, _P, _P, c_int32, _P]),
+    "fppg_project": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, _P, c_int32, c_uint32, _P, _P, c_int32, _P,
+                               c_size_t, _P]),
     "fppg_moving_list": (c_int32, [_P, _P, c_int64, _P, c_uint32, _P, _P, _P, c_size_t, _P]),
     "fppg_relax_hvp": (c_int32, [_P, _P, c_int64, _P, _P, c_uint32, c_int32, _P, _P, _P]),
     "fppg_debug_neighbors": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, c_int32, _P]),
@@ -64,7 +65,8 @@ _SIGS = {
     "fppg_vec_clamp": (c_int32, [_P, c_int64, _P, c_float, _P]),
     "fppg_tangent_project": (c_int32, [_P, _P, c_int64, _P, _P, _P, c_int32, c_uint32, _P, _P]),
     "fppg_displace": (c_int32, [_P, _P, c_int64, _P, _P, _P, c_int32, c_uint32, _P, c_float, _P, _P]),
-    "fppg_project_record": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, _P, c_int32, c_uint32, _P, _P, _P]),
+    "fppg_project_record": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, _P, c_int32, c_uint32, _P, _P, _P,
+                                      c_size_t, _P]),
     "fppg_uniformity_loss": (c_int32, [_P, _P, c_int64, _P, _P, c_uint32, c_double, _P, _P, _P, c_size_t, _P]),
     "fppg_step_adjoint": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, c_int32, c_uint32,
                                     _P, _P, _P, _P, _P]),

@@ -42,9 +42,16 @@ WsLayout ws_layout(const Geom* g, int64_t n) {
   L.list_offs = o; o += up256(4 * (nbl + 2));
   L.list_bsum = o; o += up256(4 * ((nbl + 1 + 4095) / 4096 + 2));
   L.list_end = o;
+  o = 0;
+  const size_t nvb = (N + 255) / 256;   // blocks of the volume pass
+  L.proj_count = o; o += up256(4 * nvb);
+  L.proj_vrev = o;  o += up256(4 * nvb);
+  L.proj_part = o;  o += up256(16 * ((nvb + kHeavyGroup - 1) / kHeavyGroup));
+  L.proj_queue = o; o += up256(4 * (N + 256));   // every entry lies below (launch blocks) * 256
+  L.proj_end = o;
   // relax_energy: one FP64 partial per block of 256; vec_dot: kDotPartials
   L.reduce_end = up256(8 * std::max<size_t>((N + 255) / 256 + 1, kDotPartials));
-  L.total = std::max(std::max(L.build_end, L.list_end), std::max(L.step_end, L.reduce_end));
+  L.total = std::max(std::max(std::max(L.build_end, L.list_end), std::max(L.step_end, L.reduce_end)), L.proj_end);
   return L;
 }
 
@@ -401,7 +408,7 @@ static void destroy_events(fppg_ctx* ctx) {
     p.ms = 0.0;
     p.launches = 0;
   }
-  ctx->profiling = false;
+  ctx->profiling = 0;
 }
 
 void fppg_destroy(fppg_ctx* ctx) {
@@ -411,11 +418,12 @@ void fppg_destroy(fppg_ctx* ctx) {
   delete ctx;
 }
 
-fppg_status fppg_profile(fppg_ctx* ctx, int32_t enable) {
+fppg_status fppg_profile(fppg_ctx* ctx, uint32_t phases) {
   if (!ctx) return FPPG_E_ARG;
   FPPG_HIP(ctx, hipSetDevice(ctx->device));
   destroy_events(ctx);
-  if (!enable) return FPPG_OK;
+  phases &= (1u << FPPG_NPHASES) - 1u;
+  if (!phases) return FPPG_OK;
   for (auto& p : ctx->prof) {
     p.start.resize(kProfSlots);
     p.stop.resize(kProfSlots);
@@ -424,7 +432,7 @@ fppg_status fppg_profile(fppg_ctx* ctx, int32_t enable) {
       FPPG_HIP(ctx, hipEventCreate(&p.stop[i]));
     }
   }
-  ctx->profiling = true;
+  ctx->profiling = phases;
   return FPPG_OK;
 }
 

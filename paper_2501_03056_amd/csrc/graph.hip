@@ -44,7 +44,8 @@ extern "C" fppg_status fppg_graph_create(fppg_ctx* ctx, const fppg_geom* geom, i
       st = fppg_relax_step(ctx, geom, n, po, oo, cell_start, feat_seg, n_feat, move_mask, 0u, nullptr, amax, disp,
                            nullptr, 0, ws, ws_bytes, stream);
     if (st == FPPG_OK)
-      st = fppg_project(ctx, geom, n, po, oo, disp, feat_seg, feat_u, n_feat, move_mask, counters, nullptr, 0, stream);
+      st = fppg_project(ctx, geom, n, po, oo, disp, feat_seg, feat_u, n_feat, move_mask, counters, nullptr, 0, ws,
+                        ws_bytes, stream);
   }
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamEndCapture(s, &graph);

@@ -95,7 +95,7 @@ struct fppg_ctx {
   int device = 0;
   std::string err;
   uint32_t* d_status = nullptr;     // device status word
-  bool profiling = false;
+  uint32_t profiling = 0;   // bit p: time phase p
   fppg::PhaseProf prof[FPPG_NPHASES];
 };
 
@@ -120,7 +120,7 @@ struct PhaseTimer {
   PhaseProf* p = nullptr;
   hipStream_t s;
   PhaseTimer(fppg_ctx* ctx, int phase, hipStream_t stream) : s(stream) {
-    if (ctx && ctx->profiling && ctx->prof[phase].used < kProfSlots) {
+    if (ctx && ((ctx->profiling >> phase) & 1u) && ctx->prof[phase].used < kProfSlots) {
       p = &ctx->prof[phase];
       hipEventRecord(p->start[p->used], s);
     }
@@ -133,6 +133,8 @@ struct PhaseTimer {
   }
 };
 
+constexpr int kHeavyGroup = 8;   // projection: volume-pass blocks served by one block of k_project_heavy
+
 // Workspace layout (byte offsets from the workspace base, 256-aligned).
 struct WsLayout {
   // build_cells
@@ -141,6 +143,9 @@ struct WsLayout {
   size_t accel, step_end;
   // moving_list (block counts, their offsets, scan partials)
   size_t list_cnt, list_offs, list_bsum, list_end;
+  // project (per volume-pass block: queue length and volume reverts; per
+  // k_project_heavy block: revert counts; the queue of surface and feature particles)
+  size_t proj_count, proj_vrev, proj_part, proj_queue, proj_end;
   // relax_energy / vec_dot partial sums
   size_t reduce_end;
   size_t total;

@@ -1,5 +1,6 @@
 // Projection back onto the explicit geometry (section 3.3.3 and 3.3.4), one
-// fused kernel over all particles, one lane per particle:
+// lane per particle in two kernels (volume particles in a lean streaming pass
+// that queues the others; surface and feature particles from that queue):
 //
 //   surface  y = x + dr in FP64; facet search over the search cells in the
 //            order of the paper's reprojection: the particle's own cell
@@ -29,13 +30,6 @@ __device__ __forceinline__ double bary_min(const FacetDev& F, double px, double 
   const double lc = (F.d00 * d21 - F.d01 * d20) * F.inv_den;
   const double la = 1.0 - lb - lc;
   return fmin(la, fmin(lb, lc));
-}
-
-// Count the lanes with `pred` into a counter: one atomic per wavefront that
-// has any. Called where every lane of the wavefront takes part.
-__device__ __forceinline__ void wave_count(bool pred, unsigned long long* __restrict__ ctr) {
-  const uint64_t m = __ballot(pred);
-  if (m && (threadIdx.x & 63) == __ffsll((long long)__ballot(1)) - 1) atomicAdd(ctr, (unsigned long long)__popcll(m));
 }
 
 // Search-cell coordinate of y in cell units, clamped to the grid.
@@ -143,7 +137,8 @@ __device__ __forceinline__ bool segment_crosses(const GeomDev& G, double x0, dou
     for (int y = max(ly, 0); y <= min(hy, G.tg_dims[1] - 1); ++y)
       for (int x = max(lx, 0); x <= min(hx, G.tg_dims[0] - 1); ++x) {
         const int64_t c = search_index(G, x, y, z);
-        if ((tflag[c] & kCellHasFacet) && cell_crossed(c, x0, x1, x2, y0, y1, y2, facets, tstart, ttri)) return true;
+        if ((tflag[c] & kCellHasFacet) && cell_crossed(c, x0, x1, x2, y0, y1, y2, facets, tstart, ttri))
+          return true;
       }
   return false;
 }
@@ -180,26 +175,35 @@ __device__ __forceinline__ bool feature_walk(const SegDev* __restrict__ segs, in
   return u >= 0.0 && u <= segs[s].len;
 }
 
-__global__ __launch_bounds__(kBlock) void k_project(float4* __restrict__ pos, int* __restrict__ owner,
-                                                    const float4* __restrict__ disp, int n,
-                                                    int* __restrict__ feat_seg, double* __restrict__ feat_u,
-                                                    int n_feat, int n_seg, const SegDev* __restrict__ segs,
-                                                    const GeomDev* __restrict__ geoms, int n_geom,
-                                                    const FacetDev* __restrict__ facets,
-                                                    const int* __restrict__ tstart, const int* __restrict__ ttri,
-                                                    const uint8_t* __restrict__ tflag, uint32_t move_mask,
-                                                    unsigned long long* __restrict__ counters, uint32_t* status,
-                                                    uint8_t* __restrict__ accepted, const int* __restrict__ list,
-                                                    int n_list) {
+// Volume particles (and the class dispatch) in a lean kernel; surface and
+// feature particles, whose FP64 searches need several times the registers, go
+// to a queue that k_project_heavy takes: the streaming volume pass keeps a
+// high occupancy. Each block of the volume pass compacts its queued particles
+// (in index order) into its own kBlock slots of the queue and stores their
+// number: no atomics, and the queue is the same on every run.
+// ONE_GEOM: a single geometry, whose descriptor is then read with scalar loads
+// that do not wait for the particle's position.
+template <bool ONE_GEOM>
+__global__ __launch_bounds__(kBlock) void k_project_volume(float4* __restrict__ pos, const float4* __restrict__ disp,
+                                                           int n, const GeomDev* __restrict__ geoms, int n_geom,
+                                                           const FacetDev* __restrict__ facets,
+                                                           const int* __restrict__ tstart,
+                                                           const int* __restrict__ ttri,
+                                                           const uint8_t* __restrict__ tflag, uint32_t move_mask,
+                                                           uint32_t* status, uint8_t* __restrict__ accepted,
+                                                           const int* __restrict__ list, int n_list,
+                                                           int* __restrict__ queue, int* __restrict__ qcount,
+                                                           int* __restrict__ vrev) {
   const int i = listed(blockIdx.x * blockDim.x + threadIdx.x, n, list, n_list);
-  bool rev_s = false, rev_f = false, rev_v = false, moved = false;
+  bool rev_v = false, heavy = false;
   if (i < n) {
     const float4 p = pos[i];
+    const float4 d = disp[i];   // loaded with the position: one memory round trip for both
     const int tag = tag_of(p.w);
+    bool moved = false;
     if (is_moving(tag, move_mask) && isfinite(p.x) && isfinite(p.y) && isfinite(p.z)) {
-      const float4 d = disp[i];
-      const GeomDev& G = geoms[min(geom_of(p.w), n_geom - 1)];
       if (tag == FPPG_TAG_VOLUME) {
+        const GeomDev& G = geoms[ONE_GEOM ? 0 : min(geom_of(p.w), n_geom - 1)];
         const float y0 = p.x + d.x, y1 = p.y + d.y, y2 = p.z + d.z;
         if (!(isfinite(y0) && isfinite(y1) && isfinite(y2))) {
           atomicOr(status, FPPG_S_NONFINITE_POS);
@@ -209,7 +213,82 @@ __global__ __launch_bounds__(kBlock) void k_project(float4* __restrict__ pos, in
           pos[i] = make_float4(y0, y1, y2, p.w);
           moved = true;
         }
-      } else if (tag == FPPG_TAG_SURFACE) {
+      } else {
+        heavy = true;
+      }
+    }
+    if (accepted && !heavy) accepted[i] = moved ? 1 : 0;
+  }
+  // compact the heavy lanes of the block into its queue slots
+  // (and count the block's volume reverts: one store per block, summed by
+  // k_project_heavy and k_project_counts instead of contended atomics)
+  __shared__ int s_wcnt[kBlock / 64], s_wrev[kBlock / 64];
+  const uint64_t m = __ballot(heavy);
+  const int nrev = __popcll(__ballot(rev_v));
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) {
+    s_wcnt[w] = __popcll(m);
+    s_wrev[w] = nrev;
+  }
+  __syncthreads();
+  int base = 0, total = 0, revs = 0;
+#pragma unroll
+  for (int k = 0; k < kBlock / 64; ++k) {
+    base += k < w ? s_wcnt[k] : 0;
+    total += s_wcnt[k];
+    revs += s_wrev[k];
+  }
+  if (heavy) queue[blockIdx.x * kBlock + base + __popcll(m & ((1ull << lane) - 1))] = i;
+  if (threadIdx.x == 0) {
+    qcount[blockIdx.x] = total;
+    vrev[blockIdx.x] = revs;
+  }
+}
+
+// Surface reprojection and feature walks of the queued particles: block b
+// takes the queues of volume-pass blocks [b, b + 1) * kHeavyGroup, read as
+// one list (the counts' prefix sums in LDS).
+__global__ __launch_bounds__(kBlock) void k_project_heavy(float4* __restrict__ pos, int* __restrict__ owner,
+                                                          const float4* __restrict__ disp,
+                                                          int* __restrict__ feat_seg, double* __restrict__ feat_u,
+                                                          int n_feat, int n_seg, const SegDev* __restrict__ segs,
+                                                          const GeomDev* __restrict__ geoms, int n_geom,
+                                                          const FacetDev* __restrict__ facets,
+                                                          const int* __restrict__ tstart,
+                                                          const int* __restrict__ ttri,
+                                                          const uint8_t* __restrict__ tflag,
+                                                          uint32_t* status, uint8_t* __restrict__ accepted,
+                                                          const int* __restrict__ queue,
+                                                          const int* __restrict__ qcount,
+                                                          const int* __restrict__ vrev, int n_vblocks,
+                                                          int4* __restrict__ part) {
+  __shared__ int s_pre[kHeavyGroup + 1];
+  __shared__ int s_rev[2];
+  const int b0 = blockIdx.x * kHeavyGroup;
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int k = 0; k < kHeavyGroup; ++k) {
+      s_pre[k] = acc;
+      acc += b0 + k < n_vblocks ? qcount[b0 + k] : 0;
+    }
+    s_pre[kHeavyGroup] = acc;
+    s_rev[0] = s_rev[1] = 0;
+  }
+  __syncthreads();
+  const int cnt = s_pre[kHeavyGroup];
+  int rs = 0, rf = 0;   // this lane's surface and feature reverts
+  for (int q = threadIdx.x; q < cnt; q += kBlock) {
+    bool rev_s = false, rev_f = false;
+    {
+      int k = 0;
+      while (k + 1 < kHeavyGroup && s_pre[k + 1] <= q) ++k;
+      const int i = queue[(b0 + k) * kBlock + (q - s_pre[k])];
+      const float4 p = pos[i];
+      const int tag = tag_of(p.w);
+      const float4 d = disp[i];
+      const GeomDev& G = geoms[min(geom_of(p.w), n_geom - 1)];
+      bool moved = false;
+      if (tag == FPPG_TAG_SURFACE) {
         const double yx = double(p.x) + double(d.x), yy = double(p.y) + double(d.y), yz = double(p.z) + double(d.z);
         if (!(isfinite(yx) && isfinite(yy) && isfinite(yz))) {
           atomicOr(status, FPPG_S_NONFINITE_POS);
@@ -244,12 +323,46 @@ __global__ __launch_bounds__(kBlock) void k_project(float4* __restrict__ pos, in
           }
         }
       }
+      if (accepted) accepted[i] = moved ? 1 : 0;
     }
-    if (accepted) accepted[i] = moved ? 1 : 0;
+    rs += rev_s;
+    rf += rev_f;
   }
-  wave_count(rev_s, &counters[FPPG_C_REVERT_SURFACE]);
-  wave_count(rev_f, &counters[FPPG_C_REVERT_FEATURE]);
-  wave_count(rev_v, &counters[FPPG_C_REVERT_VOLUME]);
+  if (rs) atomicAdd(&s_rev[0], rs);
+  if (rf) atomicAdd(&s_rev[1], rf);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int rv = 0;
+    for (int k = 0; k < kHeavyGroup; ++k) rv += b0 + k < n_vblocks ? vrev[b0 + k] : 0;
+    part[blockIdx.x] = make_int4(s_rev[0], s_rev[1], rv, 0);
+  }
+}
+
+// Sum the per-block revert counts into the caller's counters (one block).
+__global__ __launch_bounds__(kBlock) void k_project_counts(const int4* __restrict__ part, int n_part,
+                                                           unsigned long long* __restrict__ counters) {
+  __shared__ unsigned long long s[3][kBlock];
+  unsigned long long a = 0, b = 0, c = 0;
+  for (int k = threadIdx.x; k < n_part; k += kBlock) {
+    const int4 v = part[k];
+    a += unsigned(v.x);
+    b += unsigned(v.y);
+    c += unsigned(v.z);
+  }
+  s[0][threadIdx.x] = a;
+  s[1][threadIdx.x] = b;
+  s[2][threadIdx.x] = c;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o)
+      for (int r = 0; r < 3; ++r) s[r][threadIdx.x] += s[r][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (s[0][0]) atomicAdd(&counters[FPPG_C_REVERT_SURFACE], s[0][0]);
+    if (s[1][0]) atomicAdd(&counters[FPPG_C_REVERT_FEATURE], s[1][0]);
+    if (s[2][0]) atomicAdd(&counters[FPPG_C_REVERT_VOLUME], s[2][0]);
+  }
 }
 
 static inline int grid_for(int64_t n) { return int((n + kBlock - 1) / kBlock); }
@@ -263,7 +376,7 @@ namespace {
 static fppg_status project_impl(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, float* pos, int32_t* owner,
                                 const float* disp, int32_t* feat_seg, double* feat_u, int32_t n_feat,
                                 uint32_t move_mask, int64_t* counters, const int32_t* list, int32_t n_list,
-                                uint8_t* accepted, void* stream) {
+                                uint8_t* accepted, void* ws, size_t ws_bytes, void* stream) {
   if (!ctx || !geom) return fail(ctx, FPPG_E_ARG, "null ctx/geom");
   if (n != geom->n_part) return fail(ctx, FPPG_E_ARG, "n differs from the particle count of the geometry descriptors");
   if (n > 0 && (!pos || !owner || !disp)) return fail(ctx, FPPG_E_ARG, "null pos/owner/disp");
@@ -272,16 +385,35 @@ static fppg_status project_impl(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
   if (!counters) return fail(ctx, FPPG_E_ARG, "null counters");
   if (list && (n_list < 0 || n_list > n)) return fail(ctx, FPPG_E_ARG, "n_list must be in [0, n]");
   if (n == 0) return FPPG_OK;
+  const WsLayout L = ws_layout(geom, n);
+  if (!ws || !aligned(ws, 256)) return fail(ctx, FPPG_E_ARG, "ws is null or not 256-byte aligned");
+  if (ws_bytes < L.proj_end) return fail(ctx, FPPG_E_WORKSPACE, "workspace too small for project");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int ni = int(n);
   const int nr = list ? int(n_list) : ni;
   if (nr == 0) return FPPG_OK;
+  int* qcount = reinterpret_cast<int*>(static_cast<char*>(ws) + L.proj_count);
+  int* vrev = reinterpret_cast<int*>(static_cast<char*>(ws) + L.proj_vrev);
+  int4* part = reinterpret_cast<int4*>(static_cast<char*>(ws) + L.proj_part);
+  int* queue = reinterpret_cast<int*>(static_cast<char*>(ws) + L.proj_queue);
+  unsigned long long* ctr = reinterpret_cast<unsigned long long*>(counters);
+  float4* p4 = reinterpret_cast<float4*>(pos);
+  const float4* d4 = reinterpret_cast<const float4*>(disp);
   PhaseTimer timer(ctx, 3, s);
-  k_project<<<grid_for(nr), kBlock, 0, s>>>(reinterpret_cast<float4*>(pos), owner, reinterpret_cast<const float4*>(disp),
-                                            ni, feat_seg, feat_u, n_feat, int(geom->n_seg), geom->d_seg, geom->d_geom,
-                                            geom->n_geom, geom->d_facet, geom->d_tg_start, geom->d_tg_tri,
-                                            geom->d_tg_flag, move_mask, reinterpret_cast<unsigned long long*>(counters),
-                                            ctx->d_status, accepted, list, nr);
+  const int vb = grid_for(nr);
+  if (geom->n_geom == 1)
+    k_project_volume<true><<<vb, kBlock, 0, s>>>(p4, d4, ni, geom->d_geom, 1, geom->d_facet, geom->d_tg_start,
+                                                 geom->d_tg_tri, geom->d_tg_flag, move_mask, ctx->d_status, accepted,
+                                                 list, nr, queue, qcount, vrev);
+  else
+    k_project_volume<false><<<vb, kBlock, 0, s>>>(p4, d4, ni, geom->d_geom, geom->n_geom, geom->d_facet,
+                                                  geom->d_tg_start, geom->d_tg_tri, geom->d_tg_flag, move_mask,
+                                                  ctx->d_status, accepted, list, nr, queue, qcount, vrev);
+  const int hb = (vb + kHeavyGroup - 1) / kHeavyGroup;
+  k_project_heavy<<<hb, kBlock, 0, s>>>(p4, owner, d4, feat_seg, feat_u, n_feat, int(geom->n_seg), geom->d_seg,
+                                        geom->d_geom, geom->n_geom, geom->d_facet, geom->d_tg_start, geom->d_tg_tri,
+                                        geom->d_tg_flag, ctx->d_status, accepted, queue, qcount, vrev, vb, part);
+  k_project_counts<<<1, kBlock, 0, s>>>(part, hb, ctr);
   FPPG_HIP(ctx, hipGetLastError());
   return FPPG_OK;
 }
@@ -291,16 +423,16 @@ static fppg_status project_impl(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
 extern "C" fppg_status fppg_project(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, float* pos, int32_t* owner,
                                     const float* disp, int32_t* feat_seg, double* feat_u, int32_t n_feat,
                                     uint32_t move_mask, int64_t* counters, const int32_t* list, int32_t n_list,
-                                    void* stream) {
+                                    void* ws, size_t ws_bytes, void* stream) {
   return project_impl(ctx, geom, n, pos, owner, disp, feat_seg, feat_u, n_feat, move_mask, counters, list, n_list,
-                      nullptr, stream);
+                      nullptr, ws, ws_bytes, stream);
 }
 
 extern "C" fppg_status fppg_project_record(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, float* pos,
                                            int32_t* owner, const float* disp, int32_t* feat_seg, double* feat_u,
                                            int32_t n_feat, uint32_t move_mask, int64_t* counters, uint8_t* accepted,
-                                           void* stream) {
+                                           void* ws, size_t ws_bytes, void* stream) {
   if (n > 0 && !accepted) return fail(ctx, FPPG_E_ARG, "null accepted");
   return project_impl(ctx, geom, n, pos, owner, disp, feat_seg, feat_u, n_feat, move_mask, counters, nullptr, 0,
-                      accepted, stream);
+                      accepted, ws, ws_bytes, stream);
 }

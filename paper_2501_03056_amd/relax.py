@@ -208,14 +208,14 @@ class Relaxer:
         lib, c = self.ctx.lib, self.ctx.handle
         check(lib.fppg_project(c, self.geom.handle, self.n, ptr(self.pos), ptr(self.owner), ptr(self.disp),
                                ptr(self.feat_seg), ptr(self.feat_u), self.n_feat, self.move_mask,
-                               ptr(self.counters), *self._list_args(), self.stream), c)
+                               ptr(self.counters), *self._list_args(), self.ws_ptr, self.ws_bytes, self.stream), c)
 
     def project_record(self, accepted: torch.Tensor):
         """project() that also writes accepted [N] uint8 (1 = the particle's move was applied)."""
         lib, c = self.ctx.lib, self.ctx.handle
         check(lib.fppg_project_record(c, self.geom.handle, self.n, ptr(self.pos), ptr(self.owner), ptr(self.disp),
                                       ptr(self.feat_seg), ptr(self.feat_u), self.n_feat, self.move_mask,
-                                      ptr(self.counters), ptr(accepted), self.stream), c)
+                                      ptr(self.counters), ptr(accepted), self.ws_ptr, self.ws_bytes, self.stream), c)
 
     def hvp(self, v: torch.Tensor, transpose: bool = False, out: torch.Tensor | None = None) -> torch.Tensor:
         """J v (or J^T v) for v [N, 4] float32 in the current (sorted) order."""
@@ -304,9 +304,13 @@ class Relaxer:
                                        ptr(count), ptr(lst), cap, self.stream), c)
         return count, lst
 
-    def profile(self, enable: bool = True):
-        """Time every phase of the per-iteration calls with HIP events on the launch stream."""
-        check(self.ctx.lib.fppg_profile(self.ctx.handle, int(bool(enable))), self.ctx.handle)
+    def profile(self, enable: bool = True, phases=None):
+        """Time the phases (names of L.PHASES, default all) of the per-iteration calls with HIP events on the
+        launch stream; enable=False stops."""
+        mask = 0
+        if enable:
+            mask = (1 << L.NPHASES) - 1 if phases is None else sum(1 << L.PHASES.index(p) for p in phases)
+        check(self.ctx.lib.fppg_profile(self.ctx.handle, mask), self.ctx.handle)
 
     def profile_read(self) -> dict:
         """{phase: (total ms, launches)} since profiling was enabled."""

@@ -35,11 +35,11 @@ def test_host_side_validation_without_gpu():
     nul = None
     assert L.fppg_build_cells(nul, nul, 0, nul, nul, nul, nul, nul, nul, nul, nul, 0, nul) == _lib.E_ARG
     assert L.fppg_relax_step(nul, nul, 0, nul, nul, nul, nul, 0, 0, 0, nul, nul, nul, nul, 0, nul, 0, nul) == _lib.E_ARG
-    assert L.fppg_project(nul, nul, 0, nul, nul, nul, nul, nul, 0, 0, nul, nul, 0, nul) == _lib.E_ARG
+    assert L.fppg_project(nul, nul, 0, nul, nul, nul, nul, nul, 0, 0, nul, nul, 0, nul, 0, nul) == _lib.E_ARG
     assert L.fppg_moving_list(nul, nul, 0, nul, 0, nul, nul, nul, 0, nul) == _lib.E_ARG
     assert L.fppg_relax_hvp(nul, nul, 0, nul, nul, 0, 0, nul, nul, nul) == _lib.E_ARG
     assert L.fppg_debug_neighbors(nul, nul, 0, nul, nul, nul, nul, 0, nul) == _lib.E_ARG
-    assert L.fppg_project_record(nul, nul, 0, nul, nul, nul, nul, nul, 0, 0, nul, nul, nul) == _lib.E_ARG
+    assert L.fppg_project_record(nul, nul, 0, nul, nul, nul, nul, nul, 0, 0, nul, nul, nul, 0, nul) == _lib.E_ARG
     assert L.fppg_uniformity_loss(nul, nul, 0, nul, nul, 0, 1.0, nul, nul, nul, 0, nul) == _lib.E_ARG
     assert L.fppg_step_adjoint(nul, nul, 0, nul, nul, nul, nul, nul, nul, nul, nul, nul, 0, 0, nul, nul, nul, nul,
                                nul) == _lib.E_ARG

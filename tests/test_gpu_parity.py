@@ -406,7 +406,7 @@ def test_host_side_errors_with_a_live_context():
     # misaligned position array
     mis = ctypes.c_void_p(r.pos.data_ptr() + 4)
     assert L.fppg_project(c, g, r.n, mis, ptr(r.owner), ptr(r.disp), ptr(r.feat_seg), ptr(r.feat_u), r.n_feat,
-                          r.move_mask, ptr(r.counters), None, 0, st) == _lib.E_ARG
+                          r.move_mask, ptr(r.counters), None, 0, r.ws_ptr, r.ws_bytes, st) == _lib.E_ARG
     # aliasing input and output
     assert L.fppg_relax_hvp(c, g, r.n, ptr(r.pos), ptr(r.cell_start), r.move_mask, 0, ptr(r.disp), ptr(r.disp),
                             st) == _lib.E_ARG
