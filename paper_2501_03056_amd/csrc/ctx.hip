@@ -46,7 +46,7 @@ WsLayout ws_layout(const Geom* g, int64_t n) {
   const size_t nvb = (N + 255) / 256;   // blocks of the volume pass
   L.proj_count = o; o += up256(4 * nvb);
   L.proj_vrev = o;  o += up256(4 * nvb);
-  L.proj_part = o;  o += up256(16 * ((nvb + kHeavyGroup - 1) / kHeavyGroup));
+  L.proj_part = o;  o += up256(16 * nvb);   // one per k_project_heavy block (at most one per volume block)
   L.proj_queue = o; o += up256(4 * (N + 256));   // every entry lies below (launch blocks) * 256
   L.proj_end = o;
   // relax_energy: one FP64 partial per block of 256; vec_dot: kDotPartials

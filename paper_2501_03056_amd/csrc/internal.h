@@ -133,7 +133,7 @@ struct PhaseTimer {
   }
 };
 
-constexpr int kHeavyGroup = 8;   // projection: volume-pass blocks served by one block of k_project_heavy
+constexpr int kHeavyGroupMax = 8;   // projection: volume-pass blocks served by one block of k_project_heavy (at most)
 
 // Workspace layout (byte offsets from the workspace base, 256-aligned).
 struct WsLayout {

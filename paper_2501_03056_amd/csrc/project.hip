@@ -246,8 +246,11 @@ __global__ __launch_bounds__(kBlock) void k_project_volume(float4* __restrict__ 
 }
 
 // Surface reprojection and feature walks of the queued particles: block b
-// takes the queues of volume-pass blocks [b, b + 1) * kHeavyGroup, read as
-// one list (the counts' prefix sums in LDS).
+// takes the queues of volume-pass blocks [b, b + 1) * group, read as one list
+// (the counts' prefix sums in LDS). group is 1 when every moving particle
+// goes to the queue (no volume particle moves: dense queues, one block each)
+// and kHeavyGroupMax otherwise (a few queued particles per volume block, packed
+// into fuller wavefronts).
 __global__ __launch_bounds__(kBlock) void k_project_heavy(float4* __restrict__ pos, int* __restrict__ owner,
                                                           const float4* __restrict__ disp,
                                                           int* __restrict__ feat_seg, double* __restrict__ feat_u,
@@ -260,28 +263,28 @@ __global__ __launch_bounds__(kBlock) void k_project_heavy(float4* __restrict__ p
                                                           uint32_t* status, uint8_t* __restrict__ accepted,
                                                           const int* __restrict__ queue,
                                                           const int* __restrict__ qcount,
-                                                          const int* __restrict__ vrev, int n_vblocks,
+                                                          const int* __restrict__ vrev, int n_vblocks, int group,
                                                           int4* __restrict__ part) {
-  __shared__ int s_pre[kHeavyGroup + 1];
+  __shared__ int s_pre[kHeavyGroupMax + 1];
   __shared__ int s_rev[2];
-  const int b0 = blockIdx.x * kHeavyGroup;
+  const int b0 = blockIdx.x * group;
   if (threadIdx.x == 0) {
     int acc = 0;
-    for (int k = 0; k < kHeavyGroup; ++k) {
+    for (int k = 0; k < group; ++k) {
       s_pre[k] = acc;
       acc += b0 + k < n_vblocks ? qcount[b0 + k] : 0;
     }
-    s_pre[kHeavyGroup] = acc;
+    s_pre[group] = acc;
     s_rev[0] = s_rev[1] = 0;
   }
   __syncthreads();
-  const int cnt = s_pre[kHeavyGroup];
+  const int cnt = s_pre[group];
   int rs = 0, rf = 0;   // this lane's surface and feature reverts
   for (int q = threadIdx.x; q < cnt; q += kBlock) {
     bool rev_s = false, rev_f = false;
     {
       int k = 0;
-      while (k + 1 < kHeavyGroup && s_pre[k + 1] <= q) ++k;
+      while (k + 1 < group && s_pre[k + 1] <= q) ++k;
       const int i = queue[(b0 + k) * kBlock + (q - s_pre[k])];
       const float4 p = pos[i];
       const int tag = tag_of(p.w);
@@ -333,7 +336,7 @@ __global__ __launch_bounds__(kBlock) void k_project_heavy(float4* __restrict__ p
   __syncthreads();
   if (threadIdx.x == 0) {
     int rv = 0;
-    for (int k = 0; k < kHeavyGroup; ++k) rv += b0 + k < n_vblocks ? vrev[b0 + k] : 0;
+    for (int k = 0; k < group; ++k) rv += b0 + k < n_vblocks ? vrev[b0 + k] : 0;
     part[blockIdx.x] = make_int4(s_rev[0], s_rev[1], rv, 0);
   }
 }
@@ -409,10 +412,12 @@ static fppg_status project_impl(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
     k_project_volume<false><<<vb, kBlock, 0, s>>>(p4, d4, ni, geom->d_geom, geom->n_geom, geom->d_facet,
                                                   geom->d_tg_start, geom->d_tg_tri, geom->d_tg_flag, move_mask,
                                                   ctx->d_status, accepted, list, nr, queue, qcount, vrev);
-  const int hb = (vb + kHeavyGroup - 1) / kHeavyGroup;
+  const int group = (move_mask >> FPPG_TAG_VOLUME) & 1u ? kHeavyGroupMax : 1;
+  const int hb = (vb + group - 1) / group;
   k_project_heavy<<<hb, kBlock, 0, s>>>(p4, owner, d4, feat_seg, feat_u, n_feat, int(geom->n_seg), geom->d_seg,
                                         geom->d_geom, geom->n_geom, geom->d_facet, geom->d_tg_start, geom->d_tg_tri,
-                                        geom->d_tg_flag, ctx->d_status, accepted, queue, qcount, vrev, vb, part);
+                                        geom->d_tg_flag, ctx->d_status, accepted, queue, qcount, vrev, vb, group,
+                                        part);
   k_project_counts<<<1, kBlock, 0, s>>>(part, hb, ctr);
   FPPG_HIP(ctx, hipGetLastError());
   return FPPG_OK;
