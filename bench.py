@@ -162,7 +162,11 @@ def bench_gear(args):
     """The gear relaxed in three tiers (feature lines, then surface, then
     volume particles; the other classes are fixed sources of the moving one),
     --tier-iters iterations each on the same state. value = sum over tiers of
-    moving particles x iterations / total seconds."""
+    moving particles x iterations / total seconds. Then the three-layer
+    variant of the volume tier (section 3.3.4): the volume particles deeper
+    than --layer-width dx become a fixed core and only the layer above it
+    relaxes (reported under "three_layer", with the feature and surface tiers,
+    and not in value)."""
     import torch
     import synth
     from paper_2501_03056_amd import Relaxer
@@ -176,11 +180,20 @@ def bench_gear(args):
     t0 = time.perf_counter()
     r = Relaxer(wl, device=0)
     print(f"[bench] geometry on the device in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
-    tiers = [("feature", 1 << synth.FEATURE), ("surface", 1 << synth.SURFACE), ("volume", 1 << synth.VOLUME)]
+    tiers = [("feature", 1 << synth.FEATURE), ("surface", 1 << synth.SURFACE), ("volume", 1 << synth.VOLUME),
+             ("volume_layer", 1 << synth.VOLUME)]
     out_tiers, total_s, total_upd = {}, 0.0, 0.0
+    layer = {}
     for name, mm in tiers:
+        if name == "volume_layer":
+            # three-layer volume relaxation (section 3.3.4): the volume particles
+            # deeper than the layer width become the fixed core
+            width = args.layer_width * dx
+            layer = {"width": width, "width_dx": args.layer_width, "core": r.volume_layers(width)}
+            print(f"[bench] volume layer: width {width:g}, {layer['core']} particles fixed as the core",
+                  file=sys.stderr, flush=True)
         r.move_mask = mm
-        n_moving = int(np.sum((mm >> wl.tag) & 1))
+        n_moving = r.n_moving()
         # a sparse tier launches only its moving particles' lanes
         r.use_list = not args.no_list and n_moving < wl.n // 2
         for _ in range(args.warmup):
@@ -202,8 +215,9 @@ def bench_gear(args):
             r.step(keep_accel=False)
         prof = r.profile_read()
         r.profile(False)
-        total_s += ms / 1e3
-        total_upd += n_moving * args.tier_iters
+        if name != "volume_layer":
+            total_s += ms / 1e3
+            total_upd += n_moving * args.tier_iters
         out_tiers[name] = {"moving": n_moving, "iters": args.tier_iters, "ms_per_step": ms / args.tier_iters,
                            "particle_updates_per_s": n_moving * args.tier_iters / (ms / 1e3),
                            "pairs_per_step": pairs, "pair_evals_per_s": pairs * args.tier_iters / (ms / 1e3),
@@ -211,6 +225,9 @@ def bench_gear(args):
                            "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]}}
         print(f"[bench] tier {name}: {n_moving} moving, {ms / args.tier_iters:.3f} ms/step", file=sys.stderr,
               flush=True)
+    t3 = [out_tiers[k] for k in ("feature", "surface", "volume_layer")]
+    three_layer = {"particle_updates_per_s": sum(t["moving"] * t["iters"] for t in t3)
+                   / sum(t["ms_per_step"] * t["iters"] / 1e3 for t in t3), **layer}
     out = {"metric": "particle-updates/s", "value": total_upd / total_s, "unit": "particle-updates/s",
            "n_gpus": 1, "steps": 3 * args.tier_iters, "warmup": 3 * args.warmup,
            "ms_per_step": 1e3 * total_s / (3 * args.tier_iters), "higher_is_better": True, "scaling": "weak",
@@ -218,7 +235,7 @@ def bench_gear(args):
            "config": {"workload": f"gear24_dx{dx:g}_tiers_feature_surface_volume", "particles": wl.n,
                       "counts": wl.counts(), "facets": int(r.geom.n_tri), "stencil_k": int(wl.geoms[0].k),
                       "key_slab_rows": int(args.slab)},
-           "tiers": out_tiers, "device_status": r.read_status()}
+           "tiers": out_tiers, "three_layer": three_layer, "device_status": r.read_status()}
     print(json.dumps(out), flush=True)
 
 
@@ -301,6 +318,8 @@ def main():
     ap.add_argument("--mode", default="step", choices=["step", "batch", "newton", "gear"])
     ap.add_argument("--gear-dx", type=float, default=0.004)
     ap.add_argument("--tier-iters", type=int, default=100)
+    ap.add_argument("--layer-width", type=float, default=3.0,
+                    help="gear: width of the relaxed volume layer in units of dx (three-layer tier)")
     ap.add_argument("--no-list", action="store_true",
                     help="gear tiers: launch every particle's lane instead of the moving-particle list")
     ap.add_argument("--plain-iters", type=int, default=100)

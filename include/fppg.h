@@ -374,6 +374,22 @@ fppg_status fppg_moving_list(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, co
                              void* stream);
 
 /*
+ * Three-layer volume relaxation (section 3.3.4): re-tag as fixed
+ * (FPPG_TAG_FIXED) every volume particle whose distance to its geometry's
+ * surface mesh is at least width; the volume particles closer than width are
+ * the intermediate layer that a volume tier then relaxes, with the surface
+ * particles and the fixed core as sources. The distance is the exact FP64
+ * point-triangle distance from the binary32 position to the facets registered
+ * in the facet search cells that the box [x - width, x + width] touches.
+ * pos [n*4] in/out (device; only the tag bits of w change); width: finite,
+ * >= 0 (the same for every geometry); count [1] int32 (device): the number of
+ * particles re-tagged. Non-finite positions keep their tags. Called once,
+ * before the relaxation; its cost grows with (width / search cell edge)^3.
+ */
+fppg_status fppg_volume_layers(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, float* pos, double width,
+                               int32_t* count, void* stream);
+
+/*
  * fppg_project with a per-particle record of its decisions, for reverse-mode
  * differentiation: accepted [n] uint8 (device) = 1 iff particle i moves
  * (move_mask) and its move was applied, 0 if it was reverted or does not move.

@@ -16,8 +16,9 @@
 //            bounding box touches (padded by 1e-7 cell). Away from the
 //            surface those cells hold no facet and the move is accepted after
 //            one byte of flags.
-// Reverts are counted per class with one atomic per wavefront that has any.
-#include "internal.h"
+// Reverts are counted per block and added to the caller's counters by one
+// small kernel.
+#include "search_grid.h"
 
 namespace fppg {
 
@@ -30,15 +31,6 @@ __device__ __forceinline__ double bary_min(const FacetDev& F, double px, double 
   const double lc = (F.d00 * d21 - F.d01 * d20) * F.inv_den;
   const double la = 1.0 - lb - lc;
   return fmin(la, fmin(lb, lc));
-}
-
-// Search-cell coordinate of y in cell units, clamped to the grid.
-__device__ __forceinline__ double search_t(const GeomDev& G, int a, double y) {
-  return fmin(fmax((y - G.tg_origin[a]) * G.tg_inv, 0.0), double(G.tg_dims[a] - 1));
-}
-
-__device__ __forceinline__ int64_t search_index(const GeomDev& G, int x, int y, int z) {
-  return G.tg_begin + (int64_t(z) * G.tg_dims[1] + y) * G.tg_dims[0] + x;
 }
 
 __device__ __forceinline__ double gap1(int d, double f) {

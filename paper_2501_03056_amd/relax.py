@@ -193,6 +193,18 @@ class Relaxer:
         check(lib.fppg_moving_list(c, self.geom.handle, self.n, ptr(self.pos), self.move_mask, ptr(self.mlist),
                                    ptr(self.mcount), self.ws_ptr, self.ws_bytes, self.stream), c)
 
+    def volume_layers(self, width: float) -> int:
+        """Three-layer volume relaxation: volume particles at distance >= width from the surface become fixed
+        (the core); returns how many. The others remain volume particles (the layer a volume tier relaxes)."""
+        lib, c = self.ctx.lib, self.ctx.handle
+        cnt = torch.zeros(1, dtype=torch.int32, device=self.dev)
+        check(lib.fppg_volume_layers(c, self.geom.handle, self.n, ptr(self.pos), float(width), ptr(cnt),
+                                     self.stream), c)
+        k = int(cnt.cpu()[0])
+        self._tag_counts[3] -= k
+        self._tag_counts[4] += k
+        return k
+
     def _list_args(self):
         return (ptr(self.mlist), self.n_moving()) if self.use_list else (None, 0)
 
