@@ -104,6 +104,43 @@ def cpu_baseline(wl, sample=160, seed=0):
                       f"({dt:.1f} s, numpy single thread)"}
 
 
+def bench_generate(args):
+    """The generation front end (fppg_generate: background-grid classes and the
+    initial particles) on the 24-tooth gear mesh at spacing --gear-dx; value =
+    background cells classified per second (the call's wall time, device
+    temporaries and host-device copies included; best of 3)."""
+    import torch
+    from synth import meshes as M
+    from paper_2501_03056_amd import Context
+    from paper_2501_03056_amd.front import generate
+    dx = args.gear_dx
+    mesh = M.gear()
+    lo, hi = mesh.vert.min(0) - 2 * dx, mesh.vert.max(0) + 2 * dx
+    dims = tuple(int(v) for v in np.ceil((hi - lo) / dx))
+    ctx = Context(0)
+    cap = int(np.prod(dims))
+    times = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cls, pos, owner = generate(mesh.vert, mesh.tri, dx, lo, dims, ctx=ctx, cap=cap)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    tags = (pos[:, 3].contiguous().view(torch.int32) & 7).cpu().numpy()
+    ncell = int(np.prod(dims))
+    t = min(times)
+    out = {"metric": "background cells classified/s", "value": ncell / t, "unit": "cells/s", "n_gpus": 1,
+           "steps": 3, "warmup": 0, "ms_per_step": 1e3 * t, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"gear24_generate_dx{dx:g}", "facets": int(len(mesh.tri)), "dims": list(dims),
+                      "cells": ncell},
+           "particles": {"volume": int(np.sum(tags == 3)), "surface": int(np.sum(tags == 2))},
+           "cell_classes": {k: int(v) for k, v in zip(("external", "internal", "surface"),
+                                                       np.bincount(cls.cpu().numpy().ravel(), minlength=3))},
+           "seconds_all": times}
+    print(json.dumps(out), flush=True)
+
+
 def bench_batch(args):
     """64 independent solids (boxes and cylinders, 5k-500k particles each) in
     one launch per kernel; stencil half-width and launch mode (eager or HIP
@@ -315,7 +352,7 @@ def bench_newton(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--mode", default="step", choices=["step", "batch", "newton", "gear"])
+    ap.add_argument("--mode", default="step", choices=["step", "batch", "newton", "gear", "generate"])
     ap.add_argument("--gear-dx", type=float, default=0.004)
     ap.add_argument("--tier-iters", type=int, default=100)
     ap.add_argument("--layer-width", type=float, default=3.0,
@@ -344,6 +381,8 @@ def main():
         sys.exit(2)
     if args.mode == "batch":
         return bench_batch(args)
+    if args.mode == "generate":
+        return bench_generate(args)
     if args.mode == "newton":
         return bench_newton(args)
     if args.mode == "gear":

@@ -374,6 +374,40 @@ fppg_status fppg_moving_list(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, co
                              void* stream);
 
 /*
+ * Particle generation front end (sections 3.1.1, 3.1.2, 3.2.1): on the
+ * uniform background grid of edge dx with cell (i, j, k) spanning
+ * origin + [i, i+1) dx etc. (centre origin + (i + 0.5) dx, FP64), classify
+ * every cell and seed the initial particles of one closed mesh:
+ *   surface   the cell's closed box meets a facet (separating-axis
+ *             triangle-box test, FP64; touching counts);
+ *   internal  not surface, and the vertical segment from below the mesh up
+ *             to the centre crosses an odd number of facets (ray casting;
+ *             a column through a shared edge or vertex of the facets' xy
+ *             projections is counted once by an edge fill rule; vertical
+ *             facets are not crossed);
+ *   external  otherwise.
+ * A volume particle is placed at the centre of every internal cell and a
+ * surface particle at the projection of every surface cell's centre along the
+ * normal of the facet meeting the cell whose foot lies inside it and whose
+ * |plane distance| is smallest (ties: lowest facet); a surface cell without
+ * such a facet gets no particle.
+ * vert [n_vert*3] double, tri [n_tri*3] int32: host arrays, as in
+ * fppg_geom_desc. origin [3] double, dims [3] int32: host; dims product below
+ * 2^31. cell_class [dims[2]][dims[1]][dims[0]] uint8 (device, out): 0
+ * external, 1 internal, 2 surface. pos [cap*4] float (device, 16-byte
+ * aligned, out): particles in cell order (x fastest), w = the tag bits
+ * (FPPG_TAG_VOLUME or FPPG_TAG_SURFACE, geometry 0); owner [cap] int32
+ * (device, out): the facet of a surface particle, -1 for a volume particle.
+ * counts [2] int64 (host, out): volume and surface particles written. More
+ * particles than cap: FPPG_E_CAPACITY, counts[0] = -1 and counts[1] = the
+ * total (call again with cap >= it). A set-up call: it allocates its device
+ * temporaries (about 13 bytes per cell) and synchronises the stream.
+ */
+fppg_status fppg_generate(fppg_ctx* ctx, const double* vert, int32_t n_vert, const int32_t* tri, int32_t n_tri,
+                          double dx, const double* origin, const int32_t* dims, uint8_t* cell_class, float* pos,
+                          int32_t* owner, int64_t cap, int64_t* counts, void* stream);
+
+/*
  * Three-layer volume relaxation (section 3.3.4): re-tag as fixed
  * (FPPG_TAG_FIXED) every volume particle whose distance to its geometry's
  * surface mesh is at least width; the volume particles closer than width are

@@ -1,0 +1,437 @@
+// Particle generation front end (sections 3.1.1, 3.1.2 and 3.2.1): classify
+// the cells of a uniform background grid of edge dx as surface, internal or
+// external, then seed a volume particle at the centre of every internal cell
+// and a surface particle at the projection of every surface cell's centre
+// onto its nearest facet.
+//
+//   surface cells   one wavefront per facet walks the cells of the facet's
+//                   bounding box (widened by a cell) and applies the
+//                   separating-axis triangle-box test (box normals, facet
+//                   normal, the 9 products of box axes and facet edges),
+//                   closed: touching counts. The paper first subdivides
+//                   facets until their box spans at most one cell; a cell
+//                   meets a facet iff it meets one of its sub-triangles, so
+//                   walking the whole box gives the same cells.
+//   ray parity      one wavefront per facet walks the columns under the
+//                   facet's xy box; a column whose centre lies in the
+//                   facet's xy projection (counter-clockwise, a point on an
+//                   edge counted only for edges pointing down in y, or along
+//                   -x when horizontal, each edge function evaluated with the
+//                   endpoints in lexicographic order so that two facets
+//                   sharing an edge see opposite values) toggles the parity
+//                   bit of the first cell whose centre lies above the
+//                   crossing; a prefix XOR up each column gives the parity
+//                   of the crossings below every centre. Internal = odd and
+//                   not surface. Vertical facets (zero projected area) are
+//                   not crossed.
+//   surface mapping among the facets meeting a surface cell, the projection
+//                   of the centre along the facet normal whose foot lies
+//                   inside the facet (barycentric >= 0) with the smallest
+//                   |plane distance| (ties: lowest facet), by two passes of
+//                   64-bit / 32-bit atomicMin per cell; none: discarded.
+//   output          particles in cell order (z, y, x; x fastest) by a
+//                   three-phase count / scan / write.
+//
+// All arithmetic is FP64 with the sums of three products taken left to
+// right and no contraction (the build's -ffp-contract=off), so the classes
+// are those of the plain definition evaluated in the same order.
+#include "internal.h"
+
+namespace fppg {
+
+namespace gen {
+
+constexpr uint8_t kExternal = 0, kInternal = 1, kSurface = 2;
+constexpr int kWave = 64;
+constexpr int kScanBlock = 1024;
+
+struct Grid {
+  double o[3];
+  double dx;
+  int n[3];
+};
+
+__device__ __forceinline__ double centre(const Grid& g, int a, int i) { return g.o[a] + (double(i) + 0.5) * g.dx; }
+
+__device__ __forceinline__ int64_t cell_index(const Grid& g, int i, int j, int k) {
+  return (int64_t(k) * g.n[1] + j) * g.n[0] + i;
+}
+
+// Cell range of [lo, hi] along axis a, widened by one cell, clamped.
+__device__ __forceinline__ void cell_range(const Grid& g, int a, double lo, double hi, int& i0, int& i1) {
+  i0 = min(max(int(floor((lo - g.o[a]) / g.dx)) - 1, 0), g.n[a] - 1);
+  i1 = min(max(int(floor((hi - g.o[a]) / g.dx)) + 1, 0), g.n[a] - 1);
+}
+
+struct Tri {
+  double a[3], b[3], c[3];
+};
+
+__device__ __forceinline__ Tri load_tri(const double* __restrict__ vert, const int* __restrict__ tri, int t) {
+  Tri T;
+  const int ia = tri[3 * t], ib = tri[3 * t + 1], ic = tri[3 * t + 2];
+  for (int q = 0; q < 3; ++q) {
+    T.a[q] = vert[3 * ia + q];
+    T.b[q] = vert[3 * ib + q];
+    T.c[q] = vert[3 * ic + q];
+  }
+  return T;
+}
+
+__device__ __forceinline__ bool separated(double p0, double p1, double p2, double r) {
+  return fmin(fmin(p0, p1), p2) > r || fmax(fmax(p0, p1), p2) < -r;
+}
+
+// Separating-axis test of triangle T against the box of centre c, half-width h.
+__device__ bool tri_box(const Tri& T, const double c[3], double h) {
+  double v0[3], v1[3], v2[3];
+  for (int q = 0; q < 3; ++q) {
+    v0[q] = T.a[q] - c[q];
+    v1[q] = T.b[q] - c[q];
+    v2[q] = T.c[q] - c[q];
+  }
+  double e[3][3];
+  for (int q = 0; q < 3; ++q) {
+    e[0][q] = v1[q] - v0[q];
+    e[1][q] = v2[q] - v1[q];
+    e[2][q] = v0[q] - v2[q];
+  }
+  // axes e_k x f: (0, -f2, f1), (f2, 0, -f0), (-f1, f0, 0)
+  for (int m = 0; m < 3; ++m) {
+    const double f0 = e[m][0], f1 = e[m][1], f2 = e[m][2];
+    {
+      const double r = h * fabs(f2) + h * fabs(f1);
+      if (separated(v0[1] * -f2 + v0[2] * f1, v1[1] * -f2 + v1[2] * f1, v2[1] * -f2 + v2[2] * f1, r)) return false;
+    }
+    {
+      const double r = h * fabs(f2) + h * fabs(f0);
+      if (separated(v0[0] * f2 + v0[2] * -f0, v1[0] * f2 + v1[2] * -f0, v2[0] * f2 + v2[2] * -f0, r)) return false;
+    }
+    {
+      const double r = h * fabs(f1) + h * fabs(f0);
+      if (separated(v0[0] * -f1 + v0[1] * f0, v1[0] * -f1 + v1[1] * f0, v2[0] * -f1 + v2[1] * f0, r)) return false;
+    }
+  }
+  for (int q = 0; q < 3; ++q)
+    if (fmin(fmin(v0[q], v1[q]), v2[q]) > h || fmax(fmax(v0[q], v1[q]), v2[q]) < -h) return false;
+  const double nx = e[0][1] * e[1][2] - e[0][2] * e[1][1];
+  const double ny = e[0][2] * e[1][0] - e[0][0] * e[1][2];
+  const double nz = e[0][0] * e[1][1] - e[0][1] * e[1][0];
+  const double d = (nx * v0[0] + ny * v0[1]) + nz * v0[2];
+  const double r = (h * fabs(nx) + h * fabs(ny)) + h * fabs(nz);
+  return !(fabs(d) > r);
+}
+
+// Projection of c along the unit normal of T: plane distance d, foot p, and
+// whether the foot lies in T (all barycentric coordinates >= 0).
+__device__ bool project_inside(const Tri& T, const double c[3], double& d, double p[3]) {
+  double e0[3], e1[3];
+  for (int q = 0; q < 3; ++q) {
+    e0[q] = T.b[q] - T.a[q];
+    e1[q] = T.c[q] - T.a[q];
+  }
+  double n[3] = {e0[1] * e1[2] - e0[2] * e1[1], e0[2] * e1[0] - e0[0] * e1[2], e0[0] * e1[1] - e0[1] * e1[0]};
+  const double len = sqrt((n[0] * n[0] + n[1] * n[1]) + n[2] * n[2]);
+  for (int q = 0; q < 3; ++q) n[q] = n[q] / len;
+  d = ((c[0] - T.a[0]) * n[0] + (c[1] - T.a[1]) * n[1]) + (c[2] - T.a[2]) * n[2];
+  double v[3];
+  for (int q = 0; q < 3; ++q) {
+    p[q] = c[q] - d * n[q];
+    v[q] = p[q] - T.a[q];
+  }
+  const double d00 = (e0[0] * e0[0] + e0[1] * e0[1]) + e0[2] * e0[2];
+  const double d01 = (e0[0] * e1[0] + e0[1] * e1[1]) + e0[2] * e1[2];
+  const double d11 = (e1[0] * e1[0] + e1[1] * e1[1]) + e1[2] * e1[2];
+  const double d20 = (v[0] * e0[0] + v[1] * e0[1]) + v[2] * e0[2];
+  const double d21 = (v[0] * e1[0] + v[1] * e1[1]) + v[2] * e1[2];
+  const double den = d00 * d11 - d01 * d01;
+  const double lb = (d11 * d20 - d01 * d21) / den;
+  const double lc = (d00 * d21 - d01 * d20) / den;
+  return fmin(fmin(1.0 - lb - lc, lb), lc) >= 0.0;
+}
+
+__global__ __launch_bounds__(kWave) void k_surface_cells(const double* __restrict__ vert, const int* __restrict__ tri,
+                                                          Grid g, uint8_t* __restrict__ cls,
+                                                          unsigned long long* __restrict__ dkey, int pass,
+                                                          int* __restrict__ best) {
+  const int t = blockIdx.x;
+  const Tri T = load_tri(vert, tri, t);
+  int r0[3], r1[3];
+  for (int a = 0; a < 3; ++a) {
+    const double lo = fmin(fmin(T.a[a], T.b[a]), T.c[a]), hi = fmax(fmax(T.a[a], T.b[a]), T.c[a]);
+    cell_range(g, a, lo, hi, r0[a], r1[a]);
+  }
+  const int sx = r1[0] - r0[0] + 1, sy = r1[1] - r0[1] + 1, sz = r1[2] - r0[2] + 1;
+  const int64_t cnt = int64_t(sx) * sy * sz;
+  const double h = 0.5 * g.dx;
+  for (int64_t q = threadIdx.x; q < cnt; q += kWave) {
+    const int i = r0[0] + int(q % sx), j = r0[1] + int((q / sx) % sy), k = r0[2] + int(q / (int64_t(sx) * sy));
+    const double c[3] = {centre(g, 0, i), centre(g, 1, j), centre(g, 2, k)};
+    if (!tri_box(T, c, h)) continue;
+    const int64_t cell = cell_index(g, i, j, k);
+    double d, p[3];
+    const bool in = project_inside(T, c, d, p);
+    const unsigned long long key = __double_as_longlong(fabs(d));
+    if (pass == 0) {
+      cls[cell] = kSurface;
+      if (in) atomicMin(&dkey[cell], key);
+    } else if (in && key == dkey[cell]) {
+      atomicMin(&best[cell], t);
+    }
+  }
+}
+
+// Edge function of the directed edge (ax, ay) -> (bx, by) at (px, py), with
+// the endpoints taken in lexicographic order and the sign restored.
+__device__ __forceinline__ double edge_fn(double ax, double ay, double bx, double by, double px, double py) {
+  const bool swap = ax > bx || (ax == bx && ay > by);
+  const double ux = swap ? bx : ax, uy = swap ? by : ay, wx = swap ? ax : bx, wy = swap ? ay : by;
+  const double e = (wx - ux) * (py - uy) - (wy - uy) * (px - ux);
+  return swap ? -e : e;
+}
+
+__device__ __forceinline__ bool edge_in(double ax, double ay, double bx, double by, double px, double py) {
+  const double e = edge_fn(ax, ay, bx, by, px, py);
+  const double dxe = bx - ax, dye = by - ay;
+  return e > 0.0 || (e == 0.0 && (dye < 0.0 || (dye == 0.0 && dxe < 0.0)));
+}
+
+__global__ __launch_bounds__(kWave) void k_ray_crossings(const double* __restrict__ vert, const int* __restrict__ tri,
+                                                          Grid g, unsigned* __restrict__ toggle) {
+  const int t = blockIdx.x;
+  const Tri T = load_tri(vert, tri, t);
+  const double p0x = T.a[0], p0y = T.a[1], p1x = T.b[0], p1y = T.b[1], p2x = T.c[0], p2y = T.c[1];
+  const double area = (p1x - p0x) * (p2y - p0y) - (p1y - p0y) * (p2x - p0x);
+  if (area == 0.0) return;   // vertical facet: not crossed
+  const bool cw = area < 0.0;
+  const double q1x = cw ? p2x : p1x, q1y = cw ? p2y : p1y, q2x = cw ? p1x : p2x, q2y = cw ? p1y : p2y;
+  int r0[2], r1[2];
+  for (int a = 0; a < 2; ++a) {
+    const double lo = fmin(fmin(T.a[a], T.b[a]), T.c[a]), hi = fmax(fmax(T.a[a], T.b[a]), T.c[a]);
+    cell_range(g, a, lo, hi, r0[a], r1[a]);
+  }
+  const int sx = r1[0] - r0[0] + 1, sy = r1[1] - r0[1] + 1;
+  for (int q = threadIdx.x; q < sx * sy; q += kWave) {
+    const int i = r0[0] + q % sx, j = r0[1] + q / sx;
+    const double px = centre(g, 0, i), py = centre(g, 1, j);
+    if (!(edge_in(p0x, p0y, q1x, q1y, px, py) && edge_in(q1x, q1y, q2x, q2y, px, py) &&
+          edge_in(q2x, q2y, p0x, p0y, px, py)))
+      continue;
+    const double l1 = ((px - p0x) * (p2y - p0y) - (py - p0y) * (p2x - p0x)) / area;
+    const double l2 = ((p1x - p0x) * (py - p0y) - (p1y - p0y) * (px - p0x)) / area;
+    const double z = T.a[2] + l1 * (T.b[2] - T.a[2]) + l2 * (T.c[2] - T.a[2]);
+    // first cell whose centre lies strictly above z
+    double fk = floor((z - g.o[2]) / g.dx - 0.5) + 1.0;
+    int k = int(fmin(fmax(fk, 0.0), double(g.n[2])));
+    while (k > 0 && centre(g, 2, k - 1) > z) --k;
+    while (k < g.n[2] && !(centre(g, 2, k) > z)) ++k;
+    if (k < g.n[2]) {
+      const int64_t cell = cell_index(g, i, j, k);
+      atomicXor(&toggle[cell >> 5], 1u << (cell & 31));
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_column_parity(Grid g, const unsigned* __restrict__ toggle,
+                                                        uint8_t* __restrict__ cls) {
+  const int64_t col = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (col >= int64_t(g.n[0]) * g.n[1]) return;
+  const int i = int(col % g.n[0]), j = int(col / g.n[0]);
+  unsigned par = 0;
+  for (int k = 0; k < g.n[2]; ++k) {
+    const int64_t cell = cell_index(g, i, j, k);
+    par ^= (toggle[cell >> 5] >> (cell & 31)) & 1u;
+    if (par && cls[cell] != kSurface) cls[cell] = kInternal;
+  }
+}
+
+__device__ __forceinline__ bool emits(const uint8_t* __restrict__ cls, const int* __restrict__ best, int64_t cell) {
+  const uint8_t c = cls[cell];
+  return c == kInternal || (c == kSurface && best[cell] != 0x7fffffff);
+}
+
+// per block of 256 cells: the number of particles it emits
+__global__ __launch_bounds__(256) void k_emit_count(const uint8_t* __restrict__ cls, const int* __restrict__ best,
+                                                     int64_t ncell, int* __restrict__ bcount) {
+  const int64_t cell = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const bool e = cell < ncell && emits(cls, best, cell);
+  __shared__ int w[4];
+  const uint64_t m = __ballot(e);
+  if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = __popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) bcount[blockIdx.x] = w[0] + w[1] + w[2] + w[3];
+}
+
+// exclusive scan of the block counts, one block (sequential over chunks)
+__global__ __launch_bounds__(kScanBlock) void k_emit_scan(const int* __restrict__ bcount, int nb,
+                                                           long long* __restrict__ boff) {
+  __shared__ long long s[kScanBlock];
+  long long carry = 0;
+  for (int base = 0; base < nb; base += kScanBlock) {
+    const int b = base + threadIdx.x;
+    const long long v = b < nb ? bcount[b] : 0;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < kScanBlock; o <<= 1) {
+      const long long add = threadIdx.x >= o ? s[threadIdx.x - o] : 0;
+      __syncthreads();
+      s[threadIdx.x] += add;
+      __syncthreads();
+    }
+    if (b < nb) boff[b] = carry + s[threadIdx.x] - v;
+    carry += s[kScanBlock - 1];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) boff[nb] = carry;
+}
+
+__global__ __launch_bounds__(256) void k_emit_write(const uint8_t* __restrict__ cls, const int* __restrict__ best,
+                                                     const double* __restrict__ vert, const int* __restrict__ tri,
+                                                     Grid g, int64_t ncell, const long long* __restrict__ boff,
+                                                     int64_t cap, float4* __restrict__ pos, int* __restrict__ owner,
+                                                     unsigned long long* __restrict__ nsurf) {
+  const int64_t cell = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const bool e = cell < ncell && emits(cls, best, cell);
+  __shared__ int w[4];
+  const uint64_t m = __ballot(e);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) w[wid] = __popcll(m);
+  __syncthreads();
+  int before = 0;
+  for (int k = 0; k < wid; ++k) before += w[k];
+  if (!e) return;
+  const int64_t slot = boff[blockIdx.x] + before + __popcll(m & ((1ull << lane) - 1));
+  if (slot >= cap) return;
+  const int i = int(cell % g.n[0]), j = int((cell / g.n[0]) % g.n[1]), k = int(cell / (int64_t(g.n[0]) * g.n[1]));
+  const double c[3] = {centre(g, 0, i), centre(g, 1, j), centre(g, 2, k)};
+  if (cls[cell] == kInternal) {
+    pos[slot] = make_float4(float(c[0]), float(c[1]), float(c[2]), __int_as_float(FPPG_TAG_VOLUME));
+    owner[slot] = -1;
+  } else {
+    const int t = best[cell];
+    double d, p[3];
+    project_inside(load_tri(vert, tri, t), c, d, p);
+    pos[slot] = make_float4(float(p[0]), float(p[1]), float(p[2]), __int_as_float(FPPG_TAG_SURFACE));
+    owner[slot] = t;
+    atomicAdd(nsurf, 1ull);
+  }
+}
+
+__global__ void k_fill_u64(unsigned long long* __restrict__ a, int64_t n, unsigned long long v) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+__global__ void k_fill_i32b(int* __restrict__ a, int64_t n, int v) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+__global__ void k_fill_u8(uint8_t* __restrict__ a, int64_t n, uint8_t v) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+inline int blocks(int64_t n, int b) { return int((n + b - 1) / b); }
+
+}  // namespace gen
+}  // namespace fppg
+
+using namespace fppg;
+
+extern "C" fppg_status fppg_generate(fppg_ctx* ctx, const double* vert, int32_t n_vert, const int32_t* tri,
+                                     int32_t n_tri, double dx, const double* origin, const int32_t* dims,
+                                     uint8_t* cell_class, float* pos, int32_t* owner, int64_t cap, int64_t* counts,
+                                     void* stream) {
+  if (!ctx) return fail(ctx, FPPG_E_ARG, "null ctx");
+  if (!vert || !tri || n_vert < 3 || n_tri < 1 || !origin || !dims || !counts || !cell_class)
+    return fail(ctx, FPPG_E_ARG, "null or empty mesh/grid/output");
+  if (!(dx > 0.0) || !std::isfinite(dx)) return fail(ctx, FPPG_E_ARG, "dx must be finite and > 0");
+  if (cap < 0 || (cap > 0 && (!pos || !owner))) return fail(ctx, FPPG_E_ARG, "bad particle capacity/outputs");
+  if (!aligned(pos, 16)) return fail(ctx, FPPG_E_ARG, "pos must be 16-byte aligned");
+  for (int a = 0; a < 3; ++a)
+    if (dims[a] < 1 || !std::isfinite(origin[a])) return fail(ctx, FPPG_E_ARG, "bad grid");
+  for (int64_t q = 0; q < 3 * int64_t(n_tri); ++q)
+    if (tri[q] < 0 || tri[q] >= n_vert) return fail(ctx, FPPG_E_ARG, "facet vertex index out of range");
+  const int64_t ncell = int64_t(dims[0]) * dims[1] * dims[2];
+  if (ncell >= (int64_t(1) << 31)) return fail(ctx, FPPG_E_CAPACITY, "background grid exceeds 2^31 cells");
+  counts[0] = counts[1] = 0;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  gen::Grid g;
+  for (int a = 0; a < 3; ++a) {
+    g.o[a] = origin[a];
+    g.n[a] = dims[a];
+  }
+  g.dx = dx;
+  const int nb = gen::blocks(ncell, 256);
+  double* d_vert = nullptr;
+  int* d_tri = nullptr;
+  unsigned long long* d_key = nullptr;
+  int* d_best = nullptr;
+  unsigned* d_tog = nullptr;
+  int* d_bcount = nullptr;
+  long long* d_boff = nullptr;
+  unsigned long long* d_nsurf = nullptr;
+  fppg_status st = FPPG_OK;
+  auto cleanup = [&]() {
+    hipStreamSynchronize(s);
+    hipFree(d_vert);
+    hipFree(d_tri);
+    hipFree(d_key);
+    hipFree(d_best);
+    hipFree(d_tog);
+    hipFree(d_bcount);
+    hipFree(d_boff);
+    hipFree(d_nsurf);
+  };
+#define GEN_HIP(call)                                   \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) {                             \
+      st = fail(ctx, FPPG_E_HIP, hipGetErrorString(e_)); \
+      cleanup();                                        \
+      return st;                                        \
+    }                                                   \
+  } while (0)
+  GEN_HIP(hipMalloc(&d_vert, sizeof(double) * 3 * n_vert));
+  GEN_HIP(hipMalloc(&d_tri, sizeof(int) * 3 * n_tri));
+  GEN_HIP(hipMalloc(&d_key, sizeof(unsigned long long) * ncell));
+  GEN_HIP(hipMalloc(&d_best, sizeof(int) * ncell));
+  GEN_HIP(hipMalloc(&d_tog, sizeof(unsigned) * ((ncell + 31) / 32)));
+  GEN_HIP(hipMalloc(&d_bcount, sizeof(int) * nb));
+  GEN_HIP(hipMalloc(&d_boff, sizeof(long long) * (nb + 1)));
+  GEN_HIP(hipMalloc(&d_nsurf, sizeof(unsigned long long)));
+  GEN_HIP(hipMemcpyAsync(d_vert, vert, sizeof(double) * 3 * n_vert, hipMemcpyHostToDevice, s));
+  GEN_HIP(hipMemcpyAsync(d_tri, tri, sizeof(int) * 3 * n_tri, hipMemcpyHostToDevice, s));
+  gen::k_fill_u8<<<gen::blocks(ncell, 256), 256, 0, s>>>(cell_class, ncell, gen::kExternal);
+  gen::k_fill_u64<<<gen::blocks(ncell, 256), 256, 0, s>>>(d_key, ncell, ~0ull);
+  gen::k_fill_i32b<<<gen::blocks(ncell, 256), 256, 0, s>>>(d_best, ncell, 0x7fffffff);
+  gen::k_fill_i32b<<<gen::blocks((ncell + 31) / 32, 256), 256, 0, s>>>(reinterpret_cast<int*>(d_tog),
+                                                                         (ncell + 31) / 32, 0);
+  gen::k_fill_u64<<<1, 64, 0, s>>>(d_nsurf, 1, 0ull);
+  gen::k_surface_cells<<<n_tri, gen::kWave, 0, s>>>(d_vert, d_tri, g, cell_class, d_key, 0, d_best);
+  gen::k_surface_cells<<<n_tri, gen::kWave, 0, s>>>(d_vert, d_tri, g, cell_class, d_key, 1, d_best);
+  gen::k_ray_crossings<<<n_tri, gen::kWave, 0, s>>>(d_vert, d_tri, g, d_tog);
+  gen::k_column_parity<<<gen::blocks(int64_t(dims[0]) * dims[1], 256), 256, 0, s>>>(g, d_tog, cell_class);
+  gen::k_emit_count<<<nb, 256, 0, s>>>(cell_class, d_best, ncell, d_bcount);
+  gen::k_emit_scan<<<1, gen::kScanBlock, 0, s>>>(d_bcount, nb, d_boff);
+  gen::k_emit_write<<<nb, 256, 0, s>>>(cell_class, d_best, d_vert, d_tri, g, ncell, d_boff, cap,
+                                       reinterpret_cast<float4*>(pos), owner, d_nsurf);
+  GEN_HIP(hipGetLastError());
+  long long total = 0;
+  unsigned long long nsurf = 0;
+  GEN_HIP(hipMemcpyAsync(&total, d_boff + nb, sizeof(long long), hipMemcpyDeviceToHost, s));
+  GEN_HIP(hipMemcpyAsync(&nsurf, d_nsurf, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  GEN_HIP(hipStreamSynchronize(s));
+#undef GEN_HIP
+  cleanup();
+  counts[0] = total - int64_t(nsurf);
+  counts[1] = int64_t(nsurf);
+  if (total > cap) {
+    // nsurf counts only the surface particles written below cap
+    counts[0] = -1;
+    counts[1] = total;
+    return fail(ctx, FPPG_E_CAPACITY, "more particles than cap (counts[1] holds the total)");
+  }
+  return FPPG_OK;
+}

@@ -1,0 +1,42 @@
+"""Particle generation front end (sections 3.1.1-3.2.1) through
+fppg_generate: background-grid cell classes and the initial volume and
+surface particles of a closed mesh, on the GPU."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from ._lib import check, ptr
+from .relax import Context
+
+
+def generate(vert, tri, dx: float, origin, dims, device: int = 0, ctx: Context | None = None, cap: int | None = None):
+    """Classify the cells of the grid (origin, dx, dims = (nx, ny, nz)) and seed
+    particles. Returns (cls uint8 [nz, ny, nx] with 0 external / 1 internal /
+    2 surface, pos float32 [P, 4] with the tag bits in w, owner int32 [P]:
+    the facet of a surface particle, -1 for a volume particle), particles in
+    cell order."""
+    if not torch.cuda.is_available():
+        raise RuntimeError("generate() needs a GPU (no CPU fallback)")
+    ctx = ctx or Context(device)
+    dev = torch.device("cuda", device)
+    vert = np.ascontiguousarray(vert, np.float64).reshape(-1, 3)
+    tri = np.ascontiguousarray(tri, np.int32).reshape(-1, 3)
+    nx, ny, nz = (int(v) for v in dims)
+    cls = torch.empty((nz, ny, nx), dtype=torch.uint8, device=dev)
+    if cap is None:
+        cap = nx * ny * nz
+    pos = torch.empty((max(cap, 1), 4), dtype=torch.float32, device=dev)
+    owner = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    o = (ctypes.c_double * 3)(*[float(v) for v in origin])
+    d = (ctypes.c_int32 * 3)(nx, ny, nz)
+    counts = (ctypes.c_int64 * 2)()
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    check(ctx.lib.fppg_generate(ctx.handle, vert.ctypes.data_as(ctypes.c_void_p), len(vert),
+                                tri.ctypes.data_as(ctypes.c_void_p), len(tri), float(dx), o, d, ptr(cls),
+                                ptr(pos), ptr(owner), int(cap), counts, stream), ctx.handle)
+    n = int(counts[0]) + int(counts[1])
+    return cls, pos[:n], owner[:n]

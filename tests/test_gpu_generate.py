@@ -1,0 +1,65 @@
+"""Generation front end on the GPU (fppg_generate, sections 3.1.1-3.2.1)
+against the oracle: cell classes bit for bit, the particles (binary32 of the
+FP64 positions, owners, order) exactly, and the capacity error path."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import generate as G
+from synth import meshes as M
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _gen(vert, tri, dx, origin, dims, cap=None):
+    from paper_2501_03056_amd.front import generate
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    cls, pos, owner = generate(vert, tri, dx, origin, dims, cap=cap)
+    return cls.cpu().numpy(), pos.cpu().numpy(), owner.cpu().numpy()
+
+
+def _cavity():
+    outer = M.cube((0.0, 0.0, 0.0), (1.0, 1.0, 1.0))
+    inner = M.cube((0.3, 0.3, 0.3), (0.7, 0.7, 0.7))
+    return np.concatenate([outer.vert, inner.vert]), np.concatenate([outer.tri, inner.tri[:, ::-1] + len(outer.vert)])
+
+
+def _gear():
+    m = M.gear(samples_per_period=12, rings=4)
+    return m.vert, m.tri
+
+
+CASES = {
+    "offset_box": (lambda: (M.cube((0.13, 0.21, 0.07), (0.87, 0.79, 0.93)).vert,
+                            M.cube((0.13, 0.21, 0.07), (0.87, 0.79, 0.93)).tri), 0.1, (0.0, 0.0, 0.0), (10, 10, 10)),
+    "aligned_cube": (lambda: (M.cube().vert, M.cube().tri), 0.125, (-0.125,) * 3, (10, 10, 10)),
+    "cavity": (_cavity, 0.1, (-0.15,) * 3, (13, 13, 13)),
+    "sphere_l3": (lambda: (M.icosphere(3).vert, M.icosphere(3).tri), 0.1, (-1.25,) * 3, (25, 25, 25)),
+    "tetra": (lambda: (M.tetrahedron().vert, M.tetrahedron().tri), 0.05, (-1.1, -1.1, -1.1), (44, 44, 44)),
+    "gear_coarse": (_gear, 0.05, (-1.1, -1.1, -0.25), (44, 44, 10)),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_generate_matches_oracle(case):
+    make, dx, origin, dims = CASES[case]
+    vert, tri = make()
+    cls, pos, owner = _gen(vert, tri, dx, origin, dims)
+    ref_cls, ref_pos, ref_tag, ref_owner = G.generate(vert, tri, dx, np.array(origin, np.float64), dims)
+    assert np.array_equal(cls, ref_cls)
+    assert len(pos) == len(ref_pos)
+    assert np.array_equal(pos[:, :3], ref_pos.astype(np.float32))
+    assert np.array_equal(pos[:, 3].view(np.int32) & 7, ref_tag)
+    assert np.array_equal(owner, ref_owner)
+    assert (ref_cls == G.INTERNAL).any() and (ref_cls == G.SURFACE).any()
+
+
+def test_capacity_error_reports_the_total():
+    from paper_2501_03056_amd import _lib
+    vert, tri = M.cube().vert, M.cube().tri
+    with pytest.raises(_lib.FppgError) as e:
+        _gen(vert, tri, 0.125, (-0.125,) * 3, (10, 10, 10), cap=10)
+    assert e.value.status == _lib.E_CAPACITY
