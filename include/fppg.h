@@ -408,6 +408,46 @@ fppg_status fppg_generate(fppg_ctx* ctx, const double* vert, int32_t n_vert, con
                           int32_t* owner, int64_t cap, int64_t* counts, void* stream);
 
 /*
+ * Feature extraction and feature-line particles (section 3.2.2) of one mesh
+ * (vert, tri as in fppg_geom_desc; host arrays):
+ *   feature edge   a mesh edge with other than two facets, or whose two
+ *                  facets' FP64 unit normals satisfy n1 . n2 < cos_threshold;
+ *   singular       a vertex on one feature edge or on more than two;
+ *   feature lines  maximal chains of feature edges between singular
+ *                  vertices, each listed once from the end whose (vertex,
+ *                  next vertex) pair is smaller, in the order of those pairs;
+ *                  then the loops (chains without a singular vertex), each
+ *                  from its smallest vertex towards its smaller neighbour, in
+ *                  the order of that vertex;
+ *   particles      per line of length L, n = max(1, ceil(L / dx)) equal steps
+ *                  of arc length: the n - 1 interior points of an open line
+ *                  (its ends are singular points), all n points of a loop
+ *                  starting at its first vertex.
+ * Outputs in *out (device arrays, caller-allocated, with capacities): edges
+ * [2 * n_edges] int32 (u < v, ascending), singular [n_singular] int32
+ * (ascending), line_begin [n_lines + 1] int32 and line_vert [n_line_vert]
+ * int32 (line l is line_vert[line_begin[l] .. line_begin[l+1]-1]; a loop does
+ * not repeat its first vertex), line_closed [n_lines] uint8, pos
+ * [n_particles * 4] float (16-byte aligned; w = FPPG_TAG_FEATURE), line_of
+ * [n_particles] int32, arc [n_particles] double (arc length from the line's
+ * first vertex). The n_* fields are set on return; with line_begin = NULL
+ * the call only reports them (FPPG_OK); if one exceeds its capacity the call
+ * returns FPPG_E_CAPACITY without writing the arrays. A set-up call: it
+ * allocates device temporaries and synchronises the stream.
+ */
+typedef struct {
+  int32_t* edges;      int64_t cap_edges;
+  int32_t* singular;   int64_t cap_singular;
+  int32_t* line_begin; int32_t* line_vert; uint8_t* line_closed;
+  int64_t  cap_lines;  int64_t cap_line_vert;
+  float*   pos;        int32_t* line_of;   double* arc;  int64_t cap_particles;
+  int64_t  n_edges, n_singular, n_lines, n_line_vert, n_particles;   /* out */
+} fppg_features_out;
+
+fppg_status fppg_features(fppg_ctx* ctx, const double* vert, int32_t n_vert, const int32_t* tri, int32_t n_tri,
+                          double cos_threshold, double dx, fppg_features_out* out, void* stream);
+
+/*
  * Three-layer volume relaxation (section 3.3.4): re-tag as fixed
  * (FPPG_TAG_FIXED) every volume particle whose distance to its geometry's
  * surface mesh is at least width; the volume particles closer than width are

@@ -54,6 +54,7 @@ _SIGS = {
     "fppg_moving_list": (c_int32, [_P, _P, c_int64, _P, c_uint32, _P, _P, _P, c_size_t, _P]),
     "fppg_volume_layers": (c_int32, [_P, _P, c_int64, _P, c_double, _P, _P]),
     "fppg_generate": (c_int32, [_P, _P, c_int32, _P, c_int32, c_double, _P, _P, _P, _P, _P, c_int64, _P, _P]),
+    "fppg_features": (c_int32, [_P, _P, c_int32, _P, c_int32, c_double, c_double, _P, _P]),
     "fppg_relax_hvp": (c_int32, [_P, _P, c_int64, _P, _P, c_uint32, c_int32, _P, _P, _P]),
     "fppg_debug_neighbors": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, c_int32, _P]),
     "fppg_graph_create": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, c_int32, c_uint32,
@@ -81,6 +82,18 @@ _SIGS = {
 }
 
 _lib = None
+
+
+class FeaturesOut(ctypes.Structure):
+    """fppg_features_out."""
+    _fields_ = [
+        ("edges", c_void_p), ("cap_edges", c_int64), ("singular", c_void_p), ("cap_singular", c_int64),
+        ("line_begin", c_void_p), ("line_vert", c_void_p), ("line_closed", c_void_p),
+        ("cap_lines", c_int64), ("cap_line_vert", c_int64),
+        ("pos", c_void_p), ("line_of", c_void_p), ("arc", c_void_p), ("cap_particles", c_int64),
+        ("n_edges", c_int64), ("n_singular", c_int64), ("n_lines", c_int64), ("n_line_vert", c_int64),
+        ("n_particles", c_int64),
+    ]
 
 
 class FppgError(RuntimeError):

@@ -40,3 +40,40 @@ def generate(vert, tri, dx: float, origin, dims, device: int = 0, ctx: Context |
                                 ptr(pos), ptr(owner), int(cap), counts, stream), ctx.handle)
     n = int(counts[0]) + int(counts[1])
     return cls, pos[:n], owner[:n]
+
+
+def features(vert, tri, cos_threshold: float, dx: float, device: int = 0, ctx: Context | None = None):
+    """Feature edges, singular vertices, feature lines and feature-line
+    particles of a mesh (fppg_features). Returns a dict of device tensors:
+    edges [E, 2], singular [S], line_begin [L + 1], line_vert [V],
+    line_closed [L], pos [P, 4] (w = tag bits), line_of [P], arc [P] (float64)."""
+    if not torch.cuda.is_available():
+        raise RuntimeError("features() needs a GPU (no CPU fallback)")
+    ctx = ctx or Context(device)
+    dev = torch.device("cuda", device)
+    vert = np.ascontiguousarray(vert, np.float64).reshape(-1, 3)
+    tri = np.ascontiguousarray(tri, np.int32).reshape(-1, 3)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+    def call(o):
+        return ctx.lib.fppg_features(ctx.handle, vert.ctypes.data_as(ctypes.c_void_p), len(vert),
+                                     tri.ctypes.data_as(ctypes.c_void_p), len(tri), float(cos_threshold), float(dx),
+                                     ctypes.byref(o), stream)
+
+    sizes = L.FeaturesOut()
+    check(call(sizes), ctx.handle)   # line_begin = NULL: sizes only
+    t = {"edges": torch.empty((max(sizes.n_edges, 1), 2), dtype=torch.int32, device=dev),
+         "singular": torch.empty(max(sizes.n_singular, 1), dtype=torch.int32, device=dev),
+         "line_begin": torch.empty(sizes.n_lines + 1, dtype=torch.int32, device=dev),
+         "line_vert": torch.empty(max(sizes.n_line_vert, 1), dtype=torch.int32, device=dev),
+         "line_closed": torch.empty(max(sizes.n_lines, 1), dtype=torch.uint8, device=dev),
+         "pos": torch.empty((max(sizes.n_particles, 1), 4), dtype=torch.float32, device=dev),
+         "line_of": torch.empty(max(sizes.n_particles, 1), dtype=torch.int32, device=dev),
+         "arc": torch.empty(max(sizes.n_particles, 1), dtype=torch.float64, device=dev)}
+    o = L.FeaturesOut(ptr(t["edges"]), sizes.n_edges, ptr(t["singular"]), sizes.n_singular, ptr(t["line_begin"]),
+                      ptr(t["line_vert"]), ptr(t["line_closed"]), sizes.n_lines, sizes.n_line_vert, ptr(t["pos"]),
+                      ptr(t["line_of"]), ptr(t["arc"]), sizes.n_particles)
+    check(call(o), ctx.handle)
+    n = {"edges": o.n_edges, "singular": o.n_singular, "line_vert": o.n_line_vert, "line_closed": o.n_lines,
+         "pos": o.n_particles, "line_of": o.n_particles, "arc": o.n_particles}
+    return {k: (v[: n[k]] if k in n else v) for k, v in t.items()}
