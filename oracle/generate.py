@@ -193,3 +193,34 @@ def generate(vert, tri, dx, origin, dims):
         if t >= 0:
             pos.append(p); tag.append(SURFACE_TAG); owner.append(t)
     return cls, np.array(pos).reshape(-1, 3), np.array(tag, np.int32), np.array(owner, np.int32)
+
+
+UNION, INTERSECTION, DIFFERENCE = 0, 1, 2
+
+
+def boolean(cls_a, cls_b, op):
+    """Cell classes of a Boolean combination of two solids classified on the
+    same grid (section 3.2.3). Reading: the paper combines the solids' cell
+    sets as set operations on their internal (volume-particle) cells; surface
+    cells are kept where the combined surface can pass:
+      union         I = Ai | Bi;          S = (As & ~Bi) | (Bs & ~Ai)
+      intersection  I = Ai & Bi;          S = (As & (Bi | Bs)) | (Bs & (Ai | As))
+      difference    I = Ai & ~(Bi | Bs);  S = (As & ~Bi) | (Bs & (Ai | As))
+    with S taken outside I."""
+    ai, as_ = cls_a == INTERNAL, cls_a == SURFACE
+    bi, bs = cls_b == INTERNAL, cls_b == SURFACE
+    if op == UNION:
+        i = ai | bi
+        s = (as_ & ~bi) | (bs & ~ai)
+    elif op == INTERSECTION:
+        i = ai & bi
+        s = (as_ & (bi | bs)) | (bs & (ai | as_))
+    elif op == DIFFERENCE:
+        i = ai & ~(bi | bs)
+        s = (as_ & ~bi) | (bs & (ai | as_))
+    else:
+        raise ValueError(op)
+    out = np.zeros_like(cls_a)
+    out[s & ~i] = SURFACE
+    out[i] = INTERNAL
+    return out

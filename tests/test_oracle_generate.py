@@ -114,3 +114,42 @@ def test_triangle_box_overlap_cases():
     # the same plane shifted beyond the box corner (|x + y + z| > 1.5)
     sh = np.full(3, 0.51)
     assert not G.tri_box_overlap(c, hw, a + sh, b + sh, cc + sh)
+
+
+def _classes(lo, hi, dx, origin, dims):
+    m = M.cube(lo, hi)
+    return G.classify(m.vert, m.tri, dx, np.asarray(origin, np.float64), dims)
+
+
+def test_boolean_of_boxes_matches_the_combined_box():
+    """Axis-aligned boxes whose intersection, difference and union are boxes:
+    the internal cells of the combination are those of the combined box."""
+    dx, origin, dims = 0.1, (-0.05, -0.05, -0.05), (24, 14, 14)
+    A = ((0.0, 0.0, 0.0), (1.0, 1.0, 1.0))
+    B = ((0.53, 0.0 - 0.2, 0.0 - 0.2), (2.03, 1.2, 1.2))       # covers A beyond x = 0.53 in y and z
+    ca, cb = _classes(*A, dx, origin, dims), _classes(*B, dx, origin, dims)
+    inter = _classes((0.53, 0.0, 0.0), (1.0, 1.0, 1.0), dx, origin, dims)
+    diff = _classes((0.0, 0.0, 0.0), (0.53, 1.0, 1.0), dx, origin, dims)
+    assert np.array_equal(G.boolean(ca, cb, G.INTERSECTION) == G.INTERNAL, inter == G.INTERNAL)
+    assert np.array_equal(G.boolean(ca, cb, G.DIFFERENCE) == G.INTERNAL, diff == G.INTERNAL)
+    # union with a box that extends A along x through a thick overlap
+    C = ((0.47, 0.0, 0.0), (2.03, 1.0, 1.0))
+    cc = _classes(*C, dx, origin, dims)
+    uni = _classes((0.0, 0.0, 0.0), (2.03, 1.0, 1.0), dx, origin, dims)
+    assert np.array_equal(G.boolean(ca, cc, G.UNION) == G.INTERNAL, uni == G.INTERNAL)
+    # the combined surface cells cover the combined box's surface cells
+    for op, box in ((G.INTERSECTION, inter), (G.DIFFERENCE, diff)):
+        got = G.boolean(ca, cb, op)
+        assert np.all(got[box == G.SURFACE] == G.SURFACE)
+    assert np.all(G.boolean(ca, cc, G.UNION)[uni == G.SURFACE] != G.EXTERNAL)
+
+
+def test_boolean_identities():
+    dx, origin, dims = 0.1, (-0.15, -0.15, -0.15), (14, 14, 14)
+    ca = _classes((0.0, 0.0, 0.0), (1.0, 1.0, 1.0), dx, origin, dims)
+    empty = np.zeros_like(ca)
+    assert np.array_equal(G.boolean(ca, ca, G.UNION), ca)
+    assert np.array_equal(G.boolean(ca, ca, G.INTERSECTION), ca)
+    assert np.array_equal(G.boolean(ca, empty, G.UNION), ca)
+    assert np.array_equal(G.boolean(ca, empty, G.DIFFERENCE), ca)
+    assert not np.any(G.boolean(ca, ca, G.DIFFERENCE) == G.INTERNAL)
