@@ -408,6 +408,19 @@ fppg_status fppg_generate(fppg_ctx* ctx, const double* vert, int32_t n_vert, con
                           int32_t* owner, int64_t cap, int64_t* counts, void* stream);
 
 /*
+ * Boolean combination of two solids classified by fppg_generate on the same
+ * grid (section 3.2.3), cell by cell (I internal, S surface):
+ *   op 0 union         I = Ai | Bi,           S = (As & ~Bi) | (Bs & ~Ai)
+ *   op 1 intersection  I = Ai & Bi,           S = (As & (Bi | Bs)) | (Bs & (Ai | As))
+ *   op 2 difference    I = Ai & ~(Bi | Bs),   S = (As & ~Bi) | (Bs & (Ai | As))
+ * with S outside I, everything else external. a, b, out [n] uint8 (device;
+ * out may alias a or b). The volume particles of the combination sit at the
+ * centres of its internal cells.
+ */
+fppg_status fppg_cells_boolean(fppg_ctx* ctx, const uint8_t* a, const uint8_t* b, int64_t n, int32_t op,
+                               uint8_t* out, void* stream);
+
+/*
  * Feature extraction and feature-line particles (section 3.2.2) of one mesh
  * (vert, tri as in fppg_geom_desc; host arrays):
  *   feature edge   a mesh edge with other than two facets, or whose two

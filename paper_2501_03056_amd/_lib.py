@@ -55,6 +55,7 @@ _SIGS = {
     "fppg_volume_layers": (c_int32, [_P, _P, c_int64, _P, c_double, _P, _P]),
     "fppg_generate": (c_int32, [_P, _P, c_int32, _P, c_int32, c_double, _P, _P, _P, _P, _P, c_int64, _P, _P]),
     "fppg_features": (c_int32, [_P, _P, c_int32, _P, c_int32, c_double, c_double, _P, _P]),
+    "fppg_cells_boolean": (c_int32, [_P, _P, _P, c_int64, c_int32, _P, _P]),
     "fppg_relax_hvp": (c_int32, [_P, _P, c_int64, _P, _P, c_uint32, c_int32, _P, _P, _P]),
     "fppg_debug_neighbors": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, c_int32, _P]),
     "fppg_graph_create": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, c_int32, c_uint32,

@@ -332,6 +332,28 @@ __global__ void k_fill_u8(uint8_t* __restrict__ a, int64_t n, uint8_t v) {
   if (i < n) a[i] = v;
 }
 
+// Boolean combination of two classified solids on the same grid (section
+// 3.2.3): set operations on the internal cells, surface cells kept where the
+// combined surface can pass.
+__global__ void k_cells_boolean(const uint8_t* __restrict__ a, const uint8_t* __restrict__ b, int64_t n, int op,
+                                uint8_t* __restrict__ out) {
+  const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const bool ai = a[q] == kInternal, as = a[q] == kSurface, bi = b[q] == kInternal, bs = b[q] == kSurface;
+  bool i, s;
+  if (op == 0) {          // union
+    i = ai || bi;
+    s = (as && !bi) || (bs && !ai);
+  } else if (op == 1) {   // intersection
+    i = ai && bi;
+    s = (as && (bi || bs)) || (bs && (ai || as));
+  } else {                // difference a - b
+    i = ai && !(bi || bs);
+    s = (as && !bi) || (bs && (ai || as));
+  }
+  out[q] = i ? kInternal : (s ? kSurface : kExternal);
+}
+
 inline int blocks(int64_t n, int b) { return int((n + b - 1) / b); }
 
 }  // namespace gen
@@ -433,5 +455,16 @@ extern "C" fppg_status fppg_generate(fppg_ctx* ctx, const double* vert, int32_t 
     counts[1] = total;
     return fail(ctx, FPPG_E_CAPACITY, "more particles than cap (counts[1] holds the total)");
   }
+  return FPPG_OK;
+}
+
+extern "C" fppg_status fppg_cells_boolean(fppg_ctx* ctx, const uint8_t* a, const uint8_t* b, int64_t n, int32_t op,
+                                          uint8_t* out, void* stream) {
+  if (!ctx) return fail(ctx, FPPG_E_ARG, "null ctx");
+  if (n < 0 || (n > 0 && (!a || !b || !out))) return fail(ctx, FPPG_E_ARG, "null class array");
+  if (op < 0 || op > 2) return fail(ctx, FPPG_E_ARG, "op must be 0 (union), 1 (intersection) or 2 (difference)");
+  if (n == 0) return FPPG_OK;
+  gen::k_cells_boolean<<<gen::blocks(n, 256), 256, 0, static_cast<hipStream_t>(stream)>>>(a, b, n, op, out);
+  FPPG_HIP(ctx, hipGetLastError());
   return FPPG_OK;
 }

@@ -77,3 +77,19 @@ def features(vert, tri, cos_threshold: float, dx: float, device: int = 0, ctx: C
     n = {"edges": o.n_edges, "singular": o.n_singular, "line_vert": o.n_line_vert, "line_closed": o.n_lines,
          "pos": o.n_particles, "line_of": o.n_particles, "arc": o.n_particles}
     return {k: (v[: n[k]] if k in n else v) for k, v in t.items()}
+
+
+UNION, INTERSECTION, DIFFERENCE = 0, 1, 2
+
+
+def cells_boolean(cls_a: torch.Tensor, cls_b: torch.Tensor, op: int, ctx: Context | None = None) -> torch.Tensor:
+    """Boolean combination (fppg_cells_boolean) of two class arrays of generate()
+    on the same grid: op UNION, INTERSECTION or DIFFERENCE (a - b)."""
+    if cls_a.shape != cls_b.shape or cls_a.dtype != torch.uint8 or cls_b.dtype != torch.uint8:
+        raise ValueError("class arrays of the same grid (uint8) expected")
+    ctx = ctx or Context(cls_a.device.index or 0)
+    a, b = cls_a.contiguous(), cls_b.contiguous()
+    out = torch.empty_like(a)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(a.device).cuda_stream)
+    check(ctx.lib.fppg_cells_boolean(ctx.handle, ptr(a), ptr(b), a.numel(), int(op), ptr(out), stream), ctx.handle)
+    return out

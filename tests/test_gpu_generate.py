@@ -63,3 +63,23 @@ def test_capacity_error_reports_the_total():
     with pytest.raises(_lib.FppgError) as e:
         _gen(vert, tri, 0.125, (-0.125,) * 3, (10, 10, 10), cap=10)
     assert e.value.status == _lib.E_CAPACITY
+
+
+@pytest.mark.parametrize("op", [0, 1, 2])
+def test_cells_boolean_matches_oracle(op):
+    from paper_2501_03056_amd.front import cells_boolean, generate
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    dx, origin, dims = 0.1, (-0.15, -0.15, -0.15), (16, 14, 14)
+    a = M.cube((0.0, 0.0, 0.0), (1.0, 1.0, 1.0))
+    b = M.icosphere(2, radius=0.45)
+    bv = b.vert + np.array([0.95, 0.5, 0.55])
+    ca, _, _ = generate(a.vert, a.tri, dx, origin, dims)
+    cb, _, _ = generate(bv, b.tri, dx, origin, dims)
+    got = cells_boolean(ca, cb, op).cpu().numpy()
+    want = G.boolean(ca.cpu().numpy(), cb.cpu().numpy(), op)
+    assert np.array_equal(got, want)
+    rng = np.random.default_rng(op)
+    ra = torch.from_numpy(rng.integers(0, 3, 5000).astype(np.uint8)).cuda()
+    rb = torch.from_numpy(rng.integers(0, 3, 5000).astype(np.uint8)).cuda()
+    assert np.array_equal(cells_boolean(ra, rb, op).cpu().numpy(), G.boolean(ra.cpu().numpy(), rb.cpu().numpy(), op))
