@@ -209,7 +209,21 @@ def bench_gear(args):
     from paper_2501_03056_amd import Relaxer
     dx = args.gear_dx
     t0 = time.perf_counter()
-    wl = synth.gear_workload(dx=dx, seed=3, k=args.k)
+    gen = None
+    if args.gear_source == "pipeline":
+        # the particles from the GPU front end (feature extraction + generation)
+        from synth import meshes as M
+        from paper_2501_03056_amd import Context, pipeline
+        ctx = Context(0)
+        mesh = M.gear()
+        pipeline.from_mesh(mesh.vert, mesh.tri, dx, ctx=ctx)          # warm-up (kernel loading)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        wl = pipeline.from_mesh(mesh.vert, mesh.tri, dx, ctx=ctx)
+        torch.cuda.synchronize()
+        gen = {"seconds": time.perf_counter() - t0, "note": "fppg_features + fppg_generate + host assembly"}
+    else:
+        wl = synth.gear_workload(dx=dx, seed=3, k=args.k)
     for g in wl.geoms:
         g.slab = args.slab
     print(f"[bench] gear dx={dx:g}: {wl.n} particles {wl.counts()} built in {time.perf_counter() - t0:.1f}s",
@@ -269,7 +283,8 @@ def bench_gear(args):
            "n_gpus": 1, "steps": 3 * args.tier_iters, "warmup": 3 * args.warmup,
            "ms_per_step": 1e3 * total_s / (3 * args.tier_iters), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": f"gear24_dx{dx:g}_tiers_feature_surface_volume", "particles": wl.n,
+           "config": {"workload": f"gear24_dx{dx:g}_tiers_feature_surface_volume"
+                                  + ("_gpu_generated" if gen else ""), "particles": wl.n, "generation": gen,
                       "counts": wl.counts(), "facets": int(r.geom.n_tri), "stencil_k": int(wl.geoms[0].k),
                       "key_slab_rows": int(args.slab)},
            "tiers": out_tiers, "three_layer": three_layer, "device_status": r.read_status()}
@@ -355,6 +370,8 @@ def main():
     ap.add_argument("--mode", default="step", choices=["step", "batch", "newton", "gear", "generate"])
     ap.add_argument("--gear-dx", type=float, default=0.004)
     ap.add_argument("--tier-iters", type=int, default=100)
+    ap.add_argument("--gear-source", default="synth", choices=["synth", "pipeline"],
+                    help="gear: particles from the synthetic generator or from the GPU front end")
     ap.add_argument("--layer-width", type=float, default=3.0,
                     help="gear: width of the relaxed volume layer in units of dx (three-layer tier)")
     ap.add_argument("--no-list", action="store_true",

@@ -443,7 +443,9 @@ fppg_status fppg_cells_boolean(fppg_ctx* ctx, const uint8_t* a, const uint8_t* b
  * not repeat its first vertex), line_closed [n_lines] uint8, pos
  * [n_particles * 4] float (16-byte aligned; w = FPPG_TAG_FEATURE), line_of
  * [n_particles] int32, arc [n_particles] double (arc length from the line's
- * first vertex). The n_* fields are set on return; with line_begin = NULL
+ * first vertex), seg [n_particles] int32 (the segment of the line, from its
+ * vertex k to k + 1, that holds the particle) and u [n_particles] double (arc
+ * length inside that segment). The n_* fields are set on return; with line_begin = NULL
  * the call only reports them (FPPG_OK); if one exceeds its capacity the call
  * returns FPPG_E_CAPACITY without writing the arrays. A set-up call: it
  * allocates device temporaries and synchronises the stream.
@@ -453,7 +455,8 @@ typedef struct {
   int32_t* singular;   int64_t cap_singular;
   int32_t* line_begin; int32_t* line_vert; uint8_t* line_closed;
   int64_t  cap_lines;  int64_t cap_line_vert;
-  float*   pos;        int32_t* line_of;   double* arc;  int64_t cap_particles;
+  float*   pos;        int32_t* line_of;   double* arc;  int32_t* seg;  double* u;
+  int64_t  cap_particles;
   int64_t  n_edges, n_singular, n_lines, n_line_vert, n_particles;   /* out */
 } fppg_features_out;
 

@@ -91,7 +91,8 @@ class FeaturesOut(ctypes.Structure):
         ("edges", c_void_p), ("cap_edges", c_int64), ("singular", c_void_p), ("cap_singular", c_int64),
         ("line_begin", c_void_p), ("line_vert", c_void_p), ("line_closed", c_void_p),
         ("cap_lines", c_int64), ("cap_line_vert", c_int64),
-        ("pos", c_void_p), ("line_of", c_void_p), ("arc", c_void_p), ("cap_particles", c_int64),
+        ("pos", c_void_p), ("line_of", c_void_p), ("arc", c_void_p), ("seg", c_void_p), ("u", c_void_p),
+        ("cap_particles", c_int64),
         ("n_edges", c_int64), ("n_singular", c_int64), ("n_lines", c_int64), ("n_line_vert", c_int64),
         ("n_particles", c_int64),
     ]

@@ -217,7 +217,8 @@ __device__ __forceinline__ int lv(const int* __restrict__ line_vert, int b, int 
 __global__ void k_line_particles(const double* __restrict__ vert, const int* __restrict__ line_begin,
                                  const int* __restrict__ line_vert, const uint8_t* __restrict__ closed, int n_lines,
                                  double dx, int pass, int* __restrict__ cnt, const int* __restrict__ poff,
-                                 float4* __restrict__ pos, int* __restrict__ line_of, double* __restrict__ arc) {
+                                 float4* __restrict__ pos, int* __restrict__ line_of, double* __restrict__ arc,
+                                 int* __restrict__ seg_of, double* __restrict__ u_in) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= n_lines) return;
   const int b = line_begin[l], nv = line_begin[l + 1] - b;
@@ -247,6 +248,8 @@ __global__ void k_line_particles(const double* __restrict__ vert, const int* __r
     pos[o] = make_float4(p[0], p[1], p[2], __int_as_float(FPPG_TAG_FEATURE));
     line_of[o] = l;
     arc[o] = target;
+    seg_of[o] = i;
+    u_in[o] = target - acc;
     ++o;
   }
 }
@@ -446,7 +449,7 @@ extern "C" fppg_status fppg_features(fppg_ctx* ctx, const double* vert, int32_t 
   int* poff = d.alloc<int>(n_lines + 1);
   if (!pcnt || !poff) return fail(ctx, FPPG_E_HIP, "device allocation failed");
   feat::k_line_particles<<<feat::nb(n_lines), 256, 0, s>>>(d_vert, lbegin, lvert, lclosed, n_lines, dx, 0, pcnt,
-                                                           nullptr, nullptr, nullptr, nullptr);
+                                                           nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
   int np = 0;
   if (!scan(d, pcnt, poff, n_lines, s, &np)) return fail(ctx, FPPG_E_HIP, "scan failed");
   out->n_edges = ne;
@@ -464,13 +467,13 @@ extern "C" fppg_status fppg_features(fppg_ctx* ctx, const double* vert, int32_t 
     return fail(ctx, FPPG_E_CAPACITY, "an output exceeds its capacity (the counts hold the sizes needed)");
   }
   if ((ne && !out->edges) || (nsing && !out->singular) || (n_lines && !out->line_closed) ||
-      (n_lv && !out->line_vert) || (np && (!out->pos || !out->line_of || !out->arc))) {
+      (n_lv && !out->line_vert) || (np && (!out->pos || !out->line_of || !out->arc || !out->seg || !out->u))) {
     FPPG_HIP(ctx, hipStreamSynchronize(s));
     return fail(ctx, FPPG_E_ARG, "null output array");
   }
   feat::k_line_particles<<<feat::nb(n_lines), 256, 0, s>>>(d_vert, lbegin, lvert, lclosed, n_lines, dx, 1, pcnt,
                                                            poff, reinterpret_cast<float4*>(out->pos), out->line_of,
-                                                           out->arc);
+                                                           out->arc, out->seg, out->u);
   FPPG_HIP(ctx, hipGetLastError());
   if (ne) FPPG_HIP(ctx, hipMemcpyAsync(out->edges, edges, sizeof(int) * 2 * ne, hipMemcpyDeviceToDevice, s));
   if (nsing) FPPG_HIP(ctx, hipMemcpyAsync(out->singular, sing, sizeof(int) * nsing, hipMemcpyDeviceToDevice, s));

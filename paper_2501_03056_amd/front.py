@@ -46,7 +46,8 @@ def features(vert, tri, cos_threshold: float, dx: float, device: int = 0, ctx: C
     """Feature edges, singular vertices, feature lines and feature-line
     particles of a mesh (fppg_features). Returns a dict of device tensors:
     edges [E, 2], singular [S], line_begin [L + 1], line_vert [V],
-    line_closed [L], pos [P, 4] (w = tag bits), line_of [P], arc [P] (float64)."""
+    line_closed [L], pos [P, 4] (w = tag bits), line_of [P], arc [P] (float64),
+    seg [P] (segment of the line) and u [P] (float64, arc length inside it)."""
     if not torch.cuda.is_available():
         raise RuntimeError("features() needs a GPU (no CPU fallback)")
     ctx = ctx or Context(device)
@@ -69,13 +70,16 @@ def features(vert, tri, cos_threshold: float, dx: float, device: int = 0, ctx: C
          "line_closed": torch.empty(max(sizes.n_lines, 1), dtype=torch.uint8, device=dev),
          "pos": torch.empty((max(sizes.n_particles, 1), 4), dtype=torch.float32, device=dev),
          "line_of": torch.empty(max(sizes.n_particles, 1), dtype=torch.int32, device=dev),
-         "arc": torch.empty(max(sizes.n_particles, 1), dtype=torch.float64, device=dev)}
+         "arc": torch.empty(max(sizes.n_particles, 1), dtype=torch.float64, device=dev),
+         "seg": torch.empty(max(sizes.n_particles, 1), dtype=torch.int32, device=dev),
+         "u": torch.empty(max(sizes.n_particles, 1), dtype=torch.float64, device=dev)}
     o = L.FeaturesOut(ptr(t["edges"]), sizes.n_edges, ptr(t["singular"]), sizes.n_singular, ptr(t["line_begin"]),
                       ptr(t["line_vert"]), ptr(t["line_closed"]), sizes.n_lines, sizes.n_line_vert, ptr(t["pos"]),
-                      ptr(t["line_of"]), ptr(t["arc"]), sizes.n_particles)
+                      ptr(t["line_of"]), ptr(t["arc"]), ptr(t["seg"]), ptr(t["u"]), sizes.n_particles)
     check(call(o), ctx.handle)
     n = {"edges": o.n_edges, "singular": o.n_singular, "line_vert": o.n_line_vert, "line_closed": o.n_lines,
-         "pos": o.n_particles, "line_of": o.n_particles, "arc": o.n_particles}
+         "pos": o.n_particles, "line_of": o.n_particles, "arc": o.n_particles, "seg": o.n_particles,
+         "u": o.n_particles}
     return {k: (v[: n[k]] if k in n else v) for k, v in t.items()}
 
 

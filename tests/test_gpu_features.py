@@ -60,3 +60,19 @@ def test_open_mesh_boundary_edges_are_features():
     assert [tuple(e) for e in got["edges"].tolist()] == fe == [(0, 1), (0, 3), (1, 2), (2, 3)]
     assert got["line_closed"].tolist() == closed == [1]
     assert np.array_equal(got["pos"][:, :3], parts.astype(np.float32))
+
+
+def test_particle_segment_and_arc_are_consistent():
+    m = M.gear(samples_per_period=12, rings=4)
+    got = _features(m.vert, m.tri, COS30, 0.02)
+    lb, lv = got["line_begin"], got["line_vert"]
+    closed = got["line_closed"]
+    for k in range(0, len(got["pos"]), 7):
+        l, s, u = int(got["line_of"][k]), int(got["seg"][k]), float(got["u"][k])
+        vs = lv[lb[l]:lb[l + 1]].tolist() + ([lv[lb[l]]] if closed[l] else [])
+        a, b = m.vert[vs[s]], m.vert[vs[s + 1]]
+        L = np.linalg.norm(b - a)
+        assert -1e-12 <= u <= L + 1e-12
+        before = sum(np.linalg.norm(m.vert[vs[i + 1]] - m.vert[vs[i]]) for i in range(s))
+        assert abs(before + u - got["arc"][k]) < 1e-12
+        assert np.allclose(got["pos"][k, :3], (a + (u / L) * (b - a)).astype(np.float32), atol=1e-6)
