@@ -76,3 +76,50 @@ def test_particle_segment_and_arc_are_consistent():
         before = sum(np.linalg.norm(m.vert[vs[i + 1]] - m.vert[vs[i]]) for i in range(s))
         assert abs(before + u - got["arc"][k]) < 1e-12
         assert np.allclose(got["pos"][k, :3], (a + (u / L) * (b - a)).astype(np.float32), atol=1e-6)
+
+
+def test_capacity_error_keeps_the_sizes():
+    """Outputs one particle short: E_CAPACITY, nothing written, and the counts
+    still hold the sizes needed."""
+    import ctypes
+    from paper_2501_03056_amd import _lib as L
+    from paper_2501_03056_amd.relax import Context
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    m = M.cube()
+    ctx = Context(0)
+    vert = np.ascontiguousarray(m.vert, np.float64)
+    tri = np.ascontiguousarray(m.tri, np.int32)
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def call(o):
+        return ctx.lib.fppg_features(ctx.handle, vert.ctypes.data_as(ctypes.c_void_p), len(vert),
+                                     tri.ctypes.data_as(ctypes.c_void_p), len(tri), COS30, 0.05, ctypes.byref(o),
+                                     stream)
+
+    sizes = L.FeaturesOut()
+    assert call(sizes) == L.OK
+    assert (sizes.n_edges, sizes.n_singular, sizes.n_lines) == (12, 8, 12)
+    np_ = sizes.n_particles
+    d = "cuda"
+    edges = torch.empty((12, 2), dtype=torch.int32, device=d)
+    sing = torch.empty(8, dtype=torch.int32, device=d)
+    lb = torch.full((13,), -7, dtype=torch.int32, device=d)
+    lv = torch.empty(sizes.n_line_vert, dtype=torch.int32, device=d)
+    lc = torch.empty(12, dtype=torch.uint8, device=d)
+    pos = torch.empty((np_, 4), dtype=torch.float32, device=d)
+    li = torch.empty(np_, dtype=torch.int32, device=d)
+    arc = torch.empty(np_, dtype=torch.float64, device=d)
+    seg = torch.empty(np_, dtype=torch.int32, device=d)
+    u = torch.empty(np_, dtype=torch.float64, device=d)
+    P = L.ptr
+    o = L.FeaturesOut(P(edges), 12, P(sing), 8, P(lb), P(lv), P(lc), 12, sizes.n_line_vert, P(pos), P(li), P(arc),
+                      P(seg), P(u), np_ - 1)
+    assert call(o) == L.E_CAPACITY
+    assert o.n_particles == np_ and o.n_edges == 12
+    assert (lb == -7).all()
+    o.cap_particles = np_
+    assert call(o) == L.OK
+    torch.cuda.synchronize()
+    assert lb[-1].item() == sizes.n_line_vert
+    ctx.close()

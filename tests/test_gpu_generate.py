@@ -83,3 +83,30 @@ def test_cells_boolean_matches_oracle(op):
     ra = torch.from_numpy(rng.integers(0, 3, 5000).astype(np.uint8)).cuda()
     rb = torch.from_numpy(rng.integers(0, 3, 5000).astype(np.uint8)).cuda()
     assert np.array_equal(cells_boolean(ra, rb, op).cpu().numpy(), G.boolean(ra.cpu().numpy(), rb.cpu().numpy(), op))
+
+
+EDGE_CASES = {
+    # (mesh, dx, origin, dims): grids that miss, straddle or barely cover the solid
+    "away": (lambda: M.cube(), 0.1, (3.0, 3.0, 3.0), (5, 4, 3)),
+    "above": (lambda: M.cube(), 0.1, (-0.15, -0.15, 1.5), (13, 13, 4)),
+    "cut_through": (lambda: M.cube(), 0.1, (-0.15, -0.15, 0.45), (13, 13, 10)),
+    "single_cell": (lambda: M.cube(), 2.0, (-0.5, -0.5, -0.5), (1, 1, 1)),
+    "one_column": (lambda: M.icosphere(2), 0.1, (-0.05, -0.05, -1.25), (1, 1, 25)),
+}
+
+
+@pytest.mark.parametrize("case", list(EDGE_CASES))
+def test_generate_edge_grids_match_oracle(case):
+    make, dx, origin, dims = EDGE_CASES[case]
+    m = make()
+    cls, pos, owner = _gen(m.vert, m.tri, dx, origin, dims)
+    ref_cls, ref_pos, ref_tag, ref_owner = G.generate(m.vert, m.tri, dx, np.array(origin, np.float64), dims)
+    assert np.array_equal(cls, ref_cls)
+    assert len(pos) == len(ref_pos)
+    assert np.array_equal(pos[:, :3], ref_pos.astype(np.float32))
+    assert np.array_equal(pos[:, 3].view(np.int32) & 7, ref_tag)
+    assert np.array_equal(owner, ref_owner)
+    if case in ("away", "above"):
+        assert not cls.any() and len(pos) == 0
+    if case == "cut_through":
+        assert (cls == G.INTERNAL).any() and (cls[-1] == G.EXTERNAL).all()
