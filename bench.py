@@ -39,6 +39,39 @@ def roofline_note():
             "3 fma (accumulate); candidates rejected by the predicate are not counted")
 
 
+# Algorithmic HBM bytes of the streaming phases (each particle or cell read or
+# written once, as the kernels are designed to do): cell rebuild 112 B per
+# particle (pos 16 read; key + rank 8 written, 8 read; scatter 20; final
+# gather 48 + 12) + 12 B per cell (count, scan, cell_start); update 52 B per
+# launched particle (pos, accel, owner read, disp written); projection 48 B per
+# moving particle (pos and disp read, pos written) + 8 B per surface particle
+# (owner read and written); force 32 B per moving receiver (own pos read,
+# accel written; the sources are re-read from cache).
+BUILD_B_PER_PARTICLE, BUILD_B_PER_CELL = 112, 12
+UPDATE_B, PROJECT_B, PROJECT_SURF_B, FORCE_B = 52, 48, 8, 32
+
+
+def hbm_phases(wl, ncell, n_moving, phase_ms, ms_step):
+    """Achieved GB/s of algorithmic bytes per phase against the 8 TB/s HBM
+    peak (phase times from the event-timed breakdown pass), and for the whole
+    step with the force kernel's own bytes included."""
+    n_surf = int(np.sum(np.asarray(wl.tag) == 2))
+    bytes_ = {"build_cells": BUILD_B_PER_PARTICLE * wl.n + BUILD_B_PER_CELL * ncell,
+              "update": UPDATE_B * wl.n,
+              "project": PROJECT_B * n_moving + PROJECT_SURF_B * n_surf,
+              "force": FORCE_B * n_moving}
+    out = {}
+    for k, b in bytes_.items():
+        if k in phase_ms and phase_ms[k] > 0:
+            gbs = b / (phase_ms[k] / 1e3) / 1e9
+            out[k] = {"bytes": b, "ms": phase_ms[k], "GB/s": gbs, "frac": gbs / PEAK_HBM_GBS}
+    step_b = sum(bytes_.values())
+    gbs = step_b / (ms_step / 1e3) / 1e9
+    out["step"] = {"bytes": step_b, "ms": ms_step, "GB/s": gbs, "frac": gbs / PEAK_HBM_GBS,
+                   "note": "the step is bound by the force kernel's instruction issue, not by HBM"}
+    return out
+
+
 def make_workload(name, k=2, slab=0):
     import synth
     if name == "sphere":
@@ -243,10 +276,12 @@ def bench_gear(args):
             layer = {"width": width, "width_dx": args.layer_width, "core": r.volume_layers(width)}
             print(f"[bench] volume layer: width {width:g}, {layer['core']} particles fixed as the core",
                   file=sys.stderr, flush=True)
-        r.move_mask = mm
+        # a sparse tier leaves out the particles it does not reach (rank above
+        # its moving class: neither receivers nor sources)
+        r.tier(mm, compact=not args.no_compact)
         n_moving = r.n_moving()
         # a sparse tier launches only its moving particles' lanes
-        r.use_list = not args.no_list and n_moving < wl.n // 2
+        r.use_list = not args.no_list and n_moving < r.na // 2
         for _ in range(args.warmup):
             r.step(keep_accel=False)
         r.build_cells()
@@ -272,9 +307,10 @@ def bench_gear(args):
         out_tiers[name] = {"moving": n_moving, "iters": args.tier_iters, "ms_per_step": ms / args.tier_iters,
                            "particle_updates_per_s": n_moving * args.tier_iters / (ms / 1e3),
                            "pairs_per_step": pairs, "pair_evals_per_s": pairs * args.tier_iters / (ms / 1e3),
-                           "receiver_list": bool(r.use_list),
+                           "receiver_list": bool(r.use_list), "active_particles": r.na,
                            "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]}}
-        print(f"[bench] tier {name}: {n_moving} moving, {ms / args.tier_iters:.3f} ms/step", file=sys.stderr,
+        print(f"[bench] tier {name}: {n_moving} moving of {r.na} active, {ms / args.tier_iters:.3f} ms/step",
+              file=sys.stderr,
               flush=True)
     t3 = [out_tiers[k] for k in ("feature", "surface", "volume_layer")]
     three_layer = {"particle_updates_per_s": sum(t["moving"] * t["iters"] for t in t3)
@@ -376,6 +412,8 @@ def main():
                     help="gear: width of the relaxed volume layer in units of dx (three-layer tier)")
     ap.add_argument("--no-list", action="store_true",
                     help="gear tiers: launch every particle's lane instead of the moving-particle list")
+    ap.add_argument("--no-compact", action="store_true",
+                    help="gear tiers: keep every particle active (no tier partition)")
     ap.add_argument("--plain-iters", type=int, default=100)
     ap.add_argument("--newton-dx", type=float, default=None, help="default 0.004 (gear), 0.01 (sphere)")
     ap.add_argument("--newton-workload", default="gear", choices=["gear", "sphere"])
@@ -463,6 +501,8 @@ def main():
     achieved = pairs * FLOPS_PER_PAIR / (force_ms / 1e3) / 1e12
     khash = source_hash(KERNEL_SOURCES)
     traffic = traffic_from_profile(khash)
+    phase_ms = {k: (v[0] / max(v[1], 1)) for k, v in prof.items() if v[1]}
+    hbm = hbm_phases(wl, int(r.geom.ncell), n_moving, phase_ms, ms_step)
     out = {
         "metric": "particle-updates/s per relaxation step",
         "value": value,
@@ -480,7 +520,8 @@ def main():
                    "stencil_k": int(wl.geoms[0].k), "key_slab_rows": int(args.slab), "h_over_dx": 1.3,
                    "pairs_per_step": pairs},
         "pair_evals_per_s": pairs * args.steps / (ms / 1e3),
-        "kernels_ms_per_step": {k: (v[0] / max(v[1], 1)) for k, v in prof.items() if v[1]},
+        "kernels_ms_per_step": phase_ms,
+        "hbm_phases": hbm,
         "roofline": {"bound": "alu", "kernel": "k_force", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                      "work_per_launch": pairs * FLOPS_PER_PAIR, "avg_launch_ms": force_ms,

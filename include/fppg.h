@@ -173,6 +173,8 @@ fppg_status fppg_profile_read(fppg_ctx* ctx, double* ms /*[FPPG_NPHASES]*/, int6
  * every cell they touch, section 3.1.1-3.1.2; built on the host), feature
  * segments, and the per-geometry particle-grid descriptors. Synchronous;
  * allocates device memory owned by the returned object.
+ * The per-iteration calls take n = the descriptors' particle count (the
+ * active count, until fppg_tier_partition narrows it).
  * Errors: FPPG_E_ARG for inconsistent descriptors (particle ranges must tile
  * [0, n) in order, indices in range), FPPG_E_UNSUPPORTED for k not in {1, 2}
  * or differing across the batch, FPPG_E_CAPACITY beyond 2^31 cells/entries.
@@ -188,6 +190,35 @@ fppg_status fppg_geom_info(const fppg_geom* geom, int64_t* ncell, int64_t* n_tri
 
 /* Workspace bytes needed by the per-iteration calls for n particles. */
 fppg_status fppg_workspace_size(const fppg_geom* geom, int64_t n, size_t* bytes);
+
+/*
+ * Tier partition (the tiers of Algorithm 1: feature lines, then surfaces,
+ * then the volume, section 3.3). A particle takes as sources only the classes
+ * of rank at most its own (section 2.2), so in a tier whose highest moving
+ * class has rank R the particles of rank > R are neither receivers nor
+ * sources: a volume particle plays no part while the feature lines or the
+ * surfaces relax. The call stably partitions the n = all particles of the
+ * geometry (pos_in, id_in, owner_in, in their current order) into out: first
+ * the *n_active particles of rank <= R, then the rest, each part in input
+ * order. The rest [*n_active, n) is also copied back into the input arrays,
+ * so both buffers of a double-buffered state hold it.
+ * From then on the geometry's active count is *n_active: every call that
+ * takes the geometry (build_cells, relax_step, project, relax_hvp, ...)
+ * must be passed n = *n_active and touches only that prefix; the other
+ * particles stay where they are. The forces, displacements and projections
+ * of the movers are bitwise those of the calls on all n particles (the
+ * skipped particles contribute exact zeros there). A move_mask with the volume
+ * class (R = 3), or with no moving class, reaches every particle: out is a
+ * copy of the input and the active count is n again.
+ * R is the highest of rank 1 (feature, bit FPPG_TAG_FEATURE), 2 (surface)
+ * and 3 (volume) set in move_mask. ws: at least fppg_workspace_size(n) bytes.
+ * Synchronous (it reads the count back). Errors: FPPG_E_ARG for null or
+ * misaligned arrays, aliasing outputs or n other than the descriptors'
+ * particle count; FPPG_E_WORKSPACE.
+ */
+fppg_status fppg_tier_partition(fppg_ctx* ctx, fppg_geom* geom, int64_t n, float* pos_in, int32_t* id_in,
+                                int32_t* owner_in, float* pos_out, int32_t* id_out, int32_t* owner_out,
+                                uint32_t move_mask, int64_t* n_active, void* ws, size_t ws_bytes, void* stream);
 
 /* ---- per-iteration calls (device pointers, stream-ordered, no allocation) ---------------- */
 

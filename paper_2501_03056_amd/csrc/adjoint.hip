@@ -305,7 +305,7 @@ extern "C" fppg_status fppg_uniformity_loss(fppg_ctx* ctx, const fppg_geom* geom
                                             const int32_t* cell_start, uint32_t move_mask, double rho0, double* out,
                                             float* grad, void* ws, size_t ws_bytes, void* stream) {
   if (!ctx || !geom) return fail(ctx, FPPG_E_ARG, "null ctx/geom");
-  if (n != geom->n_part || n < 1) return fail(ctx, FPPG_E_ARG, "n differs from the geometry's particle count");
+  if (n != geom->n_active || n < 1) return fail(ctx, FPPG_E_ARG, "n differs from the active particle count of the geometry");
   if (!pos || !cell_start || !out || !ws || !aligned(pos, 16) || !aligned(ws, 256) || (grad && !aligned(grad, 16)))
     return fail(ctx, FPPG_E_ARG, "null or misaligned argument");
   if (!(rho0 > 0.0)) return fail(ctx, FPPG_E_ARG, "rho0 must be > 0");
@@ -341,7 +341,7 @@ extern "C" fppg_status fppg_step_adjoint(fppg_ctx* ctx, const fppg_geom* geom, i
                                          uint32_t move_mask, const float* xbar_next, float* ybar, float* xbar,
                                          int64_t* vbar_fixed, void* stream) {
   if (!ctx || !geom) return fail(ctx, FPPG_E_ARG, "null ctx/geom");
-  if (n != geom->n_part) return fail(ctx, FPPG_E_ARG, "n differs from the geometry's particle count");
+  if (n != geom->n_active) return fail(ctx, FPPG_E_ARG, "n differs from the active particle count of the geometry");
   if (n_feat < 0 || (n_feat > 0 && (!fseg_before || !fseg_after || !fu_after)))
     return fail(ctx, FPPG_E_ARG, "bad feature tables");
   if (n > 0 && (!pos || !accepted || !owner || !owner_next || !accel || !amax || !xbar_next || !ybar || !xbar ||
@@ -368,7 +368,7 @@ extern "C" fppg_status fppg_fixed_adjoint(fppg_ctx* ctx, const fppg_geom* geom, 
                                           int32_t n_feat, uint32_t move_mask, const float* xbar, int64_t* vbar_fixed,
                                           void* stream) {
   if (!ctx || !geom) return fail(ctx, FPPG_E_ARG, "null ctx/geom");
-  if (n != geom->n_part) return fail(ctx, FPPG_E_ARG, "n differs from the geometry's particle count");
+  if (n != geom->n_active) return fail(ctx, FPPG_E_ARG, "n differs from the active particle count of the geometry");
   if (n > 0 && (!pos || !owner || !xbar || !vbar_fixed)) return fail(ctx, FPPG_E_ARG, "null argument");
   if (n_feat < 0 || (n_feat > 0 && (!feat_seg || !feat_u))) return fail(ctx, FPPG_E_ARG, "bad feature table");
   if (!aligned(pos, 16) || !aligned(xbar, 16)) return fail(ctx, FPPG_E_ARG, "misaligned argument");

@@ -105,7 +105,7 @@ using namespace fppg;
 extern "C" fppg_status fppg_volume_layers(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, float* pos, double width,
                                           int32_t* count, void* stream) {
   if (!ctx || !geom) return fail(ctx, FPPG_E_ARG, "null ctx/geom");
-  if (n != geom->n_part) return fail(ctx, FPPG_E_ARG, "n differs from the particle count of the geometry descriptors");
+  if (n != geom->n_active) return fail(ctx, FPPG_E_ARG, "n differs from the active particle count of the geometry");
   if (!count || (n > 0 && !pos)) return fail(ctx, FPPG_E_ARG, "null pos/count");
   if (!aligned(pos, 16)) return fail(ctx, FPPG_E_ARG, "pos must be 16-byte aligned");
   if (!(width >= 0.0) || !std::isfinite(width)) return fail(ctx, FPPG_E_ARG, "width must be finite and >= 0");

@@ -223,6 +223,47 @@ __global__ __launch_bounds__(kBlock) void k_list_write(const float4* __restrict_
   if (blockIdx.x == nb - 1 && threadIdx.x == 0) count[0] = offs[blockIdx.x] + total;
 }
 
+// ---- tier partition: the particles a tier reaches first -----------------------------------
+// A particle is reached when its class rank is at most R, the highest rank of
+// the moving classes: the movers and every class they take as a source.
+
+__device__ __forceinline__ bool reached_at(const float4* __restrict__ pos, int i, int n, int R) {
+  return i < n && rank_of(tag_of(pos[i].w)) <= R;
+}
+
+__global__ __launch_bounds__(kBlock) void k_part_count(const float4* __restrict__ pos, int n, int R,
+                                                       int* __restrict__ cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int total;
+  block_rank(reached_at(pos, i, n, R), &total);
+  if (threadIdx.x == 0) cnt[blockIdx.x] = total;
+}
+
+// offs = exclusive prefix of cnt over the blocks: reached particles go to
+// offs[b] + (reached lanes below), the others after all reached ones in the
+// same relative order
+__global__ __launch_bounds__(kBlock) void k_part_write(const float4* __restrict__ pos_in,
+                                                       const int* __restrict__ id_in,
+                                                       const int* __restrict__ owner_in, int n, int R,
+                                                       const int* __restrict__ cnt, const int* __restrict__ offs,
+                                                       int nb, float4* __restrict__ pos_out,
+                                                       int* __restrict__ id_out, int* __restrict__ owner_out,
+                                                       int* __restrict__ count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool m = reached_at(pos_in, i, n, R);
+  int total;
+  const int r = block_rank(m, &total);
+  const int reached = offs[nb - 1] + cnt[nb - 1];
+  if (i < n) {
+    const int dst = m ? offs[blockIdx.x] + r
+                      : reached + (blockIdx.x * kBlock - offs[blockIdx.x]) + (int(threadIdx.x) - r);
+    pos_out[dst] = pos_in[i];
+    id_out[dst] = id_in[i];
+    owner_out[dst] = owner_in[i];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) count[0] = reached;
+}
+
 static inline int grid_for(int64_t n, int block) { return int((n + block - 1) / block); }
 
 }  // namespace fppg
@@ -234,7 +275,7 @@ extern "C" fppg_status fppg_build_cells(fppg_ctx* ctx, const fppg_geom* geom, in
                                         int32_t* id_out, int32_t* owner_out, int32_t* cell_start, void* ws,
                                         size_t ws_bytes, void* stream) {
   if (!ctx || !geom) return fail(ctx, FPPG_E_ARG, "null ctx/geom");
-  if (n != geom->n_part) return fail(ctx, FPPG_E_ARG, "n differs from the particle count of the geometry descriptors");
+  if (n != geom->n_active) return fail(ctx, FPPG_E_ARG, "n differs from the active particle count of the geometry");
   if (n > 0 && (!pos_in || !id_in || !owner_in || !pos_out || !id_out || !owner_out))
     return fail(ctx, FPPG_E_ARG, "null particle array");
   if (!cell_start || !ws) return fail(ctx, FPPG_E_ARG, "null cell_start/ws");
@@ -279,7 +320,7 @@ extern "C" fppg_status fppg_moving_list(fppg_ctx* ctx, const fppg_geom* geom, in
                                         uint32_t move_mask, int32_t* list, int32_t* count, void* ws,
                                         size_t ws_bytes, void* stream) {
   if (!ctx || !geom) return fail(ctx, FPPG_E_ARG, "null ctx/geom");
-  if (n != geom->n_part) return fail(ctx, FPPG_E_ARG, "n differs from the particle count of the geometry descriptors");
+  if (n != geom->n_active) return fail(ctx, FPPG_E_ARG, "n differs from the active particle count of the geometry");
   if (!count || !ws || (n > 0 && (!pos || !list))) return fail(ctx, FPPG_E_ARG, "null argument");
   if (!aligned(pos, 16) || !aligned(ws, 256)) return fail(ctx, FPPG_E_ARG, "pos must be 16-byte and ws 256-byte aligned");
   const WsLayout L = ws_layout(geom, n);
@@ -304,5 +345,60 @@ extern "C" fppg_status fppg_moving_list(fppg_ctx* ctx, const fppg_geom* geom, in
   k_scan_down<<<nt, kScanThreads, 0, s>>>(cnt, nb, bsum, offs, 0);
   k_list_write<<<nb, kBlock, 0, s>>>(p4, ni, move_mask, offs, nb, list, count);
   FPPG_HIP(ctx, hipGetLastError());
+  return FPPG_OK;
+}
+
+extern "C" fppg_status fppg_tier_partition(fppg_ctx* ctx, fppg_geom* geom, int64_t n, float* pos_in, int32_t* id_in,
+                                           int32_t* owner_in, float* pos_out, int32_t* id_out, int32_t* owner_out,
+                                           uint32_t move_mask, int64_t* n_active, void* ws, size_t ws_bytes,
+                                           void* stream) {
+  if (!ctx || !geom || !n_active) return fail(ctx, FPPG_E_ARG, "null ctx/geom/n_active");
+  if (n != geom->n_part) return fail(ctx, FPPG_E_ARG, "n differs from the particle count of the geometry descriptors");
+  if (n > 0 && (!pos_in || !id_in || !owner_in || !pos_out || !id_out || !owner_out))
+    return fail(ctx, FPPG_E_ARG, "null particle array");
+  if (!ws || !aligned(pos_in, 16) || !aligned(pos_out, 16) || !aligned(ws, 256))
+    return fail(ctx, FPPG_E_ARG, "null ws, or pos not 16-byte / ws not 256-byte aligned");
+  if (n > 0 && (pos_in == pos_out || id_in == id_out || owner_in == owner_out))
+    return fail(ctx, FPPG_E_ARG, "tier_partition output must not alias its input");
+  const WsLayout L = ws_layout(geom, n);
+  if (ws_bytes < L.list_end) return fail(ctx, FPPG_E_WORKSPACE, "workspace too small for tier_partition");
+  int R = -1;
+  for (int t = FPPG_TAG_FEATURE; t <= FPPG_TAG_VOLUME; ++t)
+    if ((move_mask >> t) & 1u) R = t;   // rank_of(t) = t for these classes
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int ni = int(n);
+  int na = ni;
+  if (ni > 0 && R >= 0 && R < FPPG_TAG_VOLUME) {
+    char* w = static_cast<char*>(ws);
+    int* cnt = reinterpret_cast<int*>(w + L.list_cnt);
+    int* offs = reinterpret_cast<int*>(w + L.list_offs);
+    int* bsum = reinterpret_cast<int*>(w + L.list_bsum);
+    int* dcount = cnt + grid_for(ni, kBlock);   // list_cnt holds nb + 1 ints
+    const int nb = grid_for(ni, kBlock);
+    const int nt = int((int64_t(nb) + kScanTile - 1) / kScanTile);
+    k_part_count<<<nb, kBlock, 0, s>>>(reinterpret_cast<const float4*>(pos_in), ni, R, cnt);
+    k_scan_reduce<<<nt, kScanThreads, 0, s>>>(cnt, nb, bsum);
+    k_scan_top<<<1, kScanThreads, 0, s>>>(bsum, nt);
+    k_scan_down<<<nt, kScanThreads, 0, s>>>(cnt, nb, bsum, offs, 0);
+    k_part_write<<<nb, kBlock, 0, s>>>(reinterpret_cast<const float4*>(pos_in), id_in, owner_in, ni, R, cnt, offs,
+                                       nb, reinterpret_cast<float4*>(pos_out), id_out, owner_out, dcount);
+    FPPG_HIP(ctx, hipGetLastError());
+    FPPG_HIP(ctx, hipMemcpyAsync(&na, dcount, sizeof(int), hipMemcpyDeviceToHost, s));
+    FPPG_HIP(ctx, hipStreamSynchronize(s));
+    if (na < ni) {   // the unreached tail into the input buffers too: both halves of a double buffer hold it
+      const size_t t = size_t(ni - na);
+      FPPG_HIP(ctx, hipMemcpyAsync(pos_in + 4 * size_t(na), pos_out + 4 * size_t(na), 16 * t,
+                                   hipMemcpyDeviceToDevice, s));
+      FPPG_HIP(ctx, hipMemcpyAsync(id_in + na, id_out + na, 4 * t, hipMemcpyDeviceToDevice, s));
+      FPPG_HIP(ctx, hipMemcpyAsync(owner_in + na, owner_out + na, 4 * t, hipMemcpyDeviceToDevice, s));
+    }
+  } else if (ni > 0) {   // every particle is reached (or nothing moves): order unchanged
+    FPPG_HIP(ctx, hipMemcpyAsync(pos_out, pos_in, 16 * size_t(ni), hipMemcpyDeviceToDevice, s));
+    FPPG_HIP(ctx, hipMemcpyAsync(id_out, id_in, 4 * size_t(ni), hipMemcpyDeviceToDevice, s));
+    FPPG_HIP(ctx, hipMemcpyAsync(owner_out, owner_in, 4 * size_t(ni), hipMemcpyDeviceToDevice, s));
+  }
+  FPPG_HIP(ctx, hipStreamSynchronize(s));
+  geom->n_active = na;
+  *n_active = na;
   return FPPG_OK;
 }

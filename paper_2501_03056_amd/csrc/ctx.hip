@@ -337,6 +337,7 @@ static fppg_status geom_create(fppg_ctx* ctx, const fppg_geom_desc* descs, int32
   geo->tg_cells = tg_cells;
   geo->tg_entries = int64_t(tg_tri.size());
   geo->n_part = part;
+  geo->n_active = part;
   geo->n_vert = vert_off;
   geo->host = gd;
   geo->device = ctx->device;

@@ -172,7 +172,7 @@ static inline int grid_for(int64_t n) { return int((n + kBlock - 1) / kBlock); }
 static fppg_status check_common(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, const float* pos,
                                 const int32_t* cs) {
   if (!ctx || !geom) return fail(ctx, FPPG_E_ARG, "null ctx/geom");
-  if (n != geom->n_part) return fail(ctx, FPPG_E_ARG, "n differs from the particle count of the geometry descriptors");
+  if (n != geom->n_active) return fail(ctx, FPPG_E_ARG, "n differs from the active particle count of the geometry");
   if (n > 0 && (!pos || !cs)) return fail(ctx, FPPG_E_ARG, "null pos/cell_start");
   if (!aligned(pos, 16)) return fail(ctx, FPPG_E_ARG, "pos must be 16-byte aligned");
   return FPPG_OK;

@@ -65,6 +65,7 @@ struct Geom {
   int64_t n_tri = 0, n_seg = 0;
   int64_t tg_cells = 0, tg_entries = 0;
   int64_t n_part = 0;
+  int64_t n_active = 0;             // particles the per-iteration calls take (a tier's reached prefix)
   int64_t n_vert = 0;               // mesh vertices over the batch
   std::vector<GeomDev> host;
   GeomDev* d_geom = nullptr;

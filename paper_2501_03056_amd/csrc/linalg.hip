@@ -237,7 +237,7 @@ extern "C" fppg_status fppg_tangent_project(fppg_ctx* ctx, const fppg_geom* geom
                                             const int32_t* owner, const int32_t* feat_seg, int32_t n_feat,
                                             uint32_t move_mask, float* v, void* stream) {
   if (!ctx || !geom) return fail(ctx, FPPG_E_ARG, "null ctx/geom");
-  if (n != geom->n_part) return fail(ctx, FPPG_E_ARG, "n differs from the particle count of the geometry descriptors");
+  if (n != geom->n_active) return fail(ctx, FPPG_E_ARG, "n differs from the active particle count of the geometry");
   if (n > 0 && (!pos || !owner || !v)) return fail(ctx, FPPG_E_ARG, "null argument");
   if (n_feat < 0 || (n_feat > 0 && !feat_seg)) return fail(ctx, FPPG_E_ARG, "bad feature table");
   if (!aligned(pos, 16) || !aligned(v, 16)) return fail(ctx, FPPG_E_ARG, "misaligned argument");
@@ -272,7 +272,7 @@ extern "C" fppg_status fppg_displace(fppg_ctx* ctx, const fppg_geom* geom, int64
                                      const int32_t* owner, const int32_t* feat_seg, int32_t n_feat, uint32_t move_mask,
                                      const float* v, float alpha, float* disp, void* stream) {
   if (!ctx || !geom) return fail(ctx, FPPG_E_ARG, "null ctx/geom");
-  if (n != geom->n_part) return fail(ctx, FPPG_E_ARG, "n differs from the particle count of the geometry descriptors");
+  if (n != geom->n_active) return fail(ctx, FPPG_E_ARG, "n differs from the active particle count of the geometry");
   if (n > 0 && (!pos || !owner || !v || !disp)) return fail(ctx, FPPG_E_ARG, "null argument");
   if (n_feat < 0 || (n_feat > 0 && !feat_seg)) return fail(ctx, FPPG_E_ARG, "bad feature table");
   if (!aligned(pos, 16) || !aligned(v, 16) || !aligned(disp, 16)) return fail(ctx, FPPG_E_ARG, "misaligned argument");

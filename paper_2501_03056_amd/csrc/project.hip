@@ -373,7 +373,7 @@ static fppg_status project_impl(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
                                 uint32_t move_mask, int64_t* counters, const int32_t* list, int32_t n_list,
                                 uint8_t* accepted, void* ws, size_t ws_bytes, void* stream) {
   if (!ctx || !geom) return fail(ctx, FPPG_E_ARG, "null ctx/geom");
-  if (n != geom->n_part) return fail(ctx, FPPG_E_ARG, "n differs from the particle count of the geometry descriptors");
+  if (n != geom->n_active) return fail(ctx, FPPG_E_ARG, "n differs from the active particle count of the geometry");
   if (n > 0 && (!pos || !owner || !disp)) return fail(ctx, FPPG_E_ARG, "null pos/owner/disp");
   if (n_feat < 0 || (n_feat > 0 && (!feat_seg || !feat_u))) return fail(ctx, FPPG_E_ARG, "bad feature table");
   if (!aligned(pos, 16) || !aligned(disp, 16)) return fail(ctx, FPPG_E_ARG, "pos/disp must be 16-byte aligned");

@@ -133,6 +133,7 @@ class Relaxer:
         self.ctx = ctx or Context(device)
         self.geom = Geometry(self.ctx, wl.geoms)
         self.n = int(wl.n)
+        self.na = self.n   # active particles (a tier's reached prefix, see tier())
         self.n_feat = int(len(wl.feat_seg))
         self.move_mask = int(wl.move_mask)
         self.h_min = min(float(g.h) for g in wl.geoms)
@@ -178,7 +179,7 @@ class Relaxer:
 
     def build_cells(self):
         lib, c = self.ctx.lib, self.ctx.handle
-        check(lib.fppg_build_cells(c, self.geom.handle, self.n, ptr(self.pos), ptr(self.id), ptr(self.owner),
+        check(lib.fppg_build_cells(c, self.geom.handle, self.na, ptr(self.pos), ptr(self.id), ptr(self.owner),
                                    ptr(self.pos_b), ptr(self.id_b), ptr(self.owner_b), ptr(self.cell_start),
                                    self.ws_ptr, self.ws_bytes, self.stream), c)
         self.pos, self.pos_b = self.pos_b, self.pos
@@ -187,10 +188,29 @@ class Relaxer:
         if self.use_list:
             self.moving_list()
 
+    def tier(self, move_mask: int, compact: bool = True) -> int:
+        """Switch to the tier in which the classes of move_mask move. With
+        compact, the particles that the tier does not reach (rank above its
+        highest moving class: neither receivers nor sources) are partitioned
+        behind the others and left out of every call until the next tier;
+        returns the number of active particles."""
+        lib, c = self.ctx.lib, self.ctx.handle
+        self.move_mask = int(move_mask)
+        mm = self.move_mask if compact else (1 << 3)   # volume bit: every particle active
+        na = ctypes.c_int64()
+        check(lib.fppg_tier_partition(c, self.geom.handle, self.n, ptr(self.pos), ptr(self.id), ptr(self.owner),
+                                      ptr(self.pos_b), ptr(self.id_b), ptr(self.owner_b), mm, ctypes.byref(na),
+                                      self.ws_ptr, self.ws_bytes, self.stream), c)
+        self.pos, self.pos_b = self.pos_b, self.pos
+        self.id, self.id_b = self.id_b, self.id
+        self.owner, self.owner_b = self.owner_b, self.owner
+        self.na = int(na.value)
+        return self.na
+
     def moving_list(self):
         """Sorted indices of the moving particles into self.mlist (count in self.mcount)."""
         lib, c = self.ctx.lib, self.ctx.handle
-        check(lib.fppg_moving_list(c, self.geom.handle, self.n, ptr(self.pos), self.move_mask, ptr(self.mlist),
+        check(lib.fppg_moving_list(c, self.geom.handle, self.na, ptr(self.pos), self.move_mask, ptr(self.mlist),
                                    ptr(self.mcount), self.ws_ptr, self.ws_bytes, self.stream), c)
 
     def volume_layers(self, width: float) -> int:
@@ -198,7 +218,7 @@ class Relaxer:
         (the core); returns how many. The others remain volume particles (the layer a volume tier relaxes)."""
         lib, c = self.ctx.lib, self.ctx.handle
         cnt = torch.zeros(1, dtype=torch.int32, device=self.dev)
-        check(lib.fppg_volume_layers(c, self.geom.handle, self.n, ptr(self.pos), float(width), ptr(cnt),
+        check(lib.fppg_volume_layers(c, self.geom.handle, self.na, ptr(self.pos), float(width), ptr(cnt),
                                      self.stream), c)
         k = int(cnt.cpu()[0])
         self._tag_counts[3] -= k
@@ -211,21 +231,21 @@ class Relaxer:
     def relax_step(self, count_pairs: bool = False, keep_accel: bool = True):
         lib, c = self.ctx.lib, self.ctx.handle
         flags = L.F_COUNT_PAIRS if count_pairs else 0
-        check(lib.fppg_relax_step(c, self.geom.handle, self.n, ptr(self.pos), ptr(self.owner), ptr(self.cell_start),
+        check(lib.fppg_relax_step(c, self.geom.handle, self.na, ptr(self.pos), ptr(self.owner), ptr(self.cell_start),
                                   ptr(self.feat_seg), self.n_feat, self.move_mask, flags,
                                   ptr(self.accel) if keep_accel else None, ptr(self.amax), ptr(self.disp),
                                   *self._list_args(), self.ws_ptr, self.ws_bytes, self.stream), c)
 
     def project(self):
         lib, c = self.ctx.lib, self.ctx.handle
-        check(lib.fppg_project(c, self.geom.handle, self.n, ptr(self.pos), ptr(self.owner), ptr(self.disp),
+        check(lib.fppg_project(c, self.geom.handle, self.na, ptr(self.pos), ptr(self.owner), ptr(self.disp),
                                ptr(self.feat_seg), ptr(self.feat_u), self.n_feat, self.move_mask,
                                ptr(self.counters), *self._list_args(), self.ws_ptr, self.ws_bytes, self.stream), c)
 
     def project_record(self, accepted: torch.Tensor):
         """project() that also writes accepted [N] uint8 (1 = the particle's move was applied)."""
         lib, c = self.ctx.lib, self.ctx.handle
-        check(lib.fppg_project_record(c, self.geom.handle, self.n, ptr(self.pos), ptr(self.owner), ptr(self.disp),
+        check(lib.fppg_project_record(c, self.geom.handle, self.na, ptr(self.pos), ptr(self.owner), ptr(self.disp),
                                       ptr(self.feat_seg), ptr(self.feat_u), self.n_feat, self.move_mask,
                                       ptr(self.counters), ptr(accepted), self.ws_ptr, self.ws_bytes, self.stream), c)
 
@@ -233,7 +253,7 @@ class Relaxer:
         """J v (or J^T v) for v [N, 4] float32 in the current (sorted) order."""
         lib, c = self.ctx.lib, self.ctx.handle
         out = torch.empty_like(v) if out is None else out
-        check(lib.fppg_relax_hvp(c, self.geom.handle, self.n, ptr(self.pos), ptr(self.cell_start),
+        check(lib.fppg_relax_hvp(c, self.geom.handle, self.na, ptr(self.pos), ptr(self.cell_start),
                                  self.move_mask, int(bool(transpose)), ptr(v), ptr(out), self.stream), c)
         return out
 
@@ -247,36 +267,36 @@ class Relaxer:
         """Pair energy E of the moving particles at the current state (cells must be current)."""
         lib, c = self.ctx.lib, self.ctx.handle
         out = self._scalar()
-        check(lib.fppg_relax_energy(c, self.geom.handle, self.n, ptr(self.pos), ptr(self.cell_start),
+        check(lib.fppg_relax_energy(c, self.geom.handle, self.na, ptr(self.pos), ptr(self.cell_start),
                                     self.move_mask, ptr(out), self.ws_ptr, self.ws_bytes, self.stream), c)
         return float(out[0].item())
 
     def dot(self, a: torch.Tensor, b: torch.Tensor) -> float:
         lib, c = self.ctx.lib, self.ctx.handle
         out = self._scalar()
-        check(lib.fppg_vec_dot(c, self.n, ptr(a), ptr(b), ptr(out), self.ws_ptr, self.ws_bytes, self.stream), c)
+        check(lib.fppg_vec_dot(c, self.na, ptr(a), ptr(b), ptr(out), self.ws_ptr, self.ws_bytes, self.stream), c)
         return float(out[0].item())
 
     def axpby(self, alpha: float, x: torch.Tensor, beta: float, y: torch.Tensor):
         """y <- alpha x + beta y (in place)."""
         lib, c = self.ctx.lib, self.ctx.handle
-        check(lib.fppg_vec_axpby(c, self.n, float(alpha), ptr(x), float(beta), ptr(y), self.stream), c)
+        check(lib.fppg_vec_axpby(c, self.na, float(alpha), ptr(x), float(beta), ptr(y), self.stream), c)
 
     def maxnorm(self, a: torch.Tensor) -> float:
         lib, c = self.ctx.lib, self.ctx.handle
         out = self._scalar()
-        check(lib.fppg_vec_maxnorm(c, self.n, ptr(a), ptr(out), self.stream), c)
+        check(lib.fppg_vec_maxnorm(c, self.na, ptr(a), ptr(out), self.stream), c)
         return float(out.view(torch.float32)[0].item())
 
     def clamp(self, v: torch.Tensor, cap: float):
         """Cap every row of v at length `cap` (in place)."""
         lib, c = self.ctx.lib, self.ctx.handle
-        check(lib.fppg_vec_clamp(c, self.n, ptr(v), float(cap), self.stream), c)
+        check(lib.fppg_vec_clamp(c, self.na, ptr(v), float(cap), self.stream), c)
 
     def hvp_projected(self, v: torch.Tensor, scale: float, out: torch.Tensor) -> torch.Tensor:
         """out = scale P (J v) in one sweep (cells must be current)."""
         lib, c = self.ctx.lib, self.ctx.handle
-        check(lib.fppg_relax_hvp_projected(c, self.geom.handle, self.n, ptr(self.pos), ptr(self.cell_start),
+        check(lib.fppg_relax_hvp_projected(c, self.geom.handle, self.na, ptr(self.pos), ptr(self.cell_start),
                                            ptr(self.owner), ptr(self.feat_seg), self.n_feat, self.move_mask,
                                            ptr(v), float(scale), ptr(out), self.stream), c)
         return out
@@ -284,19 +304,19 @@ class Relaxer:
     def combine3(self, a, x, b, y, c3, z, out, phi=0.0, acc=None):
         """out = a x + b y + c3 z; acc += phi out if acc is given."""
         lib, c = self.ctx.lib, self.ctx.handle
-        check(lib.fppg_vec_combine3(c, self.n, float(a), ptr(x), float(b), ptr(y), float(c3), ptr(z), ptr(out),
+        check(lib.fppg_vec_combine3(c, self.na, float(a), ptr(x), float(b), ptr(y), float(c3), ptr(z), ptr(out),
                                     float(phi), ptr(acc), self.stream), c)
 
     def tangent(self, v: torch.Tensor):
         """v <- P v (tangent spaces of the constrained particles; 0 where nothing moves)."""
         lib, c = self.ctx.lib, self.ctx.handle
-        check(lib.fppg_tangent_project(c, self.geom.handle, self.n, ptr(self.pos), ptr(self.owner),
+        check(lib.fppg_tangent_project(c, self.geom.handle, self.na, ptr(self.pos), ptr(self.owner),
                                        ptr(self.feat_seg), self.n_feat, self.move_mask, ptr(v), self.stream), c)
 
     def displace(self, v: torch.Tensor, alpha: float):
         """self.disp <- alpha P v in the displacement format that project() applies."""
         lib, c = self.ctx.lib, self.ctx.handle
-        check(lib.fppg_displace(c, self.geom.handle, self.n, ptr(self.pos), ptr(self.owner), ptr(self.feat_seg),
+        check(lib.fppg_displace(c, self.geom.handle, self.na, ptr(self.pos), ptr(self.owner), ptr(self.feat_seg),
                                 self.n_feat, self.move_mask, ptr(v), float(alpha), ptr(self.disp), self.stream), c)
 
     def snapshot(self):
@@ -312,7 +332,7 @@ class Relaxer:
         lib, c = self.ctx.lib, self.ctx.handle
         count = torch.zeros(self.n, dtype=torch.int32, device=self.dev)
         lst = torch.full((self.n, cap), -1, dtype=torch.int32, device=self.dev)
-        check(lib.fppg_debug_neighbors(c, self.geom.handle, self.n, ptr(self.pos), ptr(self.cell_start),
+        check(lib.fppg_debug_neighbors(c, self.geom.handle, self.na, ptr(self.pos), ptr(self.cell_start),
                                        ptr(count), ptr(lst), cap, self.stream), c)
         return count, lst
 
@@ -356,7 +376,7 @@ class Relaxer:
         lib, c = self.ctx.lib, self.ctx.handle
         h = ctypes.c_void_p()
         st = ctypes.c_void_p(self.graph_stream.cuda_stream)
-        check(lib.fppg_graph_create(c, self.geom.handle, self.n, ptr(self.pos), ptr(self.id), ptr(self.owner),
+        check(lib.fppg_graph_create(c, self.geom.handle, self.na, ptr(self.pos), ptr(self.id), ptr(self.owner),
                                     ptr(self.pos_b), ptr(self.id_b), ptr(self.owner_b), ptr(self.cell_start),
                                     ptr(self.feat_seg), ptr(self.feat_u), self.n_feat, self.move_mask,
                                     ptr(self.amax), ptr(self.disp), ptr(self.counters), self.ws_ptr,
