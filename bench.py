@@ -51,6 +51,19 @@ BUILD_B_PER_PARTICLE, BUILD_B_PER_CELL = 112, 12
 UPDATE_B, PROJECT_B, PROJECT_SURF_B, FORCE_B = 52, 48, 8, 32
 
 
+def valu_issue(kernel_hash, force_ms, pairs):
+    """VALU lane-operations per second of the force kernel: the counted VALU
+    instructions per launch (SQ_INSTS_VALU of the committed counter summary) x
+    64 lanes / the live launch time, against the non-packed issue peak."""
+    insts = profile_value(kernel_hash, "valu_insts_per_launch")
+    if insts is None:
+        return None
+    rate = insts * 64 / (force_ms / 1e3)
+    return {"valu_insts_per_launch": insts, "lane_ops_per_s": rate, "single_issue_peak": VALU_LANE_OPS_PEAK,
+            "frac": rate / VALU_LANE_OPS_PEAK, "lane_slots_per_true_pair": insts * 64 / pairs,
+            "note": "instruction issue (dual issue lets it pass 1), not algorithmic flops"}
+
+
 def hbm_phases(wl, ncell, n_moving, phase_ms, ms_step):
     """Achieved GB/s of algorithmic bytes per phase against the 8 TB/s HBM
     peak (phase times from the event-timed breakdown pass), and for the whole
@@ -92,19 +105,29 @@ def source_hash(paths):
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(kernel_hash):
-    """HBM bytes per force launch measured by rocprofv3 counters (the committed
-    summary's `kernel_source_hash:` and `hbm_bytes_per_launch:` lines), or
-    None if absent or taken on a different kernel source."""
+def profile_value(kernel_hash, key):
+    """A per-launch figure of the force kernel measured by rocprofv3 counters
+    (the committed summary's `kernel_source_hash:` line and the `key:` line),
+    or None if absent or taken on a different kernel source."""
     p = os.path.join(ROOT, "profiles", "force_sphere_l5_counters.md")
     if not os.path.exists(p):
         return None
     text = open(p).read()
     h = re.search(r"^kernel_source_hash:\s*(\S+)", text, re.M)
-    b = re.search(r"^hbm_bytes_per_launch:\s*(\d+)", text, re.M)
+    b = re.search(r"^" + key + r":\s*(\d+)", text, re.M)
     if not h or not b or h.group(1) != kernel_hash:
         return None
     return int(b.group(1))
+
+
+def traffic_from_profile(kernel_hash):
+    """HBM bytes per force launch (FETCH_SIZE and WRITE_SIZE, calibrated)."""
+    return profile_value(kernel_hash, "hbm_bytes_per_launch")
+
+
+# Non-packed VALU issue: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz
+# (the build keeps packed FP32 off); dual issue can exceed it.
+VALU_LANE_OPS_PEAK = 256 * 64 * 2.4e9
 
 
 def cpu_baseline(wl, sample=160, seed=0):
@@ -525,7 +548,7 @@ def main():
         "roofline": {"bound": "alu", "kernel": "k_force", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                      "work_per_launch": pairs * FLOPS_PER_PAIR, "avg_launch_ms": force_ms,
-                     "kernel_source_hash": khash},
+                     "kernel_source_hash": khash, "valu_issue": valu_issue(khash, force_ms, pairs)},
         "device_status": status,
         "wall_s": wall,
     }

@@ -320,7 +320,9 @@ namespace {
 
 struct Dev {
   std::vector<void*> p;
+  hipStream_t s = nullptr;   // work that may still use the buffers (an early return) ends first
   ~Dev() {
+    hipStreamSynchronize(s);
     for (void* q : p) hipFree(q);
   }
   template <class T>
@@ -363,6 +365,7 @@ extern "C" fppg_status fppg_features(fppg_ctx* ctx, const double* vert, int32_t 
   out->n_edges = out->n_singular = out->n_lines = out->n_line_vert = out->n_particles = 0;
   hipStream_t s = static_cast<hipStream_t>(stream);
   Dev d;
+  d.s = s;
   const int m = 3 * n_tri;
   double* d_vert = d.alloc<double>(3 * size_t(n_vert));
   int* d_tri = d.alloc<int>(3 * size_t(n_tri));
@@ -397,6 +400,7 @@ extern "C" fppg_status fppg_features(fppg_ctx* ctx, const double* vert, int32_t 
   int nsing = 0;
   if (!scan(d, flag, off, n_vert, s, &nsing)) return fail(ctx, FPPG_E_HIP, "scan failed");
   int* sing = d.alloc<int>(nsing);
+  if (!sing) return fail(ctx, FPPG_E_HIP, "device allocation failed");
   feat::k_write_index<<<feat::nb(n_vert), 256, 0, s>>>(flag, off, n_vert, sing);
   // adjacency
   int* aoff = d.alloc<int>(n_vert + 1);
