@@ -123,12 +123,12 @@ struct PhaseTimer {
   PhaseTimer(fppg_ctx* ctx, int phase, hipStream_t stream) : s(stream) {
     if (ctx && ((ctx->profiling >> phase) & 1u) && ctx->prof[phase].used < kProfSlots) {
       p = &ctx->prof[phase];
-      hipEventRecord(p->start[p->used], s);
+      (void)hipEventRecord(p->start[p->used], s);   // a failed record is reported by fppg_profile_read
     }
   }
   ~PhaseTimer() {
     if (p) {
-      hipEventRecord(p->stop[p->used], s);
+      (void)hipEventRecord(p->stop[p->used], s);
       p->used++;
     }
   }

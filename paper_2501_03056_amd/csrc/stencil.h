@@ -66,21 +66,22 @@ __device__ __forceinline__ void for_each_row(const Stencil s, const GeomDev& G, 
   }
 }
 
-// Visit every source index of the stencil, four loads in flight at a time.
+// Visit every source index of the stencil, two loads in flight at a time.
+// The lanes of a wavefront run a row for as long as its longest lane needs;
+// pairs leave at most one step of tail per row (measured faster than groups
+// of four, whose tail of up to three single steps per row costs more than the
+// extra loads in flight gain, and than groups of three or single steps).
 template <int K, class F>
 __device__ __forceinline__ void for_each_source(const Stencil s, const GeomDev& G, const int* __restrict__ cs,
                                                 const float4* __restrict__ pos, F&& f) {
   for_each_row<K>(s, G, cs, [&](int j0, int j1) {
     int j = j0;
-    const int j1m = j1 - 3;
-    for (; j < j1m; j += 4) {
-      const float4 q0 = pos[j], q1 = pos[j + 1], q2 = pos[j + 2], q3 = pos[j + 3];
+    for (; j + 2 <= j1; j += 2) {
+      const float4 q0 = pos[j], q1 = pos[j + 1];
       f(j, q0);
       f(j + 1, q1);
-      f(j + 2, q2);
-      f(j + 3, q3);
     }
-    for (; j < j1; ++j) f(j, pos[j]);
+    if (j < j1) f(j, pos[j]);
   });
 }
 
