@@ -72,9 +72,9 @@ __global__ __launch_bounds__(kBlock) void k_force(const float4* __restrict__ pos
     const uint32_t T = tag < FPPG_TAG_VOLUME ? uint32_t(tag) : 7u;
     const Stencil st = stencil_of(p, G);
     if (ranked)
-      for_each_source<K>(st, G, cs, pos, [&](int, const float4 q) { add_pair<true, COUNT>(p, q, rc2, inv2h, T, ax, ay, az, cnt); });
+      for_each_source<K, true>(st, G, cs, pos, [&](int, const float4 q) { add_pair<true, COUNT>(p, q, rc2, inv2h, T, ax, ay, az, cnt); });
     else
-      for_each_source<K>(st, G, cs, pos, [&](int, const float4 q) { add_pair<false, COUNT>(p, q, rc2, inv2h, T, ax, ay, az, cnt); });
+      for_each_source<K, true>(st, G, cs, pos, [&](int, const float4 q) { add_pair<false, COUNT>(p, q, rc2, inv2h, T, ax, ay, az, cnt); });
     ax *= G.kcoef;
     ay *= G.kcoef;
     az *= G.kcoef;

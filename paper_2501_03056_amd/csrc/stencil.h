@@ -66,15 +66,50 @@ __device__ __forceinline__ void for_each_row(const Stencil s, const GeomDev& G, 
   }
 }
 
+// As for_each_row, with the bounds of the five (2k+1) rows of a dz plane
+// loaded together before the plane's rows are walked, so that their loads
+// overlap (four more registers; used where the occupancy allows it).
+template <int K, class F>
+__device__ __forceinline__ void for_each_row_by_plane(const Stencil s, const GeomDev& G, const int* __restrict__ cs,
+                                                      F&& f) {
+  const float kk = float(K * K);
+#pragma unroll
+  for (int dz = -K; dz <= K; ++dz) {
+    const int z = s.z + dz;
+    if (z < 0 || z >= G.dims[2]) continue;
+    const float gz = cell_gap(dz, s.fz);
+    int j0[2 * K + 1], j1[2 * K + 1];
+#pragma unroll
+    for (int dy = -K; dy <= K; ++dy) {
+      j0[dy + K] = j1[dy + K] = 0;   // an empty range: a row outside the grid or culled
+      const int y = s.y + dy;
+      if (y < 0 || y >= G.dims[1]) continue;
+      const float gy = cell_gap(dy, s.fy);
+      const float r2 = kk - (gy * gy + gz * gz);
+      if (!(r2 > 0.0f)) continue;
+      const float rho = __builtin_amdgcn_sqrtf(r2);
+      const int below = min(K, int(ceilf(rho - s.fx + 1.0f)) - 1);
+      const int above = min(K, int(ceilf(rho + s.fx)) - 1);
+      const int x0 = max(s.x - below, 0), x1 = min(s.x + above, G.dims[0] - 1);
+      const int row = row_key(G, y, z);
+      j0[dy + K] = cs[row + x0];
+      j1[dy + K] = cs[row + x1 + 1];
+    }
+#pragma unroll
+    for (int q = 0; q < 2 * K + 1; ++q) f(j0[q], j1[q]);
+  }
+}
+
 // Visit every source index of the stencil, two loads in flight at a time.
 // The lanes of a wavefront run a row for as long as its longest lane needs;
 // pairs leave at most one step of tail per row (measured faster than groups
 // of four, whose tail of up to three single steps per row costs more than the
 // extra loads in flight gain, and than groups of three or single steps).
-template <int K, class F>
+// PLANES: walk the rows with for_each_row_by_plane (same order, same sums).
+template <int K, bool PLANES = false, class F>
 __device__ __forceinline__ void for_each_source(const Stencil s, const GeomDev& G, const int* __restrict__ cs,
                                                 const float4* __restrict__ pos, F&& f) {
-  for_each_row<K>(s, G, cs, [&](int j0, int j1) {
+  auto row = [&](int j0, int j1) {
     int j = j0;
     for (; j + 2 <= j1; j += 2) {
       const float4 q0 = pos[j], q1 = pos[j + 1];
@@ -82,7 +117,11 @@ __device__ __forceinline__ void for_each_source(const Stencil s, const GeomDev& 
       f(j + 1, q1);
     }
     if (j < j1) f(j, pos[j]);
-  });
+  };
+  if (PLANES)
+    for_each_row_by_plane<K>(s, G, cs, row);
+  else
+    for_each_row<K>(s, G, cs, row);
 }
 
 // As for_each_source, also loading row j of a second float4 field with the
