@@ -115,7 +115,11 @@ typedef struct fppg_geom fppg_geom;
  *
  * proj_radius R: a surface projection is accepted only if the particle is
  * within R of the facet plane (section 3.3.3). The facet search grid uses
- * cells of edge R(1 + 2^-6), so R should be of the order of the support radius.
+ * cells of edge R(1 + 2^-6): R = dx makes them the background grid of the
+ * generation, whose 27 cells around a particle the reprojection searches.
+ * A particle moves at most h/16 per step, so any R of a few h/16 or more
+ * accepts the same projections; a smaller R gives fewer facets per cell and
+ * more cells (memory: 5 bytes per search cell).
  */
 typedef struct {
   float   origin[3];

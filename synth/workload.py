@@ -213,7 +213,10 @@ def _make_geom(mesh, dx, k=2, proj_radius=None):
     h = f32(1.3 * dx)
     lo, hi = mesh.bbox()
     origin, inv, dims = particle_grid(lo, hi, h, k)
-    R = f32(2.0 * h) if proj_radius is None else f32(proj_radius)
+    # R = dx: the facet search cells are the background grid of the
+    # generation (one particle spacing), whose 27 cells the reprojection of
+    # section 3.3.3 searches
+    R = f32(dx) if proj_radius is None else f32(proj_radius)
     return Geometry(mesh=mesh, dx=dx, h=h, k=k, proj_radius=R, origin=origin,
                     inv_cell=inv, dims=dims)
 
