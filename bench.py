@@ -454,8 +454,8 @@ def main():
                     help="copy 1 GiB device to device first (reference kernel for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design "
-              "is described in DESIGN.md and is not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); sharding over GPUs "
+              "(geometries, or key slabs with a halo exchange) is not built", file=sys.stderr)
         sys.exit(2)
     if args.mode == "batch":
         return bench_batch(args)
