@@ -37,20 +37,20 @@ WsLayout ws_layout(const Geom* g, int64_t n) {
   L.accel = o;    o += up256(16 * N);
   L.step_end = o;
   o = 0;
-  const size_t nbl = (N + 255) / 256;
+  const size_t nbl = (N + kBlock - 1) / kBlock;
   L.list_cnt = o;  o += up256(4 * (nbl + 1));
   L.list_offs = o; o += up256(4 * (nbl + 2));
   L.list_bsum = o; o += up256(4 * ((nbl + 1 + 4095) / 4096 + 2));
   L.list_end = o;
   o = 0;
-  const size_t nvb = (N + 255) / 256;   // blocks of the volume pass
+  const size_t nvb = (N + kBlock - 1) / kBlock;   // blocks of the volume pass
   L.proj_count = o; o += up256(4 * nvb);
   L.proj_vrev = o;  o += up256(4 * nvb);
   L.proj_part = o;  o += up256(16 * nvb);   // one per k_project_heavy block (at most one per volume block)
-  L.proj_queue = o; o += up256(4 * (N + 256));   // every entry lies below (launch blocks) * 256
+  L.proj_queue = o; o += up256(4 * (N + kBlock));   // every entry lies below (launch blocks) * kBlock
   L.proj_end = o;
-  // relax_energy: one FP64 partial per block of 256; vec_dot: kDotPartials
-  L.reduce_end = up256(8 * std::max<size_t>((N + 255) / 256 + 1, kDotPartials));
+  // relax_energy: one FP64 partial per block of kBlock; vec_dot: kDotPartials
+  L.reduce_end = up256(8 * std::max<size_t>((N + kBlock - 1) / kBlock + 1, kDotPartials));
   L.total = std::max(std::max(std::max(L.build_end, L.list_end), std::max(L.step_end, L.reduce_end)), L.proj_end);
   return L;
 }
