@@ -112,3 +112,23 @@ def test_calls_with_the_full_count_are_refused_while_compacted():
     r.na = na
     r.step()
     assert r.read_status() == 0
+
+
+@pytest.mark.parametrize("mm", [0, (1 << synth.FEATURE) | (1 << synth.SURFACE)])
+def test_partition_of_no_mover_and_of_two_classes(mm):
+    """No moving class: every particle stays active, in order. Feature and
+    surface classes moving together: the tier reaches ranks 0..2."""
+    r = _relaxer(_gear(TIERS["surface"]))
+    r.build_cells()
+    torch.cuda.synchronize()
+    id0 = r.id.cpu().numpy()
+    rank0 = RANK[r.pos.cpu().numpy()[:, 3].view(np.int32) & 7]
+    na = r.tier(mm)
+    if mm == 0:
+        assert na == r.n
+        assert np.array_equal(r.id.cpu().numpy(), id0)
+    else:
+        assert na == int(np.sum(rank0 <= 2))
+        assert np.array_equal(r.id.cpu().numpy()[:na], id0[rank0 <= 2])
+    r.step()
+    assert r.read_status() == 0
