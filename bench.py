@@ -199,9 +199,9 @@ def bench_generate(args):
 
 def bench_batch(args):
     """64 independent solids (boxes and cylinders, 5k-500k particles each) in
-    one launch per kernel; stencil half-width and launch mode (eager or HIP
-    graph replay) autotuned; value = the chosen configuration, the other mode
-    reported beside it."""
+    one launch per kernel; stencil half-width, launch mode (eager or HIP
+    graph replay) and the force kernel's launch shape autotuned; value = the
+    chosen configuration, the other mode reported beside it."""
     import torch
     import synth
     from paper_2501_03056_amd import Relaxer
@@ -213,6 +213,7 @@ def bench_batch(args):
     tune = autotune(wl, cache=os.path.join(os.environ.get("TMPDIR", "/tmp"), "fppg_autotune.json"))
     print(f"[bench] autotune: {tune}", file=sys.stderr, flush=True)
     r = Relaxer(regrid(wl, tune["k"]), device=0)
+    r.ctx.set_launch(tune["force_block"], tune["xcd_remap"])
     for _ in range(args.warmup):
         r.step(keep_accel=False)
     r.profile(True)

@@ -169,6 +169,17 @@ fppg_status fppg_read_status(fppg_ctx* ctx, void* stream, uint32_t* flags);
 fppg_status fppg_profile(fppg_ctx* ctx, uint32_t phases);
 fppg_status fppg_profile_read(fppg_ctx* ctx, double* ms /*[FPPG_NPHASES]*/, int64_t* launches /*[FPPG_NPHASES]*/);
 
+/*
+ * Launch shape of the force kernel of fppg_relax_step, chosen by the
+ * autotuner: force_block threads per block (128, 256 or 512) and whether the
+ * blocks of each of the 8 XCDs take one contiguous range of receivers
+ * (xcd_remap 1) or blocks are dealt out round-robin (0). No result depends on
+ * the choice (per-receiver sums; amax is a maximum). Defaults 256 and 1.
+ * Applies to later calls on the context (and to graphs captured after it).
+ * Errors: FPPG_E_ARG for other values.
+ */
+fppg_status fppg_set_launch(fppg_ctx* ctx, int32_t force_block, int32_t xcd_remap);
+
 /* ---- geometry ----------------------------------------------------------------------------- */
 
 /*

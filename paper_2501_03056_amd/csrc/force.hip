@@ -40,13 +40,16 @@ __device__ __forceinline__ void add_pair(const float4 p, const float4 q, float r
   if (COUNT) cnt += src ? 1.0f : 0.0f;
 }
 
-template <int K, bool COUNT>
-__global__ __launch_bounds__(kBlock) void k_force(const float4* __restrict__ pos, int n,
-                                                  const int* __restrict__ cs, const GeomDev* __restrict__ geoms,
-                                                  int n_geom, uint32_t move_mask, float4* __restrict__ accel,
-                                                  unsigned* __restrict__ amax_bits, uint32_t* status,
-                                                  const int* __restrict__ list, int n_list) {
-  const int i = listed(xcd_chunk(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x, n, list, n_list);
+// B: threads per block; remap: blocks of each XCD take one contiguous range of
+// receivers (xcd_chunk). Neither changes a result (per-lane sums, max-reduced amax).
+template <int K, bool COUNT, int B>
+__global__ __launch_bounds__(B) void k_force(const float4* __restrict__ pos, int n,
+                                             const int* __restrict__ cs, const GeomDev* __restrict__ geoms,
+                                             int n_geom, uint32_t move_mask, float4* __restrict__ accel,
+                                             unsigned* __restrict__ amax_bits, uint32_t* status,
+                                             const int* __restrict__ list, int n_list, bool remap) {
+  const int blk = remap ? xcd_chunk(blockIdx.x, gridDim.x) : int(blockIdx.x);
+  const int i = listed(blk * B + threadIdx.x, n, list, n_list);
   float anorm = 0.0f;
   int g = 0;
   bool mov = false;
@@ -88,8 +91,8 @@ __global__ __launch_bounds__(kBlock) void k_force(const float4* __restrict__ pos
   }
   if (i < n) accel[i] = make_float4(ax, ay, az, cnt);
   // per-geometry max of |a|: wave max, block max, one atomic per block and geometry
-  __shared__ float s_max[kBlock / 64];
-  __shared__ int s_geo[kBlock / 64];
+  __shared__ float s_max[B / 64];
+  __shared__ int s_geo[B / 64];
   const int g0 = __shfl(g, 0);
   const bool mixed = __ballot(anorm > 0.0f && g != g0) != 0;
   if (mixed && anorm > 0.0f) atomicMax(&amax_bits[g], __float_as_uint(anorm));   // wave spans geometries
@@ -102,10 +105,10 @@ __global__ __launch_bounds__(kBlock) void k_force(const float4* __restrict__ pos
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int w = 0; w < kBlock / 64; ++w) {
+    for (int w = 0; w < B / 64; ++w) {
       float mm = s_max[w];
       if (!(mm > 0.0f)) continue;
-      for (int w2 = w + 1; w2 < kBlock / 64; ++w2)
+      for (int w2 = w + 1; w2 < B / 64; ++w2)
         if (s_geo[w2] == s_geo[w]) {
           mm = fmaxf(mm, s_max[w2]);
           s_max[w2] = 0.0f;
@@ -169,6 +172,34 @@ __global__ __launch_bounds__(kBlock) void k_update(const float4* __restrict__ po
 
 static inline int grid_for(int64_t n) { return int((n + kBlock - 1) / kBlock); }
 
+template <int K, bool COUNT, int B>
+static void launch_force_b(int nr, bool remap, hipStream_t s, const float4* p4, int n, const int* cs,
+                           const GeomDev* g, int n_geom, uint32_t mm, float4* acc, unsigned* ab, uint32_t* st,
+                           const int* list) {
+  k_force<K, COUNT, B><<<(nr + B - 1) / B, B, 0, s>>>(p4, n, cs, g, n_geom, mm, acc, ab, st, list, nr, remap);
+}
+
+template <int K, bool COUNT>
+static void launch_force_k(int block, int nr, bool remap, hipStream_t s, const float4* p4, int n, const int* cs,
+                           const GeomDev* g, int n_geom, uint32_t mm, float4* acc, unsigned* ab, uint32_t* st,
+                           const int* list) {
+  if (block == 128) launch_force_b<K, COUNT, 128>(nr, remap, s, p4, n, cs, g, n_geom, mm, acc, ab, st, list);
+  else if (block == 512) launch_force_b<K, COUNT, 512>(nr, remap, s, p4, n, cs, g, n_geom, mm, acc, ab, st, list);
+  else launch_force_b<K, COUNT, 256>(nr, remap, s, p4, n, cs, g, n_geom, mm, acc, ab, st, list);
+}
+
+static void launch_force(int k, bool count, int block, bool remap, int nr, hipStream_t s, const float4* p4, int n,
+                         const int* cs, const GeomDev* g, int n_geom, uint32_t mm, float4* acc, unsigned* ab,
+                         uint32_t* st, const int* list) {
+  if (k == 1) {
+    if (count) launch_force_k<1, true>(block, nr, remap, s, p4, n, cs, g, n_geom, mm, acc, ab, st, list);
+    else launch_force_k<1, false>(block, nr, remap, s, p4, n, cs, g, n_geom, mm, acc, ab, st, list);
+  } else {
+    if (count) launch_force_k<2, true>(block, nr, remap, s, p4, n, cs, g, n_geom, mm, acc, ab, st, list);
+    else launch_force_k<2, false>(block, nr, remap, s, p4, n, cs, g, n_geom, mm, acc, ab, st, list);
+  }
+}
+
 static fppg_status check_common(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, const float* pos,
                                 const int32_t* cs) {
   if (!ctx || !geom) return fail(ctx, FPPG_E_ARG, "null ctx/geom");
@@ -210,13 +241,8 @@ extern "C" fppg_status fppg_relax_step(fppg_ctx* ctx, const fppg_geom* geom, int
     unsigned* ab = reinterpret_cast<unsigned*>(amax);
     {
     PhaseTimer timer(ctx, 1, s);
-    if (geom->k == 1) {
-      if (count) k_force<1, true><<<grid_for(nr), kBlock, 0, s>>>(p4, ni, cell_start, geom->d_geom, geom->n_geom, move_mask, acc, ab, ctx->d_status, list, nr);
-      else k_force<1, false><<<grid_for(nr), kBlock, 0, s>>>(p4, ni, cell_start, geom->d_geom, geom->n_geom, move_mask, acc, ab, ctx->d_status, list, nr);
-    } else {
-      if (count) k_force<2, true><<<grid_for(nr), kBlock, 0, s>>>(p4, ni, cell_start, geom->d_geom, geom->n_geom, move_mask, acc, ab, ctx->d_status, list, nr);
-      else k_force<2, false><<<grid_for(nr), kBlock, 0, s>>>(p4, ni, cell_start, geom->d_geom, geom->n_geom, move_mask, acc, ab, ctx->d_status, list, nr);
-    }
+    launch_force(geom->k, count, ctx->force_block, ctx->xcd_remap, nr, s, p4, ni, cell_start, geom->d_geom,
+                 geom->n_geom, move_mask, acc, ab, ctx->d_status, list);
     }
     PhaseTimer timer(ctx, 2, s);
     k_update<<<grid_for(nr), kBlock, 0, s>>>(p4, acc, owner, feat_seg, ni, n_feat, int(geom->n_tri), int(geom->n_seg),
@@ -224,5 +250,15 @@ extern "C" fppg_status fppg_relax_step(fppg_ctx* ctx, const fppg_geom* geom, int
                                              reinterpret_cast<float4*>(disp), ctx->d_status, list, nr);
   }
   FPPG_HIP(ctx, hipGetLastError());
+  return FPPG_OK;
+}
+
+extern "C" fppg_status fppg_set_launch(fppg_ctx* ctx, int32_t force_block, int32_t xcd_remap) {
+  if (!ctx) return FPPG_E_ARG;
+  if (force_block != 128 && force_block != 256 && force_block != 512)
+    return fail(ctx, FPPG_E_ARG, "force_block must be 128, 256 or 512");
+  if (xcd_remap != 0 && xcd_remap != 1) return fail(ctx, FPPG_E_ARG, "xcd_remap must be 0 or 1");
+  ctx->force_block = force_block;
+  ctx->xcd_remap = xcd_remap != 0;
   return FPPG_OK;
 }

@@ -98,6 +98,8 @@ struct fppg_ctx {
   uint32_t* d_status = nullptr;     // device status word
   uint32_t profiling = 0;   // bit p: time phase p
   fppg::PhaseProf prof[FPPG_NPHASES];
+  int force_block = 256;    // launch shape of the force kernel (fppg_set_launch)
+  bool xcd_remap = true;
 };
 
 struct fppg_geom : fppg::Geom {};

@@ -80,6 +80,10 @@ class Context:
         self.handle = h
         self.device = device
 
+    def set_launch(self, force_block: int = 256, xcd_remap: bool = True):
+        """Launch shape of the force kernel (fppg_set_launch)."""
+        check(self.lib.fppg_set_launch(self.handle, int(force_block), int(bool(xcd_remap))), self.handle)
+
     def close(self):
         if self.handle:
             self.lib.fppg_destroy(self.handle)

@@ -10,9 +10,12 @@ launch latency (decisive for small workloads whose kernels last
 microseconds) but, measured on this runtime, adds time per node for large
 ones (and on the runtime measured here, for small ones too: graph replay of
 the 17.6k-particle cube costs 0.107 ms per iteration against 0.095 ms eager).
-`autotune` times real iterations for each (k, mode) and caches the
-winner in a JSON file keyed by device, particle-count bucket and geometry
-count. The neighbour sets do not depend on k (bit-exact either way); the
+`autotune` times real iterations for each (k, mode), then the launch
+shape of the force kernel for the winner (threads per block 128 / 256 / 512,
+blocks of each XCD on one contiguous range of receivers or dealt out
+round-robin), and caches the choice in a JSON file keyed by device,
+particle-count bucket and geometry count. No result depends on the launch
+shape. The neighbour sets do not depend on k (bit-exact either way); the
 particle order and hence the summation order do, so forces for different k
 agree to rounding (well inside the 1e-5 bar), and for a fixed k every run is
 bitwise reproducible; graph replays are bitwise equal to eager iterations.
@@ -85,9 +88,14 @@ def _time_graph(r, steps):
     return ms
 
 
+LAUNCH_SHAPES = ((256, True), (128, True), (512, True), (256, False), (128, False), (512, False))
+
+
 def autotune(wl, candidates=(1, 2), modes=("eager", "graph"), steps: int = 20, warmup: int = 4,
-             cache: str | None = DEFAULT_CACHE, device: int = 0) -> dict:
-    """Time `steps` iterations per (k, mode); return {"k", "mode", "ms_per_step"}."""
+             cache: str | None = DEFAULT_CACHE, device: int = 0, shapes=LAUNCH_SHAPES) -> dict:
+    """Time `steps` iterations per (k, mode), then per launch shape for the
+    best of them; return {"k", "mode", "force_block", "xcd_remap",
+    "ms_per_step", "launch_ms_per_step"}."""
     from .relax import Relaxer
     key = _key(wl)
     table = {}
@@ -96,7 +104,7 @@ def autotune(wl, candidates=(1, 2), modes=("eager", "graph"), steps: int = 20, w
             table = json.load(open(cache))
         except (OSError, ValueError):
             table = {}
-    if key in table and "mode" in table[key]:
+    if key in table and "force_block" in table[key]:
         return table[key]
     times = {}
     for k in candidates:
@@ -108,7 +116,18 @@ def autotune(wl, candidates=(1, 2), modes=("eager", "graph"), steps: int = 20, w
         del r
     best = min(times, key=times.get)
     k, mode = best.split("_")
-    res = {"k": int(k[1:]), "mode": mode, "ms_per_step": times}
+    shape_ms = {}
+    r = Relaxer(regrid(wl, int(k[1:])), device=device)
+    for _ in range(warmup):
+        r.step(keep_accel=False)
+    for block, remap in shapes:
+        r.ctx.set_launch(block, remap)
+        shape_ms[f"b{block}_{'xcd' if remap else 'rr'}"] = \
+            _time_eager(r, steps) if mode == "eager" else _time_graph(r, steps)
+    del r
+    shape = min(shape_ms, key=shape_ms.get)
+    res = {"k": int(k[1:]), "mode": mode, "force_block": int(shape.split("_")[0][1:]),
+           "xcd_remap": shape.endswith("xcd"), "ms_per_step": times, "launch_ms_per_step": shape_ms}
     if cache:
         table[key] = res
         try:

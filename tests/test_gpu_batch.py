@@ -110,6 +110,9 @@ def test_autotune_picks_a_measured_configuration_and_results_do_not_depend_on_it
     assert res["k"] in (1, 2) and res["mode"] in ("eager", "graph")
     assert set(res["ms_per_step"]) == {"k1_eager", "k1_graph", "k2_eager", "k2_graph"}
     assert min(res["ms_per_step"].values()) == res["ms_per_step"][f"k{res['k']}_{res['mode']}"]
+    assert len(res["launch_ms_per_step"]) == 6 and res["force_block"] in (128, 256, 512)
+    shape = f"b{res['force_block']}_{'xcd' if res['xcd_remap'] else 'rr'}"
+    assert min(res["launch_ms_per_step"].values()) == res["launch_ms_per_step"][shape]
     states = []
     for k in (1, 2):
         r = Relaxer(regrid(wl, k), device=0)
@@ -118,3 +121,30 @@ def test_autotune_picks_a_measured_configuration_and_results_do_not_depend_on_it
     # one step from the same state: neighbour sets agree bit for bit, sums only in order
     dx = min(g.dx for g in wl.geoms)
     assert np.abs(states[0] - states[1]).max() <= 1e-5 * max(1.0, np.abs(states[0]).max()) + 1e-6 * dx
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_force_launch_shape_does_not_change_results(k):
+    """Every launch shape of the force kernel (threads per block, XCD remap)
+    gives the same iterations bit for bit, on a batch with a receiver list too."""
+    from paper_2501_03056_amd import Relaxer
+    from paper_2501_03056_amd.tune import LAUNCH_SHAPES, regrid
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    wl = regrid(W.batch_workload(n_geom=5, n_min=1.5e3, n_max=8e3, seed=4100), k)
+    ref = None
+    for block, remap in LAUNCH_SHAPES:
+        r = Relaxer(wl, device=0)
+        r.ctx.set_launch(block, remap)
+        for _ in range(3):
+            r.step()
+        st = r.host_state()
+        if ref is None:
+            ref = st
+        else:
+            for a, b in zip(ref, st):
+                assert np.array_equal(a, b), (block, remap)
+        assert r.read_status() == 0
+    from paper_2501_03056_amd import _lib
+    with pytest.raises(_lib.FppgError):
+        r.ctx.set_launch(64, True)
