@@ -233,12 +233,16 @@ __global__ void k_line_particles(const double* __restrict__ vert, const int* __r
     return;
   }
   int o = poff[l];
+  // the targets grow with k, so the segment walk resumes where the previous
+  // particle's stopped (acc is the same left-to-right sum of the lengths)
+  double acc = 0.0;
+  int i = 0;
   for (int k = k0; k < n; ++k) {
     const double target = k * (L / n);
-    double acc = 0.0;
-    int i = 0;
-    while (i < nseg - 1 && acc + seg_len(vert, lv(line_vert, b, nv, cl, i), lv(line_vert, b, nv, cl, i + 1)) < target) {
-      acc += seg_len(vert, lv(line_vert, b, nv, cl, i), lv(line_vert, b, nv, cl, i + 1));
+    while (i < nseg - 1) {
+      const double len = seg_len(vert, lv(line_vert, b, nv, cl, i), lv(line_vert, b, nv, cl, i + 1));
+      if (!(acc + len < target)) break;
+      acc += len;
       ++i;
     }
     const int pa = lv(line_vert, b, nv, cl, i), pb = lv(line_vert, b, nv, cl, i + 1);
@@ -285,28 +289,31 @@ __global__ void k_set_last(int* __restrict__ a, int idx, int v) { a[idx] = v; }
 
 constexpr int kScanThreads = 1024;
 
-// exclusive scan of in [n] into out [n], the total into *total; one block
-// walking the array in chunks of kScanThreads (Hillis-Steele within a chunk)
+// exclusive scan of in [n] into out [n], the total into *total; one block:
+// each thread sums a contiguous run, the run totals are scanned once
+// (Hillis-Steele), then each thread writes its run's prefix sums
 __global__ __launch_bounds__(kScanThreads) void k_scan1(const int* __restrict__ in, int* __restrict__ out, int n,
                                                         int* __restrict__ total) {
   __shared__ int sh[kScanThreads];
-  int carry = 0;
-  for (int base = 0; base < n; base += kScanThreads) {
-    const int i = base + threadIdx.x;
-    const int v = i < n ? in[i] : 0;
-    sh[threadIdx.x] = v;
+  const int per = (n + kScanThreads - 1) / kScanThreads;
+  const int i0 = min(n, int(threadIdx.x) * per), i1 = min(n, i0 + per);
+  int v = 0;
+  for (int i = i0; i < i1; ++i) v += in[i];
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 1; o < kScanThreads; o <<= 1) {
+    const int add = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
     __syncthreads();
-    for (int o = 1; o < kScanThreads; o <<= 1) {
-      const int add = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
-      __syncthreads();
-      sh[threadIdx.x] += add;
-      __syncthreads();
-    }
-    if (i < n) out[i] = carry + sh[threadIdx.x] - v;
-    carry += sh[kScanThreads - 1];
+    sh[threadIdx.x] += add;
     __syncthreads();
   }
-  if (threadIdx.x == 0) *total = carry;
+  int run = sh[threadIdx.x] - v;
+  for (int i = i0; i < i1; ++i) {
+    const int x = in[i];
+    out[i] = run;
+    run += x;
+  }
+  if (threadIdx.x == kScanThreads - 1) *total = sh[kScanThreads - 1];
 }
 
 inline int nb(int64_t n) { return int(std::max<int64_t>(1, (n + 255) / 256)); }   // kernels check bounds

@@ -250,26 +250,40 @@ __device__ __forceinline__ bool emits(const uint8_t* __restrict__ cls, const int
   return c == kInternal || (c == kSurface && best[cell] != 0x7fffffff);
 }
 
-// per block of 256 cells: the number of particles it emits
+// per block of 256 cells: the number of particles it emits, and of them
+// surface particles
 __global__ __launch_bounds__(256) void k_emit_count(const uint8_t* __restrict__ cls, const int* __restrict__ best,
-                                                     int64_t ncell, int* __restrict__ bcount) {
+                                                     int64_t ncell, int* __restrict__ bcount,
+                                                     int* __restrict__ scount) {
   const int64_t cell = int64_t(blockIdx.x) * 256 + threadIdx.x;
   const bool e = cell < ncell && emits(cls, best, cell);
-  __shared__ int w[4];
-  const uint64_t m = __ballot(e);
-  if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = __popcll(m);
+  const bool sf = e && cls[cell] == kSurface;
+  __shared__ int w[4], ws[4];
+  const uint64_t m = __ballot(e), ms = __ballot(sf);
+  if ((threadIdx.x & 63) == 0) {
+    w[threadIdx.x >> 6] = __popcll(m);
+    ws[threadIdx.x >> 6] = __popcll(ms);
+  }
   __syncthreads();
-  if (threadIdx.x == 0) bcount[blockIdx.x] = w[0] + w[1] + w[2] + w[3];
+  if (threadIdx.x == 0) {
+    bcount[blockIdx.x] = w[0] + w[1] + w[2] + w[3];
+    scount[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+  }
 }
 
-// exclusive scan of the block counts, one block (sequential over chunks)
-__global__ __launch_bounds__(kScanBlock) void k_emit_scan(const int* __restrict__ bcount, int nb,
-                                                           long long* __restrict__ boff) {
+// exclusive scan of the block counts (one block walking them in chunks,
+// Hillis-Steele within a chunk) and the total of the surface counts
+__global__ __launch_bounds__(kScanBlock) void k_emit_scan(const int* __restrict__ bcount,
+                                                           const int* __restrict__ scount, int nb,
+                                                           long long* __restrict__ boff,
+                                                           unsigned long long* __restrict__ nsurf) {
   __shared__ long long s[kScanBlock];
   long long carry = 0;
+  unsigned long long sv = 0;
   for (int base = 0; base < nb; base += kScanBlock) {
     const int b = base + threadIdx.x;
     const long long v = b < nb ? bcount[b] : 0;
+    sv += b < nb ? unsigned(scount[b]) : 0u;
     s[threadIdx.x] = v;
     __syncthreads();
     for (int o = 1; o < kScanBlock; o <<= 1) {
@@ -282,14 +296,24 @@ __global__ __launch_bounds__(kScanBlock) void k_emit_scan(const int* __restrict_
     carry += s[kScanBlock - 1];
     __syncthreads();
   }
-  if (threadIdx.x == 0) boff[nb] = carry;
+  // the surface total: block reduction of the per-thread sums
+  __shared__ unsigned long long ss[kScanBlock];
+  ss[threadIdx.x] = sv;
+  __syncthreads();
+  for (int o = kScanBlock / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) ss[threadIdx.x] += ss[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    boff[nb] = carry;
+    nsurf[0] = ss[0];
+  }
 }
 
 __global__ __launch_bounds__(256) void k_emit_write(const uint8_t* __restrict__ cls, const int* __restrict__ best,
                                                      const double* __restrict__ vert, const int* __restrict__ tri,
                                                      Grid g, int64_t ncell, const long long* __restrict__ boff,
-                                                     int64_t cap, float4* __restrict__ pos, int* __restrict__ owner,
-                                                     unsigned long long* __restrict__ nsurf) {
+                                                     int64_t cap, float4* __restrict__ pos, int* __restrict__ owner) {
   const int64_t cell = int64_t(blockIdx.x) * 256 + threadIdx.x;
   const bool e = cell < ncell && emits(cls, best, cell);
   __shared__ int w[4];
@@ -313,7 +337,6 @@ __global__ __launch_bounds__(256) void k_emit_write(const uint8_t* __restrict__ 
     project_inside(load_tri(vert, tri, t), c, d, p);
     pos[slot] = make_float4(float(p[0]), float(p[1]), float(p[2]), __int_as_float(FPPG_TAG_SURFACE));
     owner[slot] = t;
-    atomicAdd(nsurf, 1ull);
   }
 }
 
@@ -392,6 +415,7 @@ extern "C" fppg_status fppg_generate(fppg_ctx* ctx, const double* vert, int32_t 
   int* d_best = nullptr;
   unsigned* d_tog = nullptr;
   int* d_bcount = nullptr;
+  int* d_scount = nullptr;
   long long* d_boff = nullptr;
   unsigned long long* d_nsurf = nullptr;
   fppg_status st = FPPG_OK;
@@ -403,6 +427,7 @@ extern "C" fppg_status fppg_generate(fppg_ctx* ctx, const double* vert, int32_t 
     hipFree(d_best);
     hipFree(d_tog);
     hipFree(d_bcount);
+    hipFree(d_scount);
     hipFree(d_boff);
     hipFree(d_nsurf);
   };
@@ -421,6 +446,7 @@ extern "C" fppg_status fppg_generate(fppg_ctx* ctx, const double* vert, int32_t 
   GEN_HIP(hipMalloc(&d_best, sizeof(int) * ncell));
   GEN_HIP(hipMalloc(&d_tog, sizeof(unsigned) * ((ncell + 31) / 32)));
   GEN_HIP(hipMalloc(&d_bcount, sizeof(int) * nb));
+  GEN_HIP(hipMalloc(&d_scount, sizeof(int) * nb));
   GEN_HIP(hipMalloc(&d_boff, sizeof(long long) * (nb + 1)));
   GEN_HIP(hipMalloc(&d_nsurf, sizeof(unsigned long long)));
   GEN_HIP(hipMemcpyAsync(d_vert, vert, sizeof(double) * 3 * n_vert, hipMemcpyHostToDevice, s));
@@ -430,15 +456,14 @@ extern "C" fppg_status fppg_generate(fppg_ctx* ctx, const double* vert, int32_t 
   gen::k_fill_i32b<<<gen::blocks(ncell, 256), 256, 0, s>>>(d_best, ncell, 0x7fffffff);
   gen::k_fill_i32b<<<gen::blocks((ncell + 31) / 32, 256), 256, 0, s>>>(reinterpret_cast<int*>(d_tog),
                                                                          (ncell + 31) / 32, 0);
-  gen::k_fill_u64<<<1, 64, 0, s>>>(d_nsurf, 1, 0ull);
   gen::k_surface_cells<<<n_tri, gen::kWave, 0, s>>>(d_vert, d_tri, g, cell_class, d_key, 0, d_best);
   gen::k_surface_cells<<<n_tri, gen::kWave, 0, s>>>(d_vert, d_tri, g, cell_class, d_key, 1, d_best);
   gen::k_ray_crossings<<<n_tri, gen::kWave, 0, s>>>(d_vert, d_tri, g, d_tog);
   gen::k_column_parity<<<gen::blocks(int64_t(dims[0]) * dims[1], 256), 256, 0, s>>>(g, d_tog, cell_class);
-  gen::k_emit_count<<<nb, 256, 0, s>>>(cell_class, d_best, ncell, d_bcount);
-  gen::k_emit_scan<<<1, gen::kScanBlock, 0, s>>>(d_bcount, nb, d_boff);
+  gen::k_emit_count<<<nb, 256, 0, s>>>(cell_class, d_best, ncell, d_bcount, d_scount);
+  gen::k_emit_scan<<<1, gen::kScanBlock, 0, s>>>(d_bcount, d_scount, nb, d_boff, d_nsurf);
   gen::k_emit_write<<<nb, 256, 0, s>>>(cell_class, d_best, d_vert, d_tri, g, ncell, d_boff, cap,
-                                       reinterpret_cast<float4*>(pos), owner, d_nsurf);
+                                       reinterpret_cast<float4*>(pos), owner);
   GEN_HIP(hipGetLastError());
   long long total = 0;
   unsigned long long nsurf = 0;
@@ -450,7 +475,6 @@ extern "C" fppg_status fppg_generate(fppg_ctx* ctx, const double* vert, int32_t 
   counts[0] = total - int64_t(nsurf);
   counts[1] = int64_t(nsurf);
   if (total > cap) {
-    // nsurf counts only the surface particles written below cap
     counts[0] = -1;
     counts[1] = total;
     return fail(ctx, FPPG_E_CAPACITY, "more particles than cap (counts[1] holds the total)");
