@@ -197,6 +197,37 @@ def bench_generate(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_features(args):
+    """Feature extraction (fppg_features: feature edges, singular vertices,
+    lines and loops, feature-line particles at spacing --gear-dx) on the
+    24-tooth gear mesh; value = facets processed per second (the call's wall
+    time with its size query, device temporaries and copies; best of 3)."""
+    import math
+    import torch
+    from synth import meshes as M
+    from paper_2501_03056_amd import Context
+    from paper_2501_03056_amd.front import features
+    dx = args.gear_dx
+    mesh = M.gear()
+    ctx = Context(0)
+    times = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f = features(mesh.vert, mesh.tri, math.cos(math.radians(30.0)), dx, ctx=ctx)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    t = min(times)
+    out = {"metric": "facets processed/s (feature extraction)", "value": len(mesh.tri) / t, "unit": "facets/s",
+           "n_gpus": 1, "steps": 3, "warmup": 0, "ms_per_step": 1e3 * t, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"gear24_features_dx{dx:g}", "facets": int(len(mesh.tri)), "threshold_deg": 30.0},
+           "features": {"edges": int(len(f["edges"])), "singular": int(len(f["singular"])),
+                        "lines": int(len(f["line_closed"])), "particles": int(len(f["pos"]))},
+           "seconds_all": times}
+    print(json.dumps(out), flush=True)
+
+
 def bench_batch(args):
     """64 independent solids (boxes and cylinders, 5k-500k particles each) in
     one launch per kernel; stencil half-width, launch mode (eager or HIP
@@ -427,7 +458,7 @@ def bench_newton(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--mode", default="step", choices=["step", "batch", "newton", "gear", "generate"])
+    ap.add_argument("--mode", default="step", choices=["step", "batch", "newton", "gear", "generate", "features"])
     ap.add_argument("--gear-dx", type=float, default=0.004)
     ap.add_argument("--tier-iters", type=int, default=100)
     ap.add_argument("--gear-source", default="synth", choices=["synth", "pipeline"],
@@ -462,6 +493,8 @@ def main():
         return bench_batch(args)
     if args.mode == "generate":
         return bench_generate(args)
+    if args.mode == "features":
+        return bench_features(args)
     if args.mode == "newton":
         return bench_newton(args)
     if args.mode == "gear":
