@@ -316,6 +316,62 @@ __global__ __launch_bounds__(kScanThreads) void k_scan1(const int* __restrict__ 
   if (threadIdx.x == kScanThreads - 1) *total = sh[kScanThreads - 1];
 }
 
+// Multi-block exclusive scan for long arrays: tiles of kTile = 256 threads x 8
+// consecutive items; the tile sums, their one-block scan (k_scan1), then each
+// tile rescanned with its offset.
+constexpr int kTileThreads = 256, kTileItems = 8, kTile = kTileThreads * kTileItems;
+
+// exclusive scan of one value per thread over a 256-thread block; returns the prefix, *total the sum
+__device__ __forceinline__ int tile_block_scan(int v, int* total) {
+  __shared__ int wsum[kTileThreads / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int inc = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(inc, o);
+    if (lane >= o) inc += t;
+  }
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  int before = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < kTileThreads / 64; ++k) {
+    before += k < w ? wsum[k] : 0;
+    tot += wsum[k];
+  }
+  *total = tot;
+  return before + inc - v;
+}
+
+__global__ __launch_bounds__(kTileThreads) void k_tile_sums(const int* __restrict__ in, int n, int* __restrict__ sums) {
+  const int i0 = blockIdx.x * kTile + threadIdx.x * kTileItems;
+  int v = 0;
+#pragma unroll
+  for (int q = 0; q < kTileItems; ++q) v += i0 + q < n ? in[i0 + q] : 0;
+  int total;
+  tile_block_scan(v, &total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kTileThreads) void k_tile_apply(const int* __restrict__ in, int n,
+                                                             const int* __restrict__ offs, int* __restrict__ out) {
+  const int i0 = blockIdx.x * kTile + threadIdx.x * kTileItems;
+  int x[kTileItems];
+  int v = 0;
+#pragma unroll
+  for (int q = 0; q < kTileItems; ++q) {
+    x[q] = i0 + q < n ? in[i0 + q] : 0;
+    v += x[q];
+  }
+  int total;
+  int run = offs[blockIdx.x] + tile_block_scan(v, &total);
+#pragma unroll
+  for (int q = 0; q < kTileItems; ++q) {
+    if (i0 + q < n) out[i0 + q] = run;
+    run += x[q];
+  }
+}
+
 inline int nb(int64_t n) { return int(std::max<int64_t>(1, (n + 255) / 256)); }   // kernels check bounds
 
 }  // namespace feat
@@ -350,7 +406,17 @@ bool scan(Dev& d, const int* in, int* out, int n, hipStream_t s, int* total) {
   }
   int* tot = d.alloc<int>(1);
   if (!tot) return false;
-  feat::k_scan1<<<1, feat::kScanThreads, 0, s>>>(in, out, n, tot);
+  if (n <= feat::kTile) {
+    feat::k_scan1<<<1, feat::kScanThreads, 0, s>>>(in, out, n, tot);
+  } else {
+    const int nt = (n + feat::kTile - 1) / feat::kTile;
+    int* sums = d.alloc<int>(nt);
+    int* offs = d.alloc<int>(nt);
+    if (!sums || !offs) return false;
+    feat::k_tile_sums<<<nt, feat::kTileThreads, 0, s>>>(in, n, sums);
+    feat::k_scan1<<<1, feat::kScanThreads, 0, s>>>(sums, offs, nt, tot);
+    feat::k_tile_apply<<<nt, feat::kTileThreads, 0, s>>>(in, n, offs, out);
+  }
   if (hipGetLastError() != hipSuccess) return false;
   if (hipMemcpyAsync(total, tot, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) return false;
   return hipStreamSynchronize(s) == hipSuccess;
