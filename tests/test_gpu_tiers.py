@@ -132,3 +132,23 @@ def test_partition_of_no_mover_and_of_two_classes(mm):
         assert np.array_equal(r.id.cpu().numpy()[:na], id0[rank0 <= 2])
     r.step()
     assert r.read_status() == 0
+
+
+def test_graph_replay_of_a_compacted_tier_with_a_launch_shape_equals_eager():
+    """A HIP graph captured after the tier partition and a launch-shape change
+    replays bit for bit the eager iterations of the same compacted tier."""
+    mm = TIERS["surface"]
+    wl = _gear(mm)
+    eager, g = _relaxer(wl), _relaxer(wl)
+    for r in (eager, g):
+        r.step()
+        r.tier(mm)
+        r.ctx.set_launch(128, False)
+    for _ in range(4):
+        eager.step(keep_accel=False)
+    g.capture(iters=2)
+    g.replay(2)
+    for a, b in zip(g.host_state(), eager.host_state()):
+        assert np.array_equal(a, b)
+    assert g.read_status() == 0
+    g.release_graph()
