@@ -199,6 +199,7 @@ class Relaxer:
         behind the others and left out of every call until the next tier;
         returns the number of active particles."""
         lib, c = self.ctx.lib, self.ctx.handle
+        self.release_graph()   # a captured graph holds the previous tier's mask and count
         self.move_mask = int(move_mask)
         mm = self.move_mask if compact else (1 << 3)   # volume bit: every particle active
         na = ctypes.c_int64()
@@ -391,6 +392,8 @@ class Relaxer:
 
     def replay(self, repeats: int = 1):
         """Run repeats * graph_iters iterations from the captured graph (state ends in the same buffers)."""
+        if not getattr(self, "graph", None):
+            raise RuntimeError("no captured graph (capture() first; tier() releases it)")
         cur = torch.cuda.current_stream(self.dev)
         if self.pos.data_ptr() != self._graph_a:
             # an odd number of eager rebuilds since the capture left the state in
