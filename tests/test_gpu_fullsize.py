@@ -84,3 +84,46 @@ def test_full_size_one_step_properties(sphere):
     n /= np.linalg.norm(n, axis=1, keepdims=True)
     assert np.abs(np.einsum("ij,ij->i", pos[s].astype(np.float64) - A, n)).max() <= 1e-6
     assert r.read_status() == 0
+
+
+def test_full_size_hundred_iterations_keep_the_invariants(sphere):
+    """100 iterations at the benchmark's size: surface particles stay on their
+    owner facet (within the binary32 rounding of a point on a tilted plane),
+    every particle stays inside the mesh (no particle past a facet plane of
+    the sphere's hull, and within the facet sag of the unit sphere), no
+    position is lost, and the projected force residual falls."""
+    wl = sphere
+    r = _relaxer(wl)
+    r.step(count_pairs=False)
+    a0 = r.by_id(r.accel)[:, :3].astype(np.float64)
+    mov = wl.tag == synth.VOLUME
+    R0 = np.sqrt(np.mean(np.sum(a0[mov] ** 2, 1)))
+    for _ in range(99):
+        r.step(keep_accel=False)
+    r.build_cells()
+    r.relax_step()
+    a1 = r.by_id(r.accel)[:, :3].astype(np.float64)
+    R1 = np.sqrt(np.mean(np.sum(a1[mov] ** 2, 1)))
+    assert R1 < 0.5 * R0, (R0, R1)
+    pos, owner, _, _ = r.host_state()
+    assert np.all(np.isfinite(pos))
+    mesh = wl.geoms[0].mesh
+    s = np.nonzero(wl.tag == synth.SURFACE)[0]
+    A, B, C = (mesh.vert[mesh.tri[owner[s], q]] for q in range(3))
+    n = np.cross(B - A, C - A)
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    assert np.abs(np.einsum("ij,ij->i", pos[s].astype(np.float64) - A, n)).max() <= 1e-6
+    # the icosphere is convex: inside means below every facet plane; its
+    # facets lie within the sag (< 3e-4) of the unit sphere
+    rad = np.linalg.norm(pos.astype(np.float64), axis=1)
+    assert rad.max() <= 1.0 + 1e-6
+    v = np.nonzero(mov)[0]
+    An, Bn, Cn = (mesh.vert[mesh.tri[:, q]] for q in range(3))
+    fn = np.cross(Bn - An, Cn - An)
+    fn /= np.linalg.norm(fn, axis=1, keepdims=True)
+    off = np.einsum("ij,ij->i", fn, An)
+    far = v[rad[v] > 1.0 - 1e-3]   # only particles within the sag band can reach a plane
+    for c in range(0, len(far), 1000):
+        sd = pos[far[c:c + 1000]].astype(np.float64) @ fn.T - off
+        assert sd.max() < 0.0
+    assert r.read_status() == 0
