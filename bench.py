@@ -390,8 +390,10 @@ def _first_at_or_below(curve, target):
 
 
 def bench_newton(args):
-    """Newton-Krylov vs the plain loop on the volume tier (volume particles
-    move, surface, feature and singular particles are fixed sources), from the
+    """Newton-Krylov vs the plain loop on one tier (--newton-tier: by default
+    the volume tier, where volume particles move and surface, feature and
+    singular particles are fixed sources; on the gear also the surface or the
+    feature tier, each after the tier partition), from the
     same initial state: the plain loop runs --plain-iters iterations (the
     paper's fixed iteration count) and its final force residual R_plain is the
     target; Newton-MINRES runs until R <= R_plain. value = plain seconds /
@@ -402,10 +404,13 @@ def bench_newton(args):
     import synth
     from paper_2501_03056_amd import Relaxer
     from paper_2501_03056_amd.newton import newton_relax, plain_relax
-    mm = 1 << synth.VOLUME
+    tier = args.newton_tier
+    mm = 1 << {"volume": synth.VOLUME, "surface": synth.SURFACE, "feature": synth.FEATURE}[tier]
+    if tier != "volume" and args.newton_workload != "gear":
+        raise SystemExit("--newton-tier surface/feature needs the gear (the sphere has no feature lines)")
     if args.newton_workload == "gear":
         dx = args.newton_dx or 0.004
-        wl, wname = synth.gear_workload(dx=dx, seed=3, k=args.k, move_mask=mm), f"gear24_dx{dx:g}_volume_tier"
+        wl, wname = synth.gear_workload(dx=dx, seed=3, k=args.k, move_mask=mm), f"gear24_dx{dx:g}_{tier}_tier"
     else:
         dx = args.newton_dx or 0.01
         wl, wname = synth.sphere_workload(level=5, dx=dx, seed=2, k=args.k, move_mask=mm), \
@@ -413,6 +418,7 @@ def bench_newton(args):
     n_moving = wl.n_moving()
     print(f"[bench] newton {wname}: {wl.n} particles, {n_moving} moving", file=sys.stderr, flush=True)
     rp = Relaxer(wl, device=0)
+    rp.tier(mm)   # a feature or surface tier leaves out the particles it does not reach
     plain = plain_relax(rp, n_moving, iters=args.plain_iters, record_every=1)
     target, t_plain = plain[-1][1], plain[-1][0]
     t_first = _first_at_or_below(plain, target)
@@ -422,6 +428,7 @@ def bench_newton(args):
           file=sys.stderr, flush=True)
     del rp
     rn = Relaxer(wl, device=0)
+    rn.tier(mm)
     torch.cuda.synchronize()
     kw = dict(forcing="ew", krylov_tol=1e-4, krylov_max=args.krylov_max, checkpoint_every=10)
     log = newton_relax(rn, n_moving, target=target, max_iter=500, time_limit=20 * t_plain + 20, **kw)
@@ -473,6 +480,7 @@ def main():
     ap.add_argument("--newton-dx", type=float, default=None, help="default 0.004 (gear), 0.01 (sphere)")
     ap.add_argument("--newton-workload", default="gear", choices=["gear", "sphere"])
     ap.add_argument("--krylov-max", type=int, default=3)
+    ap.add_argument("--newton-tier", default="volume", choices=["volume", "surface", "feature"])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
