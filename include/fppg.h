@@ -147,6 +147,11 @@ void        fppg_destroy(fppg_ctx* ctx);
 const char* fppg_status_str(fppg_status s);
 const char* fppg_last_error(const fppg_ctx* ctx);   /* never NULL */
 
+/* Hash of the sources and compiler flags the library was built from (32 hex
+ * digits, a static string; "unknown" if the build did not define it). A
+ * loader compares it with the sources it expects, to refuse a stale build. */
+const char* fppg_source_hash(void);
+
 /* Synchronise `stream`, return the device status bits (FPPG_S_*) and clear them. */
 fppg_status fppg_read_status(fppg_ctx* ctx, void* stream, uint32_t* flags);
 
@@ -292,7 +297,9 @@ fppg_status fppg_relax_step(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
 
 /*
  * Apply the displacement and project back onto the geometry (section 3.3.3).
- * No workspace: one kernel, one lane per particle.
+ * One lane per particle in two kernels: a streaming pass applies the volume
+ * rule and queues the surface and feature particles in the workspace, a
+ * second pass projects the queued particles.
  *  surface: y = x + dr (FP64); among the facets registered in the 27 search
  *           cells around y, the plane foot p = y - d n with all barycentric
  *           coordinates >= 0 and |d| <= R and the smallest |d| (ties: lowest
@@ -562,6 +569,17 @@ fppg_status fppg_project_record(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
  * fppg_fixed_to_double converts. Global vertex ids number the vertices of
  * geometry g after those of geometries 0..g-1 (fppg_geom_desc.n_vert).
  */
+
+/*
+ * Rest density rho0 of the uniformity loss: the kernel sum of Eq. 7's form,
+ * W(0) + sum over the non-zero points k dx of the infinite cubic lattice
+ * (k in Z^3) of W(|k| dx), with W the Wendland C2 kernel of Eq. 16 (alpha =
+ * 21/(16 pi h^3), support 2h): the density every particle of an exactly
+ * uniform lattice of spacing dx has. FP64, host call (no device, no context).
+ * out: one double (host). Errors: FPPG_E_ARG for a null out, dx or h not
+ * finite and > 0, or 2h/dx > 1024.
+ */
+fppg_status fppg_lattice_density(double dx, double h, double* out);
 
 /*
  * Uniformity loss of the positions (binary32 input, FP64 arithmetic):

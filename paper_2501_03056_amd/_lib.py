@@ -82,6 +82,8 @@ _SIGS = {
     "fppg_relax_hvp_projected": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, c_int32, c_uint32, _P, c_float, _P,
                                            _P]),
     "fppg_fixed_to_double": (c_int32, [_P, c_int64, _P, _P, _P]),
+    "fppg_lattice_density": (c_int32, [c_double, c_double, POINTER(c_double)]),
+    "fppg_source_hash": (c_char_p, []),
 }
 
 _lib = None
@@ -107,14 +109,24 @@ class FppgError(RuntimeError):
 
 
 def lib():
-    """Load libfppg.so (building it first if it is not there)."""
+    """Load libfppg.so. A library that is missing, or whose embedded source
+    hash differs from the sources in the tree (a stale build), is rebuilt
+    first; if that fails the import fails loudly."""
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(LIB_PATH):
-        from .build import build
-        build()
+    from . import build as B
+    want = B.source_hash()
+    if B.built_hash(LIB_PATH) != want:
+        B.build()
+        if B.built_hash(LIB_PATH) != want:
+            raise RuntimeError(f"{LIB_PATH}: the rebuilt library does not carry the source hash {want}")
     L = ctypes.CDLL(LIB_PATH)
+    got = L.fppg_source_hash
+    got.restype = c_char_p
+    got.argtypes = []
+    if got().decode() != want:
+        raise RuntimeError(f"{LIB_PATH} reports source hash {got().decode()}, the sources have {want}")
     for name, (res, args) in _SIGS.items():
         fn = getattr(L, name)        # AttributeError = library does not export it: fail loudly
         fn.restype = res

@@ -17,6 +17,8 @@
 // on the order of the atomics (deterministic), and converted to double at the end.
 #include "stencil.h"
 
+#include <cmath>
+
 namespace fppg {
 
 constexpr double kFixScale = 1099511627776.0;   // 2^40
@@ -300,6 +302,28 @@ static inline int grid_for(int64_t n) { return int((n + kBlock - 1) / kBlock); }
 }  // namespace fppg
 
 using namespace fppg;
+
+extern "C" fppg_status fppg_lattice_density(double dx, double h, double* out) {
+  if (!out || !(dx > 0.0) || !(h > 0.0) || !std::isfinite(dx) || !std::isfinite(h)) return FPPG_E_ARG;
+  const double m_real = std::ceil(2.0 * h / dx);
+  if (m_real > 1024.0) return FPPG_E_ARG;   // (2m+1)^3 lattice points: keep the sum bounded
+  const int m = int(m_real) + 1;
+  const double alpha = 21.0 / (16.0 * M_PI * h * h * h);
+  // Wendland C2 (Eq. 16-17): alpha (1 - q/2)^4 (2q + 1) for q = r/h < 2, summed
+  // over the points (i, j, k) dx of the cubic lattice, the origin included
+  double sum = 0.0;
+  for (int i = -m; i <= m; ++i)
+    for (int j = -m; j <= m; ++j)
+      for (int k = -m; k <= m; ++k) {
+        const double x = i * dx, y = j * dx, z = k * dx;
+        const double q = std::sqrt(x * x + y * y + z * z) / h;
+        if (q >= 2.0) continue;
+        const double t = 1.0 - 0.5 * q;
+        sum += alpha * (t * t) * (t * t) * (2.0 * q + 1.0);
+      }
+  *out = sum;
+  return FPPG_OK;
+}
 
 extern "C" fppg_status fppg_uniformity_loss(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, const float* pos,
                                             const int32_t* cell_start, uint32_t move_mask, double rho0, double* out,

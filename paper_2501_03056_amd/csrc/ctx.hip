@@ -377,6 +377,14 @@ const char* fppg_status_str(fppg_status s) {
 
 const char* fppg_last_error(const fppg_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
+#ifndef FPPG_SOURCE_HASH
+#define FPPG_SOURCE_HASH "unknown"
+#endif
+// The marker makes the hash readable from the file without loading it.
+__attribute__((used)) static const char kSourceHashRecord[] = "FPPG_SOURCE_HASH:" FPPG_SOURCE_HASH;
+
+const char* fppg_source_hash(void) { return kSourceHashRecord + 17; }
+
 fppg_status fppg_create(int32_t device, fppg_ctx** out) {
   if (!out) return FPPG_E_ARG;
   *out = nullptr;

@@ -26,22 +26,19 @@ All arithmetic runs in the library's kernels; this module marshals.
 """
 from __future__ import annotations
 
-import numpy as np
 import torch
 
 from ._lib import check, ptr
 
 
 def lattice_density(dx: float, h: float) -> float:
-    """Density of the infinite cubic lattice of spacing dx with the kernel of
-    Eq. 16 (the loss's rest density rho0), summed over the lattice points
-    within the support radius 2h."""
-    alpha = 21.0 / (16.0 * np.pi * h ** 3)
-    m = int(np.ceil(2.0 * h / dx)) + 1
-    i = np.arange(-m, m + 1, dtype=np.float64) * dx
-    r = np.sqrt(i[:, None, None] ** 2 + i[None, :, None] ** 2 + i[None, None, :] ** 2).ravel() / h
-    t = np.clip(1.0 - 0.5 * r, 0.0, None)
-    return float(np.sum(alpha * t ** 4 * (2.0 * r + 1.0)))
+    """Rest density rho0 of the loss (fppg_lattice_density: the kernel sum of
+    an infinite cubic lattice of spacing dx, computed by the library)."""
+    import ctypes
+    from . import _lib as L
+    out = ctypes.c_double()
+    check(L.lib().fppg_lattice_density(float(dx), float(h), ctypes.byref(out)))
+    return float(out.value)
 
 
 class _Tape:

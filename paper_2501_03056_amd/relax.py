@@ -332,6 +332,9 @@ class Relaxer:
     def restore(self, snap):
         for dst, src in zip((self.pos, self.id, self.owner, self.feat_seg, self.feat_u, self.cell_start), snap):
             dst.copy_(src)
+        if self.use_list:
+            # the receiver list indexes the sorted order: rebuild it for the restored order
+            self.moving_list()
 
     def neighbors(self, cap: int = 160):
         lib, c = self.ctx.lib, self.ctx.handle

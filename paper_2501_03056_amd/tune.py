@@ -31,18 +31,9 @@ import time
 import numpy as np
 import torch
 
+from .pipeline import particle_grid
+
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "fppg_autotune.json")
-
-
-def particle_grid(lo, hi, h: float, k: int):
-    """Grid covering [lo, hi] plus one support radius: (origin, inv_cell, dims)."""
-    rc = float(np.float32(2.0 * h))
-    cell = float(np.float32((rc / k) * (1.0 + 2.0 ** -8)))
-    inv = float(np.float32(1.0 / cell))
-    origin = (np.asarray(lo, np.float64) - rc).astype(np.float32)
-    ext = np.asarray(hi, np.float64) + rc - origin.astype(np.float64)
-    dims = np.ceil(ext * inv).astype(np.int64) + 1
-    return origin, inv, dims
 
 
 def regrid(wl, k: int):

@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -90,3 +91,42 @@ def test_relaxer_refuses_to_run_without_gpu():
     from paper_2501_03056_amd import Relaxer
     with pytest.raises(RuntimeError):
         Relaxer(synth.cube_workload(n=4))
+
+
+def test_loader_refuses_a_stale_build(tmp_path):
+    """The library carries the hash of the sources it was built from; the
+    loader compares it with the tree's sources (a stale build is rebuilt)."""
+    from paper_2501_03056_amd import _lib, build as B
+    L = _lib.lib()
+    want = B.source_hash()
+    assert L.fppg_source_hash().decode() == want
+    assert B.built_hash(_lib.LIB_PATH) == want
+    # a copy whose embedded hash differs is recognised as stale
+    data = open(_lib.LIB_PATH, "rb").read()
+    i = data.find(B.HASH_MARK) + len(B.HASH_MARK)
+    stale = data[:i] + b"0" * 32 + data[i + 32:]
+    p = tmp_path / "libfppg_stale.so"
+    p.write_bytes(stale)
+    assert B.built_hash(str(p)) != want
+    assert B.built_hash(str(tmp_path / "missing.so")) is None
+
+
+def test_rest_density_is_computed_by_the_library():
+    """rho0 of the uniformity loss comes from fppg_lattice_density (the Python
+    package holds no kernel arithmetic); it equals the oracle's lattice sum."""
+    from oracle import metrics
+    from paper_2501_03056_amd import _lib
+    L = _lib.lib()
+    for dx in (0.01, 0.045, 0.12, 1.0 / 24):
+        h = float(np.float32(1.3 * dx))
+        out = ctypes.c_double()
+        assert L.fppg_lattice_density(dx, h, ctypes.byref(out)) == _lib.OK
+        assert out.value == pytest.approx(metrics.lattice_density(dx, h), rel=1e-13)
+    out = ctypes.c_double()
+    assert L.fppg_lattice_density(0.0, 1.0, ctypes.byref(out)) == _lib.E_ARG
+    assert L.fppg_lattice_density(1.0, float("nan"), ctypes.byref(out)) == _lib.E_ARG
+    assert L.fppg_lattice_density(1.0, 1.0, None) == _lib.E_ARG
+    for f in _py_sources("paper_2501_03056_amd"):
+        if f.endswith(".py"):
+            src = open(f).read()
+            assert "np.pi" not in src and "math.pi" not in src and "21.0 /" not in src, f

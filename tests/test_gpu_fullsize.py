@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 import synth
+from facet_bound import assert_on_facets
 from oracle import cells as ocells
 from oracle import force as oforce
 
@@ -79,10 +80,7 @@ def test_full_size_one_step_properties(sphere):
     assert np.all(dev <= 1.01 * ulp + 1e-5 * np.abs(tau * a64).max(1, keepdims=True)), float(np.max(dev / ulp))
     mesh = wl.geoms[0].mesh
     s = np.nonzero(wl.tag == synth.SURFACE)[0]
-    A, B, C = (mesh.vert[mesh.tri[owner[s], q]] for q in range(3))
-    n = np.cross(B - A, C - A)
-    n /= np.linalg.norm(n, axis=1, keepdims=True)
-    assert np.abs(np.einsum("ij,ij->i", pos[s].astype(np.float64) - A, n)).max() <= 1e-6
+    assert_on_facets(pos[s], mesh, owner[s], wl.geoms[0].dx)
     assert r.read_status() == 0
 
 
@@ -109,10 +107,7 @@ def test_full_size_hundred_iterations_keep_the_invariants(sphere):
     assert np.all(np.isfinite(pos))
     mesh = wl.geoms[0].mesh
     s = np.nonzero(wl.tag == synth.SURFACE)[0]
-    A, B, C = (mesh.vert[mesh.tri[owner[s], q]] for q in range(3))
-    n = np.cross(B - A, C - A)
-    n /= np.linalg.norm(n, axis=1, keepdims=True)
-    assert np.abs(np.einsum("ij,ij->i", pos[s].astype(np.float64) - A, n)).max() <= 1e-6
+    assert_on_facets(pos[s], mesh, owner[s], wl.geoms[0].dx)
     # the icosphere is convex: inside means below every facet plane; its
     # facets lie within the sag (< 3e-4) of the unit sphere
     rad = np.linalg.norm(pos.astype(np.float64), axis=1)

@@ -25,13 +25,6 @@ def _rho0(wl):
     return metrics.lattice_density(wl.geoms[0].dx, float(wl.geoms[0].h))
 
 
-def test_rest_density_matches_oracle():
-    from paper_2501_03056_amd.grad import lattice_density
-    for dx in (0.01, 0.045, 0.12):
-        h = float(np.float32(1.3 * dx))
-        assert lattice_density(dx, h) == pytest.approx(metrics.lattice_density(dx, h), rel=1e-13)
-
-
 def test_uniformity_loss_and_gradient_match_oracle():
     from paper_2501_03056_amd.grad import uniformity_loss
     wl = synth.tetra_workload(dx=0.06, move_mask=SURF_VOL)

@@ -481,3 +481,100 @@ def test_lattice_density_equals_interior_kernel_sum():
     assert np.allclose(rho[interior], rho0, rtol=1e-13)
     # a perfect lattice has (numerically) zero uniformity loss at interior particles
     assert np.max(np.abs(rho[interior] / rho0 - 1)) < 1e-13
+
+
+def _cube_facet_on(mesh, axis, value):
+    """Index of a facet of the axis-aligned cube whose three vertices lie on the plane x[axis] = value."""
+    v = mesh.vert[mesh.tri]
+    return int(np.nonzero(np.all(v[:, :, axis] == value, axis=1))[0][0])
+
+
+def _cube_segment_along(mesh, axis):
+    """Index of a feature segment of the cube whose end points differ only along `axis`."""
+    p = mesh.lines.seg_p
+    d = p[:, 1] - p[:, 0]
+    other = [a for a in range(3) if a != axis]
+    return int(np.nonzero((np.abs(d[:, axis]) > 0) & np.all(d[:, other] == 0, axis=1))[0][0])
+
+
+def test_residual_closed_form_on_cube_face_edge_and_volume():
+    """R = sqrt(mean over moving particles of |P a|^2) with P = I - n n^T on a
+    cube face (n = +z: the z part of a drops), P = t t^T on a straight edge
+    (t = x: only the x part stays), I for a volume particle; a fixed particle is
+    not in the mean. The expected value is written from the cube's geometry."""
+    mesh = M.cube()
+    dx = 1.0 / 8
+    top = _cube_facet_on(mesh, 2, 1.0)
+    seg = _cube_segment_along(mesh, 0)
+    p0 = mesh.lines.seg_p[seg, 0]
+    pos = np.array([[0.4, 0.6, 1.0], p0 + [0.3 * np.sign(mesh.lines.seg_p[seg, 1, 0] - p0[0]), 0, 0],
+                    [0.5, 0.5, 0.5], [0.25, 0.25, 0.25]])
+    wl = synth.workload.custom_workload(mesh, dx, pos, [2, 1, 3, 4], owner=[top, 0, -1, -1],
+                                        feat_seg=[seg], feat_u=[0.3])
+    a = np.array([[3.0, -4.0, 7.0], [2.0, 5.0, -6.0], [1.0, -2.0, 2.0], [9.0, 9.0, 9.0]])
+    pa = metrics.projected_accel(wl, a, wl.owner, wl.feat_seg)
+    assert np.allclose(pa[0], [3.0, -4.0, 0.0], atol=1e-15)
+    assert np.allclose(pa[1], [2.0, 0.0, 0.0], atol=1e-15)
+    assert np.array_equal(pa[2], a[2])
+    want = math.sqrt((25.0 + 4.0 + 9.0) / 3.0)
+    assert metrics.residual(wl, a, wl.owner, wl.feat_seg) == pytest.approx(want, rel=1e-15)
+    # only the moving classes count: with the surface class fixed the mean runs over two particles
+    wl.move_mask = (1 << 1) | (1 << 3)
+    assert metrics.residual(wl, a, wl.owner, wl.feat_seg) == pytest.approx(math.sqrt((4.0 + 9.0) / 2.0), rel=1e-15)
+
+
+def test_residual_vanishes_on_exact_lattice_interior():
+    """On the exact dyadic lattice with the particles within 2h of the edge of
+    the block fixed, every moving particle has zero force: R = 0 up to rounding
+    of the force sums (1e-14 of the one-sided force scale)."""
+    wl = synth.dyadic_lattice_workload(m=12)
+    h = float(wl.geoms[0].h)
+    x = wl.pos.astype(np.float64)
+    interior = np.all((x - x.min(0) >= 2 * h) & (x.max(0) - x >= 2 * h), 1)
+    wl.tag = np.where(interior, 3, 4).astype(np.int32)
+    a, S, _ = force.accel(wl)
+    R = metrics.residual(wl, a, wl.owner, wl.feat_seg)
+    assert interior.sum() > 50
+    assert R <= 1e-14 * float(np.max(S[interior]))
+    # and the same lattice with one interior particle displaced has R > 0
+    k = int(np.nonzero(interior)[0][len(np.nonzero(interior)[0]) // 2])
+    wl.pos = wl.pos.copy()
+    wl.pos[k, 0] += np.float32(wl.geoms[0].dx / 8)
+    a, S, _ = force.accel(wl)
+    assert metrics.residual(wl, a, wl.owner, wl.feat_seg) > 1e-3 * float(np.max(S[interior]))
+
+
+def test_uniformity_loss_closed_form_with_displaced_particles():
+    """Nearest-neighbour support (2h = 1.2 dx): in an exact cubic lattice every
+    particle has 6 neighbours at dx, so rho0 = W(0) + 6 W(dx). A particle moved
+    by d along x has two neighbours at dx -+ d and four at sqrt(dx^2 + d^2);
+    one moved along y the same. Two such movers far apart, every other particle
+    fixed: L = mean over the two of (rho/rho0 - 1)^2."""
+    dx = 2.0 ** -5
+    m = 12
+    c = (np.arange(m) + 0.5) * dx
+    pos = np.stack(np.meshgrid(c, c, c, indexing="ij"), -1).reshape(-1, 3)
+    idx = lambda i, j, k: (i * m + j) * m + k
+    a, b = idx(3, 3, 3), idx(8, 8, 8)
+    d1, d2 = dx / 8, dx / 4
+    pos[a, 0] += d1
+    pos[b, 1] -= d2
+    tag = np.full(len(pos), 4, np.int32)
+    tag[[a, b]] = 3
+    wl = synth.workload.custom_workload(M.cube((0, 0, 0), (m * dx,) * 3), dx, pos.astype(np.float32), tag,
+                                        move_mask=1 << 3)
+    h = 0.6 * dx
+    wl.geoms[0].h = h
+    W = lambda r: kernel.W(np.asarray(r, np.float64), h)
+    rho0 = W(0.0) + 6 * W(dx)
+    assert metrics.lattice_density(dx, h) == pytest.approx(rho0, rel=1e-15)
+    rho = lambda d: W(0.0) + W(dx - d) + W(dx + d) + 4 * W(math.hypot(dx, d))
+    want = 0.5 * ((rho(d1) / rho0 - 1) ** 2 + (rho(d2) / rho0 - 1) ** 2)
+    assert want > 0
+    assert metrics.uniformity_loss(wl) == pytest.approx(want, rel=1e-12)
+    # the undisplaced lattice has zero loss
+    wl0 = synth.workload.custom_workload(M.cube((0, 0, 0), (m * dx,) * 3), dx,
+                                         np.stack(np.meshgrid(c, c, c, indexing="ij"), -1).reshape(-1, 3), tag,
+                                         move_mask=1 << 3)
+    wl0.geoms[0].h = h
+    assert metrics.uniformity_loss(wl0) <= 1e-28
