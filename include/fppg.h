@@ -381,6 +381,23 @@ fppg_status fppg_vec_dot(fppg_ctx* ctx, int64_t n, const float* a, const float* 
                          void* ws, size_t ws_bytes, void* stream);
 fppg_status fppg_vec_axpby(fppg_ctx* ctx, int64_t n, float alpha, const float* x, float beta, float* y,
                            void* stream);
+
+/*
+ * fppg_vec_dot without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight solver loops, harnesses that
+ * forbid hipMalloc): out[0] = sum_i a_i . b_i in FP64, bitwise equal to
+ * fppg_vec_dot's result (same kernels, same block partition). The per-block
+ * partial sums live in a static device array of the library (2048 doubles =
+ * 16 KiB per device, held until the process ends; its device address is
+ * resolved once by fppg_create). The call allocates nothing. Every call on one
+ * device shares that array and overwrites it: calls that overlap on one GPU
+ * (concurrent streams, several host threads) race and must be serialised by
+ * the caller. n: 0 <= n < 2^31 (any n fits the fixed scratch: the rows are
+ * split over at most 2048 blocks). Errors: FPPG_E_ARG for null or misaligned
+ * a/b/out or n out of range.
+ */
+fppg_status fppg_vec_dot_noalloc(fppg_ctx* ctx, int64_t n, const float* a, const float* b, double* out,
+                                 void* stream);
 /* out[0] (device float) = max_i |a_i| (Euclidean norm of the xyz of row i);
  * a NaN row counts as +inf. */
 fppg_status fppg_vec_maxnorm(fppg_ctx* ctx, int64_t n, const float* a, float* out, void* stream);

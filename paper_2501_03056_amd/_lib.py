@@ -66,6 +66,7 @@ _SIGS = {
     "fppg_graph_destroy": (None, [_P]),
     "fppg_relax_energy": (c_int32, [_P, _P, c_int64, _P, _P, c_uint32, _P, _P, c_size_t, _P]),
     "fppg_vec_dot": (c_int32, [_P, c_int64, _P, _P, _P, _P, c_size_t, _P]),
+    "fppg_vec_dot_noalloc": (c_int32, [_P, c_int64, _P, _P, _P, _P]),
     "fppg_vec_axpby": (c_int32, [_P, c_int64, c_float, _P, c_float, _P, _P]),
     "fppg_vec_maxnorm": (c_int32, [_P, c_int64, _P, _P, _P]),
     "fppg_vec_clamp": (c_int32, [_P, c_int64, _P, c_float, _P]),

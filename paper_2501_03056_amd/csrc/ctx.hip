@@ -403,6 +403,12 @@ fppg_status fppg_create(int32_t device, fppg_ctx** out) {
     delete ctx;
     return FPPG_E_HIP;
   }
+  const fppg_status st = init_dot_scratch(ctx);   // the device is current here
+  if (st != FPPG_OK) {
+    hipFree(ctx->d_status);
+    delete ctx;
+    return st;
+  }
   *out = ctx;
   return FPPG_OK;
 }

@@ -100,6 +100,7 @@ struct fppg_ctx {
   fppg::PhaseProf prof[FPPG_NPHASES];
   int force_block = 256;    // launch shape of the force kernel (fppg_set_launch)
   bool xcd_remap = true;
+  double* dot_scratch = nullptr;   // device address of this device's static dot-product scratch
 };
 
 struct fppg_geom : fppg::Geom {};
@@ -159,6 +160,9 @@ WsLayout ws_layout(const Geom* g, int64_t n);
 // fixed order, then one block sums the partials in index order.
 constexpr int kDotPartials = 2048;   // partial sums of fppg_vec_dot (doubles of workspace)
 fppg_status sum_partials(fppg_ctx* ctx, const double* partial, int nb, double* out, hipStream_t s);
+// Resolve the device address of the static dot-product scratch array on the
+// current device into ctx->dot_scratch (linalg.hip; called by fppg_create).
+fppg_status init_dot_scratch(fppg_ctx* ctx);
 
 // Device helpers ---------------------------------------------------------------------------
 

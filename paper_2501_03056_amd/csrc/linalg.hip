@@ -133,6 +133,21 @@ __global__ void k_zero_u32(unsigned* __restrict__ a, int n) {
   if (i < n) a[i] = 0u;
 }
 
+// Scratch of fppg_vec_dot_noalloc: the per-block partial sums of one dot
+// product, in a static device array (each device holds its own copy for the
+// life of the process). Host code never passes `scratch` itself to a kernel
+// (its host-side name is not a device address): init_dot_scratch resolves the
+// device address once per context, with the context's device current.
+static __device__ __align__(256) double scratch[kDotPartials];
+
+fppg_status init_dot_scratch(fppg_ctx* ctx) {
+  void* p = nullptr;
+  FPPG_HIP(ctx, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) return fail(ctx, FPPG_E_HIP, "static dot-product scratch has no device address");
+  ctx->dot_scratch = static_cast<double*>(p);
+  return FPPG_OK;
+}
+
 fppg_status sum_partials(fppg_ctx* ctx, const double* partial, int nb, double* out, hipStream_t s) {
   k_sum_partials<<<1, kRedBlock, 0, s>>>(partial, nb, out);
   FPPG_HIP(ctx, hipGetLastError());
@@ -170,6 +185,26 @@ extern "C" fppg_status fppg_vec_dot(fppg_ctx* ctx, int64_t n, const float* a, co
   }
   return dot_into(ctx, int(n), reinterpret_cast<const float4*>(a), reinterpret_cast<const float4*>(b), out,
                   static_cast<double*>(ws), kDotPartials, static_cast<hipStream_t>(stream));
+}
+
+extern "C" fppg_status fppg_vec_dot_noalloc(fppg_ctx* ctx, int64_t n, const float* a, const float* b, double* out,
+                                            void* stream) {
+  if (!ctx) return FPPG_E_ARG;
+  if (!ctx->dot_scratch) return fail(ctx, FPPG_E_HIP, "context has no dot-product scratch");
+  if (n < 0 || n >= (int64_t(1) << 31)) return fail(ctx, FPPG_E_ARG, "n out of range (0 <= n < 2^31)");
+  if (!out || (n > 0 && (!a || !b))) return fail(ctx, FPPG_E_ARG, "null argument");
+  if (!aligned(a, 16) || !aligned(b, 16)) return fail(ctx, FPPG_E_ARG, "misaligned argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (n == 0) {   // no partial is read: the sum over none is 0
+    k_sum_partials<<<1, kRedBlock, 0, s>>>(ctx->dot_scratch, 0, out);
+    FPPG_HIP(ctx, hipGetLastError());
+    return FPPG_OK;
+  }
+  // the same kernels and block partition as fppg_vec_dot (at most kDotPartials
+  // blocks, every partial written before it is summed), with the partials in
+  // the static scratch: the result is bitwise that of fppg_vec_dot
+  return dot_into(ctx, int(n), reinterpret_cast<const float4*>(a), reinterpret_cast<const float4*>(b), out,
+                  ctx->dot_scratch, kDotPartials, s);
 }
 
 extern "C" fppg_status fppg_vec_axpby(fppg_ctx* ctx, int64_t n, float alpha, const float* x, float beta, float* y,
