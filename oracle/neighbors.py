@@ -24,15 +24,21 @@ def pair_d2(pi: np.ndarray, pj: np.ndarray) -> np.ndarray:
     """binary32 squared distance of broadcastable position arrays [..., 3]."""
     pi = np.asarray(pi, np.float32)
     pj = np.asarray(pj, np.float32)
+    acc = pair_d2_xyz(pi[..., 0], pi[..., 1], pi[..., 2], pj[..., 0], pj[..., 1], pj[..., 2])
+    return acc if acc.shape == np.broadcast_shapes(pi.shape, pj.shape)[:-1] else acc.reshape(())
+
+
+def pair_d2_xyz(xi, yi, zi, xj, yj, zj) -> np.ndarray:
+    """The same binary32 squared distance from coordinate arrays (broadcastable)."""
     acc = None
-    for k in range(3):                      # ((ddx^2 + ddy^2) + ddz^2), each op rounded
-        d = np.atleast_1d(np.subtract(pi[..., k], pj[..., k], dtype=np.float32))
+    for a, b in ((xi, xj), (yi, yj), (zi, zj)):   # ((ddx^2 + ddy^2) + ddz^2), each op rounded
+        d = np.atleast_1d(np.subtract(a, b, dtype=np.float32))
         np.multiply(d, d, out=d)
         if acc is None:
             acc = d
         else:
             np.add(acc, d, out=acc)
-    return acc if acc.shape == np.broadcast_shapes(pi.shape, pj.shape)[:-1] else acc.reshape(())
+    return acc
 
 
 def neighbor_lists(wl, receivers=None, pos32=None, chunk=256):

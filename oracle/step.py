@@ -125,38 +125,50 @@ def project_surface(wl, y, g, lam_margin=1e-7, d_margin=1e-9):
     over all its facets. Returns (accepted, foot point, global facet, margin)."""
     geo = wl.geoms[g]
     A, B, C, n = facet_frames(geo.mesh.vert, geo.mesh.tri)
-    R = float(geo.proj_radius)
+    ids = np.arange(len(A))
     ok = np.zeros(len(y), bool)
     foot = y.copy()
     own = np.full(len(y), -1, np.int64)
     margin = np.zeros(len(y), bool)
     for s in range(0, len(y), 256):
-        q = y[s:s + 256, None, :]
-        d = np.sum((q - A[None]) * n[None], -1)                 # [P, T] signed plane distance
-        p = q - d[..., None] * n[None]
-        la, lb, lc = barycentric(p, A[None], B[None], C[None])
-        lmin = np.minimum(np.minimum(la, lb), lc)
-        ad = np.abs(d)
-        acc = (lmin >= 0) & (ad <= R)
-        key = np.where(acc, ad, np.inf)
-        best = np.argmin(key, axis=1)                            # first index among equal minima
-        has = np.isfinite(key[np.arange(len(best)), best])
-        ok[s:s + 256] = has
-        rows = np.nonzero(has)[0]
-        foot[s + rows] = p[rows, best[rows]]
-        own[s + rows] = best[rows] + geo.tri_begin
-        # decisions that rounding could flip: the winner's foot point on its
-        # facet boundary or its |d| at the radius, another facet on the edge of
-        # acceptance that would beat the winner, or two accepted facets within
-        # d_margin of each other
-        bd = np.where(has, key[np.arange(len(best)), best], np.inf)
-        edge = (np.abs(lmin) <= lam_margin) & (ad <= np.minimum(bd, R)[:, None] + d_margin)
-        near_R = has & (np.abs(bd - R) <= d_margin)
-        srt = np.sort(key, axis=1)
+        o, f, w, m = project_onto_facets(y[s:s + 256], A, B, C, n, ids, float(geo.proj_radius),
+                                         lam_margin, d_margin)
+        ok[s:s + 256], foot[s:s + 256], margin[s:s + 256] = o, f, m
+        own[s:s + 256] = np.where(o, w + geo.tri_begin, -1)
+    return ok, foot, own, margin
+
+
+def project_onto_facets(y, A, B, C, n, ids, R, lam_margin=1e-7, d_margin=1e-9):
+    """The section 3.3.3 decision for points y [P, 3] over the facets (A, B, C,
+    n) whose local indices `ids` are ascending: plane distance d, foot point
+    p = y - d n, accepted iff every barycentric coordinate of p is >= 0 and
+    |d| <= R; the accepted facet with the smallest |d| wins, ties to the
+    lowest index. Returns (accepted, foot, winning index from ids, margin)."""
+    q = y[:, None, :]
+    d = np.sum((q - A[None]) * n[None], -1)                     # [P, T] signed plane distance
+    p = q - d[..., None] * n[None]
+    la, lb, lc = barycentric(p, A[None], B[None], C[None])
+    lmin = np.minimum(np.minimum(la, lb), lc)
+    ad = np.abs(d)
+    acc = (lmin >= 0) & (ad <= R)
+    key = np.where(acc, ad, np.inf)
+    best = np.argmin(key, axis=1)                                # first index among equal minima
+    has = np.isfinite(key[np.arange(len(best)), best])
+    foot = y.copy()
+    rows = np.nonzero(has)[0]
+    foot[rows] = p[rows, best[rows]]
+    # decisions that rounding could flip: the winner's foot point on its
+    # facet boundary or its |d| at the radius, another facet on the edge of
+    # acceptance that would beat the winner, or two accepted facets within
+    # d_margin of each other
+    bd = np.where(has, key[np.arange(len(best)), best], np.inf)
+    edge = (np.abs(lmin) <= lam_margin) & (ad <= np.minimum(bd, R)[:, None] + d_margin)
+    near_R = has & (np.abs(bd - R) <= d_margin)
+    srt = np.sort(key, axis=1)
+    with np.errstate(invalid="ignore"):                          # inf - inf where nothing is accepted
         tie = (np.isfinite(srt[:, 1]) & (srt[:, 1] - srt[:, 0] <= d_margin)) if key.shape[1] > 1 \
             else np.zeros(len(best), bool)
-        margin[s:s + 256] = edge.any(1) | near_R | tie
-    return ok, foot, own, margin
+    return has, foot, np.asarray(ids)[best], edge.any(1) | near_R | tie
 
 
 def advance_feature(seg, u, du, segs, margin_tol=1e-9):

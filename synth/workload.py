@@ -23,6 +23,7 @@ performs none of the relaxation method's arithmetic.
 """
 from __future__ import annotations
 
+import copy
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -762,3 +763,73 @@ def gear_workload(dx=0.004, jitter=0.3, seed=3, k=2, move_mask=ALL_MOVING, sampl
     _feature_particles(b, mesh, dx, rng, jitter)
     b.add(mesh.singular, SINGULAR, mesh.singular_vert)
     return _finish(name or f"gear24_dx{dx:g}", [(geom, b)], move_mask, seed, {"dx": dx})
+
+
+def forced_reverts(wl: Workload, seed: int = 0, n_skin: int = 12, surface_every: int = 40) -> Workload:
+    """The same single-geometry workload with particles placed where a step must
+    revert (inputs for revert tests; no method arithmetic):
+      * the first feature particle of every open line moved to 1e-7 of the
+        line's start, where its neighbour along the line pushes it off the end;
+      * every `surface_every`-th surface particle lifted off its facet along
+        the facet normal by 1.5 times the projection radius;
+      * `n_skin` volume particles put 1e-6 under the centroid of random facets,
+        with every other particle within the support radius of that point that
+        is not a deeper volume particle removed, so the volume pushes them out.
+    """
+    assert len(wl.geoms) == 1
+    geo = wl.geoms[0]
+    mesh = geo.mesh
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pos = wl.pos.astype(np.float64).copy()
+    tag = wl.tag.copy()
+    owner = wl.owner.copy()
+    fs, fu = wl.feat_seg.copy(), wl.feat_u.copy()
+    keep = np.ones(len(pos), bool)
+    L = mesh.lines
+    seg_line = np.zeros(L.n_seg, np.int64)
+    for l in range(L.n_line):
+        seg_line[L.line_seg_begin[l]:L.line_seg_begin[l + 1]] = l
+    f = np.nonzero(tag == FEATURE)[0]
+    if len(f):
+        slot = owner[f]
+        seg = fs[slot] - geo.seg_begin
+        line = seg_line[seg]
+        for l in range(L.n_line):
+            if L.line_closed[l]:
+                continue
+            on = np.nonzero(line == l)[0]
+            if len(on) == 0:
+                continue
+            first = on[np.lexsort((fu[slot[on]], seg[on]))[0]]
+            s0 = int(L.line_seg_begin[l])
+            a, b = L.seg_p[s0]
+            u = 1e-7 * float(np.linalg.norm(b - a))
+            fs[slot[first]], fu[slot[first]] = s0 + geo.seg_begin, u
+            pos[f[first]] = a + (u / np.linalg.norm(b - a)) * (b - a)
+    A, B, C = (mesh.vert[mesh.tri[:, q]] for q in range(3))
+    nrm = np.cross(B - A, C - A)
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    s = np.nonzero(tag == SURFACE)[0][::surface_every]
+    pos[s] += 1.5 * float(geo.proj_radius) * nrm[owner[s] - geo.tri_begin]
+    rc = 2.0 * float(geo.h)
+    v = np.nonzero(tag == VOLUME)[0]
+    for t in rng.choice(len(mesh.tri), size=min(n_skin, len(mesh.tri)), replace=False):
+        c = (A[t] + B[t] + C[t]) / 3.0
+        p = c - 1e-6 * nrm[t]
+        d = np.linalg.norm(pos - p, axis=1)
+        depth = (pos - c) @ nrm[t]
+        near = keep & (d < rc)
+        keep &= ~(near & ~((tag == VOLUME) & (depth < -0.3 * geo.dx)))
+        k = v[np.argmin(np.where(keep[v], np.linalg.norm(pos[v] - p, axis=1), np.inf))]
+        pos[k] = p
+        keep[k] = True
+    idx = np.nonzero(keep)[0]
+    out = copy.copy(wl)
+    out.pos = pos[idx].astype(np.float32)
+    out.tag, out.owner, out.gid = tag[idx], owner[idx], wl.gid[idx]
+    out.feat_seg, out.feat_u = fs, fu
+    g2 = copy.copy(geo)
+    g2.part_begin, g2.part_end = 0, len(idx)
+    out.geoms = [g2]
+    out.name = wl.name + "_forced_reverts"
+    return out
