@@ -40,14 +40,15 @@ def _relaxer(wl):
     return Relaxer(wl, device=0)
 
 
-def _compare(wl, r, ref, label):
+def _compare(wl, r, ref, label, max_margin=1e-3):
     """Positions, owners, feature tables and revert counts of the GPU's step
-    against the oracle's; returns (GPU positions, owners, margin count)."""
+    against the oracle's; returns (GPU positions, owners, margin count).
+    max_margin: the largest fraction of the movers that may be margin cases."""
     pos, owner, fs, fu = r.host_state()
     mov = oforce.moving_mask(wl.tag, wl.move_mask)
     ok = ~ref.margin
     n_margin = int(np.sum(ref.margin & mov))
-    assert n_margin <= max(1, 1e-3 * mov.sum()), (label, n_margin, int(mov.sum()))
+    assert n_margin <= max(1, max_margin * mov.sum()), (label, n_margin, int(mov.sum()))
     x = ref.pos32.astype(np.float64)
     dx = wl.geoms[0].dx
     tol = 1e-5 * np.maximum(np.abs(x).max(1), dx)
@@ -174,8 +175,14 @@ def test_cube_hundred_iterations_invariants_and_oracle_every_tenth():
         if it % 10 == 0:
             pos, owner, fs, fu = r.host_state()
             ref = olocal.relax_step(wl, pos32=pos, owner=owner, feat_seg=fs, feat_u=fu)
+            r.counters.zero_()   # revert counts of this step only
             r.step()
-            _compare(wl, r, ref, f"cube iteration {it}")
+            # as the surface particles relax they gather along the cube's edges and
+            # cross the diagonals splitting each face into two coplanar facets: foot
+            # points within 1e-7 (barycentric) of a facet edge are margin cases
+            # (0.03 % after 10 iterations, 0.12 % after 20, 0.23 % after 30 on the
+            # oracle's own trajectory), so the long run allows 0.5 %
+            _compare(wl, r, ref, f"cube iteration {it}", max_margin=5e-3)
             checked += 1
         else:
             r.step()
