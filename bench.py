@@ -1,17 +1,23 @@
 """Benchmark: particle-relaxation iterations per second on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sphere|cube|gear]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
 
 A step is one iteration of the relaxation loop (Algorithm 1 of arXiv
 2501.03056): cell rebuild, forces + time step + displacement, projection.
-Default workload: icosphere of radius 1 (subdivision level 5, 20,480 facets),
-dx = 0.01, h = 1.3 dx: ~4.13 M volume + 125,664 surface particles, all moving,
-synthetic and seeded (the paper's models are not available).
+Default workload: the 24-tooth gear on its full mesh (207,360 facets), dx =
+0.004, h = 1.3 dx, 12.4 M particles (11.8 M volume, 0.54 M surface, 13 k
+feature, 192 singular), synthetic and seeded (the paper's models are not
+available); the timed steps are its volume tier (volume particles move, the
+other classes are fixed sources), the largest single-GPU configuration and the
+one whose state exceeds the MI355X's 256 MB Infinity Cache.
 
 Prints ONE JSON line with the whole-job throughput (particle-updates/s), the
 pair-evaluation rate, the force kernel's roofline figures (timed with HIP
-events on its launch stream, inside the timed region) and the CPU oracle timed
-on a bounded sample of the same workload.
+events on its launch stream, inside the timed region), the feature and surface
+tiers of the same gear, the Newton-Krylov form against the plain loop on the
+volume tier (seconds to the plain loop's residual, against its first arrival
+there), the icosphere workload as a secondary line, and the CPU oracle timed
+on a bounded sample of the same workload on all host cores.
 """
 import argparse
 import hashlib
@@ -51,11 +57,11 @@ BUILD_B_PER_PARTICLE, BUILD_B_PER_CELL = 112, 12
 UPDATE_B, PROJECT_B, PROJECT_SURF_B, FORCE_B = 52, 48, 8, 32
 
 
-def valu_issue(kernel_hash, force_ms, pairs):
+def valu_issue(kernel_hash, force_ms, pairs, profile=None):
     """VALU lane-operations per second of the force kernel: the counted VALU
     instructions per launch (SQ_INSTS_VALU of the committed counter summary) x
     64 lanes / the live launch time, against the non-packed issue peak."""
-    insts = profile_value(kernel_hash, "valu_insts_per_launch")
+    insts = profile_value(kernel_hash, "valu_insts_per_launch", profile)
     if insts is None:
         return None
     rate = insts * 64 / (force_ms / 1e3)
@@ -64,14 +70,13 @@ def valu_issue(kernel_hash, force_ms, pairs):
             "note": "instruction issue (dual issue lets it pass 1), not algorithmic flops"}
 
 
-def hbm_phases(wl, ncell, n_moving, phase_ms, ms_step):
+def hbm_phases(n_active, ncell, n_moving, n_surf_moving, phase_ms, ms_step):
     """Achieved GB/s of algorithmic bytes per phase against the 8 TB/s HBM
     peak (phase times from the event-timed breakdown pass), and for the whole
     step with the force kernel's own bytes included."""
-    n_surf = int(np.sum(np.asarray(wl.tag) == 2))
-    bytes_ = {"build_cells": BUILD_B_PER_PARTICLE * wl.n + BUILD_B_PER_CELL * ncell,
-              "update": UPDATE_B * wl.n,
-              "project": PROJECT_B * n_moving + PROJECT_SURF_B * n_surf,
+    bytes_ = {"build_cells": BUILD_B_PER_PARTICLE * n_active + BUILD_B_PER_CELL * ncell,
+              "update": UPDATE_B * n_active,
+              "project": PROJECT_B * n_moving + PROJECT_SURF_B * n_surf_moving,
               "force": FORCE_B * n_moving}
     out = {}
     for k, b in bytes_.items():
@@ -105,11 +110,14 @@ def source_hash(paths):
     return h.hexdigest()[:16]
 
 
-def profile_value(kernel_hash, key):
+COUNTER_PROFILE = "force_gear_volume_counters.md"
+
+
+def profile_value(kernel_hash, key, profile=None):
     """A per-launch figure of the force kernel measured by rocprofv3 counters
     (the committed summary's `kernel_source_hash:` line and the `key:` line),
     or None if absent or taken on a different kernel source."""
-    p = os.path.join(ROOT, "profiles", "force_sphere_l5_counters.md")
+    p = os.path.join(ROOT, "profiles", profile or COUNTER_PROFILE)
     if not os.path.exists(p):
         return None
     text = open(p).read()
@@ -120,9 +128,9 @@ def profile_value(kernel_hash, key):
     return int(b.group(1))
 
 
-def traffic_from_profile(kernel_hash):
+def traffic_from_profile(kernel_hash, profile=None):
     """HBM bytes per force launch (FETCH_SIZE and WRITE_SIZE, calibrated)."""
-    return profile_value(kernel_hash, "hbm_bytes_per_launch")
+    return profile_value(kernel_hash, "hbm_bytes_per_launch", profile)
 
 
 # Non-packed VALU issue: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz
@@ -130,34 +138,51 @@ def traffic_from_profile(kernel_hash):
 VALU_LANE_OPS_PEAK = 256 * 64 * 2.4e9
 
 
-def cpu_baseline(wl, sample=160, seed=0):
-    """The oracle (brute force, FP64) on a bounded sample of the same step:
-    forces of `sample` moving receivers against all particles, then their
-    projection / inside test. Reported rate = sampled particle-updates / s."""
+def host_cores():
+    """CPUs this process may run on (at most 16, the host share of one GPU)
+    and the CPU model name."""
+    n = min(16, len(os.sched_getaffinity(0)))
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return n, model
+
+
+def cpu_baseline(wl, sample=1 << 20, seed=0):
+    """The oracle's full-size mode (oracle/local.py: FP64 forces over candidate
+    neighbour cells, the projection over candidate facets, the volume rule by
+    the ray winding number) on a bounded sample of the same step: forces of
+    `sample` random moving particles against all particles, then their
+    displacement and projection or volume rule, on all host cores (threads).
+    Reported rate = sampled particle-updates / s."""
     from oracle import force as oforce
-    from oracle import geometry as ogeo
-    from oracle import step as ostep
-    from threadpoolctl import threadpool_limits
+    from oracle import local as olocal
+    cores, model = host_cores()
     rng = np.random.Generator(np.random.PCG64(seed))
     mov = np.nonzero(oforce.moving_mask(wl.tag, wl.move_mask))[0]
     rec = np.sort(rng.choice(mov, size=min(sample, len(mov)), replace=False))
-    with threadpool_limits(limits=1):          # one core: numpy and any BLAS it calls
-        t0 = time.perf_counter()
-        a, S, cnt = oforce.accel(wl, rec)
-        # the step needs amax over all particles; the sample uses its own max (same cost per particle)
-        tau = (float(wl.geoms[0].h) / 16.0) / max(np.linalg.norm(a, axis=1).max(), 1e-300)
-        y = wl.pos[rec].astype(np.float64) + tau * a
-        s = wl.tag[rec] == 2
-        if s.any():
-            ostep.project_surface(wl, y[s], 0)
-        v = wl.tag[rec] == 3
-        if v.any():
-            ogeo.winding_number(y[v], wl.geoms[0].mesh.vert, wl.geoms[0].mesh.tri)
-        dt = time.perf_counter() - t0
-    return {"value": len(rec) / dt, "unit": "particle-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{len(rec)} random moving particles of the same workload: brute-force forces against "
-                      f"all {wl.n} particles, FP64 projection over all facets or winding-number inside test "
-                      f"({dt:.1f} s, numpy single thread)"}
+    t0 = time.perf_counter()
+    a, S, cnt = olocal.accel(wl, receivers=rec, threads=cores)
+    # the step needs amax over all movers; the sample uses its own (same cost per particle)
+    tau = (float(wl.geoms[0].h) / 16.0) / max(np.linalg.norm(a, axis=1).max(), 1e-300)
+    y = wl.pos[rec].astype(np.float64) + tau * a
+    s = wl.tag[rec] == 2
+    if s.any():
+        olocal.project_surface(wl, y[s], 0)
+    v = wl.tag[rec] == 3
+    if v.any():
+        olocal.volume_rule(y[v], wl.geoms[0].mesh)
+    dt = time.perf_counter() - t0
+    return {"value": len(rec) / dt, "unit": "particle-updates/s", "cores": cores, "cpu_model": model,
+            "kind": "oracle",
+            "sample": f"{len(rec)} random moving particles of the same workload: FP64 forces over the candidate "
+                      f"neighbour cells of all {wl.n} particles, then their projection or volume rule "
+                      f"({dt:.1f} s on {cores} threads; the oracle's full-size mode, pinned to its brute force)"}
 
 
 def bench_generate(args):
@@ -396,10 +421,10 @@ def bench_newton(args):
     feature tier, each after the tier partition), from the
     same initial state: the plain loop runs --plain-iters iterations (the
     paper's fixed iteration count) and its final force residual R_plain is the
-    target; Newton-MINRES runs until R <= R_plain. value = plain seconds /
-    Newton seconds. The plain loop's residual is not monotone (its step keeps
-    the fastest particle moving h/16), so the first time it dips to R_plain
-    and its best residual are reported as well."""
+    target; Newton-MINRES runs until R <= R_plain. The plain loop's residual
+    is not monotone (its step keeps the fastest particle moving h/16): value =
+    the seconds at which it FIRST dips to R_plain / Newton's seconds to it; the
+    ratio to its full run and to its best residual are reported as well."""
     import torch
     import synth
     from paper_2501_03056_amd import Relaxer
@@ -441,8 +466,9 @@ def bench_newton(args):
     t_best = t_newton + more.residual[-1][0] if more.residual[-1][1] <= plain[best][1] else None
     rest = newton_relax(rn, n_moving, target=None, max_iter=500,
                         time_limit=max(t_plain - (t_best or t_newton), 0.0), **kw)
-    out = {"metric": "Newton-HVP vs plain s to residual", "value": t_plain / t_newton if reached else 0.0,
-           "unit": "x (plain-loop seconds for its iterations / Newton seconds to the same force residual)",
+    out = {"metric": "Newton-HVP vs plain s to residual",
+           "value": (t_first / t_newton) if reached and t_first else 0.0,
+           "unit": "x (the plain loop's first arrival at its final force residual / Newton seconds to it)",
            "n_gpus": 1, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
            "config": {"workload": wname, "particles": wl.n, "moving": n_moving,
                       "plain_iters": args.plain_iters, "krylov": "MINRES", "forcing": "Eisenstat-Walker 2",
@@ -458,6 +484,7 @@ def bench_newton(args):
                       "seconds_to_plain_best": t_best,
                       "R_after_plain_seconds": rest.residual[-1][1]},
            "ratios": {"vs_plain_first_arrival": (t_first / t_newton) if reached and t_first else None,
+                      "vs_plain_final": (t_plain / t_newton) if reached else None,
                       "vs_plain_best": (plain[best][0] / t_best) if t_best else None},
            "device_status": rn.read_status()}
     print(json.dumps(out), flush=True)
@@ -482,11 +509,12 @@ def main():
     ap.add_argument("--krylov-max", type=int, default=3)
     ap.add_argument("--newton-tier", default="volume", choices=["volume", "surface", "feature"])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="sphere")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=960)
+    ap.add_argument("--no-newton", action="store_true", help="skip the Newton-vs-plain comparison")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the icosphere secondary workload")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 19)
     ap.add_argument("--k", type=int, default=2, help="stencil half-width of the particle cells (1 or 2)")
     ap.add_argument("--slab", type=int, default=0,
                     help="cell rows per slab of the cell key (0: one slab per geometry)")
@@ -507,7 +535,93 @@ def main():
         return bench_newton(args)
     if args.mode == "gear":
         return bench_gear(args)
+    return bench_step(args)
+
+
+def timed_steps(r, steps, warmup, label):
+    """W untimed iterations, a pair-counting pass, then exactly `steps` timed
+    iterations bracketed by synchronisations (HIP events on the launch stream
+    around the whole region and around every force launch), then a separate
+    event-timed pass for the per-phase breakdown."""
     import torch
+    for _ in range(warmup):
+        r.step(keep_accel=False)
+    r.build_cells()
+    r.accel.zero_()   # a receiver list leaves the other rows unwritten
+    r.relax_step(count_pairs=True)
+    r.project()
+    pairs0 = float(r.accel[:, 3].double().sum().item())
+    torch.cuda.synchronize()
+    print(f"[bench] {label}: warmup done, {pairs0:.4g} pairs/step", file=sys.stderr, flush=True)
+    r.profile(True, phases=("force",))
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    start.record()
+    for _ in range(steps):
+        r.step(keep_accel=False)
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = start.elapsed_time(stop)
+    f_ms, f_n = r.profile_read()["force"]
+    r.profile(True)
+    for _ in range(min(steps, 50)):
+        r.step(keep_accel=False)
+    prof = r.profile_read()
+    r.profile(False)
+    r.build_cells()
+    r.accel.zero_()
+    r.relax_step(count_pairs=True)
+    pairs1 = float(r.accel[:, 3].double().sum().item())
+    print(f"[bench] {label}: {ms / steps:.4f} ms/step", file=sys.stderr, flush=True)
+    return {"ms": ms, "ms_step": ms / steps, "wall": wall, "force_ms": f_ms / max(f_n, 1),
+            "pairs": 0.5 * (pairs0 + pairs1), "phase_ms": {k: (v[0] / max(v[1], 1)) for k, v in prof.items() if v[1]},
+            "status": r.read_status()}
+
+
+def newton_vs_plain(wl, mm, plain_iters, krylov_max):
+    """Newton-MINRES against the plain loop from the same state on one tier:
+    the plain loop's residual after its iterations is the target; the
+    headline ratio is the plain loop's FIRST arrival at that residual over
+    Newton's time to it (its residual is not monotone)."""
+    import torch
+    from paper_2501_03056_amd import Relaxer
+    from paper_2501_03056_amd.newton import newton_relax, plain_relax
+    n_moving = wl.n_moving()
+    rp = Relaxer(wl, device=0)
+    rp.tier(mm)
+    plain = plain_relax(rp, n_moving, iters=plain_iters, record_every=1)
+    target, t_plain = plain[-1][1], plain[-1][0]
+    t_first = _first_at_or_below(plain, target)
+    best = min(range(len(plain)), key=lambda q: plain[q][1])
+    del rp
+    rn = Relaxer(wl, device=0)
+    rn.tier(mm)
+    torch.cuda.synchronize()
+    kw = dict(forcing="ew", krylov_tol=1e-4, krylov_max=krylov_max, checkpoint_every=10)
+    log = newton_relax(rn, n_moving, target=target, max_iter=500, time_limit=20 * t_plain + 20, **kw)
+    t_newton = log.residual[-1][0]
+    reached = log.residual[-1][1] <= target
+    print(f"[bench] newton: R {log.residual[-1][1]:.4g} at {t_newton:.4f}s vs plain first arrival "
+          f"{t_first:.4f}s, plain {plain_iters} iterations {t_plain:.4f}s", file=sys.stderr, flush=True)
+    return {"metric": "Newton-HVP vs plain s to residual",
+            "value": (t_first / t_newton) if reached and t_first else 0.0,
+            "unit": "x (plain loop's first arrival at its final residual / Newton's seconds to it)",
+            "reached": reached, "moving": n_moving, "plain_iters": plain_iters,
+            "plain": {"seconds": t_plain, "R0": plain[0][1], "R_final": target,
+                      "seconds_first_at_or_below_R_final": t_first, "R_best": plain[best][1],
+                      "iters_to_best": best, "seconds_to_best": plain[best][0]},
+            "newton_result": {"seconds": t_newton, "R": log.residual[-1][1], "newton_iters": log.newton_iters,
+                              "krylov_iters": log.krylov_iters, "backtracks": log.backtracks},
+            "vs_plain_final": (t_plain / t_newton) if reached else None,
+            "krylov": "MINRES", "forcing": "Eisenstat-Walker 2", "krylov_max": krylov_max}
+
+
+def bench_step(args):
+    import torch
+    import synth
     from paper_2501_03056_amd import Relaxer
 
     if args.calibrate_copy:
@@ -516,83 +630,91 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    dx = args.gear_dx
     t0 = time.perf_counter()
-    wl, wname = make_workload(args.workload, args.k, args.slab)
-    print(f"[bench] workload {wname}: {wl.n} particles {wl.counts()} built in {time.perf_counter() - t0:.1f}s",
+    wl = synth.gear_workload(dx=dx, seed=3, k=args.k)
+    for g in wl.geoms:
+        g.slab = args.slab
+    wname = f"gear24_full_mesh_dx{dx:g}_volume_tier"
+    print(f"[bench] gear dx={dx:g}: {wl.n} particles {wl.counts()} built in {time.perf_counter() - t0:.1f}s",
           file=sys.stderr, flush=True)
+    mm_vol = 1 << synth.VOLUME
+    wl.move_mask = mm_vol
     r = Relaxer(wl, device=0)
-    n_moving = wl.n_moving()
-    for _ in range(args.warmup):
-        r.step(keep_accel=False)
-    # true pair count (separate counting pass, not timed)
-    r.build_cells()
-    r.relax_step(count_pairs=True)
-    r.project()
-    pairs0 = float(r.accel[:, 3].double().sum().item())
-    torch.cuda.synchronize()
-    print(f"[bench] warmup done, {pairs0:.4g} pairs/step", file=sys.stderr, flush=True)
+    r.tier(mm_vol)
+    n_moving = r.n_moving()
+    main = timed_steps(r, args.steps, args.warmup, "gear volume tier")
+    ncell = int(r.geom.ncell)
+    n_tri = int(r.geom.n_tri)
+    del r
+    # the sparse tiers of the same gear (each after the tier partition, with the receiver list)
+    tiers = {}
+    for name, mm in (("feature", 1 << synth.FEATURE), ("surface", 1 << synth.SURFACE)):
+        wl.move_mask = mm
+        rt = Relaxer(wl, device=0)
+        rt.tier(mm)
+        rt.use_list = True
+        t = timed_steps(rt, args.tier_iters, args.warmup, f"gear {name} tier")
+        tiers[name] = {"moving": rt.n_moving(), "active_particles": rt.na, "iters": args.tier_iters,
+                       "ms_per_step": t["ms_step"],
+                       "particle_updates_per_s": rt.n_moving() * args.tier_iters / (t["ms"] / 1e3),
+                       "pairs_per_step": t["pairs"], "kernels_ms_per_step": t["phase_ms"],
+                       "device_status": t["status"]}
+        del rt
+    tiers["volume"] = {"moving": n_moving, "ms_per_step": main["ms_step"]}
+    tot_upd = sum(tiers[k]["moving"] for k in tiers) * 1.0
+    tiers["three_tiers_particle_updates_per_s"] = tot_upd / sum(tiers[k]["ms_per_step"] / 1e3
+                                                               for k in ("feature", "surface", "volume"))
+    wl.move_mask = mm_vol
+    newton = None if args.no_newton else newton_vs_plain(wl, mm_vol, args.plain_iters, args.krylov_max)
+    secondary = None
+    if not args.no_secondary:
+        sw, sname = make_workload("sphere", args.k, args.slab)
+        rs = Relaxer(sw, device=0)
+        t = timed_steps(rs, args.steps, args.warmup, "sphere")
+        secondary = {"workload": sname, "particles": sw.n, "moving": sw.n_moving(),
+                     "value": sw.n_moving() * args.steps / (t["ms"] / 1e3), "unit": "particle-updates/s",
+                     "ms_per_step": t["ms_step"], "pair_evals_per_s": t["pairs"] * args.steps / (t["ms"] / 1e3),
+                     "force_kernel_ms": t["force_ms"],
+                     "force_tflops": t["pairs"] * FLOPS_PER_PAIR / (t["force_ms"] / 1e3) / 1e12,
+                     "kernels_ms_per_step": t["phase_ms"], "device_status": t["status"]}
+        del rs, sw
 
-    # timed region: HIP events on the launch stream bracket the force kernel
-    # only (the roofline's kernel); the per-phase breakdown comes from a
-    # separate pass, since every event pair adds a little time to the stream
-    r.profile(True, phases=("force",))
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    start.record()
-    for _ in range(args.steps):
-        r.step(keep_accel=False)
-    stop.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms = start.elapsed_time(stop)
-    force_prof = r.profile_read()["force"]
-    r.profile(True)
-    for _ in range(min(args.steps, 50)):
-        r.step(keep_accel=False)
-    prof = r.profile_read()
-    r.profile(False)
-    r.build_cells()
-    r.relax_step(count_pairs=True)
-    pairs1 = float(r.accel[:, 3].double().sum().item())
-    status = r.read_status()
-    pairs = 0.5 * (pairs0 + pairs1)
-
-    ms_step = ms / args.steps
-    value = n_moving * args.steps / (ms / 1e3)
-    f_ms, f_n = force_prof
-    force_ms = f_ms / max(f_n, 1)
+    ms, steps = main["ms"], args.steps
+    pairs = main["pairs"]
+    force_ms = main["force_ms"]
     achieved = pairs * FLOPS_PER_PAIR / (force_ms / 1e3) / 1e12
     khash = source_hash(KERNEL_SOURCES)
     traffic = traffic_from_profile(khash)
-    phase_ms = {k: (v[0] / max(v[1], 1)) for k, v in prof.items() if v[1]}
-    hbm = hbm_phases(wl, int(r.geom.ncell), n_moving, phase_ms, ms_step)
+    hbm = hbm_phases(wl.n, ncell, n_moving, 0, main["phase_ms"], main["ms_step"])
     out = {
         "metric": "particle-updates/s per relaxation step",
-        "value": value,
+        "value": n_moving * steps / (ms / 1e3),
         "unit": "particle-updates/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": main["ms_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": wname, "particles": wl.n, "moving": n_moving, "facets": int(r.geom.n_tri),
-                   "stencil_k": int(wl.geoms[0].k), "key_slab_rows": int(args.slab), "h_over_dx": 1.3,
-                   "pairs_per_step": pairs},
-        "pair_evals_per_s": pairs * args.steps / (ms / 1e3),
-        "kernels_ms_per_step": phase_ms,
+        "config": {"workload": wname, "particles": wl.n, "moving": n_moving, "counts": wl.counts(),
+                   "facets": n_tri, "stencil_k": int(wl.geoms[0].k), "key_slab_rows": int(args.slab),
+                   "h_over_dx": 1.3, "pairs_per_step": pairs},
+        "pair_evals_per_s": pairs * steps / (ms / 1e3),
+        "kernels_ms_per_step": main["phase_ms"],
         "hbm_phases": hbm,
         "roofline": {"bound": "alu", "kernel": "k_force", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                      "work_per_launch": pairs * FLOPS_PER_PAIR, "avg_launch_ms": force_ms,
                      "kernel_source_hash": khash, "valu_issue": valu_issue(khash, force_ms, pairs)},
-        "device_status": status,
-        "wall_s": wall,
+        "tiers": tiers,
+        "newton": newton,
+        "secondary": secondary,
+        "device_status": main["status"],
+        "wall_s": main["wall"],
     }
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)

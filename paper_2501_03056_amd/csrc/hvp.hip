@@ -6,6 +6,9 @@
 // neighbour predicate is the same binary32 expression.
 #include "stencil.h"
 
+#include <cfloat>
+#include <type_traits>
+
 namespace fppg {
 
 // ---- pair energy (line search of Newton-Krylov relaxation) --------------------------------
@@ -102,22 +105,46 @@ __global__ __launch_bounds__(kBlock) void k_jvp(const float4* __restrict__ pos, 
     // both rows are issued up front and no exec mask is juggled per
     // candidate. M(r) is linear in w, so the two terms of the transposed
     // product share one application.
-    for_each_source_with<K>(stencil_of(p, G), G, cs, pos, v, [&](int j, const float4 q, const float4 vj) {
-      const float dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
-      const float d2 = pair_d2(dx, dy, dz);
-      const uint32_t tj = __float_as_uint(q.w) & 7u;
-      // bitwise, not short-circuit, so that nothing here branches
-      const bool pair = (d2 < rc2) & (j != i);
-      if (!TRANSPOSE) {
-        const float sc = (pair & (tj <= T)) ? 1.0f : 0.0f;
-        pair_jac_apply(dx, dy, dz, d2, inv2h, k3, vi.x - vj.x, vi.y - vj.y, vi.z - vj.z, o0, o1, o2, sc);
-      } else {
+    const Stencil st = stencil_of(p, G);
+    if (!TRANSPOSE) {
+      // J v: every source's term M(r)(v_i - v_j). The receiver itself needs no
+      // test: there w = v_i - v_i = 0 and r = 0, so its term is exactly 0 (the
+      // clamp of d2 keeps 1/|r| finite). Wavefronts of volume receivers only
+      // (which take every class) skip the class test.
+      auto body = [&](auto ranked) {
+        for_each_source_with<K>(st, G, cs, pos, v, [&](int, const float4 q, const float4 vj) {
+          const float dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
+          const float d2 = pair_d2(dx, dy, dz);
+          bool pair = d2 < rc2;
+          if (decltype(ranked)::value) pair = pair & ((__float_as_uint(q.w) & 7u) <= T);
+          const float inv_r = __builtin_amdgcn_rsqf(fmaxf(d2, FLT_MIN));
+          const float t0 = fmaf(-(d2 * inv_r), inv2h, 1.0f);
+          const float t = pair ? t0 : 0.0f;
+          const float t2 = t * t;
+          const float c1 = t2 * t;
+          const float w0 = vi.x - vj.x, w1 = vi.y - vj.y, w2 = vi.z - vj.z;
+          const float rw = fmaf(dz, w2, fmaf(dy, w1, dx * w0));
+          const float c2 = (k3 * t2) * (rw * inv_r);
+          o0 = fmaf(-c2, dx, fmaf(c1, w0, o0));
+          o1 = fmaf(-c2, dy, fmaf(c1, w1, o1));
+          o2 = fmaf(-c2, dz, fmaf(c1, w2, o2));
+        });
+      };
+      if (__ballot(mov_i && tag < FPPG_TAG_VOLUME) != 0) body(std::true_type{});
+      else body(std::false_type{});
+    } else {
+      for_each_source_with<K>(st, G, cs, pos, v, [&](int j, const float4 q, const float4 vj) {
+        const float dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
+        const float d2 = pair_d2(dx, dy, dz);
+        const uint32_t tj = __float_as_uint(q.w) & 7u;
+        // bitwise, not short-circuit, so that nothing here branches
+        const bool pair = (d2 < rc2) & (j != i);
         const float s1 = (pair & mov_i & (tj <= T)) ? 1.0f : 0.0f;
         const float s2 = (pair & is_moving(int(tj), move_mask) & (rk <= rank_of(int(tj)))) ? -1.0f : 0.0f;
         pair_jac_apply(dx, dy, dz, d2, inv2h, k3, fmaf(s1, vi.x, s2 * vj.x), fmaf(s1, vi.y, s2 * vj.y),
                        fmaf(s1, vi.z, s2 * vj.z), o0, o1, o2, 1.0f);
-      }
-    });
+      });
+    }
     o0 *= G.kcoef;
     o1 *= G.kcoef;
     o2 *= G.kcoef;

@@ -106,17 +106,23 @@ __device__ __forceinline__ void for_each_row_by_plane(const Stencil s, const Geo
 // of four, whose tail of up to three single steps per row costs more than the
 // extra loads in flight gain, and than groups of three or single steps).
 // PLANES: walk the rows with for_each_row_by_plane (same order, same sums).
+// The walk advances a pointer (the loop costs one add and one compare per two
+// candidates); the index j passed to f is only formed where f uses it.
 template <int K, bool PLANES = false, class F>
 __device__ __forceinline__ void for_each_source(const Stencil s, const GeomDev& G, const int* __restrict__ cs,
                                                 const float4* __restrict__ pos, F&& f) {
   auto row = [&](int j0, int j1) {
-    int j = j0;
-    for (; j + 2 <= j1; j += 2) {
-      const float4 q0 = pos[j], q1 = pos[j + 1];
-      f(j, q0);
-      f(j + 1, q1);
+    const float4* q = pos + j0;
+    const float4* const e = pos + j1;
+    // a pair remains while q < e - 1; that bound is formed from the address
+    // (device addresses are far above one float4), not by pointer arithmetic
+    const float4* const last = reinterpret_cast<const float4*>(reinterpret_cast<uintptr_t>(e) - sizeof(float4));
+    for (; q < last; q += 2) {
+      const float4 q0 = q[0], q1 = q[1];
+      f(int(q - pos), q0);
+      f(int(q - pos) + 1, q1);
     }
-    if (j < j1) f(j, pos[j]);
+    if (q < e) f(int(q - pos), q[0]);
   };
   if (PLANES)
     for_each_row_by_plane<K>(s, G, cs, row);
@@ -131,14 +137,18 @@ __device__ __forceinline__ void for_each_source_with(const Stencil s, const Geom
                                                      const float4* __restrict__ pos,
                                                      const float4* __restrict__ aux, F&& f) {
   for_each_row<K>(s, G, cs, [&](int j0, int j1) {
-    int j = j0;
-    for (; j + 2 <= j1; j += 2) {
-      const float4 q0 = pos[j], q1 = pos[j + 1];
-      const float4 a0 = aux[j], a1 = aux[j + 1];
-      f(j, q0, a0);
-      f(j + 1, q1, a1);
+    // byte offsets from the row start, shared by the two fields
+    const float4* q = pos + j0;
+    const float4* w = aux + j0;
+    const int n = j1 - j0;
+    int k = 0;
+    for (; k + 1 < n; k += 2) {
+      const float4 q0 = q[k], q1 = q[k + 1];
+      const float4 a0 = w[k], a1 = w[k + 1];
+      f(j0 + k, q0, a0);
+      f(j0 + k + 1, q1, a1);
     }
-    if (j < j1) f(j, pos[j], aux[j]);
+    if (k < n) f(j0 + k, q[k], w[k]);
   });
 }
 
