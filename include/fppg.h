@@ -137,7 +137,23 @@ typedef struct {
   const int32_t* seg_vert;                /* [n_seg * 2] mesh vertex (local index) at each segment
                                              end, -1 if none; may be NULL (mesh gradients only) */
   int32_t slab;                           /* cell rows per slab of the key (see above) */
+  /* Boolean assembly (section 3.2.3): 0 = the mesh is the solid; otherwise the
+     mesh is the facets of n_part closed convex parts, part k owning the facets
+     part_tri_begin[k] .. part_tri_begin[k+1]-1 (part_tri_begin[0] = 0,
+     part_tri_begin[n_part] = n_tri), and the solid is
+       FPPG_CSG_UNION       the union of the parts
+       FPPG_CSG_DIFFERENCE  part 0 minus the union of the others.
+     Every part must be convex (each vertex of a part on the inner side of every
+     plane of its facets; FPPG_E_ARG otherwise). See fppg_project for how the
+     relaxation treats an assembly. */
+  int32_t csg_op;
+  int32_t n_part;
+  const int32_t* part_tri_begin;          /* [n_part + 1]; may be NULL if csg_op = 0 */
 } fppg_geom_desc;
+
+#define FPPG_CSG_NONE       0
+#define FPPG_CSG_UNION      1
+#define FPPG_CSG_DIFFERENCE 2
 
 /* ---- context ---------------------------------------------------------------------------- */
 
@@ -314,6 +330,16 @@ fppg_status fppg_relax_step(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
  *           meets a facet (tested against the facets of the search cells the
  *           segment's bounding box touches). With x inside, this equals "the
  *           signed distance of y is >= 0" for meshes thicker than the step.
+ *  Boolean assembly (fppg_geom_desc.csg_op): a surface foot point p on a
+ *           facet of part k is accepted only on the assembly's boundary (FP64
+ *           plane tests of the convex parts; a part's interior is where every
+ *           plane test is < 0): union, p in no other part's interior;
+ *           difference, for k = 0 p in no cut part's interior, for a cut part
+ *           p in the closure of part 0 and in no other cut part's interior.
+ *           A volume move whose segment's search cells hold facets is reverted
+ *           iff y is outside the assembly (union: in no part's interior;
+ *           difference: not in part 0's interior, or in a cut part's closure);
+ *           elsewhere it is accepted.
  * pos [n*4] in: positions x, out: new positions; owner [n] in/out;
  * disp [n*4] from fppg_relax_step; feat_seg/feat_u [n_feat] in/out (may be
  * NULL if n_feat = 0); counters [FPPG_NCOUNTERS] int64 on the device,
@@ -545,6 +571,7 @@ fppg_status fppg_features(fppg_ctx* ctx, const double* vert, int32_t n_vert, con
  * >= 0 (the same for every geometry); count [1] int32 (device): the number of
  * particles re-tagged. Non-finite positions keep their tags. Called once,
  * before the relaxation; its cost grows with (width / search cell edge)^3.
+ * A batch with a Boolean assembly: FPPG_E_UNSUPPORTED.
  */
 fppg_status fppg_volume_layers(fppg_ctx* ctx, const fppg_geom* geom, int64_t n, float* pos, double width,
                                int32_t* count, void* stream);

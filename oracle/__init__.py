@@ -18,9 +18,11 @@ Modules (each function cites the passage it follows):
              and the projection / revert rules of section 3.3.3
   hvp        Jacobian of the force field (Hessian-vector product of the pair energy)
   metrics    force residual and density-uniformity loss
+  csg        Boolean assemblies: part signed distances, boundary membership
+  local      the same step at full size (candidate searches, pinned to brute force)
 
 Readings of points where the paper is silent or garbled are listed where they
 are used; the functions with no independent pin say "parity unpinned" in their
 docstring (time-step rule, feature-line motion, volume revert rule, metrics).
 """
-from . import kernel, cells, neighbors, force, geometry, step, hvp, metrics  # noqa: F401
+from . import kernel, cells, neighbors, force, geometry, step, hvp, metrics, csg, local  # noqa: F401

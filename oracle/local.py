@@ -46,7 +46,8 @@ from . import force as F
 from .geometry import facet_frames, winding_number, unsigned_distance_many
 from .kernel import force_coef
 from .neighbors import pair_d2_xyz, rc2_f32
-from .step import (FEATURE, SURFACE, VOLUME, StepOut, advance_feature, batch_segments, displacement,
+from . import csg
+from .step import (FEATURE, SURFACE, VOLUME, StepOut, advance_feature, batch_segments, csg_filter, displacement,
                    project_onto_facets, time_step)
 
 RANK = F.RANK
@@ -236,6 +237,7 @@ def project_surface(wl, y, g, lam_margin=1e-7, d_margin=1e-9, grid=None):
     geo = wl.geoms[g]
     R = float(geo.proj_radius)
     grid = grid or FacetGrid(geo.mesh.vert, geo.mesh.tri, R * (1.0 + 1e-3) + 1e-6)
+    filt = csg_filter(geo)
     ok = np.zeros(len(y), bool)
     foot = y.copy()
     own = np.full(len(y), -1, np.int64)
@@ -244,7 +246,7 @@ def project_surface(wl, y, g, lam_margin=1e-7, d_margin=1e-9, grid=None):
         if len(fac) == 0:
             continue
         o, f, w, m = project_onto_facets(y[pts], grid.A[fac], grid.B[fac], grid.C[fac], grid.n[fac], fac, R,
-                                         lam_margin, d_margin)
+                                         lam_margin, d_margin, filt)
         ok[pts], foot[pts], margin[pts] = o, f, m
         own[pts] = np.where(o, w + geo.tri_begin, -1)
     return ok, foot, own, margin
@@ -365,7 +367,11 @@ def relax_step(wl, pos32=None, owner=None, feat_seg=None, feat_u=None, tag=None,
         v = np.nonzero(mov & (gid == g) & (tag == VOLUME))[0]
         if len(v):
             y = x[v] + dr[v]
-            ok, mg = volume_rule(y, geo.mesh, sd_margin)
+            if getattr(geo, "csg", None) is not None:   # parts have few facets: the brute-force rule
+                sd = csg.assembly_sd(y, geo)
+                ok, mg = sd < 0, np.abs(sd) <= sd_margin
+            else:
+                ok, mg = volume_rule(y, geo.mesh, sd_margin)
             x_new[v[ok]] = y[ok]
             reverted[v[~ok]] = True
             margin[v] = mg

@@ -130,20 +130,31 @@ def project_surface(wl, y, g, lam_margin=1e-7, d_margin=1e-9):
     foot = y.copy()
     own = np.full(len(y), -1, np.int64)
     margin = np.zeros(len(y), bool)
+    filt = csg_filter(geo)
     for s in range(0, len(y), 256):
         o, f, w, m = project_onto_facets(y[s:s + 256], A, B, C, n, ids, float(geo.proj_radius),
-                                         lam_margin, d_margin)
+                                         lam_margin, d_margin, filt)
         ok[s:s + 256], foot[s:s + 256], margin[s:s + 256] = o, f, m
         own[s:s + 256] = np.where(o, w + geo.tri_begin, -1)
     return ok, foot, own, margin
 
 
-def project_onto_facets(y, A, B, C, n, ids, R, lam_margin=1e-7, d_margin=1e-9):
+def csg_filter(geo):
+    """For a Boolean assembly: the test that a foot point on a facet lies on the
+    assembly's boundary (csg.on_boundary); None for a single mesh."""
+    if getattr(geo, "csg", None) is None:
+        return None
+    from . import csg
+    return lambda p, facets: csg.on_boundary(p, facets, geo)
+
+
+def project_onto_facets(y, A, B, C, n, ids, R, lam_margin=1e-7, d_margin=1e-9, filt=None):
     """The section 3.3.3 decision for points y [P, 3] over the facets (A, B, C,
     n) whose local indices `ids` are ascending: plane distance d, foot point
     p = y - d n, accepted iff every barycentric coordinate of p is >= 0 and
-    |d| <= R; the accepted facet with the smallest |d| wins, ties to the
-    lowest index. Returns (accepted, foot, winning index from ids, margin)."""
+    |d| <= R (and, for a Boolean assembly, `filt` places p on its boundary);
+    the accepted facet with the smallest |d| wins, ties to the lowest index.
+    Returns (accepted, foot, winning index from ids, margin)."""
     q = y[:, None, :]
     d = np.sum((q - A[None]) * n[None], -1)                     # [P, T] signed plane distance
     p = q - d[..., None] * n[None]
@@ -151,6 +162,12 @@ def project_onto_facets(y, A, B, C, n, ids, R, lam_margin=1e-7, d_margin=1e-9):
     lmin = np.minimum(np.minimum(la, lb), lc)
     ad = np.abs(d)
     acc = (lmin >= 0) & (ad <= R)
+    csg_margin = np.zeros(len(y), bool)
+    if filt is not None and acc.any():
+        r, c = np.nonzero(acc)
+        ok, near = filt(p[r, c], np.asarray(ids)[c])
+        acc[r[~ok], c[~ok]] = False
+        csg_margin[r[near]] = True
     key = np.where(acc, ad, np.inf)
     best = np.argmin(key, axis=1)                                # first index among equal minima
     has = np.isfinite(key[np.arange(len(best)), best])
@@ -168,7 +185,7 @@ def project_onto_facets(y, A, B, C, n, ids, R, lam_margin=1e-7, d_margin=1e-9):
     with np.errstate(invalid="ignore"):                          # inf - inf where nothing is accepted
         tie = (np.isfinite(srt[:, 1]) & (srt[:, 1] - srt[:, 0] <= d_margin)) if key.shape[1] > 1 \
             else np.zeros(len(best), bool)
-    return has, foot, np.asarray(ids)[best], edge.any(1) | near_R | tie
+    return has, foot, np.asarray(ids)[best], edge.any(1) | near_R | tie | csg_margin
 
 
 def advance_feature(seg, u, du, segs, margin_tol=1e-9):
@@ -238,7 +255,11 @@ def relax_step(wl, pos32=None, owner=None, feat_seg=None, feat_u=None, tag=None,
         v = np.nonzero(mov & (gid == g) & (tag == VOLUME))[0]
         if len(v):
             y = x[v] + dr[v]
-            sd = signed_distance_many(y, geo.mesh.vert, geo.mesh.tri)
+            if getattr(geo, "csg", None) is not None:
+                from . import csg
+                sd = csg.assembly_sd(y, geo)
+            else:
+                sd = signed_distance_many(y, geo.mesh.vert, geo.mesh.tri)
             ok = sd < 0
             x_new[v[ok]] = y[ok]
             reverted[v[~ok]] = True

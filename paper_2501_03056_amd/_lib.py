@@ -12,6 +12,7 @@ LIB_PATH = os.path.join(HERE, "libfppg.so")
 
 OK, E_ARG, E_HIP, E_WORKSPACE, E_CAPACITY, E_UNSUPPORTED, E_NODEVICE = 0, -1, -2, -3, -4, -5, -6
 F_COUNT_PAIRS = 1
+CSG_NONE, CSG_UNION, CSG_DIFFERENCE = 0, 1, 2
 S_NONFINITE_ACCEL, S_NONFINITE_POS, S_BAD_INDEX = 1, 2, 4
 C_REVERT_SURFACE, C_REVERT_FEATURE, C_REVERT_VOLUME = 0, 1, 2
 NCOUNTERS = 8
@@ -29,6 +30,7 @@ class GeomDesc(ctypes.Structure):
         ("seg_p", POINTER(c_double)), ("line_closed", POINTER(c_uint8)),
         ("seg_vert", POINTER(c_int32)),
         ("slab", c_int32),
+        ("csg_op", c_int32), ("n_part", c_int32), ("part_tri_begin", POINTER(c_int32)),
     ]
 
 

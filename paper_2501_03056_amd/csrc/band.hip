@@ -109,6 +109,8 @@ extern "C" fppg_status fppg_volume_layers(fppg_ctx* ctx, const fppg_geom* geom, 
   if (!count || (n > 0 && !pos)) return fail(ctx, FPPG_E_ARG, "null pos/count");
   if (!aligned(pos, 16)) return fail(ctx, FPPG_E_ARG, "pos must be 16-byte aligned");
   if (!(width >= 0.0) || !std::isfinite(width)) return fail(ctx, FPPG_E_ARG, "width must be finite and >= 0");
+  if (geom->has_csg)   // the distance to all facets includes the parts' faces inside the assembly
+    return fail(ctx, FPPG_E_UNSUPPORTED, "volume layers of a Boolean assembly are not supported");
   hipStream_t s = static_cast<hipStream_t>(stream);
   k_zero_i32<<<1, 64, 0, s>>>(count);
   if (n > 0)

@@ -187,6 +187,68 @@ static void free_geom(Geom* g) {
   hipFree(g->d_tg_start);
   hipFree(g->d_tg_tri);
   hipFree(g->d_tg_flag);
+  hipFree(g->d_facet_part);
+  hipFree(g->d_part);
+  hipFree(g->d_plane);
+}
+
+// Planes of the convex parts of an assembly (section 3.2.3): every facet of a
+// part gives a plane (n, d), n the unit outward normal and d = n.A; planes
+// equal within 1e-12 are stored once. A part is accepted only if it is convex:
+// every vertex of its facets within 1e-9 (1 + size) of the inner side of each
+// of its planes.
+static fppg_status build_parts(fppg_ctx* ctx, const fppg_geom_desc& d, int32_t g, int32_t tri_off,
+                               std::vector<int32_t>& facet_part, std::vector<int2>& parts,
+                               std::vector<double4>& planes, GeomDev& G) {
+  G.csg_op = d.csg_op;
+  G.part_begin_csg = G.part_end_csg = int32_t(parts.size());
+  if (d.csg_op == FPPG_CSG_NONE) {
+    facet_part.insert(facet_part.end(), size_t(d.n_tri), -1);
+    return FPPG_OK;
+  }
+  const std::string where = "geometry " + std::to_string(g) + ": ";
+  if (d.csg_op != FPPG_CSG_UNION && d.csg_op != FPPG_CSG_DIFFERENCE)
+    return fail(ctx, FPPG_E_ARG, where + "csg_op must be 0, 1 or 2");
+  if (d.n_part < 1 || !d.part_tri_begin || d.part_tri_begin[0] != 0 || d.part_tri_begin[d.n_part] != d.n_tri)
+    return fail(ctx, FPPG_E_ARG, where + "part_tri_begin must run from 0 to n_tri over n_part >= 1 parts");
+  for (int32_t k = 0; k < d.n_part; ++k) {
+    const int32_t b = d.part_tri_begin[k], e = d.part_tri_begin[k + 1];
+    if (e <= b) return fail(ctx, FPPG_E_ARG, where + "every part needs a facet (part_tri_begin increasing)");
+    const int32_t p0 = int32_t(planes.size());
+    double lo = INFINITY, hi = -INFINITY;
+    for (int32_t t = b; t < e; ++t) {
+      const double* A = d.vert + 3 * d.tri[3 * t];
+      const double* B = d.vert + 3 * d.tri[3 * t + 1];
+      const double* C = d.vert + 3 * d.tri[3 * t + 2];
+      const double e0[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]}, e1[3] = {C[0] - A[0], C[1] - A[1], C[2] - A[2]};
+      double n[3] = {e0[1] * e1[2] - e0[2] * e1[1], e0[2] * e1[0] - e0[0] * e1[2], e0[0] * e1[1] - e0[1] * e1[0]};
+      const double ln = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+      for (int q = 0; q < 3; ++q) n[q] /= ln;
+      const double dd = n[0] * A[0] + n[1] * A[1] + n[2] * A[2];
+      bool dup = false;
+      for (int32_t j = p0; j < int32_t(planes.size()) && !dup; ++j)
+        dup = std::fabs(planes[j].x - n[0]) <= 1e-12 && std::fabs(planes[j].y - n[1]) <= 1e-12 &&
+              std::fabs(planes[j].z - n[2]) <= 1e-12 && std::fabs(planes[j].w - dd) <= 1e-12;
+      if (!dup) planes.push_back(make_double4(n[0], n[1], n[2], dd));
+      for (int q = 0; q < 3; ++q) {
+        lo = std::min(lo, std::min(A[q], std::min(B[q], C[q])));
+        hi = std::max(hi, std::max(A[q], std::max(B[q], C[q])));
+      }
+      facet_part.push_back(int32_t(parts.size()));
+    }
+    const double tol = 1e-9 * (1.0 + (hi - lo));
+    for (int32_t t = b; t < e; ++t)
+      for (int c = 0; c < 3; ++c) {
+        const double* V = d.vert + 3 * d.tri[3 * t + c];
+        for (int32_t j = p0; j < int32_t(planes.size()); ++j)
+          if (planes[j].x * V[0] + planes[j].y * V[1] + planes[j].z * V[2] - planes[j].w > tol)
+            return fail(ctx, FPPG_E_ARG, where + "part " + std::to_string(k) + " is not convex");
+      }
+    parts.push_back(make_int2(p0, int32_t(planes.size())));
+  }
+  G.part_end_csg = int32_t(parts.size());
+  (void)tri_off;
+  return FPPG_OK;
 }
 
 static fppg_status geom_create(fppg_ctx* ctx, const fppg_geom_desc* descs, int32_t n_geom,
@@ -202,6 +264,9 @@ static fppg_status geom_create(fppg_ctx* ctx, const fppg_geom_desc* descs, int32
   std::vector<SegDev> segs;
   std::vector<int4> tri_vert;
   std::vector<int2> seg_vert;
+  std::vector<int32_t> facet_part;
+  std::vector<int2> parts;
+  std::vector<double4> planes;
   int32_t vert_off = 0;
   std::vector<int32_t> tg_start;   // global
   std::vector<int32_t> tg_tri;
@@ -269,6 +334,11 @@ static fppg_status geom_create(fppg_ctx* ctx, const fppg_geom_desc* descs, int32
       facets.push_back(f);
       n32.push_back(make_float4(float(f.n[0]), float(f.n[1]), float(f.n[2]), 0.f));
       tri_vert.push_back(make_int4(vert_off + d.tri[3 * t], vert_off + d.tri[3 * t + 1], vert_off + d.tri[3 * t + 2], 0));
+    }
+    // parts of a Boolean assembly
+    {
+      const fppg_status pst = build_parts(ctx, d, g, tri_off, facet_part, parts, planes, G);
+      if (pst != FPPG_OK) return pst;
     }
     // feature segments
     G.seg_begin = seg_off;
@@ -341,13 +411,16 @@ static fppg_status geom_create(fppg_ctx* ctx, const fppg_geom_desc* descs, int32
   geo->n_vert = vert_off;
   geo->host = gd;
   geo->device = ctx->device;
+  geo->has_csg = !parts.empty();
   fppg_status st = FPPG_OK;
   if ((st = upload(ctx, &geo->d_geom, gd)) != FPPG_OK || (st = upload(ctx, &geo->d_facet, facets)) != FPPG_OK ||
       (st = upload(ctx, &geo->d_n32, n32)) != FPPG_OK || (st = upload(ctx, &geo->d_seg, segs)) != FPPG_OK ||
       (st = upload(ctx, &geo->d_tri_vert, tri_vert)) != FPPG_OK ||
       (st = upload(ctx, &geo->d_seg_vert, seg_vert)) != FPPG_OK ||
       (st = upload(ctx, &geo->d_tg_start, tg_start)) != FPPG_OK ||
-      (st = upload(ctx, &geo->d_tg_tri, tg_tri)) != FPPG_OK || (st = upload(ctx, &geo->d_tg_flag, tg_flag)) != FPPG_OK) {
+      (st = upload(ctx, &geo->d_tg_tri, tg_tri)) != FPPG_OK || (st = upload(ctx, &geo->d_tg_flag, tg_flag)) != FPPG_OK ||
+      (st = upload(ctx, &geo->d_facet_part, facet_part)) != FPPG_OK || (st = upload(ctx, &geo->d_part, parts)) != FPPG_OK ||
+      (st = upload(ctx, &geo->d_plane, planes)) != FPPG_OK) {
     free_geom(geo);
     delete static_cast<fppg_geom*>(geo);
     return st;

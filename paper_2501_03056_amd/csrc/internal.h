@@ -34,6 +34,16 @@ struct GeomDev {
   int32_t slab;     // rows of cells along y per slab of the cell key (1..dims[1])
   int64_t tg_begin; // offset of this geometry's cells in the global search-cell arrays
   int32_t tri_begin, tri_end, seg_begin, seg_end;
+  int32_t csg_op;            // FPPG_CSG_*: the facets are those of convex parts combined by a Boolean operation
+  int32_t part_begin_csg, part_end_csg;   // global part range of an assembly
+};
+
+// Boolean assemblies: per global facet its part (-1: not in an assembly), per
+// part its plane range, planes (n, d) with n.x - d < 0 inside the part.
+struct CsgDev {
+  const int* facet_part = nullptr;
+  const int2* part = nullptr;
+  const double4* plane = nullptr;
 };
 
 // FP64 facet frame for the projection and crossing tests.
@@ -77,6 +87,11 @@ struct Geom {
   int32_t* d_tg_start = nullptr;    // [tg_cells + 1]
   int32_t* d_tg_tri = nullptr;      // [tg_entries] global facet ids
   uint8_t* d_tg_flag = nullptr;     // [tg_cells]
+  int32_t* d_facet_part = nullptr;  // [n_tri] part of each facet in an assembly, -1 otherwise
+  int2* d_part = nullptr;           // [n_parts] plane range of each part
+  double4* d_plane = nullptr;       // [n_planes]
+  bool has_csg = false;
+  CsgDev csg() const { return CsgDev{d_facet_part, d_part, d_plane}; }
   int device = 0;
 };
 

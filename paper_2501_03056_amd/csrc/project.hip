@@ -16,6 +16,9 @@
 //            bounding box touches (padded by 1e-7 cell). Away from the
 //            surface those cells hold no facet and the move is accepted after
 //            one byte of flags.
+// Boolean assemblies (section 3.2.3): a foot point counts only on the
+// assembly's boundary and a volume move near facets only inside the assembly,
+// both by FP64 plane tests of the convex parts.
 // Reverts are counted per block and added to the caller's counters by one
 // small kernel.
 #include "search_grid.h"
@@ -37,6 +40,55 @@ __device__ __forceinline__ double gap1(int d, double f) {
   return d > 0 ? double(d) - f : (d < 0 ? f + double(-d - 1) : 0.0);
 }
 
+// ---- Boolean assemblies (section 3.2.3) ----------------------------------------------------
+// Plane tests of the convex parts in FP64 (n.x - d per plane).
+__device__ __forceinline__ bool in_part_open(const CsgDev& cs, int k, double x, double y, double z) {
+  const int2 r = cs.part[k];
+  for (int j = r.x; j < r.y; ++j) {
+    const double4 P = cs.plane[j];
+    if (P.x * x + P.y * y + P.z * z - P.w >= 0.0) return false;
+  }
+  return true;
+}
+
+__device__ __forceinline__ bool in_part_closed(const CsgDev& cs, int k, double x, double y, double z) {
+  const int2 r = cs.part[k];
+  for (int j = r.x; j < r.y; ++j) {
+    const double4 P = cs.plane[j];
+    if (P.x * x + P.y * y + P.z * z - P.w > 0.0) return false;
+  }
+  return true;
+}
+
+// Is a point of part k's surface on the assembly's boundary?
+__device__ __forceinline__ bool csg_on_boundary(const GeomDev& G, const CsgDev& cs, int k, double x, double y,
+                                                double z) {
+  const int base = G.part_begin_csg;
+  for (int j = base; j < G.part_end_csg; ++j) {
+    if (j == k) continue;
+    if (G.csg_op == FPPG_CSG_DIFFERENCE && j == base && k != base) {
+      if (!in_part_closed(cs, j, x, y, z)) return false;   // a cut face counts inside part 0
+    } else if (in_part_open(cs, j, x, y, z)) {
+      return false;
+    }
+  }
+  return true;
+}
+
+// Is a point inside the assembly?
+__device__ __forceinline__ bool csg_inside(const GeomDev& G, const CsgDev& cs, double x, double y, double z) {
+  const int base = G.part_begin_csg;
+  if (G.csg_op == FPPG_CSG_UNION) {
+    for (int j = base; j < G.part_end_csg; ++j)
+      if (in_part_open(cs, j, x, y, z)) return true;
+    return false;
+  }
+  if (!in_part_open(cs, base, x, y, z)) return false;
+  for (int j = base + 1; j < G.part_end_csg; ++j)
+    if (in_part_closed(cs, j, x, y, z)) return false;
+  return true;
+}
+
 struct SurfaceHit {
   double best = INFINITY, x = 0.0, y = 0.0, z = 0.0;
   int t = 0x7fffffff;
@@ -44,7 +96,8 @@ struct SurfaceHit {
 
 __device__ __forceinline__ void scan_surface_cell(int64_t c, double yx, double yy, double yz, double R,
                                                   const FacetDev* __restrict__ facets, const int* __restrict__ tstart,
-                                                  const int* __restrict__ ttri, SurfaceHit& h) {
+                                                  const int* __restrict__ ttri, SurfaceHit& h, const GeomDev& G,
+                                                  const CsgDev& cs) {
   const int b = tstart[c], e = tstart[c + 1];
   for (int q = b; q < e; ++q) {
     const int t = ttri[q];
@@ -53,7 +106,7 @@ __device__ __forceinline__ void scan_surface_cell(int64_t c, double yx, double y
     const double ad = fabs(dist);
     if (!(ad <= R) || ad > h.best || (ad == h.best && t >= h.t)) continue;
     const double px = yx - dist * F.n[0], py = yy - dist * F.n[1], pz = yz - dist * F.n[2];
-    if (bary_min(F, px, py, pz) >= 0.0) {
+    if (bary_min(F, px, py, pz) >= 0.0 && (G.csg_op == FPPG_CSG_NONE || csg_on_boundary(G, cs, cs.facet_part[t], px, py, pz))) {
       h.best = ad;
       h.t = t;
       h.x = px;
@@ -66,14 +119,14 @@ __device__ __forceinline__ void scan_surface_cell(int64_t c, double yx, double y
 __device__ __forceinline__ SurfaceHit surface_search(const GeomDev& G, double yx, double yy, double yz,
                                                      const FacetDev* __restrict__ facets,
                                                      const int* __restrict__ tstart, const int* __restrict__ ttri,
-                                                     const uint8_t* __restrict__ tflag) {
+                                                     const uint8_t* __restrict__ tflag, const CsgDev& cs) {
   SurfaceHit h;
   const double R = G.R;
   const double tx = search_t(G, 0, yx), ty = search_t(G, 1, yy), tz = search_t(G, 2, yz);
   const int cx = int(floor(tx)), cy = int(floor(ty)), cz = int(floor(tz));
   const double fx = tx - cx, fy = ty - cy, fz = tz - cz;
   const int64_t c0 = search_index(G, cx, cy, cz);
-  if (tflag[c0] & kCellHasFacet) scan_surface_cell(c0, yx, yy, yz, R, facets, tstart, ttri, h);
+  if (tflag[c0] & kCellHasFacet) scan_surface_cell(c0, yx, yy, yz, R, facets, tstart, ttri, h, G, cs);
   const double slack = 1e-7;   // cell units, covers the rounding of the gaps
   for (int dz = -1; dz <= 1; ++dz) {
     const int z = cz + dz;
@@ -88,7 +141,7 @@ __device__ __forceinline__ SurfaceHit surface_search(const GeomDev& G, double yx
         const double lim = fmin(h.best, R) * G.tg_inv + slack;   // the cell must come within |d| of y
         if (gx * gx + gy * gy + gz * gz > lim * lim) continue;
         const int64_t c = search_index(G, x, y, z);
-        if (tflag[c] & kCellHasFacet) scan_surface_cell(c, yx, yy, yz, R, facets, tstart, ttri, h);
+        if (tflag[c] & kCellHasFacet) scan_surface_cell(c, yx, yy, yz, R, facets, tstart, ttri, h, G, cs);
       }
     }
   }
@@ -132,6 +185,20 @@ __device__ __forceinline__ bool segment_crosses(const GeomDev& G, double x0, dou
         if ((tflag[c] & kCellHasFacet) && cell_crossed(c, x0, x1, x2, y0, y1, y2, facets, tstart, ttri))
           return true;
       }
+  return false;
+}
+
+// Does any search cell that the box of the segment [x, y] touches hold a facet?
+__device__ __forceinline__ bool segment_near_facets(const GeomDev& G, double x0, double x1, double x2, double y0,
+                                                    double y1, double y2, const uint8_t* __restrict__ tflag) {
+  const double pad = 1e-7;   // cell units
+  const int lx = int(floor(search_t(G, 0, fmin(x0, y0)) - pad)), hx = int(floor(search_t(G, 0, fmax(x0, y0)) + pad));
+  const int ly = int(floor(search_t(G, 1, fmin(x1, y1)) - pad)), hy = int(floor(search_t(G, 1, fmax(x1, y1)) + pad));
+  const int lz = int(floor(search_t(G, 2, fmin(x2, y2)) - pad)), hz = int(floor(search_t(G, 2, fmax(x2, y2)) + pad));
+  for (int z = max(lz, 0); z <= min(hz, G.tg_dims[2] - 1); ++z)
+    for (int y = max(ly, 0); y <= min(hy, G.tg_dims[1] - 1); ++y)
+      for (int x = max(lx, 0); x <= min(hx, G.tg_dims[0] - 1); ++x)
+        if (tflag[search_index(G, x, y, z)] & kCellHasFacet) return true;
   return false;
 }
 
@@ -185,7 +252,7 @@ __global__ __launch_bounds__(kBlock) void k_project_volume(float4* __restrict__ 
                                                            uint32_t* status, uint8_t* __restrict__ accepted,
                                                            const int* __restrict__ list, int n_list,
                                                            int* __restrict__ queue, int* __restrict__ qcount,
-                                                           int* __restrict__ vrev) {
+                                                           int* __restrict__ vrev, CsgDev cs) {
   const int i = listed(blockIdx.x * blockDim.x + threadIdx.x, n, list, n_list);
   bool rev_v = false, heavy = false;
   if (i < n) {
@@ -199,7 +266,9 @@ __global__ __launch_bounds__(kBlock) void k_project_volume(float4* __restrict__ 
         const float y0 = p.x + d.x, y1 = p.y + d.y, y2 = p.z + d.z;
         if (!(isfinite(y0) && isfinite(y1) && isfinite(y2))) {
           atomicOr(status, FPPG_S_NONFINITE_POS);
-        } else if (segment_crosses(G, p.x, p.y, p.z, y0, y1, y2, facets, tstart, ttri, tflag)) {
+        } else if (G.csg_op == FPPG_CSG_NONE
+                       ? segment_crosses(G, p.x, p.y, p.z, y0, y1, y2, facets, tstart, ttri, tflag)
+                       : (segment_near_facets(G, p.x, p.y, p.z, y0, y1, y2, tflag) && !csg_inside(G, cs, y0, y1, y2))) {
           rev_v = true;                                    // would leave the volume: stays at x
         } else {
           pos[i] = make_float4(y0, y1, y2, p.w);
@@ -256,7 +325,7 @@ __global__ __launch_bounds__(kBlock) void k_project_heavy(float4* __restrict__ p
                                                           const int* __restrict__ queue,
                                                           const int* __restrict__ qcount,
                                                           const int* __restrict__ vrev, int n_vblocks, int group,
-                                                          int4* __restrict__ part) {
+                                                          int4* __restrict__ part, CsgDev cs) {
   __shared__ int s_pre[kHeavyGroupMax + 1];
   __shared__ int s_rev[2];
   const int b0 = blockIdx.x * group;
@@ -288,7 +357,7 @@ __global__ __launch_bounds__(kBlock) void k_project_heavy(float4* __restrict__ p
         if (!(isfinite(yx) && isfinite(yy) && isfinite(yz))) {
           atomicOr(status, FPPG_S_NONFINITE_POS);
         } else {
-          const SurfaceHit h = surface_search(G, yx, yy, yz, facets, tstart, ttri, tflag);
+          const SurfaceHit h = surface_search(G, yx, yy, yz, facets, tstart, ttri, tflag, cs);
           if (h.t != 0x7fffffff) {
             pos[i] = make_float4(float(h.x), float(h.y), float(h.z), p.w);
             owner[i] = h.t;
@@ -399,17 +468,17 @@ static fppg_status project_impl(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
   if (geom->n_geom == 1)
     k_project_volume<true><<<vb, kBlock, 0, s>>>(p4, d4, ni, geom->d_geom, 1, geom->d_facet, geom->d_tg_start,
                                                  geom->d_tg_tri, geom->d_tg_flag, move_mask, ctx->d_status, accepted,
-                                                 list, nr, queue, qcount, vrev);
+                                                 list, nr, queue, qcount, vrev, geom->csg());
   else
     k_project_volume<false><<<vb, kBlock, 0, s>>>(p4, d4, ni, geom->d_geom, geom->n_geom, geom->d_facet,
                                                   geom->d_tg_start, geom->d_tg_tri, geom->d_tg_flag, move_mask,
-                                                  ctx->d_status, accepted, list, nr, queue, qcount, vrev);
+                                                  ctx->d_status, accepted, list, nr, queue, qcount, vrev, geom->csg());
   const int group = (move_mask >> FPPG_TAG_VOLUME) & 1u ? kHeavyGroupMax : 1;
   const int hb = (vb + group - 1) / group;
   k_project_heavy<<<hb, kBlock, 0, s>>>(p4, owner, d4, feat_seg, feat_u, n_feat, int(geom->n_seg), geom->d_seg,
                                         geom->d_geom, geom->n_geom, geom->d_facet, geom->d_tg_start, geom->d_tg_tri,
                                         geom->d_tg_flag, ctx->d_status, accepted, queue, qcount, vrev, vb, group,
-                                        part);
+                                        part, geom->csg());
   k_project_counts<<<1, kBlock, 0, s>>>(part, hb, ctr);
   FPPG_HIP(ctx, hipGetLastError());
   return FPPG_OK;

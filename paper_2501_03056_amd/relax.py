@@ -67,6 +67,15 @@ def geom_descs(geoms):
         else:
             d.seg_vert = None
         d.slab = int(getattr(geo, "slab", 0))
+        csg = getattr(geo, "csg", None)
+        if csg is not None:
+            tb = np.ascontiguousarray(csg.part_tri_begin, np.int32)
+            keep.append(tb)
+            d.csg_op = int(csg.op)
+            d.n_part = len(tb) - 1
+            d.part_tri_begin = tb.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        else:
+            d.csg_op, d.n_part, d.part_tri_begin = L.CSG_NONE, 0, None
     return arr, keep
 
 

@@ -28,6 +28,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
+from . import csg as C
 from . import meshes as M
 
 SINGULAR, FEATURE, SURFACE, VOLUME, FIXED = 0, 1, 2, 3, 4
@@ -64,6 +65,7 @@ class Geometry:
     feat_begin: int = 0
     vert_begin: int = 0   # global id of the mesh's first vertex (singular-particle owners)
     slab: int = 0         # rows of cells along y per slab of the cell key (0: one slab)
+    csg: object = None    # csg.CSG: the mesh is the facets of convex parts combined by a Boolean operation
 
     @property
     def ncell(self) -> int:
@@ -574,17 +576,70 @@ def split_geometry(wl: Workload, g: int) -> Workload:
         b.feat_seg.append(wl.feat_seg[geo.feat_begin:geo.feat_begin + nf] - geo.seg_begin)
         b.feat_u.append(wl.feat_u[geo.feat_begin:geo.feat_begin + nf].copy())
     single = Geometry(mesh=geo.mesh, dx=geo.dx, h=geo.h, k=geo.k, proj_radius=geo.proj_radius,
-                      origin=geo.origin.copy(), inv_cell=geo.inv_cell, dims=geo.dims.copy())
+                      origin=geo.origin.copy(), inv_cell=geo.inv_cell, dims=geo.dims.copy(), csg=geo.csg)
     out = _finish(f"{wl.name}_g{g}", [(single, b)], wl.move_mask, wl.seed)
     out.pos = wl.pos[m].copy()     # keep the exact binary32 positions
     return out
 
 
+def assembly_geometry(rng, n_target: float, jitter=0.3, k=2, mc_samples=1_000_000):
+    """One Boolean assembly of 2-6 random boxes and cylinders (csg.random_assembly)
+    with dx = (V / n_target)^(1/3) from its Monte Carlo volume V, filled like
+    the other workloads: volume particles on a jittered (i+1/2)dx lattice at
+    least dx/2 inside, surface particles on every part's faces where they lie
+    on the assembly's boundary at least dx/2 from the other parts, feature
+    particles along the clipped sharp edges, the surviving corners as
+    singular points. Returns (Geometry, _Builder, description)."""
+    parts, op, vol = C.random_assembly(rng, mc_samples)
+    mesh, info, parts_P = C.combine(parts, op)
+    dx = (vol / n_target) ** (1.0 / 3.0)
+    geom = _make_geom(mesh, dx, k)
+    geom.csg = info
+    b = _Builder()
+    lo, hi = mesh.bbox()
+    axes = [np.arange(lo[a] + 0.5 * dx, hi[a], dx) for a in range(3)]
+    for x in axes[0]:   # one x column at a time to bound memory
+        g = np.stack(np.meshgrid([x], axes[1], axes[2], indexing="ij"), -1).reshape(-1, 3)
+        g = g + rng.uniform(-jitter, jitter, g.shape) * dx
+        b.add(g[C.inside_with_margin(op, parts_P, g, 0.5 * dx)], VOLUME)
+    for q, part in enumerate(parts):
+        bp = _Builder()
+        _surface_particles_planar(bp, part, dx, rng, jitter)
+        if not bp.pos:
+            continue
+        pts = np.concatenate(bp.pos, 0)
+        own = np.concatenate(bp.owner)
+        keep = C.on_boundary_with_margin(op, parts_P, q, pts, 0.5 * dx)
+        b.add(pts[keep], SURFACE, own[keep] + info.part_tri_begin[q])
+    _feature_particles(b, mesh, dx, rng, jitter)
+    if len(mesh.singular):
+        b.add(mesh.singular, SINGULAR, mesh.singular_vert)
+    desc = {"op": "union" if op == C.UNION else "difference", "parts": len(parts),
+            "kinds": ["box" if len(p.tri) == 12 else "cylinder" for p in parts], "volume": vol}
+    return geom, b, desc
+
+
 def batch_workload(n_geom=64, n_min=5e3, n_max=5e5, seed=4000, jitter=0.3, k=2,
-                   move_mask=ALL_MOVING, name=None) -> Workload:
-    """A batch of independent solids relaxed together: geometry b uses PCG64
-    seed `seed + b`, a log-uniform target count in [n_min, n_max]. The
+                   move_mask=ALL_MOVING, name=None, mc_samples=1_000_000) -> Workload:
+    """A batch of independent Boolean assemblies relaxed together (section
+    3.2.3 assemblies; assembly_geometry): geometry b uses PCG64 seed
+    `seed + b` and a log-uniform target count in [n_min, n_max]. The
     geometries do not interact (each has its own cell grid and facets)."""
+    parts, descs, targets = [], [], []
+    for g in range(n_geom):
+        rng = np.random.Generator(np.random.PCG64(seed + g))
+        n_t = float(np.exp(rng.uniform(np.log(n_min), np.log(n_max))))
+        geom, b, desc = assembly_geometry(rng, n_t, jitter, k, mc_samples)
+        parts.append((geom, b))
+        descs.append(desc)
+        targets.append(n_t)
+    return _finish(name or f"batch{n_geom}_seed{seed}", parts, move_mask, seed,
+                   {"assemblies": descs, "targets": targets})
+
+
+def solid_batch_workload(n_geom=64, n_min=5e3, n_max=5e5, seed=4000, jitter=0.3, k=2,
+                         move_mask=ALL_MOVING, name=None) -> Workload:
+    """A batch of single convex solids (one box or cylinder per geometry)."""
     parts, kinds, targets = [], [], []
     for g in range(n_geom):
         rng = np.random.Generator(np.random.PCG64(seed + g))
@@ -593,7 +648,7 @@ def batch_workload(n_geom=64, n_min=5e3, n_max=5e5, seed=4000, jitter=0.3, k=2,
         parts.append((geom, b))
         kinds.append(kind)
         targets.append(n_t)
-    return _finish(name or f"batch{n_geom}_seed{seed}", parts, move_mask, seed,
+    return _finish(name or f"solids{n_geom}_seed{seed}", parts, move_mask, seed,
                    {"kinds": kinds, "targets": targets})
 
 

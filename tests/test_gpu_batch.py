@@ -3,7 +3,8 @@
   * a batch relaxed in one launch per kernel equals the same geometries
     relaxed one at a time, bitwise (no interaction across geometries, amax
     per geometry, fixed summation order)
-  * one step of a batch matches the CPU oracle (1e-5 bar)
+  * one step of a batch of Boolean assemblies matches the CPU oracle (1e-5
+    bar), also with particles forced to revert
   * graph replays equal eager iterations bitwise, with eager work between
     replays
 """
@@ -57,19 +58,15 @@ def test_batch_equals_separate_runs_bitwise():
 
 
 def test_batch_one_step_matches_oracle():
-    wl = W.batch_workload(n_geom=3, n_min=1e3, n_max=3e3, seed=4200)
+    """One step of a batch of Boolean assemblies (unions and differences of
+    2-6 boxes and cylinders) against the brute-force oracle."""
+    wl = W.batch_workload(n_geom=4, n_min=1e3, n_max=3e3, seed=4212)
+    assert {a["op"] for a in wl.meta["assemblies"]} == {"union", "difference"}
     r = _relaxer(wl)
     r.step()
-    pos, owner, fs, fu = r.host_state()
     ref = ostep.relax_step(wl)
-    ok = ~ref.margin
-    x = ref.pos32.astype(np.float64)
-    dx = np.array([g.dx for g in wl.geoms])[wl.gid]
-    tol = 1e-5 * np.maximum(np.abs(x).max(1), dx)
-    err = np.abs(pos.astype(np.float64) - x).max(1)
-    assert not np.any(ok & (err > tol)), float(err[ok].max())
-    s = ok & (wl.tag == synth.SURFACE)
-    assert np.array_equal(owner[s], ref.owner[s])
+    _compare_one_step(wl, r, ref)
+    assert r.read_status() == 0
 
 
 def test_graph_replay_equals_eager_bitwise():
@@ -148,3 +145,43 @@ def test_force_launch_shape_does_not_change_results(k):
     from paper_2501_03056_amd import _lib
     with pytest.raises(_lib.FppgError):
         r.ctx.set_launch(64, True)
+
+
+def _compare_one_step(wl, r, ref):
+    pos, owner, fs, fu = r.host_state()
+    mov = (wl.move_mask >> wl.tag) & 1 == 1
+    ok = ~ref.margin
+    assert int(np.sum(ref.margin & mov)) <= max(1, 1e-3 * mov.sum())
+    x = ref.pos32.astype(np.float64)
+    dx = np.array([g.dx for g in wl.geoms])[wl.gid]
+    tol = 1e-5 * np.maximum(np.abs(x).max(1), dx)
+    err = np.abs(pos.astype(np.float64) - x).max(1)
+    assert not np.any(ok & (err > tol)), float(err[ok].max())
+    s = ok & (wl.tag == synth.SURFACE)
+    assert np.array_equal(owner[s], ref.owner[s])
+    f = np.nonzero(ok & (wl.tag == synth.FEATURE))[0]
+    if len(f):
+        assert np.array_equal(fs[wl.owner[f]], ref.feat_seg[wl.owner[f]])
+    c = r.counters.cpu().numpy()
+    for k, tg in ((0, synth.SURFACE), (1, synth.FEATURE), (2, synth.VOLUME)):
+        m = mov & (wl.tag == tg)
+        assert abs(int(c[k]) - int(np.sum(ref.reverted & m))) <= int(np.sum(ref.margin & m)), (tg, int(c[k]))
+
+
+@pytest.mark.parametrize("g", [0, 1, 2])
+def test_assembly_with_forced_reverts_matches_oracle(g):
+    """One Boolean assembly of the batch (union or difference of boxes and
+    cylinders) with particles placed where the step must revert: feature
+    particles at the starts of the clipped open lines, surface particles off
+    their facets, volume particles at the skin pushed out by the volume. The
+    step, its reverts and the assembly's surface rule match the oracle."""
+    wl = W.forced_reverts(W.split_geometry(W.batch_workload(n_geom=3, n_min=2e3, n_max=6e3, seed=4300), g),
+                          seed=g)
+    print(f"[batch] assembly {g}: {wl.n} particles, {wl.meta}", flush=True)
+    r = _relaxer(wl)
+    r.step()
+    ref = ostep.relax_step(wl)
+    mov = (wl.move_mask >> wl.tag) & 1 == 1
+    assert ref.reverted[mov].sum() >= 3
+    _compare_one_step(wl, r, ref)
+    assert r.read_status() == 0
