@@ -148,7 +148,7 @@ typedef struct {
      relaxation treats an assembly. */
   int32_t csg_op;
   int32_t n_part;
-  const int32_t* part_tri_begin;          /* [n_part + 1]; may be NULL if csg_op = 0 */
+  const int32_t* part_tri_begin;          /* [n_part + 1], 1 <= n_part <= 8; may be NULL if csg_op = 0 */
 } fppg_geom_desc;
 
 #define FPPG_CSG_NONE       0
@@ -200,6 +200,19 @@ fppg_status fppg_profile_read(fppg_ctx* ctx, double* ms /*[FPPG_NPHASES]*/, int6
  * Errors: FPPG_E_ARG for other values.
  */
 fppg_status fppg_set_launch(fppg_ctx* ctx, int32_t force_block, int32_t xcd_remap);
+
+/*
+ * Schedule of the force kernel of fppg_relax_step, chosen by the autotuner:
+ * persistent = 0 launches one block per chunk of force_block receivers;
+ * persistent = 1 launches as many blocks as fit on the device at once, each
+ * taking chunks by tickets: the blocks of XCD x (workgroup b runs on XCD b %
+ * 8) first take the contiguous range of chunks that xcd_remap would give x,
+ * then the other XCDs' leftovers. The ticket counters are cleared by a small
+ * kernel before every launch (stream-ordered; graph-capturable) and live in
+ * the context, so calls on one context must not overlap. No result depends
+ * on the schedule (each chunk is computed the same way). Errors: FPPG_E_ARG.
+ */
+fppg_status fppg_set_schedule(fppg_ctx* ctx, int32_t persistent);
 
 /* ---- geometry ----------------------------------------------------------------------------- */
 
@@ -315,13 +328,16 @@ fppg_status fppg_relax_step(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
  * Apply the displacement and project back onto the geometry (section 3.3.3).
  * One lane per particle in two kernels: a streaming pass applies the volume
  * rule and queues the surface and feature particles in the workspace, a
- * second pass projects the queued particles.
+ * second pass projects the queued particles (and a third searches the few
+ * surface particles whose own search cell accepts no facet).
  *  surface: y = x + dr (FP64); among the facets registered in the 27 search
  *           cells around y, the plane foot p = y - d n with all barycentric
  *           coordinates >= 0 and |d| <= R and the smallest |d| (ties: lowest
  *           facet) wins: pos = fl32(p), owner = that facet; none: pos stays x
  *           (revert). The own cell is searched first and a neighbouring cell
- *           only if it comes within the best |d| found (same result).
+ *           only if it comes within the best |d| found (same result); a
+ *           particle whose own cell accepts no facet has its 27 cells searched
+ *           side by side by one wavefront in a further kernel (same result).
  *  feature: u' = u + du walked along the polyline of segment feat_seg[slot],
  *           carrying into neighbouring segments; leaving an open line
  *           reverts, a loop wraps; pos = fl32(p0 + u' t), feat_seg/feat_u
@@ -336,10 +352,9 @@ fppg_status fppg_relax_step(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
  *           plane test is < 0): union, p in no other part's interior;
  *           difference, for k = 0 p in no cut part's interior, for a cut part
  *           p in the closure of part 0 and in no other cut part's interior.
- *           A volume move whose segment's search cells hold facets is reverted
- *           iff y is outside the assembly (union: in no part's interior;
- *           difference: not in part 0's interior, or in a cut part's closure);
- *           elsewhere it is accepted.
+ *           A volume move is reverted iff its segment meets a facet at a point
+ *           of the assembly's boundary (the same test on the crossing point):
+ *           crossing a part's face inside the assembly is no revert.
  * pos [n*4] in: positions x, out: new positions; owner [n] in/out;
  * disp [n*4] from fppg_relax_step; feat_seg/feat_u [n_feat] in/out (may be
  * NULL if n_feat = 0); counters [FPPG_NCOUNTERS] int64 on the device,

@@ -55,6 +55,7 @@ _SIGS = {
                                c_size_t, _P]),
     "fppg_moving_list": (c_int32, [_P, _P, c_int64, _P, c_uint32, _P, _P, _P, c_size_t, _P]),
     "fppg_set_launch": (c_int32, [_P, c_int32, c_int32]),
+    "fppg_set_schedule": (c_int32, [_P, c_int32]),
     "fppg_tier_partition": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, _P, _P, c_uint32, _P, _P, c_size_t, _P]),
     "fppg_volume_layers": (c_int32, [_P, _P, c_int64, _P, c_double, _P, _P]),
     "fppg_generate": (c_int32, [_P, _P, c_int32, _P, c_int32, c_double, _P, _P, _P, _P, _P, c_int64, _P, _P]),

@@ -48,6 +48,7 @@ WsLayout ws_layout(const Geom* g, int64_t n) {
   L.proj_vrev = o;  o += up256(4 * nvb);
   L.proj_part = o;  o += up256(16 * nvb);   // one per k_project_heavy block (at most one per volume block)
   L.proj_queue = o; o += up256(4 * (N + kBlock));   // every entry lies below (launch blocks) * kBlock
+  L.proj_hard = o;  o += up256(4 * (N + 1));          // count, then the particles the parallel search takes
   L.proj_end = o;
   // relax_energy: one FP64 partial per block of kBlock; vec_dot: kDotPartials
   L.reduce_end = up256(8 * std::max<size_t>((N + kBlock - 1) / kBlock + 1, kDotPartials));
@@ -116,7 +117,7 @@ struct SearchGrid {
 // relative margin so that a point on a facet whose cell index is computed with
 // rounding still finds the facet in the computed cell.
 static fppg_status build_search_grid(fppg_ctx* ctx, const fppg_geom_desc& d, int32_t tri_begin,
-                                     SearchGrid& sg) {
+                                     SearchGrid& sg, const std::vector<uint8_t>& facet_class) {
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   for (int32_t v = 0; v < d.n_vert; ++v)
     for (int q = 0; q < 3; ++q) {
@@ -137,6 +138,7 @@ static fppg_status build_search_grid(fppg_ctx* ctx, const fppg_geom_desc& d, int
   const double pad = 1e-6 * sg.cell;
   std::vector<std::pair<int64_t, int32_t>> reg;
   for (int32_t t = 0; t < d.n_tri; ++t) {
+    if (!facet_class.empty() && facet_class[t] == 0) continue;   // an assembly's facet never on its boundary
     const double* P[3] = {d.vert + 3 * d.tri[3 * t], d.vert + 3 * d.tri[3 * t + 1], d.vert + 3 * d.tri[3 * t + 2]};
     int32_t c0[3], c1[3];
     for (int q = 0; q < 3; ++q) {
@@ -190,6 +192,7 @@ static void free_geom(Geom* g) {
   hipFree(g->d_facet_part);
   hipFree(g->d_part);
   hipFree(g->d_plane);
+  hipFree(g->d_facet_mask);
 }
 
 // Planes of the convex parts of an assembly (section 3.2.3): every facet of a
@@ -198,10 +201,13 @@ static void free_geom(Geom* g) {
 // every vertex of its facets within 1e-9 (1 + size) of the inner side of each
 // of its planes.
 static fppg_status build_parts(fppg_ctx* ctx, const fppg_geom_desc& d, int32_t g, int32_t tri_off,
-                               std::vector<int32_t>& facet_part, std::vector<int2>& parts,
-                               std::vector<double4>& planes, GeomDev& G) {
+                               std::vector<int32_t>& facet_part, std::vector<PartDev>& parts,
+                               std::vector<double4>& planes, GeomDev& G, std::vector<uint8_t>& facet_class,
+                               std::vector<uint8_t>& facet_mask) {
   G.csg_op = d.csg_op;
   G.part_begin_csg = G.part_end_csg = int32_t(parts.size());
+  facet_class.clear();
+  facet_mask.insert(facet_mask.end(), size_t(d.n_tri), uint8_t(0));
   if (d.csg_op == FPPG_CSG_NONE) {
     facet_part.insert(facet_part.end(), size_t(d.n_tri), -1);
     return FPPG_OK;
@@ -209,13 +215,19 @@ static fppg_status build_parts(fppg_ctx* ctx, const fppg_geom_desc& d, int32_t g
   const std::string where = "geometry " + std::to_string(g) + ": ";
   if (d.csg_op != FPPG_CSG_UNION && d.csg_op != FPPG_CSG_DIFFERENCE)
     return fail(ctx, FPPG_E_ARG, where + "csg_op must be 0, 1 or 2");
-  if (d.n_part < 1 || !d.part_tri_begin || d.part_tri_begin[0] != 0 || d.part_tri_begin[d.n_part] != d.n_tri)
-    return fail(ctx, FPPG_E_ARG, where + "part_tri_begin must run from 0 to n_tri over n_part >= 1 parts");
+  if (d.n_part < 1 || d.n_part > 8 || !d.part_tri_begin || d.part_tri_begin[0] != 0 ||
+      d.part_tri_begin[d.n_part] != d.n_tri)
+    return fail(ctx, FPPG_E_ARG, where + "part_tri_begin must run from 0 to n_tri over 1 to 8 parts");
   for (int32_t k = 0; k < d.n_part; ++k) {
     const int32_t b = d.part_tri_begin[k], e = d.part_tri_begin[k + 1];
     if (e <= b) return fail(ctx, FPPG_E_ARG, where + "every part needs a facet (part_tri_begin increasing)");
     const int32_t p0 = int32_t(planes.size());
     double lo = INFINITY, hi = -INFINITY;
+    PartDev pd;
+    for (int q = 0; q < 3; ++q) {
+      pd.lo[q] = INFINITY;
+      pd.hi[q] = -INFINITY;
+    }
     for (int32_t t = b; t < e; ++t) {
       const double* A = d.vert + 3 * d.tri[3 * t];
       const double* B = d.vert + 3 * d.tri[3 * t + 1];
@@ -233,6 +245,8 @@ static fppg_status build_parts(fppg_ctx* ctx, const fppg_geom_desc& d, int32_t g
       for (int q = 0; q < 3; ++q) {
         lo = std::min(lo, std::min(A[q], std::min(B[q], C[q])));
         hi = std::max(hi, std::max(A[q], std::max(B[q], C[q])));
+        pd.lo[q] = std::min(pd.lo[q], std::min(A[q], std::min(B[q], C[q])));
+        pd.hi[q] = std::max(pd.hi[q], std::max(A[q], std::max(B[q], C[q])));
       }
       facet_part.push_back(int32_t(parts.size()));
     }
@@ -244,9 +258,66 @@ static fppg_status build_parts(fppg_ctx* ctx, const fppg_geom_desc& d, int32_t g
           if (planes[j].x * V[0] + planes[j].y * V[1] + planes[j].z * V[2] - planes[j].w > tol)
             return fail(ctx, FPPG_E_ARG, where + "part " + std::to_string(k) + " is not convex");
       }
-    parts.push_back(make_int2(p0, int32_t(planes.size())));
+    pd.plane_begin = p0;
+    pd.plane_end = int32_t(planes.size());
+    for (int q = 0; q < 3; ++q) {   // widened so that the box never decides what the planes would not
+      pd.lo[q] -= 1e-12 * (1.0 + std::fabs(pd.lo[q]));
+      pd.hi[q] += 1e-12 * (1.0 + std::fabs(pd.hi[q]));
+    }
+    parts.push_back(pd);
   }
   G.part_end_csg = int32_t(parts.size());
+  // Classify every facet against the other parts once, so that the per-point
+  // test is needed only where a facet crosses another part's surface. With
+  // V the three corners: "V strictly inside part j" (every plane < -tol) holds
+  // for the whole facet (convexity); "a plane of j has every corner >= tol"
+  // separates the whole facet from j. A facet that lies in a part it must
+  // avoid (or outside part 0 for a cut part) is never on the boundary and is
+  // left out of the facet search grid; one that is separated from every part
+  // it must avoid (and inside part 0 for a cut part) is always on it and gets
+  // part -1; any other keeps its part index for the per-point test.
+  const int32_t pb = G.part_begin_csg;
+  auto side = [&](int32_t j, const double* const V[3], double tol) {   // -1 all inside, +1 separated, 0 mixed
+    const PartDev& r = parts[j];
+    bool inside = true;
+    for (int32_t q = r.plane_begin; q < r.plane_end; ++q) {
+      const double4 P = planes[q];
+      double mx = -INFINITY, mn = INFINITY;
+      for (int c = 0; c < 3; ++c) {
+        const double v = P.x * V[c][0] + P.y * V[c][1] + P.z * V[c][2] - P.w;
+        mx = std::max(mx, v);
+        mn = std::min(mn, v);
+      }
+      if (mn >= tol) return 1;
+      if (mx >= -tol) inside = false;
+    }
+    return inside ? -1 : 0;
+  };
+  for (int32_t k = 0; k < d.n_part; ++k) {
+    for (int32_t t = d.part_tri_begin[k]; t < d.part_tri_begin[k + 1]; ++t) {
+      const double* V[3] = {d.vert + 3 * d.tri[3 * t], d.vert + 3 * d.tri[3 * t + 1], d.vert + 3 * d.tri[3 * t + 2]};
+      double ext = 0.0;
+      for (int q = 0; q < 3; ++q) ext = std::max(ext, std::fabs(V[0][q]) + std::fabs(V[1][q]) + std::fabs(V[2][q]));
+      const double tol = 1e-12 * (1.0 + ext);
+      int cls = 1;   // 0 never, 1 always, 2 per point
+      uint8_t mask = 0;   // the parts a point of the facet must be tested against
+      for (int32_t j = 0; j < d.n_part && cls != 0; ++j) {
+        if (j == k) continue;
+        const int sd = side(pb + j, V, tol);
+        if (d.csg_op == FPPG_CSG_DIFFERENCE && j == 0 && k > 0) {   // must lie in part 0
+          if (sd == 1) cls = 0;
+          else if (sd == 0) cls = 2;
+        } else {                                                   // must avoid part j
+          if (sd == -1) cls = 0;
+          else if (sd == 0) cls = 2;
+        }
+        if (sd == 0) mask |= uint8_t(1u << j);
+      }
+      facet_class.push_back(uint8_t(cls));
+      facet_mask[facet_mask.size() - size_t(d.n_tri) + size_t(t)] = cls == 2 ? mask : 0;
+      if (cls != 2) facet_part[facet_part.size() - size_t(d.n_tri) + size_t(t)] = -1;
+    }
+  }
   (void)tri_off;
   return FPPG_OK;
 }
@@ -265,8 +336,10 @@ static fppg_status geom_create(fppg_ctx* ctx, const fppg_geom_desc* descs, int32
   std::vector<int4> tri_vert;
   std::vector<int2> seg_vert;
   std::vector<int32_t> facet_part;
-  std::vector<int2> parts;
+  std::vector<PartDev> parts;
   std::vector<double4> planes;
+  std::vector<uint8_t> facet_class;   // of the current geometry's facets (assemblies only)
+  std::vector<uint8_t> facet_mask;
   int32_t vert_off = 0;
   std::vector<int32_t> tg_start;   // global
   std::vector<int32_t> tg_tri;
@@ -337,7 +410,8 @@ static fppg_status geom_create(fppg_ctx* ctx, const fppg_geom_desc* descs, int32
     }
     // parts of a Boolean assembly
     {
-      const fppg_status pst = build_parts(ctx, d, g, tri_off, facet_part, parts, planes, G);
+      const fppg_status pst = build_parts(ctx, d, g, tri_off, facet_part, parts, planes, G, facet_class,
+                                          facet_mask);
       if (pst != FPPG_OK) return pst;
     }
     // feature segments
@@ -376,7 +450,7 @@ static fppg_status geom_create(fppg_ctx* ctx, const fppg_geom_desc* descs, int32
     G.seg_end = seg_off;
     // facet search grid
     SearchGrid sg;
-    fppg_status st = build_search_grid(ctx, d, tri_off, sg);
+    fppg_status st = build_search_grid(ctx, d, tri_off, sg, facet_class);
     if (st != FPPG_OK) return st;
     tri_off += d.n_tri;
     vert_off += d.n_vert;
@@ -420,7 +494,8 @@ static fppg_status geom_create(fppg_ctx* ctx, const fppg_geom_desc* descs, int32
       (st = upload(ctx, &geo->d_tg_start, tg_start)) != FPPG_OK ||
       (st = upload(ctx, &geo->d_tg_tri, tg_tri)) != FPPG_OK || (st = upload(ctx, &geo->d_tg_flag, tg_flag)) != FPPG_OK ||
       (st = upload(ctx, &geo->d_facet_part, facet_part)) != FPPG_OK || (st = upload(ctx, &geo->d_part, parts)) != FPPG_OK ||
-      (st = upload(ctx, &geo->d_plane, planes)) != FPPG_OK) {
+      (st = upload(ctx, &geo->d_plane, planes)) != FPPG_OK ||
+      (st = upload(ctx, &geo->d_facet_mask, facet_mask)) != FPPG_OK) {
     free_geom(geo);
     delete static_cast<fppg_geom*>(geo);
     return st;
@@ -472,13 +547,16 @@ fppg_status fppg_create(int32_t device, fppg_ctx** out) {
   if (!ctx) return FPPG_E_CAPACITY;
   ctx->device = device;
   if (hipMalloc(reinterpret_cast<void**>(&ctx->d_status), 64) != hipSuccess ||
-      hipMemset(ctx->d_status, 0, 64) != hipSuccess) {
+      hipMemset(ctx->d_status, 0, 64) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&ctx->d_tickets), 64) != hipSuccess) {
+    hipFree(ctx->d_status);
     delete ctx;
     return FPPG_E_HIP;
   }
   const fppg_status st = init_dot_scratch(ctx);   // the device is current here
   if (st != FPPG_OK) {
     hipFree(ctx->d_status);
+    hipFree(ctx->d_tickets);
     delete ctx;
     return st;
   }
@@ -503,6 +581,7 @@ void fppg_destroy(fppg_ctx* ctx) {
   if (!ctx) return;
   destroy_events(ctx);
   hipFree(ctx->d_status);
+  hipFree(ctx->d_tickets);
   delete ctx;
 }
 

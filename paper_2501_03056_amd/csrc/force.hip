@@ -10,6 +10,8 @@
 // it, and the accumulations use explicit fmaf.
 #include "stencil.h"
 
+#include <algorithm>
+
 namespace fppg {
 
 __global__ void k_zero_f32(float* __restrict__ a, int n) {
@@ -40,15 +42,14 @@ __device__ __forceinline__ void add_pair(const float4 p, const float4 q, float r
   if (COUNT) cnt += src ? 1.0f : 0.0f;
 }
 
-// B: threads per block; remap: blocks of each XCD take one contiguous range of
-// receivers (xcd_chunk). Neither changes a result (per-lane sums, max-reduced amax).
+// The B receivers of chunk blk (launch slots blk * B ...): forces, and the
+// chunk's contribution to amax. Called by every thread of a block.
 template <int K, bool COUNT, int B>
-__global__ __launch_bounds__(B) void k_force(const float4* __restrict__ pos, int n,
-                                             const int* __restrict__ cs, const GeomDev* __restrict__ geoms,
-                                             int n_geom, uint32_t move_mask, float4* __restrict__ accel,
-                                             unsigned* __restrict__ amax_bits, uint32_t* status,
-                                             const int* __restrict__ list, int n_list, bool remap) {
-  const int blk = remap ? xcd_chunk(blockIdx.x, gridDim.x) : int(blockIdx.x);
+__device__ __forceinline__ void force_chunk(int blk, const float4* __restrict__ pos, int n,
+                                            const int* __restrict__ cs, const GeomDev* __restrict__ geoms,
+                                            int n_geom, uint32_t move_mask, float4* __restrict__ accel,
+                                            unsigned* __restrict__ amax_bits, uint32_t* status,
+                                            const int* __restrict__ list, int n_list) {
   const int i = listed(blk * B + threadIdx.x, n, list, n_list);
   float anorm = 0.0f;
   int g = 0;
@@ -116,6 +117,65 @@ __global__ __launch_bounds__(B) void k_force(const float4* __restrict__ pos, int
       atomicMax(&amax_bits[s_geo[w]], __float_as_uint(mm));
     }
   }
+  __syncthreads();   // s_max / s_geo are reused by the block's next chunk
+}
+
+// One block per chunk of B receivers. remap: the blocks of each XCD take one
+// contiguous range of chunks (xcd_chunk). Neither changes a result (per-lane
+// sums, max-reduced amax).
+template <int K, bool COUNT, int B>
+__global__ __launch_bounds__(B) void k_force(const float4* __restrict__ pos, int n,
+                                             const int* __restrict__ cs, const GeomDev* __restrict__ geoms,
+                                             int n_geom, uint32_t move_mask, float4* __restrict__ accel,
+                                             unsigned* __restrict__ amax_bits, uint32_t* status,
+                                             const int* __restrict__ list, int n_list, bool remap) {
+  const int blk = remap ? xcd_chunk(blockIdx.x, gridDim.x) : int(blockIdx.x);
+  force_chunk<K, COUNT, B>(blk, pos, n, cs, geoms, n_geom, move_mask, accel, amax_bits, status, list, n_list);
+}
+
+// Persistent schedule: a grid of resident blocks takes chunks by tickets.
+// Block b starts on the ticket counter of XCD b % 8 (workgroups are dealt to
+// the XCDs round-robin), which hands out that XCD's contiguous range of
+// chunks, as xcd_chunk splits them; a block whose range is used up takes
+// tickets from the next XCD's range, and so on, and leaves once all eight
+// are used up (every block exits after at most nchunks + 8 ticket draws in
+// all). tickets [8] must be zero at launch. Each chunk is processed exactly as
+// by k_force, so the results are the same bit for bit.
+template <int K, bool COUNT, int B>
+__global__ __launch_bounds__(B) void k_force_tickets(const float4* __restrict__ pos, int n,
+                                                     const int* __restrict__ cs, const GeomDev* __restrict__ geoms,
+                                                     int n_geom, uint32_t move_mask, float4* __restrict__ accel,
+                                                     unsigned* __restrict__ amax_bits, uint32_t* status,
+                                                     const int* __restrict__ list, int n_list, int nchunks,
+                                                     int* __restrict__ tickets) {
+  __shared__ int s_chunk;
+  const int q = nchunks / kNumXcd, r = nchunks % kNumXcd;
+  const int home = int(blockIdx.x) % kNumXcd;
+  int step = 0;   // ranges used up so far (thread 0)
+  for (;;) {
+    if (threadIdx.x == 0) {
+      int c = -1;
+      while (step < kNumXcd) {
+        const int x = (home + step) % kNumXcd;
+        const int t = atomicAdd(&tickets[x], 1);
+        if (t < q + (x < r ? 1 : 0)) {
+          c = x * q + min(x, r) + t;
+          break;
+        }
+        ++step;
+      }
+      s_chunk = c;
+    }
+    __syncthreads();
+    const int c = s_chunk;
+    __syncthreads();
+    if (c < 0) break;
+    force_chunk<K, COUNT, B>(c, pos, n, cs, geoms, n_geom, move_mask, accel, amax_bits, status, list, n_list);
+  }
+}
+
+__global__ void k_zero_tickets(int* __restrict__ t) {
+  if (threadIdx.x < kNumXcd) t[threadIdx.x] = 0;
 }
 
 // ---- displacement (Eq. 22-25) ------------------------------------------------------------
@@ -172,31 +232,56 @@ __global__ __launch_bounds__(kBlock) void k_update(const float4* __restrict__ po
 
 static inline int grid_for(int64_t n) { return int((n + kBlock - 1) / kBlock); }
 
+// Launch of the force kernel in the context's schedule: one block per chunk,
+// or the persistent ticket schedule with as many resident blocks as fit.
+struct ForceLaunch {
+  int block;
+  bool remap, persistent;
+  int* tickets;
+  fppg_ctx* ctx;   // occupancy of the persistent kernel, queried once per context
+};
+
 template <int K, bool COUNT, int B>
-static void launch_force_b(int nr, bool remap, hipStream_t s, const float4* p4, int n, const int* cs,
+static void launch_force_b(const ForceLaunch& fl, int nr, hipStream_t s, const float4* p4, int n, const int* cs,
                            const GeomDev* g, int n_geom, uint32_t mm, float4* acc, unsigned* ab, uint32_t* st,
                            const int* list) {
-  k_force<K, COUNT, B><<<(nr + B - 1) / B, B, 0, s>>>(p4, n, cs, g, n_geom, mm, acc, ab, st, list, nr, remap);
+  const int nchunks = (nr + B - 1) / B;
+  if (!fl.persistent) {
+    k_force<K, COUNT, B><<<nchunks, B, 0, s>>>(p4, n, cs, g, n_geom, mm, acc, ab, st, list, nr, fl.remap);
+    return;
+  }
+  int& per_cu = fl.ctx->resident[K - 1][B == 128 ? 0 : (B == 256 ? 1 : 2)];
+  if (!per_cu) {   // queried outside graph capture too: host calls only, no stream work
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_force_tickets<K, COUNT, B>, B, 0) != hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    hipDeviceProp_t prop;
+    fl.ctx->num_cu = hipGetDeviceProperties(&prop, fl.ctx->device) == hipSuccess ? prop.multiProcessorCount : 256;
+  }
+  const int grid = std::max(1, std::min(nchunks, fl.ctx->num_cu * per_cu));
+  k_zero_tickets<<<1, 64, 0, s>>>(fl.tickets);
+  k_force_tickets<K, COUNT, B><<<grid, B, 0, s>>>(p4, n, cs, g, n_geom, mm, acc, ab, st, list, nr, nchunks,
+                                                  fl.tickets);
 }
 
 template <int K, bool COUNT>
-static void launch_force_k(int block, int nr, bool remap, hipStream_t s, const float4* p4, int n, const int* cs,
+static void launch_force_k(const ForceLaunch& fl, int nr, hipStream_t s, const float4* p4, int n, const int* cs,
                            const GeomDev* g, int n_geom, uint32_t mm, float4* acc, unsigned* ab, uint32_t* st,
                            const int* list) {
-  if (block == 128) launch_force_b<K, COUNT, 128>(nr, remap, s, p4, n, cs, g, n_geom, mm, acc, ab, st, list);
-  else if (block == 512) launch_force_b<K, COUNT, 512>(nr, remap, s, p4, n, cs, g, n_geom, mm, acc, ab, st, list);
-  else launch_force_b<K, COUNT, 256>(nr, remap, s, p4, n, cs, g, n_geom, mm, acc, ab, st, list);
+  if (fl.block == 128) launch_force_b<K, COUNT, 128>(fl, nr, s, p4, n, cs, g, n_geom, mm, acc, ab, st, list);
+  else if (fl.block == 512) launch_force_b<K, COUNT, 512>(fl, nr, s, p4, n, cs, g, n_geom, mm, acc, ab, st, list);
+  else launch_force_b<K, COUNT, 256>(fl, nr, s, p4, n, cs, g, n_geom, mm, acc, ab, st, list);
 }
 
-static void launch_force(int k, bool count, int block, bool remap, int nr, hipStream_t s, const float4* p4, int n,
+static void launch_force(int k, bool count, const ForceLaunch& fl, int nr, hipStream_t s, const float4* p4, int n,
                          const int* cs, const GeomDev* g, int n_geom, uint32_t mm, float4* acc, unsigned* ab,
                          uint32_t* st, const int* list) {
   if (k == 1) {
-    if (count) launch_force_k<1, true>(block, nr, remap, s, p4, n, cs, g, n_geom, mm, acc, ab, st, list);
-    else launch_force_k<1, false>(block, nr, remap, s, p4, n, cs, g, n_geom, mm, acc, ab, st, list);
+    if (count) launch_force_k<1, true>(fl, nr, s, p4, n, cs, g, n_geom, mm, acc, ab, st, list);
+    else launch_force_k<1, false>(fl, nr, s, p4, n, cs, g, n_geom, mm, acc, ab, st, list);
   } else {
-    if (count) launch_force_k<2, true>(block, nr, remap, s, p4, n, cs, g, n_geom, mm, acc, ab, st, list);
-    else launch_force_k<2, false>(block, nr, remap, s, p4, n, cs, g, n_geom, mm, acc, ab, st, list);
+    if (count) launch_force_k<2, true>(fl, nr, s, p4, n, cs, g, n_geom, mm, acc, ab, st, list);
+    else launch_force_k<2, false>(fl, nr, s, p4, n, cs, g, n_geom, mm, acc, ab, st, list);
   }
 }
 
@@ -241,8 +326,9 @@ extern "C" fppg_status fppg_relax_step(fppg_ctx* ctx, const fppg_geom* geom, int
     unsigned* ab = reinterpret_cast<unsigned*>(amax);
     {
     PhaseTimer timer(ctx, 1, s);
-    launch_force(geom->k, count, ctx->force_block, ctx->xcd_remap, nr, s, p4, ni, cell_start, geom->d_geom,
-                 geom->n_geom, move_mask, acc, ab, ctx->d_status, list);
+    const ForceLaunch fl{ctx->force_block, ctx->xcd_remap, ctx->persistent, ctx->d_tickets, ctx};
+    launch_force(geom->k, count, fl, nr, s, p4, ni, cell_start, geom->d_geom, geom->n_geom, move_mask, acc, ab,
+                 ctx->d_status, list);
     }
     PhaseTimer timer(ctx, 2, s);
     k_update<<<grid_for(nr), kBlock, 0, s>>>(p4, acc, owner, feat_seg, ni, n_feat, int(geom->n_tri), int(geom->n_seg),
@@ -260,5 +346,12 @@ extern "C" fppg_status fppg_set_launch(fppg_ctx* ctx, int32_t force_block, int32
   if (xcd_remap != 0 && xcd_remap != 1) return fail(ctx, FPPG_E_ARG, "xcd_remap must be 0 or 1");
   ctx->force_block = force_block;
   ctx->xcd_remap = xcd_remap != 0;
+  return FPPG_OK;
+}
+
+extern "C" fppg_status fppg_set_schedule(fppg_ctx* ctx, int32_t persistent) {
+  if (!ctx) return FPPG_E_ARG;
+  if (persistent != 0 && persistent != 1) return fail(ctx, FPPG_E_ARG, "persistent must be 0 or 1");
+  ctx->persistent = persistent != 0;
   return FPPG_OK;
 }

@@ -38,11 +38,19 @@ struct GeomDev {
   int32_t part_begin_csg, part_end_csg;   // global part range of an assembly
 };
 
-// Boolean assemblies: per global facet its part (-1: not in an assembly), per
-// part its plane range, planes (n, d) with n.x - d < 0 inside the part.
+// Boolean assemblies: per global facet its part where a point test is needed
+// (-1: not in an assembly, or a facet wholly on the assembly's boundary; a
+// facet never on it is not in the facet search grid), per part its plane
+// range, planes (n, d) with n.x - d < 0 inside the part.
+struct PartDev {
+  int32_t plane_begin, plane_end;   // range in the plane array
+  double lo[3], hi[3];              // bounding box of the part's vertices
+};
+
 struct CsgDev {
   const int* facet_part = nullptr;
-  const int2* part = nullptr;
+  const uint8_t* facet_mask = nullptr;   // per facet: bit j = the facet crosses part (first part + j) of its assembly
+  const PartDev* part = nullptr;
   const double4* plane = nullptr;
 };
 
@@ -88,10 +96,11 @@ struct Geom {
   int32_t* d_tg_tri = nullptr;      // [tg_entries] global facet ids
   uint8_t* d_tg_flag = nullptr;     // [tg_cells]
   int32_t* d_facet_part = nullptr;  // [n_tri] part of each facet in an assembly, -1 otherwise
-  int2* d_part = nullptr;           // [n_parts] plane range of each part
+  PartDev* d_part = nullptr;        // [n_parts] plane range and bounding box of each part
+  uint8_t* d_facet_mask = nullptr;  // [n_tri] the parts a facet's points must be tested against
   double4* d_plane = nullptr;       // [n_planes]
   bool has_csg = false;
-  CsgDev csg() const { return CsgDev{d_facet_part, d_part, d_plane}; }
+  CsgDev csg() const { return CsgDev{d_facet_part, d_facet_mask, d_part, d_plane}; }
   int device = 0;
 };
 
@@ -116,6 +125,10 @@ struct fppg_ctx {
   int force_block = 256;    // launch shape of the force kernel (fppg_set_launch)
   bool xcd_remap = true;
   double* dot_scratch = nullptr;   // device address of this device's static dot-product scratch
+  bool persistent = false;  // force kernel schedule (fppg_set_schedule)
+  int* d_tickets = nullptr; // [8] ticket counters of the persistent schedule
+  int resident[2][3] = {};  // resident force blocks per CU by (k - 1, block 128/256/512); 0 = not queried
+  int num_cu = 0;
 };
 
 struct fppg_geom : fppg::Geom {};
@@ -164,7 +177,7 @@ struct WsLayout {
   size_t list_cnt, list_offs, list_bsum, list_end;
   // project (per volume-pass block: queue length and volume reverts; per
   // k_project_heavy block: revert counts; the queue of surface and feature particles)
-  size_t proj_count, proj_vrev, proj_part, proj_queue, proj_end;
+  size_t proj_count, proj_vrev, proj_part, proj_queue, proj_hard, proj_end;
   // relax_energy / vec_dot partial sums
   size_t reduce_end;
   size_t total;

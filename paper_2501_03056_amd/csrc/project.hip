@@ -16,12 +16,15 @@
 //            bounding box touches (padded by 1e-7 cell). Away from the
 //            surface those cells hold no facet and the move is accepted after
 //            one byte of flags.
-// Boolean assemblies (section 3.2.3): a foot point counts only on the
-// assembly's boundary and a volume move near facets only inside the assembly,
-// both by FP64 plane tests of the convex parts.
+// Boolean assemblies (section 3.2.3): a foot point, and the point where a
+// volume move crosses a facet, count only on the assembly's boundary (FP64
+// plane tests of the convex parts): a move across a part's face that lies
+// inside the assembly is accepted.
 // Reverts are counted per block and added to the caller's counters by one
 // small kernel.
 #include "search_grid.h"
+
+#include <algorithm>
 
 namespace fppg {
 
@@ -41,51 +44,51 @@ __device__ __forceinline__ double gap1(int d, double f) {
 }
 
 // ---- Boolean assemblies (section 3.2.3) ----------------------------------------------------
-// Plane tests of the convex parts in FP64 (n.x - d per plane).
-__device__ __forceinline__ bool in_part_open(const CsgDev& cs, int k, double x, double y, double z) {
-  const int2 r = cs.part[k];
-  for (int j = r.x; j < r.y; ++j) {
-    const double4 P = cs.plane[j];
-    if (P.x * x + P.y * y + P.z * z - P.w >= 0.0) return false;
+// Plane tests of the convex parts in FP64 (n.x - d per plane). A point
+// outside a part's bounding box is outside the part; otherwise the planes are
+// read eight at a time, so that their loads overlap, and the test stops after
+// the first batch that decides it.
+template <bool CLOSED>
+__device__ __forceinline__ bool in_part(const CsgDev& cs, int k, double x, double y, double z) {
+  const PartDev& P = cs.part[k];
+  if (x < P.lo[0] || x > P.hi[0] || y < P.lo[1] || y > P.hi[1] || z < P.lo[2] || z > P.hi[2]) return false;
+  for (int j = P.plane_begin; j < P.plane_end; j += 8) {
+    bool out = false;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (j + u < P.plane_end) {
+        const double4 Q = cs.plane[j + u];
+        const double v = Q.x * x + Q.y * y + Q.z * z - Q.w;
+        out |= CLOSED ? (v > 0.0) : (v >= 0.0);
+      }
+    }
+    if (out) return false;
   }
   return true;
+}
+
+__device__ __forceinline__ bool in_part_open(const CsgDev& cs, int k, double x, double y, double z) {
+  return in_part<false>(cs, k, x, y, z);
 }
 
 __device__ __forceinline__ bool in_part_closed(const CsgDev& cs, int k, double x, double y, double z) {
-  const int2 r = cs.part[k];
-  for (int j = r.x; j < r.y; ++j) {
-    const double4 P = cs.plane[j];
-    if (P.x * x + P.y * y + P.z * z - P.w > 0.0) return false;
-  }
-  return true;
+  return in_part<true>(cs, k, x, y, z);
 }
 
-// Is a point of part k's surface on the assembly's boundary?
-__device__ __forceinline__ bool csg_on_boundary(const GeomDev& G, const CsgDev& cs, int k, double x, double y,
+// Is a point of facet t (part k) on the assembly's boundary? Only the parts
+// the facet crosses are tested: the facet lies wholly outside (or, for part 0
+// of a difference, wholly inside) every other part it must avoid.
+__device__ __forceinline__ bool csg_on_boundary(const GeomDev& G, const CsgDev& cs, int t, int k, double x, double y,
                                                 double z) {
   const int base = G.part_begin_csg;
-  for (int j = base; j < G.part_end_csg; ++j) {
-    if (j == k) continue;
+  for (uint32_t m = cs.facet_mask[t]; m; m &= m - 1) {
+    const int j = base + __ffs(int(m)) - 1;
     if (G.csg_op == FPPG_CSG_DIFFERENCE && j == base && k != base) {
       if (!in_part_closed(cs, j, x, y, z)) return false;   // a cut face counts inside part 0
     } else if (in_part_open(cs, j, x, y, z)) {
       return false;
     }
   }
-  return true;
-}
-
-// Is a point inside the assembly?
-__device__ __forceinline__ bool csg_inside(const GeomDev& G, const CsgDev& cs, double x, double y, double z) {
-  const int base = G.part_begin_csg;
-  if (G.csg_op == FPPG_CSG_UNION) {
-    for (int j = base; j < G.part_end_csg; ++j)
-      if (in_part_open(cs, j, x, y, z)) return true;
-    return false;
-  }
-  if (!in_part_open(cs, base, x, y, z)) return false;
-  for (int j = base + 1; j < G.part_end_csg; ++j)
-    if (in_part_closed(cs, j, x, y, z)) return false;
   return true;
 }
 
@@ -106,7 +109,8 @@ __device__ __forceinline__ void scan_surface_cell(int64_t c, double yx, double y
     const double ad = fabs(dist);
     if (!(ad <= R) || ad > h.best || (ad == h.best && t >= h.t)) continue;
     const double px = yx - dist * F.n[0], py = yy - dist * F.n[1], pz = yz - dist * F.n[2];
-    if (bary_min(F, px, py, pz) >= 0.0 && (G.csg_op == FPPG_CSG_NONE || csg_on_boundary(G, cs, cs.facet_part[t], px, py, pz))) {
+    if (bary_min(F, px, py, pz) >= 0.0 && (G.csg_op == FPPG_CSG_NONE || cs.facet_part[t] < 0 ||
+                                           csg_on_boundary(G, cs, t, cs.facet_part[t], px, py, pz))) {
       h.best = ad;
       h.t = t;
       h.x = px;
@@ -116,10 +120,13 @@ __device__ __forceinline__ void scan_surface_cell(int64_t c, double yx, double y
   }
 }
 
+// The search from the own cell. If the own cell accepts no facet, *wide is
+// set and the caller hands the particle to the parallel search over all 27
+// cells (k_project_wide) instead of scanning the neighbours one by one here.
 __device__ __forceinline__ SurfaceHit surface_search(const GeomDev& G, double yx, double yy, double yz,
                                                      const FacetDev* __restrict__ facets,
                                                      const int* __restrict__ tstart, const int* __restrict__ ttri,
-                                                     const uint8_t* __restrict__ tflag, const CsgDev& cs) {
+                                                     const uint8_t* __restrict__ tflag, const CsgDev& cs, bool* wide) {
   SurfaceHit h;
   const double R = G.R;
   const double tx = search_t(G, 0, yx), ty = search_t(G, 1, yy), tz = search_t(G, 2, yz);
@@ -127,6 +134,8 @@ __device__ __forceinline__ SurfaceHit surface_search(const GeomDev& G, double yx
   const double fx = tx - cx, fy = ty - cy, fz = tz - cz;
   const int64_t c0 = search_index(G, cx, cy, cz);
   if (tflag[c0] & kCellHasFacet) scan_surface_cell(c0, yx, yy, yz, R, facets, tstart, ttri, h, G, cs);
+  *wide = h.t == 0x7fffffff;
+  if (*wide) return h;
   const double slack = 1e-7;   // cell units, covers the rounding of the gaps
   for (int dz = -1; dz <= 1; ++dz) {
     const int z = cz + dz;
@@ -148,13 +157,15 @@ __device__ __forceinline__ SurfaceHit surface_search(const GeomDev& G, double yx
   return h;
 }
 
-// Does the segment [x, y] meet a facet registered in cell c?
+// Does the segment [x, y] meet a facet registered in cell c (for an
+// assembly: at a point of the assembly's boundary)?
 __device__ __forceinline__ bool cell_crossed(int64_t c, double x0, double x1, double x2, double y0, double y1, double y2,
                                              const FacetDev* __restrict__ facets, const int* __restrict__ tstart,
-                                             const int* __restrict__ ttri) {
+                                             const int* __restrict__ ttri, const GeomDev& G, const CsgDev& cs) {
   const int b = tstart[c], e = tstart[c + 1];
   for (int q = b; q < e; ++q) {
-    const FacetDev& F = facets[ttri[q]];
+    const int t = ttri[q];
+    const FacetDev& F = facets[t];
     const double sx = (x0 - F.a[0]) * F.n[0] + (x1 - F.a[1]) * F.n[1] + (x2 - F.a[2]) * F.n[2];
     const double sy = (y0 - F.a[0]) * F.n[0] + (y1 - F.a[1]) * F.n[1] + (y2 - F.a[2]) * F.n[2];
     if ((sx > 0.0 && sy > 0.0) || (sx < 0.0 && sy < 0.0)) continue;   // both ends on one side of the plane
@@ -165,7 +176,9 @@ __device__ __forceinline__ bool cell_crossed(int64_t c, double x0, double x1, do
       py = x1 + s * (y1 - x1);
       pz = x2 + s * (y2 - x2);
     }
-    if (bary_min(F, px, py, pz) >= 0.0) return true;
+    if (bary_min(F, px, py, pz) >= 0.0 &&
+        (G.csg_op == FPPG_CSG_NONE || cs.facet_part[t] < 0 || csg_on_boundary(G, cs, t, cs.facet_part[t], px, py, pz)))
+      return true;
   }
   return false;
 }
@@ -173,7 +186,7 @@ __device__ __forceinline__ bool cell_crossed(int64_t c, double x0, double x1, do
 __device__ __forceinline__ bool segment_crosses(const GeomDev& G, double x0, double x1, double x2, double y0,
                                                 double y1, double y2, const FacetDev* __restrict__ facets,
                                                 const int* __restrict__ tstart, const int* __restrict__ ttri,
-                                                const uint8_t* __restrict__ tflag) {
+                                                const uint8_t* __restrict__ tflag, const CsgDev& cs) {
   const double pad = 1e-7;   // cell units
   const int lx = int(floor(search_t(G, 0, fmin(x0, y0)) - pad)), hx = int(floor(search_t(G, 0, fmax(x0, y0)) + pad));
   const int ly = int(floor(search_t(G, 1, fmin(x1, y1)) - pad)), hy = int(floor(search_t(G, 1, fmax(x1, y1)) + pad));
@@ -182,23 +195,9 @@ __device__ __forceinline__ bool segment_crosses(const GeomDev& G, double x0, dou
     for (int y = max(ly, 0); y <= min(hy, G.tg_dims[1] - 1); ++y)
       for (int x = max(lx, 0); x <= min(hx, G.tg_dims[0] - 1); ++x) {
         const int64_t c = search_index(G, x, y, z);
-        if ((tflag[c] & kCellHasFacet) && cell_crossed(c, x0, x1, x2, y0, y1, y2, facets, tstart, ttri))
+        if ((tflag[c] & kCellHasFacet) && cell_crossed(c, x0, x1, x2, y0, y1, y2, facets, tstart, ttri, G, cs))
           return true;
       }
-  return false;
-}
-
-// Does any search cell that the box of the segment [x, y] touches hold a facet?
-__device__ __forceinline__ bool segment_near_facets(const GeomDev& G, double x0, double x1, double x2, double y0,
-                                                    double y1, double y2, const uint8_t* __restrict__ tflag) {
-  const double pad = 1e-7;   // cell units
-  const int lx = int(floor(search_t(G, 0, fmin(x0, y0)) - pad)), hx = int(floor(search_t(G, 0, fmax(x0, y0)) + pad));
-  const int ly = int(floor(search_t(G, 1, fmin(x1, y1)) - pad)), hy = int(floor(search_t(G, 1, fmax(x1, y1)) + pad));
-  const int lz = int(floor(search_t(G, 2, fmin(x2, y2)) - pad)), hz = int(floor(search_t(G, 2, fmax(x2, y2)) + pad));
-  for (int z = max(lz, 0); z <= min(hz, G.tg_dims[2] - 1); ++z)
-    for (int y = max(ly, 0); y <= min(hy, G.tg_dims[1] - 1); ++y)
-      for (int x = max(lx, 0); x <= min(hx, G.tg_dims[0] - 1); ++x)
-        if (tflag[search_index(G, x, y, z)] & kCellHasFacet) return true;
   return false;
 }
 
@@ -252,7 +251,8 @@ __global__ __launch_bounds__(kBlock) void k_project_volume(float4* __restrict__ 
                                                            uint32_t* status, uint8_t* __restrict__ accepted,
                                                            const int* __restrict__ list, int n_list,
                                                            int* __restrict__ queue, int* __restrict__ qcount,
-                                                           int* __restrict__ vrev, CsgDev cs) {
+                                                           int* __restrict__ vrev, CsgDev cs, int* __restrict__ hard) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) hard[0] = 0;   // the wide-search queue of this projection
   const int i = listed(blockIdx.x * blockDim.x + threadIdx.x, n, list, n_list);
   bool rev_v = false, heavy = false;
   if (i < n) {
@@ -266,9 +266,7 @@ __global__ __launch_bounds__(kBlock) void k_project_volume(float4* __restrict__ 
         const float y0 = p.x + d.x, y1 = p.y + d.y, y2 = p.z + d.z;
         if (!(isfinite(y0) && isfinite(y1) && isfinite(y2))) {
           atomicOr(status, FPPG_S_NONFINITE_POS);
-        } else if (G.csg_op == FPPG_CSG_NONE
-                       ? segment_crosses(G, p.x, p.y, p.z, y0, y1, y2, facets, tstart, ttri, tflag)
-                       : (segment_near_facets(G, p.x, p.y, p.z, y0, y1, y2, tflag) && !csg_inside(G, cs, y0, y1, y2))) {
+        } else if (segment_crosses(G, p.x, p.y, p.z, y0, y1, y2, facets, tstart, ttri, tflag, cs)) {
           rev_v = true;                                    // would leave the volume: stays at x
         } else {
           pos[i] = make_float4(y0, y1, y2, p.w);
@@ -325,7 +323,7 @@ __global__ __launch_bounds__(kBlock) void k_project_heavy(float4* __restrict__ p
                                                           const int* __restrict__ queue,
                                                           const int* __restrict__ qcount,
                                                           const int* __restrict__ vrev, int n_vblocks, int group,
-                                                          int4* __restrict__ part, CsgDev cs) {
+                                                          int4* __restrict__ part, CsgDev cs, int* __restrict__ hard) {
   __shared__ int s_pre[kHeavyGroupMax + 1];
   __shared__ int s_rev[2];
   const int b0 = blockIdx.x * group;
@@ -357,14 +355,15 @@ __global__ __launch_bounds__(kBlock) void k_project_heavy(float4* __restrict__ p
         if (!(isfinite(yx) && isfinite(yy) && isfinite(yz))) {
           atomicOr(status, FPPG_S_NONFINITE_POS);
         } else {
-          const SurfaceHit h = surface_search(G, yx, yy, yz, facets, tstart, ttri, tflag, cs);
-          if (h.t != 0x7fffffff) {
-            pos[i] = make_float4(float(h.x), float(h.y), float(h.z), p.w);
-            owner[i] = h.t;
-            moved = true;
-          } else {
-            rev_s = true;                                  // no facet accepts: stays at x (section 3.3.3)
+          bool wide = false;
+          const SurfaceHit h = surface_search(G, yx, yy, yz, facets, tstart, ttri, tflag, cs, &wide);
+          if (wide) {
+            hard[1 + atomicAdd(&hard[0], 1)] = i;          // decided by k_project_wide
+            continue;
           }
+          pos[i] = make_float4(float(h.x), float(h.y), float(h.z), p.w);
+          owner[i] = h.t;
+          moved = true;
         }
       } else {   // feature
         const int slot = owner[i];
@@ -400,6 +399,71 @@ __global__ __launch_bounds__(kBlock) void k_project_heavy(float4* __restrict__ p
     for (int k = 0; k < group; ++k) rv += b0 + k < n_vblocks ? vrev[b0 + k] : 0;
     part[blockIdx.x] = make_int4(s_rev[0], s_rev[1], rv, 0);
   }
+}
+
+// Surface particles whose own search cell accepts no facet: one wavefront
+// per particle, lane c (< 27) scanning cell c of the 3 x 3 x 3 block around y
+// when it lies within R, then the wavefront's smallest (|d|, facet): the same
+// argmin as the one-by-one search, in the time of one cell instead of 27.
+__global__ __launch_bounds__(kBlock) void k_project_wide(float4* __restrict__ pos, int* __restrict__ owner,
+                                                         const float4* __restrict__ disp,
+                                                         const GeomDev* __restrict__ geoms, int n_geom,
+                                                         const FacetDev* __restrict__ facets,
+                                                         const int* __restrict__ tstart, const int* __restrict__ ttri,
+                                                         const uint8_t* __restrict__ tflag,
+                                                         uint8_t* __restrict__ accepted, const int* __restrict__ hard,
+                                                         CsgDev cs, unsigned long long* __restrict__ counters) {
+  const int lane = threadIdx.x & 63;
+  const int wave = int((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int nwaves = int((gridDim.x * blockDim.x) >> 6);
+  const int cnt = hard[0];
+  int reverts = 0;
+  for (int q = wave; q < cnt; q += nwaves) {
+    const int i = hard[1 + q];
+    const float4 p = pos[i];
+    const float4 d = disp[i];
+    const GeomDev& G = geoms[min(geom_of(p.w), n_geom - 1)];
+    const double yx = double(p.x) + double(d.x), yy = double(p.y) + double(d.y), yz = double(p.z) + double(d.z);
+    const double R = G.R;
+    const double tx = search_t(G, 0, yx), ty = search_t(G, 1, yy), tz = search_t(G, 2, yz);
+    const int cx = int(floor(tx)), cy = int(floor(ty)), cz = int(floor(tz));
+    SurfaceHit h;
+    if (lane < 27) {
+      const int dx = lane % 3 - 1, dy = (lane / 3) % 3 - 1, dz = lane / 9 - 1;
+      const int x = cx + dx, y = cy + dy, z = cz + dz;
+      if (x >= 0 && x < G.tg_dims[0] && y >= 0 && y < G.tg_dims[1] && z >= 0 && z < G.tg_dims[2]) {
+        const double gx = gap1(dx, tx - cx), gy = gap1(dy, ty - cy), gz = gap1(dz, tz - cz);
+        const double lim = R * G.tg_inv + 1e-7;   // cell units: the cell must come within R of y
+        const int64_t c = search_index(G, x, y, z);
+        if (gx * gx + gy * gy + gz * gz <= lim * lim && (tflag[c] & kCellHasFacet))
+          scan_surface_cell(c, yx, yy, yz, R, facets, tstart, ttri, h, G, cs);
+      }
+    }
+    double b = h.best;
+    int t = h.t;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ob = __shfl_xor(b, o);
+      const int ot = __shfl_xor(t, o);
+      if (ob < b || (ob == b && ot < t)) {
+        b = ob;
+        t = ot;
+      }
+    }
+    if (t != 0x7fffffff) {
+      const int src = __ffsll((long long)__ballot(h.t == t && h.best == b)) - 1;
+      const double fx = __shfl(h.x, src), fy = __shfl(h.y, src), fz = __shfl(h.z, src);
+      if (lane == 0) {
+        pos[i] = make_float4(float(fx), float(fy), float(fz), p.w);
+        owner[i] = t;
+        if (accepted) accepted[i] = 1;
+      }
+    } else if (lane == 0) {
+      ++reverts;                                          // no facet accepts: stays at x (section 3.3.3)
+      if (accepted) accepted[i] = 0;
+    }
+  }
+  if (lane == 0 && reverts) atomicAdd(&counters[FPPG_C_REVERT_SURFACE], (unsigned long long)reverts);
 }
 
 // Sum the per-block revert counts into the caller's counters (one block).
@@ -460,6 +524,7 @@ static fppg_status project_impl(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
   int* vrev = reinterpret_cast<int*>(static_cast<char*>(ws) + L.proj_vrev);
   int4* part = reinterpret_cast<int4*>(static_cast<char*>(ws) + L.proj_part);
   int* queue = reinterpret_cast<int*>(static_cast<char*>(ws) + L.proj_queue);
+  int* hard = reinterpret_cast<int*>(static_cast<char*>(ws) + L.proj_hard);
   unsigned long long* ctr = reinterpret_cast<unsigned long long*>(counters);
   float4* p4 = reinterpret_cast<float4*>(pos);
   const float4* d4 = reinterpret_cast<const float4*>(disp);
@@ -468,18 +533,23 @@ static fppg_status project_impl(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
   if (geom->n_geom == 1)
     k_project_volume<true><<<vb, kBlock, 0, s>>>(p4, d4, ni, geom->d_geom, 1, geom->d_facet, geom->d_tg_start,
                                                  geom->d_tg_tri, geom->d_tg_flag, move_mask, ctx->d_status, accepted,
-                                                 list, nr, queue, qcount, vrev, geom->csg());
+                                                 list, nr, queue, qcount, vrev, geom->csg(), hard);
   else
     k_project_volume<false><<<vb, kBlock, 0, s>>>(p4, d4, ni, geom->d_geom, geom->n_geom, geom->d_facet,
                                                   geom->d_tg_start, geom->d_tg_tri, geom->d_tg_flag, move_mask,
-                                                  ctx->d_status, accepted, list, nr, queue, qcount, vrev, geom->csg());
+                                                  ctx->d_status, accepted, list, nr, queue, qcount, vrev, geom->csg(),
+                                                  hard);
   const int group = (move_mask >> FPPG_TAG_VOLUME) & 1u ? kHeavyGroupMax : 1;
   const int hb = (vb + group - 1) / group;
   k_project_heavy<<<hb, kBlock, 0, s>>>(p4, owner, d4, feat_seg, feat_u, n_feat, int(geom->n_seg), geom->d_seg,
                                         geom->d_geom, geom->n_geom, geom->d_facet, geom->d_tg_start, geom->d_tg_tri,
                                         geom->d_tg_flag, ctx->d_status, accepted, queue, qcount, vrev, vb, group,
-                                        part, geom->csg());
+                                        part, geom->csg(), hard);
   k_project_counts<<<1, kBlock, 0, s>>>(part, hb, ctr);
+  // the wide searches: every wavefront loops over the queue, whose length the device holds
+  k_project_wide<<<std::max(1, std::min(hb, 256)), kBlock, 0, s>>>(p4, owner, d4, geom->d_geom, geom->n_geom,
+                                                                  geom->d_facet, geom->d_tg_start, geom->d_tg_tri,
+                                                                  geom->d_tg_flag, accepted, hard, geom->csg(), ctr);
   FPPG_HIP(ctx, hipGetLastError());
   return FPPG_OK;
 }

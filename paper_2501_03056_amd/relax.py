@@ -89,9 +89,10 @@ class Context:
         self.handle = h
         self.device = device
 
-    def set_launch(self, force_block: int = 256, xcd_remap: bool = True):
-        """Launch shape of the force kernel (fppg_set_launch)."""
+    def set_launch(self, force_block: int = 256, xcd_remap: bool = True, persistent: bool = False):
+        """Launch shape (fppg_set_launch) and schedule (fppg_set_schedule) of the force kernel."""
         check(self.lib.fppg_set_launch(self.handle, int(force_block), int(bool(xcd_remap))), self.handle)
+        check(self.lib.fppg_set_schedule(self.handle, int(bool(persistent))), self.handle)
 
     def close(self):
         if self.handle:

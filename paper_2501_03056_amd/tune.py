@@ -79,7 +79,13 @@ def _time_graph(r, steps):
     return ms
 
 
-LAUNCH_SHAPES = ((256, True), (128, True), (512, True), (256, False), (128, False), (512, False))
+# (threads per block, XCD remap, persistent ticket schedule)
+LAUNCH_SHAPES = ((256, True, False), (128, True, False), (512, True, False), (256, False, False),
+                 (128, False, False), (512, False, False), (256, True, True), (512, True, True))
+
+
+def shape_name(block: int, remap: bool, persistent: bool) -> str:
+    return f"b{block}_{'xcd' if remap else 'rr'}" + ("_tickets" if persistent else "")
 
 
 def autotune(wl, candidates=(1, 2), modes=("eager", "graph"), steps: int = 20, warmup: int = 4,
@@ -95,14 +101,16 @@ def autotune(wl, candidates=(1, 2), modes=("eager", "graph"), steps: int = 20, w
             table = json.load(open(cache))
         except (OSError, ValueError):
             table = {}
-    if key in table and "force_block" in table[key]:
+    if key in table and "persistent" in table[key]:
         return table[key]
     times = {}
     for k in candidates:
         r = Relaxer(regrid(wl, k), device=device)
         for _ in range(warmup):
             r.step(keep_accel=False)
+        snap = r.snapshot()
         for mode in modes:
+            r.restore(snap)
             times[f"k{k}_{mode}"] = _time_eager(r, steps) if mode == "eager" else _time_graph(r, steps)
         del r
     best = min(times, key=times.get)
@@ -111,14 +119,18 @@ def autotune(wl, candidates=(1, 2), modes=("eager", "graph"), steps: int = 20, w
     r = Relaxer(regrid(wl, int(k[1:])), device=device)
     for _ in range(warmup):
         r.step(keep_accel=False)
-    for block, remap in shapes:
-        r.ctx.set_launch(block, remap)
-        shape_ms[f"b{block}_{'xcd' if remap else 'rr'}"] = \
+    snap = r.snapshot()   # every shape is timed from the same state (an iteration's cost drifts as it relaxes)
+    for block, remap, persistent in shapes:
+        r.restore(snap)
+        r.ctx.set_launch(block, remap, persistent)
+        shape_ms[shape_name(block, remap, persistent)] = \
             _time_eager(r, steps) if mode == "eager" else _time_graph(r, steps)
+    r.ctx.set_launch()
     del r
     shape = min(shape_ms, key=shape_ms.get)
-    res = {"k": int(k[1:]), "mode": mode, "force_block": int(shape.split("_")[0][1:]),
-           "xcd_remap": shape.endswith("xcd"), "ms_per_step": times, "launch_ms_per_step": shape_ms}
+    block, remap, persistent = next(sh for sh in shapes if shape_name(*sh) == shape)
+    res = {"k": int(k[1:]), "mode": mode, "force_block": block, "xcd_remap": remap, "persistent": persistent,
+           "ms_per_step": times, "launch_ms_per_step": shape_ms}
     if cache:
         table[key] = res
         try:

@@ -40,6 +40,7 @@ def test_host_side_validation_without_gpu():
     assert L.fppg_moving_list(nul, nul, 0, nul, 0, nul, nul, nul, 0, nul) == _lib.E_ARG
     assert L.fppg_volume_layers(nul, nul, 0, nul, 0.1, nul, nul) == _lib.E_ARG
     assert L.fppg_set_launch(nul, 256, 1) == _lib.E_ARG
+    assert L.fppg_set_schedule(nul, 1) == _lib.E_ARG
     assert L.fppg_tier_partition(nul, nul, 0, nul, nul, nul, nul, nul, nul, 0, nul, nul, 0, nul) == _lib.E_ARG
     assert L.fppg_generate(nul, nul, 0, nul, 0, 0.1, nul, nul, nul, nul, nul, 0, nul, nul) == _lib.E_ARG
     assert L.fppg_features(nul, nul, 0, nul, 0, 0.5, 0.1, nul, nul) == _lib.E_ARG

@@ -107,8 +107,9 @@ def test_autotune_picks_a_measured_configuration_and_results_do_not_depend_on_it
     assert res["k"] in (1, 2) and res["mode"] in ("eager", "graph")
     assert set(res["ms_per_step"]) == {"k1_eager", "k1_graph", "k2_eager", "k2_graph"}
     assert min(res["ms_per_step"].values()) == res["ms_per_step"][f"k{res['k']}_{res['mode']}"]
-    assert len(res["launch_ms_per_step"]) == 6 and res["force_block"] in (128, 256, 512)
-    shape = f"b{res['force_block']}_{'xcd' if res['xcd_remap'] else 'rr'}"
+    from paper_2501_03056_amd.tune import LAUNCH_SHAPES, shape_name
+    assert len(res["launch_ms_per_step"]) == len(LAUNCH_SHAPES) and res["force_block"] in (128, 256, 512)
+    shape = shape_name(res["force_block"], res["xcd_remap"], res["persistent"])
     assert min(res["launch_ms_per_step"].values()) == res["launch_ms_per_step"][shape]
     states = []
     for k in (1, 2):
@@ -122,17 +123,18 @@ def test_autotune_picks_a_measured_configuration_and_results_do_not_depend_on_it
 
 @pytest.mark.parametrize("k", [1, 2])
 def test_force_launch_shape_does_not_change_results(k):
-    """Every launch shape of the force kernel (threads per block, XCD remap)
-    gives the same iterations bit for bit, on a batch with a receiver list too."""
+    """Every launch shape and schedule of the force kernel (threads per block,
+    XCD remap, one block per chunk or persistent blocks taking tickets) gives
+    the same iterations bit for bit."""
     from paper_2501_03056_amd import Relaxer
     from paper_2501_03056_amd.tune import LAUNCH_SHAPES, regrid
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     wl = regrid(W.batch_workload(n_geom=5, n_min=1.5e3, n_max=8e3, seed=4100), k)
     ref = None
-    for block, remap in LAUNCH_SHAPES:
+    for block, remap, persistent in LAUNCH_SHAPES:
         r = Relaxer(wl, device=0)
-        r.ctx.set_launch(block, remap)
+        r.ctx.set_launch(block, remap, persistent)
         for _ in range(3):
             r.step()
         st = r.host_state()
@@ -140,7 +142,7 @@ def test_force_launch_shape_does_not_change_results(k):
             ref = st
         else:
             for a, b in zip(ref, st):
-                assert np.array_equal(a, b), (block, remap)
+                assert np.array_equal(a, b), (block, remap, persistent)
         assert r.read_status() == 0
     from paper_2501_03056_amd import _lib
     with pytest.raises(_lib.FppgError):
