@@ -77,6 +77,8 @@ typedef int32_t fppg_status;
 #define FPPG_S_NONFINITE_ACCEL 1u  /* a receiver's acceleration was not finite (it did not move) */
 #define FPPG_S_NONFINITE_POS   2u  /* a moved position was not finite (the move was reverted) */
 #define FPPG_S_BAD_INDEX       4u  /* a geometry, owner or feature index was out of range (particle held) */
+#define FPPG_S_FIXED_RANGE     8u  /* a vertex-gradient contribution or running sum left the 64-bit
+                                      fixed-point range |v| < 2^23 (step/fixed adjoint): that gradient is invalid */
 
 /* counters accumulated by fppg_project (int64 each) */
 #define FPPG_C_REVERT_SURFACE 0
@@ -237,6 +239,16 @@ void        fppg_geom_destroy(fppg_geom* geom);
 fppg_status fppg_geom_info(const fppg_geom* geom, int64_t* ncell, int64_t* n_tri, int64_t* n_seg,
                            int64_t* search_cells, int64_t* search_entries);
 
+/* Copy the facet search grid (registered on the device at fppg_geom_create:
+ * facets subdivided and tested against the cells as fppg_sparse_grid_create
+ * does, with a pad of 1e-6 cell) into caller device buffers: start
+ * [search_cells + 1] (facet-list offsets of every search cell, the
+ * geometries' grids one after another), tri [search_entries] (global facet
+ * ids, ascending within a cell), flag [search_cells] (1: the cell holds a
+ * facet). A null destination is skipped. Stream-ordered. */
+fppg_status fppg_geom_search_grid(fppg_ctx* ctx, const fppg_geom* geom, int32_t* start, int32_t* tri, uint8_t* flag,
+                                  void* stream);
+
 /* Workspace bytes needed by the per-iteration calls for n particles. */
 fppg_status fppg_workspace_size(const fppg_geom* geom, int64_t n, size_t* bytes);
 
@@ -280,7 +292,9 @@ fppg_status fppg_tier_partition(fppg_ctx* ctx, fppg_geom* geom, int64_t n, float
  *      quarantine range and cell_start[ncell + 1] = n. Particles with a
  *      non-finite coordinate get the key ncell (after every geometry, where no
  *      stencil reaches: they are nobody's neighbour) and FPPG_S_NONFINITE_POS.
- * The order is deterministic (independent of atomic ordering).
+ * The order is deterministic (independent of atomic ordering). Work per
+ * cell of m particles: O(m^2) lane steps up to m = 64, a sort of
+ * O(m log m) above that (a clump of particles, or many non-finite ones).
  */
 fppg_status fppg_build_cells(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
                              const float* pos_in, const int32_t* id_in, const int32_t* owner_in,
@@ -530,6 +544,66 @@ fppg_status fppg_generate(fppg_ctx* ctx, const double* vert, int32_t n_vert, con
  */
 fppg_status fppg_cells_boolean(fppg_ctx* ctx, const uint8_t* a, const uint8_t* b, int64_t n, int32_t op,
                                uint8_t* out, void* stream);
+
+/*
+ * Sparse storage of the cells a mesh meets (section 3.1.1 facet subdivision,
+ * section 3.1.3 Morton code and compact hash, Eq. 9-10), built on the device.
+ *   subdivision  an edge whose extent along some axis exceeds `cell` is split
+ *                at its midpoint (a + b) * 0.5, the others' midpoints are
+ *                virtual; a triangle with no split edge (box within one cell
+ *                per axis) is a leaf; three split edges give the 4 corner and
+ *                centre triangles, two give the corner where they meet and the
+ *                rest cut along the diagonal from the far end of the unsplit
+ *                edge, one gives 2 triangles through the opposite vertex
+ *   registration (cell, facet) for every cell whose box widened by pad a leaf
+ *                of the facet meets (closed separating-axis test, FP64)
+ *   C_compact    the registered cells in Morton order (Eq. 9: bits of x, y, z
+ *                interleaved, x lowest), each with begin/length of its facets
+ *                in the (Morton code, facet) ordered facet list
+ *   hash table   H(x) = (p1 x + p2 y + p3 z) mod H_size (Eq. 10, the paper's
+ *                primes, 64-bit unsigned arithmetic); C_compact's entries in
+ *                (hash, Morton) order with H_begin/H_length per hash value
+ * in:  vert [n_vert*3], tri [n_tri*3] (host, FP64 / int32); grid origin (the
+ *      corner of cell (0,0,0)), cell edge, dims (each in [1, 2^21]); pad >= 0;
+ *      hash_size (0: the number of registered cells).
+ * out: *out, a device-resident structure (fppg_sparse_grid_destroy frees it).
+ * Synchronous. Errors: FPPG_E_ARG (bad sizes, indices, non-finite input),
+ * FPPG_E_CAPACITY (more than 48 subdivision levels or 2^31 entries).
+ */
+typedef struct fppg_sparse_grid fppg_sparse_grid;
+typedef struct {
+  int64_t n_entry;          /* length of the facet list */
+  int64_t n_cell;           /* registered cells (C_compact) */
+  int64_t hash_size;        /* H_size */
+  int64_t levels;           /* subdivision levels taken */
+  const int32_t* facets;    /* [n_entry] facet ids, by (Morton code, facet) */
+  const uint64_t* morton;   /* [n_cell] ascending */
+  const int32_t* begin;     /* [n_cell] first entry of each cell in facets */
+  const int32_t* length;    /* [n_cell] */
+  const int32_t* order;     /* [n_cell] C_compact indices by (hash, Morton code) */
+  const int32_t* h_begin;   /* [hash_size + 1] first position in order of each hash value */
+  const int32_t* h_length;  /* [hash_size] */
+} fppg_sparse_grid_view;  /* device pointers, valid until the grid is destroyed */
+
+fppg_status fppg_sparse_grid_create(fppg_ctx* ctx, const double* vert, int32_t n_vert, const int32_t* tri,
+                                    int32_t n_tri, const double origin[3], double cell, const int32_t dims[3],
+                                    double pad, int64_t hash_size, fppg_sparse_grid** out);
+fppg_status fppg_sparse_grid_info(const fppg_sparse_grid* grid, fppg_sparse_grid_view* view);
+/* Copy the arrays of the view (sizes as there) into caller device buffers;
+ * a null destination is skipped. Stream-ordered. */
+fppg_status fppg_sparse_grid_copy(fppg_ctx* ctx, const fppg_sparse_grid* grid, int32_t* facets, uint64_t* morton,
+                                  int32_t* begin, int32_t* length, int32_t* order, int32_t* h_begin,
+                                  int32_t* h_length, void* stream);
+/*
+ * For each point [n*3] (device, FP64): the cell floor((p - origin) / cell)
+ * (the FP64 product with 1/cell), its hash, a scan of that hash value's
+ * entries for the cell's Morton code; begin [n] / length [n] (device int32)
+ * of its facets in the view's facet list, or -1 / 0 for a cell outside the
+ * grid or not registered. Stream-ordered.
+ */
+fppg_status fppg_sparse_grid_lookup(fppg_ctx* ctx, const fppg_sparse_grid* grid, int64_t n, const double* points,
+                                    int32_t* begin, int32_t* length, void* stream);
+fppg_status fppg_sparse_grid_destroy(fppg_sparse_grid* grid);
 
 /*
  * Feature extraction and feature-line particles (section 3.2.2) of one mesh

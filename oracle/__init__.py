@@ -20,9 +20,13 @@ Modules (each function cites the passage it follows):
   metrics    force residual and density-uniformity loss
   csg        Boolean assemblies: part signed distances, boundary membership
   local      the same step at full size (candidate searches, pinned to brute force)
+  register   facet subdivision and registration on a grid, Morton code and
+             compact hash of the registered cells (sections 3.1.1, 3.1.3)
+
+The front-end modules generate, features and band are imported by name.
 
 Readings of points where the paper is silent or garbled are listed where they
 are used; the functions with no independent pin say "parity unpinned" in their
 docstring (time-step rule, feature-line motion, volume revert rule, metrics).
 """
-from . import kernel, cells, neighbors, force, geometry, step, hvp, metrics, csg, local  # noqa: F401
+from . import kernel, cells, neighbors, force, geometry, step, hvp, metrics, csg, local, register  # noqa: F401

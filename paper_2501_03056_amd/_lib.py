@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libfppg.so")
 OK, E_ARG, E_HIP, E_WORKSPACE, E_CAPACITY, E_UNSUPPORTED, E_NODEVICE = 0, -1, -2, -3, -4, -5, -6
 F_COUNT_PAIRS = 1
 CSG_NONE, CSG_UNION, CSG_DIFFERENCE = 0, 1, 2
-S_NONFINITE_ACCEL, S_NONFINITE_POS, S_BAD_INDEX = 1, 2, 4
+S_NONFINITE_ACCEL, S_NONFINITE_POS, S_BAD_INDEX, S_FIXED_RANGE = 1, 2, 4, 8
 C_REVERT_SURFACE, C_REVERT_FEATURE, C_REVERT_VOLUME = 0, 1, 2
 NCOUNTERS = 8
 NPHASES = 5
@@ -48,6 +48,7 @@ _SIGS = {
     "fppg_geom_info": (c_int32, [_P, POINTER(c_int64), POINTER(c_int64), POINTER(c_int64),
                                  POINTER(c_int64), POINTER(c_int64)]),
     "fppg_workspace_size": (c_int32, [_P, c_int64, POINTER(c_size_t)]),
+    "fppg_geom_search_grid": (c_int32, [_P, _P, _P, _P, _P, _P]),
     "fppg_build_cells": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, _P, _P, _P, _P, c_size_t, _P]),
     "fppg_relax_step": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, c_int32, c_uint32, c_uint32,
                                   _P, _P, _P, _P, c_int32, _P, c_size_t, _P]),
@@ -88,6 +89,12 @@ _SIGS = {
     "fppg_fixed_to_double": (c_int32, [_P, c_int64, _P, _P, _P]),
     "fppg_lattice_density": (c_int32, [c_double, c_double, POINTER(c_double)]),
     "fppg_source_hash": (c_char_p, []),
+    "fppg_sparse_grid_create": (c_int32, [_P, _P, c_int32, _P, c_int32, POINTER(c_double), c_double,
+                                          POINTER(c_int32), c_double, c_int64, POINTER(c_void_p)]),
+    "fppg_sparse_grid_info": (c_int32, [_P, _P]),
+    "fppg_sparse_grid_copy": (c_int32, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "fppg_sparse_grid_lookup": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P]),
+    "fppg_sparse_grid_destroy": (c_int32, [_P]),
 }
 
 _lib = None
@@ -103,6 +110,15 @@ class FeaturesOut(ctypes.Structure):
         ("cap_particles", c_int64),
         ("n_edges", c_int64), ("n_singular", c_int64), ("n_lines", c_int64), ("n_line_vert", c_int64),
         ("n_particles", c_int64),
+    ]
+
+
+class SparseGridView(ctypes.Structure):
+    """fppg_sparse_grid_view."""
+    _fields_ = [
+        ("n_entry", c_int64), ("n_cell", c_int64), ("hash_size", c_int64), ("levels", c_int64),
+        ("facets", c_void_p), ("morton", c_void_p), ("begin", c_void_p), ("length", c_void_p),
+        ("order", c_void_p), ("h_begin", c_void_p), ("h_length", c_void_p),
     ]
 
 

@@ -14,7 +14,8 @@
 //
 // Vertex gradients are accumulated as 64-bit fixed point (2^-40 units) with
 // integer atomics: integer addition is associative, so the sums do not depend
-// on the order of the atomics (deterministic), and converted to double at the end.
+// on the order of the atomics (deterministic), and converted to double at the
+// end. Their range is |sum| < 2^23; leaving it raises FPPG_S_FIXED_RANGE.
 #include "stencil.h"
 
 #include <cmath>
@@ -22,16 +23,31 @@
 namespace fppg {
 
 constexpr double kFixScale = 1099511627776.0;   // 2^40
+constexpr double kFixLimit = 8388608.0;         // 2^23: 2^63 units of 2^-40
 
-__device__ __forceinline__ void fix_add(unsigned long long* __restrict__ acc, int idx, double v) {
-  if (v != 0.0) atomicAdd(&acc[idx], (unsigned long long)(long long)llrint(v * kFixScale));
+// One contribution to a fixed-point sum. A contribution of magnitude 2^23 or
+// more is dropped, and a signed overflow of the running sum is detected from
+// the value the atomic returns; both raise FPPG_S_FIXED_RANGE. The overflow
+// test sees the partial sums in the order the atomics took, so it can also
+// fire when only a partial sum left the range (conservative).
+__device__ __forceinline__ void fix_add(unsigned long long* __restrict__ acc, int idx, double v, uint32_t* status) {
+  if (v == 0.0) return;
+  if (!(fabs(v) < kFixLimit)) {
+    atomicOr(status, FPPG_S_FIXED_RANGE);
+    return;
+  }
+  const long long inc = llrint(v * kFixScale);
+  const long long old = (long long)atomicAdd(&acc[idx], (unsigned long long)inc);
+  const long long sum = (long long)((unsigned long long)old + (unsigned long long)inc);
+  if (((old ^ sum) & (inc ^ sum)) < 0) atomicOr(status, FPPG_S_FIXED_RANGE);
 }
 
-__device__ __forceinline__ void fix_add3(unsigned long long* __restrict__ acc, int vert, double x, double y, double z) {
+__device__ __forceinline__ void fix_add3(unsigned long long* __restrict__ acc, uint32_t* status, int vert, double x,
+                                         double y, double z) {
   if (vert < 0) return;
-  fix_add(acc, 3 * vert, x);
-  fix_add(acc, 3 * vert + 1, y);
-  fix_add(acc, 3 * vert + 2, z);
+  fix_add(acc, 3 * vert, x, status);
+  fix_add(acc, 3 * vert + 1, y, status);
+  fix_add(acc, 3 * vert + 2, z, status);
 }
 
 // ---- uniformity loss -----------------------------------------------------------------------
@@ -117,7 +133,8 @@ __device__ __forceinline__ void cross3(const double a[3], const double b[3], dou
 
 // Given the adjoint nbar of a facet's unit normal, add the vertex adjoints.
 __device__ __forceinline__ void normal_to_vertices(const FacetDev& F, int4 tv, const double nbar[3],
-                                                   unsigned long long* __restrict__ vbar, double extraA[3]) {
+                                                   unsigned long long* __restrict__ vbar, uint32_t* status,
+                                                   double extraA[3]) {
   double N[3];
   cross3(F.e0, F.e1, N);
   const double len = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
@@ -127,9 +144,9 @@ __device__ __forceinline__ void normal_to_vertices(const FacetDev& F, int4 tv, c
   double e0b[3], e1b[3];
   cross3(F.e1, Nbar, e0b);   // dN = de0 x e1 + e0 x de1
   cross3(Nbar, F.e0, e1b);
-  fix_add3(vbar, tv.x, extraA[0] - e0b[0] - e1b[0], extraA[1] - e0b[1] - e1b[1], extraA[2] - e0b[2] - e1b[2]);
-  fix_add3(vbar, tv.y, e0b[0], e0b[1], e0b[2]);
-  fix_add3(vbar, tv.z, e1b[0], e1b[1], e1b[2]);
+  fix_add3(vbar, status, tv.x, extraA[0] - e0b[0] - e1b[0], extraA[1] - e0b[1] - e1b[1], extraA[2] - e0b[2] - e1b[2]);
+  fix_add3(vbar, status, tv.y, e0b[0], e0b[1], e0b[2]);
+  fix_add3(vbar, status, tv.z, e1b[0], e1b[1], e1b[2]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_step_adjoint(
@@ -139,7 +156,7 @@ __global__ __launch_bounds__(kBlock) void k_step_adjoint(
     const int4* __restrict__ tri_vert, const int* __restrict__ fseg_before, const int* __restrict__ fseg_after,
     const double* __restrict__ fu_after, int n_feat, int n_seg, const SegDev* __restrict__ segs,
     const int2* __restrict__ seg_vert, uint32_t move_mask, const float4* __restrict__ xbar_next,
-    float4* __restrict__ ybar, float4* __restrict__ xbar, unsigned long long* __restrict__ vbar) {
+    float4* __restrict__ ybar, float4* __restrict__ xbar, unsigned long long* __restrict__ vbar, uint32_t* status) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float4 p = pos[i];
@@ -168,8 +185,8 @@ __global__ __launch_bounds__(kBlock) void k_step_adjoint(
           double d[3];
           for (int q = 0; q < 3; ++q) d[q] = (w[q] - wt * B.t[q]) / B.len;
           const int2 sv = seg_vert[s2];
-          fix_add3(vbar, sv.y, d[0], d[1], d[2]);
-          fix_add3(vbar, sv.x, xb.x - d[0], xb.y - d[1], xb.z - d[2]);
+          fix_add3(vbar, status, sv.y, d[0], d[1], d[2]);
+          fix_add3(vbar, status, sv.x, xb.x - d[0], xb.y - d[1], xb.z - d[2]);
         }
         {
           // t_s0 through du = dt^2 a.t_s0, and P0_s0 through u = t_s0.(x - P0_s0)
@@ -178,8 +195,8 @@ __global__ __launch_bounds__(kBlock) void k_step_adjoint(
           double d[3];
           for (int q = 0; q < 3; ++q) d[q] = (w[q] - wt * A.t[q]) / A.len;
           const int2 sv = seg_vert[s0];
-          fix_add3(vbar, sv.y, d[0], d[1], d[2]);
-          fix_add3(vbar, sv.x, -d[0] - gu * A.t[0], -d[1] - gu * A.t[1], -d[2] - gu * A.t[2]);
+          fix_add3(vbar, status, sv.y, d[0], d[1], d[2]);
+          fix_add3(vbar, status, sv.x, -d[0] - gu * A.t[0], -d[1] - gu * A.t[1], -d[2] - gu * A.t[2]);
         }
         if (s2 != s0) {
           // the walk's direction, recomputed as the forward computed du
@@ -195,8 +212,8 @@ __global__ __launch_bounds__(kBlock) void k_step_adjoint(
             const double sg = fwd ? -gu : gu;
             const SegDev C = segs[k];
             const int2 sv = seg_vert[k];
-            fix_add3(vbar, sv.y, sg * C.t[0], sg * C.t[1], sg * C.t[2]);
-            fix_add3(vbar, sv.x, -sg * C.t[0], -sg * C.t[1], -sg * C.t[2]);
+            fix_add3(vbar, status, sv.y, sg * C.t[0], sg * C.t[1], sg * C.t[2]);
+            fix_add3(vbar, status, sv.x, -sg * C.t[0], -sg * C.t[1], -sg * C.t[2]);
             if (fwd) k = k + 1 < A.hi ? k + 1 : (A.closed ? A.lo : -1);
             if (k < 0) break;
           }
@@ -230,12 +247,12 @@ __global__ __launch_bounds__(kBlock) void k_step_adjoint(
           nbar_t[q] = -d * xbv[q] - ym[q] * nx;
           Adir[q] = Ft.n[q] * nx;
         }
-        normal_to_vertices(Ft, tri_vert[t], nbar_t, vbar, Adir);
+        normal_to_vertices(Ft, tri_vert[t], nbar_t, vbar, status, Adir);
         // tangential displacement with the owner normal: y = x + tau (a - (a.n) n)
         const double ny = Fo.n[0] * yb[0] + Fo.n[1] * yb[1] + Fo.n[2] * yb[2];
         double nbar_o[3], zero[3] = {0.0, 0.0, 0.0};
         for (int q = 0; q < 3; ++q) nbar_o[q] = -tau * (a[q] * ny + an * yb[q]);
-        normal_to_vertices(Fo, tri_vert[o], nbar_o, vbar, zero);
+        normal_to_vertices(Fo, tri_vert[o], nbar_o, vbar, status, zero);
         yb_out = make_float4(float(tau * (yb[0] - Fo.n[0] * ny)), float(tau * (yb[1] - Fo.n[1] * ny)),
                              float(tau * (yb[2] - Fo.n[2] * ny)), 0.0f);
         xb_out = make_float4(float(yb[0]), float(yb[1]), float(yb[2]), 0.0f);
@@ -252,7 +269,7 @@ __global__ __launch_bounds__(kBlock) void k_fixed_adjoint(const float4* __restri
                                                           int n_seg, int n_vert, const SegDev* __restrict__ segs,
                                                           const int2* __restrict__ seg_vert, uint32_t move_mask,
                                                           const float4* __restrict__ xbar,
-                                                          unsigned long long* __restrict__ vbar) {
+                                                          unsigned long long* __restrict__ vbar, uint32_t* status) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int tag = tag_of(pos[i].w);
@@ -261,7 +278,7 @@ __global__ __launch_bounds__(kBlock) void k_fixed_adjoint(const float4* __restri
   const float4 xb = xbar[i];
   if (tag == FPPG_TAG_SINGULAR) {
     const int v = owner[i];
-    if (v >= 0 && v < n_vert) fix_add3(vbar, v, xb.x, xb.y, xb.z);
+    if (v >= 0 && v < n_vert) fix_add3(vbar, status, v, xb.x, xb.y, xb.z);
   } else if (tag == FPPG_TAG_FEATURE) {
     const int slot = owner[i];
     const int s = (slot >= 0 && slot < n_feat) ? feat_seg[slot] : -1;
@@ -273,8 +290,8 @@ __global__ __launch_bounds__(kBlock) void k_fixed_adjoint(const float4* __restri
     const double tx = S.t[0] * xb.x + S.t[1] * xb.y + S.t[2] * xb.z;
     const double c = u / S.len;
     const double p1[3] = {c * (xb.x - S.t[0] * tx), c * (xb.y - S.t[1] * tx), c * (xb.z - S.t[2] * tx)};
-    fix_add3(vbar, sv.y, p1[0], p1[1], p1[2]);
-    fix_add3(vbar, sv.x, xb.x - p1[0], xb.y - p1[1], xb.z - p1[2]);
+    fix_add3(vbar, status, sv.y, p1[0], p1[1], p1[2]);
+    fix_add3(vbar, status, sv.x, xb.x - p1[0], xb.y - p1[1], xb.z - p1[2]);
   }
 }
 
@@ -382,7 +399,7 @@ extern "C" fppg_status fppg_step_adjoint(fppg_ctx* ctx, const fppg_geom* geom, i
       geom->d_facet, geom->d_tri_vert, fseg_before, fseg_after, fu_after, n_feat, int(geom->n_seg), geom->d_seg,
       geom->d_seg_vert, move_mask, reinterpret_cast<const float4*>(xbar_next),
       reinterpret_cast<float4*>(ybar), reinterpret_cast<float4*>(xbar),
-      reinterpret_cast<unsigned long long*>(vbar_fixed));
+      reinterpret_cast<unsigned long long*>(vbar_fixed), ctx->d_status);
   FPPG_HIP(ctx, hipGetLastError());
   return FPPG_OK;
 }
@@ -400,7 +417,7 @@ extern "C" fppg_status fppg_fixed_adjoint(fppg_ctx* ctx, const fppg_geom* geom, 
   k_fixed_adjoint<<<grid_for(n), kBlock, 0, static_cast<hipStream_t>(stream)>>>(
       reinterpret_cast<const float4*>(pos), owner, feat_seg, feat_u, int(n), n_feat, int(geom->n_seg),
       int(geom->n_vert), geom->d_seg, geom->d_seg_vert, move_mask, reinterpret_cast<const float4*>(xbar),
-      reinterpret_cast<unsigned long long*>(vbar_fixed));
+      reinterpret_cast<unsigned long long*>(vbar_fixed), ctx->d_status);
   FPPG_HIP(ctx, hipGetLastError());
   return FPPG_OK;
 }

@@ -10,7 +10,12 @@
 //   scan      cell_start = exclusive prefix sum of count (reduce / top / down)
 //   scatter   slot = cell_start[key] + rank: id, source index and key to slot
 //   final     inside each cell, the rank of the particle's id among the cell's
-//             ids gives its final slot; gather pos/id/owner there
+//             ids gives its final slot; gather pos/id/owner there. A lane counts
+//             the smaller ids of its cell, which bounds the work at
+//             kRankDirect^2 per cell; a fuller cell (a clump, or the quarantine
+//             cell of many non-finite particles) is listed instead, and
+//             k_final_big sorts it: ids sorted in LDS chunks, then merged in
+//             passes of doubling width (O(m log m) per cell of m particles)
 #include "internal.h"
 
 namespace fppg {
@@ -162,15 +167,23 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const int* __restrict__ key,
   tmp_key[slot] = k;
 }
 
+// Cells of more particles than this are ranked by k_final_big.
+constexpr int kRankDirect = 64;
+
 __global__ __launch_bounds__(kBlock) void k_final(const int* __restrict__ tmp_id, const int* __restrict__ tmp_src,
                                                   const int* __restrict__ tmp_key, const int* __restrict__ cell_start,
                                                   int n, const float4* __restrict__ pos_in,
                                                   const int* __restrict__ owner_in, float4* __restrict__ pos_out,
-                                                  int* __restrict__ id_out, int* __restrict__ owner_out) {
+                                                  int* __restrict__ id_out, int* __restrict__ owner_out,
+                                                  int* __restrict__ big, int* __restrict__ big_count) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const int k = tmp_key[s];
   const int b = cell_start[k], e = cell_start[k + 1];
+  if (e - b > kRankDirect) {
+    if (s == b) big[atomicAdd(big_count, 1)] = k;   // one entry per cell; the list's order does not matter
+    return;
+  }
   const int my = tmp_id[s];
   int r = 0;
   for (int t = b; t < e; ++t) r += tmp_id[t] < my;
@@ -179,6 +192,109 @@ __global__ __launch_bounds__(kBlock) void k_final(const int* __restrict__ tmp_id
   pos_out[dst] = pos_in[src];
   id_out[dst] = my;
   owner_out[dst] = owner_in[src];
+}
+
+constexpr int kBigThreads = 1024;
+constexpr int kBigChunk = 4096;   // (id, source) pairs sorted together in LDS
+constexpr int kBigBlocks = 64;
+
+// (id, source slot) as one unsigned key ordered as (signed id, slot)
+__device__ __forceinline__ uint64_t id_slot_key(int id, int slot) {
+  return (uint64_t(uint32_t(id) ^ 0x80000000u) << 32) | uint32_t(slot);
+}
+
+// Ascending bitonic sort of kBigChunk keys in LDS by the whole block.
+__device__ void lds_bitonic_sort(uint64_t* sh) {
+  for (int size = 2; size <= kBigChunk; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = threadIdx.x; t < kBigChunk / 2; t += kBigThreads) {
+        const int lo = 2 * t - (t & (stride - 1));   // the partner index with the stride bit clear
+        const int hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const uint64_t a = sh[lo], c = sh[hi];
+        if ((a > c) == up) {
+          sh[lo] = c;
+          sh[hi] = a;
+        }
+      }
+      __syncthreads();
+    }
+}
+
+// Number of entries of the sorted run [lo, hi) of (id, src) below (x, xs), or
+// at or below it with `upto` (a stable merge: left-run entries count the right
+// run's smaller keys, right-run entries the left run's smaller or equal ones).
+__device__ __forceinline__ int run_rank(const int* __restrict__ rid, const int* __restrict__ rsrc, int lo, int hi,
+                                        int x, int xs, bool upto) {
+  const int base = lo;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    const int y = rid[mid], ys = rsrc[mid];
+    const bool before = (y < x) || (y == x && (upto ? ys <= xs : ys < xs));
+    if (before)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo - base;
+}
+
+// One block per listed cell (blocks stride over the list): the cell's slots
+// [b, e) of tmp_id / tmp_src are sorted by (id, source) — chunks of kBigChunk
+// in LDS, written back in place, then merge passes ping-ponging with the same
+// slots of two scratch arrays (the key and rank arrays of the counting pass,
+// free by now) — and gathered to the output.
+__global__ __launch_bounds__(kBigThreads) void k_final_big(int* __restrict__ tmp_id, int* __restrict__ tmp_src,
+                                                           const int* __restrict__ cell_start,
+                                                           const int* __restrict__ big,
+                                                           const int* __restrict__ big_count,
+                                                           int* __restrict__ scratch_id, int* __restrict__ scratch_src,
+                                                           const float4* __restrict__ pos_in,
+                                                           const int* __restrict__ owner_in,
+                                                           float4* __restrict__ pos_out, int* __restrict__ id_out,
+                                                           int* __restrict__ owner_out) {
+  __shared__ uint64_t sh[kBigChunk];
+  const int nbig = *big_count;
+  for (int c = blockIdx.x; c < nbig; c += gridDim.x) {
+    const int k = big[c];
+    const int b = cell_start[k], m = cell_start[k + 1] - b;
+    for (int c0 = 0; c0 < m; c0 += kBigChunk) {
+      const int len = min(kBigChunk, m - c0);
+      for (int t = threadIdx.x; t < kBigChunk; t += kBigThreads)
+        sh[t] = t < len ? id_slot_key(tmp_id[b + c0 + t], tmp_src[b + c0 + t]) : ~0ull;
+      __syncthreads();
+      lds_bitonic_sort(sh);
+      for (int t = threadIdx.x; t < len; t += kBigThreads) {
+        tmp_id[b + c0 + t] = int(uint32_t(sh[t] >> 32) ^ 0x80000000u);
+        tmp_src[b + c0 + t] = int(uint32_t(sh[t]));
+      }
+      __syncthreads();
+    }
+    int *aid = tmp_id + b, *asrc = tmp_src + b, *bid = scratch_id + b, *bsrc = scratch_src + b;
+    for (int64_t w = kBigChunk; w < m; w *= 2) {
+      for (int p = threadIdx.x; p < m; p += kBigThreads) {
+        const int pair = int(p / (2 * w) * (2 * w));
+        const bool left = p < pair + w;
+        const int os = int(left ? pair + w : pair);              // the other run of the pair
+        const int oe = int(left ? std::min<int64_t>(pair + 2 * w, m) : pair + w);
+        const int x = aid[p], xs = asrc[p];
+        const int own = int(p - (left ? pair : pair + w));
+        const int other = os < oe ? run_rank(aid, asrc, os, oe, x, xs, !left) : 0;
+        bid[pair + own + other] = x;
+        bsrc[pair + own + other] = xs;
+      }
+      __syncthreads();
+      int* t = aid; aid = bid; bid = t;
+      t = asrc; asrc = bsrc; bsrc = t;
+    }
+    for (int r = threadIdx.x; r < m; r += kBigThreads) {
+      const int src = asrc[r];
+      pos_out[b + r] = pos_in[src];
+      id_out[b + r] = aid[r];
+      owner_out[b + r] = owner_in[src];
+    }
+    __syncthreads();
+  }
 }
 
 // ---- list of the moving particles (sorted indices, ascending) -----------------------------
@@ -266,6 +382,24 @@ __global__ __launch_bounds__(kBlock) void k_part_write(const float4* __restrict_
 
 static inline int grid_for(int64_t n, int block) { return int((n + block - 1) / block); }
 
+__global__ void k_scan_total(const int* __restrict__ in, int64_t n, int* __restrict__ out) {
+  if (threadIdx.x == 0) out[n] = n > 0 ? out[n - 1] + in[n - 1] : 0;
+}
+
+fppg_status exclusive_scan(fppg_ctx* ctx, const int* in, int64_t n, int* out, int* blocksum, hipStream_t s) {
+  const int nb = int((n + kScanTile - 1) / kScanTile);
+  if (n > 0) {
+    k_scan_reduce<<<nb, kScanThreads, 0, s>>>(in, n, blocksum);
+    k_scan_top<<<1, kScanThreads, 0, s>>>(blocksum, nb);
+    k_scan_down<<<nb, kScanThreads, 0, s>>>(in, n, blocksum, out, 0);
+  }
+  k_scan_total<<<1, 64, 0, s>>>(in, n, out);   // after k_scan_down, which writes out[n] = 0
+  FPPG_HIP(ctx, hipGetLastError());
+  return FPPG_OK;
+}
+
+int64_t scan_blocksum_len(int64_t n) { return (n + kScanTile - 1) / kScanTile + 2; }
+
 }  // namespace fppg
 
 using namespace fppg;
@@ -294,11 +428,13 @@ extern "C" fppg_status fppg_build_cells(fppg_ctx* ctx, const fppg_geom* geom, in
   int* tmp_key = reinterpret_cast<int*>(w + L.tmp_key);
   int* count = reinterpret_cast<int*>(w + L.count);
   int* blocksum = reinterpret_cast<int*>(w + L.blocksum);
+  int* big = reinterpret_cast<int*>(w + L.big);
   const int64_t nc = geom->ncell + 1;   // the geometries' cells and the quarantine cell
+  int* big_count = count + nc;          // the slot after the scanned counts
   const int nb = int((nc + kScanTile - 1) / kScanTile);
   const int ni = int(n);
   PhaseTimer timer(ctx, 0, s);
-  k_fill_i32<<<std::min(grid_for(nc, kBlock), 4096), kBlock, 0, s>>>(count, nc, 0);
+  k_fill_i32<<<std::min(grid_for(nc + 1, kBlock), 4096), kBlock, 0, s>>>(count, nc + 1, 0);
   if (ni > 0)
     k_key_count<<<grid_for(ni, kBlock), kBlock, 0, s>>>(reinterpret_cast<const float4*>(pos_in), ni, geom->d_geom,
                                                         geom->n_geom, int(geom->ncell), key, rank, count,
@@ -310,7 +446,11 @@ extern "C" fppg_status fppg_build_cells(fppg_ctx* ctx, const fppg_geom* geom, in
     k_scatter<<<grid_for(ni, kBlock), kBlock, 0, s>>>(key, rank, id_in, cell_start, ni, tmp_id, tmp_src, tmp_key);
     k_final<<<grid_for(ni, kBlock), kBlock, 0, s>>>(tmp_id, tmp_src, tmp_key, cell_start, ni,
                                                     reinterpret_cast<const float4*>(pos_in), owner_in,
-                                                    reinterpret_cast<float4*>(pos_out), id_out, owner_out);
+                                                    reinterpret_cast<float4*>(pos_out), id_out, owner_out,
+                                                    big, big_count);
+    k_final_big<<<kBigBlocks, kBigThreads, 0, s>>>(tmp_id, tmp_src, cell_start, big, big_count, key, rank,
+                                                   reinterpret_cast<const float4*>(pos_in), owner_in,
+                                                   reinterpret_cast<float4*>(pos_out), id_out, owner_out);
   }
   FPPG_HIP(ctx, hipGetLastError());
   return FPPG_OK;

@@ -32,6 +32,7 @@ WsLayout ws_layout(const Geom* g, int64_t n) {
   L.tmp_key = o;  o += up256(4 * N);
   L.count = o;    o += up256(4 * (nc + 2));
   L.blocksum = o; o += up256(4 * ((nc + 1 + 4095) / 4096 + 2));
+  L.big = o;      o += up256(4 * (N / 65 + 1));   // cells of more than 64 particles: at most N / 65
   L.build_end = o;
   o = 0;
   L.accel = o;    o += up256(16 * N);
@@ -56,68 +57,20 @@ WsLayout ws_layout(const Geom* g, int64_t n) {
   return L;
 }
 
-// ---- facet search grid (host) ------------------------------------------------------------
-
-// Separating-axis test of a triangle against an axis-aligned box given by its
-// centre and half extents (the triangle-box overlap test of Akenine-Moeller,
-// written as the generic 13-axis separating-axis theorem: the 3 box normals,
-// the triangle normal and the 9 products of box axes with triangle edges).
-static bool tri_box_overlap(const double c[3], const double hw[3], const double* A,
-                            const double* B, const double* C) {
-  double v[3][3];
-  for (int q = 0; q < 3; ++q) {
-    v[0][q] = A[q] - c[q];
-    v[1][q] = B[q] - c[q];
-    v[2][q] = C[q] - c[q];
-  }
-  double e[3][3];
-  for (int q = 0; q < 3; ++q) {
-    e[0][q] = v[1][q] - v[0][q];
-    e[1][q] = v[2][q] - v[1][q];
-    e[2][q] = v[0][q] - v[2][q];
-  }
-  auto separated = [&](const double L[3]) {
-    if (L[0] == 0.0 && L[1] == 0.0 && L[2] == 0.0) return false;
-    double p0 = L[0] * v[0][0] + L[1] * v[0][1] + L[2] * v[0][2];
-    double p1 = L[0] * v[1][0] + L[1] * v[1][1] + L[2] * v[1][2];
-    double p2 = L[0] * v[2][0] + L[1] * v[2][1] + L[2] * v[2][2];
-    double lo = std::min(p0, std::min(p1, p2)), hi = std::max(p0, std::max(p1, p2));
-    double r = hw[0] * std::fabs(L[0]) + hw[1] * std::fabs(L[1]) + hw[2] * std::fabs(L[2]);
-    return lo > r || hi < -r;
-  };
-  for (int a = 0; a < 3; ++a) {
-    double L[3] = {0, 0, 0};
-    L[a] = 1.0;
-    if (separated(L)) return false;
-  }
-  double nrm[3] = {e[0][1] * e[1][2] - e[0][2] * e[1][1], e[0][2] * e[1][0] - e[0][0] * e[1][2],
-                   e[0][0] * e[1][1] - e[0][1] * e[1][0]};
-  if (separated(nrm)) return false;
-  for (int a = 0; a < 3; ++a) {
-    for (int k = 0; k < 3; ++k) {
-      double u[3] = {0, 0, 0};
-      u[a] = 1.0;
-      double L[3] = {u[1] * e[k][2] - u[2] * e[k][1], u[2] * e[k][0] - u[0] * e[k][2],
-                     u[0] * e[k][1] - u[1] * e[k][0]};
-      if (separated(L)) return false;
-    }
-  }
-  return true;
-}
+// ---- facet search grid -------------------------------------------------------------------
 
 struct SearchGrid {
   double origin[3], cell, inv;
   int32_t dims[3];
-  std::vector<int64_t> start;  // [ncell + 1]
-  std::vector<int32_t> tri;    // global facet ids, ascending within a cell
-  std::vector<uint8_t> flag;
 };
 
-// Register every facet in every search cell it touches. Cells are padded by a
-// relative margin so that a point on a facet whose cell index is computed with
-// rounding still finds the facet in the computed cell.
-static fppg_status build_search_grid(fppg_ctx* ctx, const fppg_geom_desc& d, int32_t tri_begin,
-                                     SearchGrid& sg, const std::vector<uint8_t>& facet_class) {
+// The facet search grid of one geometry: cells of edge R (1 + 2^-6) over the
+// mesh's box widened by two cells. Its facets are registered on the device
+// (register.hip: subdivision, separating-axis test against the cells widened
+// by a relative pad of 1e-6 cell, so that a point on a facet whose cell index
+// is computed with rounding still finds the facet in that cell). Facets of an
+// assembly that never lie on its boundary are left out.
+static fppg_status search_grid_params(fppg_ctx* ctx, const fppg_geom_desc& d, SearchGrid& sg) {
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   for (int32_t v = 0; v < d.n_vert; ++v)
     for (int q = 0; q < 3; ++q) {
@@ -135,39 +88,13 @@ static fppg_status build_search_grid(fppg_ctx* ctx, const fppg_geom_desc& d, int
     ncell *= sg.dims[q];
   }
   if (ncell > (int64_t(1) << 30)) return fail(ctx, FPPG_E_CAPACITY, "facet search grid exceeds 2^30 cells");
-  const double pad = 1e-6 * sg.cell;
-  std::vector<std::pair<int64_t, int32_t>> reg;
-  for (int32_t t = 0; t < d.n_tri; ++t) {
-    if (!facet_class.empty() && facet_class[t] == 0) continue;   // an assembly's facet never on its boundary
-    const double* P[3] = {d.vert + 3 * d.tri[3 * t], d.vert + 3 * d.tri[3 * t + 1], d.vert + 3 * d.tri[3 * t + 2]};
-    int32_t c0[3], c1[3];
-    for (int q = 0; q < 3; ++q) {
-      double mn = std::min(P[0][q], std::min(P[1][q], P[2][q])) - pad;
-      double mx = std::max(P[0][q], std::max(P[1][q], P[2][q])) + pad;
-      c0[q] = std::max(0, int32_t(std::floor((mn - sg.origin[q]) * sg.inv)));
-      c1[q] = std::min(sg.dims[q] - 1, int32_t(std::floor((mx - sg.origin[q]) * sg.inv)));
-    }
-    for (int32_t z = c0[2]; z <= c1[2]; ++z)
-      for (int32_t y = c0[1]; y <= c1[1]; ++y)
-        for (int32_t x = c0[0]; x <= c1[0]; ++x) {
-          double cen[3] = {sg.origin[0] + (x + 0.5) * sg.cell, sg.origin[1] + (y + 0.5) * sg.cell,
-                           sg.origin[2] + (z + 0.5) * sg.cell};
-          double hw[3] = {0.5 * sg.cell + pad, 0.5 * sg.cell + pad, 0.5 * sg.cell + pad};
-          if (tri_box_overlap(cen, hw, P[0], P[1], P[2]))
-            reg.emplace_back((int64_t(z) * sg.dims[1] + y) * sg.dims[0] + x, tri_begin + t);
-        }
-  }
-  if (reg.size() >= (size_t(1) << 31)) return fail(ctx, FPPG_E_CAPACITY, "facet search grid exceeds 2^31 entries");
-  sg.start.assign(ncell + 1, 0);
-  for (auto& r : reg) sg.start[r.first + 1]++;
-  for (int64_t c = 0; c < ncell; ++c) sg.start[c + 1] += sg.start[c];
-  sg.tri.resize(reg.size());
-  std::vector<int64_t> cur(sg.start.begin(), sg.start.end() - 1);
-  for (auto& r : reg) sg.tri[cur[r.first]++] = r.second;  // facets visited in ascending order
-  sg.flag.assign(ncell, 0);
-  for (int64_t c = 0; c < ncell; ++c)
-    if (sg.start[c + 1] > sg.start[c]) sg.flag[c] = kCellHasFacet;
   return FPPG_OK;
+}
+
+static int bits_for(uint64_t v) {
+  int b = 0;
+  while (b < 64 && (v >> b) != 0) ++b;
+  return b;
 }
 
 template <class T>
@@ -341,9 +268,8 @@ static fppg_status geom_create(fppg_ctx* ctx, const fppg_geom_desc* descs, int32
   std::vector<uint8_t> facet_class;   // of the current geometry's facets (assemblies only)
   std::vector<uint8_t> facet_mask;
   int32_t vert_off = 0;
-  std::vector<int32_t> tg_start;   // global
-  std::vector<int32_t> tg_tri;
-  std::vector<uint8_t> tg_flag;
+  std::vector<RegItem> reg_items;  // facets to register in the search grids
+  std::vector<RegGrid> reg_grids;  // one per geometry
   int64_t ncell = 0, part = 0, tg_cells = 0;
   int32_t tri_off = 0, seg_off = 0;
   for (int32_t g = 0; g < n_geom; ++g) {
@@ -450,8 +376,32 @@ static fppg_status geom_create(fppg_ctx* ctx, const fppg_geom_desc* descs, int32
     G.seg_end = seg_off;
     // facet search grid
     SearchGrid sg;
-    fppg_status st = build_search_grid(ctx, d, tri_off, sg, facet_class);
+    fppg_status st = search_grid_params(ctx, d, sg);
     if (st != FPPG_OK) return st;
+    {
+      RegGrid rg{};
+      for (int q = 0; q < 3; ++q) {
+        rg.o[q] = sg.origin[q];
+        rg.dims[q] = sg.dims[q];
+      }
+      rg.cell = sg.cell;
+      rg.inv = sg.inv;
+      rg.pad = 1e-6 * sg.cell;
+      rg.key_begin = tg_cells;
+      for (int32_t t = 0; t < d.n_tri; ++t) {
+        if (!facet_class.empty() && facet_class[t] == 0) continue;   // an assembly's facet never on its boundary
+        RegItem it{};
+        for (int q = 0; q < 3; ++q) {
+          it.a[q] = d.vert[3 * d.tri[3 * t] + q];
+          it.b[q] = d.vert[3 * d.tri[3 * t + 1] + q];
+          it.c[q] = d.vert[3 * d.tri[3 * t + 2] + q];
+        }
+        it.facet = tri_off + t;
+        it.grid = int(reg_grids.size());
+        reg_items.push_back(it);
+      }
+      reg_grids.push_back(rg);
+    }
     tri_off += d.n_tri;
     vert_off += d.n_vert;
     for (int q = 0; q < 3; ++q) {
@@ -462,24 +412,42 @@ static fppg_status geom_create(fppg_ctx* ctx, const fppg_geom_desc* descs, int32
     G.slab = (d.slab <= 0 || d.slab > d.dims[1]) ? d.dims[1] : d.slab;
     G.inv_slab = 1.0f / float(G.slab);
     G.tg_begin = tg_cells;
-    const int64_t base = int64_t(tg_tri.size());
-    if (base + int64_t(sg.tri.size()) >= (int64_t(1) << 31))
-      return fail(ctx, FPPG_E_CAPACITY, "facet search grid exceeds 2^31 entries");
-    for (size_t c = 0; c + 1 < sg.start.size(); ++c) tg_start.push_back(int32_t(base + sg.start[c]));
-    tg_tri.insert(tg_tri.end(), sg.tri.begin(), sg.tri.end());
-    tg_flag.insert(tg_flag.end(), sg.flag.begin(), sg.flag.end());
-    tg_cells += int64_t(sg.flag.size());
+    tg_cells += int64_t(sg.dims[0]) * sg.dims[1] * sg.dims[2];
+    if (tg_cells >= (int64_t(1) << 31)) return fail(ctx, FPPG_E_CAPACITY, "facet search grids exceed 2^31 cells");
   }
-  tg_start.push_back(int32_t(tg_tri.size()));
+  // the search grids of all geometries registered on the device in one pass
+  RegPairs reg{};
+  {
+    const fppg_status rst = register_facets(ctx, reg_items, reg_grids, false, bits_for(uint64_t(std::max<int64_t>(tg_cells - 1, 0))),
+                                            bits_for(uint64_t(std::max(tri_off - 1, 0))), &reg, nullptr);
+    if (rst != FPPG_OK) return rst;
+  }
+  int* d_tg_start = nullptr;
+  int* d_tg_tri = nullptr;
+  uint8_t* d_tg_flag = nullptr;
+  {
+    const fppg_status cst = registration_csr(ctx, reg, tg_cells, &d_tg_start, &d_tg_tri, &d_tg_flag, nullptr);
+    hipFree(reg.keys);
+    hipFree(reg.facets);
+    if (cst != FPPG_OK) return cst;
+  }
   Geom* geo = new (std::nothrow) fppg_geom();
-  if (!geo) return fail(ctx, FPPG_E_CAPACITY, "out of host memory");
+  if (!geo) {
+    hipFree(d_tg_start);
+    hipFree(d_tg_tri);
+    hipFree(d_tg_flag);
+    return fail(ctx, FPPG_E_CAPACITY, "out of host memory");
+  }
   geo->n_geom = n_geom;
   geo->k = k;
   geo->ncell = ncell;
   geo->n_tri = tri_off;
   geo->n_seg = seg_off;
   geo->tg_cells = tg_cells;
-  geo->tg_entries = int64_t(tg_tri.size());
+  geo->tg_entries = reg.n;
+  geo->d_tg_start = d_tg_start;
+  geo->d_tg_tri = d_tg_tri;
+  geo->d_tg_flag = d_tg_flag;
   geo->n_part = part;
   geo->n_active = part;
   geo->n_vert = vert_off;
@@ -491,8 +459,6 @@ static fppg_status geom_create(fppg_ctx* ctx, const fppg_geom_desc* descs, int32
       (st = upload(ctx, &geo->d_n32, n32)) != FPPG_OK || (st = upload(ctx, &geo->d_seg, segs)) != FPPG_OK ||
       (st = upload(ctx, &geo->d_tri_vert, tri_vert)) != FPPG_OK ||
       (st = upload(ctx, &geo->d_seg_vert, seg_vert)) != FPPG_OK ||
-      (st = upload(ctx, &geo->d_tg_start, tg_start)) != FPPG_OK ||
-      (st = upload(ctx, &geo->d_tg_tri, tg_tri)) != FPPG_OK || (st = upload(ctx, &geo->d_tg_flag, tg_flag)) != FPPG_OK ||
       (st = upload(ctx, &geo->d_facet_part, facet_part)) != FPPG_OK || (st = upload(ctx, &geo->d_part, parts)) != FPPG_OK ||
       (st = upload(ctx, &geo->d_plane, planes)) != FPPG_OK ||
       (st = upload(ctx, &geo->d_facet_mask, facet_mask)) != FPPG_OK) {
@@ -652,6 +618,18 @@ fppg_status fppg_geom_info(const fppg_geom* g, int64_t* ncell, int64_t* n_tri, i
   if (n_seg) *n_seg = g->n_seg;
   if (search_cells) *search_cells = g->tg_cells;
   if (search_entries) *search_entries = g->tg_entries;
+  return FPPG_OK;
+}
+
+fppg_status fppg_geom_search_grid(fppg_ctx* ctx, const fppg_geom* g, int32_t* start, int32_t* tri, uint8_t* flag,
+                                  void* stream) {
+  if (!ctx || !g) return fail(ctx, FPPG_E_ARG, "null ctx/geom");
+  if (g->device != ctx->device) return fail(ctx, FPPG_E_ARG, "geometry and context on different devices");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (start) FPPG_HIP(ctx, hipMemcpyAsync(start, g->d_tg_start, size_t(g->tg_cells + 1) * 4, hipMemcpyDeviceToDevice, s));
+  if (tri && g->tg_entries > 0)
+    FPPG_HIP(ctx, hipMemcpyAsync(tri, g->d_tg_tri, size_t(g->tg_entries) * 4, hipMemcpyDeviceToDevice, s));
+  if (flag) FPPG_HIP(ctx, hipMemcpyAsync(flag, g->d_tg_flag, size_t(g->tg_cells), hipMemcpyDeviceToDevice, s));
   return FPPG_OK;
 }
 

@@ -21,25 +21,33 @@ __global__ void k_zero_f32(float* __restrict__ a, int n) {
 
 // ---- forces + amax ---------------------------------------------------------------------
 
-// One source: K-less pair term (1 - r/2h)^3 r_ij if j is a source of i.
-// RANKED: check rank(tag_j) <= rank(tag_i) as tag_j <= T (T = rank, or 7 for
-// volume receivers which take every class). The receiver itself contributes
-// r = 0, so it needs no test (the count subtracts it). No clamp of 1 - r/2h at
-// 0: a pair that passes the predicate has r < 2h up to the rounding of the
-// square root, so the term is at worst -(2^-23)^3 instead of 0.
+// One source: K-less pair term (1 - r/2h)^3 r_ij with 1 - r/2h clamped to
+// [0, 1], which is zero at and beyond the support radius, so that the sum
+// needs no neighbour test: a candidate beyond 2h adds exact zeros. Next to the
+// sum over the predicate's neighbours (the binary32 test |r|^2 < fl32(2h)^2)
+// it differs only by pairs within rounding of r = 2h, whose terms are below
+// 2^-69 of a unit-distance term. r^2 is taken with two FMAs and the clamp is
+// the FMA's output modifier: 14 VALU instructions per candidate.
+// RANKED: sources of a class above the receiver's (tag_j > T; T = 7 for volume
+// receivers, which take every class) add nothing. The receiver itself adds
+// r = 0. COUNT: counts the predicate's neighbours (the receiver subtracted
+// by the caller) for the pair statistics.
 template <bool RANKED, bool COUNT>
 __device__ __forceinline__ void add_pair(const float4 p, const float4 q, float rc2, float inv2h, uint32_t T,
                                          float& ax, float& ay, float& az, float& cnt) {
   const float dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
-  const float d2 = pair_d2(dx, dy, dz);
-  bool src = d2 < rc2;
-  if (RANKED) src = src & ((__float_as_uint(q.w) & 7u) <= T);
-  const float t = fmaf(-__builtin_amdgcn_sqrtf(d2), inv2h, 1.0f);
-  const float w = src ? t * t * t : 0.0f;
+  const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+  const float t = __builtin_amdgcn_fmed3f(fmaf(-__builtin_amdgcn_sqrtf(r2), inv2h, 1.0f), 0.0f, 1.0f);
+  float w = t * t * t;
+  bool src = true;
+  if (RANKED) {
+    src = (__float_as_uint(q.w) & 7u) <= T;
+    w = src ? w : 0.0f;
+  }
   ax = fmaf(w, dx, ax);
   ay = fmaf(w, dy, ay);
   az = fmaf(w, dz, az);
-  if (COUNT) cnt += src ? 1.0f : 0.0f;
+  if (COUNT) cnt += (src && pair_d2(dx, dy, dz) < rc2) ? 1.0f : 0.0f;
 }
 
 // The B receivers of chunk blk (launch slots blk * B ...): forces, and the

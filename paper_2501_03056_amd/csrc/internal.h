@@ -170,7 +170,7 @@ constexpr int kHeavyGroupMax = 8;   // projection: volume-pass blocks served by 
 // Workspace layout (byte offsets from the workspace base, 256-aligned).
 struct WsLayout {
   // build_cells
-  size_t key, rank, tmp_id, tmp_src, tmp_key, count, blocksum, build_end;
+  size_t key, rank, tmp_id, tmp_src, tmp_key, count, blocksum, big, build_end;
   // relax_step
   size_t accel, step_end;
   // moving_list (block counts, their offsets, scan partials)
@@ -183,6 +183,41 @@ struct WsLayout {
   size_t total;
 };
 WsLayout ws_layout(const Geom* g, int64_t n);
+
+// Facet registration on uniform grids (register.hip).
+struct RegGrid {
+  double o[3];         // origin of cell (0, 0, 0)
+  double cell, inv;    // cell edge and its reciprocal
+  double pad;          // boxes widened by pad on every side
+  int dims[3];
+  int unused;
+  int64_t key_begin;   // dense keys: index of this grid's first cell
+};
+struct RegItem {       // a triangle to register: its vertices, facet and grid
+  double a[3], b[3], c[3];
+  int facet, grid;
+};
+struct RegPairs {      // unique (key, facet) pairs sorted by (key, facet), device
+  uint64_t* keys = nullptr;
+  uint32_t* facets = nullptr;
+  int64_t n = 0;
+  int levels = 0;      // subdivision levels
+};
+// Subdivide and register `items` (facets, by grid); key = Morton code of the
+// cell (morton) or key_begin + its dense index. key_bits / facet_bits bound
+// the keys and facet ids (the radix passes). Synchronous on s.
+fppg_status register_facets(fppg_ctx* ctx, const std::vector<RegItem>& items, const std::vector<RegGrid>& grids,
+                            bool morton, int key_bits, int facet_bits, RegPairs* out, hipStream_t s);
+// Dense CSR of registered pairs with dense keys < n_cells: start [n_cells + 1],
+// facets [pairs.n] (int32), non-empty flags [n_cells] (kCellHasFacet); device
+// arrays the caller frees. Synchronous on s.
+fppg_status registration_csr(fppg_ctx* ctx, const RegPairs& pairs, int64_t n_cells, int** start, int** tri,
+                             uint8_t** flag, hipStream_t s);
+
+// Exclusive prefix sum of in[0..n) into out[0..n), out[n] = the total
+// (cells.hip). blocksum: scan_blocksum_len(n) ints of device scratch.
+fppg_status exclusive_scan(fppg_ctx* ctx, const int* in, int64_t n, int* out, int* blocksum, hipStream_t s);
+int64_t scan_blocksum_len(int64_t n);
 
 // Deterministic FP64 reductions (linalg.hip): per-block partial sums in a
 // fixed order, then one block sums the partials in index order.

@@ -97,3 +97,66 @@ def cells_boolean(cls_a: torch.Tensor, cls_b: torch.Tensor, op: int, ctx: Contex
     stream = ctypes.c_void_p(torch.cuda.current_stream(a.device).cuda_stream)
     check(ctx.lib.fppg_cells_boolean(ctx.handle, ptr(a), ptr(b), a.numel(), int(op), ptr(out), stream), ctx.handle)
     return out
+
+
+class SparseGrid:
+    """The sparse storage of the cells a mesh meets (fppg_sparse_grid_*):
+    facet subdivision and registration on the grid (origin, cell, dims =
+    (nx, ny, nz)), C_compact in Morton order and the hash table of Eq. 10."""
+
+    def __init__(self, vert, tri, origin, cell: float, dims, pad: float = 0.0, hash_size: int = 0,
+                 device: int = 0, ctx: Context | None = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("SparseGrid needs a GPU (no CPU fallback)")
+        self.ctx = ctx or Context(device)
+        self.dev = torch.device("cuda", device)
+        vert = np.ascontiguousarray(vert, np.float64).reshape(-1, 3)
+        tri = np.ascontiguousarray(tri, np.int32).reshape(-1, 3)
+        o = (ctypes.c_double * 3)(*[float(v) for v in origin])
+        d = (ctypes.c_int32 * 3)(*[int(v) for v in dims])
+        h = ctypes.c_void_p()
+        check(self.ctx.lib.fppg_sparse_grid_create(self.ctx.handle, vert.ctypes.data_as(ctypes.c_void_p), len(vert),
+                                                   tri.ctypes.data_as(ctypes.c_void_p), len(tri), o, float(cell), d,
+                                                   float(pad), int(hash_size), ctypes.byref(h)), self.ctx.handle)
+        self.handle = h
+        v = L.SparseGridView()
+        check(self.ctx.lib.fppg_sparse_grid_info(self.handle, ctypes.byref(v)), self.ctx.handle)
+        self.n_entry, self.n_cell, self.hash_size, self.levels = v.n_entry, v.n_cell, v.hash_size, v.levels
+
+    def arrays(self) -> dict:
+        """Device copies of the structure's arrays."""
+        def e(n, dt):
+            return torch.empty(max(int(n), 1), dtype=dt, device=self.dev)
+        t = {"facets": e(self.n_entry, torch.int32), "morton": e(self.n_cell, torch.int64),
+             "begin": e(self.n_cell, torch.int32), "length": e(self.n_cell, torch.int32),
+             "order": e(self.n_cell, torch.int32), "h_begin": e(self.hash_size + 1, torch.int32),
+             "h_length": e(self.hash_size, torch.int32)}
+        stream = ctypes.c_void_p(torch.cuda.current_stream(self.dev).cuda_stream)
+        check(self.ctx.lib.fppg_sparse_grid_copy(self.ctx.handle, self.handle, *[ptr(t[k]) for k in
+                                                 ("facets", "morton", "begin", "length", "order", "h_begin",
+                                                  "h_length")], stream), self.ctx.handle)
+        n = {"facets": self.n_entry, "morton": self.n_cell, "begin": self.n_cell, "length": self.n_cell,
+             "order": self.n_cell, "h_begin": self.hash_size + 1, "h_length": self.hash_size}
+        return {k: v[: int(n[k])] for k, v in t.items()}
+
+    def lookup(self, points: torch.Tensor):
+        """(begin, length) [P] of the facets of each point's cell (-1, 0: none)."""
+        p = points.to(self.dev, torch.float64).contiguous()
+        n = p.shape[0]
+        b = torch.empty(max(n, 1), dtype=torch.int32, device=self.dev)
+        ln = torch.empty(max(n, 1), dtype=torch.int32, device=self.dev)
+        stream = ctypes.c_void_p(torch.cuda.current_stream(self.dev).cuda_stream)
+        check(self.ctx.lib.fppg_sparse_grid_lookup(self.ctx.handle, self.handle, n, ptr(p), ptr(b), ptr(ln), stream),
+              self.ctx.handle)
+        return b[:n], ln[:n]
+
+    def close(self):
+        if self.handle:
+            self.ctx.lib.fppg_sparse_grid_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

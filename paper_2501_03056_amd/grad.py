@@ -28,7 +28,7 @@ from __future__ import annotations
 
 import torch
 
-from ._lib import check, ptr
+from ._lib import S_FIXED_RANGE, check, ptr
 
 
 def lattice_density(dx: float, h: float) -> float:
@@ -149,6 +149,10 @@ def backward(r, tape: Tape, n_vert: int | None = None) -> torch.Tensor:
               ptr(tape.feat0[1]), r.n_feat, r.move_mask, ptr(xb), ptr(vbar), r.stream)
     vd = torch.empty(3 * n_vert, dtype=torch.float64, device=dev)
     _lib_call(r, "fppg_fixed_to_double", 3 * n_vert, ptr(vbar), ptr(vd), r.stream)
+    # the device status is read (and cleared) here: a vertex gradient outside
+    # the fixed-point range is an error, not a value
+    if r.read_status() & S_FIXED_RANGE:
+        raise FloatingPointError("a vertex gradient left the fixed-point range |g| < 2^23")
     _restore(r, tape.final)
     return vd.view(n_vert, 3)
 

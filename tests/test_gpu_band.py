@@ -39,7 +39,7 @@ def _distance(wl):
 CASES = {
     "cube_n12": (lambda: synth.cube_workload(n=12, seed=3), 2.5 / 12),
     "sphere_l3": (lambda: synth.sphere_workload(level=3, dx=0.08, seed=2), 0.2),
-    "batch3": (lambda: synth.workload.batch_workload(n_geom=3, n_min=3000, n_max=8000, seed=21), None),
+    "batch3": (lambda: synth.workload.solid_batch_workload(n_geom=3, n_min=3000, n_max=8000, seed=21), None),
     "gear_coarse": (lambda: synth.gear_workload(dx=0.04, seed=3, samples_per_period=12, rings=4), 0.1),
 }
 

@@ -116,3 +116,32 @@ def test_autograd_function_matches_the_driver():
     np.testing.assert_array_equal(V.grad.numpy(), 2.0 * g0)
     with pytest.raises(ValueError):
         RelaxedUniformity.apply(V.detach() + 1e-3, _relaxer(wl), 1, _rho0(wl), 1)
+
+
+@pytest.mark.parametrize("scale,flag", [(1.0, False), (6.0e6, True), (1.0e7, True)])
+def test_fixed_point_range_is_guarded(scale, flag):
+    """The vertex adjoint of the particles that do not move, with xbar = scale
+    along x for every particle: at 1 the sums are exact and unflagged; at 6e6
+    each contribution fits but the sums of a cube edge's feature particles at
+    one vertex pass 2^23; at 1e7 single contributions are out of range.
+    Both raise FPPG_S_FIXED_RANGE."""
+    from paper_2501_03056_amd._lib import S_FIXED_RANGE, ptr
+    from paper_2501_03056_amd.grad import _lib_call
+    wl = synth.cube_workload(n=8, seed=1)
+    r = _relaxer(wl)
+    r.build_cells()
+    r.read_status()
+    xb = torch.zeros((r.n, 4), dtype=torch.float32, device=r.dev)
+    xb[:, 0] = scale
+    vbar = torch.zeros(3 * r.n_vert, dtype=torch.int64, device=r.dev)
+    _lib_call(r, "fppg_fixed_adjoint", r.geom.handle, r.n, ptr(r.pos), ptr(r.owner), ptr(r.feat_seg),
+              ptr(r.feat_u), r.n_feat, r.move_mask, ptr(xb), ptr(vbar), r.stream)
+    st = r.read_status()
+    assert bool(st & S_FIXED_RANGE) == flag
+    if not flag:
+        # every singular and feature particle's adjoint lands on the vertices: the x sums equal their count
+        vd = vbar.view(-1, 3).cpu().numpy().astype(np.float64) / 2.0 ** 40
+        tags = wl.tag
+        want = float(np.sum((tags == synth.SINGULAR) | (tags == synth.FEATURE)))
+        assert vd[:, 0].sum() == pytest.approx(want, rel=1e-11)
+        assert np.abs(vd[:, 1:]).max() < 1e-9

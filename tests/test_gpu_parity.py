@@ -446,3 +446,37 @@ def test_receiver_list_gives_the_same_iterations(tier):
         assert np.array_equal(x, y)
     assert torch.equal(ra.counters, rb.counters)
     assert ra.read_status() == 0 and rb.read_status() == 0
+
+
+@pytest.mark.parametrize("n_clump,n_nan", [(65, 0), (4096, 0), (4097, 70), (20000, 0), (0, 9000), (9000, 5000)])
+def test_cells_bit_exact_with_crowded_cells(n_clump, n_nan):
+    """Cells of more than 64 particles (a clump inside one particle cell, the
+    quarantine cell of the non-finite particles) are ordered by id like the
+    others; the sizes cross the LDS chunk (4096) and need merge passes."""
+    from synth import meshes as M
+    base = synth.cube_workload(n=8, seed=1)
+    rng = np.random.Generator(np.random.PCG64(n_clump + 7 * n_nan))
+    centre = np.array([0.5, 0.5, 0.5]) + 0.01 * base.geoms[0].dx
+    clump = centre + rng.uniform(-1e-4, 1e-4, size=(n_clump, 3)) * base.geoms[0].dx
+    nan = np.full((n_nan, 3), np.nan)
+    pos = np.concatenate([base.pos.astype(np.float64), clump, nan])
+    tag = np.concatenate([base.tag, np.full(n_clump + n_nan, 3, np.int32)])
+    perm = rng.permutation(len(pos))   # ids in no spatial order
+    wl = synth.workload.custom_workload(M.cube(), base.geoms[0].dx, pos[perm], tag[perm])
+    r = _relaxer(wl)
+    r.build_cells()
+    torch.cuda.synchronize()
+    keys = ocells.cell_keys(wl)
+    order = ocells.sort_order(keys, wl.ids)
+    cs = ocells.cell_start(keys[order], ocells.total_cells(wl))
+    occ = np.diff(cs)
+    assert occ.max() > 64   # the clump's cell holds two lattice particles besides it
+    assert np.array_equal(r.id.cpu().numpy(), order)
+    assert np.array_equal(r.cell_start.cpu().numpy(), cs)
+    got = r.pos.cpu().numpy()[:, :3]
+    want = wl.pos[order]
+    assert np.array_equal(np.isnan(got), np.isnan(want))
+    assert np.array_equal(np.nan_to_num(got), np.nan_to_num(want))
+    before = r.pos.clone()
+    r.build_cells()
+    assert torch.equal(before.nan_to_num(), r.pos.nan_to_num())

@@ -71,7 +71,7 @@ def test_distance_to_single_facet_regions():
 
 
 def test_multi_geometry_uses_each_geometry_mesh():
-    wl = synth.workload.batch_workload(n_geom=3, n_min=2000, n_max=5000, seed=11)
+    wl = synth.workload.solid_batch_workload(n_geom=3, n_min=2000, n_max=5000, seed=11)
     W = 2.0 * float(wl.geoms[0].dx)
     tag = band.layer_tags(wl, W)
     for g, geo in enumerate(wl.geoms):
