@@ -98,7 +98,7 @@ def test_clipped_rim_of_a_cut_cylinder():
     64-gon's arc with x < 0.2."""
     cyl = M.cylinder(0.5, 1.0, 64)
     cut = M.cube((0.2, -1, -1), (2, 1, 1))
-    mesh, info, parts_P = C.combine([cyl, cut], C.DIFFERENCE)
+    mesh, info, parts_P = C.combine([cyl, cut], C.DIFFERENCE, with_curves=False)
     L = mesh.lines
     assert L.n_line == 2 and not L.line_closed.any()
     p = L.seg_p.reshape(-1, 3)
@@ -119,6 +119,49 @@ def test_clipped_rim_of_a_cut_cylinder():
         got = np.linalg.norm(L.seg_p[s0:s1, 1] - L.seg_p[s0:s1, 0], axis=1).sum()
         assert got == pytest.approx(length, rel=1e-12)
     assert math.isfinite(length)
+
+
+@pytest.mark.parametrize("boxes,op,length,loops", [
+    # [0,1]^3 minus [0.5,2]x[-1,2]^2: the cut face x = 0.5 meets the box's four faces
+    ([((0, 0, 0), (1, 1, 1)), ((0.5, -1, -1), (2, 2, 2))], C.DIFFERENCE, 4.0, 1),
+    # corner-overlapping cubes: six half-edges around the shared corner region
+    ([((0, 0, 0), (1, 1, 1)), ((0.5, 0.5, 0.5), (1.5, 1.5, 1.5))], C.UNION, 3.0, 1),
+    ([((0, 0, 0), (1, 1, 1)), ((0.5, 0.5, 0.5), (1.5, 1.5, 1.5))], C.DIFFERENCE, 3.0, 1),
+    # a union that is again a box has no crease between the parts
+    ([((0, 0, 0), (1, 1, 1)), ((0.5, 0, 0), (1.5, 1, 1))], C.UNION, 0.0, 0),
+])
+def test_intersection_curves_of_boxes(boxes, op, length, loops):
+    """The curves where the parts' faces meet on the assembly's boundary at a
+    crease, by hand; every point of them on the assembly's surface."""
+    parts = [M.cube(a, b) for a, b in boxes]
+    P = [C.planes(p) for p in parts]
+    polys, closed = C.intersection_lines(op, parts, P)
+    got = sum(np.linalg.norm(np.diff(np.asarray(pl), axis=0), axis=1).sum() for pl in polys)
+    assert got == pytest.approx(length, abs=1e-12)
+    assert sum(closed) == loops and all(closed)
+    if polys:
+        pts = np.concatenate([np.asarray(pl) for pl in polys])
+        geo = _geo(parts, op)
+        assert np.abs(csg.assembly_sd(pts, geo)).max() < 1e-12
+
+
+def test_assembly_lines_run_between_singular_points():
+    """With the curves, every open line of an assembly starts and ends at a
+    singular point and none passes through one."""
+    rng = np.random.Generator(np.random.PCG64(4001))
+    parts, op, _ = C.random_assembly(rng, 50_000)
+    mesh, info, _ = C.combine(parts, op)
+    L = mesh.lines
+    S = mesh.singular
+    tol = 1e-9 * max(np.ptp(p.vert, 0).max() for p in parts)
+    for l in range(L.n_line):
+        s0, s1 = L.line_seg_begin[l], L.line_seg_begin[l + 1]
+        pts = np.concatenate([L.seg_p[s0:s1, 0], L.seg_p[s1 - 1:s1, 1]])
+        d = np.linalg.norm(pts[:, None, :] - S[None], axis=2).min(1) if len(S) else np.full(len(pts), np.inf)
+        if L.line_closed[l]:
+            assert (d > tol).all()
+        else:
+            assert d[0] <= tol and d[-1] <= tol and (d[1:-1] > tol).all()
 
 
 def test_full_size_mode_on_an_assembly_batch():
