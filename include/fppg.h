@@ -32,10 +32,12 @@
  *    found on the device (non-finite values) set bits of a device status word
  *    read by fppg_read_status, which synchronises the stream.
  *  - Positions are float4 arrays passed as float*, 16-byte aligned: x, y, z
- *    in binary32 and w holding int32 bits  tag | (geometry << 8)  where tag is
- *    the particle class 0 singular point, 1 feature-line particle, 2 surface
- *    particle, 3 volume particle, 4 fixed volume particle (innermost layer),
- *    and geometry is the index of the particle's geometry in the batch.
+ *    in binary32 and w holding int32 bits  tag | (level << 3) | (geometry << 8)
+ *    where tag is the particle class 0 singular point, 1 feature-line
+ *    particle, 2 surface particle, 3 volume particle, 4 fixed volume particle
+ *    (innermost layer), level (0..3) the resolution level of a particle of a
+ *    multi-resolution geometry (fppg_geom_desc.max_level; 0 otherwise), and
+ *    geometry is the index of the particle's geometry in the batch.
  *  - Facets and feature segments are numbered globally over a batch: the
  *    facets of geometry g follow those of geometries 0..g-1 (same for
  *    segments). `owner` holds the global facet of a surface particle, the
@@ -151,6 +153,15 @@ typedef struct {
   int32_t csg_op;
   int32_t n_part;
   const int32_t* part_tri_begin;          /* [n_part + 1], 1 <= n_part <= 8; may be NULL if csg_op = 0 */
+  /* Multi-resolution (the paper's future work; the pair length of Eq. 6):
+     0 = one smoothing length h. 1..3 = a particle of level l (pos.w bits 3-4,
+     l <= max_level) has h_i = h 2^-l; a pair uses h_ij = (h_i + h_j) / 2:
+     neighbours iff |r|^2 < fl32(fl32(h_i + h_j)^2), force term
+     K(h_ij) (1 - r / 2h_ij)^3 r_ij, and the time step moves each particle at
+     most h_i / 16 (amax is the largest |a_i| 2^l_i). The particle cells are
+     sized by h, the coarsest length. The Jacobian, energy, density and
+     neighbour-export calls refuse such a geometry (FPPG_E_UNSUPPORTED). */
+  int32_t max_level;
 } fppg_geom_desc;
 
 #define FPPG_CSG_NONE       0

@@ -22,6 +22,7 @@ Modules (each function cites the passage it follows):
   local      the same step at full size (candidate searches, pinned to brute force)
   register   facet subdivision and registration on a grid, Morton code and
              compact hash of the registered cells (sections 3.1.1, 3.1.3)
+  multires   per-particle resolution levels with the pair length of Eq. 6
 
 The front-end modules generate, features and band are imported by name.
 
@@ -29,4 +30,4 @@ Readings of points where the paper is silent or garbled are listed where they
 are used; the functions with no independent pin say "parity unpinned" in their
 docstring (time-step rule, feature-line motion, volume revert rule, metrics).
 """
-from . import kernel, cells, neighbors, force, geometry, step, hvp, metrics, csg, local, register  # noqa: F401
+from . import kernel, cells, neighbors, force, geometry, step, hvp, metrics, csg, local, register, multires  # noqa: F401

@@ -223,16 +223,21 @@ def advance_feature(seg, u, du, segs, margin_tol=1e-9):
 
 
 def relax_step(wl, pos32=None, owner=None, feat_seg=None, feat_u=None, tag=None, gid=None,
-               sd_margin=1e-6) -> StepOut:
-    """Algorithm 1, one iteration, for all particles of the workload."""
+               sd_margin=1e-6, accel_override=None) -> StepOut:
+    """Algorithm 1, one iteration, for all particles of the workload.
+    accel_override = (a, S, counts, amax) replaces the force and its maximum
+    (the multi-resolution step of multires.py)."""
     pos32 = wl.pos if pos32 is None else np.asarray(pos32, np.float32)
     owner = wl.owner if owner is None else np.asarray(owner)
     feat_seg = wl.feat_seg if feat_seg is None else np.asarray(feat_seg)
     feat_u = wl.feat_u if feat_u is None else np.asarray(feat_u, np.float64)
     tag = wl.tag if tag is None else tag
     gid = wl.gid if gid is None else gid
-    a, S, cnt = F.accel(wl, None, pos32, tag, gid)
-    amax = F.amax_per_geometry(wl, a, tag, gid)
+    if accel_override is None:
+        a, S, cnt = F.accel(wl, None, pos32, tag, gid)
+        amax = F.amax_per_geometry(wl, a, tag, gid)
+    else:
+        a, S, cnt, amax = accel_override
     tau = time_step(wl, amax)
     dr, du = displacement(wl, a, tau, owner, feat_seg, tag, gid)
     mov = F.moving_mask(tag, wl.move_mask)

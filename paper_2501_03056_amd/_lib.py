@@ -31,6 +31,7 @@ class GeomDesc(ctypes.Structure):
         ("seg_vert", POINTER(c_int32)),
         ("slab", c_int32),
         ("csg_op", c_int32), ("n_part", c_int32), ("part_tri_begin", POINTER(c_int32)),
+        ("max_level", c_int32),
     ]
 
 

@@ -346,6 +346,8 @@ extern "C" fppg_status fppg_uniformity_loss(fppg_ctx* ctx, const fppg_geom* geom
                                             const int32_t* cell_start, uint32_t move_mask, double rho0, double* out,
                                             float* grad, void* ws, size_t ws_bytes, void* stream) {
   if (!ctx || !geom) return fail(ctx, FPPG_E_ARG, "null ctx/geom");
+  if (geom->has_levels)
+    return fail(ctx, FPPG_E_UNSUPPORTED, "the uniformity loss of a multi-resolution geometry is not supported");
   if (n != geom->n_active || n < 1) return fail(ctx, FPPG_E_ARG, "n differs from the active particle count of the geometry");
   if (!pos || !cell_start || !out || !ws || !aligned(pos, 16) || !aligned(ws, 256) || (grad && !aligned(grad, 16)))
     return fail(ctx, FPPG_E_ARG, "null or misaligned argument");

@@ -271,6 +271,7 @@ static fppg_status geom_create(fppg_ctx* ctx, const fppg_geom_desc* descs, int32
   std::vector<RegItem> reg_items;  // facets to register in the search grids
   std::vector<RegGrid> reg_grids;  // one per geometry
   int64_t ncell = 0, part = 0, tg_cells = 0;
+  bool any_levels = false;
   int32_t tri_off = 0, seg_off = 0;
   for (int32_t g = 0; g < n_geom; ++g) {
     const fppg_geom_desc& d = descs[g];
@@ -298,6 +299,10 @@ static fppg_status geom_create(fppg_ctx* ctx, const fppg_geom_desc* descs, int32
     G.R = d.proj_radius;
     const double hd = d.h;
     G.kcoef = float(105.0 / (16.0 * M_PI * hd * hd * hd * hd * hd));
+    if (d.max_level < 0 || d.max_level > 3)
+      return fail(ctx, FPPG_E_ARG, "geometry " + std::to_string(g) + ": max_level must lie in [0, 3]");
+    G.max_level = d.max_level;
+    any_levels = any_levels || d.max_level > 0;
     G.cell_begin = ncell;
     G.part_begin = d.part_begin;
     G.part_end = d.part_end;
@@ -454,6 +459,7 @@ static fppg_status geom_create(fppg_ctx* ctx, const fppg_geom_desc* descs, int32
   geo->host = gd;
   geo->device = ctx->device;
   geo->has_csg = !parts.empty();
+  geo->has_levels = any_levels;
   fppg_status st = FPPG_OK;
   if ((st = upload(ctx, &geo->d_geom, gd)) != FPPG_OK || (st = upload(ctx, &geo->d_facet, facets)) != FPPG_OK ||
       (st = upload(ctx, &geo->d_n32, n32)) != FPPG_OK || (st = upload(ctx, &geo->d_seg, segs)) != FPPG_OK ||

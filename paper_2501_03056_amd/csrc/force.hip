@@ -50,9 +50,37 @@ __device__ __forceinline__ void add_pair(const float4 p, const float4 q, float r
   if (COUNT) cnt += (src && pair_d2(dx, dy, dz) < rc2) ? 1.0f : 0.0f;
 }
 
+// Multi-resolution pair term: the source's level l_j (pos.w bits 3-4) gives
+// h_j = h 2^-l_j, the pair's support h_i + h_j = 2 h_ij, and the term is
+// (h / h_ij)^5 (1 - r / 2h_ij)^3 r_ij, so that the geometry's K(h) applied at
+// the end gives K(h_ij) per pair (K scales as h^-5). The predicate of the
+// counting variant is |r|^2 < fl32(fl32(h_i + h_j)^2).
+template <bool RANKED, bool COUNT>
+__device__ __forceinline__ void add_pair_mr(const float4 p, const float4 q, float h, float hi, uint32_t T,
+                                            float& ax, float& ay, float& az, float& cnt) {
+  const float dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
+  const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+  const int lj = int((__float_as_uint(q.w) >> 3) & 3u);
+  const float hs = hi + ldexpf(h, -lj);
+  const float inv = __builtin_amdgcn_rcpf(hs);
+  const float t = __builtin_amdgcn_fmed3f(fmaf(-__builtin_amdgcn_sqrtf(r2), inv, 1.0f), 0.0f, 1.0f);
+  const float ratio = (2.0f * h) * inv;
+  const float ratio2 = ratio * ratio;
+  float w = (t * t * t) * (ratio2 * ratio2 * ratio);
+  bool src = true;
+  if (RANKED) {
+    src = (__float_as_uint(q.w) & 7u) <= T;
+    w = src ? w : 0.0f;
+  }
+  ax = fmaf(w, dx, ax);
+  ay = fmaf(w, dy, ay);
+  az = fmaf(w, dz, az);
+  if (COUNT) cnt += (src && pair_d2(dx, dy, dz) < hs * hs) ? 1.0f : 0.0f;
+}
+
 // The B receivers of chunk blk (launch slots blk * B ...): forces, and the
 // chunk's contribution to amax. Called by every thread of a block.
-template <int K, bool COUNT, int B>
+template <int K, bool COUNT, int B, bool MR = false>
 __device__ __forceinline__ void force_chunk(int blk, const float4* __restrict__ pos, int n,
                                             const int* __restrict__ cs, const GeomDev* __restrict__ geoms,
                                             int n_geom, uint32_t move_mask, float4* __restrict__ accel,
@@ -83,7 +111,13 @@ __device__ __forceinline__ void force_chunk(int blk, const float4* __restrict__ 
     const float inv2h = 0.5f / G.h;
     const uint32_t T = tag < FPPG_TAG_VOLUME ? uint32_t(tag) : 7u;
     const Stencil st = stencil_of(p, G);
-    if (ranked)
+    if (MR) {
+      const float hi = ldexpf(G.h, -int((__float_as_uint(p.w) >> 3) & 3u));
+      if (ranked)
+        for_each_source<K, true>(st, G, cs, pos, [&](int, const float4 q) { add_pair_mr<true, COUNT>(p, q, G.h, hi, T, ax, ay, az, cnt); });
+      else
+        for_each_source<K, true>(st, G, cs, pos, [&](int, const float4 q) { add_pair_mr<false, COUNT>(p, q, G.h, hi, T, ax, ay, az, cnt); });
+    } else if (ranked)
       for_each_source<K, true>(st, G, cs, pos, [&](int, const float4 q) { add_pair<true, COUNT>(p, q, rc2, inv2h, T, ax, ay, az, cnt); });
     else
       for_each_source<K, true>(st, G, cs, pos, [&](int, const float4 q) { add_pair<false, COUNT>(p, q, rc2, inv2h, T, ax, ay, az, cnt); });
@@ -92,6 +126,8 @@ __device__ __forceinline__ void force_chunk(int blk, const float4* __restrict__ 
     az *= G.kcoef;
     if (COUNT) cnt -= 1.0f;   // the receiver itself
     anorm = sqrtf(ax * ax + ay * ay + az * az);
+    // multi-resolution: amax takes |a_i| 2^l_i, so that dt^2 moves particle i at most h_i / 16
+    if (MR) anorm = ldexpf(anorm, int((__float_as_uint(p.w) >> 3) & 3u));
     if (!isfinite(anorm)) {
       atomicOr(status, FPPG_S_NONFINITE_ACCEL);
       ax = ay = az = 0.0f;
@@ -131,14 +167,14 @@ __device__ __forceinline__ void force_chunk(int blk, const float4* __restrict__ 
 // One block per chunk of B receivers. remap: the blocks of each XCD take one
 // contiguous range of chunks (xcd_chunk). Neither changes a result (per-lane
 // sums, max-reduced amax).
-template <int K, bool COUNT, int B>
+template <int K, bool COUNT, int B, bool MR = false>
 __global__ __launch_bounds__(B) void k_force(const float4* __restrict__ pos, int n,
                                              const int* __restrict__ cs, const GeomDev* __restrict__ geoms,
                                              int n_geom, uint32_t move_mask, float4* __restrict__ accel,
                                              unsigned* __restrict__ amax_bits, uint32_t* status,
                                              const int* __restrict__ list, int n_list, bool remap) {
   const int blk = remap ? xcd_chunk(blockIdx.x, gridDim.x) : int(blockIdx.x);
-  force_chunk<K, COUNT, B>(blk, pos, n, cs, geoms, n_geom, move_mask, accel, amax_bits, status, list, n_list);
+  force_chunk<K, COUNT, B, MR>(blk, pos, n, cs, geoms, n_geom, move_mask, accel, amax_bits, status, list, n_list);
 }
 
 // Persistent schedule: a grid of resident blocks takes chunks by tickets.
@@ -281,9 +317,28 @@ static void launch_force_k(const ForceLaunch& fl, int nr, hipStream_t s, const f
   else launch_force_b<K, COUNT, 256>(fl, nr, s, p4, n, cs, g, n_geom, mm, acc, ab, st, list);
 }
 
-static void launch_force(int k, bool count, const ForceLaunch& fl, int nr, hipStream_t s, const float4* p4, int n,
-                         const int* cs, const GeomDev* g, int n_geom, uint32_t mm, float4* acc, unsigned* ab,
+template <int K, bool COUNT>
+static void launch_force_mr(bool remap, int nr, hipStream_t s, const float4* p4, int n, const int* cs,
+                            const GeomDev* g, int n_geom, uint32_t mm, float4* acc, unsigned* ab, uint32_t* st,
+                            const int* list) {
+  k_force<K, COUNT, 256, true><<<(nr + 255) / 256, 256, 0, s>>>(p4, n, cs, g, n_geom, mm, acc, ab, st, list, nr, remap);
+}
+
+// A multi-resolution geometry takes the level-aware variant (256 threads, one
+// block per chunk, whatever the launch shape set for the single-resolution kernel).
+static void launch_force(int k, bool count, bool mr, const ForceLaunch& fl, int nr, hipStream_t s, const float4* p4,
+                         int n, const int* cs, const GeomDev* g, int n_geom, uint32_t mm, float4* acc, unsigned* ab,
                          uint32_t* st, const int* list) {
+  if (mr) {
+    if (k == 1) {
+      if (count) launch_force_mr<1, true>(fl.remap, nr, s, p4, n, cs, g, n_geom, mm, acc, ab, st, list);
+      else launch_force_mr<1, false>(fl.remap, nr, s, p4, n, cs, g, n_geom, mm, acc, ab, st, list);
+    } else {
+      if (count) launch_force_mr<2, true>(fl.remap, nr, s, p4, n, cs, g, n_geom, mm, acc, ab, st, list);
+      else launch_force_mr<2, false>(fl.remap, nr, s, p4, n, cs, g, n_geom, mm, acc, ab, st, list);
+    }
+    return;
+  }
   if (k == 1) {
     if (count) launch_force_k<1, true>(fl, nr, s, p4, n, cs, g, n_geom, mm, acc, ab, st, list);
     else launch_force_k<1, false>(fl, nr, s, p4, n, cs, g, n_geom, mm, acc, ab, st, list);
@@ -335,7 +390,8 @@ extern "C" fppg_status fppg_relax_step(fppg_ctx* ctx, const fppg_geom* geom, int
     {
     PhaseTimer timer(ctx, 1, s);
     const ForceLaunch fl{ctx->force_block, ctx->xcd_remap, ctx->persistent, ctx->d_tickets, ctx};
-    launch_force(geom->k, count, fl, nr, s, p4, ni, cell_start, geom->d_geom, geom->n_geom, move_mask, acc, ab,
+    launch_force(geom->k, count, geom->has_levels, fl, nr, s, p4, ni, cell_start, geom->d_geom, geom->n_geom,
+                 move_mask, acc, ab,
                  ctx->d_status, list);
     }
     PhaseTimer timer(ctx, 2, s);

@@ -190,6 +190,8 @@ static fppg_status check_common(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
   if (n != geom->n_active) return fail(ctx, FPPG_E_ARG, "n differs from the active particle count of the geometry");
   if (n > 0 && (!pos || !cs)) return fail(ctx, FPPG_E_ARG, "null pos/cell_start");
   if (!aligned(pos, 16)) return fail(ctx, FPPG_E_ARG, "pos must be 16-byte aligned");
+  if (geom->has_levels)   // these sweeps use one smoothing length per geometry
+    return fail(ctx, FPPG_E_UNSUPPORTED, "Jacobian, energy and neighbour sweeps of a multi-resolution geometry are not supported");
   return FPPG_OK;
 }
 

@@ -36,6 +36,7 @@ struct GeomDev {
   int32_t tri_begin, tri_end, seg_begin, seg_end;
   int32_t csg_op;            // FPPG_CSG_*: the facets are those of convex parts combined by a Boolean operation
   int32_t part_begin_csg, part_end_csg;   // global part range of an assembly
+  int32_t max_level;         // multi-resolution levels 0..max_level (0: one smoothing length)
 };
 
 // Boolean assemblies: per global facet its part where a point test is needed
@@ -100,6 +101,7 @@ struct Geom {
   uint8_t* d_facet_mask = nullptr;  // [n_tri] the parts a facet's points must be tested against
   double4* d_plane = nullptr;       // [n_planes]
   bool has_csg = false;
+  bool has_levels = false;   // some geometry is multi-resolution
   CsgDev csg() const { return CsgDev{d_facet_part, d_facet_mask, d_part, d_plane}; }
   int device = 0;
 };

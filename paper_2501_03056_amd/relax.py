@@ -7,7 +7,7 @@ entry points in order every iteration:
     build_cells -> relax_step -> project
 
 Particle state (structure of arrays, sorted by (cell, id) after build_cells):
-    pos    float32 [N, 4]  x, y, z and the int32 bits tag | geometry << 8
+    pos    float32 [N, 4]  x, y, z and the int32 bits tag | level << 3 | geometry << 8
     id     int32   [N]     original particle index
     owner  int32   [N]     facet (surface), feature slot (feature), else -1
     feat_seg int32 [F], feat_u float64 [F]  feature table (by slot, not permuted)
@@ -24,8 +24,10 @@ from . import _lib as L
 from ._lib import check, ptr
 
 
-def _pack_w(tag: np.ndarray, gid: np.ndarray) -> np.ndarray:
+def _pack_w(tag: np.ndarray, gid: np.ndarray, level: np.ndarray | None = None) -> np.ndarray:
     bits = (np.asarray(tag, np.int32) & 7) | (np.asarray(gid, np.int32) << 8)
+    if level is not None:
+        bits = bits | ((np.asarray(level, np.int32) & 3) << 3)
     return bits.astype(np.int32).view(np.float32)
 
 
@@ -42,6 +44,7 @@ def geom_descs(geoms):
         d.k = int(geo.k)
         d.h = float(geo.h)
         d.proj_radius = float(geo.proj_radius)
+        d.max_level = int(getattr(geo, "max_level", 0))
         d.part_begin = int(geo.part_begin)
         d.part_end = int(geo.part_end)
         vert = np.ascontiguousarray(geo.mesh.vert, np.float64)
@@ -155,7 +158,7 @@ class Relaxer:
         self.vert = np.concatenate([np.asarray(g.mesh.vert, np.float64) for g in wl.geoms], 0)
         pos = np.zeros((self.n, 4), np.float32)
         pos[:, :3] = wl.pos
-        pos[:, 3] = _pack_w(wl.tag, wl.gid)
+        pos[:, 3] = _pack_w(wl.tag, wl.gid, getattr(wl, "level", None))
         t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(self.dev, dt)
         self.pos = t(pos, torch.float32)
         self.id = t(np.arange(self.n, dtype=np.int32), torch.int32)

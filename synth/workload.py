@@ -66,6 +66,7 @@ class Geometry:
     vert_begin: int = 0   # global id of the mesh's first vertex (singular-particle owners)
     slab: int = 0         # rows of cells along y per slab of the cell key (0: one slab)
     csg: object = None    # csg.CSG: the mesh is the facets of convex parts combined by a Boolean operation
+    max_level: int = 0    # multi-resolution: particle levels 0..max_level, h_i = h 2^-level
 
     @property
     def ncell(self) -> int:
@@ -97,6 +98,7 @@ class Workload:
     move_mask: int = ALL_MOVING
     seed: int = 0
     meta: dict = field(default_factory=dict)
+    level: np.ndarray = None   # int32 [N] resolution level (multi-resolution geometries), None: all 0
 
     @property
     def n(self) -> int:
@@ -368,6 +370,51 @@ def sphere_workload(level=5, dx=0.01, jitter=0.3, seed=2, k=2, with_volume=True,
         b.add(p, SURFACE, own)
     return _finish(name or f"sphere_l{level}_dx{dx:g}", [(geom, b)], move_mask, seed,
                    {"dx": dx, "jitter": jitter, "r_in": r_in})
+
+
+def multires_sphere_workload(level=3, dx=0.08, shell=2.0, jitter=0.3, seed=2, k=2, move_mask=ALL_MOVING,
+                             name=None) -> Workload:
+    """Icosphere of radius 1 at two resolutions: a fine shell (level 1,
+    spacing dx/2) and a coarse core (level 0, spacing dx). Fine volume
+    particles: jittered (i+1/2)(dx/2) lattice with radius in [r_in - shell*dx,
+    r_in - dx/4]; coarse ones: jittered (i+1/2)dx lattice with radius below
+    r_in - shell*dx - dx/2 (r_in the inscribed radius of the mesh); surface
+    particles at the fine spacing (Fibonacci directions mapped radially), level
+    1. The geometry's h = 1.3 dx is the coarse length (cells sized by it)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mesh = M.icosphere(level)
+    geom = _make_geom(mesh, dx, k)
+    geom.max_level = 1
+    A, B, C, n = _facet_planes(mesh)
+    r_in = float(np.min(np.einsum("ij,ij->i", n, A)))
+    b = _Builder()
+    lv = []
+    for sp, lo_r, hi_r, lev in ((dx, -1.0, r_in - shell * dx - 0.5 * dx, 0),
+                                (0.5 * dx, r_in - shell * dx, r_in - 0.25 * dx, 1)):
+        m = int(round(2.0 / sp))
+        c = -1.0 + (np.arange(m) + 0.5) * sp
+        keep = []
+        for ix in range(m):
+            yy, zz = np.meshgrid(c, c, indexing="ij")
+            g = np.stack([np.full(yy.size, c[ix]), yy.ravel(), zz.ravel()], 1)
+            g = g + rng.uniform(-jitter, jitter, g.shape) * sp
+            r = np.linalg.norm(g, axis=1)
+            keep.append(g[(r <= hi_r) & (r >= lo_r)])
+        pts = np.concatenate(keep, 0)
+        b.add(pts, VOLUME)
+        lv.append(np.full(len(pts), lev, np.int32))
+    fine = 0.5 * dx
+    ms = int(round(4.0 * np.pi / fine ** 2))
+    d = fibonacci_sphere(ms)
+    d = d + rng.uniform(-jitter, jitter, d.shape) * fine
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    p, own = _radial_map_sphere(mesh, d)
+    b.add(p, SURFACE, own)
+    lv.append(np.full(len(p), 1, np.int32))
+    wl = _finish(name or f"mr_sphere_l{level}_dx{dx:g}", [(geom, b)], move_mask, seed,
+                 {"dx": dx, "jitter": jitter, "r_in": r_in, "shell": shell})
+    wl.level = np.concatenate(lv)
+    return wl
 
 
 # ---------------------------------------------------------------------------
