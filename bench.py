@@ -455,6 +455,41 @@ def _first_at_or_below(curve, target):
     return None
 
 
+def bench_multires(args):
+    """Two-level icosphere (level-5 mesh, coarse dx = 0.02 inside, a fine shell
+    of spacing 0.01 and the surface at 0.01: multi-resolution levels 0 and 1)
+    against the single-resolution sphere at the fine spacing everywhere (the
+    secondary workload of the default line): the same surface resolution with
+    fewer particles. value = the two-level run's particle-updates/s."""
+    import torch
+    import synth
+    from paper_2501_03056_amd import Relaxer
+    t0 = time.perf_counter()
+    wl = synth.workload.multires_sphere_workload(level=5, dx=0.02, shell=2.0)
+    print(f"[bench] two-level sphere: {wl.n} particles (levels {np.bincount(wl.level).tolist()}) built in "
+          f"{time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    r = Relaxer(wl, device=0)
+    t = timed_steps(r, args.steps, args.warmup, "two-level sphere")
+    n_mov = r.n_moving()
+    del r
+    wf, _ = make_workload("sphere", k=args.k)
+    rf = Relaxer(wf, device=0)
+    tf = timed_steps(rf, args.steps, args.warmup, "sphere at the fine spacing")
+    nf = rf.n_moving()
+    out = {"metric": "particle-updates/s per relaxation step", "value": n_mov * args.steps / (t["ms"] / 1e3),
+           "unit": "particle-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": t["ms_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "icosphere_l5_two_levels_dx0.02_shell0.01", "particles": wl.n, "moving": n_mov,
+                      "levels": np.bincount(wl.level).tolist(), "pairs_per_step": t["pairs"]},
+           "force_kernel_ms": t["force_ms"], "kernels_ms_per_step": t["phase_ms"],
+           "fine_everywhere": {"workload": "icosphere_l5_r1_dx0.01", "particles": wf.n, "ms_per_step": tf["ms_step"],
+                               "force_kernel_ms": tf["force_ms"], "pairs_per_step": tf["pairs"],
+                               "particle_updates_per_s": nf * args.steps / (tf["ms"] / 1e3)},
+           "device_status": t["status"]}
+    print(json.dumps(out), flush=True)
+
+
 def bench_newton(args):
     """Newton-Krylov vs the plain loop on one tier (--newton-tier: by default
     the volume tier, where volume particles move and surface, feature and
@@ -533,7 +568,8 @@ def bench_newton(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--mode", default="step", choices=["step", "batch", "newton", "gear", "generate", "features"])
+    ap.add_argument("--mode", default="step",
+                    choices=["step", "batch", "newton", "gear", "generate", "features", "multires"])
     ap.add_argument("--gear-dx", type=float, default=0.004)
     ap.add_argument("--tier-iters", type=int, default=100)
     ap.add_argument("--gear-source", default="synth", choices=["synth", "pipeline"],
@@ -578,6 +614,8 @@ def main():
         return bench_newton(args)
     if args.mode == "gear":
         return bench_gear(args)
+    if args.mode == "multires":
+        return bench_multires(args)
     return bench_step(args)
 
 

@@ -112,11 +112,15 @@ __device__ __forceinline__ void force_chunk(int blk, const float4* __restrict__ 
     const uint32_t T = tag < FPPG_TAG_VOLUME ? uint32_t(tag) : 7u;
     const Stencil st = stencil_of(p, G);
     if (MR) {
-      const float hi = ldexpf(G.h, -int((__float_as_uint(p.w) >> 3) & 3u));
+      // pairs of receiver i reach at most h_i + h = 2h (1 + 2^-l_i) / 2: the
+      // stencil is culled to that radius, K (1 + 2^-l_i) / 2 cell edges
+      const int li = int((__float_as_uint(p.w) >> 3) & 3u);
+      const float hi = ldexpf(G.h, -li);
+      const float rad = float(K) * (0.5f + ldexpf(0.5f, -li));
       if (ranked)
-        for_each_source<K, true>(st, G, cs, pos, [&](int, const float4 q) { add_pair_mr<true, COUNT>(p, q, G.h, hi, T, ax, ay, az, cnt); });
+        for_each_source<K, true>(st, G, cs, pos, [&](int, const float4 q) { add_pair_mr<true, COUNT>(p, q, G.h, hi, T, ax, ay, az, cnt); }, rad * rad);
       else
-        for_each_source<K, true>(st, G, cs, pos, [&](int, const float4 q) { add_pair_mr<false, COUNT>(p, q, G.h, hi, T, ax, ay, az, cnt); });
+        for_each_source<K, true>(st, G, cs, pos, [&](int, const float4 q) { add_pair_mr<false, COUNT>(p, q, G.h, hi, T, ax, ay, az, cnt); }, rad * rad);
     } else if (ranked)
       for_each_source<K, true>(st, G, cs, pos, [&](int, const float4 q) { add_pair<true, COUNT>(p, q, rc2, inv2h, T, ax, ay, az, cnt); });
     else

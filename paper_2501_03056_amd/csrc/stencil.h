@@ -40,10 +40,11 @@ __device__ __forceinline__ float cell_gap(int d, float f) {
 }
 
 // Visit the source index ranges of the stencil of a receiver, culled to the
-// cells within k cell edges.
+// cells within k cell edges (or within sqrt(kk) cell edges, kk <= k^2, for a
+// receiver whose pairs reach less far: the multi-resolution force).
 template <int K, class F>
-__device__ __forceinline__ void for_each_row(const Stencil s, const GeomDev& G, const int* __restrict__ cs, F&& f) {
-  const float kk = float(K * K);
+__device__ __forceinline__ void for_each_row(const Stencil s, const GeomDev& G, const int* __restrict__ cs, F&& f,
+                                             const float kk = float(K * K)) {
 #pragma unroll
   for (int dz = -K; dz <= K; ++dz) {
     const int z = s.z + dz;
@@ -71,8 +72,7 @@ __device__ __forceinline__ void for_each_row(const Stencil s, const GeomDev& G, 
 // overlap (four more registers; used where the occupancy allows it).
 template <int K, class F>
 __device__ __forceinline__ void for_each_row_by_plane(const Stencil s, const GeomDev& G, const int* __restrict__ cs,
-                                                      F&& f) {
-  const float kk = float(K * K);
+                                                      F&& f, const float kk = float(K * K)) {
 #pragma unroll
   for (int dz = -K; dz <= K; ++dz) {
     const int z = s.z + dz;
@@ -110,7 +110,8 @@ __device__ __forceinline__ void for_each_row_by_plane(const Stencil s, const Geo
 // candidates); the index j passed to f is only formed where f uses it.
 template <int K, bool PLANES = false, class F>
 __device__ __forceinline__ void for_each_source(const Stencil s, const GeomDev& G, const int* __restrict__ cs,
-                                                const float4* __restrict__ pos, F&& f) {
+                                                const float4* __restrict__ pos, F&& f,
+                                                const float kk = float(K * K)) {
   auto row = [&](int j0, int j1) {
     const float4* q = pos + j0;
     const float4* const e = pos + j1;
@@ -125,9 +126,9 @@ __device__ __forceinline__ void for_each_source(const Stencil s, const GeomDev& 
     if (q < e) f(int(q - pos), q[0]);
   };
   if (PLANES)
-    for_each_row_by_plane<K>(s, G, cs, row);
+    for_each_row_by_plane<K>(s, G, cs, row, kk);
   else
-    for_each_row<K>(s, G, cs, row);
+    for_each_row<K>(s, G, cs, row, kk);
 }
 
 // As for_each_source, also loading row j of a second float4 field with the
