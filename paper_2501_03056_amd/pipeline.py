@@ -25,14 +25,15 @@ def _f32(x) -> float:
     return float(np.float32(x))
 
 
-def particle_grid(lo, hi, h, k=2):
-    """Particle-grid constants covering [lo, hi] with a margin of one support
-    radius: cell edge (2h/k)(1 + 2^-8) in binary32."""
+def particle_grid(lo, hi, h, k=2, pad=None):
+    """Particle-grid constants covering [lo, hi] with a margin of `pad` (one
+    support radius by default): cell edge (2h/k)(1 + 2^-8) in binary32."""
     rc = _f32(2.0 * h)
+    pad = rc if pad is None else pad
     cell = _f32((rc / k) * (1.0 + 2.0 ** -8))
     inv = _f32(1.0 / cell)
-    origin = (np.asarray(lo, np.float64) - rc).astype(np.float32)
-    ext = np.asarray(hi, np.float64) + rc - origin.astype(np.float64)
+    origin = (np.asarray(lo, np.float64) - pad).astype(np.float32)
+    ext = np.asarray(hi, np.float64) + pad - origin.astype(np.float64)
     dims = np.ceil(ext * inv).astype(np.int64) + 1
     return origin, inv, dims
 

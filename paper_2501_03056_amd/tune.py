@@ -43,8 +43,10 @@ def regrid(wl, k: int):
     cell_begin = 0
     for g in wl.geoms:
         g2 = copy.copy(g)
-        lo, hi = g.mesh.bbox()
-        g2.origin, g2.inv_cell, g2.dims = particle_grid(lo, hi, float(g.h), k)
+        if g.k != k:   # the same box, cells of (2h/k)(1 + 2^-8)
+            lo = np.asarray(g.origin, np.float64)
+            hi = lo + np.asarray(g.dims, np.float64) / float(g.inv_cell)
+            g2.origin, g2.inv_cell, g2.dims = particle_grid(lo, hi, float(g.h), k, pad=0.0)
         g2.k = k
         g2.cell_begin = cell_begin
         cell_begin += int(np.prod(g2.dims))

@@ -642,6 +642,13 @@ def assembly_geometry(rng, n_target: float, jitter=0.3, k=2, mc_samples=1_000_00
     dx = (vol / n_target) ** (1.0 / 3.0)
     geom = _make_geom(mesh, dx, k)
     geom.csg = info
+    # the particle cells cover the solid (a difference lies inside part 0),
+    # with a margin of one cell: the cell lookups clamp, so no stencil reaches out
+    solid = parts if op == C.UNION else parts[:1]
+    slo = np.min([p.vert.min(0) for p in solid], 0)
+    shi = np.max([p.vert.max(0) for p in solid], 0)
+    cell = float(f32((f32(2.0 * geom.h) / k) * (1.0 + 2.0 ** -8)))
+    geom.origin, geom.inv_cell, geom.dims = particle_grid(slo, shi, geom.h, k, pad=cell)
     b = _Builder()
     lo, hi = mesh.bbox()
     axes = [np.arange(lo[a] + 0.5 * dx, hi[a], dx) for a in range(3)]
