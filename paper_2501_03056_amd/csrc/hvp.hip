@@ -110,16 +110,19 @@ __global__ __launch_bounds__(kBlock) void k_jvp(const float4* __restrict__ pos, 
       // J v: every source's term M(r)(v_i - v_j). The receiver itself needs no
       // test: there w = v_i - v_i = 0 and r = 0, so its term is exactly 0 (the
       // clamp of d2 keeps 1/|r| finite). Wavefronts of volume receivers only
-      // (which take every class) skip the class test.
+      // (which take every class) skip the class test. As in the force kernel,
+      // t = 1 - r/2h is clamped to [0, 1] by the FMA's output modifier and no
+      // neighbour test is needed: both terms carry t^2, zero at and beyond
+      // 2h; next to the predicate's pairs the product differs only by pairs
+      // within rounding of r = 2h, whose terms are below 2^-46 of a
+      // unit-distance term.
       auto body = [&](auto ranked) {
         for_each_source_with<K>(st, G, cs, pos, v, [&](int, const float4 q, const float4 vj) {
           const float dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
-          const float d2 = pair_d2(dx, dy, dz);
-          bool pair = d2 < rc2;
-          if (decltype(ranked)::value) pair = pair & ((__float_as_uint(q.w) & 7u) <= T);
+          const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
           const float inv_r = __builtin_amdgcn_rsqf(fmaxf(d2, FLT_MIN));
-          const float t0 = fmaf(-(d2 * inv_r), inv2h, 1.0f);
-          const float t = pair ? t0 : 0.0f;
+          const float t0 = __builtin_amdgcn_fmed3f(fmaf(-(d2 * inv_r), inv2h, 1.0f), 0.0f, 1.0f);
+          const float t = decltype(ranked)::value ? (((__float_as_uint(q.w) & 7u) <= T) ? t0 : 0.0f) : t0;
           const float t2 = t * t;
           const float c1 = t2 * t;
           const float w0 = vi.x - vj.x, w1 = vi.y - vj.y, w2 = vi.z - vj.z;
