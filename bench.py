@@ -189,11 +189,13 @@ def bench_generate(args):
     """The generation front end (fppg_generate: background-grid classes and the
     initial particles) on the 24-tooth gear mesh at spacing --gear-dx; value =
     background cells classified per second (the call's wall time, device
-    temporaries and host-device copies included; best of 3)."""
+    temporaries and host-device copies included; best of 3). The same
+    particles through the sparse storage (fppg_generate_sparse) are timed
+    beside it and compared bit for bit."""
     import torch
     from synth import meshes as M
     from paper_2501_03056_amd import Context
-    from paper_2501_03056_amd.front import generate
+    from paper_2501_03056_amd.front import generate, generate_sparse
     dx = args.gear_dx
     mesh = M.gear()
     lo, hi = mesh.vert.min(0) - 2 * dx, mesh.vert.max(0) + 2 * dx
@@ -210,6 +212,16 @@ def bench_generate(args):
     tags = (pos[:, 3].contiguous().view(torch.int32) & 7).cpu().numpy()
     ncell = int(np.prod(dims))
     t = min(times)
+    # the same particles through the sparse cell storage (no per-cell class array)
+    sparse_times = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        spos, sowner, sinfo = generate_sparse(mesh.vert, mesh.tri, dx, lo, dims, ctx=ctx, cap=len(pos))
+        torch.cuda.synchronize()
+        sparse_times.append(time.perf_counter() - t0)
+    same = bool(torch.equal(spos.view(torch.int32), pos.view(torch.int32)) and torch.equal(sowner, owner))
+    del spos, sowner
     out = {"metric": "background cells classified/s", "value": ncell / t, "unit": "cells/s", "n_gpus": 1,
            "steps": 3, "warmup": 0, "ms_per_step": 1e3 * t, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
@@ -218,7 +230,9 @@ def bench_generate(args):
            "particles": {"volume": int(np.sum(tags == 3)), "surface": int(np.sum(tags == 2))},
            "cell_classes": {k: int(v) for k, v in zip(("external", "internal", "surface"),
                                                        np.bincount(cls.cpu().numpy().ravel(), minlength=3))},
-           "seconds_all": times}
+           "seconds_all": times,
+           "sparse": {"ms": 1e3 * min(sparse_times), "cells_per_s": ncell / min(sparse_times),
+                      "equal_to_dense": same, "seconds_all": sparse_times, **sinfo}}
     print(json.dumps(out), flush=True)
 
 

@@ -544,6 +544,29 @@ fppg_status fppg_generate(fppg_ctx* ctx, const double* vert, int32_t n_vert, con
                           int32_t* owner, int64_t cap, int64_t* counts, void* stream);
 
 /*
+ * The particles of fppg_generate (the same classes, mapping, order and bits)
+ * computed through the sparse storage of section 3.1.3 instead of a dense
+ * per-cell class array: the cells the mesh meets are taken from a sparse grid
+ * of the mesh (fppg_sparse_grid_create with cell = dx and pad = 1e-6 dx, a
+ * superset of the meeting cells while the coordinates are far below 2^50 dx)
+ * re-tested with the whole-facet separating-axis test; the vertical ray
+ * crossings of section 3.1.2 become (column, height) events, radix-sorted, an
+ * event of even multiplicity cancelling; a cell that is not a surface cell is
+ * internal iff an odd number of its column's surviving events lie at or below
+ * it. Memory: about 40 bytes per registered cell and per crossing event, 16
+ * per column (nx * ny) and 8 per 256 background cells. Arguments as
+ * fppg_generate without cell_class; dims each in [1, 2^21] (the Morton code),
+ * nx * ny below 2^31, the cell count below 2^38. stats [4] int64 (host, out,
+ * may be null): registered cells, crossing events, events left after
+ * cancellation, subdivision levels. Errors as fppg_generate (capacity:
+ * counts[0] = -1, counts[1] = the total). A set-up call: it allocates its
+ * device temporaries and synchronises the stream.
+ */
+fppg_status fppg_generate_sparse(fppg_ctx* ctx, const double* vert, int32_t n_vert, const int32_t* tri,
+                                 int32_t n_tri, double dx, const double* origin, const int32_t* dims, float* pos,
+                                 int32_t* owner, int64_t cap, int64_t* counts, int64_t* stats, void* stream);
+
+/*
  * Boolean combination of two solids classified by fppg_generate on the same
  * grid (section 3.2.3), cell by cell (I internal, S surface):
  *   op 0 union         I = Ai | Bi,           S = (As & ~Bi) | (Bs & ~Ai)

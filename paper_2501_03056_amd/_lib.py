@@ -61,6 +61,8 @@ _SIGS = {
     "fppg_tier_partition": (c_int32, [_P, _P, c_int64, _P, _P, _P, _P, _P, _P, c_uint32, _P, _P, c_size_t, _P]),
     "fppg_volume_layers": (c_int32, [_P, _P, c_int64, _P, c_double, _P, _P]),
     "fppg_generate": (c_int32, [_P, _P, c_int32, _P, c_int32, c_double, _P, _P, _P, _P, _P, c_int64, _P, _P]),
+    "fppg_generate_sparse": (c_int32, [_P, _P, c_int32, _P, c_int32, c_double, _P, _P, _P, _P, c_int64, _P, _P,
+                                       _P]),
     "fppg_features": (c_int32, [_P, _P, c_int32, _P, c_int32, c_double, c_double, _P, _P]),
     "fppg_cells_boolean": (c_int32, [_P, _P, _P, c_int64, c_int32, _P, _P]),
     "fppg_relax_hvp": (c_int32, [_P, _P, c_int64, _P, _P, c_uint32, c_int32, _P, _P, _P]),

@@ -35,76 +35,11 @@
 // All arithmetic is FP64 with the sums of three products taken left to
 // right and no contraction (the build's -ffp-contract=off), so the classes
 // are those of the plain definition evaluated in the same order.
-#include "internal.h"
-#include "sat.h"
+#include "gen_common.h"
 
 namespace fppg {
 
 namespace gen {
-
-using fppg::Tri;
-using fppg::tri_box;
-
-constexpr uint8_t kExternal = 0, kInternal = 1, kSurface = 2;
-constexpr int kWave = 64;
-constexpr int kScanBlock = 1024;
-
-struct Grid {
-  double o[3];
-  double dx;
-  int n[3];
-};
-
-__device__ __forceinline__ double centre(const Grid& g, int a, int i) { return g.o[a] + (double(i) + 0.5) * g.dx; }
-
-__device__ __forceinline__ int64_t cell_index(const Grid& g, int i, int j, int k) {
-  return (int64_t(k) * g.n[1] + j) * g.n[0] + i;
-}
-
-// Cell range of [lo, hi] along axis a, widened by one cell, clamped.
-__device__ __forceinline__ void cell_range(const Grid& g, int a, double lo, double hi, int& i0, int& i1) {
-  i0 = min(max(int(floor((lo - g.o[a]) / g.dx)) - 1, 0), g.n[a] - 1);
-  i1 = min(max(int(floor((hi - g.o[a]) / g.dx)) + 1, 0), g.n[a] - 1);
-}
-
-__device__ __forceinline__ Tri load_tri(const double* __restrict__ vert, const int* __restrict__ tri, int t) {
-  Tri T;
-  const int ia = tri[3 * t], ib = tri[3 * t + 1], ic = tri[3 * t + 2];
-  for (int q = 0; q < 3; ++q) {
-    T.a[q] = vert[3 * ia + q];
-    T.b[q] = vert[3 * ib + q];
-    T.c[q] = vert[3 * ic + q];
-  }
-  return T;
-}
-
-// Projection of c along the unit normal of T: plane distance d, foot p, and
-// whether the foot lies in T (all barycentric coordinates >= 0).
-__device__ bool project_inside(const Tri& T, const double c[3], double& d, double p[3]) {
-  double e0[3], e1[3];
-  for (int q = 0; q < 3; ++q) {
-    e0[q] = T.b[q] - T.a[q];
-    e1[q] = T.c[q] - T.a[q];
-  }
-  double n[3] = {e0[1] * e1[2] - e0[2] * e1[1], e0[2] * e1[0] - e0[0] * e1[2], e0[0] * e1[1] - e0[1] * e1[0]};
-  const double len = sqrt((n[0] * n[0] + n[1] * n[1]) + n[2] * n[2]);
-  for (int q = 0; q < 3; ++q) n[q] = n[q] / len;
-  d = ((c[0] - T.a[0]) * n[0] + (c[1] - T.a[1]) * n[1]) + (c[2] - T.a[2]) * n[2];
-  double v[3];
-  for (int q = 0; q < 3; ++q) {
-    p[q] = c[q] - d * n[q];
-    v[q] = p[q] - T.a[q];
-  }
-  const double d00 = (e0[0] * e0[0] + e0[1] * e0[1]) + e0[2] * e0[2];
-  const double d01 = (e0[0] * e1[0] + e0[1] * e1[1]) + e0[2] * e1[2];
-  const double d11 = (e1[0] * e1[0] + e1[1] * e1[1]) + e1[2] * e1[2];
-  const double d20 = (v[0] * e0[0] + v[1] * e0[1]) + v[2] * e0[2];
-  const double d21 = (v[0] * e1[0] + v[1] * e1[1]) + v[2] * e1[2];
-  const double den = d00 * d11 - d01 * d01;
-  const double lb = (d11 * d20 - d01 * d21) / den;
-  const double lc = (d00 * d21 - d01 * d20) / den;
-  return fmin(fmin(1.0 - lb - lc, lb), lc) >= 0.0;
-}
 
 __global__ __launch_bounds__(kWave) void k_surface_cells(const double* __restrict__ vert, const int* __restrict__ tri,
                                                           Grid g, uint8_t* __restrict__ cls,
@@ -137,51 +72,14 @@ __global__ __launch_bounds__(kWave) void k_surface_cells(const double* __restric
   }
 }
 
-// Edge function of the directed edge (ax, ay) -> (bx, by) at (px, py), with
-// the endpoints taken in lexicographic order and the sign restored.
-__device__ __forceinline__ double edge_fn(double ax, double ay, double bx, double by, double px, double py) {
-  const bool swap = ax > bx || (ax == bx && ay > by);
-  const double ux = swap ? bx : ax, uy = swap ? by : ay, wx = swap ? ax : bx, wy = swap ? ay : by;
-  const double e = (wx - ux) * (py - uy) - (wy - uy) * (px - ux);
-  return swap ? -e : e;
-}
-
-__device__ __forceinline__ bool edge_in(double ax, double ay, double bx, double by, double px, double py) {
-  const double e = edge_fn(ax, ay, bx, by, px, py);
-  const double dxe = bx - ax, dye = by - ay;
-  return e > 0.0 || (e == 0.0 && (dye < 0.0 || (dye == 0.0 && dxe < 0.0)));
-}
-
 __global__ __launch_bounds__(kWave) void k_ray_crossings(const double* __restrict__ vert, const int* __restrict__ tri,
                                                           Grid g, unsigned* __restrict__ toggle) {
-  const int t = blockIdx.x;
-  const Tri T = load_tri(vert, tri, t);
-  const double p0x = T.a[0], p0y = T.a[1], p1x = T.b[0], p1y = T.b[1], p2x = T.c[0], p2y = T.c[1];
-  const double area = (p1x - p0x) * (p2y - p0y) - (p1y - p0y) * (p2x - p0x);
-  if (area == 0.0) return;   // vertical facet: not crossed
-  const bool cw = area < 0.0;
-  const double q1x = cw ? p2x : p1x, q1y = cw ? p2y : p1y, q2x = cw ? p1x : p2x, q2y = cw ? p1y : p2y;
-  int r0[2], r1[2];
-  for (int a = 0; a < 2; ++a) {
-    const double lo = fmin(fmin(T.a[a], T.b[a]), T.c[a]), hi = fmax(fmax(T.a[a], T.b[a]), T.c[a]);
-    cell_range(g, a, lo, hi, r0[a], r1[a]);
-  }
-  const int sx = r1[0] - r0[0] + 1, sy = r1[1] - r0[1] + 1;
-  for (int q = threadIdx.x; q < sx * sy; q += kWave) {
-    const int i = r0[0] + q % sx, j = r0[1] + q / sx;
-    const double px = centre(g, 0, i), py = centre(g, 1, j);
-    if (!(edge_in(p0x, p0y, q1x, q1y, px, py) && edge_in(q1x, q1y, q2x, q2y, px, py) &&
-          edge_in(q2x, q2y, p0x, p0y, px, py)))
-      continue;
-    const double l1 = ((px - p0x) * (p2y - p0y) - (py - p0y) * (p2x - p0x)) / area;
-    const double l2 = ((p1x - p0x) * (py - p0y) - (p1y - p0y) * (px - p0x)) / area;
-    const double z = T.a[2] + l1 * (T.b[2] - T.a[2]) + l2 * (T.c[2] - T.a[2]);
-    // first cell whose centre lies strictly above z
-    double fk = floor((z - g.o[2]) / g.dx - 0.5) + 1.0;
-    int k = int(fmin(fmax(fk, 0.0), double(g.n[2])));
-    while (k > 0 && centre(g, 2, k - 1) > z) --k;
-    while (k < g.n[2] && !(centre(g, 2, k) > z)) ++k;
-    if (k < g.n[2]) {
+  const Crossing X = crossing_of(load_tri(vert, tri, blockIdx.x), g);
+  if (!X.valid) return;
+  for (int q = threadIdx.x; q < X.sx * X.sy; q += kWave) {
+    const int i = X.r0[0] + q % X.sx, j = X.r0[1] + q / X.sx;
+    const int k = crossing_cell(X, g, i, j);
+    if (k >= 0 && k < g.n[2]) {
       const int64_t cell = cell_index(g, i, j, k);
       atomicXor(&toggle[cell >> 5], 1u << (cell & 31));
     }

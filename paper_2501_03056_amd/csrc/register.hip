@@ -427,6 +427,11 @@ static fppg_status unique_pairs(fppg_ctx* ctx, uint64_t*& keys, uint32_t*& vals,
 
 using namespace reg;
 
+fppg_status radix_sort_pairs(fppg_ctx* ctx, uint64_t*& keys, uint32_t*& vals, uint64_t*& ktmp, uint32_t*& vtmp,
+                             int n, int val_bits, int key_bits, hipStream_t s) {
+  return radix_sort(ctx, keys, vals, ktmp, vtmp, n, val_bits, key_bits, s);
+}
+
 fppg_status register_facets(fppg_ctx* ctx, const std::vector<RegItem>& items, const std::vector<RegGrid>& grids,
                             bool morton, int key_bits, int facet_bits, RegPairs* out, hipStream_t s) {
   *out = RegPairs{};

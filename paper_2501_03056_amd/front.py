@@ -42,6 +42,44 @@ def generate(vert, tri, dx: float, origin, dims, device: int = 0, ctx: Context |
     return cls, pos[:n], owner[:n]
 
 
+def generate_sparse(vert, tri, dx: float, origin, dims, device: int = 0, ctx: Context | None = None,
+                    cap: int | None = None):
+    """The particles of generate() through the sparse cell storage (no dense
+    class array; fppg_generate_sparse). Returns (pos float32 [P, 4], owner
+    int32 [P], stats dict: registered cells, crossing events, events after
+    cancellation, subdivision levels). Without cap, a first call sizes the
+    output."""
+    if not torch.cuda.is_available():
+        raise RuntimeError("generate_sparse() needs a GPU (no CPU fallback)")
+    ctx = ctx or Context(device)
+    dev = torch.device("cuda", device)
+    vert = np.ascontiguousarray(vert, np.float64).reshape(-1, 3)
+    tri = np.ascontiguousarray(tri, np.int32).reshape(-1, 3)
+    o = (ctypes.c_double * 3)(*[float(v) for v in origin])
+    d = (ctypes.c_int32 * 3)(*[int(v) for v in dims])
+    counts = (ctypes.c_int64 * 2)()
+    stats = (ctypes.c_int64 * 4)()
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+    def call(cap_, pos, owner):
+        return ctx.lib.fppg_generate_sparse(ctx.handle, vert.ctypes.data_as(ctypes.c_void_p), len(vert),
+                                            tri.ctypes.data_as(ctypes.c_void_p), len(tri), float(dx), o, d,
+                                            ptr(pos), ptr(owner), int(cap_), counts, stats, stream)
+
+    pos = torch.empty((max(cap or 1, 1), 4), dtype=torch.float32, device=dev)
+    owner = torch.empty(max(cap or 1, 1), dtype=torch.int32, device=dev)
+    rc = call(cap or 0, pos, owner)
+    if rc == L.E_CAPACITY and cap is None and counts[0] == -1:
+        n = int(counts[1])
+        pos = torch.empty((max(n, 1), 4), dtype=torch.float32, device=dev)
+        owner = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        rc = call(n, pos, owner)
+    check(rc, ctx.handle)
+    n = int(counts[0]) + int(counts[1])
+    info = {"cells": int(stats[0]), "events": int(stats[1]), "toggles": int(stats[2]), "levels": int(stats[3])}
+    return pos[:n], owner[:n], info
+
+
 def features(vert, tri, cos_threshold: float, dx: float, device: int = 0, ctx: Context | None = None):
     """Feature edges, singular vertices, feature lines and feature-line
     particles of a mesh (fppg_features). Returns a dict of device tensors:
