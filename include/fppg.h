@@ -553,8 +553,9 @@ fppg_status fppg_generate(fppg_ctx* ctx, const double* vert, int32_t n_vert, con
  * crossings of section 3.1.2 become (column, height) events, radix-sorted, an
  * event of even multiplicity cancelling; a cell that is not a surface cell is
  * internal iff an odd number of its column's surviving events lie at or below
- * it. Memory: about 40 bytes per registered cell and per crossing event, 16
- * per column (nx * ny) and 8 per 256 background cells. Arguments as
+ * it. Memory: about 40 bytes per registered cell and per crossing event,
+ * half a byte per grid column (nx * ny) and one per 256 background cells;
+ * the sweep reads no per-cell array. Arguments as
  * fppg_generate without cell_class; dims each in [1, 2^21] (the Morton code),
  * nx * ny below 2^31, the cell count below 2^38. stats [4] int64 (host, out,
  * may be null): registered cells, crossing events, events left after

@@ -1,7 +1,7 @@
 // Particle generation through the sparse storage of section 3.1.3: the same
 // particles as fppg_generate (classes and mapping of the dense path, output
-// in cell order) with memory proportional to the grid's columns, the surface
-// and the output instead of one byte per background cell.
+// in cell order) with memory proportional to the surface, the output and the
+// grid's columns instead of one byte per background cell.
 //
 //   surface cells   the registered cells of the mesh's sparse grid (facet
 //                   subdivision, separating-axis test with a pad of 1e-6 dx,
@@ -11,14 +11,20 @@
 //                   maps the centre onto the nearest of them whose foot lies
 //                   inside (smallest |plane distance|, ties: lowest facet)
 //   crossings       one wavefront per facet emits the (column, height) events
-//                   of the vertical ray casting; the events are radix-sorted
-//                   and an event of even multiplicity cancels (parity)
-//   column lists    toggles and surface cells as int32 heights, sorted, with
-//                   per-column offsets (counts + exclusive scan)
-//   emission        one lane per background cell in cell order reads its
-//                   column's lists: a surface cell emits iff it maps onto a
-//                   facet, another cell iff an odd number of toggles lie at or
-//                   below it; per block count, scan, write (as the dense path)
+//                   of the vertical ray casting; sorted, an event of even
+//                   multiplicity cancels (parity)
+//   sweep           the columns are dealt to wavefronts in groups of 2048:
+//                   lane l of group g owns the 32 columns 2048 g + 64 b + l
+//                   (b = 0..31), its parity as the bits of one word. Events
+//                   are keyed (owner, height, b), so one sort leaves every
+//                   lane's events in height order. The wavefront sweeps the
+//                   planes upwards: toggles at the height flip parity bits, a
+//                   surface cell emits iff it maps onto a facet, another cell
+//                   iff its parity bit is set. Pass 0 counts per (plane,
+//                   group), an exclusive scan gives the offsets in cell order,
+//                   pass 1 writes: for b = 0..31 the 64 lanes hold 64
+//                   consecutive columns, so a ballot places them and the
+//                   stores are contiguous.
 #include "gen_common.h"
 
 #include <algorithm>
@@ -28,7 +34,7 @@ namespace fppg {
 namespace gen {
 
 constexpr int kT = 256;
-constexpr int kTotalSlots = 512;
+constexpr int kGroupCols = 2048;   // columns per sweeping wavefront: 64 lanes x 32 bits
 
 __device__ __forceinline__ uint32_t compact_bits(uint64_t v) {
   v &= 0x1249249249249249ull;
@@ -40,18 +46,24 @@ __device__ __forceinline__ uint32_t compact_bits(uint64_t v) {
   return uint32_t(v);
 }
 
+// Sweep key of cell (column col, height k): ((owner * nz + k) * 32 + b) with
+// owner = 64 * group + lane.
+__device__ __forceinline__ uint64_t sweep_key(int64_t col, int k, int nz) {
+  const uint64_t owner = (uint64_t(col) / kGroupCols) * kWave + uint64_t(col % kWave);
+  const uint64_t b = uint64_t((col / kWave) % 32);
+  return ((owner * uint64_t(nz) + uint64_t(k)) << 5) | b;
+}
+
 // One lane per registered cell: the facets registered to it (ascending) are
 // re-tested against the cell with the whole-facet separating-axis test of the
-// dense classification; a cell that none passes is not a surface cell
-// (column key = the sentinel ncol * (nz + 1), sorted last). A surface cell
-// gets its column key (column, height) and the facet its centre maps onto
-// (-1: none).
+// dense classification; a cell that none passes is not a surface cell (key =
+// the sentinel, sorted last). A surface cell gets its sweep key and the facet
+// its centre maps onto (-1: none).
 __global__ __launch_bounds__(kT) void k_map_cells(const uint64_t* __restrict__ code, const int* __restrict__ begin,
                                                    const int* __restrict__ length, const int* __restrict__ facets,
                                                    int nc, const double* __restrict__ vert,
-                                                   const int* __restrict__ tri, Grid g,
-                                                   int* __restrict__ best,
-                                                   uint64_t* __restrict__ col_key) {
+                                                   const int* __restrict__ tri, Grid g, uint64_t sentinel,
+                                                   int* __restrict__ best, uint64_t* __restrict__ key) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nc) return;
   const uint64_t m = code[c];
@@ -68,15 +80,14 @@ __global__ __launch_bounds__(kT) void k_map_cells(const uint64_t* __restrict__ c
     surface = true;
     double d, p[3];
     if (!project_inside(T, ce, d, p)) continue;
-    const unsigned long long key = __double_as_longlong(fabs(d));
-    if (key < bkey) {   // strict: the lowest facet on ties
-      bkey = key;
+    const unsigned long long dk = __double_as_longlong(fabs(d));
+    if (dk < bkey) {   // strict: the lowest facet on ties
+      bkey = dk;
       bt = t;
     }
   }
-  const uint64_t per = uint64_t(g.n[2] + 1), ncol = uint64_t(g.n[0]) * uint64_t(g.n[1]);
   best[c] = surface ? bt : -2;
-  col_key[c] = surface ? (uint64_t(j) * uint64_t(g.n[0]) + uint64_t(i)) * per + uint64_t(k) : ncol * per;
+  key[c] = surface ? sweep_key(int64_t(j) * g.n[0] + i, k, g.n[2]) : sentinel;
 }
 
 // Per facet (one wavefront): the number of crossing events, then the events.
@@ -98,8 +109,7 @@ __global__ __launch_bounds__(kWave) void k_cross_events(const double* __restrict
       const bool hit = k >= 0 && k < g.n[2];
       const uint64_t m = __ballot(hit);
       if (hit && offs)
-        ev[base + c + __popcll(m & ((1ull << threadIdx.x) - 1ull))] =
-            (uint64_t(j) * uint64_t(g.n[0]) + uint64_t(i)) * uint64_t(g.n[2] + 1) + uint64_t(k);
+        ev[base + c + __popcll(m & ((1ull << threadIdx.x) - 1ull))] = sweep_key(int64_t(j) * g.n[0] + i, k, g.n[2]);
       c += __popcll(m);
     }
   }
@@ -119,18 +129,29 @@ __global__ __launch_bounds__(kT) void k_odd_runs(const uint64_t* __restrict__ ev
   flag[i] = f;
 }
 
-__global__ __launch_bounds__(kT) void k_compact_u64(const uint64_t* __restrict__ in, int n,
-                                                     const int* __restrict__ flag, const int* __restrict__ pos,
-                                                     uint64_t* __restrict__ out) {
+// Surviving toggles: owner counts and (height << 5 | b) words, compacted.
+__global__ __launch_bounds__(kT) void k_compact_toggles(const uint64_t* __restrict__ ev, int n,
+                                                         const int* __restrict__ flag, const int* __restrict__ pos,
+                                                         int nz, int* __restrict__ tkb, int* __restrict__ cnt) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n && flag[i]) out[pos[i]] = in[i];
+  if (i >= n || !flag[i]) return;
+  const uint64_t r = ev[i] >> 5;
+  tkb[pos[i]] = int(((r % uint64_t(nz)) << 5) | (ev[i] & 31u));
+  atomicAdd(&cnt[r / uint64_t(nz)], 1);
 }
 
-// Entries per column; keys at or past ncol * per_col (the sentinel) are skipped.
-__global__ __launch_bounds__(kT) void k_count_columns(const uint64_t* __restrict__ key, int n, uint64_t per_col,
-                                                       uint64_t ncol, int* __restrict__ cnt) {
+// Surface cells (sorted keys; the sentinels last): owner counts, the
+// (height << 5 | b) words and the facets.
+__global__ __launch_bounds__(kT) void k_surface_lists(const uint64_t* __restrict__ key,
+                                                       const uint32_t* __restrict__ idx, const int* __restrict__ best,
+                                                       int n, uint64_t sentinel, int nz, int* __restrict__ skb,
+                                                       int* __restrict__ sb, int* __restrict__ cnt) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n && key[i] < ncol * per_col) atomicAdd(&cnt[key[i] / per_col], 1);
+  if (i >= n || key[i] >= sentinel) return;
+  const uint64_t r = key[i] >> 5;
+  skb[i] = int(((r % uint64_t(nz)) << 5) | (key[i] & 31u));
+  sb[i] = best[idx[i]];
+  atomicAdd(&cnt[r / uint64_t(nz)], 1);
 }
 
 __global__ __launch_bounds__(kT) void k_zero(int* __restrict__ a, int64_t n) {
@@ -138,107 +159,92 @@ __global__ __launch_bounds__(kT) void k_zero(int* __restrict__ a, int64_t n) {
     a[i] = 0;
 }
 
-// Per-column lists as int32 cell heights: the surviving toggles, and the
-// surface cells with the facet each maps onto (-1: none).
-__global__ __launch_bounds__(kT) void k_heights(const uint64_t* __restrict__ key, int n, uint64_t per,
-                                                 int* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = int(key[i] % per);
-}
-
-__global__ __launch_bounds__(kT) void k_surface_heights(const uint64_t* __restrict__ col_key,
-                                                         const uint32_t* __restrict__ idx, const int* __restrict__ best,
-                                                         const int* __restrict__ n_surf, uint64_t per,
-                                                         int* __restrict__ sk, int* __restrict__ sb) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= *n_surf) return;
-  sk[i] = int(col_key[i] % per);
-  sb[i] = best[idx[i]];
-}
-
 __global__ __launch_bounds__(kT) void k_iota(uint32_t* __restrict__ a, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) a[i] = uint32_t(i);
 }
 
-// The class of cell (i, j, k) from its column's lists: a surface cell emits
-// iff it maps onto a facet (*facet = that facet), any other cell iff an odd
-// number of toggles lie at or below k (internal; *facet = -1).
-__device__ __forceinline__ bool emits_cell(const int* __restrict__ toff, const int* __restrict__ tk,
-                                           const int* __restrict__ soff, const int* __restrict__ sk,
-                                           const int* __restrict__ sb, int64_t col, int k, int* facet) {
-  for (int s = soff[col], e = soff[col + 1]; s < e; ++s) {
-    const int h = sk[s];
-    if (h == k) {
-      *facet = sb[s];
-      return sb[s] >= 0;
-    }
-    if (h > k) break;
-  }
-  int par = 0;
-  for (int t = toff[col], e = toff[col + 1]; t < e && tk[t] <= k; ++t) par ^= 1;
-  *facet = -1;
-  return par != 0;
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
 }
 
-// Blocks of 256 cells in cell order (chunk of cells starting at base): pass 0
-// counts each block's particles (and the totals), pass 1 writes them at the
-// block's scanned offset, in cell order within the block.
+// One wavefront per group of 2048 columns sweeping the planes upwards. Pass 0
+// (WRITE false): cnt[k * ngroups + group] = the particles of the group in
+// plane k, totals += (particles, surface particles). Pass 1: the particles at
+// off[k * ngroups + group] onwards, in column order.
 template <bool WRITE>
-__global__ __launch_bounds__(kT) void k_emit(const int* __restrict__ toff, const int* __restrict__ tk,
-                                              const int* __restrict__ soff, const int* __restrict__ sk,
-                                              const int* __restrict__ sb, Grid g, int64_t ncell, int64_t base,
-                                              int* __restrict__ bcount, unsigned long long* __restrict__ totals,
-                                              const int* __restrict__ boff, const double* __restrict__ vert,
-                                              const int* __restrict__ tri, float4* __restrict__ pos,
-                                              int* __restrict__ owner) {
-  const int64_t blk = base / kT + blockIdx.x;
-  const int64_t cell = blk * kT + threadIdx.x;
-  int facet = -1;
-  bool e = false;
-  int i = 0, j = 0, k = 0;
-  if (cell < ncell) {
-    const int64_t plane = int64_t(g.n[0]) * g.n[1];
-    k = int(cell / plane);
-    const int64_t col = cell - int64_t(k) * plane;
-    i = int(col % g.n[0]);
-    j = int(col / g.n[0]);
-    e = emits_cell(toff, tk, soff, sk, sb, col, k, &facet);
-  }
-  __shared__ int w[kT / kWave], ws[kT / kWave];
-  const uint64_t m = __ballot(e), ms = __ballot(e && facet >= 0);
-  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  if (lane == 0) {
-    w[wid] = __popcll(m);
-    ws[wid] = __popcll(ms);
-  }
-  __syncthreads();
-  if (!WRITE) {
-    if (threadIdx.x == 0) {
-      int c = 0, cs = 0;
-      for (int q = 0; q < kT / kWave; ++q) {
-        c += w[q];
-        cs += ws[q];
-      }
-      bcount[blk] = c;   // the totals over kTotalSlots addresses (one would serialise the blocks' atomics)
-      if (c) atomicAdd(&totals[2 * (blk % kTotalSlots)], (unsigned long long)c);
-      if (cs) atomicAdd(&totals[2 * (blk % kTotalSlots) + 1], (unsigned long long)cs);
+__global__ __launch_bounds__(kWave) void k_sweep(const int* __restrict__ toff, const int* __restrict__ tkb,
+                                                  const int* __restrict__ soff, const int* __restrict__ skb,
+                                                  const int* __restrict__ sb, Grid g, int ngroups,
+                                                  int* __restrict__ cnt, unsigned long long* __restrict__ totals,
+                                                  const int* __restrict__ off, const double* __restrict__ vert,
+                                                  const int* __restrict__ tri, float4* __restrict__ pos,
+                                                  int* __restrict__ owner) {
+  const int group = blockIdx.x, lane = threadIdx.x;
+  const int o = group * kWave + lane;
+  int t = toff[o];
+  const int te = toff[o + 1];
+  int sp = soff[o];
+  const int se = soff[o + 1];
+  const int nz = g.n[2];
+  uint32_t par = 0;
+  long long all = 0, surf = 0;
+  for (int k = 0; k < nz; ++k) {
+    while (t < te && (tkb[t] >> 5) == k) {
+      par ^= 1u << (tkb[t] & 31);
+      ++t;
     }
-    return;
+    uint32_t S = 0, M = 0;
+    const int s0 = sp;
+    while (sp < se && (skb[sp] >> 5) == k) {
+      const uint32_t bit = 1u << (skb[sp] & 31);
+      S |= bit;
+      if (sb[sp] >= 0) M |= bit;
+      ++sp;
+    }
+    const uint32_t E = (par & ~S) | M;
+    if (!WRITE) {
+      const int c = wave_sum(__popc(E));
+      if (lane == 0) cnt[int64_t(k) * ngroups + group] = c;
+      all += __popc(E);
+      surf += __popc(M);
+      continue;
+    }
+    if (__ballot(E != 0u) == 0ull) continue;
+    int64_t base = off[int64_t(k) * ngroups + group];
+    int q = s0;
+    for (int b = 0; b < 32; ++b) {
+      const bool e = (E >> b) & 1u;
+      const uint64_t m = __ballot(e);
+      if (e) {
+        const int64_t col = int64_t(group) * kGroupCols + b * kWave + lane;
+        const int64_t slot = base + __popcll(m & ((1ull << lane) - 1ull));
+        const int i = int(col % g.n[0]), j = int(col / g.n[0]);
+        const double c[3] = {centre(g, 0, i), centre(g, 1, j), centre(g, 2, k)};
+        if ((M >> b) & 1u) {
+          while ((skb[q] & 31) < b) ++q;   // this plane's surface cells, by b
+          const int f = sb[q];
+          double d, p[3];
+          project_inside(load_tri(vert, tri, f), c, d, p);
+          pos[slot] = make_float4(float(p[0]), float(p[1]), float(p[2]), __int_as_float(FPPG_TAG_SURFACE));
+          owner[slot] = f;
+        } else {
+          pos[slot] = make_float4(float(c[0]), float(c[1]), float(c[2]), __int_as_float(FPPG_TAG_VOLUME));
+          owner[slot] = -1;
+        }
+      }
+      base += __popcll(m);
+    }
   }
-  if (!e) return;
-  int before = 0;
-  for (int q = 0; q < wid; ++q) before += w[q];
-  const int64_t slot = int64_t(boff[blk]) + before + __popcll(m & ((1ull << lane) - 1ull));
-  const double c[3] = {centre(g, 0, i), centre(g, 1, j), centre(g, 2, k)};
-  if (facet < 0) {
-    pos[slot] = make_float4(float(c[0]), float(c[1]), float(c[2]), __int_as_float(FPPG_TAG_VOLUME));
-    owner[slot] = -1;
-  } else {
-    double d, p[3];
-    project_inside(load_tri(vert, tri, facet), c, d, p);
-    pos[slot] = make_float4(float(p[0]), float(p[1]), float(p[2]), __int_as_float(FPPG_TAG_SURFACE));
-    owner[slot] = facet;
+  if (!WRITE) {
+    all = wave_sum(all);
+    surf = wave_sum(surf);
+    if (lane == 0) {
+      atomicAdd(&totals[0], (unsigned long long)all);
+      atomicAdd(&totals[1], (unsigned long long)surf);
+    }
   }
 }
 
@@ -287,9 +293,11 @@ extern "C" fppg_status fppg_generate_sparse(fppg_ctx* ctx, const double* vert, i
     g.n[a] = dims[a];
   }
   g.dx = dx;
-  const int ncol = int(ncol64);
-  const uint64_t per = uint64_t(dims[2] + 1);
-  const int colkey_bits = bits_of(uint64_t(ncol) * per);
+  const int nz = dims[2];
+  const int ngroups = int((ncol64 + kGroupCols - 1) / kGroupCols);
+  const int n_owner = ngroups * kWave;
+  const uint64_t sentinel = (uint64_t(n_owner) * uint64_t(nz)) << 5;
+  const int key_bits = bits_of(sentinel);
   std::vector<void*> owned;
   auto dalloc = [&](void** p, size_t bytes) -> hipError_t {
     hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 16));
@@ -324,28 +332,29 @@ extern "C" fppg_status fppg_generate_sparse(fppg_ctx* ctx, const double* vert, i
   GS_HIP(dalloc(reinterpret_cast<void**>(&d_tri), sizeof(int) * 3 * n_tri));
   GS_HIP(hipMemcpyAsync(d_vert, vert, sizeof(double) * 3 * n_vert, hipMemcpyHostToDevice, s));
   GS_HIP(hipMemcpyAsync(d_tri, tri, sizeof(int) * 3 * n_tri, hipMemcpyHostToDevice, s));
-  // surface cells, their mapping, and their (column, height) order
-  uint64_t *col_key, *col_tmp;
+  // surface cells, their mapping, and their sweep order
+  uint64_t *skey, *skey_tmp;
   int* best;
   uint32_t *idx, *idx_tmp;
-  GS_HIP(dalloc(reinterpret_cast<void**>(&col_key), 8 * size_t(nc)));
-  GS_HIP(dalloc(reinterpret_cast<void**>(&col_tmp), 8 * size_t(nc)));
+  GS_HIP(dalloc(reinterpret_cast<void**>(&skey), 8 * size_t(nc)));
+  GS_HIP(dalloc(reinterpret_cast<void**>(&skey_tmp), 8 * size_t(nc)));
   GS_HIP(dalloc(reinterpret_cast<void**>(&best), 4 * size_t(nc)));
   GS_HIP(dalloc(reinterpret_cast<void**>(&idx), 4 * size_t(nc)));
   GS_HIP(dalloc(reinterpret_cast<void**>(&idx_tmp), 4 * size_t(nc)));
   if (nc > 0) {
-    k_map_cells<<<nblk(nc), kT, 0, s>>>(v.morton, v.begin, v.length, v.facets, nc, d_vert, d_tri, g, best, col_key);
+    k_map_cells<<<nblk(nc), kT, 0, s>>>(v.morton, v.begin, v.length, v.facets, nc, d_vert, d_tri, g, sentinel, best,
+                                        skey);
     k_iota<<<nblk(nc), kT, 0, s>>>(idx, nc);
   }
   GS_HIP(hipGetLastError());
-  GS_ST(radix_sort_pairs(ctx, col_key, idx, col_tmp, idx_tmp, nc, 0, colkey_bits, s));
+  GS_ST(radix_sort_pairs(ctx, skey, idx, skey_tmp, idx_tmp, nc, 0, key_bits, s));
   // crossing events: count, scan, write, sort
   int *fcnt, *foff, *bsum;
   GS_HIP(dalloc(reinterpret_cast<void**>(&fcnt), 4 * size_t(n_tri)));
   GS_HIP(dalloc(reinterpret_cast<void**>(&foff), 4 * (size_t(n_tri) + 1)));
-  const int64_t nblocks = (ncell + kT - 1) / kT;
-  const int64_t bs_len = std::max<int64_t>({scan_blocksum_len(n_tri), scan_blocksum_len(ncol), scan_blocksum_len(nc),
-                                            scan_blocksum_len(nblocks)});
+  const int64_t n_plane_group = int64_t(nz) * ngroups;
+  const int64_t bs_len = std::max<int64_t>({scan_blocksum_len(n_tri), scan_blocksum_len(n_owner),
+                                            scan_blocksum_len(n_plane_group)});
   GS_HIP(dalloc(reinterpret_cast<void**>(&bsum), 4 * size_t(bs_len)));
   k_cross_events<<<n_tri, kWave, 0, s>>>(d_vert, d_tri, g, fcnt, nullptr, nullptr);
   GS_ST(exclusive_scan(ctx, fcnt, n_tri, foff, bsum, s));
@@ -360,62 +369,45 @@ extern "C" fppg_status fppg_generate_sparse(fppg_ctx* ctx, const double* vert, i
   GS_HIP(dalloc(reinterpret_cast<void**>(&evv_tmp), 4 * size_t(nev)));
   k_cross_events<<<n_tri, kWave, 0, s>>>(d_vert, d_tri, g, fcnt, foff, ev);
   GS_HIP(hipGetLastError());
-  GS_ST(radix_sort_pairs(ctx, ev, evv, ev_tmp, evv_tmp, nev, 0, colkey_bits, s));
-  // parity: the events of odd multiplicity survive, once
-  int *eflag, *epos, *ebs;
+  GS_ST(radix_sort_pairs(ctx, ev, evv, ev_tmp, evv_tmp, nev, 0, key_bits, s));
+  // parity: the events of odd multiplicity survive, once; per-owner lists of
+  // toggles and of surface cells
+  int *eflag, *epos, *ebs, *tkb, *tcnt, *toff, *skb, *sb, *scnt, *soff;
   GS_HIP(dalloc(reinterpret_cast<void**>(&eflag), 4 * size_t(nev)));
   GS_HIP(dalloc(reinterpret_cast<void**>(&epos), 4 * (size_t(nev) + 1)));
   GS_HIP(dalloc(reinterpret_cast<void**>(&ebs), 4 * size_t(scan_blocksum_len(nev))));
+  GS_HIP(dalloc(reinterpret_cast<void**>(&tkb), 4 * size_t(nev)));
+  GS_HIP(dalloc(reinterpret_cast<void**>(&tcnt), 4 * size_t(n_owner)));
+  GS_HIP(dalloc(reinterpret_cast<void**>(&toff), 4 * (size_t(n_owner) + 1)));
+  GS_HIP(dalloc(reinterpret_cast<void**>(&skb), 4 * size_t(nc)));
+  GS_HIP(dalloc(reinterpret_cast<void**>(&sb), 4 * size_t(nc)));
+  GS_HIP(dalloc(reinterpret_cast<void**>(&scnt), 4 * size_t(n_owner)));
+  GS_HIP(dalloc(reinterpret_cast<void**>(&soff), 4 * (size_t(n_owner) + 1)));
+  const int gz = std::min(nblk(n_owner), 4096);
+  k_zero<<<gz, kT, 0, s>>>(tcnt, n_owner);
+  k_zero<<<gz, kT, 0, s>>>(scnt, n_owner);
   if (nev > 0) k_odd_runs<<<nblk(nev), kT, 0, s>>>(ev, nev, eflag);
   GS_ST(exclusive_scan(ctx, eflag, nev, epos, ebs, s));
+  if (nev > 0) k_compact_toggles<<<nblk(nev), kT, 0, s>>>(ev, nev, eflag, epos, nz, tkb, tcnt);
+  if (nc > 0) k_surface_lists<<<nblk(nc), kT, 0, s>>>(skey, idx, best, nc, sentinel, nz, skb, sb, scnt);
+  GS_HIP(hipGetLastError());
+  GS_ST(exclusive_scan(ctx, tcnt, n_owner, toff, bsum, s));
+  GS_ST(exclusive_scan(ctx, scnt, n_owner, soff, bsum, s));
   int ntog = 0;
   GS_HIP(hipMemcpyAsync(&ntog, epos + nev, 4, hipMemcpyDeviceToHost, s));
-  GS_HIP(hipStreamSynchronize(s));
-  uint64_t* tog;
-  int* tk;
-  GS_HIP(dalloc(reinterpret_cast<void**>(&tog), 8 * size_t(ntog)));
-  GS_HIP(dalloc(reinterpret_cast<void**>(&tk), 4 * size_t(ntog)));
-  if (nev > 0) k_compact_u64<<<nblk(nev), kT, 0, s>>>(ev, nev, eflag, epos, tog);
-  if (ntog > 0) k_heights<<<nblk(ntog), kT, 0, s>>>(tog, ntog, per, tk);
-  // per-column offsets of the toggles and of the surface cells
-  int *tcnt, *toff, *scnt, *soff, *sk, *sb;
-  GS_HIP(dalloc(reinterpret_cast<void**>(&tcnt), 4 * size_t(ncol)));
-  GS_HIP(dalloc(reinterpret_cast<void**>(&toff), 4 * (size_t(ncol) + 1)));
-  GS_HIP(dalloc(reinterpret_cast<void**>(&scnt), 4 * size_t(ncol)));
-  GS_HIP(dalloc(reinterpret_cast<void**>(&soff), 4 * (size_t(ncol) + 1)));
-  GS_HIP(dalloc(reinterpret_cast<void**>(&sk), 4 * size_t(nc)));
-  GS_HIP(dalloc(reinterpret_cast<void**>(&sb), 4 * size_t(nc)));
-  const int gz = std::min(nblk(ncol), 4096);
-  k_zero<<<gz, kT, 0, s>>>(tcnt, ncol);
-  k_zero<<<gz, kT, 0, s>>>(scnt, ncol);
-  if (ntog > 0) k_count_columns<<<nblk(ntog), kT, 0, s>>>(tog, ntog, per, uint64_t(ncol), tcnt);
-  if (nc > 0) k_count_columns<<<nblk(nc), kT, 0, s>>>(col_key, nc, per, uint64_t(ncol), scnt);
-  GS_ST(exclusive_scan(ctx, tcnt, ncol, toff, bsum, s));
-  GS_ST(exclusive_scan(ctx, scnt, ncol, soff, bsum, s));
-  if (nc > 0) k_surface_heights<<<nblk(nc), kT, 0, s>>>(col_key, idx, best, soff + ncol, per, sk, sb);
-  GS_HIP(hipGetLastError());
-  // emission, pass 0: particles per block of cells and the totals
-  int *bcount, *boff;
+  // the sweep, pass 0: particles per (plane, group) and the totals
+  int *pcnt, *poff;
   unsigned long long* totals;
-  GS_HIP(dalloc(reinterpret_cast<void**>(&bcount), 4 * size_t(nblocks)));
-  GS_HIP(dalloc(reinterpret_cast<void**>(&boff), 4 * (size_t(nblocks) + 1)));
-  GS_HIP(dalloc(reinterpret_cast<void**>(&totals), 16 * kTotalSlots));
-  k_zero<<<4, kT, 0, s>>>(reinterpret_cast<int*>(totals), 4 * kTotalSlots);
-  constexpr int64_t kChunkBlocks = int64_t(1) << 22;   // cells per launch: 2^30
-  for (int64_t b0 = 0; b0 < nblocks; b0 += kChunkBlocks) {
-    const int nb = int(std::min(kChunkBlocks, nblocks - b0));
-    k_emit<false><<<nb, kT, 0, s>>>(toff, tk, soff, sk, sb, g, ncell, b0 * kT, bcount, totals, nullptr, nullptr,
-                                    nullptr, nullptr, nullptr);
-  }
+  GS_HIP(dalloc(reinterpret_cast<void**>(&pcnt), 4 * size_t(n_plane_group)));
+  GS_HIP(dalloc(reinterpret_cast<void**>(&poff), 4 * (size_t(n_plane_group) + 1)));
+  GS_HIP(dalloc(reinterpret_cast<void**>(&totals), 16));
+  k_zero<<<1, kT, 0, s>>>(reinterpret_cast<int*>(totals), 4);
+  k_sweep<false><<<ngroups, kWave, 0, s>>>(toff, tkb, soff, skb, sb, g, ngroups, pcnt, totals, nullptr,
+                                           nullptr, nullptr, nullptr, nullptr);
   GS_HIP(hipGetLastError());
-  std::vector<unsigned long long> slots(2 * kTotalSlots);
-  GS_HIP(hipMemcpyAsync(slots.data(), totals, 16 * kTotalSlots, hipMemcpyDeviceToHost, s));
-  GS_HIP(hipStreamSynchronize(s));
   unsigned long long tot[2] = {0, 0};
-  for (int q = 0; q < kTotalSlots; ++q) {
-    tot[0] += slots[2 * q];
-    tot[1] += slots[2 * q + 1];
-  }
+  GS_HIP(hipMemcpyAsync(tot, totals, 16, hipMemcpyDeviceToHost, s));
+  GS_HIP(hipStreamSynchronize(s));
   if (stats) {
     stats[0] = nc;
     stats[1] = nev;
@@ -433,13 +425,11 @@ extern "C" fppg_status fppg_generate_sparse(fppg_ctx* ctx, const double* vert, i
     cleanup();
     return fail(ctx, FPPG_E_CAPACITY, "more than 2^31 particles");
   }
-  // pass 1: block offsets, then the particles in cell order
-  GS_ST(exclusive_scan(ctx, bcount, nblocks, boff, bsum, s));
-  for (int64_t b0 = 0; b0 < nblocks && total > 0; b0 += kChunkBlocks) {
-    const int nb = int(std::min(kChunkBlocks, nblocks - b0));
-    k_emit<true><<<nb, kT, 0, s>>>(toff, tk, soff, sk, sb, g, ncell, b0 * kT, nullptr, nullptr, boff, d_vert, d_tri,
-                                   reinterpret_cast<float4*>(pos), owner);
-  }
+  // pass 1: offsets in cell order, then the particles
+  GS_ST(exclusive_scan(ctx, pcnt, n_plane_group, poff, bsum, s));
+  if (total > 0)
+    k_sweep<true><<<ngroups, kWave, 0, s>>>(toff, tkb, soff, skb, sb, g, ngroups, nullptr, nullptr, poff,
+                                            d_vert, d_tri, reinterpret_cast<float4*>(pos), owner);
   GS_HIP(hipGetLastError());
   cleanup();
 #undef GS_HIP

@@ -12,11 +12,10 @@
 //                the cell box widened by pad give (key, facet) pairs. One lane
 //                per leaf: the work per lane is bounded however large or thin
 //                the facet (the reason for the subdivision on a GPU).
-//   sort         stable LSD radix sort, 4-bit digits (wavefront ballots rank
-//                equal digits in lane order): facet digits first, then key
-//                digits, so the pairs end in (key, facet) order; duplicates
-//                (a facet met by several of its leaves in one cell) dropped by
-//                a flag and a prefix sum.
+//   sort         rocPRIM's stable device radix sort of the packed (key,
+//                facet) words, so the pairs end in (key, facet) order;
+//                duplicates (a facet met by several of its leaves in one cell)
+//                dropped by a flag and a prefix sum.
 //   dense CSR    the facet search grid of the projection: per-cell counts,
 //                a prefix sum, the non-empty flags.
 //   sparse       key = Morton code of the cell (Eq. 9); C_compact = the runs
@@ -29,6 +28,8 @@
 #include "internal.h"
 #include "sat.h"
 
+#include <rocprim/device/device_radix_sort.hpp>
+
 #include <vector>
 
 namespace fppg {
@@ -37,7 +38,6 @@ namespace reg {
 
 constexpr int kThreads = 256;
 constexpr int kMaxLevels = 48;
-constexpr int kDigits = 16;   // 4-bit digits
 
 __device__ __forceinline__ bool needs_split(const double p[3], const double q[3], double cell) {
   return fmax(fmax(fabs(q[0] - p[0]), fabs(q[1] - p[1])), fabs(q[2] - p[2])) > cell;
@@ -187,56 +187,21 @@ __global__ __launch_bounds__(kThreads) void k_level_write(const RegItem* __restr
   });
 }
 
-template <bool KEYDIG>
-__device__ __forceinline__ int digit_of(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals, int i,
-                                        int shift) {
-  return KEYDIG ? int((keys[i] >> shift) & 15u) : int((vals[i] >> shift) & 15u);
+// (key << val_bits) | val, and back: one 64-bit sort key when both fit.
+__global__ __launch_bounds__(kThreads) void k_pack_pairs(const uint64_t* __restrict__ keys,
+                                                         const uint32_t* __restrict__ vals, int n, int val_bits,
+                                                         uint64_t* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (keys[i] << val_bits) | uint64_t(vals[i]);
 }
 
-template <bool KEYDIG>
-__global__ __launch_bounds__(kThreads) void k_rs_count(const uint64_t* __restrict__ keys,
-                                                       const uint32_t* __restrict__ vals, int n, int shift,
-                                                       int* __restrict__ hist, int nb) {
-  __shared__ int cnt[kDigits];
-  if (threadIdx.x < kDigits) cnt[threadIdx.x] = 0;
-  __syncthreads();
+__global__ __launch_bounds__(kThreads) void k_unpack_pairs(uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                           int n, int val_bits) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) atomicAdd(&cnt[digit_of<KEYDIG>(keys, vals, i, shift)], 1);
-  __syncthreads();
-  if (threadIdx.x < kDigits) hist[threadIdx.x * nb + blockIdx.x] = cnt[threadIdx.x];
-}
-
-// Stable scatter: the rank of an item among the block's items of its digit
-// is the count in earlier wavefronts plus the count in earlier lanes of its
-// own wavefront (ballots over the four digit bits).
-template <bool KEYDIG>
-__global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint64_t* __restrict__ kin,
-                                                         const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
-                                                         uint32_t* __restrict__ vout, int n, int shift,
-                                                         const int* __restrict__ offs, int nb) {
-  __shared__ int wc[kThreads / 64][kDigits];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const bool valid = i < n;
-  const int d = valid ? digit_of<KEYDIG>(kin, vin, i, shift) : 0;
-  uint64_t peers = __ballot(valid);
-#pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    const bool bit = (d >> b) & 1;
-    const uint64_t bb = __ballot(valid && bit);
-    peers &= bit ? bb : ~bb;
-  }
-  const int rank = __popcll(peers & ((1ull << lane) - 1ull));
-  if (threadIdx.x < (kThreads / 64) * kDigits) wc[threadIdx.x / kDigits][threadIdx.x % kDigits] = 0;
-  __syncthreads();
-  if (valid && rank == 0) wc[w][d] = __popcll(peers);
-  __syncthreads();
-  if (!valid) return;
-  int before = 0;
-  for (int q = 0; q < w; ++q) before += wc[q][d];
-  const int dst = offs[d * nb + blockIdx.x] + before + rank;
-  kout[dst] = kin[i];
-  vout[dst] = vin[i];
+  if (i >= n) return;
+  const uint64_t c = keys[i];
+  keys[i] = c >> val_bits;
+  vals[i] = uint32_t(c & ((uint64_t(1) << val_bits) - 1u));
 }
 
 __global__ __launch_bounds__(kThreads) void k_head_flags(const uint64_t* __restrict__ keys,
@@ -363,34 +328,40 @@ static int bits_for(uint64_t v) {
   return b;
 }
 
-// Stable sort of (keys, vals) by val bits [0, val_bits) then key bits [0, key_bits).
+// Stable sort of (keys, vals) by (key bits [0, key_bits), val bits [0,
+// val_bits)), on rocPRIM's device radix sort (stable, LSD): one sort of the
+// packed 64-bit (key, val) when both fit, else by val and then by key.
 static fppg_status radix_sort(fppg_ctx* ctx, uint64_t*& keys, uint32_t*& vals, uint64_t*& ktmp, uint32_t*& vtmp,
                               int n, int val_bits, int key_bits, hipStream_t s) {
-  if (n <= 1) return FPPG_OK;
-  const int nb = blocks(n);
-  DevBuf<int> hist, offs, bsum;
-  FPPG_HIP(ctx, hist.alloc(int64_t(kDigits) * nb));
-  FPPG_HIP(ctx, offs.alloc(int64_t(kDigits) * nb + 1));
-  FPPG_HIP(ctx, bsum.alloc(scan_blocksum_len(int64_t(kDigits) * nb)));
-  auto pass = [&](bool keydig, int shift) -> fppg_status {
-    if (keydig) k_rs_count<true><<<nb, kThreads, 0, s>>>(keys, vals, n, shift, hist.p, nb);
-    else k_rs_count<false><<<nb, kThreads, 0, s>>>(keys, vals, n, shift, hist.p, nb);
-    fppg_status st = exclusive_scan(ctx, hist.p, int64_t(kDigits) * nb, offs.p, bsum.p, s);
-    if (st != FPPG_OK) return st;
-    if (keydig) k_rs_scatter<true><<<nb, kThreads, 0, s>>>(keys, vals, ktmp, vtmp, n, shift, offs.p, nb);
-    else k_rs_scatter<false><<<nb, kThreads, 0, s>>>(keys, vals, ktmp, vtmp, n, shift, offs.p, nb);
-    FPPG_HIP(ctx, hipGetLastError());
+  if (n <= 1 || key_bits + val_bits == 0) return FPPG_OK;
+  const size_t m = size_t(n);
+  DevBuf<char> tmp;
+  size_t bytes = 0;
+  if (val_bits == 0) {
+    FPPG_HIP(ctx, rocprim::radix_sort_pairs(nullptr, bytes, keys, ktmp, vals, vtmp, m, 0u, unsigned(key_bits), s));
+    FPPG_HIP(ctx, tmp.alloc(int64_t(bytes)));
+    FPPG_HIP(ctx, rocprim::radix_sort_pairs(tmp.p, bytes, keys, ktmp, vals, vtmp, m, 0u, unsigned(key_bits), s));
     std::swap(keys, ktmp);
     std::swap(vals, vtmp);
-    return FPPG_OK;
-  };
-  for (int sh = 0; sh < val_bits; sh += 4) {
-    fppg_status st = pass(false, sh);
-    if (st != FPPG_OK) return st;
-  }
-  for (int sh = 0; sh < key_bits; sh += 4) {
-    fppg_status st = pass(true, sh);
-    if (st != FPPG_OK) return st;
+  } else if (key_bits + val_bits <= 64) {
+    k_pack_pairs<<<blocks(n), kThreads, 0, s>>>(keys, vals, n, val_bits, ktmp);
+    FPPG_HIP(ctx, hipGetLastError());
+    const unsigned end = unsigned(key_bits + val_bits);
+    FPPG_HIP(ctx, rocprim::radix_sort_keys(nullptr, bytes, ktmp, keys, m, 0u, end, s));
+    FPPG_HIP(ctx, tmp.alloc(int64_t(bytes)));
+    FPPG_HIP(ctx, rocprim::radix_sort_keys(tmp.p, bytes, ktmp, keys, m, 0u, end, s));
+    k_unpack_pairs<<<blocks(n), kThreads, 0, s>>>(keys, vals, n, val_bits);
+    FPPG_HIP(ctx, hipGetLastError());
+  } else {
+    size_t b2 = 0;
+    FPPG_HIP(ctx, rocprim::radix_sort_pairs(nullptr, bytes, vals, vtmp, keys, ktmp, m, 0u, unsigned(val_bits), s));
+    FPPG_HIP(ctx, rocprim::radix_sort_pairs(nullptr, b2, ktmp, keys, vtmp, vals, m, 0u, unsigned(key_bits), s));
+    bytes = std::max(bytes, b2);
+    FPPG_HIP(ctx, tmp.alloc(int64_t(bytes)));
+    b2 = bytes;
+    FPPG_HIP(ctx, rocprim::radix_sort_pairs(tmp.p, b2, vals, vtmp, keys, ktmp, m, 0u, unsigned(val_bits), s));
+    b2 = bytes;
+    FPPG_HIP(ctx, rocprim::radix_sort_pairs(tmp.p, b2, ktmp, keys, vtmp, vals, m, 0u, unsigned(key_bits), s));
   }
   FPPG_HIP(ctx, hipStreamSynchronize(s));   // the scratch above is freed on return
   return FPPG_OK;
