@@ -610,7 +610,7 @@ typedef struct {
   int64_t n_entry;          /* length of the facet list */
   int64_t n_cell;           /* registered cells (C_compact) */
   int64_t hash_size;        /* H_size */
-  int64_t levels;           /* subdivision levels taken */
+  int64_t levels;           /* subdivision level passes (items stored level by level) */
   const int32_t* facets;    /* [n_entry] facet ids, by (Morton code, facet) */
   const uint64_t* morton;   /* [n_cell] ascending */
   const int32_t* begin;     /* [n_cell] first entry of each cell in facets */

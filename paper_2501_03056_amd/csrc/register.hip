@@ -9,9 +9,13 @@
 //                pass, two prefix sums, a write pass (children in item order).
 //   registration a leaf's box widened by pad reaches at most two cells per
 //                axis; those passing the closed separating-axis test against
-//                the cell box widened by pad give (key, facet) pairs. One lane
-//                per leaf: the work per lane is bounded however large or thin
-//                the facet (the reason for the subdivision on a GPU).
+//                the cell box widened by pad give (key, facet) pairs. An item
+//                whose widened box spans at most 4 cells per axis is finished
+//                inside its lane (depth-first over its subtree, the cells its
+//                leaves meet gathered in a 64-bit mask: one pair per cell and
+//                item), so the last, largest levels are never stored. The
+//                work per lane stays bounded however large or thin the facet
+//                (the reason for the subdivision on a GPU).
 //   sort         rocPRIM's stable device radix sort of the packed (key,
 //                facet) words, so the pairs end in (key, facet) order;
 //                duplicates (a facet met by several of its leaves in one cell)
@@ -125,10 +129,8 @@ __device__ __forceinline__ uint32_t hash3(uint32_t x, uint32_t y, uint32_t z, ui
   return uint32_t((738560931ull * x + 19349663ull * y + 83492791ull * z) % size);
 }
 
-// Visit the cells met by leaf T: f(x, y, z).
-template <class F>
-__device__ void leaf_cells(const RegItem& T, const RegGrid& g, F&& f) {
-  int lo[3], hi[3];
+// The cell range [lo, hi] per axis of T's box widened by pad.
+__device__ __forceinline__ void cell_box(const RegItem& T, const RegGrid& g, int lo[3], int hi[3]) {
   const double* v[3] = {T.a, T.b, T.c};
   for (int q = 0; q < 3; ++q) {
     const double mn = fmin(fmin(v[0][q], v[1][q]), v[2][q]);
@@ -137,6 +139,13 @@ __device__ void leaf_cells(const RegItem& T, const RegGrid& g, F&& f) {
     lo[q] = max(0, int(fmax(floor((mn - g.pad - g.o[q]) * g.inv), -1.0)));
     hi[q] = min(g.dims[q] - 1, int(fmin(floor((mx + g.pad - g.o[q]) * g.inv), double(g.dims[q]))));
   }
+}
+
+// Visit the cells met by leaf T: f(x, y, z).
+template <class F>
+__device__ void leaf_cells(const RegItem& T, const RegGrid& g, F&& f) {
+  int lo[3], hi[3];
+  cell_box(T, g, lo, hi);
   const Tri tri{{T.a[0], T.a[1], T.a[2]}, {T.b[0], T.b[1], T.b[2]}, {T.c[0], T.c[1], T.c[2]}};
   const double h = 0.5 * g.cell + g.pad;
   for (int z = lo[2]; z <= hi[2]; ++z)
@@ -148,6 +157,63 @@ __device__ void leaf_cells(const RegItem& T, const RegGrid& g, F&& f) {
       }
 }
 
+// Child `which` of T as make_children builds it (the same arithmetic).
+__device__ void make_child(const RegItem& T, double cell, int which, RegItem& out) {
+  RegItem ch[4];
+  make_children(T, cell, ch);
+  out = ch[0];
+  for (int k = 1; k < 4; ++k)
+    if (k == which) out = ch[k];
+}
+
+// A small item (its widened box within 4 x 4 x 4 cells) is subdivided inside
+// one lane, depth first, down to its leaves; the cells its leaves meet are
+// gathered as bits of a 4 x 4 x 4 mask relative to lo, so that a cell met by
+// several leaves of one item gives one pair. Returns false (the item then
+// goes on level by level) if the subtree is deeper than kLocalDepth.
+constexpr int kLocalDepth = 8;
+
+__device__ bool small_box(const RegItem& T, const RegGrid& g, int lo[3]) {
+  int hi[3];
+  cell_box(T, g, lo, hi);
+  return hi[0] - lo[0] < 4 && hi[1] - lo[1] < 4 && hi[2] - lo[2] < 4;
+}
+
+__device__ bool subtree_mask(const RegItem& T, const RegGrid& g, const int lo[3], uint64_t& mask) {
+  int d[kLocalDepth], nn[kLocalDepth];
+  int depth = 0;
+  RegItem node = T;
+  mask = 0;
+  bool inside = true;
+  for (;;) {
+    RegItem ch[4];
+    const int c = make_children(node, g.cell, ch);
+    if (c > 0) {
+      if (depth == kLocalDepth) return false;
+      d[depth] = 0;
+      nn[depth] = c;
+      ++depth;
+      node = ch[0];
+      continue;
+    }
+    leaf_cells(node, g, [&](int x, int y, int z) {
+      const int bx = x - lo[0], by = y - lo[1], bz = z - lo[2];
+      if (bx < 0 || by < 0 || bz < 0 || bx > 3 || by > 3 || bz > 3) inside = false;
+      else mask |= uint64_t(1) << ((bz * 4 + by) * 4 + bx);
+    });
+    if (!inside) return false;
+    while (depth > 0 && d[depth - 1] + 1 >= nn[depth - 1]) --depth;
+    if (depth == 0) return true;
+    ++d[depth - 1];
+    node = T;   // down the path again to the next sibling
+    for (int k = 0; k < depth; ++k) {
+      RegItem nx;
+      make_child(node, g.cell, d[k], nx);
+      node = nx;
+    }
+  }
+}
+
 __global__ __launch_bounds__(kThreads) void k_level_count(const RegItem* __restrict__ items, int n,
                                                           const RegGrid* __restrict__ grids, int* __restrict__ nch,
                                                           int* __restrict__ npair) {
@@ -156,9 +222,16 @@ __global__ __launch_bounds__(kThreads) void k_level_count(const RegItem* __restr
   const RegItem T = items[i];
   const RegGrid g = grids[T.grid];
   RegItem ch[4];
-  const int c = make_children(T, g.cell, ch);
+  int c = make_children(T, g.cell, ch);
   int p = 0;
-  if (c == 0) leaf_cells(T, g, [&](int, int, int) { ++p; });
+  int lo[3];
+  uint64_t mask;
+  if (c == 0) {
+    leaf_cells(T, g, [&](int, int, int) { ++p; });
+  } else if (small_box(T, g, lo) && subtree_mask(T, g, lo, mask)) {
+    c = 0;
+    p = __popcll(mask);
+  }
   nch[i] = c;
   npair[i] = p;
 }
@@ -174,17 +247,27 @@ __global__ __launch_bounds__(kThreads) void k_level_write(const RegItem* __restr
   const RegGrid g = grids[T.grid];
   RegItem ch[4];
   const int c = make_children(T, g.cell, ch);
-  if (c > 0) {
-    for (int k = 0; k < c; ++k) next[choff[i] + k] = ch[k];
-    return;
-  }
   int o = poff[i];
-  leaf_cells(T, g, [&](int x, int y, int z) {
+  auto emit = [&](int x, int y, int z) {
     keys[o] = morton ? morton3(x, y, z)
                      : uint64_t(g.key_begin + (int64_t(z) * g.dims[1] + y) * g.dims[0] + x);
     facets[o] = uint32_t(T.facet);
     ++o;
-  });
+  };
+  if (c == 0) {
+    leaf_cells(T, g, emit);
+    return;
+  }
+  int lo[3];
+  uint64_t mask;
+  if (small_box(T, g, lo) && subtree_mask(T, g, lo, mask)) {
+    for (; mask; mask &= mask - 1) {
+      const int b = __ffsll((unsigned long long)mask) - 1;
+      emit(lo[0] + (b & 3), lo[1] + ((b >> 2) & 3), lo[2] + (b >> 4));
+    }
+    return;
+  }
+  for (int k = 0; k < c; ++k) next[choff[i] + k] = ch[k];
 }
 
 // (key << val_bits) | val, and back: one 64-bit sort key when both fit.
