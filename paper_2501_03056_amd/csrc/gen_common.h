@@ -21,7 +21,6 @@ using fppg::tri_box;
 
 constexpr uint8_t kExternal = 0, kInternal = 1, kSurface = 2;
 constexpr int kWave = 64;
-constexpr int kScanBlock = 1024;
 
 struct Grid {
   double o[3];

@@ -17,8 +17,9 @@
 //                   lane l of group g owns the 32 columns 2048 g + 64 b + l
 //                   (b = 0..31), its parity as the bits of one word. Events
 //                   are keyed (owner, height, b), so one sort leaves every
-//                   lane's events in height order. The wavefront sweeps the
-//                   planes upwards: toggles at the height flip parity bits, a
+//                   lane's events in height order. A wavefront takes a group
+//                   and 8 planes, starts from the parity of the toggles below
+//                   them and sweeps upwards: toggles at the height flip parity bits, a
 //                   surface cell emits iff it maps onto a facet, another cell
 //                   iff its parity bit is set. Pass 0 counts per (plane,
 //                   group), an exclusive scan gives the offsets in cell order,
@@ -35,6 +36,8 @@ namespace gen {
 
 constexpr int kT = 256;
 constexpr int kGroupCols = 2048;   // columns per sweeping wavefront: 64 lanes x 32 bits
+constexpr int kChunkPlanes = 8;    // planes per sweeping wavefront
+constexpr int kTotalSlots = 256;   // the count pass's totals, spread over this many address pairs
 
 __device__ __forceinline__ uint32_t compact_bits(uint64_t v) {
   v &= 0x1249249249249249ull;
@@ -170,9 +173,11 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
-// One wavefront per group of 2048 columns sweeping the planes upwards. Pass 0
-// (WRITE false): cnt[k * ngroups + group] = the particles of the group in
-// plane k, totals += (particles, surface particles). Pass 1: the particles at
+// One wavefront per group of 2048 columns and chunk of kChunkPlanes planes
+// (w = chunk * ngroups + group), sweeping its planes upwards from the parity
+// of the toggles below them. Pass 0 (WRITE false): cnt[k * ngroups + group] =
+// the particles of the group in plane k; totals (over kTotalSlots slots) +=
+// (particles, surface particles). Pass 1: the particles at
 // off[k * ngroups + group] onwards, in column order.
 template <bool WRITE>
 __global__ __launch_bounds__(kWave) void k_sweep(const int* __restrict__ toff, const int* __restrict__ tkb,
@@ -182,16 +187,19 @@ __global__ __launch_bounds__(kWave) void k_sweep(const int* __restrict__ toff, c
                                                   const int* __restrict__ off, const double* __restrict__ vert,
                                                   const int* __restrict__ tri, float4* __restrict__ pos,
                                                   int* __restrict__ owner) {
-  const int group = blockIdx.x, lane = threadIdx.x;
+  const int group = int(blockIdx.x % unsigned(ngroups)), chunk = int(blockIdx.x / unsigned(ngroups));
+  const int lane = threadIdx.x;
   const int o = group * kWave + lane;
   int t = toff[o];
   const int te = toff[o + 1];
   int sp = soff[o];
   const int se = soff[o + 1];
-  const int nz = g.n[2];
+  const int k0 = chunk * kChunkPlanes, k1 = min(g.n[2], k0 + kChunkPlanes);
   uint32_t par = 0;
+  for (; t < te && (tkb[t] >> 5) < k0; ++t) par ^= 1u << (tkb[t] & 31);
+  while (sp < se && (skb[sp] >> 5) < k0) ++sp;
   long long all = 0, surf = 0;
-  for (int k = 0; k < nz; ++k) {
+  for (int k = k0; k < k1; ++k) {
     while (t < te && (tkb[t] >> 5) == k) {
       par ^= 1u << (tkb[t] & 31);
       ++t;
@@ -242,8 +250,9 @@ __global__ __launch_bounds__(kWave) void k_sweep(const int* __restrict__ toff, c
     all = wave_sum(all);
     surf = wave_sum(surf);
     if (lane == 0) {
-      atomicAdd(&totals[0], (unsigned long long)all);
-      atomicAdd(&totals[1], (unsigned long long)surf);
+      const unsigned slot = 2u * (blockIdx.x % unsigned(kTotalSlots));
+      atomicAdd(&totals[slot], (unsigned long long)all);
+      atomicAdd(&totals[slot + 1], (unsigned long long)surf);
     }
   }
 }
@@ -400,14 +409,24 @@ extern "C" fppg_status fppg_generate_sparse(fppg_ctx* ctx, const double* vert, i
   unsigned long long* totals;
   GS_HIP(dalloc(reinterpret_cast<void**>(&pcnt), 4 * size_t(n_plane_group)));
   GS_HIP(dalloc(reinterpret_cast<void**>(&poff), 4 * (size_t(n_plane_group) + 1)));
-  GS_HIP(dalloc(reinterpret_cast<void**>(&totals), 16));
-  k_zero<<<1, kT, 0, s>>>(reinterpret_cast<int*>(totals), 4);
-  k_sweep<false><<<ngroups, kWave, 0, s>>>(toff, tkb, soff, skb, sb, g, ngroups, pcnt, totals, nullptr,
+  GS_HIP(dalloc(reinterpret_cast<void**>(&totals), 16 * kTotalSlots));
+  k_zero<<<4, kT, 0, s>>>(reinterpret_cast<int*>(totals), 4 * kTotalSlots);
+  const int64_t nwaves = int64_t(ngroups) * ((nz + kChunkPlanes - 1) / kChunkPlanes);
+  if (nwaves >= (int64_t(1) << 31)) {
+    cleanup();
+    return fail(ctx, FPPG_E_CAPACITY, "background grid too large for the sweep");
+  }
+  k_sweep<false><<<int(nwaves), kWave, 0, s>>>(toff, tkb, soff, skb, sb, g, ngroups, pcnt, totals, nullptr,
                                            nullptr, nullptr, nullptr, nullptr);
   GS_HIP(hipGetLastError());
-  unsigned long long tot[2] = {0, 0};
-  GS_HIP(hipMemcpyAsync(tot, totals, 16, hipMemcpyDeviceToHost, s));
+  std::vector<unsigned long long> slots(2 * kTotalSlots);
+  GS_HIP(hipMemcpyAsync(slots.data(), totals, 16 * kTotalSlots, hipMemcpyDeviceToHost, s));
   GS_HIP(hipStreamSynchronize(s));
+  unsigned long long tot[2] = {0, 0};
+  for (int q = 0; q < kTotalSlots; ++q) {
+    tot[0] += slots[2 * q];
+    tot[1] += slots[2 * q + 1];
+  }
   if (stats) {
     stats[0] = nc;
     stats[1] = nev;
@@ -428,7 +447,7 @@ extern "C" fppg_status fppg_generate_sparse(fppg_ctx* ctx, const double* vert, i
   // pass 1: offsets in cell order, then the particles
   GS_ST(exclusive_scan(ctx, pcnt, n_plane_group, poff, bsum, s));
   if (total > 0)
-    k_sweep<true><<<ngroups, kWave, 0, s>>>(toff, tkb, soff, skb, sb, g, ngroups, nullptr, nullptr, poff,
+    k_sweep<true><<<int(nwaves), kWave, 0, s>>>(toff, tkb, soff, skb, sb, g, ngroups, nullptr, nullptr, poff,
                                             d_vert, d_tri, reinterpret_cast<float4*>(pos), owner);
   GS_HIP(hipGetLastError());
   cleanup();

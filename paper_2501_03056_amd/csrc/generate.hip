@@ -30,7 +30,8 @@
 //                   |plane distance| (ties: lowest facet), by two passes of
 //                   64-bit / 32-bit atomicMin per cell; none: discarded.
 //   output          particles in cell order (z, y, x; x fastest) by a
-//                   three-phase count / scan / write.
+//                   three-phase count / scan / write (per-block counts, the
+//                   multi-block exclusive scan of the cell rebuild).
 //
 // All arithmetic is FP64 with the sums of three products taken left to
 // right and no contraction (the build's -ffp-contract=off), so the classes
@@ -125,48 +126,9 @@ __global__ __launch_bounds__(256) void k_emit_count(const uint8_t* __restrict__ 
   }
 }
 
-// exclusive scan of the block counts (one block walking them in chunks,
-// Hillis-Steele within a chunk) and the total of the surface counts
-__global__ __launch_bounds__(kScanBlock) void k_emit_scan(const int* __restrict__ bcount,
-                                                           const int* __restrict__ scount, int nb,
-                                                           long long* __restrict__ boff,
-                                                           unsigned long long* __restrict__ nsurf) {
-  __shared__ long long s[kScanBlock];
-  long long carry = 0;
-  unsigned long long sv = 0;
-  for (int base = 0; base < nb; base += kScanBlock) {
-    const int b = base + threadIdx.x;
-    const long long v = b < nb ? bcount[b] : 0;
-    sv += b < nb ? unsigned(scount[b]) : 0u;
-    s[threadIdx.x] = v;
-    __syncthreads();
-    for (int o = 1; o < kScanBlock; o <<= 1) {
-      const long long add = threadIdx.x >= o ? s[threadIdx.x - o] : 0;
-      __syncthreads();
-      s[threadIdx.x] += add;
-      __syncthreads();
-    }
-    if (b < nb) boff[b] = carry + s[threadIdx.x] - v;
-    carry += s[kScanBlock - 1];
-    __syncthreads();
-  }
-  // the surface total: block reduction of the per-thread sums
-  __shared__ unsigned long long ss[kScanBlock];
-  ss[threadIdx.x] = sv;
-  __syncthreads();
-  for (int o = kScanBlock / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) ss[threadIdx.x] += ss[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    boff[nb] = carry;
-    nsurf[0] = ss[0];
-  }
-}
-
 __global__ __launch_bounds__(256) void k_emit_write(const uint8_t* __restrict__ cls, const int* __restrict__ best,
                                                      const double* __restrict__ vert, const int* __restrict__ tri,
-                                                     Grid g, int64_t ncell, const long long* __restrict__ boff,
+                                                     Grid g, int64_t ncell, const int* __restrict__ boff,
                                                      int64_t cap, float4* __restrict__ pos, int* __restrict__ owner) {
   const int64_t cell = int64_t(blockIdx.x) * 256 + threadIdx.x;
   const bool e = cell < ncell && emits(cls, best, cell);
@@ -270,8 +232,9 @@ extern "C" fppg_status fppg_generate(fppg_ctx* ctx, const double* vert, int32_t 
   unsigned* d_tog = nullptr;
   int* d_bcount = nullptr;
   int* d_scount = nullptr;
-  long long* d_boff = nullptr;
-  unsigned long long* d_nsurf = nullptr;
+  int* d_boff = nullptr;
+  int* d_soff = nullptr;
+  int* d_bsum = nullptr;
   fppg_status st = FPPG_OK;
   auto cleanup = [&]() {
     hipStreamSynchronize(s);
@@ -283,7 +246,8 @@ extern "C" fppg_status fppg_generate(fppg_ctx* ctx, const double* vert, int32_t 
     hipFree(d_bcount);
     hipFree(d_scount);
     hipFree(d_boff);
-    hipFree(d_nsurf);
+    hipFree(d_soff);
+    hipFree(d_bsum);
   };
 #define GEN_HIP(call)                                   \
   do {                                                  \
@@ -301,8 +265,9 @@ extern "C" fppg_status fppg_generate(fppg_ctx* ctx, const double* vert, int32_t 
   GEN_HIP(hipMalloc(&d_tog, sizeof(unsigned) * ((ncell + 31) / 32)));
   GEN_HIP(hipMalloc(&d_bcount, sizeof(int) * nb));
   GEN_HIP(hipMalloc(&d_scount, sizeof(int) * nb));
-  GEN_HIP(hipMalloc(&d_boff, sizeof(long long) * (nb + 1)));
-  GEN_HIP(hipMalloc(&d_nsurf, sizeof(unsigned long long)));
+  GEN_HIP(hipMalloc(&d_boff, sizeof(int) * (nb + 1)));
+  GEN_HIP(hipMalloc(&d_soff, sizeof(int) * (nb + 1)));
+  GEN_HIP(hipMalloc(&d_bsum, sizeof(int) * scan_blocksum_len(nb)));
   GEN_HIP(hipMemcpyAsync(d_vert, vert, sizeof(double) * 3 * n_vert, hipMemcpyHostToDevice, s));
   GEN_HIP(hipMemcpyAsync(d_tri, tri, sizeof(int) * 3 * n_tri, hipMemcpyHostToDevice, s));
   gen::k_fill_u8<<<gen::blocks(ncell, 256), 256, 0, s>>>(cell_class, ncell, gen::kExternal);
@@ -315,19 +280,23 @@ extern "C" fppg_status fppg_generate(fppg_ctx* ctx, const double* vert, int32_t 
   gen::k_ray_crossings<<<n_tri, gen::kWave, 0, s>>>(d_vert, d_tri, g, d_tog);
   gen::k_column_parity<<<gen::blocks(int64_t(dims[0]) * dims[1], 256), 256, 0, s>>>(g, d_tog, cell_class);
   gen::k_emit_count<<<nb, 256, 0, s>>>(cell_class, d_best, ncell, d_bcount, d_scount);
-  gen::k_emit_scan<<<1, gen::kScanBlock, 0, s>>>(d_bcount, d_scount, nb, d_boff, d_nsurf);
+  // block offsets (the total below 2^31 cells fits) and the surface total
+  if ((st = exclusive_scan(ctx, d_bcount, nb, d_boff, d_bsum, s)) != FPPG_OK ||
+      (st = exclusive_scan(ctx, d_scount, nb, d_soff, d_bsum, s)) != FPPG_OK) {
+    cleanup();
+    return st;
+  }
   gen::k_emit_write<<<nb, 256, 0, s>>>(cell_class, d_best, d_vert, d_tri, g, ncell, d_boff, cap,
                                        reinterpret_cast<float4*>(pos), owner);
   GEN_HIP(hipGetLastError());
-  long long total = 0;
-  unsigned long long nsurf = 0;
-  GEN_HIP(hipMemcpyAsync(&total, d_boff + nb, sizeof(long long), hipMemcpyDeviceToHost, s));
-  GEN_HIP(hipMemcpyAsync(&nsurf, d_nsurf, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  int total = 0, nsurf = 0;
+  GEN_HIP(hipMemcpyAsync(&total, d_boff + nb, sizeof(int), hipMemcpyDeviceToHost, s));
+  GEN_HIP(hipMemcpyAsync(&nsurf, d_soff + nb, sizeof(int), hipMemcpyDeviceToHost, s));
   GEN_HIP(hipStreamSynchronize(s));
 #undef GEN_HIP
   cleanup();
-  counts[0] = total - int64_t(nsurf);
-  counts[1] = int64_t(nsurf);
+  counts[0] = int64_t(total) - nsurf;
+  counts[1] = nsurf;
   if (total > cap) {
     counts[0] = -1;
     counts[1] = total;

@@ -62,43 +62,6 @@ __device__ __forceinline__ void set_item(RegItem& o, const double a[3], const do
   o.grid = grid;
 }
 
-// Children of item T (vertex order as the oracle's); returns their number.
-__device__ int make_children(const RegItem& T, double cell, RegItem out[4]) {
-  const bool s[3] = {needs_split(T.a, T.b, cell), needs_split(T.b, T.c, cell), needs_split(T.c, T.a, cell)};
-  const int n = int(s[0]) + int(s[1]) + int(s[2]);
-  if (n == 0) return 0;
-  const double* v[3] = {T.a, T.b, T.c};
-  if (n == 3) {
-    double mab[3], mbc[3], mca[3];
-    midpoint(T.a, T.b, mab);
-    midpoint(T.b, T.c, mbc);
-    midpoint(T.c, T.a, mca);
-    set_item(out[0], T.a, mab, mca, T.facet, T.grid);
-    set_item(out[1], mab, T.b, mbc, T.facet, T.grid);
-    set_item(out[2], mca, mbc, T.c, T.facet, T.grid);
-    set_item(out[3], mab, mbc, mca, T.facet, T.grid);
-    return 4;
-  }
-  if (n == 2) {
-    const int r = !s[0] ? 0 : (!s[1] ? 1 : 2);   // the unsplit edge (u, v)
-    const double *u = v[r], *vv = v[(r + 1) % 3], *w = v[(r + 2) % 3];
-    double mvw[3], mwu[3];
-    midpoint(vv, w, mvw);
-    midpoint(w, u, mwu);
-    set_item(out[0], mvw, w, mwu, T.facet, T.grid);
-    set_item(out[1], u, vv, mvw, T.facet, T.grid);
-    set_item(out[2], u, mvw, mwu, T.facet, T.grid);
-    return 3;
-  }
-  const int r = s[0] ? 0 : (s[1] ? 1 : 2);      // the split edge (u, v)
-  const double *u = v[r], *vv = v[(r + 1) % 3], *w = v[(r + 2) % 3];
-  double muv[3];
-  midpoint(u, vv, muv);
-  set_item(out[0], u, muv, w, T.facet, T.grid);
-  set_item(out[1], muv, vv, w, T.facet, T.grid);
-  return 2;
-}
-
 // Eq. 9: bits of x, y, z interleaved (x lowest), 21 bits per axis.
 __device__ __forceinline__ uint64_t spread3(uint64_t v) {
   v &= 0x1fffffull;
@@ -157,13 +120,66 @@ __device__ void leaf_cells(const RegItem& T, const RegGrid& g, F&& f) {
       }
 }
 
-// Child `which` of T as make_children builds it (the same arithmetic).
+// The number of children of T (0: a leaf).
+__device__ __forceinline__ int child_count(const RegItem& T, double cell) {
+  const int n = int(needs_split(T.a, T.b, cell)) + int(needs_split(T.b, T.c, cell)) + int(needs_split(T.c, T.a, cell));
+  return n == 0 ? 0 : n + 1;
+}
+
+__device__ __forceinline__ void pick3(int r, const double a[3], const double b[3], const double c[3], double o[3]) {
+  for (int k = 0; k < 3; ++k) o[k] = r == 0 ? a[k] : (r == 1 ? b[k] : c[k]);
+}
+
+// Child `which` of T (vertex order as the oracle's). Three split edges: the
+// corner triangles at a, b, c and the centre one; two: the corner where the
+// split edges meet, then the rest cut along the diagonal from the far end of
+// the unsplit edge (u, v); one: the two halves through the opposite vertex.
+// The vertices are chosen by selects (no array of children or of vertex
+// pointers), so a lane keeps everything in registers.
 __device__ void make_child(const RegItem& T, double cell, int which, RegItem& out) {
-  RegItem ch[4];
-  make_children(T, cell, ch);
-  out = ch[0];
-  for (int k = 1; k < 4; ++k)
-    if (k == which) out = ch[k];
+  const bool s0 = needs_split(T.a, T.b, cell), s1 = needs_split(T.b, T.c, cell), s2 = needs_split(T.c, T.a, cell);
+  const int n = int(s0) + int(s1) + int(s2);
+  double p[3], q[3], r[3];
+  if (n == 3) {
+    double mab[3], mbc[3], mca[3];
+    midpoint(T.a, T.b, mab);
+    midpoint(T.b, T.c, mbc);
+    midpoint(T.c, T.a, mca);
+    // (a, mab, mca), (mab, b, mbc), (mca, mbc, c), (mab, mbc, mca)
+    for (int k = 0; k < 3; ++k) {
+      p[k] = which == 0 ? T.a[k] : (which == 2 ? mca[k] : mab[k]);
+      q[k] = which == 0 ? mab[k] : (which == 1 ? T.b[k] : mbc[k]);
+      r[k] = which == 0 ? mca[k] : (which == 1 ? mbc[k] : (which == 2 ? T.c[k] : mca[k]));
+    }
+  } else if (n == 2) {
+    const int e = !s0 ? 0 : (!s1 ? 1 : 2);   // the unsplit edge (u, v)
+    double u[3], v[3], w[3], mvw[3], mwu[3];
+    pick3(e, T.a, T.b, T.c, u);
+    pick3((e + 1) % 3, T.a, T.b, T.c, v);
+    pick3((e + 2) % 3, T.a, T.b, T.c, w);
+    midpoint(v, w, mvw);
+    midpoint(w, u, mwu);
+    // (mvw, w, mwu), (u, v, mvw), (u, mvw, mwu)
+    for (int k = 0; k < 3; ++k) {
+      p[k] = which == 0 ? mvw[k] : u[k];
+      q[k] = which == 0 ? w[k] : (which == 1 ? v[k] : mvw[k]);
+      r[k] = which == 0 ? mwu[k] : (which == 1 ? mvw[k] : mwu[k]);
+    }
+  } else {
+    const int e = s0 ? 0 : (s1 ? 1 : 2);      // the split edge (u, v)
+    double u[3], v[3], w[3], muv[3];
+    pick3(e, T.a, T.b, T.c, u);
+    pick3((e + 1) % 3, T.a, T.b, T.c, v);
+    pick3((e + 2) % 3, T.a, T.b, T.c, w);
+    midpoint(u, v, muv);
+    // (u, muv, w), (muv, v, w)
+    for (int k = 0; k < 3; ++k) {
+      p[k] = which == 0 ? u[k] : muv[k];
+      q[k] = which == 0 ? muv[k] : v[k];
+      r[k] = w[k];
+    }
+  }
+  set_item(out, p, q, r, T.facet, T.grid);
 }
 
 // A small item (its widened box within 4 x 4 x 4 cells) is subdivided inside
@@ -180,20 +196,22 @@ __device__ bool small_box(const RegItem& T, const RegGrid& g, int lo[3]) {
 }
 
 __device__ bool subtree_mask(const RegItem& T, const RegGrid& g, const int lo[3], uint64_t& mask) {
-  int d[kLocalDepth], nn[kLocalDepth];
+  // the path as 3-bit fields: the child taken (d) and the siblings (nn) per depth
+  uint32_t d = 0, nn = 0;
   int depth = 0;
   RegItem node = T;
   mask = 0;
   bool inside = true;
   for (;;) {
-    RegItem ch[4];
-    const int c = make_children(node, g.cell, ch);
+    const int c = child_count(node, g.cell);
     if (c > 0) {
       if (depth == kLocalDepth) return false;
-      d[depth] = 0;
-      nn[depth] = c;
+      d &= ~(7u << (3 * depth));
+      nn = (nn & ~(7u << (3 * depth))) | (uint32_t(c) << (3 * depth));
       ++depth;
-      node = ch[0];
+      RegItem ch;
+      make_child(node, g.cell, 0, ch);
+      node = ch;
       continue;
     }
     leaf_cells(node, g, [&](int x, int y, int z) {
@@ -202,14 +220,14 @@ __device__ bool subtree_mask(const RegItem& T, const RegGrid& g, const int lo[3]
       else mask |= uint64_t(1) << ((bz * 4 + by) * 4 + bx);
     });
     if (!inside) return false;
-    while (depth > 0 && d[depth - 1] + 1 >= nn[depth - 1]) --depth;
+    while (depth > 0 && ((d >> (3 * (depth - 1))) & 7u) + 1 >= ((nn >> (3 * (depth - 1))) & 7u)) --depth;
     if (depth == 0) return true;
-    ++d[depth - 1];
+    d += 1u << (3 * (depth - 1));
     node = T;   // down the path again to the next sibling
     for (int k = 0; k < depth; ++k) {
-      RegItem nx;
-      make_child(node, g.cell, d[k], nx);
-      node = nx;
+      RegItem ch;
+      make_child(node, g.cell, int((d >> (3 * k)) & 7u), ch);
+      node = ch;
     }
   }
 }
@@ -221,8 +239,7 @@ __global__ __launch_bounds__(kThreads) void k_level_count(const RegItem* __restr
   if (i >= n) return;
   const RegItem T = items[i];
   const RegGrid g = grids[T.grid];
-  RegItem ch[4];
-  int c = make_children(T, g.cell, ch);
+  int c = child_count(T, g.cell);
   int p = 0;
   int lo[3];
   uint64_t mask;
@@ -245,8 +262,7 @@ __global__ __launch_bounds__(kThreads) void k_level_write(const RegItem* __restr
   if (i >= n) return;
   const RegItem T = items[i];
   const RegGrid g = grids[T.grid];
-  RegItem ch[4];
-  const int c = make_children(T, g.cell, ch);
+  const int c = child_count(T, g.cell);
   int o = poff[i];
   auto emit = [&](int x, int y, int z) {
     keys[o] = morton ? morton3(x, y, z)
@@ -267,7 +283,11 @@ __global__ __launch_bounds__(kThreads) void k_level_write(const RegItem* __restr
     }
     return;
   }
-  for (int k = 0; k < c; ++k) next[choff[i] + k] = ch[k];
+  for (int k = 0; k < c; ++k) {
+    RegItem ch;
+    make_child(T, g.cell, k, ch);
+    next[choff[i] + k] = ch;
+  }
 }
 
 // (key << val_bits) | val, and back: one 64-bit sort key when both fit.
