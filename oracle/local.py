@@ -330,10 +330,13 @@ def volume_rule(y, mesh, sd_margin=1e-6, grid=None):
 # ---------------------------------------------------------------------------- one iteration
 
 def relax_step(wl, pos32=None, owner=None, feat_seg=None, feat_u=None, tag=None, gid=None, sd_margin=1e-6,
-               a=None):
+               a=None, sample=None):
     """step.relax_step with the candidate searches above. `a` may pass the
     accelerations of all particles already computed by accel() (the same
-    positions)."""
+    positions). sample (boolean mask, optional): the forces, amax and
+    displacements are still those of every particle, but only the sampled
+    moving particles are projected; the others keep their position and are
+    neither reverted nor margin cases."""
     pos32 = wl.pos if pos32 is None else np.asarray(pos32, np.float32)
     owner = wl.owner if owner is None else np.asarray(owner)
     feat_seg = wl.feat_seg if feat_seg is None else np.asarray(feat_seg)
@@ -341,6 +344,7 @@ def relax_step(wl, pos32=None, owner=None, feat_seg=None, feat_u=None, tag=None,
     tag = wl.tag if tag is None else tag
     gid = wl.gid if gid is None else gid
     mov = F.moving_mask(tag, wl.move_mask)
+    proj = mov if sample is None else (mov & np.asarray(sample, bool))
     if a is None:
         a, S, cnt = accel(wl, None, pos32, tag, gid)
     else:
@@ -356,7 +360,7 @@ def relax_step(wl, pos32=None, owner=None, feat_seg=None, feat_u=None, tag=None,
     reverted = np.zeros(len(x), bool)
     margin = np.zeros(len(x), bool)
     for g, geo in enumerate(wl.geoms):
-        s = np.nonzero(mov & (gid == g) & (tag == SURFACE))[0]
+        s = np.nonzero(proj & (gid == g) & (tag == SURFACE))[0]
         if len(s):
             y = x[s] + dr[s]
             ok, foot, own, mg = project_surface(wl, y, g)
@@ -364,7 +368,7 @@ def relax_step(wl, pos32=None, owner=None, feat_seg=None, feat_u=None, tag=None,
             owner_new[s[ok]] = own[ok]
             reverted[s[~ok]] = True
             margin[s] = mg
-        v = np.nonzero(mov & (gid == g) & (tag == VOLUME))[0]
+        v = np.nonzero(proj & (gid == g) & (tag == VOLUME))[0]
         if len(v):
             y = x[v] + dr[v]
             if getattr(geo, "csg", None) is not None:   # parts have few facets: the brute-force rule
@@ -375,7 +379,7 @@ def relax_step(wl, pos32=None, owner=None, feat_seg=None, feat_u=None, tag=None,
             x_new[v[ok]] = y[ok]
             reverted[v[~ok]] = True
             margin[v] = mg
-    f = np.nonzero(mov & (tag == FEATURE))[0]
+    f = np.nonzero(proj & (tag == FEATURE))[0]
     if len(f):
         segs = batch_segments(wl)
         p0, p1, ln = segs[0], segs[1], segs[2]
@@ -389,7 +393,7 @@ def relax_step(wl, pos32=None, owner=None, feat_seg=None, feat_u=None, tag=None,
             else:
                 reverted[i] = True
     pos_new32 = x_new.astype(np.float32)
-    pos_new32[~mov] = pos32[~mov]
+    pos_new32[~proj] = pos32[~proj]
     pos_new32[reverted] = pos32[reverted]
     return StepOut(a=a, S=S, nsrc=cnt, amax=amax, tau=tau, dr=dr, du=du, x_new=x_new,
                    pos32=pos_new32, owner=owner_new, feat_seg=fs_new, feat_u=fu_new,

@@ -673,22 +673,35 @@ def assembly_geometry(rng, n_target: float, jitter=0.3, k=2, mc_samples=1_000_00
     return geom, b, desc
 
 
+def batch_targets(n_geom=64, n_min=5e3, n_max=5e5, seed=4000):
+    """The target particle counts of batch_workload's geometries (the first
+    draw of each geometry's generator), without building them."""
+    return [float(np.exp(np.random.Generator(np.random.PCG64(seed + g)).uniform(np.log(n_min), np.log(n_max))))
+            for g in range(n_geom)]
+
+
 def batch_workload(n_geom=64, n_min=5e3, n_max=5e5, seed=4000, jitter=0.3, k=2,
-                   move_mask=ALL_MOVING, name=None, mc_samples=1_000_000) -> Workload:
+                   move_mask=ALL_MOVING, name=None, mc_samples=1_000_000, members=None) -> Workload:
     """A batch of independent Boolean assemblies relaxed together (section
     3.2.3 assemblies; assembly_geometry): geometry b uses PCG64 seed
     `seed + b` and a log-uniform target count in [n_min, n_max]. The
-    geometries do not interact (each has its own cell grid and facets)."""
+    geometries do not interact (each has its own cell grid and facets).
+    members: build only these geometries of the batch (in the given order),
+    each exactly as in the whole batch."""
     parts, descs, targets = [], [], []
-    for g in range(n_geom):
+    for g in (range(n_geom) if members is None else members):
         rng = np.random.Generator(np.random.PCG64(seed + g))
         n_t = float(np.exp(rng.uniform(np.log(n_min), np.log(n_max))))
         geom, b, desc = assembly_geometry(rng, n_t, jitter, k, mc_samples)
         parts.append((geom, b))
         descs.append(desc)
         targets.append(n_t)
-    return _finish(name or f"batch{n_geom}_seed{seed}", parts, move_mask, seed,
-                   {"assemblies": descs, "targets": targets})
+    meta = {"assemblies": descs, "targets": targets}
+    if members is not None:
+        meta["members"] = list(members)
+    return _finish(name or (f"batch{n_geom}_seed{seed}" if members is None else
+                            f"batch{n_geom}_seed{seed}_members{'_'.join(map(str, members))}"),
+                   parts, move_mask, seed, meta)
 
 
 def solid_batch_workload(n_geom=64, n_min=5e3, n_max=5e5, seed=4000, jitter=0.3, k=2,

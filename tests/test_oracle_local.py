@@ -59,6 +59,24 @@ def test_local_step_equals_brute_force_step(case):
     _same_step(got, ref)
 
 
+def test_sampled_step_equals_the_full_step_on_the_sample():
+    """A sampled step (an assembly of the batch, every class moving) decides
+    the sampled movers as the full step does and leaves the others in place."""
+    wl = synth.workload.batch_workload(n_geom=2, n_min=1.5e3, n_max=3e3, seed=4212, mc_samples=50_000)
+    full = local.relax_step(wl)
+    sample = np.random.default_rng(0).random(wl.n) < 0.3
+    got = local.relax_step(wl, sample=sample)
+    mov = force.moving_mask(wl.tag, wl.move_mask)
+    on = sample & mov
+    assert on.sum() > 100 and (~sample & mov).sum() > 100
+    assert np.array_equal(got.pos32[on], full.pos32[on])
+    assert np.array_equal(got.reverted[on], full.reverted[on])
+    assert np.array_equal(got.owner[on], full.owner[on])
+    assert np.array_equal(got.pos32[~on], wl.pos[~on])
+    assert not got.reverted[~on].any() and not got.margin[~on].any()
+    assert np.array_equal(got.amax, full.amax)
+
+
 FORCED = {
     "cube": lambda: synth.workload.forced_reverts(synth.cube_workload(n=10, seed=3), seed=1),
     "tetra": lambda: synth.workload.forced_reverts(synth.tetra_workload(dx=0.06, seed=5), seed=2),
