@@ -95,18 +95,24 @@ typedef struct fppg_geom fppg_geom;
  * One geometry of a batch (host memory; fppg_geom_create copies it).
  *
  * Particle grid (cell list of section 3.1.1's uniform background grid,
- * rebuilt every iteration): cell (cx, cy, cz) of a position p is
- *   c = clamp(floor(fl32(fl32(p - origin) * inv_cell)), 0, dims - 1)
- * (binary32, one rounding per operation) and its key is
- *   cell_begin(g) + s S dims[0] dims[2] + (cz w + cy - s S) dims[0] + cx,
+ * rebuilt every iteration): the cells of the grid (origin, inv_cell, dims)
+ * split in two along x, nx = 2 dims[0] of them per row. Cell (cx, cy, cz) of
+ * a position p is
+ *   cx = clamp(floor(fl32(fl32(p.x - origin[0]) * fl32(2 inv_cell))), 0, nx - 1)
+ *   cy, cz = clamp(floor(fl32(fl32(p - origin) * inv_cell)), 0, dims - 1)
+ * (binary32, one rounding per operation; 2 inv_cell is exact) and its key is
+ *   cell_begin(g) + s S nx dims[2] + (cz w + cy - s S) nx + cx,
  *   s = cy div S,  w = min(S, dims[1] - s S),  S = slab
  * with cell_begin(g) the total cell count of geometries 0..g-1: the y range
  * is cut into slabs of S rows (slab <= 0 or > dims[1]: one slab, the plain
- * (cz dims[1] + cy) dims[0] + cx), each slab numbered z-major with x fastest.
+ * (cz dims[1] + cy) nx + cx), each slab numbered z-major with x fastest.
  * Any S gives the same cell list; narrow slabs keep the rows a stencil reads
- * close in memory. The cell edge
+ * close in memory; the half-width cells along x let a stencil row end within
+ * half a cell of the support sphere. The cell edge
  * 1/inv_cell must be at least (2h/k)(1 + 2^-9) so that the (2k+1)^3 cell
  * stencil holds every pair with q < 2; k is 1 or 2 and equal across a batch.
+ * fppg_geom_info reports the total cell count (2 dims[0] dims[1] dims[2]
+ * summed over the geometries).
  *
  * Particles of geometry g occupy the index range [part_begin, part_end) of
  * the particle arrays, which the cell sort preserves.

@@ -16,20 +16,40 @@ A particle with a non-finite coordinate gets the key ncell (one past every
 geometry's cells; reading: such a particle is nobody's neighbour), so
 cell_start has ncell + 2 entries, the last being N.
 
-The cell coordinate is defined in binary32, one rounding per operation:
-    t = fl32(fl32(x - origin) * inv_cell),  c = clamp(floor(t), 0, dim - 1)
-with NaN mapped to cell 0.
+The cells are those of the geometry's grid (origin, inv_cell, dims) split in
+X_SPLIT along x (nx = X_SPLIT dims[0] cells per row), a layout choice of the
+library's stencil (half-width cells along x). The cell coordinate is defined
+in binary32, one rounding per operation:
+    t = fl32(fl32(x - origin) * inv),  c = clamp(floor(t), 0, n - 1)
+with inv = fl32(X_SPLIT inv_cell) (exact) and n = nx along x, inv = inv_cell
+and n = dims along y and z, NaN mapped to cell 0. Geometry g's keys start at
+the total cell count of geometries 0..g-1.
 """
 import numpy as np
 
+X_SPLIT = 2
+
+
+def grid_dims(geo):
+    """Cells per axis of a geometry's particle grid (x split)."""
+    return (X_SPLIT * int(geo.dims[0]), int(geo.dims[1]), int(geo.dims[2]))
+
+
+def geometry_cells(geo) -> int:
+    nx, ny, nz = grid_dims(geo)
+    return nx * ny * nz
+
 
 def cell_coords(pos32: np.ndarray, origin, inv_cell, dims) -> np.ndarray:
-    """Integer cell coordinates [N, 3] of binary32 positions [N, 3]."""
+    """Integer cell coordinates [N, 3] of binary32 positions [N, 3] in the grid
+    (origin, inv_cell, dims) with its cells split in X_SPLIT along x; dims are
+    the unsplit grid's."""
     p = np.asarray(pos32, np.float32)
     t = (p - np.asarray(origin, np.float32)).astype(np.float32)
-    t = (t * np.float32(inv_cell)).astype(np.float32)
-    hi = (np.asarray(dims, np.int64) - 1).astype(np.float32)
-    t = np.fmin(np.fmax(t, np.float32(0.0)), hi)   # fmax/fmin drop NaN -> 0
+    inv = np.array([X_SPLIT * np.float32(inv_cell), inv_cell, inv_cell], np.float32)
+    t = (t * inv).astype(np.float32)
+    n = np.array([X_SPLIT * int(dims[0]), int(dims[1]), int(dims[2])], np.int64)
+    t = np.fmin(np.fmax(t, np.float32(0.0)), (n - 1).astype(np.float32))   # fmax/fmin drop NaN -> 0
     return np.floor(t).astype(np.int64)
 
 
@@ -38,10 +58,12 @@ def cell_keys(wl, pos32=None, gid=None) -> np.ndarray:
     pos32 = wl.pos if pos32 is None else pos32
     gid = wl.gid if gid is None else gid
     keys = np.empty(len(pos32), np.int64)
+    begin = 0
     for g, geo in enumerate(wl.geoms):
         m = gid == g
         c = cell_coords(pos32[m], geo.origin, geo.inv_cell, geo.dims)
-        keys[m] = geo.cell_begin + linear_key(c, geo.dims, getattr(geo, "slab", 0))
+        keys[m] = begin + linear_key(c, grid_dims(geo), getattr(geo, "slab", 0))
+        begin += geometry_cells(geo)
     keys[~np.all(np.isfinite(pos32), axis=1)] = total_cells(wl)
     return keys
 
@@ -56,7 +78,7 @@ def linear_key(c: np.ndarray, dims, slab: int) -> np.ndarray:
 
 
 def total_cells(wl) -> int:
-    return int(sum(g.ncell for g in wl.geoms))
+    return int(sum(geometry_cells(g) for g in wl.geoms))
 
 
 def sort_order(keys: np.ndarray, ids: np.ndarray) -> np.ndarray:

@@ -22,7 +22,7 @@ namespace fppg {
 
 __device__ __forceinline__ int cell_key(const float4 p, const GeomDev& G) {
   // binary32, one rounding per operation (file compiled without FP contraction)
-  float tx = (p.x - G.origin[0]) * G.inv_cell;
+  float tx = (p.x - G.origin[0]) * G.inv_cell_x;
   float ty = (p.y - G.origin[1]) * G.inv_cell;
   float tz = (p.z - G.origin[2]) * G.inv_cell;
   tx = fminf(fmaxf(tx, 0.0f), float(G.dims[0] - 1));   // fmaxf(NaN, 0) = 0

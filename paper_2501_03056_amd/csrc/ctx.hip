@@ -288,11 +288,12 @@ static fppg_status geom_create(fppg_ctx* ctx, const fppg_geom_desc* descs, int32
     int64_t nc = 1;
     for (int q = 0; q < 3; ++q) {
       if (d.dims[q] < 1 || d.dims[q] >= (1 << 20)) return fail(ctx, FPPG_E_ARG, "dims must be in [1, 2^20)");
-      nc *= d.dims[q];
       G.origin[q] = d.origin[q];
-      G.dims[q] = d.dims[q];
+      G.dims[q] = d.dims[q] * (q == 0 ? kXSplit : 1);
+      nc *= G.dims[q];
     }
     G.inv_cell = d.inv_cell;
+    G.inv_cell_x = d.inv_cell * float(kXSplit);
     G.k = k;
     G.h = d.h;
     G.rc2 = rc * rc;

@@ -12,13 +12,18 @@
 namespace fppg {
 
 constexpr int kBlock = 256;          // threads per block of the streaming kernels
+// The particle cells are the cells of the caller's grid split in kXSplit along
+// x: a receiver's stencil rows then end within half a cell of its support
+// sphere instead of a whole cell (fewer candidates per row).
+constexpr int kXSplit = 2;
 constexpr int kMaxGeom = 1 << 16;    // geometry index lives in bits 8..23 of pos.w
 
 // Per-geometry descriptor as the kernels read it (device array, one per geometry).
 struct GeomDev {
   float origin[3];
-  float inv_cell;
-  int32_t dims[3];
+  float inv_cell;   // 1 / cell edge along y and z
+  float inv_cell_x; // kXSplit inv_cell (exact): 1 / cell edge along x
+  int32_t dims[3];  // particle cells per axis (dims[0] = kXSplit times the caller's)
   int32_t k;
   float h;
   float rc2;        // fl32(fl32(2h)^2)

@@ -7,7 +7,10 @@
 // row are culled in cell units against the support radius: a skipped cell is
 // at least k cell edges (> 2h, the edge being (2h/k)(1+2^-9) or more) from the
 // receiver, so it holds no source and culled sums are bitwise identical to
-// full-stencil sums. Sources are visited in a fixed order (rows by dz then dy
+// full-stencil sums. Along x the cells are kXSplit times narrower (the x
+// coordinate in x-cell units is exactly kXSplit times the one in cell units),
+// so a row reaches k kXSplit x-cells and ends within half a cell edge of the
+// receiver's support sphere. Sources are visited in a fixed order (rows by dz then dy
 // ascending, then sorted index).
 #pragma once
 
@@ -22,7 +25,7 @@ struct Stencil {
 };
 
 __device__ __forceinline__ Stencil stencil_of(const float4 p, const GeomDev& G) {
-  float tx = (p.x - G.origin[0]) * G.inv_cell;
+  float tx = (p.x - G.origin[0]) * G.inv_cell_x;
   float ty = (p.y - G.origin[1]) * G.inv_cell;
   float tz = (p.z - G.origin[2]) * G.inv_cell;
   // clamping moves an outside receiver onto the grid box: gaps only shrink
@@ -57,9 +60,9 @@ __device__ __forceinline__ void for_each_row(const Stencil s, const GeomDev& G, 
       const float gy = cell_gap(dy, s.fy);
       const float r2 = kk - (gy * gy + gz * gz);
       if (!(r2 > 0.0f)) continue;
-      const float rho = __builtin_amdgcn_sqrtf(r2);
-      const int below = min(K, int(ceilf(rho - s.fx + 1.0f)) - 1);   // |dx| with f + |dx| - 1 < rho
-      const int above = min(K, int(ceilf(rho + s.fx)) - 1);          // dx with dx - f < rho
+      const float rho = __builtin_amdgcn_sqrtf(r2) * float(kXSplit);   // in x-cell edges
+      const int below = min(K * kXSplit, int(ceilf(rho - s.fx + 1.0f)) - 1);   // |dx| with f + |dx| - 1 < rho
+      const int above = min(K * kXSplit, int(ceilf(rho + s.fx)) - 1);          // dx with dx - f < rho
       const int x0 = max(s.x - below, 0), x1 = min(s.x + above, G.dims[0] - 1);
       const int row = row_key(G, y, z);
       f(cs[row + x0], cs[row + x1 + 1]);
@@ -87,9 +90,9 @@ __device__ __forceinline__ void for_each_row_by_plane(const Stencil s, const Geo
       const float gy = cell_gap(dy, s.fy);
       const float r2 = kk - (gy * gy + gz * gz);
       if (!(r2 > 0.0f)) continue;
-      const float rho = __builtin_amdgcn_sqrtf(r2);
-      const int below = min(K, int(ceilf(rho - s.fx + 1.0f)) - 1);
-      const int above = min(K, int(ceilf(rho + s.fx)) - 1);
+      const float rho = __builtin_amdgcn_sqrtf(r2) * float(kXSplit);
+      const int below = min(K * kXSplit, int(ceilf(rho - s.fx + 1.0f)) - 1);
+      const int above = min(K * kXSplit, int(ceilf(rho + s.fx)) - 1);
       const int x0 = max(s.x - below, 0), x1 = min(s.x + above, G.dims[0] - 1);
       const int row = row_key(G, y, z);
       j0[dy + K] = cs[row + x0];

@@ -98,7 +98,7 @@ def from_mesh(vert, tri, dx: float, cos_threshold: float = math.cos(math.radians
     h = _f32(h_over_dx * dx)
     origin, inv, gdims = particle_grid(vert.min(0), vert.max(0), h, k)
     geo = SimpleNamespace(mesh=mesh, dx=dx, h=h, k=k, proj_radius=_f32(dx), origin=origin, inv_cell=inv,
-                          dims=gdims, part_begin=0, part_end=len(pos), cell_begin=0, tri_begin=0, seg_begin=0,
+                          dims=gdims, part_begin=0, part_end=len(pos), tri_begin=0, seg_begin=0,
                           line_begin=0, feat_begin=0, vert_begin=0, slab=0)
     wl = _Workload(name=name, geoms=[geo], pos=pos, tag=tag, owner=owner, gid=np.zeros(len(pos), np.int32),
                    feat_seg=feat_seg, feat_u=fu.astype(np.float64), move_mask=ALL_MOVING, seed=0,

@@ -40,7 +40,6 @@ def regrid(wl, k: int):
     """Shallow copy of a workload whose geometries use stencil half-width k."""
     out = copy.copy(wl)
     geoms = []
-    cell_begin = 0
     for g in wl.geoms:
         g2 = copy.copy(g)
         if g.k != k:   # the same box, cells of (2h/k)(1 + 2^-8)
@@ -48,8 +47,6 @@ def regrid(wl, k: int):
             hi = lo + np.asarray(g.dims, np.float64) / float(g.inv_cell)
             g2.origin, g2.inv_cell, g2.dims = particle_grid(lo, hi, float(g.h), k, pad=0.0)
         g2.k = k
-        g2.cell_begin = cell_begin
-        cell_begin += int(np.prod(g2.dims))
         geoms.append(g2)
     out.geoms = geoms
     return out

@@ -45,8 +45,8 @@ class Geometry:
     """One geometry of a batch: its mesh and the particle-grid description.
 
     The particle grid is a uniform Cartesian grid of cell edge (2h/k)(1+2^-8)
-    starting at `origin`; a cell key is the x-fastest linear index of the cell
-    plus `cell_begin`, the offset of this geometry in the batch key space.
+    starting at `origin` with `dims` cells per axis (the relaxation keys its
+    own cells from it).
     """
     mesh: M.Mesh
     dx: float
@@ -58,7 +58,6 @@ class Geometry:
     dims: np.ndarray      # int64 [3]
     part_begin: int = 0
     part_end: int = 0
-    cell_begin: int = 0
     tri_begin: int = 0
     seg_begin: int = 0
     line_begin: int = 0
@@ -67,10 +66,6 @@ class Geometry:
     slab: int = 0         # rows of cells along y per slab of the cell key (0: one slab)
     csg: object = None    # csg.CSG: the mesh is the facets of convex parts combined by a Boolean operation
     max_level: int = 0    # multi-resolution: particle levels 0..max_level, h_i = h 2^-level
-
-    @property
-    def ncell(self) -> int:
-        return int(np.prod(self.dims))
 
 
 def particle_grid(lo, hi, h, k=2, pad=None):
@@ -179,7 +174,7 @@ def _feature_particles(b: _Builder, mesh: M.Mesh, dx: float, rng, jitter: float)
 def _finish(name, parts, move_mask, seed, meta=None) -> Workload:
     """Concatenate per-geometry builders into one workload with global offsets."""
     geoms, pos, tag, owner, gid, fseg, fu = [], [], [], [], [], [], []
-    n = tri_off = seg_off = line_off = feat_off = cell_off = vert_off = 0
+    n = tri_off = seg_off = line_off = feat_off = vert_off = 0
     for g, (geom, b) in enumerate(parts):
         p = np.concatenate(b.pos, 0) if b.pos else np.zeros((0, 3))
         t = np.concatenate(b.tag) if b.tag else np.zeros(0, np.int32)
@@ -190,7 +185,7 @@ def _finish(name, parts, move_mask, seed, meta=None) -> Workload:
         o[t == SINGULAR] += vert_off
         geom.part_begin, geom.part_end = n, n + len(p)
         geom.tri_begin, geom.seg_begin, geom.line_begin = tri_off, seg_off, line_off
-        geom.feat_begin, geom.cell_begin, geom.vert_begin = feat_off, cell_off, vert_off
+        geom.feat_begin, geom.vert_begin = feat_off, vert_off
         geoms.append(geom)
         pos.append(p.astype(np.float32))
         tag.append(t)
@@ -204,7 +199,6 @@ def _finish(name, parts, move_mask, seed, meta=None) -> Workload:
         tri_off += geom.mesh.n_tri
         seg_off += geom.mesh.lines.n_seg
         line_off += geom.mesh.lines.n_line
-        cell_off += geom.ncell
         vert_off += len(geom.mesh.vert)
     return Workload(
         name=name, geoms=geoms, pos=np.concatenate(pos, 0), tag=np.concatenate(tag),

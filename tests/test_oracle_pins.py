@@ -141,8 +141,10 @@ def test_cell_keys_contain_particles_and_order_is_key_then_id():
     pos = wl.pos.copy()
     pos[:5] = [[-5, 0.5, 0.5], [0.5, 9, 0.5], [np.nan, 0.5, 0.5], [0.5, 0.5, -1e30], [2, 2, 2]]
     keys = cells.cell_keys(wl, pos32=pos)
-    cell = 1.0 / np.float64(geo.inv_cell)
-    nx, ny, nz = (int(v) for v in geo.dims)
+    # the grid's cells halved along x: edges (cell / 2, cell, cell)
+    cell = 1.0 / np.float64(geo.inv_cell) * np.array([0.5, 1.0, 1.0])
+    nx, ny, nz = 2 * int(geo.dims[0]), int(geo.dims[1]), int(geo.dims[2])
+    assert cells.total_cells(wl) == nx * ny * nz
     fin = np.all(np.isfinite(pos), 1)
     c = np.stack([keys % nx, (keys // nx) % ny, keys // (nx * ny)], 1)
     assert (c[fin] >= 0).all() and (c[fin] < [nx, ny, nz]).all()
@@ -151,6 +153,8 @@ def test_cell_keys_contain_particles_and_order_is_key_then_id():
     x = pos.astype(np.float64)
     tol = 1e-5 * cell
     assert np.all(x[inside] >= lo[inside] - tol) and np.all(x[inside] < lo[inside] + cell + tol)
+    # both halves of the grid's cells are used
+    assert np.any(c[inside, 0] % 2 == 0) and np.any(c[inside, 0] % 2 == 1)
     assert keys[0] == (int(c[0, 2]) * ny + int(c[0, 1])) * nx + 0            # clamped low in x
     assert c[1, 1] == ny - 1 and c[3, 2] == 0                                 # clamped
     assert keys[2] == cells.total_cells(wl)                                   # NaN: quarantine key
