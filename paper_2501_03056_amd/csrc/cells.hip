@@ -76,10 +76,27 @@ __global__ __launch_bounds__(kBlock) void k_key_count(const float4* __restrict__
   }
 }
 
-// Block-wide exclusive scan of 4 items per thread (1024 threads).
+// Block-wide exclusive scan of 8 items per thread (1024 threads); a thread's
+// items are read (and written) as two 16-byte vectors where the array is
+// 16-byte aligned and the items are all in range.
 constexpr int kScanThreads = 1024;
-constexpr int kScanItems = 4;
+constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanThreads * kScanItems;
+
+__device__ __forceinline__ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// The kScanItems items of a thread starting at base (0 past the end).
+__device__ __forceinline__ void load_items(const int* __restrict__ a, int64_t base, int64_t n, int v[kScanItems]) {
+  if (base + kScanItems <= n && aligned16(a)) {
+    const int4 x = *reinterpret_cast<const int4*>(a + base);
+    const int4 y = *reinterpret_cast<const int4*>(a + base + 4);
+    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+    v[4] = y.x; v[5] = y.y; v[6] = y.z; v[7] = y.w;
+    return;
+  }
+#pragma unroll
+  for (int q = 0; q < kScanItems; ++q) v[q] = (base + q < n) ? a[base + q] : 0;
+}
 
 __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
 #pragma unroll
@@ -112,10 +129,11 @@ __device__ __forceinline__ int block_excl_scan(int v, int* total) {
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int* __restrict__ count, int64_t ncell,
                                                               int* __restrict__ blocksum) {
   const int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
+  int v[kScanItems];
+  load_items(count, base, ncell, v);
   int s = 0;
 #pragma unroll
-  for (int q = 0; q < kScanItems; ++q)
-    if (base + q < ncell) s += count[base + q];
+  for (int q = 0; q < kScanItems; ++q) s += v[q];
   int total;
   block_excl_scan(s, &total);
   if (threadIdx.x == 0) blocksum[blockIdx.x] = total;
@@ -138,18 +156,25 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const int* __restric
                                                             int* __restrict__ cell_start, int n) {
   const int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
   int v[kScanItems];
+  load_items(count, base, ncell, v);
   int s = 0;
 #pragma unroll
-  for (int q = 0; q < kScanItems; ++q) {
-    v[q] = (base + q < ncell) ? count[base + q] : 0;
-    s += v[q];
-  }
+  for (int q = 0; q < kScanItems; ++q) s += v[q];
   int total;
   int ex = block_excl_scan(s, &total) + blocksum[blockIdx.x];
+  int o[kScanItems];
 #pragma unroll
   for (int q = 0; q < kScanItems; ++q) {
-    if (base + q < ncell) cell_start[base + q] = ex;
+    o[q] = ex;
     ex += v[q];
+  }
+  if (base + kScanItems <= ncell && aligned16(cell_start)) {
+    *reinterpret_cast<int4*>(cell_start + base) = make_int4(o[0], o[1], o[2], o[3]);
+    *reinterpret_cast<int4*>(cell_start + base + 4) = make_int4(o[4], o[5], o[6], o[7]);
+  } else {
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q)
+      if (base + q < ncell) cell_start[base + q] = o[q];
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) cell_start[ncell] = n;   // ncell here counts the quarantine cell
 }

@@ -31,7 +31,7 @@ WsLayout ws_layout(const Geom* g, int64_t n) {
   L.tmp_src = o;  o += up256(4 * N);
   L.tmp_key = o;  o += up256(4 * N);
   L.count = o;    o += up256(4 * (nc + 2));
-  L.blocksum = o; o += up256(4 * ((nc + 1 + 4095) / 4096 + 2));
+  L.blocksum = o; o += up256(4 * size_t(scan_blocksum_len(nc + 1)));
   L.big = o;      o += up256(4 * (N / 65 + 1));   // cells of more than 64 particles: at most N / 65
   L.build_end = o;
   o = 0;
@@ -41,7 +41,7 @@ WsLayout ws_layout(const Geom* g, int64_t n) {
   const size_t nbl = (N + kBlock - 1) / kBlock;
   L.list_cnt = o;  o += up256(4 * (nbl + 1));
   L.list_offs = o; o += up256(4 * (nbl + 2));
-  L.list_bsum = o; o += up256(4 * ((nbl + 1 + 4095) / 4096 + 2));
+  L.list_bsum = o; o += up256(4 * size_t(scan_blocksum_len(nbl + 1)));
   L.list_end = o;
   o = 0;
   const size_t nvb = (N + kBlock - 1) / kBlock;   // blocks of the volume pass
