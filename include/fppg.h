@@ -74,6 +74,7 @@ typedef int32_t fppg_status;
 
 /* flags of fppg_relax_step */
 #define FPPG_F_COUNT_PAIRS 1u  /* accel.w = number of sources of the receiver (as float) */
+#define FPPG_F_FORCES_ONLY 2u  /* accel and amax only: no displacement (disp may be NULL; accel must not) */
 
 /* device status bits (fppg_read_status) */
 #define FPPG_S_NONFINITE_ACCEL 1u  /* a receiver's acceleration was not finite (it did not move) */
@@ -339,7 +340,9 @@ fppg_status fppg_build_cells(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
  *            disp[4i..4i+1] and disp[4i+2..4i+3] = 0.
  *   volume:  dr;  non-moving: 0.
  * Outputs: accel [n*4] (may be NULL: the workspace holds it; w = 0, or the
- * source count with FPPG_F_COUNT_PAIRS), amax [n_geom] (float), disp [n*4].
+ * source count with FPPG_F_COUNT_PAIRS), amax [n_geom] (float), disp [n*4]
+ * (not written, and may be NULL, with FPPG_F_FORCES_ONLY, which then needs
+ * accel).
  * Non-finite accelerations are excluded from amax and give a zero
  * displacement (FPPG_S_NONFINITE_ACCEL); an out-of-range owner or feature
  * segment gives a zero displacement (FPPG_S_BAD_INDEX).

@@ -12,6 +12,7 @@ LIB_PATH = os.path.join(HERE, "libfppg.so")
 
 OK, E_ARG, E_HIP, E_WORKSPACE, E_CAPACITY, E_UNSUPPORTED, E_NODEVICE = 0, -1, -2, -3, -4, -5, -6
 F_COUNT_PAIRS = 1
+F_FORCES_ONLY = 2   # fppg_relax_step: accel and amax only, no displacement
 CSG_NONE, CSG_UNION, CSG_DIFFERENCE = 0, 1, 2
 S_NONFINITE_ACCEL, S_NONFINITE_POS, S_BAD_INDEX, S_FIXED_RANGE = 1, 2, 4, 8
 C_REVERT_SURFACE, C_REVERT_FEATURE, C_REVERT_VOLUME = 0, 1, 2

@@ -373,7 +373,9 @@ extern "C" fppg_status fppg_relax_step(fppg_ctx* ctx, const fppg_geom* geom, int
   fppg_status st = check_common(ctx, geom, n, pos, cell_start);
   if (st != FPPG_OK) return st;
   if (list && (n_list < 0 || n_list > n)) return fail(ctx, FPPG_E_ARG, "n_list must be in [0, n]");
-  if (!amax || (n > 0 && (!disp || !owner))) return fail(ctx, FPPG_E_ARG, "null amax/disp/owner");
+  const bool forces_only = (flags & FPPG_F_FORCES_ONLY) != 0;
+  if (forces_only && !accel) return fail(ctx, FPPG_E_ARG, "FPPG_F_FORCES_ONLY needs accel");
+  if (!amax || (n > 0 && ((!disp && !forces_only) || !owner))) return fail(ctx, FPPG_E_ARG, "null amax/disp/owner");
   if (n_feat < 0 || (n_feat > 0 && !feat_seg)) return fail(ctx, FPPG_E_ARG, "bad feature table");
   if (!aligned(disp, 16) || (accel && !aligned(accel, 16))) return fail(ctx, FPPG_E_ARG, "accel/disp must be 16-byte aligned");
   const WsLayout L = ws_layout(geom, n);
@@ -398,10 +400,12 @@ extern "C" fppg_status fppg_relax_step(fppg_ctx* ctx, const fppg_geom* geom, int
                  move_mask, acc, ab,
                  ctx->d_status, list);
     }
+    if (!forces_only) {
     PhaseTimer timer(ctx, 2, s);
     k_update<<<grid_for(nr), kBlock, 0, s>>>(p4, acc, owner, feat_seg, ni, n_feat, int(geom->n_tri), int(geom->n_seg),
                                              geom->d_geom, geom->n_geom, amax, geom->d_n32, geom->d_seg, move_mask,
                                              reinterpret_cast<float4*>(disp), ctx->d_status, list, nr);
+    }
   }
   FPPG_HIP(ctx, hipGetLastError());
   return FPPG_OK;

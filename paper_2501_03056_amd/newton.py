@@ -34,7 +34,7 @@ from .relax import Relaxer
 def projected_force(r: Relaxer) -> torch.Tensor:
     """Rebuild the cells at the current positions and return F = P a."""
     r.build_cells()
-    r.relax_step(keep_accel=True)
+    r.relax_step(keep_accel=True, forces_only=True)
     b = r.accel.clone()
     r.tangent(b)
     return b

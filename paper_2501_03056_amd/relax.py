@@ -246,9 +246,12 @@ class Relaxer:
     def _list_args(self):
         return (ptr(self.mlist), self.n_moving()) if self.use_list else (None, 0)
 
-    def relax_step(self, count_pairs: bool = False, keep_accel: bool = True):
+    def relax_step(self, count_pairs: bool = False, keep_accel: bool = True, forces_only: bool = False):
+        """Forces, amax and (unless forces_only) the displacement of every receiver."""
         lib, c = self.ctx.lib, self.ctx.handle
-        flags = L.F_COUNT_PAIRS if count_pairs else 0
+        flags = (L.F_COUNT_PAIRS if count_pairs else 0) | (L.F_FORCES_ONLY if forces_only else 0)
+        if forces_only and not keep_accel:
+            raise ValueError("forces_only needs keep_accel")
         check(lib.fppg_relax_step(c, self.geom.handle, self.na, ptr(self.pos), ptr(self.owner), ptr(self.cell_start),
                                   ptr(self.feat_seg), self.n_feat, self.move_mask, flags,
                                   ptr(self.accel) if keep_accel else None, ptr(self.amax), ptr(self.disp),

@@ -56,6 +56,27 @@ def test_energy_gradient_is_minus_force_on_gpu():
     assert abs(dE + np.sum(a * v)) <= 1e-4 * abs(dE)
 
 
+def test_forces_only_step_equals_the_full_step_and_leaves_disp():
+    """fppg_relax_step with FPPG_F_FORCES_ONLY: the same accelerations and amax
+    bit for bit, and the displacement array is not written."""
+    wl = synth.gear_workload(dx=0.06, seed=3, samples_per_period=12, rings=4)
+    r = _relaxer(wl)
+    r.build_cells()
+    r.relax_step(keep_accel=True)
+    a_full, m_full, d_full = r.accel.clone(), r.amax.clone(), r.disp.clone()
+    assert torch.count_nonzero(d_full) > 0
+    r.accel.fill_(float("nan"))
+    r.amax.fill_(-1.0)
+    r.disp.fill_(7.0)
+    r.relax_step(keep_accel=True, forces_only=True)
+    assert torch.equal(r.accel.view(torch.int32), a_full.view(torch.int32))
+    assert torch.equal(r.amax, m_full)
+    assert bool((r.disp == 7.0).all())
+    with pytest.raises(ValueError):
+        r.relax_step(keep_accel=False, forces_only=True)
+    assert r.read_status() == 0
+
+
 def test_vector_ops_match_numpy():
     wl = _volume_tier(n=9, seed=24)
     r = _relaxer(wl)
