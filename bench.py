@@ -113,10 +113,12 @@ def source_hash(paths):
 COUNTER_PROFILE = "force_gear_volume_counters.md"
 
 
-def profile_value(kernel_hash, key, profile=None):
+def profile_value(kernel_hash, key, profile=None, launch=None):
     """A per-launch figure of the force kernel measured by rocprofv3 counters
     (the committed summary's `kernel_source_hash:` line and the `key:` line),
-    or None if absent or taken on a different kernel source."""
+    or None if absent, taken on a different kernel source, or (launch given as
+    "block,remap,persistent") taken in a different launch shape (the summary's
+    `force_launch:` line)."""
     p = os.path.join(ROOT, "profiles", profile or COUNTER_PROFILE)
     if not os.path.exists(p):
         return None
@@ -125,12 +127,16 @@ def profile_value(kernel_hash, key, profile=None):
     b = re.search(r"^" + key + r":\s*(\d+)", text, re.M)
     if not h or not b or h.group(1) != kernel_hash:
         return None
+    if launch is not None:
+        lm = re.search(r"^force_launch:\s*(\S+)", text, re.M)
+        if not lm or lm.group(1) != launch:
+            return None
     return int(b.group(1))
 
 
-def traffic_from_profile(kernel_hash, profile=None):
+def traffic_from_profile(kernel_hash, profile=None, launch=None):
     """HBM bytes per force launch (FETCH_SIZE and WRITE_SIZE, calibrated)."""
-    return profile_value(kernel_hash, "hbm_bytes_per_launch", profile)
+    return profile_value(kernel_hash, "hbm_bytes_per_launch", profile, launch)
 
 
 # Non-packed VALU issue: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz
@@ -610,6 +616,9 @@ def main():
     ap.add_argument("--no-secondary", action="store_true", help="skip the icosphere secondary workload")
     ap.add_argument("--cpu-sample", type=int, default=1 << 19)
     ap.add_argument("--k", type=int, default=2, help="stencil half-width of the particle cells (1 or 2)")
+    ap.add_argument("--launch", default="auto",
+                    help="force kernel launch shape of the timed gear tier: 'auto' (autotuned) or "
+                         "'block,xcd_remap,persistent', e.g. 256,1,0")
     ap.add_argument("--slab", type=int, default=0,
                     help="cell rows per slab of the cell key (0: one slab per geometry)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -691,7 +700,7 @@ def _warm_newton(rn, n_moving, kw):
     torch.cuda.synchronize()
 
 
-def newton_vs_plain(wl, mm, plain_iters, krylov_max):
+def newton_vs_plain(wl, mm, plain_iters, krylov_max, shape=None):
     """Newton-MINRES against the plain loop from the same state on one tier:
     the plain loop's residual after its iterations is the target; the
     headline ratio is the plain loop's FIRST arrival at that residual over
@@ -704,6 +713,8 @@ def newton_vs_plain(wl, mm, plain_iters, krylov_max):
     n_moving = wl.n_moving()
     rp = Relaxer(wl, device=0)
     rp.tier(mm)
+    if shape:
+        rp.ctx.set_launch(*shape)
     plain = plain_relax(rp, n_moving, iters=plain_iters, record_every=1)
     target, t_plain = plain[-1][1], plain[-1][0]
     t_first = _first_at_or_below(plain, target)
@@ -711,6 +722,8 @@ def newton_vs_plain(wl, mm, plain_iters, krylov_max):
     del rp
     rn = Relaxer(wl, device=0)
     rn.tier(mm)
+    if shape:
+        rn.ctx.set_launch(*shape)
     torch.cuda.synchronize()
     kw = dict(forcing="ew", krylov_tol=1e-4, krylov_max=krylov_max, checkpoint_every=10)
     _warm_newton(rn, n_moving, kw)
@@ -730,6 +743,22 @@ def newton_vs_plain(wl, mm, plain_iters, krylov_max):
                               "krylov_iters": log.krylov_iters, "backtracks": log.backtracks},
             "vs_plain_final": (t_plain / t_newton) if reached else None,
             "krylov": "MINRES", "forcing": "Eisenstat-Walker 2", "krylov_max": krylov_max}
+
+
+def choose_launch(args, wl):
+    """The force kernel's launch shape for the timed tier: --launch B,R,P
+    (threads per block, XCD remap, persistent tickets) or auto, the
+    autotuner's shape search (tune.autotune at the workload's stencil, eager
+    launches; 20 timed iterations per shape, cached per device in TMPDIR)."""
+    from paper_2501_03056_amd.tune import autotune
+    if args.launch != "auto":
+        b, rm, ps = (int(v) for v in args.launch.split(","))
+        return {"force_block": b, "xcd_remap": bool(rm), "persistent": bool(ps), "source": "fixed"}
+    t = autotune(wl, candidates=(args.k,), modes=("eager",), steps=20, warmup=4,
+                 cache=os.path.join(os.environ.get("TMPDIR", "/tmp"), "fppg_autotune_step.json"))
+    print(f"[bench] launch shapes (ms per iteration): {t['launch_ms_per_step']}", file=sys.stderr, flush=True)
+    return {"force_block": t["force_block"], "xcd_remap": bool(t["xcd_remap"]), "persistent": bool(t["persistent"]),
+            "source": "autotuned", "ms_per_step": t["launch_ms_per_step"]}
 
 
 def bench_step(args):
@@ -753,8 +782,11 @@ def bench_step(args):
           file=sys.stderr, flush=True)
     mm_vol = 1 << synth.VOLUME
     wl.move_mask = mm_vol
+    launch = choose_launch(args, wl)
+    shape = (launch["force_block"], launch["xcd_remap"], launch["persistent"])
     r = Relaxer(wl, device=0)
     r.tier(mm_vol)
+    r.ctx.set_launch(*shape)
     n_moving = r.n_moving()
     main = timed_steps(r, args.steps, args.warmup, "gear volume tier")
     ncell = int(r.geom.ncell)
@@ -780,7 +812,7 @@ def bench_step(args):
                                                                for k in ("feature", "surface", "volume"))
     wl.move_mask = mm_vol
     newton = None if args.no_newton else newton_vs_plain(wl, mm_vol, args.plain_iters,
-                                                         krylov_cap(args.krylov_max, "volume"))
+                                                         krylov_cap(args.krylov_max, "volume"), shape)
     secondary = None
     if not args.no_secondary:
         sw, sname = make_workload("sphere", args.k, args.slab)
@@ -799,7 +831,8 @@ def bench_step(args):
     force_ms = main["force_ms"]
     achieved = pairs * FLOPS_PER_PAIR / (force_ms / 1e3) / 1e12
     khash = source_hash(KERNEL_SOURCES)
-    traffic = traffic_from_profile(khash)
+    launch_key = f"{shape[0]},{int(shape[1])},{int(shape[2])}"
+    traffic = traffic_from_profile(khash, launch=launch_key)
     hbm = hbm_phases(wl.n, ncell, n_moving, 0, main["phase_ms"], main["ms_step"])
     out = {
         "metric": "particle-updates/s per relaxation step",
@@ -816,7 +849,7 @@ def bench_step(args):
         "data": "synthetic",
         "config": {"workload": wname, "particles": wl.n, "moving": n_moving, "counts": wl.counts(),
                    "facets": n_tri, "stencil_k": int(wl.geoms[0].k), "key_slab_rows": int(args.slab),
-                   "h_over_dx": 1.3, "pairs_per_step": pairs},
+                   "h_over_dx": 1.3, "pairs_per_step": pairs, "force_launch": launch},
         "pair_evals_per_s": pairs * steps / (ms / 1e3),
         "kernels_ms_per_step": main["phase_ms"],
         "hbm_phases": hbm,
