@@ -816,14 +816,16 @@ def bench_step(args):
     secondary = None
     if not args.no_secondary:
         sw, sname = make_workload("sphere", args.k, args.slab)
+        s_launch = choose_launch(args, sw)
         rs = Relaxer(sw, device=0)
+        rs.ctx.set_launch(s_launch["force_block"], s_launch["xcd_remap"], s_launch["persistent"])
         t = timed_steps(rs, args.steps, args.warmup, "sphere")
         secondary = {"workload": sname, "particles": sw.n, "moving": sw.n_moving(),
                      "value": sw.n_moving() * args.steps / (t["ms"] / 1e3), "unit": "particle-updates/s",
                      "ms_per_step": t["ms_step"], "pair_evals_per_s": t["pairs"] * args.steps / (t["ms"] / 1e3),
                      "force_kernel_ms": t["force_ms"],
                      "force_tflops": t["pairs"] * FLOPS_PER_PAIR / (t["force_ms"] / 1e3) / 1e12,
-                     "kernels_ms_per_step": t["phase_ms"], "device_status": t["status"]}
+                     "kernels_ms_per_step": t["phase_ms"], "device_status": t["status"], "force_launch": s_launch}
         del rs, sw
 
     ms, steps = main["ms"], args.steps

@@ -82,9 +82,11 @@ struct ProjectOut {
 template <int K, bool TRANSPOSE, bool PROJECT = false>
 __global__ __launch_bounds__(kBlock) void k_jvp(const float4* __restrict__ pos, int n, const int* __restrict__ cs,
                                                 const GeomDev* __restrict__ geoms, int n_geom, uint32_t move_mask,
-                                                const float4* __restrict__ v, float4* __restrict__ out,
+                                                const float4* __restrict__ v, float4* __restrict__ out, bool remap,
                                                 ProjectOut po = ProjectOut{}) {
-  const int i = xcd_chunk(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  // blocks dealt to the XCDs round-robin, or each XCD on one contiguous range
+  // of receivers (the context's force launch setting; per-lane sums either way)
+  const int i = (remap ? xcd_chunk(blockIdx.x, gridDim.x) : int(blockIdx.x)) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float4 p = pos[i];
   const int tag = tag_of(p.w);
@@ -218,11 +220,11 @@ extern "C" fppg_status fppg_relax_hvp(fppg_ctx* ctx, const fppg_geom* geom, int6
   float4* o4 = reinterpret_cast<float4*>(Jv);
   PhaseTimer timer(ctx, 4, s);
   if (geom->k == 1) {
-    if (transpose) k_jvp<1, true><<<grid_for(ni), kBlock, 0, s>>>(p4, ni, cell_start, geom->d_geom, geom->n_geom, move_mask, v4, o4);
-    else k_jvp<1, false><<<grid_for(ni), kBlock, 0, s>>>(p4, ni, cell_start, geom->d_geom, geom->n_geom, move_mask, v4, o4);
+    if (transpose) k_jvp<1, true><<<grid_for(ni), kBlock, 0, s>>>(p4, ni, cell_start, geom->d_geom, geom->n_geom, move_mask, v4, o4, ctx->xcd_remap);
+    else k_jvp<1, false><<<grid_for(ni), kBlock, 0, s>>>(p4, ni, cell_start, geom->d_geom, geom->n_geom, move_mask, v4, o4, ctx->xcd_remap);
   } else {
-    if (transpose) k_jvp<2, true><<<grid_for(ni), kBlock, 0, s>>>(p4, ni, cell_start, geom->d_geom, geom->n_geom, move_mask, v4, o4);
-    else k_jvp<2, false><<<grid_for(ni), kBlock, 0, s>>>(p4, ni, cell_start, geom->d_geom, geom->n_geom, move_mask, v4, o4);
+    if (transpose) k_jvp<2, true><<<grid_for(ni), kBlock, 0, s>>>(p4, ni, cell_start, geom->d_geom, geom->n_geom, move_mask, v4, o4, ctx->xcd_remap);
+    else k_jvp<2, false><<<grid_for(ni), kBlock, 0, s>>>(p4, ni, cell_start, geom->d_geom, geom->n_geom, move_mask, v4, o4, ctx->xcd_remap);
   }
   FPPG_HIP(ctx, hipGetLastError());
   return FPPG_OK;
@@ -248,9 +250,9 @@ extern "C" fppg_status fppg_relax_hvp_projected(fppg_ctx* ctx, const fppg_geom* 
   float4* o4 = reinterpret_cast<float4*>(out);
   PhaseTimer timer(ctx, 4, s);
   if (geom->k == 1)
-    k_jvp<1, false, true><<<grid_for(ni), kBlock, 0, s>>>(p4, ni, cell_start, geom->d_geom, geom->n_geom, move_mask, v4, o4, po);
+    k_jvp<1, false, true><<<grid_for(ni), kBlock, 0, s>>>(p4, ni, cell_start, geom->d_geom, geom->n_geom, move_mask, v4, o4, ctx->xcd_remap, po);
   else
-    k_jvp<2, false, true><<<grid_for(ni), kBlock, 0, s>>>(p4, ni, cell_start, geom->d_geom, geom->n_geom, move_mask, v4, o4, po);
+    k_jvp<2, false, true><<<grid_for(ni), kBlock, 0, s>>>(p4, ni, cell_start, geom->d_geom, geom->n_geom, move_mask, v4, o4, ctx->xcd_remap, po);
   FPPG_HIP(ctx, hipGetLastError());
   return FPPG_OK;
 }
