@@ -46,7 +46,6 @@ WsLayout ws_layout(const Geom* g, int64_t n) {
   o = 0;
   const size_t nvb = (N + kBlock - 1) / kBlock;   // blocks of the volume pass
   L.proj_count = o; o += up256(4 * nvb);
-  L.proj_vrev = o;  o += up256(4 * nvb);
   L.proj_part = o;  o += up256(16 * nvb);   // one per k_project_heavy block (at most one per volume block)
   L.proj_queue = o; o += up256(4 * (N + kBlock));   // every entry lies below (launch blocks) * kBlock
   L.proj_hard = o;  o += up256(4 * (N + 1));          // count, then the particles the parallel search takes

@@ -182,9 +182,9 @@ struct WsLayout {
   size_t accel, step_end;
   // moving_list (block counts, their offsets, scan partials)
   size_t list_cnt, list_offs, list_bsum, list_end;
-  // project (per volume-pass block: queue length and volume reverts; per
-  // k_project_heavy block: revert counts; the queue of surface and feature particles)
-  size_t proj_count, proj_vrev, proj_part, proj_queue, proj_hard, proj_end;
+  // project (per volume-pass block: queue length; per k_project_heavy block:
+  // revert counts; the queue of surface, feature and near-facet volume particles)
+  size_t proj_count, proj_part, proj_queue, proj_hard, proj_end;
   // relax_energy / vec_dot partial sums
   size_t reduce_end;
   size_t total;

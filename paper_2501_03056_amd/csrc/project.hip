@@ -183,21 +183,45 @@ __device__ __forceinline__ bool cell_crossed(int64_t c, double x0, double x1, do
   return false;
 }
 
+// The search cells of the segment's box, widened by 1e-7 cell units and
+// clipped to the grid: [lo, hi] per axis (empty where lo > hi).
+__device__ __forceinline__ void segment_cells(const GeomDev& G, double x0, double x1, double x2, double y0, double y1,
+                                              double y2, int lo[3], int hi[3]) {
+  const double pad = 1e-7;   // cell units
+  lo[0] = max(int(floor(search_t(G, 0, fmin(x0, y0)) - pad)), 0);
+  hi[0] = min(int(floor(search_t(G, 0, fmax(x0, y0)) + pad)), G.tg_dims[0] - 1);
+  lo[1] = max(int(floor(search_t(G, 1, fmin(x1, y1)) - pad)), 0);
+  hi[1] = min(int(floor(search_t(G, 1, fmax(x1, y1)) + pad)), G.tg_dims[1] - 1);
+  lo[2] = max(int(floor(search_t(G, 2, fmin(x2, y2)) - pad)), 0);
+  hi[2] = min(int(floor(search_t(G, 2, fmax(x2, y2)) + pad)), G.tg_dims[2] - 1);
+}
+
 __device__ __forceinline__ bool segment_crosses(const GeomDev& G, double x0, double x1, double x2, double y0,
                                                 double y1, double y2, const FacetDev* __restrict__ facets,
                                                 const int* __restrict__ tstart, const int* __restrict__ ttri,
                                                 const uint8_t* __restrict__ tflag, const CsgDev& cs) {
-  const double pad = 1e-7;   // cell units
-  const int lx = int(floor(search_t(G, 0, fmin(x0, y0)) - pad)), hx = int(floor(search_t(G, 0, fmax(x0, y0)) + pad));
-  const int ly = int(floor(search_t(G, 1, fmin(x1, y1)) - pad)), hy = int(floor(search_t(G, 1, fmax(x1, y1)) + pad));
-  const int lz = int(floor(search_t(G, 2, fmin(x2, y2)) - pad)), hz = int(floor(search_t(G, 2, fmax(x2, y2)) + pad));
-  for (int z = max(lz, 0); z <= min(hz, G.tg_dims[2] - 1); ++z)
-    for (int y = max(ly, 0); y <= min(hy, G.tg_dims[1] - 1); ++y)
-      for (int x = max(lx, 0); x <= min(hx, G.tg_dims[0] - 1); ++x) {
+  int lo[3], hi[3];
+  segment_cells(G, x0, x1, x2, y0, y1, y2, lo, hi);
+  for (int z = lo[2]; z <= hi[2]; ++z)
+    for (int y = lo[1]; y <= hi[1]; ++y)
+      for (int x = lo[0]; x <= hi[0]; ++x) {
         const int64_t c = search_index(G, x, y, z);
         if ((tflag[c] & kCellHasFacet) && cell_crossed(c, x0, x1, x2, y0, y1, y2, facets, tstart, ttri, G, cs))
           return true;
       }
+  return false;
+}
+
+// Does the segment's box touch a search cell with registered facets? If not,
+// segment_crosses is false without a facet test.
+__device__ __forceinline__ bool segment_near_facets(const GeomDev& G, double x0, double x1, double x2, double y0,
+                                                    double y1, double y2, const uint8_t* __restrict__ tflag) {
+  int lo[3], hi[3];
+  segment_cells(G, x0, x1, x2, y0, y1, y2, lo, hi);
+  for (int z = lo[2]; z <= hi[2]; ++z)
+    for (int y = lo[1]; y <= hi[1]; ++y)
+      for (int x = lo[0]; x <= hi[0]; ++x)
+        if (tflag[search_index(G, x, y, z)] & kCellHasFacet) return true;
   return false;
 }
 
@@ -233,10 +257,12 @@ __device__ __forceinline__ bool feature_walk(const SegDev* __restrict__ segs, in
   return u >= 0.0 && u <= segs[s].len;
 }
 
-// Volume particles (and the class dispatch) in a lean kernel; surface and
-// feature particles, whose FP64 searches need several times the registers, go
-// to a queue that k_project_heavy takes: the streaming volume pass keeps a
-// high occupancy. Each block of the volume pass compacts its queued particles
+// Volume particles (and the class dispatch) in a lean kernel: a volume move
+// whose box touches no search cell with facets is applied at once (it cannot
+// cross the surface); surface and feature particles, and volume moves next to
+// facets, whose FP64 tests need several times the registers, go to a queue
+// that k_project_heavy takes: the streaming volume pass keeps a high
+// occupancy. Each block of the volume pass compacts its queued particles
 // (in index order) into its own kBlock slots of the queue and stores their
 // number: no atomics, and the queue is the same on every run.
 // ONE_GEOM: a single geometry, whose descriptor is then read with scalar loads
@@ -244,17 +270,14 @@ __device__ __forceinline__ bool feature_walk(const SegDev* __restrict__ segs, in
 template <bool ONE_GEOM>
 __global__ __launch_bounds__(kBlock) void k_project_volume(float4* __restrict__ pos, const float4* __restrict__ disp,
                                                            int n, const GeomDev* __restrict__ geoms, int n_geom,
-                                                           const FacetDev* __restrict__ facets,
-                                                           const int* __restrict__ tstart,
-                                                           const int* __restrict__ ttri,
                                                            const uint8_t* __restrict__ tflag, uint32_t move_mask,
                                                            uint32_t* status, uint8_t* __restrict__ accepted,
                                                            const int* __restrict__ list, int n_list,
                                                            int* __restrict__ queue, int* __restrict__ qcount,
-                                                           int* __restrict__ vrev, CsgDev cs, int* __restrict__ hard) {
+                                                           int* __restrict__ hard) {
   if (blockIdx.x == 0 && threadIdx.x == 0) hard[0] = 0;   // the wide-search queue of this projection
   const int i = listed(blockIdx.x * blockDim.x + threadIdx.x, n, list, n_list);
-  bool rev_v = false, heavy = false;
+  bool heavy = false;
   if (i < n) {
     const float4 p = pos[i];
     const float4 d = disp[i];   // loaded with the position: one memory round trip for both
@@ -266,10 +289,10 @@ __global__ __launch_bounds__(kBlock) void k_project_volume(float4* __restrict__ 
         const float y0 = p.x + d.x, y1 = p.y + d.y, y2 = p.z + d.z;
         if (!(isfinite(y0) && isfinite(y1) && isfinite(y2))) {
           atomicOr(status, FPPG_S_NONFINITE_POS);
-        } else if (segment_crosses(G, p.x, p.y, p.z, y0, y1, y2, facets, tstart, ttri, tflag, cs)) {
-          rev_v = true;                                    // would leave the volume: stays at x
+        } else if (segment_near_facets(G, p.x, p.y, p.z, y0, y1, y2, tflag)) {
+          heavy = true;                                    // the facet test in k_project_heavy
         } else {
-          pos[i] = make_float4(y0, y1, y2, p.w);
+          pos[i] = make_float4(y0, y1, y2, p.w);           // no facet near the move: it stays inside
           moved = true;
         }
       } else {
@@ -279,32 +302,24 @@ __global__ __launch_bounds__(kBlock) void k_project_volume(float4* __restrict__ 
     if (accepted && !heavy) accepted[i] = moved ? 1 : 0;
   }
   // compact the heavy lanes of the block into its queue slots
-  // (and count the block's volume reverts: one store per block, summed by
-  // k_project_heavy and k_project_counts instead of contended atomics)
-  __shared__ int s_wcnt[kBlock / 64], s_wrev[kBlock / 64];
+  __shared__ int s_wcnt[kBlock / 64];
   const uint64_t m = __ballot(heavy);
-  const int nrev = __popcll(__ballot(rev_v));
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (lane == 0) {
-    s_wcnt[w] = __popcll(m);
-    s_wrev[w] = nrev;
-  }
+  if (lane == 0) s_wcnt[w] = __popcll(m);
   __syncthreads();
-  int base = 0, total = 0, revs = 0;
+  int base = 0, total = 0;
 #pragma unroll
   for (int k = 0; k < kBlock / 64; ++k) {
     base += k < w ? s_wcnt[k] : 0;
     total += s_wcnt[k];
-    revs += s_wrev[k];
   }
   if (heavy) queue[blockIdx.x * kBlock + base + __popcll(m & ((1ull << lane) - 1))] = i;
-  if (threadIdx.x == 0) {
-    qcount[blockIdx.x] = total;
-    vrev[blockIdx.x] = revs;
-  }
+  if (threadIdx.x == 0) qcount[blockIdx.x] = total;
 }
 
-// Surface reprojection and feature walks of the queued particles: block b
+// Facet tests of the queued volume moves (segment_crosses, the decision the
+// volume pass defers), surface reprojection and feature walks of the queued
+// particles: block b
 // takes the queues of volume-pass blocks [b, b + 1) * group, read as one list
 // (the counts' prefix sums in LDS). group is 1 when every moving particle
 // goes to the queue (no volume particle moves: dense queues, one block each)
@@ -321,11 +336,10 @@ __global__ __launch_bounds__(kBlock) void k_project_heavy(float4* __restrict__ p
                                                           const uint8_t* __restrict__ tflag,
                                                           uint32_t* status, uint8_t* __restrict__ accepted,
                                                           const int* __restrict__ queue,
-                                                          const int* __restrict__ qcount,
-                                                          const int* __restrict__ vrev, int n_vblocks, int group,
+                                                          const int* __restrict__ qcount, int n_vblocks, int group,
                                                           int4* __restrict__ part, CsgDev cs, int* __restrict__ hard) {
   __shared__ int s_pre[kHeavyGroupMax + 1];
-  __shared__ int s_rev[2];
+  __shared__ int s_rev[3];
   const int b0 = blockIdx.x * group;
   if (threadIdx.x == 0) {
     int acc = 0;
@@ -334,13 +348,13 @@ __global__ __launch_bounds__(kBlock) void k_project_heavy(float4* __restrict__ p
       acc += b0 + k < n_vblocks ? qcount[b0 + k] : 0;
     }
     s_pre[group] = acc;
-    s_rev[0] = s_rev[1] = 0;
+    s_rev[0] = s_rev[1] = s_rev[2] = 0;
   }
   __syncthreads();
   const int cnt = s_pre[group];
-  int rs = 0, rf = 0;   // this lane's surface and feature reverts
+  int rs = 0, rf = 0, rv = 0;   // this lane's surface, feature and volume reverts
   for (int q = threadIdx.x; q < cnt; q += kBlock) {
-    bool rev_s = false, rev_f = false;
+    bool rev_s = false, rev_f = false, rev_v = false;
     {
       int k = 0;
       while (k + 1 < group && s_pre[k + 1] <= q) ++k;
@@ -350,7 +364,15 @@ __global__ __launch_bounds__(kBlock) void k_project_heavy(float4* __restrict__ p
       const float4 d = disp[i];
       const GeomDev& G = geoms[min(geom_of(p.w), n_geom - 1)];
       bool moved = false;
-      if (tag == FPPG_TAG_SURFACE) {
+      if (tag == FPPG_TAG_VOLUME) {   // a move next to facets (finite, queued by the volume pass)
+        const float y0 = p.x + d.x, y1 = p.y + d.y, y2 = p.z + d.z;
+        if (segment_crosses(G, p.x, p.y, p.z, y0, y1, y2, facets, tstart, ttri, tflag, cs)) {
+          rev_v = true;                                    // would leave the volume: stays at x
+        } else {
+          pos[i] = make_float4(y0, y1, y2, p.w);
+          moved = true;
+        }
+      } else if (tag == FPPG_TAG_SURFACE) {
         const double yx = double(p.x) + double(d.x), yy = double(p.y) + double(d.y), yz = double(p.z) + double(d.z);
         if (!(isfinite(yx) && isfinite(yy) && isfinite(yz))) {
           atomicOr(status, FPPG_S_NONFINITE_POS);
@@ -390,15 +412,13 @@ __global__ __launch_bounds__(kBlock) void k_project_heavy(float4* __restrict__ p
     }
     rs += rev_s;
     rf += rev_f;
+    rv += rev_v;
   }
   if (rs) atomicAdd(&s_rev[0], rs);
   if (rf) atomicAdd(&s_rev[1], rf);
+  if (rv) atomicAdd(&s_rev[2], rv);
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int rv = 0;
-    for (int k = 0; k < group; ++k) rv += b0 + k < n_vblocks ? vrev[b0 + k] : 0;
-    part[blockIdx.x] = make_int4(s_rev[0], s_rev[1], rv, 0);
-  }
+  if (threadIdx.x == 0) part[blockIdx.x] = make_int4(s_rev[0], s_rev[1], s_rev[2], 0);
 }
 
 // Surface particles whose own search cell accepts no facet: one wavefront
@@ -521,7 +541,6 @@ static fppg_status project_impl(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
   const int nr = list ? int(n_list) : ni;
   if (nr == 0) return FPPG_OK;
   int* qcount = reinterpret_cast<int*>(static_cast<char*>(ws) + L.proj_count);
-  int* vrev = reinterpret_cast<int*>(static_cast<char*>(ws) + L.proj_vrev);
   int4* part = reinterpret_cast<int4*>(static_cast<char*>(ws) + L.proj_part);
   int* queue = reinterpret_cast<int*>(static_cast<char*>(ws) + L.proj_queue);
   int* hard = reinterpret_cast<int*>(static_cast<char*>(ws) + L.proj_hard);
@@ -531,19 +550,16 @@ static fppg_status project_impl(fppg_ctx* ctx, const fppg_geom* geom, int64_t n,
   PhaseTimer timer(ctx, 3, s);
   const int vb = grid_for(nr);
   if (geom->n_geom == 1)
-    k_project_volume<true><<<vb, kBlock, 0, s>>>(p4, d4, ni, geom->d_geom, 1, geom->d_facet, geom->d_tg_start,
-                                                 geom->d_tg_tri, geom->d_tg_flag, move_mask, ctx->d_status, accepted,
-                                                 list, nr, queue, qcount, vrev, geom->csg(), hard);
+    k_project_volume<true><<<vb, kBlock, 0, s>>>(p4, d4, ni, geom->d_geom, 1, geom->d_tg_flag, move_mask,
+                                                 ctx->d_status, accepted, list, nr, queue, qcount, hard);
   else
-    k_project_volume<false><<<vb, kBlock, 0, s>>>(p4, d4, ni, geom->d_geom, geom->n_geom, geom->d_facet,
-                                                  geom->d_tg_start, geom->d_tg_tri, geom->d_tg_flag, move_mask,
-                                                  ctx->d_status, accepted, list, nr, queue, qcount, vrev, geom->csg(),
-                                                  hard);
+    k_project_volume<false><<<vb, kBlock, 0, s>>>(p4, d4, ni, geom->d_geom, geom->n_geom, geom->d_tg_flag,
+                                                  move_mask, ctx->d_status, accepted, list, nr, queue, qcount, hard);
   const int group = (move_mask >> FPPG_TAG_VOLUME) & 1u ? kHeavyGroupMax : 1;
   const int hb = (vb + group - 1) / group;
   k_project_heavy<<<hb, kBlock, 0, s>>>(p4, owner, d4, feat_seg, feat_u, n_feat, int(geom->n_seg), geom->d_seg,
                                         geom->d_geom, geom->n_geom, geom->d_facet, geom->d_tg_start, geom->d_tg_tri,
-                                        geom->d_tg_flag, ctx->d_status, accepted, queue, qcount, vrev, vb, group,
+                                        geom->d_tg_flag, ctx->d_status, accepted, queue, qcount, vb, group,
                                         part, geom->csg(), hard);
   k_project_counts<<<1, kBlock, 0, s>>>(part, hb, ctr);
   // the wide searches: every wavefront loops over the queue, whose length the device holds
