@@ -618,7 +618,8 @@ def main():
     ap.add_argument("--k", type=int, default=2, help="stencil half-width of the particle cells (1 or 2)")
     ap.add_argument("--launch", default="auto",
                     help="force kernel launch shape of the timed gear tier: 'auto' (autotuned) or "
-                         "'block,xcd_remap,persistent', e.g. 256,1,0")
+                         "'block,xcd_remap,persistent', e.g. 256,1,0 (xcd_remap 0 round-robin, "
+                         "1 one contiguous range per XCD, 2 runs of 16 chunks)")
     ap.add_argument("--slab", type=int, default=0,
                     help="cell rows per slab of the cell key (0: one slab per geometry)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -753,11 +754,11 @@ def choose_launch(args, wl):
     from paper_2501_03056_amd.tune import autotune
     if args.launch != "auto":
         b, rm, ps = (int(v) for v in args.launch.split(","))
-        return {"force_block": b, "xcd_remap": bool(rm), "persistent": bool(ps), "source": "fixed"}
+        return {"force_block": b, "xcd_remap": rm, "persistent": bool(ps), "source": "fixed"}
     t = autotune(wl, candidates=(args.k,), modes=("eager",), steps=20, warmup=4,
                  cache=os.path.join(os.environ.get("TMPDIR", "/tmp"), "fppg_autotune_step.json"))
     print(f"[bench] launch shapes (ms per iteration): {t['launch_ms_per_step']}", file=sys.stderr, flush=True)
-    return {"force_block": t["force_block"], "xcd_remap": bool(t["xcd_remap"]), "persistent": bool(t["persistent"]),
+    return {"force_block": t["force_block"], "xcd_remap": int(t["xcd_remap"]), "persistent": bool(t["persistent"]),
             "source": "autotuned", "ms_per_step": t["launch_ms_per_step"]}
 
 

@@ -211,11 +211,15 @@ fppg_status fppg_profile(fppg_ctx* ctx, uint32_t phases);
 fppg_status fppg_profile_read(fppg_ctx* ctx, double* ms /*[FPPG_NPHASES]*/, int64_t* launches /*[FPPG_NPHASES]*/);
 
 /*
- * Launch shape of the force kernel of fppg_relax_step, chosen by the
- * autotuner: force_block threads per block (128, 256 or 512) and whether the
- * blocks of each of the 8 XCDs take one contiguous range of receivers
- * (xcd_remap 1) or blocks are dealt out round-robin (0). No result depends on
- * the choice (per-receiver sums; amax is a maximum). Defaults 256 and 1.
+ * Launch shape of the force kernel of fppg_relax_step (and of the Jacobian
+ * products), chosen by the autotuner: force_block threads per block (128, 256
+ * or 512) and the mapping of blocks to the 8 XCDs (each with its own L2):
+ * xcd_remap 0 keeps the hardware's round-robin deal, 1 gives each XCD one
+ * contiguous range of receivers, 2 deals runs of 16 consecutive chunks of
+ * force_block receivers to the XCDs in turn (each XCD walks many short
+ * contiguous stretches spread over the domain; chunks past the last whole
+ * round of 8 runs keep the round-robin deal). No result depends on the choice
+ * (per-receiver sums; amax is a maximum). Defaults 256 and 1.
  * Applies to later calls on the context (and to graphs captured after it).
  * Errors: FPPG_E_ARG for other values.
  */
@@ -226,7 +230,7 @@ fppg_status fppg_set_launch(fppg_ctx* ctx, int32_t force_block, int32_t xcd_rema
  * persistent = 0 launches one block per chunk of force_block receivers;
  * persistent = 1 launches as many blocks as fit on the device at once, each
  * taking chunks by tickets: the blocks of XCD x (workgroup b runs on XCD b %
- * 8) first take the contiguous range of chunks that xcd_remap would give x,
+ * 8) first take the contiguous range of chunks that xcd_remap 1 would give x,
  * then the other XCDs' leftovers. The ticket counters are cleared by a small
  * kernel before every launch (stream-ordered; graph-capturable) and live in
  * the context, so calls on one context must not overlap. No result depends

@@ -168,16 +168,16 @@ __device__ __forceinline__ void force_chunk(int blk, const float4* __restrict__ 
   __syncthreads();   // s_max / s_geo are reused by the block's next chunk
 }
 
-// One block per chunk of B receivers. remap: the blocks of each XCD take one
-// contiguous range of chunks (xcd_chunk). Neither changes a result (per-lane
-// sums, max-reduced amax).
+// One block per chunk of B receivers. remap: the XCD mapping of the blocks
+// (launch_chunk: round-robin, one contiguous range per XCD, or runs of
+// chunks). None changes a result (per-lane sums, max-reduced amax).
 template <int K, bool COUNT, int B, bool MR = false>
 __global__ __launch_bounds__(B) void k_force(const float4* __restrict__ pos, int n,
                                              const int* __restrict__ cs, const GeomDev* __restrict__ geoms,
                                              int n_geom, uint32_t move_mask, float4* __restrict__ accel,
                                              unsigned* __restrict__ amax_bits, uint32_t* status,
-                                             const int* __restrict__ list, int n_list, bool remap) {
-  const int blk = remap ? xcd_chunk(blockIdx.x, gridDim.x) : int(blockIdx.x);
+                                             const int* __restrict__ list, int n_list, int remap) {
+  const int blk = launch_chunk(remap, int(blockIdx.x), int(gridDim.x));
   force_chunk<K, COUNT, B, MR>(blk, pos, n, cs, geoms, n_geom, move_mask, accel, amax_bits, status, list, n_list);
 }
 
@@ -284,7 +284,8 @@ static inline int grid_for(int64_t n) { return int((n + kBlock - 1) / kBlock); }
 // or the persistent ticket schedule with as many resident blocks as fit.
 struct ForceLaunch {
   int block;
-  bool remap, persistent;
+  int remap;   // XCD mapping of the workgroups (launch_chunk)
+  bool persistent;
   int* tickets;
   fppg_ctx* ctx;   // occupancy of the persistent kernel, queried once per context
 };
@@ -322,7 +323,7 @@ static void launch_force_k(const ForceLaunch& fl, int nr, hipStream_t s, const f
 }
 
 template <int K, bool COUNT>
-static void launch_force_mr(bool remap, int nr, hipStream_t s, const float4* p4, int n, const int* cs,
+static void launch_force_mr(int remap, int nr, hipStream_t s, const float4* p4, int n, const int* cs,
                             const GeomDev* g, int n_geom, uint32_t mm, float4* acc, unsigned* ab, uint32_t* st,
                             const int* list) {
   k_force<K, COUNT, 256, true><<<(nr + 255) / 256, 256, 0, s>>>(p4, n, cs, g, n_geom, mm, acc, ab, st, list, nr, remap);
@@ -415,9 +416,9 @@ extern "C" fppg_status fppg_set_launch(fppg_ctx* ctx, int32_t force_block, int32
   if (!ctx) return FPPG_E_ARG;
   if (force_block != 128 && force_block != 256 && force_block != 512)
     return fail(ctx, FPPG_E_ARG, "force_block must be 128, 256 or 512");
-  if (xcd_remap != 0 && xcd_remap != 1) return fail(ctx, FPPG_E_ARG, "xcd_remap must be 0 or 1");
+  if (xcd_remap < 0 || xcd_remap > 2) return fail(ctx, FPPG_E_ARG, "xcd_remap must be 0, 1 or 2");
   ctx->force_block = force_block;
-  ctx->xcd_remap = xcd_remap != 0;
+  ctx->xcd_remap = xcd_remap;
   return FPPG_OK;
 }
 

@@ -82,11 +82,11 @@ struct ProjectOut {
 template <int K, bool TRANSPOSE, bool PROJECT = false>
 __global__ __launch_bounds__(kBlock) void k_jvp(const float4* __restrict__ pos, int n, const int* __restrict__ cs,
                                                 const GeomDev* __restrict__ geoms, int n_geom, uint32_t move_mask,
-                                                const float4* __restrict__ v, float4* __restrict__ out, bool remap,
+                                                const float4* __restrict__ v, float4* __restrict__ out, int remap,
                                                 ProjectOut po = ProjectOut{}) {
-  // blocks dealt to the XCDs round-robin, or each XCD on one contiguous range
-  // of receivers (the context's force launch setting; per-lane sums either way)
-  const int i = (remap ? xcd_chunk(blockIdx.x, gridDim.x) : int(blockIdx.x)) * blockDim.x + threadIdx.x;
+  // the blocks' XCD mapping is the context's force launch setting
+  // (launch_chunk; per-lane sums whichever it is)
+  const int i = launch_chunk(remap, int(blockIdx.x), int(gridDim.x)) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float4 p = pos[i];
   const int tag = tag_of(p.w);

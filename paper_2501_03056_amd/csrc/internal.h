@@ -130,7 +130,7 @@ struct fppg_ctx {
   uint32_t profiling = 0;   // bit p: time phase p
   fppg::PhaseProf prof[FPPG_NPHASES];
   int force_block = 256;    // launch shape of the force kernel (fppg_set_launch)
-  bool xcd_remap = true;
+  int xcd_remap = 1;         // 0 round-robin, 1 contiguous per XCD, 2 runs (launch_chunk)
   double* dot_scratch = nullptr;   // device address of this device's static dot-product scratch
   bool persistent = false;  // force kernel schedule (fppg_set_schedule)
   int* d_tickets = nullptr; // [8] ticket counters of the persistent schedule
@@ -258,6 +258,26 @@ __device__ __forceinline__ int xcd_chunk(int b, int nb) {
   const int q = nb / kNumXcd, r = nb % kNumXcd;
   const int x = b % kNumXcd, k = b / kNumXcd;
   return x * q + min(x, r) + k;
+}
+
+// Runs of kXcdRun consecutive chunks dealt to the XCDs in turn: run m goes to
+// XCD m % 8, so the k-th workgroup of XCD x takes chunk (8 (k / R) + x) R +
+// k % R. Each XCD then walks many shorter contiguous stretches spread over
+// the whole domain: neighbouring receivers still share an L2, and the XCDs
+// get equal shares of every region. Workgroups past the last whole round of
+// 8 runs keep their own index (a bijection on [0, nb) for any nb).
+constexpr int kXcdRun = 16;
+__device__ __forceinline__ int xcd_run_chunk(int b, int nb) {
+  const int full = nb / (kNumXcd * kXcdRun) * (kNumXcd * kXcdRun);
+  if (b >= full) return b;
+  const int x = b % kNumXcd, k = b / kNumXcd;
+  return ((k / kXcdRun) * kNumXcd + x) * kXcdRun + k % kXcdRun;
+}
+
+// Chunk of workgroup b of nb by the launch's XCD mapping: 0 round-robin (the
+// hardware's deal), 1 one contiguous range per XCD, 2 runs of kXcdRun chunks.
+__device__ __forceinline__ int launch_chunk(int mode, int b, int nb) {
+  return mode == 1 ? xcd_chunk(b, nb) : (mode == 2 ? xcd_run_chunk(b, nb) : b);
 }
 
 // Key of cell (0, y, z) of a geometry: the y range is cut into slabs of

@@ -92,9 +92,10 @@ class Context:
         self.handle = h
         self.device = device
 
-    def set_launch(self, force_block: int = 256, xcd_remap: bool = True, persistent: bool = False):
-        """Launch shape (fppg_set_launch) and schedule (fppg_set_schedule) of the force kernel."""
-        check(self.lib.fppg_set_launch(self.handle, int(force_block), int(bool(xcd_remap))), self.handle)
+    def set_launch(self, force_block: int = 256, xcd_remap: int = 1, persistent: bool = False):
+        """Launch shape (fppg_set_launch; xcd_remap 0 round-robin, 1 one contiguous
+        range per XCD, 2 runs of chunks) and schedule (fppg_set_schedule) of the force kernel."""
+        check(self.lib.fppg_set_launch(self.handle, int(force_block), int(xcd_remap)), self.handle)
         check(self.lib.fppg_set_schedule(self.handle, int(bool(persistent))), self.handle)
 
     def close(self):

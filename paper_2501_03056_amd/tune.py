@@ -80,12 +80,16 @@ def _time_graph(r, steps):
 
 
 # (threads per block, XCD remap, persistent ticket schedule)
-LAUNCH_SHAPES = ((256, True, False), (128, True, False), (512, True, False), (256, False, False),
-                 (128, False, False), (512, False, False), (256, True, True), (512, True, True))
+# (threads per block, XCD mapping: 0 round-robin / 1 contiguous / 2 runs, persistent tickets),
+# in order of preference among shapes within 1% of the fastest
+LAUNCH_SHAPES = ((256, 1, False), (128, 1, False), (512, 1, False), (256, 2, False),
+                 (512, 2, False), (256, 0, False), (128, 0, False), (512, 0, False),
+                 (256, 1, True), (512, 1, True))
+REMAP_NAMES = ("rr", "xcd", "run")
 
 
-def shape_name(block: int, remap: bool, persistent: bool) -> str:
-    return f"b{block}_{'xcd' if remap else 'rr'}" + ("_tickets" if persistent else "")
+def shape_name(block: int, remap: int, persistent: bool) -> str:
+    return f"b{block}_{REMAP_NAMES[int(remap)]}" + ("_tickets" if persistent else "")
 
 
 def autotune(wl, candidates=(1, 2), modes=("eager", "graph"), steps: int = 20, warmup: int = 4,
@@ -101,7 +105,8 @@ def autotune(wl, candidates=(1, 2), modes=("eager", "graph"), steps: int = 20, w
             table = json.load(open(cache))
         except (OSError, ValueError):
             table = {}
-    if key in table and "persistent" in table[key]:
+    names = {shape_name(*sh) for sh in shapes}
+    if key in table and "persistent" in table[key] and set(table[key].get("launch_ms_per_step", ())) == names:
         return table[key]
     times = {}
     for k in candidates:

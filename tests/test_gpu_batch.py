@@ -110,7 +110,10 @@ def test_autotune_picks_a_measured_configuration_and_results_do_not_depend_on_it
     from paper_2501_03056_amd.tune import LAUNCH_SHAPES, shape_name
     assert len(res["launch_ms_per_step"]) == len(LAUNCH_SHAPES) and res["force_block"] in (128, 256, 512)
     shape = shape_name(res["force_block"], res["xcd_remap"], res["persistent"])
-    assert min(res["launch_ms_per_step"].values()) == res["launch_ms_per_step"][shape]
+    # the tuner's rule: the first shape of LAUNCH_SHAPES within 1% of the fastest
+    fastest = min(res["launch_ms_per_step"].values())
+    first = next(shape_name(*sh) for sh in LAUNCH_SHAPES if res["launch_ms_per_step"][shape_name(*sh)] <= fastest * 1.01)
+    assert shape == first
     states = []
     for k in (1, 2):
         r = Relaxer(regrid(wl, k), device=0)
@@ -131,8 +134,11 @@ def test_force_launch_shape_does_not_change_results(k):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     wl = regrid(W.batch_workload(n_geom=5, n_min=1.5e3, n_max=8e3, seed=4100), k)
+    # 128-lane blocks with runs of 16 chunks: the run deal covers the first
+    # 8 * 16 * 128 receivers, the rest keep their index
+    assert wl.n > 8 * 16 * 128
     ref = None
-    for block, remap, persistent in LAUNCH_SHAPES:
+    for block, remap, persistent in LAUNCH_SHAPES + ((128, 2, False),):
         r = Relaxer(wl, device=0)
         r.ctx.set_launch(block, remap, persistent)
         for _ in range(3):
@@ -147,6 +153,8 @@ def test_force_launch_shape_does_not_change_results(k):
     from paper_2501_03056_amd import _lib
     with pytest.raises(_lib.FppgError):
         r.ctx.set_launch(64, True)
+    with pytest.raises(_lib.FppgError):
+        r.ctx.set_launch(256, 3)
 
 
 def _compare_one_step(wl, r, ref):
