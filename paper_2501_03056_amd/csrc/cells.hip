@@ -204,19 +204,26 @@ __global__ __launch_bounds__(kBlock) void k_final(const int* __restrict__ tmp_id
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const int k = tmp_key[s];
+  const int my = tmp_id[s];
+  const int src = tmp_src[s];
   const int b = cell_start[k], e = cell_start[k + 1];
+  const float4 p = pos_in[src];
+  const int o = owner_in[src];
+  // Three rounds of dependent loads instead of five: the entry, then the cell
+  // bounds beside the gathers, then the rank loop. The empty statement takes
+  // the values so that the compiler keeps the loads here rather than sinking
+  // them past the loop to their only use (it contains no instruction).
+  asm volatile("" ::"v"(p.x), "v"(p.y), "v"(p.z), "v"(p.w), "v"(o), "v"(my));
   if (e - b > kRankDirect) {
     if (s == b) big[atomicAdd(big_count, 1)] = k;   // one entry per cell; the list's order does not matter
     return;
   }
-  const int my = tmp_id[s];
   int r = 0;
   for (int t = b; t < e; ++t) r += tmp_id[t] < my;
   const int dst = b + r;
-  const int src = tmp_src[s];
-  pos_out[dst] = pos_in[src];
+  pos_out[dst] = p;
   id_out[dst] = my;
-  owner_out[dst] = owner_in[src];
+  owner_out[dst] = o;
 }
 
 constexpr int kBigThreads = 1024;
