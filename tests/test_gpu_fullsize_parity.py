@@ -140,6 +140,35 @@ def test_full_gear_tier_one_step_every_mover(gear_full, tier):
     assert r.read_status() == 0
 
 
+def test_full_gear_volume_tier_is_the_same_in_every_xcd_mapping(gear_full):
+    """The launch the benchmark times on the gear (256 threads, runs of 16
+    chunks dealt to the XCDs in turn: of 48,264 chunks all but the last 8,
+    the rest of a round of 8 runs, are in runs) and the other two XCD
+    mappings give the same two
+    volume-tier iterations and the same Jacobian product, bit for bit."""
+    wl = copy.copy(gear_full)
+    wl.move_mask = 1 << synth.VOLUME
+    v = np.random.default_rng(11).standard_normal((wl.n, 4)).astype(np.float32)
+    ref = None
+    for remap in (1, 2, 0):
+        print(f"[fullsize] gear volume tier, XCD mapping {remap}", flush=True)
+        r = _relaxer(wl)
+        r.tier(wl.move_mask)
+        r.ctx.set_launch(256, remap, False)
+        for _ in range(2):
+            r.step()
+        r.build_cells()
+        jv = r.hvp(torch.from_numpy(v[:r.na]).to(r.pos.device)).cpu().numpy()
+        got = [*r.host_state(), r.amax.cpu().numpy(), jv]
+        assert r.read_status() == 0
+        del r
+        if ref is None:
+            ref = got
+            continue
+        for a, b in zip(ref, got):
+            assert np.array_equal(a, b), remap
+
+
 def test_largest_batch_assemblies_one_step_every_mover():
     """The three largest Boolean assemblies of the 64-assembly benchmark batch
     (seed 4000, all unions) and its two largest differences (each built exactly
