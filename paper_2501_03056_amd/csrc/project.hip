@@ -263,7 +263,8 @@ __device__ __forceinline__ bool feature_walk(const SegDev* __restrict__ segs, in
 // facets, whose FP64 tests need several times the registers, go to a queue
 // that k_project_heavy takes: the streaming volume pass keeps a high
 // occupancy. Each block of the volume pass compacts its queued particles
-// (in index order) into its own kBlock slots of the queue and stores their
+// (its volume moves, then the others, each in index order) into its own
+// kBlock slots of the queue and stores their
 // number: no atomics, and the queue is the same on every run.
 // ONE_GEOM: a single geometry, whose descriptor is then read with scalar loads
 // that do not wait for the particle's position.
@@ -277,7 +278,7 @@ __global__ __launch_bounds__(kBlock) void k_project_volume(float4* __restrict__ 
                                                            int* __restrict__ hard) {
   if (blockIdx.x == 0 && threadIdx.x == 0) hard[0] = 0;   // the wide-search queue of this projection
   const int i = listed(blockIdx.x * blockDim.x + threadIdx.x, n, list, n_list);
-  bool heavy = false;
+  bool heavy = false, heavy_vol = false;
   if (i < n) {
     const float4 p = pos[i];
     const float4 d = disp[i];   // loaded with the position: one memory round trip for both
@@ -290,7 +291,7 @@ __global__ __launch_bounds__(kBlock) void k_project_volume(float4* __restrict__ 
         if (!(isfinite(y0) && isfinite(y1) && isfinite(y2))) {
           atomicOr(status, FPPG_S_NONFINITE_POS);
         } else if (segment_near_facets(G, p.x, p.y, p.z, y0, y1, y2, tflag)) {
-          heavy = true;                                    // the facet test in k_project_heavy
+          heavy = heavy_vol = true;                        // the facet test in k_project_heavy
         } else {
           pos[i] = make_float4(y0, y1, y2, p.w);           // no facet near the move: it stays inside
           moved = true;
@@ -301,20 +302,30 @@ __global__ __launch_bounds__(kBlock) void k_project_volume(float4* __restrict__ 
     }
     if (accepted && !heavy) accepted[i] = moved ? 1 : 0;
   }
-  // compact the heavy lanes of the block into its queue slots
-  __shared__ int s_wcnt[kBlock / 64];
-  const uint64_t m = __ballot(heavy);
+  // compact the heavy lanes of the block into its queue slots: the queued
+  // volume moves first, then the surface and feature particles, each in index
+  // order, so that the wavefronts of k_project_heavy mostly run one kind of
+  // test (a wavefront whose lanes take both runs both, one after the other)
+  __shared__ int s_wcnt[2][kBlock / 64];
+  const uint64_t mv = __ballot(heavy_vol), mo = __ballot(heavy && !heavy_vol);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (lane == 0) s_wcnt[w] = __popcll(m);
+  if (lane == 0) {
+    s_wcnt[0][w] = __popcll(mv);
+    s_wcnt[1][w] = __popcll(mo);
+  }
   __syncthreads();
-  int base = 0, total = 0;
+  int base_v = 0, base_o = 0, total_v = 0, total_o = 0;
 #pragma unroll
   for (int k = 0; k < kBlock / 64; ++k) {
-    base += k < w ? s_wcnt[k] : 0;
-    total += s_wcnt[k];
+    base_v += k < w ? s_wcnt[0][k] : 0;
+    base_o += k < w ? s_wcnt[1][k] : 0;
+    total_v += s_wcnt[0][k];
+    total_o += s_wcnt[1][k];
   }
-  if (heavy) queue[blockIdx.x * kBlock + base + __popcll(m & ((1ull << lane) - 1))] = i;
-  if (threadIdx.x == 0) qcount[blockIdx.x] = total;
+  const uint64_t below = (1ull << lane) - 1;
+  if (heavy)
+    queue[blockIdx.x * kBlock + (heavy_vol ? base_v + __popcll(mv & below) : total_v + base_o + __popcll(mo & below))] = i;
+  if (threadIdx.x == 0) qcount[blockIdx.x] = total_v + total_o;
 }
 
 // Facet tests of the queued volume moves (segment_crosses, the decision the
