@@ -42,17 +42,43 @@ __device__ __forceinline__ float cell_gap(int d, float f) {
   return d > 0 ? float(d) - f : (d < 0 ? f + float(-d - 1) : 0.0f);
 }
 
+// Keys of a receiver's stencil rows. Within one slab row_key is linear in
+// (y, z): the row dy, dz away has key base + dz zstep + dy nx, base being the
+// receiver's own row. linear: every row of the stencil on the grid lies in
+// the receiver's slab (always so with one slab over the whole y range).
+struct RowKeys {
+  int base, zstep;
+  bool linear;
+};
+
+__device__ __forceinline__ RowKeys row_keys(const Stencil s, const GeomDev& G, int k) {
+  const int S = G.slab;
+  const int y0 = int((float(s.y) + 0.5f) * G.inv_slab) * S;
+  const int w = min(S, G.dims[1] - y0);
+  return RowKeys{int(G.cell_begin) + y0 * G.dims[0] * G.dims[2] + (s.z * w + (s.y - y0)) * G.dims[0],
+                 w * G.dims[0], max(s.y - k, 0) >= y0 && min(s.y + k, G.dims[1] - 1) < y0 + w};
+}
+
+// Key of the row dy, dz away from the receiver: one multiply-add from the
+// plane's base where every active lane's stencil is in its slab (LINEAR),
+// row_key otherwise. The same key either way.
+template <bool LINEAR>
+__device__ __forceinline__ int stencil_row(const GeomDev& G, int plane_base, int dy, int y, int z) {
+  return LINEAR ? plane_base + dy * G.dims[0] : row_key(G, y, z);
+}
+
 // Visit the source index ranges of the stencil of a receiver, culled to the
 // cells within k cell edges (or within sqrt(kk) cell edges, kk <= k^2, for a
 // receiver whose pairs reach less far: the multi-resolution force).
-template <int K, class F>
-__device__ __forceinline__ void for_each_row(const Stencil s, const GeomDev& G, const int* __restrict__ cs, F&& f,
-                                             const float kk = float(K * K)) {
+template <int K, bool LINEAR, class F>
+__device__ __forceinline__ void for_each_row_keyed(const Stencil s, const GeomDev& G, const RowKeys rk,
+                                                   const int* __restrict__ cs, F&& f, const float kk) {
 #pragma unroll
   for (int dz = -K; dz <= K; ++dz) {
     const int z = s.z + dz;
     if (z < 0 || z >= G.dims[2]) continue;
     const float gz = cell_gap(dz, s.fz);
+    const int pb = rk.base + dz * rk.zstep;
 #pragma unroll
     for (int dy = -K; dy <= K; ++dy) {
       const int y = s.y + dy;
@@ -64,23 +90,32 @@ __device__ __forceinline__ void for_each_row(const Stencil s, const GeomDev& G, 
       const int below = min(K * kXSplit, int(ceilf(rho - s.fx + 1.0f)) - 1);   // |dx| with f + |dx| - 1 < rho
       const int above = min(K * kXSplit, int(ceilf(rho + s.fx)) - 1);          // dx with dx - f < rho
       const int x0 = max(s.x - below, 0), x1 = min(s.x + above, G.dims[0] - 1);
-      const int row = row_key(G, y, z);
+      const int row = stencil_row<LINEAR>(G, pb, dy, y, z);
       f(cs[row + x0], cs[row + x1 + 1]);
     }
   }
 }
 
+template <int K, class F>
+__device__ __forceinline__ void for_each_row(const Stencil s, const GeomDev& G, const int* __restrict__ cs, F&& f,
+                                             const float kk = float(K * K)) {
+  const RowKeys rk = row_keys(s, G, K);
+  if (__ballot(!rk.linear) == 0) for_each_row_keyed<K, true>(s, G, rk, cs, f, kk);
+  else for_each_row_keyed<K, false>(s, G, rk, cs, f, kk);
+}
+
 // As for_each_row, with the bounds of the five (2k+1) rows of a dz plane
 // loaded together before the plane's rows are walked, so that their loads
 // overlap (four more registers; used where the occupancy allows it).
-template <int K, class F>
-__device__ __forceinline__ void for_each_row_by_plane(const Stencil s, const GeomDev& G, const int* __restrict__ cs,
-                                                      F&& f, const float kk = float(K * K)) {
+template <int K, bool LINEAR, class F>
+__device__ __forceinline__ void for_each_row_by_plane_keyed(const Stencil s, const GeomDev& G, const RowKeys rk,
+                                                            const int* __restrict__ cs, F&& f, const float kk) {
 #pragma unroll
   for (int dz = -K; dz <= K; ++dz) {
     const int z = s.z + dz;
     if (z < 0 || z >= G.dims[2]) continue;
     const float gz = cell_gap(dz, s.fz);
+    const int pb = rk.base + dz * rk.zstep;
     int j0[2 * K + 1], j1[2 * K + 1];
 #pragma unroll
     for (int dy = -K; dy <= K; ++dy) {
@@ -94,13 +129,21 @@ __device__ __forceinline__ void for_each_row_by_plane(const Stencil s, const Geo
       const int below = min(K * kXSplit, int(ceilf(rho - s.fx + 1.0f)) - 1);
       const int above = min(K * kXSplit, int(ceilf(rho + s.fx)) - 1);
       const int x0 = max(s.x - below, 0), x1 = min(s.x + above, G.dims[0] - 1);
-      const int row = row_key(G, y, z);
+      const int row = stencil_row<LINEAR>(G, pb, dy, y, z);
       j0[dy + K] = cs[row + x0];
       j1[dy + K] = cs[row + x1 + 1];
     }
 #pragma unroll
     for (int q = 0; q < 2 * K + 1; ++q) f(j0[q], j1[q]);
   }
+}
+
+template <int K, class F>
+__device__ __forceinline__ void for_each_row_by_plane(const Stencil s, const GeomDev& G, const int* __restrict__ cs,
+                                                      F&& f, const float kk = float(K * K)) {
+  const RowKeys rk = row_keys(s, G, K);
+  if (__ballot(!rk.linear) == 0) for_each_row_by_plane_keyed<K, true>(s, G, rk, cs, f, kk);
+  else for_each_row_by_plane_keyed<K, false>(s, G, rk, cs, f, kk);
 }
 
 // Visit every source index of the stencil, two loads in flight at a time.
